@@ -1,0 +1,170 @@
+"""Per-path field computation (oracle, FP64).  Test infrastructure only.
+
+Follows Sec. II-C (transfer function), Sec. II-D-1 (specular reflection) and
+Eq. (cfr_cont) of the paper, evaluated path by path (vectorised over paths,
+one interaction slot at a time):
+
+  E <- C_T(k_1) in the (theta_hat, phi_hat) basis of the departure direction
+  for each reflection j:   E <- diag(R r_perp, R r_par) D_j E
+  at the receiver:         E <- D_{Q+1} E in the Rx (theta_hat, phi_hat) basis
+  a = lambda/(4 pi) * C_R^H E / (c tau)
+
+Readings (the paper is silent or cites without printing):
+  * spreading: planar reflectors and a point source give A^r = rho/(rho+d),
+    whose product with 1/d_1 telescopes to 1/(total length) = 1/(c tau);
+    tau is taken from the path store, not recomputed from FP32 points.
+  * reflection bases: e_perp = k_i x n / |k_i x n|, e_par_in = e_perp x k_i,
+    e_par_out = e_perp x k_r, components ordered (perp, par) as in
+    diag(r_perp, r_par).
+  * the stored normal may face either way; it is flipped per interaction so
+    that cos(theta_i) = -k_i . n > 0.
+  * normal incidence (|k_i x n| < 1e-7): e_perp is the incoming field
+    basis' first vector made orthogonal to k_i (the result does not depend
+    on the choice there because r_par = -r_perp).
+  * both antenna ends use the spherical basis of the direction pointing away
+    from the antenna along the path: k_1 at the Tx, -k_{Q+1} at the Rx.
+  * coefficients are evaluated at the carrier: lambda_c, eta(omega_c).
+  * array phase: element m of a half-wavelength ULA along u, centred on the
+    Tx, sees psi_i (m - (M-1)/2) with psi_i = pi k_1 . u (carrier only).
+"""
+import math
+
+import numpy as np
+import torch
+
+from .em import (C0, c128, f64, fresnel, materials_from_raw, pattern_isotropic,
+                 permittivity, spherical_basis, specular_amplitude, wavelength)
+
+
+def _unit(v):
+    return v / torch.linalg.norm(v, dim=-1, keepdim=True)
+
+
+def _dot(a, b):
+    return (a * b).sum(-1)
+
+
+def specular_step(E, p_out, q_out, k_in, n, eta, R):
+    """One specular reflection (Eqs. rel1, basis_transform, rel2,
+    specular_reflection).
+
+    E: complex [...,2] field in the outgoing basis (p_out, q_out) of the
+    previous process; k_in: incident unit direction; n: stored unit normal;
+    eta: complex permittivity; R: specular amplitude fraction.
+    Returns (E_out, e_perp, e_par_in, e_par_out, k_r, cos_theta)."""
+    flip = _dot(k_in, n) > 0
+    n = torch.where(flip[..., None], -n, n)
+    cos_t = -_dot(k_in, n)
+    cr = torch.cross(k_in, n, dim=-1)
+    crn = torch.linalg.norm(cr, dim=-1, keepdim=True)
+    # normal incidence fallback
+    alt = p_out - _dot(p_out, k_in)[..., None] * k_in
+    alt = alt / torch.linalg.norm(alt, dim=-1, keepdim=True)
+    small = crn < 1e-7
+    e_perp = torch.where(small, alt, cr / torch.where(small, torch.ones_like(crn), crn))
+    e_par_in = torch.cross(e_perp, k_in, dim=-1)
+    k_r = k_in - 2.0 * _dot(k_in, n)[..., None] * n
+    e_par_out = torch.cross(e_perp, k_r, dim=-1)
+    # basis change D: rows = new incoming basis, columns = previous outgoing
+    d00 = _dot(e_perp, p_out)
+    d01 = _dot(e_perp, q_out)
+    d10 = _dot(e_par_in, p_out)
+    d11 = _dot(e_par_in, q_out)
+    e0 = d00 * E[..., 0] + d01 * E[..., 1]
+    e1 = d10 * E[..., 0] + d11 * E[..., 1]
+    r_perp, r_par = fresnel(eta, cos_t)
+    E_out = torch.stack([R * r_perp * e0, R * r_par * e1], dim=-1)
+    return E_out, e_perp, e_par_in, e_par_out, k_r, cos_t
+
+
+def _gather_paths(store, sel):
+    P_all = int(store.n_paths)
+    D = int(store.max_depth)
+    link_of = np.repeat(np.arange(store.n_links), np.diff(store.link_off))[sel]
+    tx = torch.tensor(store.tx_pos[link_of], dtype=f64)
+    rx = torch.tensor(store.rx_pos[link_of], dtype=f64)
+    depth = torch.tensor(store.depth[sel].astype(np.int64))
+    pts, nrm, mat = [], [], []
+    for k in range(D):
+        idx = k * P_all + sel
+        pts.append(torch.tensor(store.pts[:, idx].T, dtype=f64))
+        nrm.append(torch.tensor(store.nrm[:, idx].T, dtype=f64))
+        mat.append(torch.tensor(store.mat[idx].astype(np.int64)))
+    tau = torch.tensor(store.tau[sel], dtype=f64)
+    return tx, rx, depth, pts, nrm, mat, tau
+
+
+def departure_direction(store, sel=None):
+    """k_1, the unit direction leaving the Tx, per path (float64 [P,3])."""
+    sel = np.arange(store.n_paths) if sel is None else np.asarray(sel)
+    tx, rx, depth, pts, _, _, _ = _gather_paths(store, sel)
+    first = torch.where((depth > 0)[:, None], pts[0], rx) if store.max_depth > 0 else rx
+    return _unit(first - tx)
+
+
+def trace_fields(store, eps_r, sigma, s, fc, zeta_tx=0.0, zeta_rx=0.0,
+                 ula_axis=(1.0, 0.0, 0.0), sel=None):
+    """Path coefficients a_i and array phase steps psi_i.
+
+    eps_r, sigma, s: per-interaction material values, float64 tensors of
+    shape [max_depth, P] (P = len(sel)), may require grad.  Slots beyond a
+    path's depth are ignored.  Returns (a complex128 [P], psi float64 [P])."""
+    sel = np.arange(store.n_paths) if sel is None else np.asarray(sel)
+    tx, rx, depth, pts, nrm, _, tau = _gather_paths(store, sel)
+    P = len(sel)
+    D = int(store.max_depth)
+    lam = wavelength(fc)
+    first = torch.where((depth > 0)[:, None], pts[0], rx) if D > 0 else rx
+    k1 = _unit(first - tx)
+    p_out, q_out = spherical_basis(k1)
+    E = pattern_isotropic(zeta_tx).expand(P, 2).clone()
+    prev = tx
+    up = torch.tensor([0.0, 0.0, 1.0], dtype=f64).expand(P, 3)
+    xhat = torch.tensor([1.0, 0.0, 0.0], dtype=f64).expand(P, 3)
+    for k in range(D):
+        act = depth > k
+        # inactive slots get a harmless stand-in geometry so that no NaN
+        # enters the graph; their results are discarded below
+        s_k = torch.where(act[:, None], pts[k], prev + up)
+        n_k = torch.where(act[:, None], nrm[k], xhat)
+        k_in = _unit(s_k - prev)
+        eta = permittivity(eps_r[k], sigma[k], fc)
+        R = specular_amplitude(s[k])
+        E_new, e_perp, _, e_par_out, _, _ = specular_step(E, p_out, q_out, k_in, n_k, eta, R)
+        E = torch.where(act[:, None], E_new, E)
+        p_out = torch.where(act[:, None], e_perp, p_out)
+        q_out = torch.where(act[:, None], e_par_out, q_out)
+        prev = torch.where(act[:, None], s_k, prev)
+    k_last = _unit(rx - prev)
+    t_r, p_r = spherical_basis(-k_last)
+    e0 = _dot(t_r, p_out) * E[:, 0] + _dot(t_r, q_out) * E[:, 1]
+    e1 = _dot(p_r, p_out) * E[:, 0] + _dot(p_r, q_out) * E[:, 1]
+    c_r = pattern_isotropic(zeta_rx)
+    received = c_r[0].conj() * e0 + c_r[1].conj() * e1
+    a = (lam / (4.0 * math.pi)) * received / (C0 * tau)
+    u = torch.tensor(ula_axis, dtype=f64)
+    psi = math.pi * _dot(k1, u.expand(P, 3))
+    return a, psi
+
+
+def per_interaction_from_ids(store, table, sel=None):
+    """Gather a per-material table [n_mat] onto interaction slots -> [D, P]."""
+    sel = np.arange(store.n_paths) if sel is None else np.asarray(sel)
+    P_all = int(store.n_paths)
+    rows = []
+    for k in range(int(store.max_depth)):
+        ids = torch.tensor(store.mat[k * P_all + sel].astype(np.int64))
+        rows.append(table[ids])
+    if not rows:
+        return torch.zeros((0, len(sel)), dtype=table.dtype)
+    return torch.stack(rows)
+
+
+def trace_fields_per_id(store, raw, fc, sel=None, **kw):
+    """Per-material-id mode: raw [n_mat, 3] -> (eps_r, sigma, S) by the
+    Sec. III-C transforms, gathered per interaction, then trace_fields."""
+    eps_r, sigma, s = materials_from_raw(raw)
+    return trace_fields(store,
+                        per_interaction_from_ids(store, eps_r, sel),
+                        per_interaction_from_ids(store, sigma, sel),
+                        per_interaction_from_ids(store, s, sel), fc, sel=sel, **kw)
