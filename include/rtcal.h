@@ -1,0 +1,217 @@
+/*
+ * rtcal.h -- C ABI of the MI355X (gfx950) library for the hot path of
+ * gradient-based radio-environment calibration by differentiable ray tracing
+ * (Hoydis et al., "Learning Radio Environments by Differentiable Ray
+ * Tracing", arXiv 2311.18558).
+ *
+ * The computation split follows the paper's forward model: fixed specular
+ * paths (found once on the host), per-path field computation giving a
+ * complex coefficient a_i and delay tau_i (Sec. II-C, II-D, Eq. cfr_cont),
+ * the channel frequency response over OFDM subcarriers (Sec. II-A), a loss
+ * on it, and the reverse-mode adjoints back to material and antenna
+ * parameters (Sec. III, Algorithm 1).
+ *
+ * Conventions shared by every entry point
+ *  - All array arguments are DEVICE pointers owned by the caller (for example
+ *    torch tensors).  The library never allocates, frees or synchronises
+ *    device memory except where an entry point says otherwise; work is
+ *    enqueued on `stream` (a hipStream_t passed as void*, NULL = default
+ *    stream) and runs asynchronously.
+ *  - Complex arrays ("c64") are interleaved {float re, float im}, the
+ *    layout of torch.complex64.
+ *  - Gradients of a real loss L with respect to a complex z are
+ *    dL/dRe(z) + j dL/dIm(z) (the torch convention).
+ *  - Host-side argument checks return a negative rtc_status and set a
+ *    thread-local message readable with rtc_last_error(); nothing is
+ *    enqueued then.  HIP launch errors return RTC_ERR_HIP.  Device-side
+ *    data (ids, offsets) is trusted: out-of-range material ids are clamped
+ *    to the last material.
+ *  - Results are deterministic run to run: every reduction has a fixed
+ *    order and no floating-point atomics are used.
+ */
+#ifndef RTCAL_H
+#define RTCAL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RTC_ABI_VERSION 1
+
+typedef enum {
+  RTC_OK = 0,
+  RTC_ERR_INVALID_ARG = -1, /* NULL pointer or nonsensical scalar          */
+  RTC_ERR_SHAPE = -2,       /* sizes inconsistent with each other          */
+  RTC_ERR_RANGE = -3,       /* a size beyond what the kernels support      */
+  RTC_ERR_WORKSPACE = -4,   /* workspace missing or smaller than required  */
+  RTC_ERR_HIP = -5,         /* a HIP runtime call failed                   */
+  RTC_ERR_UNSUPPORTED = -6  /* valid request this build does not implement */
+} rtc_status;
+
+/* OFDM grid and antennas.  Subcarrier n (0..n_sc-1) is at
+ *   f_n = fc_hz + (n - n_sc/2) * df_hz                     (Sec. II-A)
+ * The Tx is a uniform linear array of n_elem isotropic elements with
+ * half-wavelength spacing along the unit vector ula_axis, centred on the Tx
+ * position; the Rx is one isotropic element.  zeta_tx / zeta_rx are the
+ * polarisation slant angles of the polarisation model (Sec. II-B), 0 meaning
+ * vertical.  Path coefficients are evaluated at the carrier (wavelength and
+ * permittivity at fc); only the delay phase varies across subcarriers. */
+typedef struct {
+  double fc_hz;
+  double df_hz;
+  int32_t n_sc;
+  int32_t n_elem;
+  float ula_axis[3];
+  float zeta_tx;
+  float zeta_rx;
+} rtc_radio;
+
+/* Specular path store (device arrays).  Paths of link l are
+ * link_off[l] .. link_off[l+1]-1 (CSR, non-decreasing, link_off[0] = 0,
+ * link_off[n_links] = n_paths).  Interaction k (0-based) of path p lives at
+ * index k*n_paths + p of every per-interaction array (interaction-major
+ * structure of arrays); slots k >= depth[p] are ignored.
+ *   tx_pos, rx_pos : float [n_links*3]   link end points (metres)
+ *   depth          : uint8 [n_paths]     number of interactions Q <= max_depth
+ *   kind           : uint8 [max_depth*n_paths] 0 = specular reflection,
+ *                    1 = diffuse (Lambertian) reflection; may be NULL (all
+ *                    specular)
+ *   px,py,pz       : float [max_depth*n_paths] interaction points s_j
+ *   nx,ny,nz       : float [max_depth*n_paths] surface unit normals (either
+ *                    orientation)
+ *   dA             : float [max_depth*n_paths] area element of diffuse
+ *                    interactions; may be NULL when kind is NULL
+ *   mat            : uint16 [max_depth*n_paths] material class ids
+ *   tau            : double [n_paths] path delays (seconds), total length / c
+ */
+typedef struct {
+  int32_t n_links;
+  int32_t n_paths;
+  int32_t max_depth;
+  const int64_t* link_off;
+  const float* tx_pos;
+  const float* rx_pos;
+  const uint8_t* depth;
+  const uint8_t* kind;
+  const float* px;
+  const float* py;
+  const float* pz;
+  const float* nx;
+  const float* ny;
+  const float* nz;
+  const float* dA;
+  const uint16_t* mat;
+  const double* tau;
+} rtc_paths;
+
+/* Materials, in exactly one of two modes.
+ *  per-id:  raw = float [n_mat*3], raw parameters u per material class with
+ *           eps_r = 1 + exp(u0), sigma = exp(u1), S = logistic(u2)
+ *           (the trainable-material parametrisation of Sec. III-C with
+ *           one-dimensional embeddings and unit read-out); per_inter = NULL.
+ *  per-interaction (neural materials, Sec. III-D): per_inter = float
+ *           [3 * max_depth*n_paths] holding the rows eps_r, sigma, S, each
+ *           indexed like the per-interaction path arrays; raw = NULL.
+ * n_mat <= 1024.  mu_r = 1 and the XPD coefficient does not enter specular
+ * reflection. */
+typedef struct {
+  int32_t n_mat;
+  const float* raw;
+  const float* per_inter;
+} rtc_materials;
+
+/* Library version and the last error message of the calling thread. */
+int rtc_abi_version(void);
+const char* rtc_last_error(void);
+
+/* Operations that take a workspace, for rtc_workspace_size(). */
+typedef enum {
+  RTC_OP_CFR_LOSS = 1,
+  RTC_OP_CFR_ADJOINT = 2,
+  RTC_OP_TRACE_FIELDS_ADJOINT = 3,
+  RTC_OP_CFR_TARGET_STATS = 4
+} rtc_op;
+
+/* Bytes of device workspace `op` needs for n_links links (CFR rows are
+ * n_links * radio->n_elem) and n_paths paths.  0 on invalid input. */
+size_t rtc_workspace_size(int op, const rtc_radio* radio, int32_t n_links, int32_t n_paths,
+                          int32_t n_mat);
+
+/* Per-path field computation (Sec. II-C transfer chain, Sec. II-D-1
+ * specular reflection with the Fresnel coefficients of Eqs. fresnel-1/-2,
+ * Eq. cfr_cont):
+ *   a[p]   (c64 [n_paths])  = lambda/(4 pi) * C_R^H T_p(C_T) / (c tau_p),
+ *                             the delay phase factored out
+ *   psi[p] (float [n_paths]) = pi * k1_p . ula_axis, the phase step between
+ *                             adjacent Tx elements for the departure
+ *                             direction k1_p.
+ * Either output pointer may be NULL. */
+rtc_status rtc_trace_fields(const rtc_radio* radio, const rtc_paths* paths,
+                            const rtc_materials* mats, void* a, float* psi, void* stream);
+
+/* Channel frequency response (Eq. cfr_cont, discrete form of Sec. II-A):
+ *   H[l, m, n] = sum_{i in link l} a_i g_m exp(j psi_i (m - (M-1)/2))
+ *                                  exp(-j 2 pi f_n tau_i)
+ * a: c64 [n_paths], psi: float [n_paths], g: c64 [n_elem] element gains,
+ * H: c64 [n_links, n_elem, n_sc] (fully overwritten). */
+rtc_status rtc_cfr(const rtc_radio* radio, const rtc_paths* paths, const void* a,
+                   const float* psi, const void* g, void* H, void* stream);
+
+/* Target energies of a batch of CFR rows (n_rows = n_links * n_elem rows of
+ * n_sc subcarriers): stats[0] = sum |H*|^2, stats[1] = sum (p*)^2 with p* the
+ * power delay profile p_l = |h[l]|^2 of the centred 1/sqrt(N) IDFT
+ * (Sec. II-A).  stats: device double [2].  n_sc must be a power of two,
+ * 2 <= n_sc <= 4096. */
+rtc_status rtc_cfr_target_stats(const rtc_radio* radio, int32_t n_links, const void* H_tgt,
+                                double* stats, void* ws, size_t ws_bytes, void* stream);
+
+/* Coherent + power-delay-profile loss over a batch (workload loss):
+ *   L = w_coh * sum|H - H*|^2 / sum|H*|^2 + w_pdp * sum (p - p*)^2 / sum (p*)^2
+ * H, H_tgt: c64 [n_links, n_elem, n_sc].  tgt_stats: device double [2] from
+ * rtc_cfr_target_stats for the same H_tgt, or NULL to compute it here.
+ * loss: device double [3] = {L, coherent term, PDP term} (unweighted terms).
+ * dLdH: c64 like H or NULL; it may alias H (in-place).  n_sc must be a power
+ * of two, 2 <= n_sc <= 4096. */
+rtc_status rtc_cfr_loss(const rtc_radio* radio, int32_t n_links, const void* H,
+                        const void* H_tgt, const double* tgt_stats, float w_coh, float w_pdp,
+                        double* loss, void* dLdH, void* ws, size_t ws_bytes, void* stream);
+
+/* Adjoint of rtc_cfr:
+ *   G[m, i]  = sum_n dLdH[l(i), m, n] exp(+j 2 pi f_n tau_i)
+ *   dLda[i]  = sum_m G[m, i] conj(g_m exp(j psi_i (m - c)))      c64 [n_paths]
+ *   dLdg[m]  = sum_i G[m, i] conj(a_i exp(j psi_i (m - c)))      c64 [n_elem]
+ * with c = (M-1)/2.  dLdg is reduced over all links in FP64 in a fixed
+ * order.  Either output may be NULL. */
+rtc_status rtc_cfr_adjoint(const rtc_radio* radio, const rtc_paths* paths, const void* a,
+                           const float* psi, const void* g, const void* dLdH, void* dLda,
+                           void* dLdg, void* ws, size_t ws_bytes, void* stream);
+
+/* Adjoint of rtc_trace_fields: from dLda (c64 [n_paths]) to
+ *   per-id mode:          dLd_raw  float [n_mat*3], gradient w.r.t. the raw
+ *                         parameters u (overwritten, FP64-accumulated)
+ *   per-interaction mode: dLd_inter float [3 * max_depth*n_paths], rows
+ *                         dL/d eps_r, dL/d sigma, dL/d S per interaction
+ *                         (slots beyond a path's depth are set to 0)
+ * The unused output must be NULL. */
+rtc_status rtc_trace_fields_adjoint(const rtc_radio* radio, const rtc_paths* paths,
+                                    const rtc_materials* mats, const void* dLda,
+                                    float* dLd_raw, float* dLd_inter, void* ws, size_t ws_bytes,
+                                    void* stream);
+
+/* Adam step (the optimiser the paper uses, Sec. III-G / IV-B) on float32
+ * arrays of length n, in place:
+ *   m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2
+ *   p -= lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps)
+ * step t >= 1. */
+rtc_status rtc_adam_step(float* param, const float* grad, float* m, float* v, int64_t n,
+                         int32_t step, float lr, float beta1, float beta2, float eps,
+                         void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RTCAL_H */

@@ -1,0 +1,46 @@
+// Host-side helpers shared by the entry points of librtcal.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+
+#include "rtcal.h"
+
+namespace rtc {
+
+void set_error(const char* fmt, ...);
+void clear_error();
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+inline rtc_status check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_error("%s: HIP launch failed: %s", what, hipGetErrorString(e));
+    return RTC_ERR_HIP;
+  }
+  return RTC_OK;
+}
+
+// Shared validation of the radio and path-store descriptors.
+rtc_status check_radio(const rtc_radio* r, const char* fn);
+rtc_status check_paths(const rtc_paths* p, const char* fn, bool need_geometry);
+rtc_status check_mats(const rtc_materials* m, const rtc_paths* p, const char* fn);
+
+inline bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+constexpr int kMaxMat = 1024;
+constexpr int kMaxDepth = 8;
+constexpr int kMaxFFT = 4096;
+
+}  // namespace rtc
+
+#define RTC_REQUIRE(cond, code, ...)  \
+  do {                                \
+    if (!(cond)) {                    \
+      ::rtc::set_error(__VA_ARGS__);  \
+      return code;                    \
+    }                                 \
+  } while (0)

@@ -1,0 +1,344 @@
+// Coherent + power-delay-profile CFR loss and its gradient dL/dH.
+//
+// One workgroup per CFR row (link l, element m) at a time, grid-striding over
+// rows.  A row of N subcarriers (and its target) is transformed in LDS by a
+// radix-2 FFT to the CIR taps of the centred 1/sqrt(N) IDFT (Sec. II-A);
+// the power delay profile is p_l = |h[l]|^2 = |X_l|^2 / N with X the
+// unnormalised inverse DFT (the centring multiplies taps by unit-modulus
+// factors and reorders them, which changes neither |.|^2 nor the sums).
+//
+// With Z_c = sum|H*|^2 and Z_p = sum (p*)^2 over the batch,
+//   L = w_c sum|H - H*|^2 / Z_c + w_p sum (p - p*)^2 / Z_p
+//   dL/dH_n = 2 w_c (H_n - H*_n) / Z_c + FFT_n[ 4 w_p (p - p*) X / (N Z_p) ]
+// (the second term is the adjoint of the unitary IDFT applied to
+// dL/dh = 4 w_p (p - p*) h / Z_p).  Per-row partial sums are written in FP64
+// and reduced across rows in a fixed order.
+#include <cmath>
+
+#include "api_common.h"
+#include "dev_common.h"
+
+namespace rtc {
+
+constexpr int kLossBlock = 256;
+constexpr int kLossMaxPerThread = kMaxFFT / kLossBlock;  // 16
+constexpr int kRedBlock = 256;
+constexpr int kRedChunk = 4096;  // rows per first-level reduction block
+
+// tw[k] = exp(-j 2 pi k / N), k < N/2
+RTC_DEV void make_twiddles(float2* tw, int N) {
+  for (int k = threadIdx.x; k < N / 2; k += blockDim.x) {
+    float s, c;
+    sincos2pi((float)k / (float)N, &s, &c);  // k/N exact for N = 2^k
+    tw[k] = make_float2(c, -s);
+  }
+}
+
+// In-place radix-2 decimation-in-time FFT on bit-reversed input.
+// SIGN = -1: X_k = sum x_n e^{-j 2 pi nk/N}; SIGN = +1: e^{+j...}.
+template <int SIGN>
+RTC_DEV void fft_lds(float2* x, const float2* tw, int N, int logN) {
+  for (int s = 1; s <= logN; ++s) {
+    const int mh = 1 << (s - 1);
+    const int tstride = N >> s;
+    for (int b = threadIdx.x; b < N / 2; b += blockDim.x) {
+      const int k = b & (mh - 1);
+      const int i0 = ((b >> (s - 1)) << s) + k;
+      const int i1 = i0 + mh;
+      float2 w = tw[k * tstride];
+      if (SIGN > 0) w.y = -w.y;
+      float2 u = x[i0];
+      float2 v = cmul(x[i1], w);
+      x[i0] = cadd(u, v);
+      x[i1] = csub(u, v);
+    }
+    __syncthreads();
+  }
+}
+
+RTC_DEV int bitrev(int i, int logN) { return (int)(__brev((unsigned)i) >> (32 - logN)); }
+
+// Sum of a double over the block in a fixed order (wave butterfly, then the
+// waves in index order).  All threads must call; result valid on thread 0.
+RTC_DEV double block_sum_f64(double v, double* red) {
+  v = wave_sum_f64(v);
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+  __syncthreads();
+  return s;
+}
+
+// Target statistics per row: {sum |H*|^2, sum (p*)^2}.
+__global__ void __launch_bounds__(kLossBlock)
+    target_stats_kernel(const float2* __restrict__ Ht, int64_t n_rows, int N, int logN,
+                        double* row_out) {
+  extern __shared__ float2 sm[];
+  float2* tw = sm;
+  float2* xt = sm + N / 2;
+  __shared__ double red[kLossBlock / 64];
+  make_twiddles(tw, N);
+  const float invN = 1.0f / (float)N;
+  for (int64_t row = blockIdx.x; row < n_rows; row += gridDim.x) {
+    const float2* src = Ht + row * N;
+    float e = 0.0f;
+    for (int n = threadIdx.x; n < N; n += blockDim.x) {
+      float2 v = src[n];
+      e += cabs2(v);
+      xt[bitrev(n, logN)] = v;
+    }
+    __syncthreads();
+    fft_lds<+1>(xt, tw, N, logN);
+    float q = 0.0f;
+    for (int k = threadIdx.x; k < N; k += blockDim.x) {
+      float p = cabs2(xt[k]) * invN;
+      q += p * p;
+    }
+    double se = block_sum_f64((double)e, red);
+    double sq = block_sum_f64((double)q, red);
+    if (threadIdx.x == 0) {
+      row_out[row * 2 + 0] = se;
+      row_out[row * 2 + 1] = sq;
+    }
+    __syncthreads();
+  }
+}
+
+// Main per-row pass.  Z (device, 2 doubles) holds the batch normalisers when
+// dLdH is requested; row_out gets {sum|H-H*|^2, sum|H*|^2, sum(p-p*)^2,
+// sum(p*)^2}.
+__global__ void __launch_bounds__(kLossBlock)
+    cfr_loss_kernel(const float2* H, const float2* __restrict__ Ht, int64_t n_rows, int N,
+                    int logN, const double* Z, float w_coh, float w_pdp, double* row_out,
+                    float2* dLdH) {
+  extern __shared__ float2 sm[];
+  float2* tw = sm;
+  float2* x = sm + N / 2;
+  float2* xt = x + N;
+  __shared__ double red[kLossBlock / 64];
+  make_twiddles(tw, N);
+  const float invN = 1.0f / (float)N;
+  float gc = 0.0f, gp = 0.0f;
+  if (dLdH) {
+    gc = (float)(2.0 * (double)w_coh / Z[0]);
+    gp = (float)(4.0 * (double)w_pdp / (Z[1] * (double)N));
+  }
+  for (int64_t row = blockIdx.x; row < n_rows; row += gridDim.x) {
+    const float2* hs = H + row * N;
+    const float2* ts = Ht + row * N;
+    float2 diff[kLossMaxPerThread];
+    float ec = 0.0f, et = 0.0f;
+#pragma unroll
+    for (int u = 0; u < kLossMaxPerThread; ++u) {
+      const int n = threadIdx.x + u * kLossBlock;
+      if (n < N) {
+        float2 h = hs[n];
+        float2 t = ts[n];
+        diff[u] = csub(h, t);
+        ec += cabs2(diff[u]);
+        et += cabs2(t);
+        const int br = bitrev(n, logN);
+        x[br] = h;
+        xt[br] = t;
+      }
+    }
+    __syncthreads();
+    fft_lds<+1>(x, tw, N, logN);
+    fft_lds<+1>(xt, tw, N, logN);
+    float ep = 0.0f, eq = 0.0f;
+    // p - p* per tap; the gradient source 4 w_p (p - p*) X / (N Z_p) is
+    // written bit-reversed into xt (each tap k is read and written by the
+    // same thread; the barrier below separates it from the FFT)
+    float2 gsrc[kLossMaxPerThread];
+#pragma unroll
+    for (int u = 0; u < kLossMaxPerThread; ++u) {
+      const int k = threadIdx.x + u * kLossBlock;
+      if (k < N) {
+        float p = cabs2(x[k]) * invN;
+        float pt = cabs2(xt[k]) * invN;
+        float d = p - pt;
+        ep += d * d;
+        eq += pt * pt;
+        gsrc[u] = cscale(x[k], gp * d);
+      }
+    }
+    double s1 = block_sum_f64((double)ec, red);
+    double s2 = block_sum_f64((double)et, red);
+    double s3 = block_sum_f64((double)ep, red);
+    double s4 = block_sum_f64((double)eq, red);
+    if (threadIdx.x == 0) {
+      row_out[row * 4 + 0] = s1;
+      row_out[row * 4 + 1] = s2;
+      row_out[row * 4 + 2] = s3;
+      row_out[row * 4 + 3] = s4;
+    }
+    if (dLdH) {
+#pragma unroll
+      for (int u = 0; u < kLossMaxPerThread; ++u) {
+        const int k = threadIdx.x + u * kLossBlock;
+        if (k < N) x[bitrev(k, logN)] = gsrc[u];
+      }
+      __syncthreads();
+      fft_lds<-1>(x, tw, N, logN);
+      float2* out = dLdH + row * N;
+#pragma unroll
+      for (int u = 0; u < kLossMaxPerThread; ++u) {
+        const int n = threadIdx.x + u * kLossBlock;
+        if (n < N) out[n] = cadd(cscale(diff[u], gc), x[n]);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Fixed-order reduction of [R][K] doubles into [ceil(R/kRedChunk)][K].
+__global__ void __launch_bounds__(kRedBlock)
+    reduce_rows_kernel(const double* in, int64_t R, int K, double* out) {
+  __shared__ double red[kRedBlock / 64];
+  const int64_t r0 = (int64_t)blockIdx.x * kRedChunk;
+  const int64_t r1 = r0 + kRedChunk < R ? r0 + kRedChunk : R;
+  for (int c = 0; c < K; ++c) {
+    double v = 0.0;
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) v += in[r * K + c];
+    double s = block_sum_f64(v, red);
+    if (threadIdx.x == 0) out[(int64_t)blockIdx.x * K + c] = s;
+  }
+}
+
+__global__ void loss_finish_kernel(const double* sums, const double* Z, float w_coh, float w_pdp,
+                                   double* loss) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double zc = Z ? Z[0] : sums[1];
+  double zp = Z ? Z[1] : sums[3];
+  double coh = sums[0] / zc;
+  double pdp = sums[2] / zp;
+  loss[0] = (double)w_coh * coh + (double)w_pdp * pdp;
+  loss[1] = coh;
+  loss[2] = pdp;
+}
+
+__global__ void copy2_kernel(const double* src, double* dst) {
+  if (threadIdx.x < 2 && blockIdx.x == 0) dst[threadIdx.x] = src[threadIdx.x];
+}
+
+static int ilog2(int n) {
+  int k = 0;
+  while ((1 << k) < n) ++k;
+  return k;
+}
+
+static int64_t n_red1(int64_t R) { return (R + kRedChunk - 1) / kRedChunk; }
+
+// Reduce rows -> [K] in `dst` using `tmp` (n_red1(R)*K doubles, and a second
+// level if needed).
+static rtc_status reduce_all(const double* rows, int64_t R, int K, double* tmp, double* dst,
+                             hipStream_t s, const char* fn) {
+  int64_t R1 = n_red1(R);
+  hipLaunchKernelGGL(reduce_rows_kernel, dim3((unsigned)R1), dim3(kRedBlock), 0, s, rows, R, K,
+                     R1 == 1 ? dst : tmp);
+  rtc_status st = check_launch(fn);
+  if (st != RTC_OK || R1 == 1) return st;
+  int64_t R2 = n_red1(R1);
+  double* tmp2 = tmp + R1 * K;
+  hipLaunchKernelGGL(reduce_rows_kernel, dim3((unsigned)R2), dim3(kRedBlock), 0, s, tmp, R1, K,
+                     R2 == 1 ? dst : tmp2);
+  if ((st = check_launch(fn)) != RTC_OK || R2 == 1) return st;
+  hipLaunchKernelGGL(reduce_rows_kernel, dim3(1), dim3(kRedBlock), 0, s, tmp2, R2, K, dst);
+  return check_launch(fn);
+}
+
+// Workspace layout (doubles): rows[R*4] | red[(R1 + R2 + 1) * 4] | Z[2] | sums[4]
+static size_t ws_doubles(int64_t R) {
+  int64_t R1 = n_red1(R), R2 = n_red1(R1);
+  return (size_t)(R * 4 + (R1 + R2 + 1) * 4 + 2 + 4);
+}
+
+size_t ws_cfr_loss(const rtc_radio* r, int32_t n_links) {
+  int64_t R = (int64_t)(n_links > 0 ? n_links : 1) * (r->n_elem > 0 ? r->n_elem : 1);
+  return ws_doubles(R) * sizeof(double);
+}
+
+size_t ws_target_stats(const rtc_radio* r, int32_t n_links) { return ws_cfr_loss(r, n_links); }
+
+static unsigned row_grid(int64_t R) {
+  int64_t g = R < 8192 ? R : 8192;
+  return (unsigned)(g > 0 ? g : 1);
+}
+
+}  // namespace rtc
+
+using namespace rtc;
+
+static rtc_status check_fft_n(const rtc_radio* r, const char* fn) {
+  RTC_REQUIRE(is_pow2(r->n_sc) && r->n_sc >= 2 && r->n_sc <= kMaxFFT, RTC_ERR_UNSUPPORTED,
+              "%s: n_sc must be a power of two in [2, %d]", fn, kMaxFFT);
+  return RTC_OK;
+}
+
+extern "C" rtc_status rtc_cfr_target_stats(const rtc_radio* radio, int32_t n_links,
+                                           const void* H_tgt, double* stats, void* ws,
+                                           size_t ws_bytes, void* stream) {
+  const char* fn = "rtc_cfr_target_stats";
+  rtc_status st;
+  if ((st = check_radio(radio, fn)) != RTC_OK) return st;
+  if ((st = check_fft_n(radio, fn)) != RTC_OK) return st;
+  RTC_REQUIRE(n_links >= 1, RTC_ERR_SHAPE, "%s: n_links must be >= 1", fn);
+  RTC_REQUIRE(H_tgt && stats, RTC_ERR_INVALID_ARG, "%s: H_tgt and stats are required", fn);
+  int64_t R = (int64_t)n_links * radio->n_elem;
+  size_t need = ws_target_stats(radio, n_links);
+  RTC_REQUIRE(ws != nullptr && ws_bytes >= need, RTC_ERR_WORKSPACE,
+              "%s: workspace of %zu bytes required", fn, need);
+  hipStream_t s = as_stream(stream);
+  double* rows = reinterpret_cast<double*>(ws);
+  double* red = rows + R * 4;
+  int N = radio->n_sc, logN = ilog2(N);
+  size_t shm = (size_t)(N / 2 + N) * sizeof(float2);
+  hipLaunchKernelGGL(target_stats_kernel, dim3(row_grid(R)), dim3(kLossBlock), shm, s,
+                     reinterpret_cast<const float2*>(H_tgt), R, N, logN, rows);
+  if ((st = check_launch(fn)) != RTC_OK) return st;
+  return reduce_all(rows, R, 2, red, stats, s, fn);
+}
+
+extern "C" rtc_status rtc_cfr_loss(const rtc_radio* radio, int32_t n_links, const void* H,
+                                   const void* H_tgt, const double* tgt_stats, float w_coh,
+                                   float w_pdp, double* loss, void* dLdH, void* ws,
+                                   size_t ws_bytes, void* stream) {
+  const char* fn = "rtc_cfr_loss";
+  rtc_status st;
+  if ((st = check_radio(radio, fn)) != RTC_OK) return st;
+  if ((st = check_fft_n(radio, fn)) != RTC_OK) return st;
+  RTC_REQUIRE(n_links >= 1, RTC_ERR_SHAPE, "%s: n_links must be >= 1", fn);
+  RTC_REQUIRE(H && H_tgt && loss, RTC_ERR_INVALID_ARG, "%s: H, H_tgt and loss are required", fn);
+  RTC_REQUIRE(dLdH != H_tgt, RTC_ERR_INVALID_ARG, "%s: dLdH must not alias H_tgt", fn);
+  int64_t R = (int64_t)n_links * radio->n_elem;
+  size_t need = ws_cfr_loss(radio, n_links);
+  RTC_REQUIRE(ws != nullptr && ws_bytes >= need, RTC_ERR_WORKSPACE,
+              "%s: workspace of %zu bytes required", fn, need);
+  hipStream_t s = as_stream(stream);
+  double* rows = reinterpret_cast<double*>(ws);
+  int64_t R1 = n_red1(R), R2 = n_red1(R1);
+  double* red = rows + R * 4;
+  double* Z = red + (R1 + R2 + 1) * 4;
+  double* sums = Z + 2;
+  int N = radio->n_sc, logN = ilog2(N);
+  const double* Zuse = tgt_stats;
+  if (dLdH && !tgt_stats) {
+    size_t shm = (size_t)(N / 2 + N) * sizeof(float2);
+    hipLaunchKernelGGL(target_stats_kernel, dim3(row_grid(R)), dim3(kLossBlock), shm, s,
+                       reinterpret_cast<const float2*>(H_tgt), R, N, logN, rows);
+    if ((st = check_launch(fn)) != RTC_OK) return st;
+    if ((st = reduce_all(rows, R, 2, red, Z, s, fn)) != RTC_OK) return st;
+    Zuse = Z;
+  }
+  size_t shm = (size_t)(N / 2 + 2 * N) * sizeof(float2);
+  hipLaunchKernelGGL(cfr_loss_kernel, dim3(row_grid(R)), dim3(kLossBlock), shm, s,
+                     reinterpret_cast<const float2*>(H), reinterpret_cast<const float2*>(H_tgt), R,
+                     N, logN, Zuse, w_coh, w_pdp, rows, reinterpret_cast<float2*>(dLdH));
+  if ((st = check_launch(fn)) != RTC_OK) return st;
+  if ((st = reduce_all(rows, R, 4, red, sums, s, fn)) != RTC_OK) return st;
+  hipLaunchKernelGGL(loss_finish_kernel, dim3(1), dim3(64), 0, s, sums, Zuse, w_coh, w_pdp, loss);
+  return check_launch(fn);
+}

@@ -1,0 +1,237 @@
+"""ctypes binding of librtcal (argument marshalling only).
+
+Every function here forwards device pointers of torch tensors to the C ABI
+declared in include/rtcal.h and raises RuntimeError with the library's
+message on a non-zero status.  There is no fallback: if the shared library
+is not built, load() raises.
+
+torch is imported before the library is opened so that librtcal binds to the
+HIP runtime torch already loaded (one runtime per process).
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librtcal.so")
+
+c_i32 = ctypes.c_int32
+c_i64 = ctypes.c_int64
+c_f32 = ctypes.c_float
+c_f64 = ctypes.c_double
+c_vp = ctypes.c_void_p
+c_size = ctypes.c_size_t
+
+RTC_OP_CFR_LOSS = 1
+RTC_OP_CFR_ADJOINT = 2
+RTC_OP_TRACE_FIELDS_ADJOINT = 3
+RTC_OP_CFR_TARGET_STATS = 4
+
+
+class Radio(ctypes.Structure):
+    _fields_ = [("fc_hz", c_f64), ("df_hz", c_f64), ("n_sc", c_i32), ("n_elem", c_i32),
+                ("ula_axis", c_f32 * 3), ("zeta_tx", c_f32), ("zeta_rx", c_f32)]
+
+
+class Paths(ctypes.Structure):
+    _fields_ = [("n_links", c_i32), ("n_paths", c_i32), ("max_depth", c_i32),
+                ("link_off", c_vp), ("tx_pos", c_vp), ("rx_pos", c_vp), ("depth", c_vp),
+                ("kind", c_vp), ("px", c_vp), ("py", c_vp), ("pz", c_vp), ("nx", c_vp),
+                ("ny", c_vp), ("nz", c_vp), ("dA", c_vp), ("mat", c_vp), ("tau", c_vp)]
+
+
+class Materials(ctypes.Structure):
+    _fields_ = [("n_mat", c_i32), ("raw", c_vp), ("per_inter", c_vp)]
+
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "rtc_abi_version": (ctypes.c_int, []),
+    "rtc_last_error": (ctypes.c_char_p, []),
+    "rtc_workspace_size": (c_size, [ctypes.c_int, ctypes.POINTER(Radio), c_i32, c_i32, c_i32]),
+    "rtc_trace_fields": (ctypes.c_int, [ctypes.POINTER(Radio), ctypes.POINTER(Paths),
+                                        ctypes.POINTER(Materials), c_vp, c_vp, c_vp]),
+    "rtc_cfr": (ctypes.c_int, [ctypes.POINTER(Radio), ctypes.POINTER(Paths), c_vp, c_vp, c_vp,
+                               c_vp, c_vp]),
+    "rtc_cfr_target_stats": (ctypes.c_int, [ctypes.POINTER(Radio), c_i32, c_vp, c_vp, c_vp,
+                                            c_size, c_vp]),
+    "rtc_cfr_loss": (ctypes.c_int, [ctypes.POINTER(Radio), c_i32, c_vp, c_vp, c_vp, c_f32, c_f32,
+                                    c_vp, c_vp, c_vp, c_size, c_vp]),
+    "rtc_cfr_adjoint": (ctypes.c_int, [ctypes.POINTER(Radio), ctypes.POINTER(Paths), c_vp, c_vp,
+                                       c_vp, c_vp, c_vp, c_vp, c_vp, c_size, c_vp]),
+    "rtc_trace_fields_adjoint": (ctypes.c_int, [ctypes.POINTER(Radio), ctypes.POINTER(Paths),
+                                                ctypes.POINTER(Materials), c_vp, c_vp, c_vp,
+                                                c_vp, c_size, c_vp]),
+    "rtc_adam_step": (ctypes.c_int, [c_vp, c_vp, c_vp, c_vp, c_i64, c_i32, c_f32, c_f32, c_f32,
+                                     c_f32, c_vp]),
+}
+
+_lib = None
+
+
+def load():
+    """Open librtcal.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run paper_2311_18558_amd.build.build()")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def exported_names():
+    return list(_SIGS)
+
+
+def _check(status, fn):
+    if status != 0:
+        msg = load().rtc_last_error().decode(errors="replace")
+        raise RuntimeError(f"{fn} failed with status {status}: {msg}")
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def make_radio(fc, df, n_sc, n_elem, ula_axis=(1.0, 0.0, 0.0), zeta_tx=0.0, zeta_rx=0.0):
+    r = Radio()
+    r.fc_hz = float(fc)
+    r.df_hz = float(df)
+    r.n_sc = int(n_sc)
+    r.n_elem = int(n_elem)
+    for i in range(3):
+        r.ula_axis[i] = float(ula_axis[i])
+    r.zeta_tx = float(zeta_tx)
+    r.zeta_rx = float(zeta_rx)
+    return r
+
+
+def radio_from(radio):
+    """Radio struct from an object with fc, df, n_sc, n_elem, ula_axis,
+    zeta_tx, zeta_rx attributes."""
+    return make_radio(radio.fc, radio.df, radio.n_sc, radio.n_elem, radio.ula_axis,
+                      radio.zeta_tx, radio.zeta_rx)
+
+
+class DevicePaths:
+    """A path store uploaded to device memory, with its C descriptor."""
+
+    def __init__(self, store, device="cuda"):
+        d = torch.device(device)
+        t = lambda x, dt: torch.as_tensor(np.ascontiguousarray(x)).to(dtype=dt, device=d)
+        self.n_links = int(store.n_links)
+        self.n_paths = int(store.n_paths)
+        self.max_depth = int(store.max_depth)
+        self.link_off = t(store.link_off, torch.int64)
+        self.tx_pos = t(store.tx_pos.reshape(-1), torch.float32)
+        self.rx_pos = t(store.rx_pos.reshape(-1), torch.float32)
+        self.depth = t(store.depth, torch.uint8)
+        self.pts = t(store.pts, torch.float32)
+        self.nrm = t(store.nrm, torch.float32)
+        self.mat = t(store.mat.astype(np.int16), torch.int16)
+        self.tau = t(store.tau, torch.float64)
+        has_diffuse = bool(np.any(store.kind != 0))
+        self.kind = t(store.kind, torch.uint8) if has_diffuse else None
+        self.dA = t(store.dA, torch.float32) if has_diffuse else None
+        s = Paths()
+        s.n_links, s.n_paths, s.max_depth = self.n_links, self.n_paths, self.max_depth
+        s.link_off = self.link_off.data_ptr()
+        s.tx_pos = self.tx_pos.data_ptr()
+        s.rx_pos = self.rx_pos.data_ptr()
+        s.depth = self.depth.data_ptr()
+        s.kind = self.kind.data_ptr() if self.kind is not None else None
+        s.dA = self.dA.data_ptr() if self.dA is not None else None
+        DP = self.max_depth * self.n_paths
+        base_p = self.pts.data_ptr()
+        base_n = self.nrm.data_ptr()
+        s.px, s.py, s.pz = base_p, base_p + 4 * DP, base_p + 8 * DP
+        s.nx, s.ny, s.nz = base_n, base_n + 4 * DP, base_n + 8 * DP
+        s.mat = self.mat.data_ptr()
+        s.tau = self.tau.data_ptr()
+        self.c = s
+
+
+def materials_per_id(raw):
+    """Descriptor for per-id mode; keeps a reference to `raw` so the device
+    memory outlives the descriptor."""
+    m = Materials()
+    m.n_mat = int(raw.shape[0])
+    m.raw = raw.data_ptr()
+    m.per_inter = None
+    m._keep = raw
+    return m
+
+
+def materials_per_interaction(per_inter):
+    m = Materials()
+    m.n_mat = 1
+    m.raw = None
+    m.per_inter = per_inter.data_ptr()
+    m._keep = per_inter
+    return m
+
+
+def workspace_size(op, radio, n_links, n_paths, n_mat=1):
+    return int(load().rtc_workspace_size(op, ctypes.byref(radio), n_links, n_paths, n_mat))
+
+
+def workspace(op, radio, n_links, n_paths, n_mat=1, device="cuda"):
+    n = max(workspace_size(op, radio, n_links, n_paths, n_mat), 8)
+    return torch.empty(n, dtype=torch.uint8, device=device)
+
+
+# ------------------------------------------------------------ entry points
+def trace_fields(radio, paths, mats, a, psi, stream=None):
+    _check(load().rtc_trace_fields(ctypes.byref(radio), ctypes.byref(paths.c), ctypes.byref(mats),
+                                   _ptr(a), _ptr(psi), _stream(stream)), "rtc_trace_fields")
+
+
+def cfr(radio, paths, a, psi, g, H, stream=None):
+    _check(load().rtc_cfr(ctypes.byref(radio), ctypes.byref(paths.c), _ptr(a), _ptr(psi), _ptr(g),
+                          _ptr(H), _stream(stream)), "rtc_cfr")
+
+
+def cfr_target_stats(radio, n_links, H_tgt, stats, ws, stream=None):
+    _check(load().rtc_cfr_target_stats(ctypes.byref(radio), n_links, _ptr(H_tgt), _ptr(stats),
+                                       _ptr(ws), ws.numel(), _stream(stream)),
+           "rtc_cfr_target_stats")
+
+
+def cfr_loss(radio, n_links, H, H_tgt, tgt_stats, w_coh, w_pdp, loss, dLdH, ws, stream=None):
+    _check(load().rtc_cfr_loss(ctypes.byref(radio), n_links, _ptr(H), _ptr(H_tgt), _ptr(tgt_stats),
+                               float(w_coh), float(w_pdp), _ptr(loss), _ptr(dLdH), _ptr(ws),
+                               ws.numel(), _stream(stream)), "rtc_cfr_loss")
+
+
+def cfr_adjoint(radio, paths, a, psi, g, dLdH, dLda, dLdg, ws, stream=None):
+    _check(load().rtc_cfr_adjoint(ctypes.byref(radio), ctypes.byref(paths.c), _ptr(a), _ptr(psi),
+                                  _ptr(g), _ptr(dLdH), _ptr(dLda), _ptr(dLdg), _ptr(ws),
+                                  0 if ws is None else ws.numel(), _stream(stream)),
+           "rtc_cfr_adjoint")
+
+
+def trace_fields_adjoint(radio, paths, mats, dLda, dLd_raw, dLd_inter, ws, stream=None):
+    _check(load().rtc_trace_fields_adjoint(ctypes.byref(radio), ctypes.byref(paths.c),
+                                           ctypes.byref(mats), _ptr(dLda), _ptr(dLd_raw),
+                                           _ptr(dLd_inter), _ptr(ws),
+                                           0 if ws is None else ws.numel(), _stream(stream)),
+           "rtc_trace_fields_adjoint")
+
+
+def adam_step(param, grad, m, v, step, lr=0.01, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(load().rtc_adam_step(_ptr(param), _ptr(grad), _ptr(m), _ptr(v), param.numel(),
+                                int(step), float(lr), float(beta1), float(beta2), float(eps),
+                                _stream(stream)), "rtc_adam_step")

@@ -44,3 +44,60 @@ def tiny_workload(seed=1234, n_rx=64, n_sc=256, max_depth=2):
     radio = Radio(fc=3.5e9, bandwidth=50e6, n_sc=n_sc, n_elem=1)
     g = np.ones(1, np.complex64)
     return scene, store, raw, radio, g
+
+
+def ragged_subset(store, rng, keep_prob=0.7, empty_every=7):
+    """Drop paths at random (every `empty_every`-th link loses all of them)
+    to make odd and zero path counts; the result is still a valid store."""
+    from synth.store import PathStore
+    cnt = store.paths_per_link()
+    keep_links = []
+    sel = []
+    for l in range(store.n_links):
+        idx = np.arange(store.link_off[l], store.link_off[l + 1])
+        if l % empty_every == 3:
+            idx = idx[:0]
+        else:
+            idx = idx[rng.random(len(idx)) < keep_prob]
+        sel.append(idx)
+    sel_all = np.concatenate(sel)
+    off = np.zeros(store.n_links + 1, np.int64)
+    off[1:] = np.cumsum([len(s) for s in sel])
+    P, D = store.n_paths, store.max_depth
+    Pn = int(off[-1])
+    idx = (np.arange(D)[:, None] * P + sel_all[None, :]).reshape(-1)
+    return PathStore(n_links=store.n_links, n_paths=Pn, max_depth=D, link_off=off,
+                     tx_pos=store.tx_pos.copy(), rx_pos=store.rx_pos.copy(),
+                     depth=store.depth[sel_all].copy(), kind=store.kind[idx].copy(),
+                     pts=store.pts[:, idx].copy(), nrm=store.nrm[:, idx].copy(),
+                     mat=store.mat[idx].copy(), dA=store.dA[idx].copy(),
+                     tau=store.tau[sel_all].copy(), face=store.face[idx].copy())
+
+
+@functools.lru_cache(maxsize=None)
+def array_workload(seed=99, n_rx=48, n_sc=1024, n_elem=32, max_depth=2, n_mat=1):
+    """Box room with a Tx ULA: n_elem elements, n_sc subcarriers."""
+    rng = np.random.default_rng(seed)
+    scene = box_room()
+    tx = uniform_points_in_box(rng, 1, scene.aabb_min, scene.aabb_max)[0]
+    rxs = uniform_points_in_box(rng, n_rx, scene.aabb_min, scene.aabb_max)
+    store = imagemethod.find_store(scene, tx, rxs, max_depth)
+    eps_r, sigma, s = draw_materials(rng, n_mat, with_scattering=True)
+    raw = materials_to_raw(eps_r, sigma, s)
+    radio = Radio(fc=3.5e9, bandwidth=50e6, n_sc=n_sc, n_elem=n_elem,
+                  ula_axis=(0.6, 0.8, 0.0))
+    g = draw_gains(rng, n_elem)
+    return scene, store, raw, radio, g
+
+
+def multi_material_box(seed=5, n_rx=16, n_mat=3, max_depth=3):
+    """Box room whose six faces carry material ids f % n_mat."""
+    rng = np.random.default_rng(seed)
+    scene = box_room()
+    scene.face_mat = (np.arange(scene.n_face) % n_mat).astype(np.int32)
+    scene.n_mat = n_mat
+    tx = uniform_points_in_box(rng, 1, scene.aabb_min, scene.aabb_max)[0]
+    rxs = uniform_points_in_box(rng, n_rx, scene.aabb_min, scene.aabb_max)
+    store = imagemethod.find_store(scene, tx, rxs, max_depth)
+    eps_r, sigma, s = draw_materials(rng, n_mat, with_scattering=True)
+    return store, materials_to_raw(eps_r, sigma, s)

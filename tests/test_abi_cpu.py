@@ -1,0 +1,111 @@
+"""The C-ABI library loads, exports every symbol include/rtcal.h declares,
+and rejects bad arguments on the host with the documented status codes (no
+kernel is launched, so these run without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rtcal.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(rtc_[a-z_0-9]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch  # noqa: F401  (binds the HIP runtime first)
+    from paper_2311_18558_amd import lib as rl
+    return rl
+
+
+def test_library_exports_every_declared_symbol(lib):
+    so = lib.load()
+    names = _declared()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(so, n), n
+    assert set(names) == set(lib.exported_names())
+
+
+def test_abi_version(lib):
+    m = re.search(r"#define RTC_ABI_VERSION (\d+)", open(HEADER).read())
+    assert lib.load().rtc_abi_version() == int(m.group(1))
+
+
+def _radio(lib, n_sc=256, n_elem=4):
+    return lib.make_radio(3.5e9, 50e6 / n_sc, n_sc, n_elem)
+
+
+def test_null_arguments(lib):
+    so = lib.load()
+    st = so.rtc_cfr(None, None, None, None, None, None, None)
+    assert st == -1
+    assert b"radio is NULL" in so.rtc_last_error()
+    r = _radio(lib)
+    st = so.rtc_cfr(ctypes.byref(r), None, None, None, None, None, None)
+    assert st == -1 and b"paths is NULL" in so.rtc_last_error()
+
+
+def test_bad_shapes_and_ranges(lib):
+    so = lib.load()
+    r = _radio(lib)
+    p = lib.Paths()
+    p.n_links, p.n_paths, p.max_depth = 1, 1, 9
+    st = so.rtc_cfr(ctypes.byref(r), ctypes.byref(p), None, None, None, None, None)
+    assert st == -3 and b"max_depth" in so.rtc_last_error()
+    bad = lib.make_radio(3.5e9, 1e5, 0, 1)
+    st = so.rtc_cfr(ctypes.byref(bad), ctypes.byref(p), None, None, None, None, None)
+    assert st == -2 and b"n_sc" in so.rtc_last_error()
+
+
+def test_loss_needs_power_of_two_and_workspace(lib):
+    so = lib.load()
+    r = lib.make_radio(3.5e9, 1e5, 200, 1)
+    loss = ctypes.c_void_p(16)
+    st = so.rtc_cfr_loss(ctypes.byref(r), 4, ctypes.c_void_p(16), ctypes.c_void_p(32), None,
+                         1.0, 1.0, loss, None, None, 0, None)
+    assert st == -6 and b"power of two" in so.rtc_last_error()
+    r = _radio(lib)
+    st = so.rtc_cfr_loss(ctypes.byref(r), 4, ctypes.c_void_p(16), ctypes.c_void_p(32), None,
+                         1.0, 1.0, loss, None, ctypes.c_void_p(64), 8, None)
+    assert st == -4 and b"workspace" in so.rtc_last_error()
+
+
+def test_materials_mode_checks(lib):
+    so = lib.load()
+    r = _radio(lib)
+    p = lib.Paths()
+    p.n_links, p.n_paths, p.max_depth = 1, 1, 0
+    p.link_off = p.tx_pos = p.rx_pos = p.depth = p.tau = 16
+    m = lib.Materials()
+    m.n_mat = 1
+    st = so.rtc_trace_fields(ctypes.byref(r), ctypes.byref(p), ctypes.byref(m), None, None, None)
+    assert st == -1 and b"exactly one" in so.rtc_last_error()
+    m.raw = 16
+    m.n_mat = 5000
+    st = so.rtc_trace_fields(ctypes.byref(r), ctypes.byref(p), ctypes.byref(m), None, None, None)
+    assert st == -3 and b"n_mat" in so.rtc_last_error()
+
+
+def test_adam_argument_checks(lib):
+    so = lib.load()
+    st = so.rtc_adam_step(None, None, None, None, 10, 0, 0.01, 0.9, 0.999, 1e-8, None)
+    assert st == -1 and b"step" in so.rtc_last_error()
+    st = so.rtc_adam_step(None, None, None, None, 10, 1, 0.01, 1.0, 0.999, 1e-8, None)
+    assert st == -1 and b"betas" in so.rtc_last_error()
+    assert so.rtc_adam_step(None, None, None, None, 0, 1, 0.01, 0.9, 0.999, 1e-8, None) == 0
+
+
+def test_workspace_sizes(lib):
+    r = lib.make_radio(3.5e9, 48828.125, 1024, 32)
+    n_loss = lib.workspace_size(lib.RTC_OP_CFR_LOSS, r, 512, 100000)
+    assert n_loss >= 512 * 32 * 4 * 8
+    n_adj = lib.workspace_size(lib.RTC_OP_CFR_ADJOINT, r, 512, 100000)
+    assert n_adj == 512 * 32 * 16
+    assert lib.workspace_size(lib.RTC_OP_TRACE_FIELDS_ADJOINT, r, 512, 100000, 10) > 0
+    assert lib.workspace_size(99, r, 1, 1) == 0
