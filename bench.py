@@ -1,0 +1,211 @@
+"""Benchmark of the calibration hot path on one MI355X.
+
+One step = trace_fields -> cfr -> cfr_loss (dL/dH in place) -> cfr_adjoint
+-> trace_fields_adjoint -> Adam, over the whole `scale` workload (indoor
+floor, 16,384 Rx links x 32 Tx elements x 1,024 subcarriers, specular paths
+up to fifth order, ~186 paths per link), inputs resident in HBM.
+
+Prints ONE JSON line (rank 0):
+  value          CFR taps/s (taps = links x elements x subcarriers per step)
+  roofline       dominant kernel's algorithmic FLOP/s against the FP32 matrix
+                 peak, from HIP events on the launch stream
+  cpu_baseline   the FP64 oracle on a bounded sample of links, host cores
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+import torch  # noqa: E402
+
+PEAK_FP32_MATRIX_TFLOPS = 157.3  # MI355X dense FP32 MFMA
+PEAK_HBM_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def build_workload():
+    from synth import workloads
+    t0 = time.time()
+    w = workloads.scale()
+    log(f"workload scale: {w.store.n_links} links, {w.store.n_paths} paths "
+        f"({w.store.n_paths / w.store.n_links:.1f}/link), {w.meta['tris']} triangles, "
+        f"generated in {time.time() - t0:.1f}s")
+    return w
+
+
+def kernel_work(name, L, M, N, P, D):
+    """Algorithmic work per launch: (flops, bytes)."""
+    taps = L * M * N
+    if name in ("cfr", "cfr_adjoint"):
+        return 8.0 * M * N * P, 8.0 * taps + 20.0 * P
+    if name == "cfr_loss":
+        return 0.0, 24.0 * taps
+    if name in ("trace_fields", "trace_fields_adjoint"):
+        # per interaction: point, normal (24 B) + material id (2 B); per path
+        # depth (1 B) + tau (8 B); out: a (8 B) + psi (4 B) or in: dL/da
+        return 0.0, P * (26.0 * D + 9.0 + 12.0)
+    return 0.0, 0.0
+
+
+def cpu_baseline(w, budget_s=15.0, max_links=8192):
+    """The FP64 oracle (forward, loss, reverse-mode gradient) on whole
+    links of the same workload until `budget_s` of CPU time is spent."""
+    from oracle import channel as och
+    from oracle.trace import trace_fields_per_id
+    st, radio = w.store, w.radio
+    f = och.subcarrier_freqs(radio.fc, radio.bandwidth, radio.n_sc)
+    rng = np.random.default_rng(0)
+    raw_gt = torch.tensor(w.raw, dtype=torch.float64)
+    g = torch.tensor(w.g, dtype=torch.complex128)
+    raw0 = raw_gt + torch.tensor(rng.normal(scale=0.3, size=w.raw.shape))
+    order = rng.permutation(st.n_links)
+    done, t_used = 0, 0.0
+    for l in order[:max_links]:
+        sub = st.subset_links([l])
+        a_t, p_t = trace_fields_per_id(sub, raw_gt, radio.fc, ula_axis=radio.ula_axis)
+        Ht = och.cfr(sub.link_off, sub.tau, a_t, p_t, g, f)
+        t0 = time.perf_counter()
+        rr = raw0.clone().requires_grad_(True)
+        gg = g.clone().requires_grad_(True)
+        a, psi = trace_fields_per_id(sub, rr, radio.fc, ula_axis=radio.ula_axis)
+        H = och.cfr(sub.link_off, sub.tau, a, psi, gg, f)
+        L, _, _ = och.cfr_loss(H, Ht)
+        torch.autograd.grad(L, (rr, gg))
+        t_used += time.perf_counter() - t0
+        done += 1
+        if t_used >= budget_s:
+            break
+    taps = done * radio.n_elem * radio.n_sc
+    return {"value": taps / t_used, "unit": "taps/s", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": f"{done} whole links of the scale workload (forward, loss and FP64 "
+                      f"autograd gradient; targets precomputed), {t_used:.1f}s"}
+
+
+def load_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 counter summary, if present and taken on this kernel build."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return {}
+    try:
+        return json.load(open(p))
+    except Exception:
+        return {}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: the hot path here is the one-GPU share of the "
+              "workload; sharding across GPUs is described in the design notes but not built.",
+              file=sys.stderr)
+        sys.exit(2)
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    from paper_2311_18558_amd import lib as rl
+    from paper_2311_18558_amd.pipeline import Pipeline
+    rl.load()
+
+    w = build_workload()
+    st, radio = w.store, w.radio
+    L, M, N, P, D = st.n_links, radio.n_elem, radio.n_sc, st.n_paths, st.max_depth
+    rng = np.random.default_rng(7)
+    raw0 = (w.raw + rng.normal(scale=0.3, size=w.raw.shape)).astype(np.float32)
+    pipe = Pipeline(st, radio, w.raw, w.g)
+    # targets from the ground truth, then start from perturbed parameters
+    H_tgt = torch.empty_like(pipe.H)
+    pipe.trace()
+    pipe.cfr(out=H_tgt)
+    pipe.set_target(H_tgt)
+    pipe.raw.copy_(torch.tensor(raw0, device=pipe.dev))
+    torch.cuda.synchronize()
+    log("targets ready")
+
+    for _ in range(args.warmup):
+        pipe.step()
+    torch.cuda.synchronize()
+    events = {}
+    t0 = time.perf_counter()
+    e_start = torch.cuda.Event(enable_timing=True)
+    e_end = torch.cuda.Event(enable_timing=True)
+    e_start.record()
+    for _ in range(args.steps):
+        pipe.step(events=events)
+    e_end.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    total_ms = e_start.elapsed_time(e_end)
+    ms_step = total_ms / args.steps
+    per_kernel = {k: float(np.mean([a.elapsed_time(b) for a, b in v])) for k, v in events.items()}
+    log("per-stage ms: " + ", ".join(f"{k} {v:.3f}" for k, v in per_kernel.items()))
+    loss = pipe.loss.cpu().tolist()
+
+    taps = L * M * N
+    value = taps / (ms_step * 1e-3)
+    hot = max(("cfr", "cfr_adjoint"), key=lambda k: per_kernel[k])
+    fl, _ = kernel_work(hot, L, M, N, P, D)
+    achieved = fl / (per_kernel[hot] * 1e-3) / 1e12
+    traffic = load_traffic().get(hot)
+    roofline = {"bound": "mfma", "kernel": hot, "achieved": round(achieved, 2),
+                "peak": PEAK_FP32_MATRIX_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP32_MATRIX_TFLOPS, 4), "traffic": traffic}
+    kernels = {}
+    for k, ms in per_kernel.items():
+        fl_k, by_k = kernel_work(k, L, M, N, P, D)
+        ent = {"ms": round(ms, 4)}
+        if fl_k:
+            ent["tflops"] = round(fl_k / (ms * 1e-3) / 1e12, 2)
+        if by_k:
+            ent["gbs"] = round(by_k / (ms * 1e-3) / 1e9, 1)
+        kernels[k] = ent
+    fwd_adj_flops = 16.0 * M * N * P
+    out = {
+        "metric": "CFR taps/s fwd+adjoint",
+        "value": round(value, 1),
+        "unit": "taps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32",
+        "data": "synthetic",
+        "config": {"workload": "scale: procedural indoor floor (~5,000 triangles, 10 material "
+                               "classes), 1 Tx with a 32-element ULA, 16,384 Rx, specular paths "
+                               "up to 5th order, 1,024 subcarriers over 50 MHz at 3.5 GHz",
+                   "links": L, "elements": M, "subcarriers": N, "paths": P,
+                   "paths_per_link": round(P / L, 1), "max_depth": D},
+        "roofline": roofline,
+        "hot_path_tflops": round(fwd_adj_flops / ((per_kernel["cfr"] + per_kernel["cfr_adjoint"])
+                                                   * 1e-3) / 1e12, 2),
+        "kernels": kernels,
+        "loss": loss[0],
+        "wall_s": round(wall, 3),
+    }
+    if not args.no_cpu_baseline:
+        log("timing the oracle on a sample (cpu_baseline)")
+        out["cpu_baseline"] = cpu_baseline(w)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,102 @@
+"""One calibration step of the hot path with preallocated device buffers.
+
+    trace_fields -> cfr -> cfr_loss (dL/dH in place) -> cfr_adjoint
+                 -> trace_fields_adjoint -> Adam
+
+(Algorithm 1 of the paper with the workload loss, per-material-id mode.)
+Every step runs in the library's kernels; this module only owns buffers,
+workspaces and the order of calls, all on one stream.
+"""
+import numpy as np
+import torch
+
+from . import lib
+
+
+class Pipeline:
+    def __init__(self, store, radio, raw0, g0, device="cuda", stream=None):
+        self.dev = torch.device(device)
+        self.stream = stream
+        self.paths = store if isinstance(store, lib.DevicePaths) else lib.DevicePaths(store, self.dev)
+        self.radio = lib.radio_from(radio)
+        L, P = self.paths.n_links, self.paths.n_paths
+        M, N = self.radio.n_elem, self.radio.n_sc
+        self.L, self.P, self.M, self.N = L, P, M, N
+        self.raw = torch.tensor(np.asarray(raw0, np.float32), device=self.dev)
+        self.g = torch.tensor(np.asarray(g0, np.complex64), device=self.dev)
+        self.n_mat = self.raw.shape[0]
+        self.a = torch.empty(P, dtype=torch.complex64, device=self.dev)
+        self.psi = torch.empty(P, dtype=torch.float32, device=self.dev)
+        self.H = torch.empty((L, M, N), dtype=torch.complex64, device=self.dev)
+        self.loss = torch.zeros(3, dtype=torch.float64, device=self.dev)
+        self.dLda = torch.empty(P, dtype=torch.complex64, device=self.dev)
+        self.dLdg = torch.empty(M, dtype=torch.complex64, device=self.dev)
+        self.draw = torch.empty_like(self.raw)
+        self.ws_loss = lib.workspace(lib.RTC_OP_CFR_LOSS, self.radio, L, P, 1, self.dev)
+        self.ws_adj = lib.workspace(lib.RTC_OP_CFR_ADJOINT, self.radio, L, P, 1, self.dev)
+        self.ws_tr = lib.workspace(lib.RTC_OP_TRACE_FIELDS_ADJOINT, self.radio, L, P,
+                                   self.n_mat, self.dev)
+        self.mats = lib.materials_per_id(self.raw)
+        # Adam state (float32), materials and gains (as interleaved reals)
+        self.m_raw = torch.zeros_like(self.raw)
+        self.v_raw = torch.zeros_like(self.raw)
+        self.g_real = torch.view_as_real(self.g)
+        self.dLdg_real = torch.view_as_real(self.dLdg)
+        self.m_g = torch.zeros_like(self.g_real)
+        self.v_g = torch.zeros_like(self.g_real)
+        self.t = 0
+        self.H_tgt = None
+        self.tgt_stats = None
+
+    # individual stages (each one library call)
+    def trace(self):
+        lib.trace_fields(self.radio, self.paths, self.mats, self.a, self.psi, self.stream)
+
+    def cfr(self, out=None):
+        lib.cfr(self.radio, self.paths, self.a, self.psi, self.g,
+                self.H if out is None else out, self.stream)
+
+    def set_target(self, H_tgt):
+        """Targets for the loss; their energies are computed once here
+        (they do not change while calibrating on this batch)."""
+        self.H_tgt = H_tgt
+        self.tgt_stats = torch.empty(2, dtype=torch.float64, device=self.dev)
+        lib.cfr_target_stats(self.radio, self.L, H_tgt, self.tgt_stats, self.ws_loss, self.stream)
+
+    def loss_and_grad(self):
+        lib.cfr_loss(self.radio, self.L, self.H, self.H_tgt, self.tgt_stats, 1.0, 1.0,
+                     self.loss, self.H, self.ws_loss, self.stream)
+
+    def cfr_adjoint(self):
+        lib.cfr_adjoint(self.radio, self.paths, self.a, self.psi, self.g, self.H, self.dLda,
+                        self.dLdg, self.ws_adj, self.stream)
+
+    def trace_adjoint(self):
+        lib.trace_fields_adjoint(self.radio, self.paths, self.mats, self.dLda, self.draw, None,
+                                 self.ws_tr, self.stream)
+
+    def adam(self, lr=0.01, train_gains=True):
+        self.t += 1
+        lib.adam_step(self.raw, self.draw, self.m_raw, self.v_raw, self.t, lr=lr,
+                      stream=self.stream)
+        if train_gains:
+            lib.adam_step(self.g_real, self.dLdg_real, self.m_g, self.v_g, self.t, lr=lr,
+                          stream=self.stream)
+
+    STAGES = ("trace_fields", "cfr", "cfr_loss", "cfr_adjoint", "trace_fields_adjoint", "adam")
+
+    def step(self, lr=0.01, events=None):
+        """One full calibration step.  `events`, if given, maps stage name
+        to a list that receives (start, end) CUDA events per stage."""
+        fns = (self.trace, self.cfr, self.loss_and_grad, self.cfr_adjoint, self.trace_adjoint,
+               lambda: self.adam(lr))
+        for name, fn in zip(self.STAGES, fns):
+            if events is None:
+                fn()
+            else:
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                fn()
+                e1.record()
+                events.setdefault(name, []).append((e0, e1))

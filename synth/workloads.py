@@ -1,0 +1,90 @@
+"""Named synthetic workloads (seeded).
+
+  tiny      box room 10 x 8 x 3 m, one material, Tx at a seeded point,
+            64 Rx, specular depth <= 2, 256 subcarriers over 50 MHz,
+            single isotropic Tx antenna
+  scale     indoor floor 60 x 40 x 3 m (~5,000 triangles, 10 material
+            classes: floor, ceiling, four exterior sides, four interior wall
+            types), Tx at 2.5 m near the centre with a 32-element
+            half-wavelength ULA along x, 16,384 Rx at 1-2 m height,
+            specular depth <= 5, 1,024 subcarriers over 50 MHz at 3.5 GHz
+  adjoint   the scale floor and paths with hidden ground truth:
+            materials with S ~ U[0, 0.5] and 32 complex element gains;
+            14,336 training / 2,048 held-out Rx
+"""
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import imagemethod
+from .floorplan import indoor_floor
+from .params import Radio, draw_gains, draw_materials, materials_to_raw
+from .pathfind import find_store
+from .scene import box_room, uniform_points_in_box
+from .store import PathStore
+
+# Floor recipe of the scale workload: two rooms with wide openings.  With
+# specular paths up to fifth order (the order the paper traces for its
+# measured indoor scene) this gives ~185 paths per link on average.
+SCALE_FLOOR = dict(max_rooms=2, open_frac=0.7, n_pillars=0)
+SCALE_DEPTH = 5
+
+
+@dataclass
+class Workload:
+    name: str
+    store: PathStore
+    radio: Radio
+    raw: np.ndarray          # float32 [n_mat, 3] ground-truth raw material parameters
+    g: np.ndarray            # complex64 [n_elem] ground-truth element gains
+    aabb: tuple = None       # (min [3], max [3]) of the scene
+    meta: dict = field(default_factory=dict)
+
+
+def tiny(seed=1234, n_rx=64, n_sc=256, max_depth=2) -> Workload:
+    rng = np.random.default_rng(seed)
+    scene = box_room()
+    tx = uniform_points_in_box(rng, 1, scene.aabb_min, scene.aabb_max)[0]
+    rxs = uniform_points_in_box(rng, n_rx, scene.aabb_min, scene.aabb_max)
+    store = imagemethod.find_store(scene, tx, rxs, max_depth)
+    raw = materials_to_raw(*draw_materials(rng, 1, with_scattering=False))
+    radio = Radio(fc=3.5e9, bandwidth=50e6, n_sc=n_sc, n_elem=1)
+    return Workload("tiny", store, radio, raw, np.ones(1, np.complex64),
+                    (scene.aabb_min, scene.aabb_max))
+
+
+def _scale_geometry(seed, n_rx, max_depth, n_rays):
+    plan = indoor_floor(seed, **SCALE_FLOOR)
+    rng = np.random.default_rng(seed + 1)
+    tx = np.array([plan.width / 2, plan.depth / 2, 2.5])
+    while not plan.free(tx[0], tx[1], margin=0.3):
+        tx[:2] += rng.uniform(-1.0, 1.0, 2)
+    rx = plan.sample_points(rng, n_rx, 1.0, 2.0)
+    store = find_store(plan, tx, rx, max_depth, n_rays=n_rays)
+    return plan, store
+
+
+def scale(seed=3, n_rx=16384, n_sc=1024, n_elem=32, max_depth=SCALE_DEPTH,
+          n_rays=1 << 18) -> Workload:
+    plan, store = _scale_geometry(seed, n_rx, max_depth, n_rays)
+    rng = np.random.default_rng(seed + 2)
+    n_mat = plan.scene.n_mat
+    raw = materials_to_raw(*draw_materials(rng, n_mat, with_scattering=False))
+    radio = Radio(fc=3.5e9, bandwidth=50e6, n_sc=n_sc, n_elem=n_elem, ula_axis=(1.0, 0.0, 0.0))
+    return Workload("scale", store, radio, raw, np.ones(n_elem, np.complex64),
+                    (plan.scene.aabb_min, plan.scene.aabb_max),
+                    meta=dict(plan=plan, tris=plan.scene.n_tri, n_mat=n_mat))
+
+
+def adjoint(seed=3, n_rx=16384, n_sc=1024, n_elem=32, max_depth=SCALE_DEPTH,
+            n_rays=1 << 18, n_heldout=2048) -> Workload:
+    plan, store = _scale_geometry(seed, n_rx, max_depth, n_rays)
+    rng = np.random.default_rng(seed + 3)
+    n_mat = plan.scene.n_mat
+    raw = materials_to_raw(*draw_materials(rng, n_mat, with_scattering=True))
+    g = draw_gains(rng, n_elem)
+    radio = Radio(fc=3.5e9, bandwidth=50e6, n_sc=n_sc, n_elem=n_elem, ula_axis=(1.0, 0.0, 0.0))
+    perm = rng.permutation(n_rx)
+    return Workload("adjoint", store, radio, raw, g, (plan.scene.aabb_min, plan.scene.aabb_max),
+                    meta=dict(plan=plan, n_mat=n_mat, train=np.sort(perm[n_heldout:]),
+                              heldout=np.sort(perm[:n_heldout])))
