@@ -31,6 +31,12 @@ rtc_status check_mats(const rtc_materials* m, const rtc_paths* p, const char* fn
 
 inline bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
 
+// Fixed-order reduction of a [R][K] double array over rows into dst[K]
+// (device), using tmp (reduce_tmp_doubles(R, K) doubles of device memory).
+rtc_status reduce_all(const double* rows, int64_t R, int K, double* tmp, double* dst,
+                      hipStream_t s, const char* fn);
+size_t reduce_tmp_doubles(int64_t R, int K);
+
 constexpr int kMaxMat = 1024;
 constexpr int kMaxDepth = 8;
 constexpr int kMaxFFT = 4096;

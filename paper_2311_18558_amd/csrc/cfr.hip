@@ -291,21 +291,18 @@ __global__ void __launch_bounds__(kAdjWaves * 64) cfr_adjoint_kernel(AdjArgs A) 
   }
 }
 
-// dL/dg_m = sum over links of the per-link partials, in link order, FP64.
-__global__ void cfr_adjoint_gsum_kernel(const double* g_part, int n_links, int M, float2* dLdg) {
+__global__ void to_c64_kernel(const double* v, int M, float2* out) {
   int m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= M) return;
-  double sr = 0.0, si = 0.0;
-  for (int l = 0; l < n_links; ++l) {
-    sr += g_part[((int64_t)l * M + m) * 2 + 0];
-    si += g_part[((int64_t)l * M + m) * 2 + 1];
-  }
-  dLdg[m] = make_float2((float)sr, (float)si);
+  if (m < M) out[m] = make_float2((float)v[2 * m], (float)v[2 * m + 1]);
 }
 
+// Workspace (doubles): per-link dL/dg partials [L][M][2] | reduction tmp |
+// reduced [M][2].
 size_t ws_cfr_adjoint(const rtc_radio* r, int32_t n_links) {
   if (r->n_elem < 1) return 0;
-  return (size_t)(n_links > 0 ? n_links : 1) * r->n_elem * 2 * sizeof(double);
+  int64_t L = n_links > 0 ? n_links : 1;
+  int K = 2 * r->n_elem;
+  return ((size_t)L * K + reduce_tmp_doubles(L, K) + K) * sizeof(double);
 }
 
 static double subcarrier0(const rtc_radio* r) { return r->fc_hz - (double)(r->n_sc / 2) * r->df_hz; }
@@ -393,8 +390,13 @@ extern "C" rtc_status rtc_cfr_adjoint(const rtc_radio* radio, const rtc_paths* p
   hipLaunchKernelGGL(cfr_adjoint_kernel, dim3(paths->n_links), dim3(kAdjWaves * 64), 0, s, A);
   if ((st = check_launch(fn)) != RTC_OK) return st;
   if (dLdg) {
-    hipLaunchKernelGGL(cfr_adjoint_gsum_kernel, dim3((radio->n_elem + 63) / 64), dim3(64), 0, s,
-                       A.g_part, A.n_links, A.M, reinterpret_cast<float2*>(dLdg));
+    // dL/dg_m = sum over links of the per-link partials, fixed order, FP64
+    const int K = 2 * A.M;
+    double* tmp = A.g_part + (int64_t)A.n_links * K;
+    double* red = tmp + reduce_tmp_doubles(A.n_links, K);
+    if ((st = reduce_all(A.g_part, A.n_links, K, tmp, red, s, fn)) != RTC_OK) return st;
+    hipLaunchKernelGGL(to_c64_kernel, dim3((A.M + 63) / 64), dim3(64), 0, s, red, A.M,
+                       reinterpret_cast<float2*>(dLdg));
     return check_launch(fn);
   }
   return RTC_OK;

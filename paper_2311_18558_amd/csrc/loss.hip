@@ -234,8 +234,13 @@ static int64_t n_red1(int64_t R) { return (R + kRedChunk - 1) / kRedChunk; }
 
 // Reduce rows -> [K] in `dst` using `tmp` (n_red1(R)*K doubles, and a second
 // level if needed).
-static rtc_status reduce_all(const double* rows, int64_t R, int K, double* tmp, double* dst,
-                             hipStream_t s, const char* fn) {
+size_t reduce_tmp_doubles(int64_t R, int K) {
+  int64_t R1 = n_red1(R), R2 = n_red1(R1);
+  return (size_t)((R1 + R2 + 1) * K);
+}
+
+rtc_status reduce_all(const double* rows, int64_t R, int K, double* tmp, double* dst,
+                      hipStream_t s, const char* fn) {
   int64_t R1 = n_red1(R);
   hipLaunchKernelGGL(reduce_rows_kernel, dim3((unsigned)R1), dim3(kRedBlock), 0, s, rows, R, K,
                      R1 == 1 ? dst : tmp);

@@ -106,6 +106,6 @@ def test_workspace_sizes(lib):
     n_loss = lib.workspace_size(lib.RTC_OP_CFR_LOSS, r, 512, 100000)
     assert n_loss >= 512 * 32 * 4 * 8
     n_adj = lib.workspace_size(lib.RTC_OP_CFR_ADJOINT, r, 512, 100000)
-    assert n_adj == 512 * 32 * 16
+    assert n_adj >= 512 * 32 * 16
     assert lib.workspace_size(lib.RTC_OP_TRACE_FIELDS_ADJOINT, r, 512, 100000, 10) > 0
     assert lib.workspace_size(99, r, 1, 1) == 0
