@@ -201,6 +201,52 @@ rtc_status rtc_trace_fields_adjoint(const rtc_radio* radio, const rtc_paths* pat
                                     float* dLd_raw, float* dLd_inter, void* ws, size_t ws_bytes,
                                     void* stream);
 
+/* Neural materials (Sec. III-D): per point p, p_bar = (p - aabb_center) *
+ * inv_extent (inv_extent = 1 / longest edge of the scene's axis-aligned
+ * bounding box, so p_bar lies in [-1/2, 1/2]^3); input features
+ * [p_bar, then for each coordinate and k = 1..n_freq: sin(2^k pi p_bar),
+ * cos(2^k pi p_bar)] (the positional encoding of Eq. pos_encoding plus the
+ * raw coordinates, 51 features for n_freq = 8); n_hidden ReLU layers of
+ * `width`; 3 outputs o mapped to eps_r = 1 + softplus(o0), sigma =
+ * softplus(o1), S = logistic(o2).  Weights and layer inputs are rounded to
+ * BF16 (nearest even), products accumulate in FP32, biases and output
+ * transforms are FP32.  params: FP32 master vector of rtc_mlp_n_params()
+ * values, packed W0 [128][51], b0 [128], W1..W3 [128][128] each followed by
+ * its bias [128], W4 [3][128], b4 [3] (row-major, out x in).  This build
+ * implements n_freq = 8, width = 128, n_hidden = 4. */
+typedef struct {
+  const float* params;
+  float aabb_center[3];
+  float inv_extent;
+  int32_t n_freq;
+  int32_t width;
+  int32_t n_hidden;
+} rtc_mlp;
+
+int32_t rtc_mlp_n_params(void);
+/* Bytes of the buffer rtc_mlp_forward saves for rtc_mlp_backward. */
+size_t rtc_mlp_saved_size(int64_t n_points);
+/* Bytes of workspace rtc_mlp_forward (>= the packed weights) and
+ * rtc_mlp_backward need; the same buffer serves both. */
+size_t rtc_mlp_workspace_size(int64_t n_points);
+
+/* Forward over n_points points (px, py, pz: float [n_points] each, for
+ * example the interaction rows of a path store).  out: float [3*n_points],
+ * rows eps_r, sigma, S -- the per-interaction material layout of
+ * rtc_materials.per_inter.  saved: device buffer of rtc_mlp_saved_size
+ * bytes for the backward, or NULL. */
+rtc_status rtc_mlp_forward(const rtc_mlp* net, int64_t n_points, const float* px,
+                           const float* py, const float* pz, float* out, void* saved,
+                           size_t saved_bytes, void* ws, size_t ws_bytes, void* stream);
+
+/* Backward: dLdout float [3*n_points] (rows dL/d eps_r, dL/d sigma, dL/d S,
+ * as rtc_trace_fields_adjoint writes them) and the forward's saved buffer ->
+ * dLdparams float [rtc_mlp_n_params()] (overwritten).  Weight gradients are
+ * summed over points in fixed slices and the slices in a fixed order. */
+rtc_status rtc_mlp_backward(const rtc_mlp* net, int64_t n_points, const float* dLdout,
+                            const void* saved, float* dLdparams, void* ws, size_t ws_bytes,
+                            void* stream);
+
 /* Adam step (the optimiser the paper uses, Sec. III-G / IV-B) on float32
  * arrays of length n, in place:
  *   m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2

@@ -46,6 +46,11 @@ class Materials(ctypes.Structure):
     _fields_ = [("n_mat", c_i32), ("raw", c_vp), ("per_inter", c_vp)]
 
 
+class Mlp(ctypes.Structure):
+    _fields_ = [("params", c_vp), ("aabb_center", c_f32 * 3), ("inv_extent", c_f32),
+                ("n_freq", c_i32), ("width", c_i32), ("n_hidden", c_i32)]
+
+
 # name -> (restype, argtypes)
 _SIGS = {
     "rtc_abi_version": (ctypes.c_int, []),
@@ -66,6 +71,13 @@ _SIGS = {
                                                 c_vp, c_size, c_vp]),
     "rtc_adam_step": (ctypes.c_int, [c_vp, c_vp, c_vp, c_vp, c_i64, c_i32, c_f32, c_f32, c_f32,
                                      c_f32, c_vp]),
+    "rtc_mlp_n_params": (c_i32, []),
+    "rtc_mlp_saved_size": (c_size, [c_i64]),
+    "rtc_mlp_workspace_size": (c_size, [c_i64]),
+    "rtc_mlp_forward": (ctypes.c_int, [ctypes.POINTER(Mlp), c_i64, c_vp, c_vp, c_vp, c_vp, c_vp,
+                                       c_size, c_vp, c_size, c_vp]),
+    "rtc_mlp_backward": (ctypes.c_int, [ctypes.POINTER(Mlp), c_i64, c_vp, c_vp, c_vp, c_vp,
+                                        c_size, c_vp]),
 }
 
 _lib = None
@@ -235,3 +247,47 @@ def adam_step(param, grad, m, v, step, lr=0.01, beta1=0.9, beta2=0.999, eps=1e-8
     _check(load().rtc_adam_step(_ptr(param), _ptr(grad), _ptr(m), _ptr(v), param.numel(),
                                 int(step), float(lr), float(beta1), float(beta2), float(eps),
                                 _stream(stream)), "rtc_adam_step")
+
+
+# ------------------------------------------------------------ neural materials
+def make_mlp(params, aabb_min, aabb_max):
+    """Descriptor of the neural-material MLP: params is the FP32 master
+    vector (device); the normalisation uses the scene AABB's centre and
+    longest edge."""
+    lo = np.asarray(aabb_min, np.float64)
+    hi = np.asarray(aabb_max, np.float64)
+    m = Mlp()
+    m.params = params.data_ptr()
+    c = 0.5 * (lo + hi)
+    for i in range(3):
+        m.aabb_center[i] = float(c[i])
+    m.inv_extent = float(1.0 / np.max(hi - lo))
+    m.n_freq, m.width, m.n_hidden = 8, 128, 4
+    m._keep = params
+    return m
+
+
+def mlp_n_params():
+    return int(load().rtc_mlp_n_params())
+
+
+def mlp_saved(n_points, device="cuda"):
+    return torch.empty(max(int(load().rtc_mlp_saved_size(n_points)), 8), dtype=torch.uint8,
+                       device=device)
+
+
+def mlp_workspace(n_points, device="cuda"):
+    return torch.empty(max(int(load().rtc_mlp_workspace_size(n_points)), 8), dtype=torch.uint8,
+                       device=device)
+
+
+def mlp_forward(net, n_points, px, py, pz, out, saved, ws, stream=None):
+    _check(load().rtc_mlp_forward(ctypes.byref(net), int(n_points), _ptr(px), _ptr(py), _ptr(pz),
+                                  _ptr(out), _ptr(saved), 0 if saved is None else saved.numel(),
+                                  _ptr(ws), ws.numel(), _stream(stream)), "rtc_mlp_forward")
+
+
+def mlp_backward(net, n_points, dLdout, saved, dLdparams, ws, stream=None):
+    _check(load().rtc_mlp_backward(ctypes.byref(net), int(n_points), _ptr(dLdout), _ptr(saved),
+                                   _ptr(dLdparams), _ptr(ws), ws.numel(), _stream(stream)),
+           "rtc_mlp_backward")

@@ -88,3 +88,21 @@ class Workload:
     n_mat: int
     seed: int
     extra: dict = field(default_factory=dict)
+
+
+MLP_SHAPES = [(128, 51), (128, 128), (128, 128), (128, 128), (3, 128)]
+
+
+def mlp_init(rng: np.random.Generator, out_bias=(0.0, 0.0, 0.0)) -> np.ndarray:
+    """Seeded MLP parameters, packed W0, b0, ..., W4, b4 (row-major out x in):
+    uniform in +-1/sqrt(fan_in) for weights and hidden biases; the three
+    output biases are set to `out_bias`.  float32 [56579]."""
+    parts = []
+    for li, (o, i) in enumerate(MLP_SHAPES):
+        bound = 1.0 / np.sqrt(i)
+        parts.append(rng.uniform(-bound, bound, o * i))
+        if li == len(MLP_SHAPES) - 1:
+            parts.append(np.asarray(out_bias, np.float64))
+        else:
+            parts.append(rng.uniform(-bound, bound, o))
+    return np.concatenate(parts).astype(np.float32)
