@@ -1,0 +1,179 @@
+"""Gradient-based scene calibration (Algorithm 1 of the paper, with Adam as
+in Sec. IV-B) on fixed paths, in two parametrisations:
+
+  'per_id'  trainable materials per class (Sec. III-C, one-dimensional
+            embeddings): raw [n_mat, 3] plus the complex element gains
+  'neural'  neural materials (Sec. III-D): MLP weights plus the gains
+
+Every step of the method runs in librtcal; this module draws batches,
+stages their inputs (device gathers of the fixed path store and targets) and
+sequences the library calls on one stream.
+"""
+import math
+
+import numpy as np
+import torch
+
+from . import lib
+
+# prior mid-points used to initialise (eps_r in U[2, 10], sigma in
+# logU[1e-3, 1], S = 0.1)
+INIT_EPS, INIT_SIG, INIT_S = 5.5, 10 ** -1.5, 0.1
+
+
+def raw_prior(n_mat):
+    u = np.array([math.log(INIT_EPS - 1.0), math.log(INIT_SIG), math.log(INIT_S / (1 - INIT_S))])
+    return np.tile(u, (n_mat, 1)).astype(np.float32)
+
+
+def mlp_out_bias():
+    """Output biases that map to the prior mid-points through
+    eps_r = 1 + softplus, sigma = softplus, S = logistic."""
+    inv_softplus = lambda y: math.log(math.expm1(y))
+    return (inv_softplus(INIT_EPS - 1.0), inv_softplus(INIT_SIG), math.log(INIT_S / (1 - INIT_S)))
+
+
+class Calibrator:
+    def __init__(self, dp, radio, H_all, mode, raw0=None, mlp_params0=None, g0=None,
+                 aabb=None, lr=0.01, lr_mlp=1e-3, lr_gain=None, device="cuda"):
+        self.dev = torch.device(device)
+        self.dp = dp
+        self.radio = lib.radio_from(radio)
+        self.H_all = H_all
+        self.mode = mode
+        M = self.radio.n_elem
+        self.g = torch.tensor(np.ones(M, np.complex64) if g0 is None else g0, device=self.dev)
+        self.g_real = torch.view_as_real(self.g)
+        self.m_g = torch.zeros_like(self.g_real)
+        self.v_g = torch.zeros_like(self.g_real)
+        self.lr, self.lr_mlp = lr, lr_mlp
+        self.lr_gain = lr if lr_gain is None else lr_gain
+        self.t = 0
+        if mode == "per_id":
+            self.raw = torch.tensor(raw0, device=self.dev)
+            self.mats = lib.materials_per_id(self.raw)
+            self.m_p = torch.zeros_like(self.raw)
+            self.v_p = torch.zeros_like(self.raw)
+            self.params = self.raw
+        elif mode == "neural":
+            self.params = torch.tensor(mlp_params0, device=self.dev)
+            self.net = lib.make_mlp(self.params, *aabb)
+            self.m_p = torch.zeros_like(self.params)
+            self.v_p = torch.zeros_like(self.params)
+        else:
+            raise ValueError(mode)
+        self.dparams = torch.empty_like(self.params)
+        self._bufs = {}
+
+    def _buf(self, name, shape, dtype):
+        b = self._bufs.get(name)
+        n = int(np.prod(shape))
+        if b is None or b.numel() < n or b.dtype != dtype:
+            b = torch.empty(max(n, 1), dtype=dtype, device=self.dev)
+            self._bufs[name] = b
+        return b[:n].view(shape)
+
+    def _ws(self, op, L, P, n_mat=1):
+        n = lib.workspace_size(op, self.radio, L, P, n_mat)
+        return self._buf(f"ws{op}", (max(n, 8),), torch.uint8)
+
+    def _materials(self, b):
+        """Per-interaction materials of batch paths b (neural mode) or the
+        per-id descriptor."""
+        if self.mode == "per_id":
+            return self.mats, None
+        Q = b.max_depth * b.n_paths
+        per = self._buf("per", (3, Q), torch.float32)
+        saved = self._buf("saved", (int(lib.load().rtc_mlp_saved_size(Q)),), torch.uint8)
+        ws = self._buf("mlpws", (int(lib.load().rtc_mlp_workspace_size(Q)),), torch.uint8)
+        pts = b.pts
+        lib.mlp_forward(self.net, Q, pts[0], pts[1], pts[2], per, saved, ws)
+        return lib.materials_per_interaction(per), (Q, saved, ws)
+
+    def forward(self, b, H_out):
+        mats, aux = self._materials(b)
+        P = b.n_paths
+        a = self._buf("a", (P,), torch.complex64)
+        psi = self._buf("psi", (P,), torch.float32)
+        lib.trace_fields(self.radio, b, mats, a, psi)
+        lib.cfr(self.radio, b, a, psi, self.g, H_out)
+        return mats, aux, a, psi
+
+    def step(self, links, update=True):
+        """One iteration of Algorithm 1 on the batch `links`; returns the
+        loss terms as a device float64 [3] tensor.  With update=False only
+        the loss and the gradients (self.dparams, self.dLdg) are formed."""
+        b, _ = lib.subset_links(self.dp, links)
+        L, P = b.n_links, b.n_paths
+        M, N = self.radio.n_elem, self.radio.n_sc
+        H = self._buf("H", (L, M, N), torch.complex64)
+        H_t = self.H_all[links]
+        mats, aux, a, psi = self.forward(b, H)
+        loss = self._buf("loss", (3,), torch.float64)
+        lib.cfr_loss(self.radio, L, H, H_t, None, 1.0, 1.0, loss, H,
+                     self._ws(lib.RTC_OP_CFR_LOSS, L, P))
+        dLda = self._buf("dLda", (P,), torch.complex64)
+        dLdg = self._buf("dLdg", (M,), torch.complex64)
+        lib.cfr_adjoint(self.radio, b, a, psi, self.g, H, dLda, dLdg,
+                        self._ws(lib.RTC_OP_CFR_ADJOINT, L, P))
+        if self.mode == "per_id":
+            lib.trace_fields_adjoint(self.radio, b, mats, dLda, self.dparams, None,
+                                     self._ws(lib.RTC_OP_TRACE_FIELDS_ADJOINT, L, P,
+                                              self.raw.shape[0]))
+        else:
+            Q, saved, ws = aux
+            dint = self._buf("dint", (3, Q), torch.float32)
+            lib.trace_fields_adjoint(self.radio, b, mats, dLda, None, dint, None)
+            lib.mlp_backward(self.net, Q, dint, saved, self.dparams, ws)
+        self.dLdg = dLdg
+        if not update:
+            return loss
+        self.t += 1
+        lr = self.lr if self.mode == "per_id" else self.lr_mlp
+        lib.adam_step(self.params, self.dparams, self.m_p, self.v_p, self.t, lr=lr)
+        if self.lr_gain > 0:
+            lib.adam_step(self.g_real, torch.view_as_real(dLdg), self.m_g, self.v_g, self.t,
+                          lr=self.lr_gain)
+        return loss
+
+    def nmse(self, links, chunk=512):
+        """Held-out CFR NMSE = sum|H - H*|^2 / sum|H*|^2 over `links`."""
+        num, den = 0.0, 0.0
+        M, N = self.radio.n_elem, self.radio.n_sc
+        for i in range(0, len(links), chunk):
+            ls = links[i:i + chunk]
+            b, _ = lib.subset_links(self.dp, ls)
+            H = self._buf("Hn", (b.n_links, M, N), torch.complex64)
+            self.forward(b, H)
+            H_t = self.H_all[ls]
+            ws = self._ws(lib.RTC_OP_CFR_LOSS, b.n_links, b.n_paths)
+            stats = self._buf("stats", (2,), torch.float64)
+            lib.cfr_target_stats(self.radio, b.n_links, H_t, stats, ws)
+            loss = self._buf("lossn", (3,), torch.float64)
+            lib.cfr_loss(self.radio, b.n_links, H, H_t, stats, 1.0, 0.0, loss, None, ws)
+            zc = stats[0].item()
+            num += loss[1].item() * zc
+            den += zc
+        return num / den
+
+
+def targets(dp, radio, raw=None, per_inter=None, g=None, device="cuda", chunk=2048):
+    """Ground-truth CFRs of every link, computed by the library itself."""
+    rc = lib.radio_from(radio)
+    L, M, N = dp.n_links, rc.n_elem, rc.n_sc
+    H = torch.empty((L, M, N), dtype=torch.complex64, device=device)
+    g_d = torch.tensor(g, device=device)
+    if raw is not None:
+        raw_d = torch.tensor(raw, device=device)
+        mats = lib.materials_per_id(raw_d)
+        a = torch.empty(dp.n_paths, dtype=torch.complex64, device=device)
+        psi = torch.empty(dp.n_paths, dtype=torch.float32, device=device)
+        lib.trace_fields(rc, dp, mats, a, psi)
+        lib.cfr(rc, dp, a, psi, g_d, H)
+    else:
+        per = torch.tensor(per_inter, device=device)
+        a = torch.empty(dp.n_paths, dtype=torch.complex64, device=device)
+        psi = torch.empty(dp.n_paths, dtype=torch.float32, device=device)
+        lib.trace_fields(rc, dp, lib.materials_per_interaction(per), a, psi)
+        lib.cfr(rc, dp, a, psi, g_d, H)
+    return H

@@ -24,6 +24,7 @@ constexpr double kPi = 3.14159265358979323846;
 
 struct TraceArgs {
   int n_links, n_paths, n_mat;
+  int max_depth;  // interaction slots per path in the store (<= the template bound)
   int64_t DP;  // max_depth * n_paths: row stride of per-interaction rows
   const int64_t* link_off;
   const float* tx_pos;
@@ -161,6 +162,7 @@ RTC_DEV void run_chain(const TraceArgs& A, const MatVal* tab, int64_t p, Chain<M
   v3 tx = v3{A.tx_pos[3 * l], A.tx_pos[3 * l + 1], A.tx_pos[3 * l + 2]};
   v3 rx = v3{A.rx_pos[3 * l], A.rx_pos[3 * l + 1], A.rx_pos[3 * l + 2]};
   int Q = A.depth[p];
+  Q = Q < A.max_depth ? Q : A.max_depth;  // never past the store's slots
   Q = Q < MAXD ? Q : MAXD;
   C.Q = Q;
   v3 first = Q > 0 ? load3(A.px, A.py, A.pz, p) : rx;
@@ -317,6 +319,7 @@ __global__ void __launch_bounds__(kTraceBlock)
       if (valid) {
 #pragma unroll
         for (int j = 0; j < MAXD; ++j) {
+          if (j >= A.max_depth) break;  // the template bound may exceed the store's
           int64_t slot = (int64_t)j * A.n_paths + p;
           // slots past the depth get zeros
           dLd_inter[slot] = g_eps[j];
@@ -400,6 +403,7 @@ static TraceArgs make_args(const rtc_radio* r, const rtc_paths* P, const rtc_mat
   A.n_links = P->n_links;
   A.n_paths = P->n_paths;
   A.n_mat = M->raw ? M->n_mat : 1;
+  A.max_depth = P->max_depth;
   A.DP = (int64_t)P->max_depth * P->n_paths;
   A.link_off = P->link_off;
   A.tx_pos = P->tx_pos;

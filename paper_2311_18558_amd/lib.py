@@ -291,3 +291,49 @@ def mlp_backward(net, n_points, dLdout, saved, dLdparams, ws, stream=None):
     _check(load().rtc_mlp_backward(ctypes.byref(net), int(n_points), _ptr(dLdout), _ptr(saved),
                                    _ptr(dLdparams), _ptr(ws), ws.numel(), _stream(stream)),
            "rtc_mlp_backward")
+
+
+def subset_links(dp, links):
+    """Device-side batch: a DevicePaths holding only `links` (int64 device
+    tensor), gathered with index operations (input staging; no method
+    arithmetic).  Returns (DevicePaths, slot_index) where slot_index [D*Pb]
+    maps the batch's interaction slots to the full store's slots."""
+    dev = dp.link_off.device
+    links = links.to(device=dev, dtype=torch.int64)
+    start = dp.link_off[links]
+    cnt = dp.link_off[links + 1] - start
+    off = torch.zeros(len(links) + 1, dtype=torch.int64, device=dev)
+    off[1:] = torch.cumsum(cnt, 0)
+    Pb = int(off[-1].item())
+    rep = torch.repeat_interleave(torch.arange(len(links), device=dev), cnt, output_size=Pb)
+    idx = start[rep] + (torch.arange(Pb, device=dev) - off[:-1][rep])
+    D, P = dp.max_depth, dp.n_paths
+    slot = (torch.arange(D, device=dev)[:, None] * P + idx[None, :]).reshape(-1)
+    b = DevicePaths.__new__(DevicePaths)
+    b.n_links, b.n_paths, b.max_depth = len(links), Pb, D
+    b.link_off = off
+    b.tx_pos = dp.tx_pos.view(-1, 3)[links].reshape(-1).contiguous()
+    b.rx_pos = dp.rx_pos.view(-1, 3)[links].reshape(-1).contiguous()
+    b.depth = dp.depth[idx].contiguous()
+    b.pts = dp.pts[:, slot].contiguous()
+    b.nrm = dp.nrm[:, slot].contiguous()
+    b.mat = dp.mat[slot].contiguous()
+    b.tau = dp.tau[idx].contiguous()
+    b.kind = dp.kind[slot].contiguous() if dp.kind is not None else None
+    b.dA = dp.dA[slot].contiguous() if dp.dA is not None else None
+    s = Paths()
+    s.n_links, s.n_paths, s.max_depth = b.n_links, Pb, D
+    s.link_off = b.link_off.data_ptr()
+    s.tx_pos = b.tx_pos.data_ptr()
+    s.rx_pos = b.rx_pos.data_ptr()
+    s.depth = b.depth.data_ptr()
+    s.kind = b.kind.data_ptr() if b.kind is not None else None
+    s.dA = b.dA.data_ptr() if b.dA is not None else None
+    DPb = D * Pb
+    bp, bn = b.pts.data_ptr(), b.nrm.data_ptr()
+    s.px, s.py, s.pz = bp, bp + 4 * DPb, bp + 8 * DPb
+    s.nx, s.ny, s.nz = bn, bn + 4 * DPb, bn + 8 * DPb
+    s.mat = b.mat.data_ptr()
+    s.tau = b.tau.data_ptr()
+    b.c = s
+    return b, slot

@@ -88,3 +88,43 @@ def adjoint(seed=3, n_rx=16384, n_sc=1024, n_elem=32, max_depth=SCALE_DEPTH,
     return Workload("adjoint", store, radio, raw, g, (plan.scene.aabb_min, plan.scene.aabb_max),
                     meta=dict(plan=plan, n_mat=n_mat, train=np.sort(perm[n_heldout:]),
                               heldout=np.sort(perm[:n_heldout])))
+
+
+def spatial_field(store, plan, raw_base, seed, aabb):
+    """Ground-truth per-interaction materials varying in space: per-class
+    base values times smooth sinusoidal perturbations of three octaves,
+        q(p) = sum_{o=0..2} 2^-o sin(2 pi 2^o 4 (u_o . p_bar) + phi_o)
+        eps_r = 1 + (eps_base - 1) e^{0.3 q},  sigma = sigma_base e^{0.5 q},
+        S = logistic(logit(S_base) + 0.5 q)
+    with seeded unit vectors u_o and phases phi_o drawn independently per
+    parameter; p_bar is the point normalised by the scene box.  Returns
+    float32 [3, max_depth*n_paths] rows (eps_r, sigma, S)."""
+    rng = np.random.default_rng(seed)
+    lo, hi = (np.asarray(a, np.float64) for a in aabb)
+    pts = store.pts.T.astype(np.float64)
+    pbar = (pts - 0.5 * (lo + hi)) / np.max(hi - lo)
+    ids = store.mat.astype(np.int64)
+    eps_b = 1.0 + np.exp(raw_base[:, 0].astype(np.float64))
+    sig_b = np.exp(raw_base[:, 1].astype(np.float64))
+    lgt_b = raw_base[:, 2].astype(np.float64)
+    qs = []
+    for _ in range(3):
+        q = np.zeros(len(pbar))
+        for o in range(3):
+            u = rng.normal(size=3)
+            u /= np.linalg.norm(u)
+            phi = rng.uniform(0, 2 * np.pi)
+            q += 2.0 ** (-o) * np.sin(2 * np.pi * 2 ** o * 4 * (pbar @ u) + phi)
+        qs.append(q)
+    eps = 1.0 + (eps_b[ids] - 1.0) * np.exp(0.3 * qs[0])
+    sig = sig_b[ids] * np.exp(0.5 * qs[1])
+    S = 1.0 / (1.0 + np.exp(-(lgt_b[ids] + 0.5 * qs[2])))
+    return np.stack([eps, sig, S]).astype(np.float32)
+
+
+def learned(seed=3, n_rx=16384, **kw) -> Workload:
+    """The adjoint workload with a spatially varying ground-truth field."""
+    w = adjoint(seed=seed, n_rx=n_rx, **kw)
+    w.name = "learned"
+    w.meta["per_inter"] = spatial_field(w.store, w.meta["plan"], w.raw, seed + 11, w.aabb)
+    return w

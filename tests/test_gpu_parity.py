@@ -16,6 +16,7 @@ from oracle import channel as och
 from oracle import em as oem
 from oracle.adam import adam_step as oracle_adam
 from oracle.trace import trace_fields as o_trace, trace_fields_per_id as o_trace_id
+from synth.params import Radio, draw_materials, materials_to_raw
 from tests.helpers import array_workload, multi_material_box, ragged_subset, tiny_workload
 
 pytestmark = pytest.mark.gpu
@@ -82,7 +83,20 @@ def _cases():
     from synth.params import Radio as R4
     radio4 = R4(fc=3.5e9, bandwidth=50e6, n_sc=256, n_elem=4)
     g4 = np.array([1.0, 0.9 + 0.1j, 1.1 - 0.2j, 0.8j], np.complex64)
+    # a small floor at depth 5 (the scale workload's order; the kernels' depth
+    # template bound is 6 there, above the store's 5 slots)
+    from synth.floorplan import indoor_floor
+    from synth.pathfind import find_store
+    plan = indoor_floor(6, width=14.0, depth=10.0, min_room=4.0, max_rooms=2, open_frac=0.6,
+                        n_pillars=1, target_tris=600)
+    rng5 = np.random.default_rng(6)
+    st5 = find_store(plan, plan.sample_points(rng5, 1, 2.4, 2.6)[0],
+                     plan.sample_points(rng5, 24, 1.0, 2.0), 5, n_rays=1 << 16)
+    raw5 = materials_to_raw(*draw_materials(rng5, plan.scene.n_mat, with_scattering=True))
+    radio5 = Radio(fc=3.5e9, bandwidth=50e6, n_sc=512, n_elem=8, ula_axis=(1.0, 0.0, 0.0))
+    g5 = (rng5.uniform(0.8, 1.2, 8) * np.exp(1j * rng5.uniform(-0.7, 0.7, 8))).astype(np.complex64)
     return {
+        "floor_depth5": (st5, raw5, radio5, g5),
         "tiny": (st1, raw1, radio1, g1),
         "array32": (st2, raw2, radio2, g2),
         "ragged_m37_n200": (st3, raw2, radio3, g3),
@@ -269,7 +283,7 @@ def test_trace_fields_adjoint_per_id(rl, case):
     assert err <= 1e-4, err
 
 
-@pytest.mark.parametrize("case", ["tiny", "multimat_depth3"])
+@pytest.mark.parametrize("case", ["tiny", "multimat_depth3", "floor_depth5"])
 def test_trace_fields_adjoint_per_interaction(rl, case):
     st, raw, radio, g = CASES[case]
     rng = np.random.default_rng(34)
@@ -290,11 +304,14 @@ def test_trace_fields_adjoint_per_interaction(rl, case):
     per = torch.stack([e32, s32, S32]).reshape(3, D * P).contiguous().cuda()
     a = torch.empty(P, dtype=torch.complex64, device="cuda")
     rl.trace_fields(rc, dp, rl.materials_per_interaction(per), a, None)
-    dint = torch.full((3, D * P), float("nan"), dtype=torch.float32, device="cuda")
+    # one guard row past the end catches writes beyond the 3 x D*P output
+    buf = torch.full((4, D * P), float("nan"), dtype=torch.float32, device="cuda")
+    dint = buf[:3]
     rl.trace_fields_adjoint(rc, dp, rl.materials_per_interaction(per), dLda.cuda(), None, dint, None)
     torch.cuda.synchronize()
     rel = ((a.cpu().to(c128) - a_ref.detach()).abs() / _free_space(st, radio)).max().item()
     assert rel <= 1e-5, rel
+    assert torch.isnan(buf[3]).all(), "write past the end of the per-interaction rows"
     got = dint.cpu().double().reshape(3, D, P)
     depth = torch.tensor(st.depth.astype(np.int64))
     for c, ref in enumerate((ge, gs, gS)):
@@ -330,7 +347,7 @@ def _gpu_chain(rl, st, raw, radio, g, H_tgt):
     return loss.cpu(), draw.cpu(), dLdg.cpu()
 
 
-@pytest.mark.parametrize("case", ["tiny", "array32", "multimat_depth3"])
+@pytest.mark.parametrize("case", ["tiny", "array32", "multimat_depth3", "floor_depth5"])
 def test_end_to_end_gradient(rl, case):
     """Full chain gradients against the FP64 oracle gradient (<= 1e-3)."""
     st, raw, radio, g = CASES[case]
