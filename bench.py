@@ -92,6 +92,27 @@ def cpu_baseline(w, budget_s=15.0, max_links=8192):
                       f"autograd gradient; targets precomputed), {t_used:.1f}s"}
 
 
+def calib_compare(w, steps):
+    """Plain (per-material-id) vs learned (neural materials) calibration on
+    the scale scene with a spatially varying hidden material field and
+    hidden element gains: batch 512 Rx, Adam; 14,336 training / 2,048
+    held-out Rx."""
+    from paper_2311_18558_amd import lib as rl
+    from paper_2311_18558_amd.calibrate import compare_learned_vs_plain, targets
+    from synth import workloads
+    wl = workloads.learned(geometry=(w.meta["plan"], w.store))
+    dp = rl.DevicePaths(wl.store)
+    H_all = targets(dp, wl.radio, per_inter=wl.meta["per_inter"], g=wl.g)
+    log(f"calibration comparison: {steps} plain steps, learned up to {steps}")
+    res = compare_learned_vs_plain(dp, wl.radio, H_all, wl.meta["n_mat"], wl.aabb,
+                                   wl.meta["train"], wl.meta["heldout"], plain_steps=steps,
+                                   learned_max_steps=steps, log=log)
+    log(f"calib: {res}")
+    del H_all, dp
+    torch.cuda.empty_cache()
+    return res
+
+
 def load_traffic():
     """HBM bytes per launch of the dominant kernel from the committed
     rocprofv3 counter summary, if present and taken on this kernel build."""
@@ -110,6 +131,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-calib", action="store_true",
+                    help="skip the learned-vs-plain calibration comparison")
+    ap.add_argument("--calib-steps", type=int, default=3000)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the hot path here is the one-GPU share of the "
@@ -199,6 +223,10 @@ def main():
         "loss": loss[0],
         "wall_s": round(wall, 3),
     }
+    del pipe, H_tgt
+    torch.cuda.empty_cache()
+    if not args.no_calib:
+        out["calib"] = calib_compare(w, args.calib_steps)
     if not args.no_cpu_baseline:
         log("timing the oracle on a sample (cpu_baseline)")
         out["cpu_baseline"] = cpu_baseline(w)

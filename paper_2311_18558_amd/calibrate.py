@@ -177,3 +177,64 @@ def targets(dp, radio, raw=None, per_inter=None, g=None, device="cuda", chunk=20
         lib.trace_fields(rc, dp, lib.materials_per_interaction(per), a, psi)
         lib.cfr(rc, dp, a, psi, g_d, H)
     return H
+
+
+def _run(cal, train, held, max_steps, batch, eval_every, rng, stop_at=None, log=None):
+    """Steps until max_steps (or held-out NMSE <= stop_at); returns
+    (steps done, seconds spent in steps, NMSE history [(step, nmse)])."""
+    import time
+    hist = [(0, cal.nmse(held))]
+    t_steps, s = 0.0, 0
+    while s < max_steps:
+        n = min(eval_every, max_steps - s)
+        idx = [torch.tensor(rng.choice(len(train), batch, replace=False), device=cal.dev)
+               for _ in range(n)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(n):
+            cal.step(train[idx[i]])
+        torch.cuda.synchronize()
+        t_steps += time.perf_counter() - t0
+        s += n
+        nm = cal.nmse(held)
+        hist.append((s, nm))
+        if log:
+            log(f"{cal.mode} step {s} held-out NMSE {nm:.4e}")
+        if stop_at is not None and nm <= stop_at:
+            break
+    return s, t_steps, hist
+
+
+def compare_learned_vs_plain(dp, radio, H_all, n_mat, aabb, train, held, plain_steps=3000,
+                             learned_max_steps=3000, batch=512, eval_every=100, lr=0.01,
+                             lr_mlp=1e-4, seed=0, log=None):
+    """The plain per-material-id calibration for `plain_steps` gives
+    NMSE_plain; the neural-material calibration then runs until its held-out
+    NMSE reaches NMSE_plain (or `learned_max_steps`).  Steps/s of both at the
+    same batch size, steps and step-time to equal NMSE."""
+    from synth.params import mlp_init
+    rng = np.random.default_rng(seed)
+    tr = torch.as_tensor(train, device="cuda")
+    he = torch.as_tensor(held, device="cuda")
+    plain = Calibrator(dp, radio, H_all, "per_id", raw0=raw_prior(n_mat), lr=lr)
+    ps, pt, ph = _run(plain, tr, he, plain_steps, batch, eval_every, rng, log=log)
+    nmse_plain = ph[-1][1]
+    neural = Calibrator(dp, radio, H_all, "neural",
+                        mlp_params0=mlp_init(np.random.default_rng(seed + 5), mlp_out_bias()),
+                        aabb=aabb, lr=lr, lr_mlp=lr_mlp)
+    ls, lt, lh = _run(neural, tr, he, learned_max_steps, batch, eval_every, rng,
+                      stop_at=nmse_plain, log=log)
+    reached = lh[-1][1] <= nmse_plain
+    # continue to the plain method's step count to report what the network gains
+    ls2, lt2, lh2 = _run(neural, tr, he, max(0, plain_steps - ls), batch, eval_every, rng, log=log)
+    return {
+        "batch": batch,
+        "plain_steps": ps, "plain_steps_per_s": round(ps / pt, 2),
+        "plain_heldout_nmse": nmse_plain,
+        "learned_steps_per_s": round((ls + ls2) / (lt + lt2), 2),
+        "learned_reached_plain_nmse": bool(reached),
+        "learned_steps_to_plain_nmse": ls if reached else None,
+        "learned_seconds_to_plain_nmse": round(lt, 3) if reached else None,
+        "learned_heldout_nmse_at_plain_steps": (lh2[-1][1] if ls2 else lh[-1][1]),
+        "lr": lr, "lr_mlp": lr_mlp,
+    }

@@ -77,8 +77,12 @@ def scale(seed=3, n_rx=16384, n_sc=1024, n_elem=32, max_depth=SCALE_DEPTH,
 
 
 def adjoint(seed=3, n_rx=16384, n_sc=1024, n_elem=32, max_depth=SCALE_DEPTH,
-            n_rays=1 << 18, n_heldout=2048) -> Workload:
-    plan, store = _scale_geometry(seed, n_rx, max_depth, n_rays)
+            n_rays=1 << 18, n_heldout=2048, geometry=None) -> Workload:
+    """`geometry` = (plan, store) of the same seed reuses already traced
+    paths (the scale workload's)."""
+    plan, store = geometry if geometry is not None else _scale_geometry(seed, n_rx, max_depth,
+                                                                        n_rays)
+    n_rx = store.n_links
     rng = np.random.default_rng(seed + 3)
     n_mat = plan.scene.n_mat
     raw = materials_to_raw(*draw_materials(rng, n_mat, with_scattering=True))
