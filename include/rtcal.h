@@ -184,7 +184,8 @@ rtc_status rtc_cfr_loss(const rtc_radio* radio, int32_t n_links, const void* H,
  *   dLda[i]  = sum_m G[m, i] conj(g_m exp(j psi_i (m - c)))      c64 [n_paths]
  *   dLdg[m]  = sum_i G[m, i] conj(a_i exp(j psi_i (m - c)))      c64 [n_elem]
  * with c = (M-1)/2.  dLdg is reduced over all links in FP64 in a fixed
- * order.  Either output may be NULL. */
+ * order.  Either output may be NULL; the workspace
+ * (rtc_workspace_size(RTC_OP_CFR_ADJOINT, ...)) is always required. */
 rtc_status rtc_cfr_adjoint(const rtc_radio* radio, const rtc_paths* paths, const void* a,
                            const float* psi, const void* g, const void* dLdH, void* dLda,
                            void* dLdg, void* ws, size_t ws_bytes, void* stream);

@@ -69,7 +69,7 @@ rtc_status check_mats(const rtc_materials* m, const rtc_paths* p, const char* fn
 // agree.
 namespace rtc {
 size_t ws_cfr_loss(const rtc_radio* r, int32_t n_links);
-size_t ws_cfr_adjoint(const rtc_radio* r, int32_t n_links);
+size_t ws_cfr_adjoint(const rtc_radio* r, int32_t n_links, int32_t n_paths);
 size_t ws_trace_adjoint(int32_t n_paths, int32_t n_mat);
 size_t ws_target_stats(const rtc_radio* r, int32_t n_links);
 }  // namespace rtc
@@ -87,7 +87,7 @@ size_t rtc_workspace_size(int op, const rtc_radio* radio, int32_t n_links, int32
     case RTC_OP_CFR_LOSS:
       return radio ? rtc::ws_cfr_loss(radio, n_links) : 0;
     case RTC_OP_CFR_ADJOINT:
-      return radio ? rtc::ws_cfr_adjoint(radio, n_links) : 0;
+      return radio ? rtc::ws_cfr_adjoint(radio, n_links, n_paths) : 0;
     case RTC_OP_TRACE_FIELDS_ADJOINT:
       return rtc::ws_trace_adjoint(n_paths, n_mat);
     case RTC_OP_CFR_TARGET_STATS:

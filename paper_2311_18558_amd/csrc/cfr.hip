@@ -16,9 +16,9 @@
 // within a wave, tile t+1 is tile t times exp(-j 2 pi 32 df tau_i).
 //
 // The adjoint G[m, i] = sum_n dLdH[m, n] conj(E[i, n]) is the same kind of
-// product with the subcarriers as the contraction axis; dLdH is staged
-// through LDS in chunks of 64 subcarriers, and E advances by a two-step
-// recurrence exp(-j 2 pi 2 df tau_i), re-anchored in FP64 at every chunk.
+// product with the subcarriers as the contraction axis; each lane reads its
+// dL/dH row directly, and E advances by exp(-j 2 pi df tau_i) from an FP64
+// anchor every 32 subcarriers.
 #include <cmath>
 
 #include "api_common.h"
@@ -32,7 +32,6 @@ constexpr int kCfrWaves = 4;   // waves per workgroup (forward)
 constexpr int kCfrTiles = 4;   // 32-subcarrier tiles per wave (forward)
 constexpr int kAdjWaves = 4;   // waves per workgroup (adjoint)
 constexpr int kAdjTP = 2;      // 32-path tiles per wave (adjoint)
-constexpr int kAdjChunk = 64;  // subcarriers per LDS chunk (adjoint)
 constexpr double kInv2Pi = 0.15915494309189533577;
 
 RTC_DEV floatx16 mfma32(float a, float b, floatx16 c) {
@@ -119,174 +118,221 @@ __global__ void __launch_bounds__(kCfrWaves * 64) cfr_kernel(CfrArgs A, float2* 
 }
 
 // ------------------------------------------------------------------ adjoint
+// One wave per (link, group of kAdjTP 32-path tiles), found by binary search
+// in a per-link exclusive scan of wave counts.  For each 32-row element
+// block the wave contracts over subcarriers: MFMA step s of a 64-subcarrier
+// chunk takes subcarriers n0 + s (k = 0) and n0 + 32 + s (k = 1), so lane l
+// reads a contiguous run of its own row (16-byte loads) and advances its
+// exponential by exp(-j 2 pi df tau) from an FP64 anchor per half-chunk.
 struct AdjArgs {
   int n_links, M, N;
+  int64_t max_waves;
   const int64_t* link_off;
+  const int64_t* wave_off;  // [n_links + 1] exclusive scan of waves per link
   const float2* a;
   const float* psi;
   const double* tau;
   const float2* g;
   const float2* dH;
-  float2* dLda;     // may be null
-  double* g_part;   // [n_links][M][2] per-link dL/dg partials, or null
+  float2* dLda;    // may be null
+  double* g_part;  // [max_waves][M][2] per-wave dL/dg partials, or null
   double f0, df, cm;
 };
 
-__global__ void __launch_bounds__(kAdjWaves * 64) cfr_adjoint_kernel(AdjArgs A) {
-  __shared__ float sre[32][kAdjChunk + 1];
-  __shared__ float sim[32][kAdjChunk + 1];
-  __shared__ double gsum[kAdjWaves][32][2];
+__device__ __forceinline__ int adj_waves_of(const int64_t* off, int l) {
+  const int64_t P = off[l + 1] - off[l];
+  const int64_t tiles = (P + 31) / 32;
+  return (int)((tiles + kAdjTP - 1) / kAdjTP);
+}
 
+// Exclusive scan of waves per link (one block, fixed order).
+__global__ void __launch_bounds__(1024) adj_wave_scan_kernel(const int64_t* link_off, int n_links,
+                                                              int64_t* wave_off) {
+  __shared__ int64_t part[1024];
+  const int t = threadIdx.x;
+  const int per = (n_links + 1023) / 1024;
+  const int l0 = t * per, l1 = min(n_links, l0 + per);
+  int64_t s = 0;
+  for (int l = l0; l < l1; ++l) s += adj_waves_of(link_off, l);
+  part[t] = s;
+  __syncthreads();
+  if (t == 0) {
+    int64_t acc = 0;
+    for (int i = 0; i < 1024; ++i) {
+      int64_t v = part[i];
+      part[i] = acc;
+      acc += v;
+    }
+  }
+  __syncthreads();
+  int64_t acc = part[t];
+  for (int l = l0; l < l1; ++l) {
+    wave_off[l] = acc;
+    acc += adj_waves_of(link_off, l);
+  }
+  if (t == 1023) wave_off[n_links] = acc;
+}
+
+__device__ __forceinline__ void load4(const float2* row, int n, int N, bool vec, float2 h[4]) {
+  if (vec && n + 3 < N) {
+    const float4* p = reinterpret_cast<const float4*>(row + n);
+    float4 x = p[0], y = p[1];
+    h[0] = make_float2(x.x, x.y);
+    h[1] = make_float2(x.z, x.w);
+    h[2] = make_float2(y.x, y.y);
+    h[3] = make_float2(y.z, y.w);
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) h[q] = (n + q < N) ? row[n + q] : make_float2(0.0f, 0.0f);
+  }
+}
+
+__global__ void __launch_bounds__(kAdjWaves * 64) cfr_adjoint_kernel(AdjArgs A) {
   const int lane = threadIdx.x & 63;
   const int half = lane >> 5;
   const int col = lane & 31;
-  const int wave = threadIdx.x >> 6;
-  const int64_t l = blockIdx.x;
+  const int64_t w = (int64_t)blockIdx.x * kAdjWaves + (threadIdx.x >> 6);
+  if (w >= A.max_waves) return;
+  const int64_t total = A.wave_off[A.n_links];
+  if (w >= total) {
+    // surplus wave: its dL/dg partial row is zero
+    if (A.g_part)
+      for (int m = lane; m < A.M; m += 64) {
+        A.g_part[(w * A.M + m) * 2 + 0] = 0.0;
+        A.g_part[(w * A.M + m) * 2 + 1] = 0.0;
+      }
+    return;
+  }
+  int lo = 0, hi = A.n_links - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (A.wave_off[mid] <= w)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const int64_t l = lo;
+  const int grp = (int)(w - A.wave_off[l]);
   const int64_t off0 = A.link_off[l];
   const int64_t off1 = A.link_off[l + 1];
-  const int64_t P_l = off1 - off0;
-  const int n_tiles = (int)((P_l + 31) / 32);
+  const int n_tiles = (int)((off1 - off0 + 31) / 32);
   const int n_mblk = (A.M + 31) / 32;
-  const int n_chunks = (A.N + kAdjChunk - 1) / kAdjChunk;
-  const double df2 = 2.0 * A.df;
+  const bool vec = (A.N & 3) == 0;
   const float2* dHl = A.dH + l * (int64_t)A.M * A.N;
 
+  int64_t pidx[kAdjTP];
+  bool ok[kAdjTP];
+  float2 ai[kAdjTP];
+  float psv[kAdjTP];
+  double tv[kAdjTP];
+  float2 w1[kAdjTP];
+#pragma unroll
+  for (int u = 0; u < kAdjTP; ++u) {
+    const int tile = grp * kAdjTP + u;
+    pidx[u] = off0 + (int64_t)tile * 32 + col;
+    ok[u] = tile < n_tiles && pidx[u] < off1;
+    ai[u] = ok[u] ? A.a[pidx[u]] : make_float2(0.0f, 0.0f);
+    psv[u] = ok[u] ? A.psi[pidx[u]] : 0.0f;
+    tv[u] = ok[u] ? A.tau[pidx[u]] : 0.0;
+    w1[u] = expm2pi_f64(A.df * tv[u]);
+  }
+  float2 da[kAdjTP];
+#pragma unroll
+  for (int u = 0; u < kAdjTP; ++u) da[u] = make_float2(0.0f, 0.0f);
+
   for (int mblk = 0; mblk < n_mblk; ++mblk) {
-    // per-wave dL/dg partial sums for the 16 rows this lane's half reduces
-    double gacc_re[16], gacc_im[16];
+    const int row = mblk * 32 + col;
+    const bool row_ok = row < A.M;
+    const float2* rp = dHl + (int64_t)(row_ok ? row : 0) * A.N;
+    floatx16 gre[kAdjTP], gim[kAdjTP];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) gacc_re[r] = gacc_im[r] = 0.0;
-
-    for (int tg = 0; tg < n_tiles; tg += kAdjWaves * kAdjTP) {
-      // this wave's tiles
-      int64_t pidx[kAdjTP];
-      float2 ai[kAdjTP];
-      float psv[kAdjTP];
-      double tv[kAdjTP];
-      bool any_tile = false;
+    for (int u = 0; u < kAdjTP; ++u) {
+      gre[u] = floatx16{0};
+      gim[u] = floatx16{0};
+    }
+    for (int n0 = 0; n0 < A.N; n0 += 64) {
+      const int nb = n0 + 32 * half;
+      float2 e[kAdjTP];
 #pragma unroll
-      for (int u = 0; u < kAdjTP; ++u) {
-        int tile = tg + wave * kAdjTP + u;
-        pidx[u] = off0 + (int64_t)tile * 32 + col;
-        bool ok = tile < n_tiles && pidx[u] < off1;
-        any_tile |= tile < n_tiles;
-        ai[u] = ok ? A.a[pidx[u]] : make_float2(0.0f, 0.0f);
-        psv[u] = ok ? A.psi[pidx[u]] : 0.0f;
-        tv[u] = ok ? A.tau[pidx[u]] : 0.0;
-      }
-      floatx16 gre[kAdjTP], gim[kAdjTP];
+      for (int u = 0; u < kAdjTP; ++u) e[u] = expm2pi_f64((A.f0 + (double)nb * A.df) * tv[u]);
+      for (int s4 = 0; s4 < 32; s4 += 4) {
+        float2 h[4];
+        if (row_ok) {
+          load4(rp, nb + s4, A.N, vec, h);
+        } else {
 #pragma unroll
-      for (int u = 0; u < kAdjTP; ++u) {
-        gre[u] = floatx16{0};
-        gim[u] = floatx16{0};
-      }
-      float2 w2[kAdjTP];
-#pragma unroll
-      for (int u = 0; u < kAdjTP; ++u) w2[u] = expm2pi_f64(df2 * tv[u]);
-
-      for (int ch = 0; ch < n_chunks; ++ch) {
-        const int n0 = ch * kAdjChunk;
-        __syncthreads();  // previous chunk fully consumed
-        for (int idx = threadIdx.x; idx < 32 * kAdjChunk; idx += blockDim.x) {
-          int mr = idx / kAdjChunk, j = idx % kAdjChunk;
-          int row = mblk * 32 + mr, n = n0 + j;
-          float2 v = (row < A.M && n < A.N) ? dHl[(int64_t)row * A.N + n] : make_float2(0.0f, 0.0f);
-          sre[mr][j] = v.x;
-          sim[mr][j] = v.y;
+          for (int q = 0; q < 4; ++q) h[q] = make_float2(0.0f, 0.0f);
         }
-        __syncthreads();
-        if (any_tile) {
-          float2 e[kAdjTP];
 #pragma unroll
-          for (int u = 0; u < kAdjTP; ++u)
-            e[u] = expm2pi_f64((A.f0 + (double)(n0 + half) * A.df) * tv[u]);
-          const int steps = kAdjChunk / 2;
-          for (int s2 = 0; s2 < steps; ++s2) {
-            const float hre = sre[col][2 * s2 + half];
-            const float him = sim[col][2 * s2 + half];
+        for (int q = 0; q < 4; ++q) {
 #pragma unroll
-            for (int u = 0; u < kAdjTP; ++u) {
-              // G += dH conj(E):  Re: hre er + him ei,  Im: him er - hre ei
-              gre[u] = mfma32(hre, e[u].x, gre[u]);
-              gre[u] = mfma32(him, e[u].y, gre[u]);
-              gim[u] = mfma32(him, e[u].x, gim[u]);
-              gim[u] = mfma32(-hre, e[u].y, gim[u]);
-              e[u] = cmul(e[u], w2[u]);
+          for (int u = 0; u < kAdjTP; ++u) {
+            // G += dH conj(E):  Re: hre er + him ei,  Im: him er - hre ei
+            gre[u] = mfma32(h[q].x, e[u].x, gre[u]);
+            gre[u] = mfma32(h[q].y, e[u].y, gre[u]);
+            gim[u] = mfma32(h[q].y, e[u].x, gim[u]);
+            gim[u] = mfma32(-h[q].x, e[u].y, gim[u]);
+            e[u] = cmul(e[u], w1[u]);
+          }
+        }
+      }
+    }
+    // epilogue: rows m = mblk*32 + 8(r/4) + 4 half + r%4, column = path
+#pragma unroll
+    for (int u = 0; u < kAdjTP; ++u) {
+      const double psi_cyc = (double)psv[u] * kInv2Pi;
+      float gacc_re[16], gacc_im[16];
+#pragma unroll
+      for (int grp4 = 0; grp4 < 4; ++grp4) {
+        const int mrow0 = mblk * 32 + 8 * grp4 + 4 * half;
+        float2 ph = expm2pi_f64(psi_cyc * ((double)mrow0 - A.cm));  // exp(-j psi (m - c))
+        const float2 step = expm2pi_f64(psi_cyc);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = grp4 * 4 + q;
+          const int mrow = mrow0 + q;
+          if (q > 0) ph = cmul(ph, step);
+          float2 G = make_float2(gre[u][r], gim[u][r]);
+          float2 gm = mrow < A.M ? A.g[mrow] : make_float2(0.0f, 0.0f);
+          float2 Gph = cmul(G, ph);
+          da[u] = cadd(da[u], cmulc(gm, Gph));
+          float2 tg2 = cmulc(ai[u], Gph);
+          gacc_re[r] = tg2.x;
+          gacc_im[r] = tg2.y;
+        }
+      }
+      if (A.g_part) {
+        // sum over the 32 paths of this half (fixed butterfly), add tiles in order
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          float vr = gacc_re[r], vi = gacc_im[r];
+#pragma unroll
+          for (int o = 16; o >= 1; o >>= 1) {
+            vr += __shfl_xor(vr, o, 64);
+            vi += __shfl_xor(vi, o, 64);
+          }
+          const int mrow = mblk * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+          if (col == 0 && mrow < A.M) {
+            double* dst = A.g_part + (w * A.M + mrow) * 2;
+            if (u == 0) {
+              dst[0] = (double)vr;
+              dst[1] = (double)vi;
+            } else {
+              dst[0] += (double)vr;
+              dst[1] += (double)vi;
             }
           }
         }
       }
-
-      // epilogue: dL/da_i and dL/dg partials from G (rows m, columns paths)
-#pragma unroll
-      for (int u = 0; u < kAdjTP; ++u) {
-        float2 da = make_float2(0.0f, 0.0f);
-        const double psi_cyc = (double)psv[u] * kInv2Pi;
-#pragma unroll
-        for (int grp = 0; grp < 4; ++grp) {
-          const int mrow0 = mblk * 32 + 8 * grp + 4 * half;
-          // exp(-j psi (m - c)) for m = mrow0 .. mrow0+3 by a 1-step recurrence
-          float2 ph = expm2pi_f64(psi_cyc * ((double)mrow0 - A.cm));
-          float2 step = expm2pi_f64(psi_cyc);
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int r = grp * 4 + q;
-            const int mrow = mrow0 + q;
-            if (q > 0) ph = cmul(ph, step);
-            float2 G = make_float2(gre[u][r], gim[u][r]);
-            float2 gm = mrow < A.M ? A.g[mrow] : make_float2(0.0f, 0.0f);
-            float2 Gph = cmul(G, ph);
-            // conj(g_m e^{j psi (m-c)}) = conj(g_m) e^{-j psi (m-c)}
-            da = cadd(da, cmulc(gm, Gph));
-            // conj(a_i e^{j psi (m-c)}) = conj(a_i) e^{-j psi (m-c)}
-            float2 tg2 = cmulc(ai[u], Gph);
-            gacc_re[r] += (double)tg2.x;
-            gacc_im[r] += (double)tg2.y;
-          }
-        }
-        da.x += __shfl_xor(da.x, 32, 64);
-        da.y += __shfl_xor(da.y, 32, 64);
-        int tile = tg + wave * kAdjTP + u;
-        if (A.dLda && half == 0 && tile < n_tiles && pidx[u] < off1 && mblk == 0) {
-          A.dLda[pidx[u]] = da;
-        } else if (A.dLda && half == 0 && tile < n_tiles && pidx[u] < off1) {
-          float2 prev = A.dLda[pidx[u]];
-          A.dLda[pidx[u]] = cadd(prev, da);
-        }
-      }
     }
-
-    // reduce dL/dg over the 32 path lanes of each half, then over waves
-    if (A.g_part) {
+  }
+  if (A.dLda) {
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        double vr = gacc_re[r], vi = gacc_im[r];
-#pragma unroll
-        for (int o = 16; o >= 1; o >>= 1) {
-          vr += __shfl_xor(vr, o, 64);
-          vi += __shfl_xor(vi, o, 64);
-        }
-        if (col == 0) {
-          const int mr = 8 * (r >> 2) + 4 * half + (r & 3);
-          gsum[wave][mr][0] = vr;
-          gsum[wave][mr][1] = vi;
-        }
-      }
-      __syncthreads();
-      if (threadIdx.x < 32) {
-        const int mr = threadIdx.x;
-        const int row = mblk * 32 + mr;
-        if (row < A.M) {
-          double sr = 0.0, si = 0.0;
-          for (int w = 0; w < kAdjWaves; ++w) {
-            sr += gsum[w][mr][0];
-            si += gsum[w][mr][1];
-          }
-          A.g_part[(l * A.M + row) * 2 + 0] = sr;
-          A.g_part[(l * A.M + row) * 2 + 1] = si;
-        }
-      }
-      __syncthreads();
+    for (int u = 0; u < kAdjTP; ++u) {
+      float2 d = da[u];
+      d.x += __shfl_xor(d.x, 32, 64);
+      d.y += __shfl_xor(d.y, 32, 64);
+      if (half == 0 && ok[u]) A.dLda[pidx[u]] = d;
     }
   }
 }
@@ -296,13 +342,20 @@ __global__ void to_c64_kernel(const double* v, int M, float2* out) {
   if (m < M) out[m] = make_float2((float)v[2 * m], (float)v[2 * m + 1]);
 }
 
-// Workspace (doubles): per-link dL/dg partials [L][M][2] | reduction tmp |
-// reduced [M][2].
-size_t ws_cfr_adjoint(const rtc_radio* r, int32_t n_links) {
+static int64_t adj_max_waves(int32_t n_links, int32_t n_paths) {
+  // sum over links of ceil(ceil(P_l / 32) / TP) <= n_paths / (32 TP) + n_links
+  return (int64_t)n_paths / (32 * kAdjTP) + n_links + 1;
+}
+
+// Workspace: wave_off int64 [L+1] | per-wave dL/dg partials double
+// [max_waves][M][2] | reduction tmp | reduced [M][2].
+size_t ws_cfr_adjoint(const rtc_radio* r, int32_t n_links, int32_t n_paths) {
   if (r->n_elem < 1) return 0;
   int64_t L = n_links > 0 ? n_links : 1;
+  int64_t W = adj_max_waves(n_links, n_paths);
   int K = 2 * r->n_elem;
-  return ((size_t)L * K + reduce_tmp_doubles(L, K) + K) * sizeof(double);
+  return (size_t)(L + 1) * sizeof(int64_t) +
+         ((size_t)W * K + reduce_tmp_doubles(W, K) + K) * sizeof(double);
 }
 
 static double subcarrier0(const rtc_radio* r) { return r->fc_hz - (double)(r->n_sc / 2) * r->df_hz; }
@@ -358,10 +411,10 @@ extern "C" rtc_status rtc_cfr_adjoint(const rtc_radio* radio, const rtc_paths* p
   RTC_REQUIRE((a != nullptr && psi != nullptr) || paths->n_paths == 0, RTC_ERR_INVALID_ARG,
               "%s: a and psi are required", fn);
   hipStream_t s = as_stream(stream);
-  if (dLdg) {
-    size_t need = ws_cfr_adjoint(radio, paths->n_links);
+  {
+    size_t need = ws_cfr_adjoint(radio, paths->n_links, paths->n_paths);
     RTC_REQUIRE(ws != nullptr && ws_bytes >= need, RTC_ERR_WORKSPACE,
-                "%s: workspace of %zu bytes required for dLdg", fn, need);
+                "%s: workspace of %zu bytes required", fn, need);
   }
   if (paths->n_links == 0) {
     if (dLdg) {
@@ -376,25 +429,34 @@ extern "C" rtc_status rtc_cfr_adjoint(const rtc_radio* radio, const rtc_paths* p
   A.n_links = paths->n_links;
   A.M = radio->n_elem;
   A.N = radio->n_sc;
+  A.max_waves = adj_max_waves(paths->n_links, paths->n_paths);
   A.link_off = paths->link_off;
+  int64_t* wave_off = reinterpret_cast<int64_t*>(ws);
+  A.wave_off = wave_off;
   A.a = reinterpret_cast<const float2*>(a);
   A.psi = psi;
   A.tau = paths->tau;
   A.g = reinterpret_cast<const float2*>(g);
   A.dH = reinterpret_cast<const float2*>(dLdH);
   A.dLda = reinterpret_cast<float2*>(dLda);
-  A.g_part = dLdg ? reinterpret_cast<double*>(ws) : nullptr;
+  double* gpart = reinterpret_cast<double*>(wave_off + (paths->n_links + 1));
+  A.g_part = dLdg ? gpart : nullptr;
   A.f0 = subcarrier0(radio);
   A.df = radio->df_hz;
   A.cm = 0.5 * (double)(radio->n_elem - 1);
-  hipLaunchKernelGGL(cfr_adjoint_kernel, dim3(paths->n_links), dim3(kAdjWaves * 64), 0, s, A);
+  hipLaunchKernelGGL(adj_wave_scan_kernel, dim3(1), dim3(1024), 0, s, paths->link_off,
+                     paths->n_links, wave_off);
+  if ((st = check_launch(fn)) != RTC_OK) return st;
+  const int64_t blocks = (A.max_waves + kAdjWaves - 1) / kAdjWaves;
+  RTC_REQUIRE(blocks < (1ll << 31), RTC_ERR_RANGE, "%s: problem too large for one launch", fn);
+  hipLaunchKernelGGL(cfr_adjoint_kernel, dim3((unsigned)blocks), dim3(kAdjWaves * 64), 0, s, A);
   if ((st = check_launch(fn)) != RTC_OK) return st;
   if (dLdg) {
-    // dL/dg_m = sum over links of the per-link partials, fixed order, FP64
+    // dL/dg_m = sum over waves (links in order) of the partials, fixed order, FP64
     const int K = 2 * A.M;
-    double* tmp = A.g_part + (int64_t)A.n_links * K;
-    double* red = tmp + reduce_tmp_doubles(A.n_links, K);
-    if ((st = reduce_all(A.g_part, A.n_links, K, tmp, red, s, fn)) != RTC_OK) return st;
+    double* tmp = A.g_part + A.max_waves * K;
+    double* red = tmp + reduce_tmp_doubles(A.max_waves, K);
+    if ((st = reduce_all(A.g_part, A.max_waves, K, tmp, red, s, fn)) != RTC_OK) return st;
     hipLaunchKernelGGL(to_c64_kernel, dim3((A.M + 63) / 64), dim3(64), 0, s, red, A.M,
                        reinterpret_cast<float2*>(dLdg));
     return check_launch(fn);

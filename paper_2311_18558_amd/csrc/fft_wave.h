@@ -1,0 +1,245 @@
+// One-wave FFTs of length N = 2^LOGN (2..4096) for the CFR loss.
+//
+// Stockham autosort formulation: pass p (radix R, Ns = product of the radices
+// before it) takes butterfly j (0 <= j < N/R), reads x[j + r N/R], multiplies
+// element r by exp(+-j 2 pi r (j mod Ns) / (Ns R)), applies an R-point DFT
+// and writes element r to (j / Ns) Ns R + (j mod Ns) + r Ns.  After the last
+// pass the output is in natural order.  Radices are 16 while possible, then
+// the remaining 2, 4 or 8.  Butterfly j of every pass belongs to lane j mod 64.
+//
+// Two properties let the loss keep data in registers between transforms:
+//  * the first pass (Ns = 1) reads x[j + r N/R0] and the last pass leaves
+//    element r of butterfly j at index j + r N/R_last;
+//  * running the radices in reverse order, the first pass of the reverse
+//    transform reads exactly the indices the last pass of the forward
+//    transform left in each lane, and vice versa.
+#pragma once
+
+#include "dev_common.h"
+
+namespace rtc {
+
+constexpr int fft_npass(int logn) { return logn / 4 + (logn % 4 != 0 ? 1 : 0); }
+// radix of pass p in the "inverse" order: 16, 16, ..., then the remainder
+constexpr int fft_radix(int logn, int p) {
+  return p < logn / 4 ? 16 : (1 << (logn % 4));
+}
+
+// R-point DFT in registers: X_k = sum_n v_n exp(SIGN j 2 pi n k / R).
+template <int SIGN>
+RTC_DEV void dft2(float2* v) {
+  float2 a = v[0], b = v[1];
+  v[0] = cadd(a, b);
+  v[1] = csub(a, b);
+}
+
+// multiply by SIGN * j
+template <int SIGN>
+RTC_DEV float2 mulj(float2 a) {
+  return SIGN > 0 ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+
+template <int SIGN>
+RTC_DEV void dft4(float2& v0, float2& v1, float2& v2, float2& v3) {
+  float2 t0 = cadd(v0, v2), t1 = csub(v0, v2);
+  float2 t2 = cadd(v1, v3), t3 = mulj<SIGN>(csub(v1, v3));
+  v0 = cadd(t0, t2);
+  v2 = csub(t0, t2);
+  v1 = cadd(t1, t3);
+  v3 = csub(t1, t3);
+}
+
+template <int SIGN>
+RTC_DEV void dft8(float2* v) {
+  // n = 2 n1 + n2, k = k1 + 4 k2
+  constexpr float h = 0.70710678118654752440f;
+  float2 u0[4] = {v[0], v[2], v[4], v[6]};
+  float2 u1[4] = {v[1], v[3], v[5], v[7]};
+  dft4<SIGN>(u0[0], u0[1], u0[2], u0[3]);
+  dft4<SIGN>(u1[0], u1[1], u1[2], u1[3]);
+  // u1[k1] *= exp(SIGN j 2 pi k1 / 8)
+  u1[1] = cmul(u1[1], make_float2(h, SIGN * h));
+  u1[2] = mulj<SIGN>(u1[2]);
+  u1[3] = cmul(u1[3], make_float2(-h, SIGN * h));
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    v[k1] = cadd(u0[k1], u1[k1]);
+    v[k1 + 4] = csub(u0[k1], u1[k1]);
+  }
+}
+
+template <int SIGN>
+RTC_DEV void dft16(float2* v) {
+  // n = 4 n1 + n2, k = k1 + 4 k2
+  constexpr float c1 = 0.92387953251128675613f, s1 = 0.38268343236508977173f;
+  constexpr float h = 0.70710678118654752440f;
+  float2 u[4][4];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    u[n2][0] = v[n2];
+    u[n2][1] = v[4 + n2];
+    u[n2][2] = v[8 + n2];
+    u[n2][3] = v[12 + n2];
+    dft4<SIGN>(u[n2][0], u[n2][1], u[n2][2], u[n2][3]);
+  }
+  // u[n2][k1] *= exp(SIGN j 2 pi n2 k1 / 16), n2 k1 in {1, 2, 3, 4, 6, 9}
+  const float2 w1 = make_float2(c1, SIGN * s1);
+  const float2 w2 = make_float2(h, SIGN * h);
+  const float2 w3 = make_float2(s1, SIGN * c1);
+  const float2 w6 = make_float2(-h, SIGN * h);
+  const float2 w9 = make_float2(-c1, -SIGN * s1);
+  u[1][1] = cmul(u[1][1], w1);
+  u[1][2] = cmul(u[1][2], w2);
+  u[1][3] = cmul(u[1][3], w3);
+  u[2][1] = cmul(u[2][1], w2);
+  u[2][2] = mulj<SIGN>(u[2][2]);
+  u[2][3] = cmul(u[2][3], w6);
+  u[3][1] = cmul(u[3][1], w3);
+  u[3][2] = cmul(u[3][2], w6);
+  u[3][3] = cmul(u[3][3], w9);
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    float2 a = u[0][k1], b = u[1][k1], c = u[2][k1], d = u[3][k1];
+    dft4<SIGN>(a, b, c, d);
+    v[k1] = a;
+    v[k1 + 4] = b;
+    v[k1 + 8] = c;
+    v[k1 + 12] = d;
+  }
+}
+
+template <int R, int SIGN>
+RTC_DEV void dft(float2* v) {
+  if constexpr (R == 2) dft2<SIGN>(v);
+  if constexpr (R == 4) dft4<SIGN>(v[0], v[1], v[2], v[3]);
+  if constexpr (R == 8) dft8<SIGN>(v);
+  if constexpr (R == 16) dft16<SIGN>(v);
+}
+
+// Butterflies per lane for a pass of radix R over N points.
+constexpr int fft_bpl(int n, int r) { return (n / r + 63) / 64; }
+
+// Twiddle of pass (Ns, R) for butterfly j: element r times w^r,
+// w = exp(SIGN j 2 pi (j mod Ns) / (Ns R)).
+template <int R, int SIGN>
+RTC_DEV void fft_twiddle(float2* v, int j, int Ns) {
+  if (Ns == 1) return;
+  const int k = j % Ns;
+  float s, c;
+  sincos2pi((float)k / (float)(Ns * R), &s, &c);  // exact fraction for powers of two
+  const float2 w = make_float2(c, SIGN * s);
+  float2 wr = w;
+#pragma unroll
+  for (int r = 1; r < R; ++r) {
+    v[r] = cmul(v[r], wr);
+    wr = cmul(wr, w);
+  }
+}
+
+// Pass from registers (v[i][r] of butterfly j = lane + 64 i) to LDS `out`.
+template <int N, int R, int SIGN>
+RTC_DEV void fft_pass_r2l(float2 (*v)[R], float2* out, int Ns, int lane) {
+  constexpr int B = N / R;
+#pragma unroll
+  for (int i = 0; i < fft_bpl(N, R); ++i) {
+    const int j = lane + 64 * i;
+    if (j < B) {
+      fft_twiddle<R, SIGN>(v[i], j, Ns);
+      dft<R, SIGN>(v[i]);
+      const int d = (j / Ns) * Ns * R + (j % Ns);
+#pragma unroll
+      for (int r = 0; r < R; ++r) out[d + r * Ns] = v[i][r];
+    }
+  }
+}
+
+// Pass from LDS `in` to registers v[i][r] (no store).
+template <int N, int R, int SIGN>
+RTC_DEV void fft_pass_l2r(const float2* in, float2 (*v)[R], int Ns, int lane) {
+  constexpr int B = N / R;
+#pragma unroll
+  for (int i = 0; i < fft_bpl(N, R); ++i) {
+    const int j = lane + 64 * i;
+    if (j < B) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[i][r] = in[j + r * B];
+      fft_twiddle<R, SIGN>(v[i], j, Ns);
+      dft<R, SIGN>(v[i]);
+    }
+  }
+}
+
+// Radix and Ns of position P in a pass sequence: ORDER = +1 runs the radices
+// as fft_radix lists them, ORDER = -1 in reverse.
+template <int LOGN, int ORDER, int P>
+constexpr int seq_radix() {
+  return fft_radix(LOGN, ORDER > 0 ? P : fft_npass(LOGN) - 1 - P);
+}
+template <int LOGN, int ORDER, int P>
+constexpr int seq_ns() {
+  if constexpr (P == 0)
+    return 1;
+  else
+    return seq_ns<LOGN, ORDER, P - 1>() * seq_radix<LOGN, ORDER, P - 1>();
+}
+
+// Pass P (1 <= P <= npass-2): LDS -> LDS, ping-ponging b0/b1 (pass 0
+// writes b0), then the following middle passes.
+template <int LOGN, int SIGN, int ORDER, int P>
+RTC_DEV void fft_mid(float2* b0, float2* b1, int lane) {
+  constexpr int NP = fft_npass(LOGN);
+  if constexpr (P <= NP - 2) {
+    constexpr int N = 1 << LOGN;
+    constexpr int R = seq_radix<LOGN, ORDER, P>();
+    constexpr int NS = seq_ns<LOGN, ORDER, P>();
+    const float2* in = ((P - 1) & 1) ? b1 : b0;
+    float2* out = (P & 1) ? b1 : b0;
+    __syncthreads();
+    float2 v[fft_bpl(N, R)][R];
+    fft_pass_l2r<N, R, SIGN>(in, v, NS, lane);
+#pragma unroll
+    for (int i = 0; i < fft_bpl(N, R); ++i) {
+      const int j = lane + 64 * i;
+      if (j < N / R) {
+        const int d = (j / NS) * NS * R + (j % NS);
+#pragma unroll
+        for (int r = 0; r < R; ++r) out[d + r * NS] = v[i][r];
+      }
+    }
+    fft_mid<LOGN, SIGN, ORDER, P + 1>(b0, b1, lane);
+  }
+}
+
+// Whole transform: vin holds the first pass's inputs (butterfly j = lane +
+// 64 i, element r = x[j + r N/R_first]); vout receives the last pass's
+// outputs (element r of butterfly j = X[j + r N/R_last]).  b0, b1: two LDS
+// buffers of N values.
+template <int LOGN, int SIGN, int ORDER, int J0, int R0, int JL, int RL>
+RTC_DEV void fft_full(float2 (&vin)[J0][R0], float2 (&vout)[JL][RL], float2* b0, float2* b1,
+                      int lane) {
+  constexpr int N = 1 << LOGN;
+  constexpr int NP = fft_npass(LOGN);
+  static_assert(R0 == seq_radix<LOGN, ORDER, 0>(), "first-pass layout");
+  static_assert(RL == seq_radix<LOGN, ORDER, NP - 1>(), "last-pass layout");
+  static_assert(J0 == fft_bpl(N, R0) && JL == fft_bpl(N, RL), "butterflies per lane");
+  if constexpr (NP == 1) {
+#pragma unroll
+    for (int i = 0; i < fft_bpl(N, R0); ++i) {
+      if (lane + 64 * i < N / R0) {
+        dft<R0, SIGN>(vin[i]);
+#pragma unroll
+        for (int r = 0; r < R0; ++r) vout[i][r] = vin[i][r];
+      }
+    }
+  } else {
+    fft_pass_r2l<N, R0, SIGN>(vin, b0, 1, lane);
+    fft_mid<LOGN, SIGN, ORDER, 1>(b0, b1, lane);
+    constexpr int PL = NP - 1;
+    const float2* in = ((PL - 1) & 1) ? b1 : b0;
+    __syncthreads();
+    fft_pass_l2r<N, RL, SIGN>(in, vout, seq_ns<LOGN, ORDER, PL>(), lane);
+    __syncthreads();
+  }
+}
+
+}  // namespace rtc

@@ -17,6 +17,7 @@
 
 #include "api_common.h"
 #include "dev_common.h"
+#include "fft_wave.h"
 
 namespace rtc {
 
@@ -194,6 +195,148 @@ __global__ void __launch_bounds__(kLossBlock)
   }
 }
 
+// ----------------------------------------------------------- one-wave rows
+// For N <= 1024 one wave owns a row: the H and H* rows are read straight
+// into the first FFT pass, the last inverse pass leaves the taps in
+// registers where p, p* and the gradient source are formed, and the forward
+// transform (radices reversed) starts from those registers and ends with
+// dL/dH in the row's natural order, next to H - H* kept from the load.
+constexpr int kWaveMaxLogN = 10;
+
+template <int LOGN>
+__global__ void __launch_bounds__(64)
+    cfr_loss_wave_kernel(const float2* H, const float2* __restrict__ Ht, int64_t n_rows,
+                         const double* Z, float w_coh, float w_pdp, double* row_out,
+                         float2* dLdH) {
+  constexpr int N = 1 << LOGN;
+  constexpr int NP = fft_npass(LOGN);
+  constexpr int RA = fft_radix(LOGN, 0), RZ = fft_radix(LOGN, NP - 1);
+  constexpr int JA = fft_bpl(N, RA), JZ = fft_bpl(N, RZ);
+  constexpr int BA = N / RA, BZ = N / RZ;
+  __shared__ float2 b0[N], b1[N];
+  const int lane = threadIdx.x;
+  const float invN = 1.0f / (float)N;
+  float gc = 0.0f, gp = 0.0f;
+  if (dLdH) {
+    gc = (float)(2.0 * (double)w_coh / Z[0]);
+    gp = (float)(4.0 * (double)w_pdp / (Z[1] * (double)N));
+  }
+  for (int64_t row = blockIdx.x; row < n_rows; row += gridDim.x) {
+    const float2* hs = H + row * N;
+    const float2* ts = Ht + row * N;
+    float2 vh[JA][RA], vt[JA][RA], diff[JA][RA];
+    float ec = 0.0f, et = 0.0f;
+#pragma unroll
+    for (int i = 0; i < JA; ++i) {
+      const int j = lane + 64 * i;
+      if (j < BA) {
+#pragma unroll
+        for (int r = 0; r < RA; ++r) {
+          float2 h = hs[j + r * BA];
+          float2 t = ts[j + r * BA];
+          vh[i][r] = h;
+          vt[i][r] = t;
+          diff[i][r] = csub(h, t);
+          ec += cabs2(diff[i][r]);
+          et += cabs2(t);
+        }
+      }
+    }
+    float2 xh[JZ][RZ], xt[JZ][RZ];
+    fft_full<LOGN, +1, +1>(vh, xh, b0, b1, lane);
+    fft_full<LOGN, +1, +1>(vt, xt, b0, b1, lane);
+    float ep = 0.0f, eq = 0.0f;
+    float2 g[JZ][RZ];
+#pragma unroll
+    for (int i = 0; i < JZ; ++i) {
+      const int j = lane + 64 * i;
+      if (j < BZ) {
+#pragma unroll
+        for (int r = 0; r < RZ; ++r) {
+          float p = cabs2(xh[i][r]) * invN;
+          float pt = cabs2(xt[i][r]) * invN;
+          float d = p - pt;
+          ep += d * d;
+          eq += pt * pt;
+          g[i][r] = cscale(xh[i][r], gp * d);
+        }
+      }
+    }
+    double s1 = wave_sum_f64((double)ec);
+    double s2 = wave_sum_f64((double)et);
+    double s3 = wave_sum_f64((double)ep);
+    double s4 = wave_sum_f64((double)eq);
+    if (lane == 0) {
+      row_out[row * 4 + 0] = s1;
+      row_out[row * 4 + 1] = s2;
+      row_out[row * 4 + 2] = s3;
+      row_out[row * 4 + 3] = s4;
+    }
+    if (dLdH) {
+      float2 G[JA][RA];
+      fft_full<LOGN, -1, -1>(g, G, b0, b1, lane);
+      float2* out = dLdH + row * N;
+#pragma unroll
+      for (int i = 0; i < JA; ++i) {
+        const int j = lane + 64 * i;
+        if (j < BA) {
+#pragma unroll
+          for (int r = 0; r < RA; ++r) out[j + r * BA] = cadd(cscale(diff[i][r], gc), G[i][r]);
+        }
+      }
+    }
+  }
+}
+
+template <int LOGN>
+__global__ void __launch_bounds__(64)
+    target_stats_wave_kernel(const float2* __restrict__ Ht, int64_t n_rows, double* row_out) {
+  constexpr int N = 1 << LOGN;
+  constexpr int NP = fft_npass(LOGN);
+  constexpr int RA = fft_radix(LOGN, 0), RZ = fft_radix(LOGN, NP - 1);
+  constexpr int JA = fft_bpl(N, RA), JZ = fft_bpl(N, RZ);
+  constexpr int BA = N / RA, BZ = N / RZ;
+  __shared__ float2 b0[N], b1[N];
+  const int lane = threadIdx.x;
+  const float invN = 1.0f / (float)N;
+  for (int64_t row = blockIdx.x; row < n_rows; row += gridDim.x) {
+    const float2* ts = Ht + row * N;
+    float2 vt[JA][RA];
+    float et = 0.0f;
+#pragma unroll
+    for (int i = 0; i < JA; ++i) {
+      const int j = lane + 64 * i;
+      if (j < BA) {
+#pragma unroll
+        for (int r = 0; r < RA; ++r) {
+          vt[i][r] = ts[j + r * BA];
+          et += cabs2(vt[i][r]);
+        }
+      }
+    }
+    float2 xt[JZ][RZ];
+    fft_full<LOGN, +1, +1>(vt, xt, b0, b1, lane);
+    float eq = 0.0f;
+#pragma unroll
+    for (int i = 0; i < JZ; ++i) {
+      const int j = lane + 64 * i;
+      if (j < BZ) {
+#pragma unroll
+        for (int r = 0; r < RZ; ++r) {
+          float pt = cabs2(xt[i][r]) * invN;
+          eq += pt * pt;
+        }
+      }
+    }
+    double se = wave_sum_f64((double)et);
+    double sq = wave_sum_f64((double)eq);
+    if (lane == 0) {
+      row_out[row * 2 + 0] = se;
+      row_out[row * 2 + 1] = sq;
+    }
+  }
+}
+
 // Fixed-order reduction of [R][K] doubles into [ceil(R/kRedChunk)][K].
 __global__ void __launch_bounds__(kRedBlock)
     reduce_rows_kernel(const double* in, int64_t R, int K, double* out) {
@@ -273,6 +416,51 @@ static unsigned row_grid(int64_t R) {
   return (unsigned)(g > 0 ? g : 1);
 }
 
+static unsigned wave_grid(int64_t R) {
+  int64_t g = R < 40960 ? R : 40960;
+  return (unsigned)(g > 0 ? g : 1);
+}
+
+static void launch_target_stats(int logN, const float2* Ht, int64_t R, double* rows,
+                                hipStream_t s) {
+  int N = 1 << logN;
+  switch (logN) {
+#define RTC_TS(L)                                                                            \
+  case L:                                                                                    \
+    hipLaunchKernelGGL(target_stats_wave_kernel<L>, dim3(wave_grid(R)), dim3(64), 0, s, Ht, \
+                       R, rows);                                                             \
+    return;
+    RTC_TS(1) RTC_TS(2) RTC_TS(3) RTC_TS(4) RTC_TS(5) RTC_TS(6) RTC_TS(7) RTC_TS(8) RTC_TS(9)
+    RTC_TS(10)
+#undef RTC_TS
+    default: {
+      size_t shm = (size_t)(N / 2 + N) * sizeof(float2);
+      hipLaunchKernelGGL(target_stats_kernel, dim3(row_grid(R)), dim3(kLossBlock), shm, s, Ht, R,
+                         N, logN, rows);
+    }
+  }
+}
+
+static void launch_loss(int logN, const float2* H, const float2* Ht, int64_t R, const double* Z,
+                        float w_coh, float w_pdp, double* rows, float2* dLdH, hipStream_t s) {
+  int N = 1 << logN;
+  switch (logN) {
+#define RTC_LW(L)                                                                             \
+  case L:                                                                                     \
+    hipLaunchKernelGGL(cfr_loss_wave_kernel<L>, dim3(wave_grid(R)), dim3(64), 0, s, H, Ht, R, \
+                       Z, w_coh, w_pdp, rows, dLdH);                                          \
+    return;
+    RTC_LW(1) RTC_LW(2) RTC_LW(3) RTC_LW(4) RTC_LW(5) RTC_LW(6) RTC_LW(7) RTC_LW(8) RTC_LW(9)
+    RTC_LW(10)
+#undef RTC_LW
+    default: {
+      size_t shm = (size_t)(N / 2 + 2 * N) * sizeof(float2);
+      hipLaunchKernelGGL(cfr_loss_kernel, dim3(row_grid(R)), dim3(kLossBlock), shm, s, H, Ht, R, N,
+                         logN, Z, w_coh, w_pdp, rows, dLdH);
+    }
+  }
+}
+
 }  // namespace rtc
 
 using namespace rtc;
@@ -300,9 +488,8 @@ extern "C" rtc_status rtc_cfr_target_stats(const rtc_radio* radio, int32_t n_lin
   double* rows = reinterpret_cast<double*>(ws);
   double* red = rows + R * 4;
   int N = radio->n_sc, logN = ilog2(N);
-  size_t shm = (size_t)(N / 2 + N) * sizeof(float2);
-  hipLaunchKernelGGL(target_stats_kernel, dim3(row_grid(R)), dim3(kLossBlock), shm, s,
-                     reinterpret_cast<const float2*>(H_tgt), R, N, logN, rows);
+  (void)N;
+  launch_target_stats(logN, reinterpret_cast<const float2*>(H_tgt), R, rows, s);
   if ((st = check_launch(fn)) != RTC_OK) return st;
   return reduce_all(rows, R, 2, red, stats, s, fn);
 }
@@ -331,17 +518,14 @@ extern "C" rtc_status rtc_cfr_loss(const rtc_radio* radio, int32_t n_links, cons
   int N = radio->n_sc, logN = ilog2(N);
   const double* Zuse = tgt_stats;
   if (dLdH && !tgt_stats) {
-    size_t shm = (size_t)(N / 2 + N) * sizeof(float2);
-    hipLaunchKernelGGL(target_stats_kernel, dim3(row_grid(R)), dim3(kLossBlock), shm, s,
-                       reinterpret_cast<const float2*>(H_tgt), R, N, logN, rows);
+    launch_target_stats(logN, reinterpret_cast<const float2*>(H_tgt), R, rows, s);
     if ((st = check_launch(fn)) != RTC_OK) return st;
     if ((st = reduce_all(rows, R, 2, red, Z, s, fn)) != RTC_OK) return st;
     Zuse = Z;
   }
-  size_t shm = (size_t)(N / 2 + 2 * N) * sizeof(float2);
-  hipLaunchKernelGGL(cfr_loss_kernel, dim3(row_grid(R)), dim3(kLossBlock), shm, s,
-                     reinterpret_cast<const float2*>(H), reinterpret_cast<const float2*>(H_tgt), R,
-                     N, logN, Zuse, w_coh, w_pdp, rows, reinterpret_cast<float2*>(dLdH));
+  (void)N;
+  launch_loss(logN, reinterpret_cast<const float2*>(H), reinterpret_cast<const float2*>(H_tgt), R,
+              Zuse, w_coh, w_pdp, rows, reinterpret_cast<float2*>(dLdH), s);
   if ((st = check_launch(fn)) != RTC_OK) return st;
   if ((st = reduce_all(rows, R, 4, red, sums, s, fn)) != RTC_OK) return st;
   hipLaunchKernelGGL(loss_finish_kernel, dim3(1), dim3(64), 0, s, sums, Zuse, w_coh, w_pdp, loss);
