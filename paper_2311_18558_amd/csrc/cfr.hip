@@ -1,42 +1,38 @@
-// Channel frequency response and its adjoint on the FP32 matrix cores.
+// Channel frequency response and its adjoint on the matrix cores.
 //
 // For one link l the CFR is a complex matrix product
 //     H_l[m, n] = sum_i B[m, i] E[i, n],
 //     B[m, i] = a_i g_m exp(j psi_i (m - c)),  E[i, n] = exp(-j 2 pi f_n tau_i),
 // with M elements, N subcarriers and P_l paths (Eq. cfr_cont, Sec. II-A).
-// Both operands are generated in registers, one value per lane, and fed to
-// v_mfma_f32_32x32x2_f32 (A: 32 rows x 2 k, B: 2 k x 32 columns, lane l
-// holds A[l%32][l/32] and B[l/32][l%32]; D row 8(r/4)+4(l/32)+r%4, column
-// l%32 in register r).  The complex product is split into four real MFMAs
-// that share operands without any lane exchange: the two k-slices are two
-// different paths, lane l owns path i+l/32 and computes B for row l%32 and
-// E for column l%32, and
-//     Re H += B_re E_re + (-B_im) E_im,   Im H += B_im E_re + B_re E_im.
+// Both operands are generated in registers and fed to
+// v_mfma_f32_32x32x16_bf16 as three-way BF16 splits (six partial products
+// per real product, FP32 accumulation; see split_bf16.h), which keeps FP32
+// accuracy at the BF16 instruction rate.  A lane holds eight k values of its
+// row (A) or column (B): in the forward product k runs over paths, so lane l
+// generates B for row l%32 and E for column l%32 over paths 8(l/32)..+7 of a
+// 16-path chunk; the complex product takes four real products,
+//     Re H += B_re E_re + (-B_im) E_im,   Im H += B_re E_im + B_im E_re.
 // The subcarrier phase f_n tau_i (thousands of cycles) is reduced in FP64;
 // within a wave, tile t+1 is tile t times exp(-j 2 pi 32 df tau_i).
 //
 // The adjoint G[m, i] = sum_n dLdH[m, n] conj(E[i, n]) is the same kind of
-// product with the subcarriers as the contraction axis; each lane reads its
-// dL/dH row directly, and E advances by exp(-j 2 pi df tau_i) from an FP64
-// anchor every 32 subcarriers.
+// product with the subcarriers as the contraction axis: lane l reads eight
+// consecutive subcarriers of its dL/dH row and generates E for its path over
+// the same subcarriers by the recurrence exp(-j 2 pi df tau_i) from an FP64
+// anchor.
 #include <cmath>
 
 #include "api_common.h"
 #include "dev_common.h"
+#include "split_bf16.h"
 
 namespace rtc {
 
-typedef float floatx16 __attribute__((ext_vector_type(16)));
-
 constexpr int kCfrWaves = 4;   // waves per workgroup (forward)
-constexpr int kCfrTiles = 4;   // 32-subcarrier tiles per wave (forward)
+constexpr int kCfrTiles = 8;   // 32-subcarrier tiles per wave (forward)
 constexpr int kAdjWaves = 4;   // waves per workgroup (adjoint)
 constexpr int kAdjTP = 2;      // 32-path tiles per wave (adjoint)
 constexpr double kInv2Pi = 0.15915494309189533577;
-
-RTC_DEV floatx16 mfma32(float a, float b, floatx16 c) {
-  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
-}
 
 struct CfrArgs {
   int n_links, M, N;
@@ -51,7 +47,25 @@ struct CfrArgs {
   double cm;    // (M-1)/2
 };
 
+// Four accumulator chains advance together (two tiles, real and imaginary
+// parts), so consecutive MFMAs are independent.
+RTC_DEV void cfr_tile_pair(const Split3& BR, const Split3& BI, const Split3& NBI,
+                           const Split3& ER0, const Split3& EI0, const Split3& ER1,
+                           const Split3& EI1, floatx16& re0, floatx16& im0, floatx16& re1,
+                           floatx16& im1) {
+  re0 = mac6(BR, ER0, re0);
+  im0 = mac6(BR, EI0, im0);
+  re1 = mac6(BR, ER1, re1);
+  im1 = mac6(BR, EI1, im1);
+  re0 = mac6(NBI, EI0, re0);
+  im0 = mac6(BI, ER0, im0);
+  re1 = mac6(NBI, EI1, re1);
+  im1 = mac6(BI, ER1, im1);
+}
+
+// One wave per (link, 32-row element block, kCfrTiles x 32 subcarriers).
 __global__ void __launch_bounds__(kCfrWaves * 64) cfr_kernel(CfrArgs A, float2* __restrict__ H) {
+  static_assert(kCfrTiles % 2 == 0, "tiles are processed in pairs");
   const int lane = threadIdx.x & 63;
   const int half = lane >> 5;
   const int col = lane & 31;
@@ -78,30 +92,72 @@ __global__ void __launch_bounds__(kCfrWaves * 64) cfr_kernel(CfrArgs A, float2* 
     acc_im[t] = floatx16{0};
   }
 
-  for (int64_t i0 = off0; i0 < off1; i0 += 2) {
-    const int64_t i = i0 + half;
-    float2 ai = make_float2(0.0f, 0.0f);
-    float ps = 0.0f;
-    double ti = 0.0;
-    if (i < off1) {
-      ai = A.a[i];
-      ps = A.psi[i];
-      ti = A.tau[i];
-    }
-    // A operand: B[m, i] = a_i g_m exp(j psi_i (m - c))
-    double ph = (double)ps * mc_cyc;
-    float2 arr = expm2pi_f64(-ph);  // exp(+j 2 pi ph)
-    float2 b = cmul(cmul(ai, gm), arr);
-    // B operand: E[i, n] for the lane's subcarrier in each tile
-    float2 e = expm2pi_f64(f_lane * ti);
-    float2 w = expm2pi_f64(df32 * ti);
+  // The lane's eight paths of a 16-path chunk.  Software pipeline: while
+  // the MFMAs of chunk k run, the wave loads the path data of chunk k+1 and
+  // generates its operands (the FP64-reduced exponentials), so the matrix
+  // cores are not idle during that VALU work.  Loads clamp to the link's
+  // last path (always a valid address) and padding paths get a = 0.
+  auto fetch = [&](int64_t c0, float2 (&pa)[8], float (&pp)[8], double (&pt)[8]) {
+    const int64_t p0 = c0 + 8 * half;
 #pragma unroll
-    for (int t = 0; t < kCfrTiles; ++t) {
-      if (t > 0) e = cmul(e, w);
-      acc_re[t] = mfma32(b.x, e.x, acc_re[t]);
-      acc_re[t] = mfma32(-b.y, e.y, acc_re[t]);
-      acc_im[t] = mfma32(b.y, e.x, acc_im[t]);
-      acc_im[t] = mfma32(b.x, e.y, acc_im[t]);
+    for (int j = 0; j < 8; ++j) {
+      const int64_t p = p0 + j;
+      const int64_t pc = p < off1 ? p : off1 - 1;
+      const float2 av = A.a[pc];
+      pa[j] = p < off1 ? av : make_float2(0.0f, 0.0f);
+      pp[j] = A.psi[pc];
+      pt[j] = A.tau[pc];
+    }
+  };
+  // A operand B[m, i] = a_i g_m exp(j psi_i (m - c)); B operand anchor
+  // E[i, n] at the lane's subcarrier of tile 0 and the tile step w_i
+  auto operands = [&](const float2 (&pa)[8], const float (&pp)[8], const double (&pt)[8],
+                      float (&br)[8], float (&bi)[8], float2 (&ev)[8], float2 (&wv)[8]) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const float2 arr = expm2pi_f64(-(double)pp[j] * mc_cyc);
+      const float2 b = cmul(cmul(pa[j], gm), arr);
+      br[j] = b.x;
+      bi[j] = b.y;
+      ev[j] = expm2pi_f64(f_lane * pt[j]);
+      wv[j] = expm2pi_f64(df32 * pt[j]);
+    }
+  };
+  if (off0 < off1) {
+    float br[8], bi[8];
+    float2 ev[8], wv[8];
+    {
+      float2 pa[8];
+      float pp[8];
+      double pt[8];
+      fetch(off0, pa, pp, pt);
+      operands(pa, pp, pt, br, bi, ev, wv);
+    }
+    for (int64_t c0 = off0; c0 < off1; c0 += 16) {
+      // next chunk (a clamped, unused load past the last chunk)
+      float2 pa[8];
+      float pp[8];
+      double pt[8];
+      fetch(c0 + 16, pa, pp, pt);
+      const Split3 BR = split3(br), BI = split3(bi), NBI = neg3(BI);
+#pragma unroll
+      for (int t = 0; t < kCfrTiles; t += 2) {
+        float er0[8], ei0[8], er1[8], ei1[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          if (t > 0) ev[j] = cmul(ev[j], wv[j]);
+          er0[j] = ev[j].x;
+          ei0[j] = ev[j].y;
+          ev[j] = cmul(ev[j], wv[j]);
+          er1[j] = ev[j].x;
+          ei1[j] = ev[j].y;
+        }
+        const Split3 ER0 = split3(er0), EI0 = split3(ei0);
+        const Split3 ER1 = split3(er1), EI1 = split3(ei1);
+        cfr_tile_pair(BR, BI, NBI, ER0, EI0, ER1, EI1, acc_re[t], acc_im[t], acc_re[t + 1],
+                      acc_im[t + 1]);
+      }
+      operands(pa, pp, pt, br, bi, ev, wv);
     }
   }
 
@@ -173,113 +229,104 @@ __global__ void __launch_bounds__(1024) adj_wave_scan_kernel(const int64_t* link
   if (t == 1023) wave_off[n_links] = acc;
 }
 
-__device__ __forceinline__ void load4(const float2* row, int n, int N, bool vec, float2 h[4]) {
-  if (vec && n + 3 < N) {
+// Eight consecutive values of a dL/dH row starting at subcarrier n (zero
+// beyond N or for a padding row); vec: 16-byte aligned rows.
+__device__ __forceinline__ void load8(const float2* row, int n, int N, bool vec, bool ok,
+                                      float2 (&h)[8]) {
+  if (ok && vec && n + 7 < N) {
     const float4* p = reinterpret_cast<const float4*>(row + n);
-    float4 x = p[0], y = p[1];
-    h[0] = make_float2(x.x, x.y);
-    h[1] = make_float2(x.z, x.w);
-    h[2] = make_float2(y.x, y.y);
-    h[3] = make_float2(y.z, y.w);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float4 x = p[q];
+      h[2 * q] = make_float2(x.x, x.y);
+      h[2 * q + 1] = make_float2(x.z, x.w);
+    }
   } else {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) h[q] = (n + q < N) ? row[n + q] : make_float2(0.0f, 0.0f);
+    for (int j = 0; j < 8; ++j) h[j] = (ok && n + j < N) ? row[n + j] : make_float2(0.0f, 0.0f);
   }
 }
 
-__global__ void __launch_bounds__(kAdjWaves * 64) cfr_adjoint_kernel(AdjArgs A) {
-  const int lane = threadIdx.x & 63;
+// Contraction of one wave over NT (1 or 2) consecutive 32-path tiles of link
+// l, starting at tile grp * kAdjTP; the caller picks NT = 1 for a link's
+// last wave when it holds a single tile, so no MFMA runs on empty tiles.
+template <int NT>
+__device__ __forceinline__ void adj_wave(const AdjArgs& A, int64_t w, int64_t l, int grp,
+                                         int lane) {
   const int half = lane >> 5;
   const int col = lane & 31;
-  const int64_t w = (int64_t)blockIdx.x * kAdjWaves + (threadIdx.x >> 6);
-  if (w >= A.max_waves) return;
-  const int64_t total = A.wave_off[A.n_links];
-  if (w >= total) {
-    // surplus wave: its dL/dg partial row is zero
-    if (A.g_part)
-      for (int m = lane; m < A.M; m += 64) {
-        A.g_part[(w * A.M + m) * 2 + 0] = 0.0;
-        A.g_part[(w * A.M + m) * 2 + 1] = 0.0;
-      }
-    return;
-  }
-  int lo = 0, hi = A.n_links - 1;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (A.wave_off[mid] <= w)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  const int64_t l = lo;
-  const int grp = (int)(w - A.wave_off[l]);
   const int64_t off0 = A.link_off[l];
   const int64_t off1 = A.link_off[l + 1];
-  const int n_tiles = (int)((off1 - off0 + 31) / 32);
   const int n_mblk = (A.M + 31) / 32;
-  const bool vec = (A.N & 3) == 0;
+  const bool vec = (A.N & 1) == 0 && (reinterpret_cast<uintptr_t>(A.dH) & 15) == 0;
   const float2* dHl = A.dH + l * (int64_t)A.M * A.N;
 
-  int64_t pidx[kAdjTP];
-  bool ok[kAdjTP];
-  float2 ai[kAdjTP];
-  float psv[kAdjTP];
-  double tv[kAdjTP];
-  float2 w1[kAdjTP];
+  int64_t pidx[NT];
+  bool ok[NT];
+  float2 ai[NT];
+  float psv[NT];
+  double tv[NT];
+  float2 w1[NT];
 #pragma unroll
-  for (int u = 0; u < kAdjTP; ++u) {
+  for (int u = 0; u < NT; ++u) {
     const int tile = grp * kAdjTP + u;
     pidx[u] = off0 + (int64_t)tile * 32 + col;
-    ok[u] = tile < n_tiles && pidx[u] < off1;
+    ok[u] = pidx[u] < off1;
     ai[u] = ok[u] ? A.a[pidx[u]] : make_float2(0.0f, 0.0f);
     psv[u] = ok[u] ? A.psi[pidx[u]] : 0.0f;
     tv[u] = ok[u] ? A.tau[pidx[u]] : 0.0;
     w1[u] = expm2pi_f64(A.df * tv[u]);
   }
-  float2 da[kAdjTP];
+  float2 da[NT];
 #pragma unroll
-  for (int u = 0; u < kAdjTP; ++u) da[u] = make_float2(0.0f, 0.0f);
+  for (int u = 0; u < NT; ++u) da[u] = make_float2(0.0f, 0.0f);
 
   for (int mblk = 0; mblk < n_mblk; ++mblk) {
     const int row = mblk * 32 + col;
     const bool row_ok = row < A.M;
     const float2* rp = dHl + (int64_t)(row_ok ? row : 0) * A.N;
-    floatx16 gre[kAdjTP], gim[kAdjTP];
+    floatx16 gre[NT], gim[NT];
 #pragma unroll
-    for (int u = 0; u < kAdjTP; ++u) {
+    for (int u = 0; u < NT; ++u) {
       gre[u] = floatx16{0};
       gim[u] = floatx16{0};
     }
-    for (int n0 = 0; n0 < A.N; n0 += 64) {
-      const int nb = n0 + 32 * half;
-      float2 e[kAdjTP];
+    // 16-subcarrier chunks: lane l takes subcarriers n0 + 8(l/32) + j of its
+    // dL/dH row (A) and of its path's exponential (B); the next chunk's row
+    // values are loaded while the current chunk's MFMAs run
+    float2 hv[8];
+    load8(rp, 8 * half, A.N, vec, row_ok, hv);
+    for (int n0 = 0; n0 < A.N; n0 += 16) {
+      float hr[8], hi[8];
 #pragma unroll
-      for (int u = 0; u < kAdjTP; ++u) e[u] = expm2pi_f64((A.f0 + (double)nb * A.df) * tv[u]);
-      for (int s4 = 0; s4 < 32; s4 += 4) {
-        float2 h[4];
-        if (row_ok) {
-          load4(rp, nb + s4, A.N, vec, h);
-        } else {
+      for (int j = 0; j < 8; ++j) {
+        hr[j] = hv[j].x;
+        hi[j] = hv[j].y;
+      }
+      if (n0 + 16 < A.N) load8(rp, n0 + 16 + 8 * half, A.N, vec, row_ok, hv);
+      const Split3 HR = split3(hr), HI = split3(hi), NHR = neg3(HR);
+      const double f_l = A.f0 + (double)(n0 + 8 * half) * A.df;
 #pragma unroll
-          for (int q = 0; q < 4; ++q) h[q] = make_float2(0.0f, 0.0f);
+      for (int u = 0; u < NT; ++u) {
+        float2 e = expm2pi_f64(f_l * tv[u]);
+        float er[8], ei[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          er[j] = e.x;
+          ei[j] = e.y;
+          if (j < 7) e = cmul(e, w1[u]);
         }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-#pragma unroll
-          for (int u = 0; u < kAdjTP; ++u) {
-            // G += dH conj(E):  Re: hre er + him ei,  Im: him er - hre ei
-            gre[u] = mfma32(h[q].x, e[u].x, gre[u]);
-            gre[u] = mfma32(h[q].y, e[u].y, gre[u]);
-            gim[u] = mfma32(h[q].y, e[u].x, gim[u]);
-            gim[u] = mfma32(-h[q].x, e[u].y, gim[u]);
-            e[u] = cmul(e[u], w1[u]);
-          }
-        }
+        const Split3 ER = split3(er), EI = split3(ei);
+        // G += dH conj(E):  Re: hre er + him ei,  Im: him er - hre ei
+        gre[u] = mac6(HR, ER, gre[u]);
+        gim[u] = mac6(HI, ER, gim[u]);
+        gre[u] = mac6(HI, EI, gre[u]);
+        gim[u] = mac6(NHR, EI, gim[u]);
       }
     }
     // epilogue: rows m = mblk*32 + 8(r/4) + 4 half + r%4, column = path
 #pragma unroll
-    for (int u = 0; u < kAdjTP; ++u) {
+    for (int u = 0; u < NT; ++u) {
       const double psi_cyc = (double)psv[u] * kInv2Pi;
       float gacc_re[16], gacc_im[16];
 #pragma unroll
@@ -328,13 +375,44 @@ __global__ void __launch_bounds__(kAdjWaves * 64) cfr_adjoint_kernel(AdjArgs A) 
   }
   if (A.dLda) {
 #pragma unroll
-    for (int u = 0; u < kAdjTP; ++u) {
+    for (int u = 0; u < NT; ++u) {
       float2 d = da[u];
       d.x += __shfl_xor(d.x, 32, 64);
       d.y += __shfl_xor(d.y, 32, 64);
       if (half == 0 && ok[u]) A.dLda[pidx[u]] = d;
     }
   }
+}
+
+__global__ void __launch_bounds__(kAdjWaves * 64, 2) cfr_adjoint_kernel(AdjArgs A) {
+  const int lane = threadIdx.x & 63;
+  const int64_t w = (int64_t)blockIdx.x * kAdjWaves + (threadIdx.x >> 6);
+  if (w >= A.max_waves) return;
+  const int64_t total = A.wave_off[A.n_links];
+  if (w >= total) {
+    // surplus wave: its dL/dg partial row is zero
+    if (A.g_part)
+      for (int m = lane; m < A.M; m += 64) {
+        A.g_part[(w * A.M + m) * 2 + 0] = 0.0;
+        A.g_part[(w * A.M + m) * 2 + 1] = 0.0;
+      }
+    return;
+  }
+  int lo = 0, hi = A.n_links - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (A.wave_off[mid] <= w)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const int64_t l = lo;
+  const int grp = (int)(w - A.wave_off[l]);
+  const int n_tiles = (int)((A.link_off[l + 1] - A.link_off[l] + 31) / 32);
+  if (grp * kAdjTP + 1 < n_tiles)
+    adj_wave<2>(A, w, l, grp, lane);
+  else
+    adj_wave<1>(A, w, l, grp, lane);
 }
 
 __global__ void to_c64_kernel(const double* v, int M, float2* out) {

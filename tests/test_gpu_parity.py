@@ -146,6 +146,7 @@ def test_cfr_parity(rl, case):
     rl.cfr(_radio_c(rl, radio), dp, a32.cuda(), p32.cuda(), g32.cuda(), H)
     torch.cuda.synchronize()
     err = _link_rel_err(H.cpu(), H_ref)
+    say(f"cfr {case}: max per-link relative error {err:.2e}")
     assert err <= 1e-5, err
 
 
@@ -256,6 +257,7 @@ def test_cfr_adjoint_parity(rl, case):
         ea = (torch.linalg.norm(dLda.cpu().to(c128) - da_ref) / torch.linalg.norm(da_ref)).item()
         assert ea <= 1e-5, ea
         per = _per_link_rel(dLda.cpu().to(c128), da_ref, st.link_off)
+        say(f"cfr_adjoint {case}: dL/da error {ea:.2e} (max per link {per:.2e})")
         assert per <= 1e-5, per
     eg = (torch.linalg.norm(dLdg.cpu().to(c128) - dg_ref) / torch.linalg.norm(dg_ref)).item()
     assert eg <= 1e-5, eg
