@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define RTC_ABI_VERSION 1
+#define RTC_ABI_VERSION 2
 
 typedef enum {
   RTC_OK = 0,
@@ -163,21 +163,28 @@ rtc_status rtc_cfr(const rtc_radio* radio, const rtc_paths* paths, const void* a
 /* Target energies of a batch of CFR rows (n_rows = n_links * n_elem rows of
  * n_sc subcarriers): stats[0] = sum |H*|^2, stats[1] = sum (p*)^2 with p* the
  * power delay profile p_l = |h[l]|^2 of the centred 1/sqrt(N) IDFT
- * (Sec. II-A).  stats: device double [2].  n_sc must be a power of two,
- * 2 <= n_sc <= 4096. */
+ * (Sec. II-A).  stats: device double [2].  p_tgt: NULL, or device float
+ * [n_rows * n_sc] that receives p* per row in storage order,
+ * p_tgt[row, k] = |X_k|^2 / N with X_k = sum_n H*[n] exp(+j 2 pi n k / N)
+ * (the centred taps up to their order), for later rtc_cfr_loss calls on the
+ * same targets.  n_sc must be a power of two, 2 <= n_sc <= 4096. */
 rtc_status rtc_cfr_target_stats(const rtc_radio* radio, int32_t n_links, const void* H_tgt,
-                                double* stats, void* ws, size_t ws_bytes, void* stream);
+                                double* stats, float* p_tgt, void* ws, size_t ws_bytes,
+                                void* stream);
 
 /* Coherent + power-delay-profile loss over a batch (workload loss):
  *   L = w_coh * sum|H - H*|^2 / sum|H*|^2 + w_pdp * sum (p - p*)^2 / sum (p*)^2
  * H, H_tgt: c64 [n_links, n_elem, n_sc].  tgt_stats: device double [2] from
  * rtc_cfr_target_stats for the same H_tgt, or NULL to compute it here.
+ * p_tgt: the target PDP written by rtc_cfr_target_stats for the same H_tgt
+ * (saves one transform per row), or NULL to derive it from H_tgt.
  * loss: device double [3] = {L, coherent term, PDP term} (unweighted terms).
  * dLdH: c64 like H or NULL; it may alias H (in-place).  n_sc must be a power
  * of two, 2 <= n_sc <= 4096. */
 rtc_status rtc_cfr_loss(const rtc_radio* radio, int32_t n_links, const void* H,
-                        const void* H_tgt, const double* tgt_stats, float w_coh, float w_pdp,
-                        double* loss, void* dLdH, void* ws, size_t ws_bytes, void* stream);
+                        const void* H_tgt, const double* tgt_stats, const float* p_tgt,
+                        float w_coh, float w_pdp, double* loss, void* dLdH, void* ws,
+                        size_t ws_bytes, void* stream);
 
 /* Adjoint of rtc_cfr:
  *   G[m, i]  = sum_n dLdH[l(i), m, n] exp(+j 2 pi f_n tau_i)

@@ -20,6 +20,12 @@
 namespace rtc {
 
 constexpr int fft_npass(int logn) { return logn / 4 + (logn % 4 != 0 ? 1 : 0); }
+
+// LDS rows are padded by one value per 16: the first pass writes each
+// butterfly's R outputs contiguously (lane stride R values), which would put
+// every lane of a wave on the same bank; the pad spreads them.
+RTC_DEV constexpr int lds_pad(int i) { return i + (i >> 4); }
+constexpr int fft_lds_len(int n) { return n + n / 16; }
 // radix of pass p in the "inverse" order: 16, 16, ..., then the remainder
 constexpr int fft_radix(int logn, int p) {
   return p < logn / 4 ? 16 : (1 << (logn % 4));
@@ -148,7 +154,7 @@ RTC_DEV void fft_pass_r2l(float2 (*v)[R], float2* out, int Ns, int lane) {
       dft<R, SIGN>(v[i]);
       const int d = (j / Ns) * Ns * R + (j % Ns);
 #pragma unroll
-      for (int r = 0; r < R; ++r) out[d + r * Ns] = v[i][r];
+      for (int r = 0; r < R; ++r) out[lds_pad(d + r * Ns)] = v[i][r];
     }
   }
 }
@@ -162,7 +168,7 @@ RTC_DEV void fft_pass_l2r(const float2* in, float2 (*v)[R], int Ns, int lane) {
     const int j = lane + 64 * i;
     if (j < B) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[i][r] = in[j + r * B];
+      for (int r = 0; r < R; ++r) v[i][r] = in[lds_pad(j + r * B)];
       fft_twiddle<R, SIGN>(v[i], j, Ns);
       dft<R, SIGN>(v[i]);
     }
@@ -203,7 +209,7 @@ RTC_DEV void fft_mid(float2* b0, float2* b1, int lane) {
       if (j < N / R) {
         const int d = (j / NS) * NS * R + (j % NS);
 #pragma unroll
-        for (int r = 0; r < R; ++r) out[d + r * NS] = v[i][r];
+        for (int r = 0; r < R; ++r) out[lds_pad(d + r * NS)] = v[i][r];
       }
     }
     fft_mid<LOGN, SIGN, ORDER, P + 1>(b0, b1, lane);
@@ -213,7 +219,7 @@ RTC_DEV void fft_mid(float2* b0, float2* b1, int lane) {
 // Whole transform: vin holds the first pass's inputs (butterfly j = lane +
 // 64 i, element r = x[j + r N/R_first]); vout receives the last pass's
 // outputs (element r of butterfly j = X[j + r N/R_last]).  b0, b1: two LDS
-// buffers of N values.
+// buffers of fft_lds_len(N) values.
 template <int LOGN, int SIGN, int ORDER, int J0, int R0, int JL, int RL>
 RTC_DEV void fft_full(float2 (&vin)[J0][R0], float2 (&vout)[JL][RL], float2* b0, float2* b1,
                       int lane) {

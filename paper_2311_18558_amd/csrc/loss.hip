@@ -73,10 +73,10 @@ RTC_DEV double block_sum_f64(double v, double* red) {
   return s;
 }
 
-// Target statistics per row: {sum |H*|^2, sum (p*)^2}.
+// Target statistics per row: {sum |H*|^2, sum (p*)^2}; with Pt also p*.
 __global__ void __launch_bounds__(kLossBlock)
     target_stats_kernel(const float2* __restrict__ Ht, int64_t n_rows, int N, int logN,
-                        double* row_out) {
+                        double* row_out, float* Pt) {
   extern __shared__ float2 sm[];
   float2* tw = sm;
   float2* xt = sm + N / 2;
@@ -97,6 +97,7 @@ __global__ void __launch_bounds__(kLossBlock)
     for (int k = threadIdx.x; k < N; k += blockDim.x) {
       float p = cabs2(xt[k]) * invN;
       q += p * p;
+      if (Pt) Pt[row * N + k] = p;
     }
     double se = block_sum_f64((double)e, red);
     double sq = block_sum_f64((double)q, red);
@@ -198,23 +199,23 @@ __global__ void __launch_bounds__(kLossBlock)
 // ----------------------------------------------------------- one-wave rows
 // For N <= 1024 one wave owns a row: the H and H* rows are read straight
 // into the first FFT pass, the last inverse pass leaves the taps in
-// registers where p, p* and the gradient source are formed, and the forward
-// transform (radices reversed) starts from those registers and ends with
-// dL/dH in the row's natural order, next to H - H* kept from the load.
+// dL/dH in the row's natural order, next to H - H* kept from the load.  The
+// Stockham passes ping-pong between two LDS row buffers.  With PT the target
+// PDP comes precomputed (p_tgt from the target statistics) instead of from a
+// transform of H*.
 constexpr int kWaveMaxLogN = 10;
 
-template <int LOGN>
+template <int LOGN, bool PT>
 __global__ void __launch_bounds__(64)
-    cfr_loss_wave_kernel(const float2* H, const float2* __restrict__ Ht, int64_t n_rows,
-                         const double* Z, float w_coh, float w_pdp, double* row_out,
-                         float2* dLdH) {
+    cfr_loss_wave_kernel(const float2* H, const float2* __restrict__ Ht,
+                         const float* __restrict__ Pt, int64_t n_rows, const double* Z,
+                         float w_coh, float w_pdp, double* row_out, float2* dLdH) {
   constexpr int N = 1 << LOGN;
   constexpr int NP = fft_npass(LOGN);
   constexpr int RA = fft_radix(LOGN, 0), RZ = fft_radix(LOGN, NP - 1);
   constexpr int JA = fft_bpl(N, RA), JZ = fft_bpl(N, RZ);
   constexpr int BA = N / RA, BZ = N / RZ;
-  __shared__ float2 b0[N], b1[N];
-  const int lane = threadIdx.x;
+  __shared__ float2 b0[fft_lds_len(N)], b1[fft_lds_len(N)];
   const float invN = 1.0f / (float)N;
   float gc = 0.0f, gp = 0.0f;
   if (dLdH) {
@@ -222,43 +223,64 @@ __global__ void __launch_bounds__(64)
     gp = (float)(4.0 * (double)w_pdp / (Z[1] * (double)N));
   }
   for (int64_t row = blockIdx.x; row < n_rows; row += gridDim.x) {
+    int lane = threadIdx.x;
+    asm volatile("" : "+v"(lane));  // twiddles per row, not held across rows
     const float2* hs = H + row * N;
     const float2* ts = Ht + row * N;
-    float2 vh[JA][RA], vt[JA][RA], diff[JA][RA];
     float ec = 0.0f, et = 0.0f;
+    float pt[JZ][RZ];
+    if constexpr (PT) {
+      const float* ps = Pt + row * N;
+#pragma unroll
+      for (int i = 0; i < JZ; ++i) {
+        const int j = lane + 64 * i;
+#pragma unroll
+        for (int r = 0; r < RZ; ++r) pt[i][r] = j < BZ ? ps[j + r * BZ] : 0.0f;
+      }
+    } else {
+      float2 vt[JA][RA], xt[JZ][RZ];
+#pragma unroll
+      for (int i = 0; i < JA; ++i) {
+        const int j = lane + 64 * i;
+#pragma unroll
+        for (int r = 0; r < RA; ++r)
+          vt[i][r] = j < BA ? ts[j + r * BA] : make_float2(0.0f, 0.0f);
+      }
+      fft_full<LOGN, +1, +1>(vt, xt, b0, b1, lane);
+#pragma unroll
+      for (int i = 0; i < JZ; ++i) {
+#pragma unroll
+        for (int r = 0; r < RZ; ++r) pt[i][r] = cabs2(xt[i][r]) * invN;
+      }
+    }
+    float2 vh[JA][RA], diff[JA][RA];
 #pragma unroll
     for (int i = 0; i < JA; ++i) {
       const int j = lane + 64 * i;
-      if (j < BA) {
 #pragma unroll
-        for (int r = 0; r < RA; ++r) {
-          float2 h = hs[j + r * BA];
-          float2 t = ts[j + r * BA];
-          vh[i][r] = h;
-          vt[i][r] = t;
-          diff[i][r] = csub(h, t);
-          ec += cabs2(diff[i][r]);
-          et += cabs2(t);
-        }
+      for (int r = 0; r < RA; ++r) {
+        const float2 h = j < BA ? hs[j + r * BA] : make_float2(0.0f, 0.0f);
+        const float2 t = j < BA ? ts[j + r * BA] : make_float2(0.0f, 0.0f);
+        vh[i][r] = h;
+        diff[i][r] = csub(h, t);
+        ec += cabs2(diff[i][r]);
+        et += cabs2(t);
       }
     }
-    float2 xh[JZ][RZ], xt[JZ][RZ];
+    float2 xh[JZ][RZ];
     fft_full<LOGN, +1, +1>(vh, xh, b0, b1, lane);
-    fft_full<LOGN, +1, +1>(vt, xt, b0, b1, lane);
     float ep = 0.0f, eq = 0.0f;
-    float2 g[JZ][RZ];
 #pragma unroll
     for (int i = 0; i < JZ; ++i) {
       const int j = lane + 64 * i;
       if (j < BZ) {
 #pragma unroll
         for (int r = 0; r < RZ; ++r) {
-          float p = cabs2(xh[i][r]) * invN;
-          float pt = cabs2(xt[i][r]) * invN;
-          float d = p - pt;
+          const float p = cabs2(xh[i][r]) * invN;
+          const float d = p - pt[i][r];
           ep += d * d;
-          eq += pt * pt;
-          g[i][r] = cscale(xh[i][r], gp * d);
+          eq += pt[i][r] * pt[i][r];
+          xh[i][r] = cscale(xh[i][r], gp * d);  // gradient source
         }
       }
     }
@@ -274,7 +296,7 @@ __global__ void __launch_bounds__(64)
     }
     if (dLdH) {
       float2 G[JA][RA];
-      fft_full<LOGN, -1, -1>(g, G, b0, b1, lane);
+      fft_full<LOGN, -1, -1>(xh, G, b0, b1, lane);
       float2* out = dLdH + row * N;
 #pragma unroll
       for (int i = 0; i < JA; ++i) {
@@ -288,15 +310,18 @@ __global__ void __launch_bounds__(64)
   }
 }
 
+// Target statistics per row {sum |H*|^2, sum (p*)^2}; with Pt also the
+// target PDP p* (natural tap order) for later loss calls.
 template <int LOGN>
 __global__ void __launch_bounds__(64)
-    target_stats_wave_kernel(const float2* __restrict__ Ht, int64_t n_rows, double* row_out) {
+    target_stats_wave_kernel(const float2* __restrict__ Ht, int64_t n_rows, double* row_out,
+                             float* Pt) {
   constexpr int N = 1 << LOGN;
   constexpr int NP = fft_npass(LOGN);
   constexpr int RA = fft_radix(LOGN, 0), RZ = fft_radix(LOGN, NP - 1);
   constexpr int JA = fft_bpl(N, RA), JZ = fft_bpl(N, RZ);
   constexpr int BA = N / RA, BZ = N / RZ;
-  __shared__ float2 b0[N], b1[N];
+  __shared__ float2 b0[fft_lds_len(N)], b1[fft_lds_len(N)];
   const int lane = threadIdx.x;
   const float invN = 1.0f / (float)N;
   for (int64_t row = blockIdx.x; row < n_rows; row += gridDim.x) {
@@ -323,8 +348,9 @@ __global__ void __launch_bounds__(64)
       if (j < BZ) {
 #pragma unroll
         for (int r = 0; r < RZ; ++r) {
-          float pt = cabs2(xt[i][r]) * invN;
+          const float pt = cabs2(xt[i][r]) * invN;
           eq += pt * pt;
+          if (Pt) Pt[row * N + j + r * BZ] = pt;
         }
       }
     }
@@ -421,14 +447,14 @@ static unsigned wave_grid(int64_t R) {
   return (unsigned)(g > 0 ? g : 1);
 }
 
-static void launch_target_stats(int logN, const float2* Ht, int64_t R, double* rows,
+static void launch_target_stats(int logN, const float2* Ht, int64_t R, double* rows, float* Pt,
                                 hipStream_t s) {
   int N = 1 << logN;
   switch (logN) {
 #define RTC_TS(L)                                                                            \
   case L:                                                                                    \
     hipLaunchKernelGGL(target_stats_wave_kernel<L>, dim3(wave_grid(R)), dim3(64), 0, s, Ht, \
-                       R, rows);                                                             \
+                       R, rows, Pt);                                                         \
     return;
     RTC_TS(1) RTC_TS(2) RTC_TS(3) RTC_TS(4) RTC_TS(5) RTC_TS(6) RTC_TS(7) RTC_TS(8) RTC_TS(9)
     RTC_TS(10)
@@ -436,19 +462,25 @@ static void launch_target_stats(int logN, const float2* Ht, int64_t R, double* r
     default: {
       size_t shm = (size_t)(N / 2 + N) * sizeof(float2);
       hipLaunchKernelGGL(target_stats_kernel, dim3(row_grid(R)), dim3(kLossBlock), shm, s, Ht, R,
-                         N, logN, rows);
+                         N, logN, rows, Pt);
     }
   }
 }
 
-static void launch_loss(int logN, const float2* H, const float2* Ht, int64_t R, const double* Z,
-                        float w_coh, float w_pdp, double* rows, float2* dLdH, hipStream_t s) {
+// The transform-per-row kernel for N > 1024 recomputes p* from H* (Pt unused).
+static void launch_loss(int logN, const float2* H, const float2* Ht, const float* Pt, int64_t R,
+                        const double* Z, float w_coh, float w_pdp, double* rows, float2* dLdH,
+                        hipStream_t s) {
   int N = 1 << logN;
   switch (logN) {
-#define RTC_LW(L)                                                                             \
-  case L:                                                                                     \
-    hipLaunchKernelGGL(cfr_loss_wave_kernel<L>, dim3(wave_grid(R)), dim3(64), 0, s, H, Ht, R, \
-                       Z, w_coh, w_pdp, rows, dLdH);                                          \
+#define RTC_LW(L)                                                                               \
+  case L:                                                                                       \
+    if (Pt)                                                                                     \
+      hipLaunchKernelGGL((cfr_loss_wave_kernel<L, true>), dim3(wave_grid(R)), dim3(64), 0, s, H, \
+                         Ht, Pt, R, Z, w_coh, w_pdp, rows, dLdH);                               \
+    else                                                                                        \
+      hipLaunchKernelGGL((cfr_loss_wave_kernel<L, false>), dim3(wave_grid(R)), dim3(64), 0, s,   \
+                         H, Ht, Pt, R, Z, w_coh, w_pdp, rows, dLdH);                            \
     return;
     RTC_LW(1) RTC_LW(2) RTC_LW(3) RTC_LW(4) RTC_LW(5) RTC_LW(6) RTC_LW(7) RTC_LW(8) RTC_LW(9)
     RTC_LW(10)
@@ -472,8 +504,8 @@ static rtc_status check_fft_n(const rtc_radio* r, const char* fn) {
 }
 
 extern "C" rtc_status rtc_cfr_target_stats(const rtc_radio* radio, int32_t n_links,
-                                           const void* H_tgt, double* stats, void* ws,
-                                           size_t ws_bytes, void* stream) {
+                                           const void* H_tgt, double* stats, float* p_tgt,
+                                           void* ws, size_t ws_bytes, void* stream) {
   const char* fn = "rtc_cfr_target_stats";
   rtc_status st;
   if ((st = check_radio(radio, fn)) != RTC_OK) return st;
@@ -489,15 +521,15 @@ extern "C" rtc_status rtc_cfr_target_stats(const rtc_radio* radio, int32_t n_lin
   double* red = rows + R * 4;
   int N = radio->n_sc, logN = ilog2(N);
   (void)N;
-  launch_target_stats(logN, reinterpret_cast<const float2*>(H_tgt), R, rows, s);
+  launch_target_stats(logN, reinterpret_cast<const float2*>(H_tgt), R, rows, p_tgt, s);
   if ((st = check_launch(fn)) != RTC_OK) return st;
   return reduce_all(rows, R, 2, red, stats, s, fn);
 }
 
 extern "C" rtc_status rtc_cfr_loss(const rtc_radio* radio, int32_t n_links, const void* H,
-                                   const void* H_tgt, const double* tgt_stats, float w_coh,
-                                   float w_pdp, double* loss, void* dLdH, void* ws,
-                                   size_t ws_bytes, void* stream) {
+                                   const void* H_tgt, const double* tgt_stats,
+                                   const float* p_tgt, float w_coh, float w_pdp, double* loss,
+                                   void* dLdH, void* ws, size_t ws_bytes, void* stream) {
   const char* fn = "rtc_cfr_loss";
   rtc_status st;
   if ((st = check_radio(radio, fn)) != RTC_OK) return st;
@@ -518,14 +550,14 @@ extern "C" rtc_status rtc_cfr_loss(const rtc_radio* radio, int32_t n_links, cons
   int N = radio->n_sc, logN = ilog2(N);
   const double* Zuse = tgt_stats;
   if (dLdH && !tgt_stats) {
-    launch_target_stats(logN, reinterpret_cast<const float2*>(H_tgt), R, rows, s);
+    launch_target_stats(logN, reinterpret_cast<const float2*>(H_tgt), R, rows, nullptr, s);
     if ((st = check_launch(fn)) != RTC_OK) return st;
     if ((st = reduce_all(rows, R, 2, red, Z, s, fn)) != RTC_OK) return st;
     Zuse = Z;
   }
   (void)N;
-  launch_loss(logN, reinterpret_cast<const float2*>(H), reinterpret_cast<const float2*>(H_tgt), R,
-              Zuse, w_coh, w_pdp, rows, reinterpret_cast<float2*>(dLdH), s);
+  launch_loss(logN, reinterpret_cast<const float2*>(H), reinterpret_cast<const float2*>(H_tgt),
+              p_tgt, R, Zuse, w_coh, w_pdp, rows, reinterpret_cast<float2*>(dLdH), s);
   if ((st = check_launch(fn)) != RTC_OK) return st;
   if ((st = reduce_all(rows, R, 4, red, sums, s, fn)) != RTC_OK) return st;
   hipLaunchKernelGGL(loss_finish_kernel, dim3(1), dim3(64), 0, s, sums, Zuse, w_coh, w_pdp, loss);

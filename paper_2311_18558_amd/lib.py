@@ -61,9 +61,9 @@ _SIGS = {
     "rtc_cfr": (ctypes.c_int, [ctypes.POINTER(Radio), ctypes.POINTER(Paths), c_vp, c_vp, c_vp,
                                c_vp, c_vp]),
     "rtc_cfr_target_stats": (ctypes.c_int, [ctypes.POINTER(Radio), c_i32, c_vp, c_vp, c_vp,
-                                            c_size, c_vp]),
-    "rtc_cfr_loss": (ctypes.c_int, [ctypes.POINTER(Radio), c_i32, c_vp, c_vp, c_vp, c_f32, c_f32,
-                                    c_vp, c_vp, c_vp, c_size, c_vp]),
+                                            c_vp, c_size, c_vp]),
+    "rtc_cfr_loss": (ctypes.c_int, [ctypes.POINTER(Radio), c_i32, c_vp, c_vp, c_vp, c_vp, c_f32,
+                                    c_f32, c_vp, c_vp, c_vp, c_size, c_vp]),
     "rtc_cfr_adjoint": (ctypes.c_int, [ctypes.POINTER(Radio), ctypes.POINTER(Paths), c_vp, c_vp,
                                        c_vp, c_vp, c_vp, c_vp, c_vp, c_size, c_vp]),
     "rtc_trace_fields_adjoint": (ctypes.c_int, [ctypes.POINTER(Radio), ctypes.POINTER(Paths),
@@ -216,16 +216,19 @@ def cfr(radio, paths, a, psi, g, H, stream=None):
                           _ptr(H), _stream(stream)), "rtc_cfr")
 
 
-def cfr_target_stats(radio, n_links, H_tgt, stats, ws, stream=None):
+def cfr_target_stats(radio, n_links, H_tgt, stats, ws, stream=None, p_tgt=None):
+    """p_tgt: optional float32 [n_links*n_elem*n_sc] receiving the target PDP."""
     _check(load().rtc_cfr_target_stats(ctypes.byref(radio), n_links, _ptr(H_tgt), _ptr(stats),
-                                       _ptr(ws), ws.numel(), _stream(stream)),
+                                       _ptr(p_tgt), _ptr(ws), ws.numel(), _stream(stream)),
            "rtc_cfr_target_stats")
 
 
-def cfr_loss(radio, n_links, H, H_tgt, tgt_stats, w_coh, w_pdp, loss, dLdH, ws, stream=None):
+def cfr_loss(radio, n_links, H, H_tgt, tgt_stats, w_coh, w_pdp, loss, dLdH, ws, stream=None,
+             p_tgt=None):
+    """p_tgt: optional target PDP from cfr_target_stats for the same H_tgt."""
     _check(load().rtc_cfr_loss(ctypes.byref(radio), n_links, _ptr(H), _ptr(H_tgt), _ptr(tgt_stats),
-                               float(w_coh), float(w_pdp), _ptr(loss), _ptr(dLdH), _ptr(ws),
-                               ws.numel(), _stream(stream)), "rtc_cfr_loss")
+                               _ptr(p_tgt), float(w_coh), float(w_pdp), _ptr(loss), _ptr(dLdH),
+                               _ptr(ws), ws.numel(), _stream(stream)), "rtc_cfr_loss")
 
 
 def cfr_adjoint(radio, paths, a, psi, g, dLdH, dLda, dLdg, ws, stream=None):

@@ -57,15 +57,18 @@ class Pipeline:
                 self.H if out is None else out, self.stream)
 
     def set_target(self, H_tgt):
-        """Targets for the loss; their energies are computed once here
-        (they do not change while calibrating on this batch)."""
+        """Targets for the loss; their energies and power delay profiles are
+        computed once here (they do not change while calibrating on this
+        batch)."""
         self.H_tgt = H_tgt
         self.tgt_stats = torch.empty(2, dtype=torch.float64, device=self.dev)
-        lib.cfr_target_stats(self.radio, self.L, H_tgt, self.tgt_stats, self.ws_loss, self.stream)
+        self.p_tgt = torch.empty(H_tgt.shape, dtype=torch.float32, device=self.dev)
+        lib.cfr_target_stats(self.radio, self.L, H_tgt, self.tgt_stats, self.ws_loss, self.stream,
+                             p_tgt=self.p_tgt)
 
     def loss_and_grad(self):
         lib.cfr_loss(self.radio, self.L, self.H, self.H_tgt, self.tgt_stats, 1.0, 1.0,
-                     self.loss, self.H, self.ws_loss, self.stream)
+                     self.loss, self.H, self.ws_loss, self.stream, p_tgt=self.p_tgt)
 
     def cfr_adjoint(self):
         lib.cfr_adjoint(self.radio, self.paths, self.a, self.psi, self.g, self.H, self.dLda,

@@ -68,11 +68,11 @@ def test_loss_needs_power_of_two_and_workspace(lib):
     r = lib.make_radio(3.5e9, 1e5, 200, 1)
     loss = ctypes.c_void_p(16)
     st = so.rtc_cfr_loss(ctypes.byref(r), 4, ctypes.c_void_p(16), ctypes.c_void_p(32), None,
-                         1.0, 1.0, loss, None, None, 0, None)
+                         None, 1.0, 1.0, loss, None, None, 0, None)
     assert st == -6 and b"power of two" in so.rtc_last_error()
     r = _radio(lib)
     st = so.rtc_cfr_loss(ctypes.byref(r), 4, ctypes.c_void_p(16), ctypes.c_void_p(32), None,
-                         1.0, 1.0, loss, None, ctypes.c_void_p(64), 8, None)
+                         None, 1.0, 1.0, loss, None, ctypes.c_void_p(64), 8, None)
     assert st == -4 and b"workspace" in so.rtc_last_error()
 
 

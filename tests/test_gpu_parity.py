@@ -172,30 +172,27 @@ def _pow2_cases():
     return [c for c in CASES if (CASES[c][2].n_sc & (CASES[c][2].n_sc - 1)) == 0]
 
 
-@pytest.mark.parametrize("case", _pow2_cases())
-@pytest.mark.parametrize("given_stats", [False, True])
-def test_cfr_loss_parity(rl, case, given_stats):
-    st, raw, radio, g = CASES[case]
-    rng = np.random.default_rng(5)
-    L, M, N = st.n_links, radio.n_elem, radio.n_sc
-    Ht = (rng.normal(size=(L, M, N)) + 1j * rng.normal(size=(L, M, N))).astype(np.complex64) * 1e-3
-    H = (Ht + (rng.normal(size=(L, M, N)) + 1j * rng.normal(size=(L, M, N))).astype(np.complex64)
-         * 3e-4).astype(np.complex64)
-    say(f"cfr_loss {case} given_stats={given_stats}")
+def _loss_check(rl, radio, L, Ht, H, mode):
+    """mode: 'none' (the loss call derives everything from H*), 'stats'
+    (target energies given), 'stats_pdp' (energies and target PDP given)."""
+    M, N = radio.n_elem, radio.n_sc
     rc = _radio_c(rl, radio)
     Hd = torch.tensor(H, device="cuda")
     Htd = torch.tensor(Ht, device="cuda")
     ws = rl.workspace(rl.RTC_OP_CFR_LOSS, rc, L, 0)
-    stats = None
-    if given_stats:
+    stats = p_tgt = None
+    if mode != "none":
         stats = torch.empty(2, dtype=torch.float64, device="cuda")
-        rl.cfr_target_stats(rc, L, Htd, stats, ws)
+        if mode == "stats_pdp":
+            p_tgt = torch.full((L, M, N), float("nan"), dtype=torch.float32, device="cuda")
+        rl.cfr_target_stats(rc, L, Htd, stats, ws, p_tgt=p_tgt)
     loss = torch.empty(3, dtype=torch.float64, device="cuda")
     dLdH = torch.empty_like(Hd)
-    rl.cfr_loss(rc, L, Hd, Htd, stats, 0.7, 1.3, loss, dLdH, ws)
+    rl.cfr_loss(rc, L, Hd, Htd, stats, 0.7, 1.3, loss, dLdH, ws, p_tgt=p_tgt)
     torch.cuda.synchronize()
     Hr = torch.tensor(H, dtype=c128, requires_grad=True)
-    tot, coh, inc = och.cfr_loss(Hr, torch.tensor(Ht, dtype=c128), 0.7, 1.3)
+    Ht64 = torch.tensor(Ht, dtype=c128)
+    tot, coh, inc = och.cfr_loss(Hr, Ht64, 0.7, 1.3)
     (gH,) = torch.autograd.grad(tot, Hr)
     lg = loss.cpu()
     assert abs(lg[0].item() - tot.item()) <= 1e-5 * abs(tot.item())
@@ -203,11 +200,42 @@ def test_cfr_loss_parity(rl, case, given_stats):
     assert abs(lg[2].item() - inc.item()) <= 1e-5 * abs(inc.item())
     rel = (torch.linalg.norm(dLdH.cpu().to(c128) - gH) / torch.linalg.norm(gH)).item()
     assert rel <= 1e-5, rel
-    if given_stats:
+    if mode != "none":
         Z = stats.cpu()
-        zc = (torch.tensor(Ht, dtype=c128).abs() ** 2).sum().item()
-        zp = (och.pdp(torch.tensor(Ht, dtype=c128)) ** 2).sum().item()
+        zc = (Ht64.abs() ** 2).sum().item()
+        pt_ref = och.pdp(Ht64)
+        zp = (pt_ref ** 2).sum().item()
         assert abs(Z[0].item() - zc) <= 1e-6 * zc and abs(Z[1].item() - zp) <= 1e-5 * zp
+    if mode == "stats_pdp":
+        ep = (torch.linalg.norm(p_tgt.cpu().double() - pt_ref) / torch.linalg.norm(pt_ref)).item()
+        assert ep <= 1e-6, ep
+
+
+@pytest.mark.parametrize("case", _pow2_cases())
+@pytest.mark.parametrize("mode", ["none", "stats", "stats_pdp"])
+def test_cfr_loss_parity(rl, case, mode):
+    st, raw, radio, g = CASES[case]
+    rng = np.random.default_rng(5)
+    L, M, N = st.n_links, radio.n_elem, radio.n_sc
+    Ht = (rng.normal(size=(L, M, N)) + 1j * rng.normal(size=(L, M, N))).astype(np.complex64) * 1e-3
+    H = (Ht + (rng.normal(size=(L, M, N)) + 1j * rng.normal(size=(L, M, N))).astype(np.complex64)
+         * 3e-4).astype(np.complex64)
+    say(f"cfr_loss {case} mode={mode}")
+    _loss_check(rl, radio, L, Ht, H, mode)
+
+
+@pytest.mark.parametrize("N", [2048, 4096])
+@pytest.mark.parametrize("mode", ["none", "stats_pdp"])
+def test_cfr_loss_long_rows(rl, N, mode):
+    """Rows longer than one wave's transform (the workgroup-per-row path)."""
+    rng = np.random.default_rng(N)
+    L, M = 3, 5
+    radio = Radio(fc=3.5e9, bandwidth=100e6, n_sc=N, n_elem=M)
+    Ht = (rng.normal(size=(L, M, N)) + 1j * rng.normal(size=(L, M, N))).astype(np.complex64)
+    H = (Ht + 0.3 * (rng.normal(size=(L, M, N)) + 1j * rng.normal(size=(L, M, N)))).astype(
+        np.complex64)
+    say(f"cfr_loss N={N} mode={mode}")
+    _loss_check(rl, radio, L, Ht, H, mode)
 
 
 def test_cfr_loss_in_place(rl):
