@@ -7,10 +7,19 @@ up to fifth order, ~186 paths per link), inputs resident in HBM.
 
 Prints ONE JSON line (rank 0):
   value          CFR taps/s (taps = links x elements x subcarriers per step)
-  roofline       dominant kernel's algorithmic FLOP/s against the FP32 matrix
-                 peak, from HIP events on the launch stream
+  roofline       dominant kernel's algorithmic FLOP/s (8 M N P per launch) from
+                 HIP events on the launch stream, against the ceiling of an
+                 FP32-accurate contraction on the BF16 matrix cores (dense
+                 BF16 peak / 6 split products); its FP32-matrix-peak fraction
+                 is given beside it
   cpu_baseline   the FP64 oracle on a bounded sample of links, host cores
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+       python bench.py --copy-probe ...      also runs a 2 GiB device copy
+                                             first (HBM counter calibration)
+       python bench.py --traffic FETCH.csv WRITE.csv
+                                             rocprofv3 --pmc FETCH_SIZE /
+                                             WRITE_SIZE results of a
+                                             --copy-probe run -> traffic.json
 """
 import argparse
 import json
@@ -26,7 +35,13 @@ import numpy as np  # noqa: E402
 import torch  # noqa: E402
 
 PEAK_FP32_MATRIX_TFLOPS = 157.3  # MI355X dense FP32 MFMA
+PEAK_BF16_MATRIX_TFLOPS = 2500.0  # MI355X dense BF16 MFMA
+SPLIT_PRODUCTS = 6  # BF16 partial products per FP32-accurate product
+PEAK_SPLIT_TFLOPS = PEAK_BF16_MATRIX_TFLOPS / SPLIT_PRODUCTS
 PEAK_HBM_GBS = 8000.0
+COPY_PROBE_BYTES = 2 << 30
+# sources whose change invalidates the committed HBM counter figures
+HOT_SOURCES = ["cfr.hip", "split_bf16.h", "dev_common.h", "api_common.h"]
 
 
 def log(msg):
@@ -113,16 +128,75 @@ def calib_compare(w, steps):
     return res
 
 
+def hot_source_sha():
+    import hashlib
+    h = hashlib.sha1()
+    for f in HOT_SOURCES:
+        with open(os.path.join(ROOT, "paper_2311_18558_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def load_traffic():
-    """HBM bytes per launch of the dominant kernel from the committed
-    rocprofv3 counter summary, if present and taken on this kernel build."""
+    """HBM bytes per launch of the CFR kernels from the committed rocprofv3
+    counter summary; empty when absent or taken on other kernel sources."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return {}
     try:
-        return json.load(open(p))
+        t = json.load(open(p))
     except Exception:
         return {}
+    if t.get("source_sha") != hot_source_sha():
+        return {}
+    return {k: v["traffic_bytes"] for k, v in t.get("kernels", {}).items()}
+
+
+def summarize_traffic(fetch_csv, write_csv):
+    """HBM traffic per launch from FETCH_SIZE / WRITE_SIZE (KiB per dispatch)
+    of a --copy-probe run: each counter is scaled by what it reads for the
+    2 GiB device copy (COPY_PROBE_BYTES read and written).  Writes
+    profiles/traffic.json and prints a markdown summary."""
+    import csv
+    import re
+
+    def per_kernel(path, counter):
+        vals = {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            name = re.sub(r"\(.*", "", r["Kernel_Name"]).replace("void ", "")
+            vals.setdefault(name, {}).setdefault(int(r["Dispatch_Id"]), 0.0)
+            vals[name][int(r["Dispatch_Id"])] += float(r["Counter_Value"]) * 1024.0
+        return vals
+
+    fetch = per_kernel(fetch_csv, "FETCH_SIZE")
+    write = per_kernel(write_csv, "WRITE_SIZE")
+    copy_names = [k for k in fetch if "copyBuffer" in k]
+    # the probe's copies are the largest copy dispatches
+    cf = max(v for k in copy_names for v in fetch[k].values())
+    cw = max(v for k in copy_names for v in write.get(k, {0: 0.0}).values())
+    sf, sw = cf / COPY_PROBE_BYTES, cw / COPY_PROBE_BYTES
+    out = {"source_sha": hot_source_sha(), "copy_probe_bytes": COPY_PROBE_BYTES,
+           "fetch_scale": sf, "write_scale": sw, "kernels": {}}
+    names = {"rtc::cfr_kernel": "cfr", "rtc::cfr_adjoint_kernel": "cfr_adjoint",
+             "rtc::cfr_loss_wave_kernel<10, true>": "cfr_loss"}
+    lines = ["| kernel | dispatches | FETCH_SIZE (GB) | WRITE_SIZE (GB) | HBM read (GB) "
+             "| HBM write (GB) |", "|---|---:|---:|---:|---:|---:|"]
+    for k, short in names.items():
+        if k not in fetch:
+            continue
+        f = float(np.mean(list(fetch[k].values())))
+        w = float(np.mean(list(write.get(k, {0: 0.0}).values())))
+        rb, wb = f / sf, w / sw
+        out["kernels"][short] = {"fetch_bytes": rb, "write_bytes": wb, "traffic_bytes": rb + wb}
+        lines.append(f"| `{k}` | {len(fetch[k])} | {f / 1e9:.3f} | {w / 1e9:.3f} | "
+                     f"{rb / 1e9:.3f} | {wb / 1e9:.3f} |")
+    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(f"copy probe: {COPY_PROBE_BYTES / 2**30:.0f} GiB read + written; FETCH_SIZE reads "
+          f"{sf:.3f}x, WRITE_SIZE {sw:.3f}x the bytes moved\n")
+    print("\n".join(lines))
 
 
 def main():
@@ -134,7 +208,14 @@ def main():
     ap.add_argument("--no-calib", action="store_true",
                     help="skip the learned-vs-plain calibration comparison")
     ap.add_argument("--calib-steps", type=int, default=3000)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="start with a 2 GiB device copy (counter calibration)")
+    ap.add_argument("--traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="summarise rocprofv3 FETCH_SIZE / WRITE_SIZE results and exit")
     args = ap.parse_args()
+    if args.traffic:
+        summarize_traffic(*args.traffic)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the hot path here is the one-GPU share of the "
               "workload; sharding across GPUs is described in the design notes but not built.",
@@ -144,6 +225,14 @@ def main():
     from paper_2311_18558_amd import lib as rl
     from paper_2311_18558_amd.pipeline import Pipeline
     rl.load()
+    if args.copy_probe:
+        src = torch.ones(COPY_PROBE_BYTES // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log(f"copy probe: 3 x {COPY_PROBE_BYTES} bytes")
 
     w = build_workload()
     st, radio = w.store, w.radio
@@ -186,8 +275,11 @@ def main():
     achieved = fl / (per_kernel[hot] * 1e-3) / 1e12
     traffic = load_traffic().get(hot)
     roofline = {"bound": "mfma", "kernel": hot, "achieved": round(achieved, 2),
-                "peak": PEAK_FP32_MATRIX_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_MATRIX_TFLOPS, 4), "traffic": traffic}
+                "peak": round(PEAK_SPLIT_TFLOPS, 1), "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_SPLIT_TFLOPS, 4), "traffic": traffic,
+                "peak_basis": f"dense BF16 {PEAK_BF16_MATRIX_TFLOPS:.0f} TFLOP/s / "
+                              f"{SPLIT_PRODUCTS} split products (FP32-accurate)",
+                "fp32_matrix_peak_frac": round(achieved / PEAK_FP32_MATRIX_TFLOPS, 4)}
     kernels = {}
     for k, ms in per_kernel.items():
         fl_k, by_k = kernel_work(k, L, M, N, P, D)

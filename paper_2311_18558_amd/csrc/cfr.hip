@@ -17,9 +17,10 @@
 //
 // The adjoint G[m, i] = sum_n dLdH[m, n] conj(E[i, n]) is the same kind of
 // product with the subcarriers as the contraction axis: lane l reads eight
-// consecutive subcarriers of its dL/dH row and generates E for its path over
-// the same subcarriers by the recurrence exp(-j 2 pi df tau_i) from an FP64
-// anchor.
+// consecutive subcarriers of its dL/dH row.  Within a 16-subcarrier chunk
+// conj(E) factors into a per-chunk phase of the path times a pattern that is
+// the same for every chunk, so the B operand is split once per wave and the
+// per-chunk phase is applied to the FP32 product (see adj_wave).
 #include <cmath>
 
 #include "api_common.h"
@@ -31,7 +32,7 @@ namespace rtc {
 constexpr int kCfrWaves = 4;   // waves per workgroup (forward)
 constexpr int kCfrTiles = 8;   // 32-subcarrier tiles per wave (forward)
 constexpr int kAdjWaves = 4;   // waves per workgroup (adjoint)
-constexpr int kAdjTP = 2;      // 32-path tiles per wave (adjoint)
+constexpr int kAdjTP = 1;      // 32-path tiles per wave (adjoint)
 constexpr double kInv2Pi = 0.15915494309189533577;
 
 struct CfrArgs {
@@ -261,21 +262,31 @@ __device__ __forceinline__ void adj_wave(const AdjArgs& A, int64_t w, int64_t l,
   const bool vec = (A.N & 1) == 0 && (reinterpret_cast<uintptr_t>(A.dH) & 15) == 0;
   const float2* dHl = A.dH + l * (int64_t)A.M * A.N;
 
-  int64_t pidx[NT];
-  bool ok[NT];
-  float2 ai[NT];
-  float psv[NT];
+  // Per 16-subcarrier chunk starting at n0, conj(E[p, n0 + k]) =
+  // c_p(n0) v_p(k) with c_p(n0) = exp(+j 2 pi f_n0 tau_p) and
+  // v_p(k) = exp(+j 2 pi k df tau_p).  The B operand V[k, p] = v_p(k) is the
+  // same for every chunk, so it is generated and split once; each chunk's
+  // MFMA product P = dH_chunk V is rotated by the lane's c_p (the result
+  // column is the lane's path) and added to G in FP32.
+  // the lane's path in tile u (a, psi are read again in the epilogue)
+  auto path_of = [&](int u) { return off0 + (int64_t)(grp * kAdjTP + u) * 32 + col; };
   double tv[NT];
-  float2 w1[NT];
+  Split3 VR[NT], VI[NT];
+  float2 w16[NT];
 #pragma unroll
   for (int u = 0; u < NT; ++u) {
-    const int tile = grp * kAdjTP + u;
-    pidx[u] = off0 + (int64_t)tile * 32 + col;
-    ok[u] = pidx[u] < off1;
-    ai[u] = ok[u] ? A.a[pidx[u]] : make_float2(0.0f, 0.0f);
-    psv[u] = ok[u] ? A.psi[pidx[u]] : 0.0f;
-    tv[u] = ok[u] ? A.tau[pidx[u]] : 0.0;
-    w1[u] = expm2pi_f64(A.df * tv[u]);
+    const int64_t p = path_of(u);
+    tv[u] = p < off1 ? A.tau[p] : 0.0;
+    float vr[8], vi[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const float2 e = expm2pi_f64((double)(8 * half + j) * A.df * tv[u]);
+      vr[j] = e.x;
+      vi[j] = -e.y;
+    }
+    VR[u] = split3(vr);
+    VI[u] = split3(vi);
+    w16[u] = cconj(expm2pi_f64(16.0 * A.df * tv[u]));
   }
   float2 da[NT];
 #pragma unroll
@@ -286,14 +297,16 @@ __device__ __forceinline__ void adj_wave(const AdjArgs& A, int64_t w, int64_t l,
     const bool row_ok = row < A.M;
     const float2* rp = dHl + (int64_t)(row_ok ? row : 0) * A.N;
     floatx16 gre[NT], gim[NT];
+    float2 c[NT];
 #pragma unroll
     for (int u = 0; u < NT; ++u) {
       gre[u] = floatx16{0};
       gim[u] = floatx16{0};
+      c[u] = make_float2(1.0f, 0.0f);
     }
-    // 16-subcarrier chunks: lane l takes subcarriers n0 + 8(l/32) + j of its
-    // dL/dH row (A) and of its path's exponential (B); the next chunk's row
-    // values are loaded while the current chunk's MFMAs run
+    // 16-subcarrier chunks: lane l holds subcarriers n0 + 8(l/32) + j of its
+    // dL/dH row (A operand); the next chunk's values are loaded while the
+    // current chunk's MFMAs run
     float2 hv[8];
     load8(rp, 8 * half, A.N, vec, row_ok, hv);
     for (int n0 = 0; n0 < A.N; n0 += 16) {
@@ -304,30 +317,34 @@ __device__ __forceinline__ void adj_wave(const AdjArgs& A, int64_t w, int64_t l,
         hi[j] = hv[j].y;
       }
       if (n0 + 16 < A.N) load8(rp, n0 + 16 + 8 * half, A.N, vec, row_ok, hv);
-      const Split3 HR = split3(hr), HI = split3(hi), NHR = neg3(HR);
-      const double f_l = A.f0 + (double)(n0 + 8 * half) * A.df;
+      const Split3 HR = split3(hr), HI = split3(hi), NHI = neg3(HI);
+      const bool anchor = (n0 & 63) == 0;  // FP64 re-anchor every 64 subcarriers
 #pragma unroll
       for (int u = 0; u < NT; ++u) {
-        float2 e = expm2pi_f64(f_l * tv[u]);
-        float er[8], ei[8];
+        // P = dH V:  Re: hre vr - him vi,  Im: hre vi + him vr
+        floatx16 pr = mac6(HR, VR[u], floatx16{0});
+        floatx16 pim = mac6(HR, VI[u], floatx16{0});
+        pr = mac6(NHI, VI[u], pr);
+        pim = mac6(HI, VR[u], pim);
+        c[u] = anchor ? cconj(expm2pi_f64((A.f0 + (double)n0 * A.df) * tv[u]))
+                      : cmul(c[u], w16[u]);
+        const float2 cu = c[u];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          er[j] = e.x;
-          ei[j] = e.y;
-          if (j < 7) e = cmul(e, w1[u]);
+        for (int r = 0; r < 16; ++r) {
+          gre[u][r] = fmaf(cu.x, pr[r], fmaf(-cu.y, pim[r], gre[u][r]));
+          gim[u][r] = fmaf(cu.x, pim[r], fmaf(cu.y, pr[r], gim[u][r]));
         }
-        const Split3 ER = split3(er), EI = split3(ei);
-        // G += dH conj(E):  Re: hre er + him ei,  Im: him er - hre ei
-        gre[u] = mac6(HR, ER, gre[u]);
-        gim[u] = mac6(HI, ER, gim[u]);
-        gre[u] = mac6(HI, EI, gre[u]);
-        gim[u] = mac6(NHR, EI, gim[u]);
+        // one tile's product registers live at a time
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
     // epilogue: rows m = mblk*32 + 8(r/4) + 4 half + r%4, column = path
 #pragma unroll
     for (int u = 0; u < NT; ++u) {
-      const double psi_cyc = (double)psv[u] * kInv2Pi;
+      const int64_t p = path_of(u);
+      const bool ok = p < off1;
+      const float2 ai = ok ? A.a[p] : make_float2(0.0f, 0.0f);
+      const double psi_cyc = (double)(ok ? A.psi[p] : 0.0f) * kInv2Pi;
       float gacc_re[16], gacc_im[16];
 #pragma unroll
       for (int grp4 = 0; grp4 < 4; ++grp4) {
@@ -343,7 +360,7 @@ __device__ __forceinline__ void adj_wave(const AdjArgs& A, int64_t w, int64_t l,
           float2 gm = mrow < A.M ? A.g[mrow] : make_float2(0.0f, 0.0f);
           float2 Gph = cmul(G, ph);
           da[u] = cadd(da[u], cmulc(gm, Gph));
-          float2 tg2 = cmulc(ai[u], Gph);
+          float2 tg2 = cmulc(ai, Gph);
           gacc_re[r] = tg2.x;
           gacc_im[r] = tg2.y;
         }
@@ -379,7 +396,8 @@ __device__ __forceinline__ void adj_wave(const AdjArgs& A, int64_t w, int64_t l,
       float2 d = da[u];
       d.x += __shfl_xor(d.x, 32, 64);
       d.y += __shfl_xor(d.y, 32, 64);
-      if (half == 0 && ok[u]) A.dLda[pidx[u]] = d;
+      const int64_t p = path_of(u);
+      if (half == 0 && p < off1) A.dLda[p] = d;
     }
   }
 }
@@ -409,10 +427,15 @@ __global__ void __launch_bounds__(kAdjWaves * 64, 2) cfr_adjoint_kernel(AdjArgs 
   const int64_t l = lo;
   const int grp = (int)(w - A.wave_off[l]);
   const int n_tiles = (int)((A.link_off[l + 1] - A.link_off[l] + 31) / 32);
-  if (grp * kAdjTP + 1 < n_tiles)
-    adj_wave<2>(A, w, l, grp, lane);
-  else
+  if constexpr (kAdjTP == 2) {
+    if (grp * kAdjTP + 1 < n_tiles)
+      adj_wave<2>(A, w, l, grp, lane);
+    else
+      adj_wave<1>(A, w, l, grp, lane);
+  } else {
+    (void)n_tiles;
     adj_wave<1>(A, w, l, grp, lane);
+  }
 }
 
 __global__ void to_c64_kernel(const double* v, int M, float2* out) {
