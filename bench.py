@@ -72,6 +72,57 @@ def kernel_work(name, L, M, N, P, D):
     return 0.0, 0.0
 
 
+def diffuse_bench(steps=3, warmup=1):
+    """The same calibration step on the diffuse workload (specular up to
+    fifth order + single-bounce Lambertian paths, ~2,000 paths per link,
+    2,048 Rx x 32 elements x 4,096 subcarriers)."""
+    from synth import workloads
+    from paper_2311_18558_amd.pipeline import Pipeline
+    t0 = time.time()
+    w = workloads.diffuse()
+    st, radio = w.store, w.radio
+    n_dif = int(np.count_nonzero(st.kind))
+    log(f"workload diffuse: {st.n_links} links, {st.n_paths} paths ({st.n_paths / st.n_links:.1f}"
+        f"/link, {n_dif} diffuse), generated in {time.time() - t0:.1f}s")
+    L, M, N, P = st.n_links, radio.n_elem, radio.n_sc, st.n_paths
+    rng = np.random.default_rng(8)
+    raw0 = (w.raw + rng.normal(scale=0.3, size=w.raw.shape)).astype(np.float32)
+    pipe = Pipeline(st, radio, w.raw, w.g)
+    H_tgt = torch.empty_like(pipe.H)
+    pipe.trace()
+    pipe.cfr(out=H_tgt)
+    pipe.set_target(H_tgt)
+    pipe.raw.copy_(torch.tensor(raw0, device=pipe.dev))
+    for _ in range(warmup):
+        pipe.step()
+    torch.cuda.synchronize()
+    events = {}
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        pipe.step(events=events)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    per = {k: round(float(np.mean([a.elapsed_time(b) for a, b in v])), 4)
+           for k, v in events.items()}
+    log("diffuse per-stage ms: " + ", ".join(f"{k} {v:.3f}" for k, v in per.items()))
+    fl = 8.0 * M * N * P
+    out = {"workload": "scale floor, 2,048 Rx, specular up to 5th order + single-bounce "
+                       "Lambertian diffuse, 4,096 subcarriers over 100 MHz, 32-element ULA",
+           "links": L, "paths": P, "paths_per_link": round(P / L, 1), "diffuse_paths": n_dif,
+           "subcarriers": N, "elements": M, "steps": steps, "ms_per_step": round(ms, 3),
+           "taps_per_s": round(L * M * N / (ms * 1e-3), 1), "kernels_ms": per,
+           "cfr_tflops": round(fl / (per["cfr"] * 1e-3) / 1e12, 2),
+           "cfr_adjoint_tflops": round(fl / (per["cfr_adjoint"] * 1e-3) / 1e12, 2),
+           "trace_fields_paths_per_s": round(P / (per["trace_fields"] * 1e-3), 1),
+           "trace_fields_adjoint_paths_per_s": round(P / (per["trace_fields_adjoint"] * 1e-3), 1)}
+    del pipe, H_tgt
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(w, budget_s=15.0, max_links=8192):
     """The FP64 oracle (forward, loss, reverse-mode gradient) on whole
     links of the same workload until `budget_s` of CPU time is spent."""
@@ -208,6 +259,8 @@ def main():
     ap.add_argument("--no-calib", action="store_true",
                     help="skip the learned-vs-plain calibration comparison")
     ap.add_argument("--calib-steps", type=int, default=3000)
+    ap.add_argument("--no-diffuse", action="store_true",
+                    help="skip the diffuse-scattering workload line")
     ap.add_argument("--copy-probe", action="store_true",
                     help="start with a 2 GiB device copy (counter calibration)")
     ap.add_argument("--traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -317,6 +370,8 @@ def main():
     }
     del pipe, H_tgt
     torch.cuda.empty_cache()
+    if not args.no_diffuse:
+        out["diffuse"] = diffuse_bench()
     if not args.no_calib:
         out["calib"] = calib_compare(w, args.calib_steps)
     if not args.no_cpu_baseline:

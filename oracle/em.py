@@ -87,3 +87,12 @@ def pattern_isotropic(zeta):
 
 def wavelength(freq):
     return C0 / freq
+
+
+def lambertian_pattern(cos_s):
+    """Scattering pattern of a purely diffuse (Lambertian) surface, the first
+    term of Eq. (trainable_scattering_pattern): f_s = cos(theta_s) / pi on
+    the hemisphere of the incidence side, 0 behind the surface.  Its
+    integral over that hemisphere is 1."""
+    cos_s = torch.as_tensor(cos_s, dtype=f64)
+    return torch.clamp(cos_s, min=0.0) / math.pi

@@ -9,6 +9,19 @@ one interaction slot at a time):
   at the receiver:         E <- D_{Q+1} E in the Rx (theta_hat, phi_hat) basis
   a = lambda/(4 pi) * C_R^H E / (c tau)
 
+A diffuse reflection (Sec. II-D-2, Eq. scattered_field) may end a path
+(store kind 1 at its last interaction; elsewhere the kind is ignored and
+the interaction is specular):
+
+  y = D_Q E in the incidence basis, Gamma |E| = |diag(r_perp, r_par) y|,
+  |E_s|^2 = |E|^2 cos(theta_i) dA S^2 Gamma^2 f_s,  f_s = cos(theta_s)/pi,
+  E <- [|E_s|, 0] in the outgoing basis (K_x = 0, chi_1 = chi_2 = 0),
+  a = lambda/(4 pi) * C_R^H D_{Q+1} E / (rho_Q d_{Q+1})
+
+with rho_Q the unfolded length from the Tx to the diffuse point (the
+incoming wave's spreading) and d_{Q+1} the distance to the Rx (the
+scattered spherical wave's).
+
 Readings (the paper is silent or cites without printing):
   * spreading: planar reflectors and a point source give A^r = rho/(rho+d),
     whose product with 1/d_1 telescopes to 1/(total length) = 1/(c tau);
@@ -26,14 +39,22 @@ Readings (the paper is silent or cites without printing):
   * coefficients are evaluated at the carrier: lambda_c, eta(omega_c).
   * array phase: element m of a half-wavelength ULA along u, centred on the
     Tx, sees psi_i (m - (M-1)/2) with psi_i = pi k_1 . u (carrier only).
+  * diffuse reflection: the scattered field takes the outgoing basis
+    e_perp = k_s x n / |k_s x n|, e_par = e_perp x k_s (built from the
+    scattered direction and the normal as for a reflection; if k_s is along
+    n, e_perp is the incidence e_perp made orthogonal to k_s); with K_x = 0
+    all of |E_s| is in e_perp.  Its phase is the propagation delay alone
+    (chi = 0; the phase of the incoming field does not carry over, only its
+    norm does), and the Rx behind the surface (cos theta_s <= 0) gets 0.
 """
 import math
 
 import numpy as np
 import torch
 
-from .em import (C0, c128, f64, fresnel, materials_from_raw, pattern_isotropic,
-                 permittivity, spherical_basis, specular_amplitude, wavelength)
+from .em import (C0, c128, f64, fresnel, lambertian_pattern, materials_from_raw,
+                 pattern_isotropic, permittivity, spherical_basis, specular_amplitude,
+                 wavelength)
 
 
 def _unit(v):
@@ -77,6 +98,51 @@ def specular_step(E, p_out, q_out, k_in, n, eta, R):
     return E_out, e_perp, e_par_in, e_par_out, k_r, cos_t
 
 
+def _sqrt0(x):
+    """sqrt with a zero (not NaN) gradient at x <= 0."""
+    pos = x > 0
+    return torch.where(pos, torch.sqrt(torch.where(pos, x, torch.ones_like(x))),
+                       torch.zeros_like(x))
+
+
+def diffuse_step(E, p_out, q_out, k_in, n, eta, S, dA, k_s):
+    """One diffuse reflection (Eq. scattered_field, Lambertian pattern,
+    K_x = 0, chi = 0), without the spreading factors (the caller divides by
+    rho_Q d_{Q+1}).
+
+    E: complex [...,2] field in the outgoing basis (p_out, q_out) of the
+    previous process; k_in: incident direction; n: stored unit normal;
+    eta: complex permittivity; S: scattering coefficient; dA: area element;
+    k_s: scattered direction.  Returns (E_out, e_perp_s, e_par_s)."""
+    flip = _dot(k_in, n) > 0
+    n = torch.where(flip[..., None], -n, n)
+    cos_i = -_dot(k_in, n)
+    cos_s = _dot(k_s, n)
+    cr = torch.cross(k_in, n, dim=-1)
+    crn = torch.linalg.norm(cr, dim=-1, keepdim=True)
+    alt = p_out - _dot(p_out, k_in)[..., None] * k_in
+    alt = alt / torch.linalg.norm(alt, dim=-1, keepdim=True)
+    small = crn < 1e-7
+    e_perp = torch.where(small, alt, cr / torch.where(small, torch.ones_like(crn), crn))
+    e_par_in = torch.cross(e_perp, k_in, dim=-1)
+    y0 = _dot(e_perp, p_out) * E[..., 0] + _dot(e_perp, q_out) * E[..., 1]
+    y1 = _dot(e_par_in, p_out) * E[..., 0] + _dot(e_par_in, q_out) * E[..., 1]
+    r_perp, r_par = fresnel(eta, cos_i)
+    # Gamma |E_in| = |diag(r_perp, r_par) y|
+    g_norm = _sqrt0(torch.abs(r_perp * y0) ** 2 + torch.abs(r_par * y1) ** 2)
+    amp = S * g_norm * _sqrt0(torch.clamp(cos_i, min=0.0) * dA * lambertian_pattern(cos_s))
+    # outgoing basis from (k_s, n)
+    cs = torch.cross(k_s, n, dim=-1)
+    csn = torch.linalg.norm(cs, dim=-1, keepdim=True)
+    alt_s = e_perp - _dot(e_perp, k_s)[..., None] * k_s
+    alt_s = alt_s / torch.linalg.norm(alt_s, dim=-1, keepdim=True)
+    small_s = csn < 1e-7
+    e_perp_s = torch.where(small_s, alt_s, cs / torch.where(small_s, torch.ones_like(csn), csn))
+    e_par_s = torch.cross(e_perp_s, k_s, dim=-1)
+    E_out = torch.stack([amp.to(c128), torch.zeros_like(amp).to(c128)], dim=-1)
+    return E_out, e_perp_s, e_par_s
+
+
 def _gather_paths(store, sel):
     P_all = int(store.n_paths)
     D = int(store.max_depth)
@@ -84,20 +150,22 @@ def _gather_paths(store, sel):
     tx = torch.tensor(store.tx_pos[link_of], dtype=f64)
     rx = torch.tensor(store.rx_pos[link_of], dtype=f64)
     depth = torch.tensor(store.depth[sel].astype(np.int64))
-    pts, nrm, mat = [], [], []
+    pts, nrm, mat, kind, dA = [], [], [], [], []
     for k in range(D):
         idx = k * P_all + sel
         pts.append(torch.tensor(store.pts[:, idx].T, dtype=f64))
         nrm.append(torch.tensor(store.nrm[:, idx].T, dtype=f64))
         mat.append(torch.tensor(store.mat[idx].astype(np.int64)))
+        kind.append(torch.tensor(store.kind[idx].astype(np.int64)))
+        dA.append(torch.tensor(store.dA[idx], dtype=f64))
     tau = torch.tensor(store.tau[sel], dtype=f64)
-    return tx, rx, depth, pts, nrm, mat, tau
+    return tx, rx, depth, pts, nrm, mat, tau, kind, dA
 
 
 def departure_direction(store, sel=None):
     """k_1, the unit direction leaving the Tx, per path (float64 [P,3])."""
     sel = np.arange(store.n_paths) if sel is None else np.asarray(sel)
-    tx, rx, depth, pts, _, _, _ = _gather_paths(store, sel)
+    tx, rx, depth, pts, _, _, _, _, _ = _gather_paths(store, sel)
     first = torch.where((depth > 0)[:, None], pts[0], rx) if store.max_depth > 0 else rx
     return _unit(first - tx)
 
@@ -110,7 +178,7 @@ def trace_fields(store, eps_r, sigma, s, fc, zeta_tx=0.0, zeta_rx=0.0,
     shape [max_depth, P] (P = len(sel)), may require grad.  Slots beyond a
     path's depth are ignored.  Returns (a complex128 [P], psi float64 [P])."""
     sel = np.arange(store.n_paths) if sel is None else np.asarray(sel)
-    tx, rx, depth, pts, nrm, _, tau = _gather_paths(store, sel)
+    tx, rx, depth, pts, nrm, _, tau, kind, dA = _gather_paths(store, sel)
     P = len(sel)
     D = int(store.max_depth)
     lam = wavelength(fc)
@@ -119,6 +187,8 @@ def trace_fields(store, eps_r, sigma, s, fc, zeta_tx=0.0, zeta_rx=0.0,
     p_out, q_out = spherical_basis(k1)
     E = pattern_isotropic(zeta_tx).expand(P, 2).clone()
     prev = tx
+    rho = torch.zeros(P, dtype=f64)  # unfolded length from the Tx
+    diffuse_end = torch.zeros(P, dtype=torch.bool)
     up = torch.tensor([0.0, 0.0, 1.0], dtype=f64).expand(P, 3)
     xhat = torch.tensor([1.0, 0.0, 0.0], dtype=f64).expand(P, 3)
     for k in range(D):
@@ -131,9 +201,23 @@ def trace_fields(store, eps_r, sigma, s, fc, zeta_tx=0.0, zeta_rx=0.0,
         eta = permittivity(eps_r[k], sigma[k], fc)
         R = specular_amplitude(s[k])
         E_new, e_perp, _, e_par_out, _, _ = specular_step(E, p_out, q_out, k_in, n_k, eta, R)
+        # a diffuse reflection is honoured at a path's last interaction
+        dif = act & (kind[k] == 1) & (depth == k + 1)
+        if bool(dif.any()):
+            # stand-in geometry for the other lanes keeps the graph finite
+            rx_k = torch.where(dif[:, None], rx, s_k + 2.0 * n_k + up)
+            k_s = _unit(rx_k - s_k)
+            s_dif = torch.where(dif, s[k], torch.zeros_like(s[k]))
+            E_d, ep_d, eq_d = diffuse_step(E, p_out, q_out, k_in, n_k, eta, s_dif,
+                                           torch.where(dif, dA[k], torch.ones_like(dA[k])), k_s)
+            E_new = torch.where(dif[:, None], E_d, E_new)
+            e_perp = torch.where(dif[:, None], ep_d, e_perp)
+            e_par_out = torch.where(dif[:, None], eq_d, e_par_out)
+            diffuse_end = diffuse_end | dif
         E = torch.where(act[:, None], E_new, E)
         p_out = torch.where(act[:, None], e_perp, p_out)
         q_out = torch.where(act[:, None], e_par_out, q_out)
+        rho = torch.where(act, rho + torch.linalg.norm(s_k - prev, dim=-1), rho)
         prev = torch.where(act[:, None], s_k, prev)
     k_last = _unit(rx - prev)
     t_r, p_r = spherical_basis(-k_last)
@@ -141,7 +225,11 @@ def trace_fields(store, eps_r, sigma, s, fc, zeta_tx=0.0, zeta_rx=0.0,
     e1 = _dot(p_r, p_out) * E[:, 0] + _dot(p_r, q_out) * E[:, 1]
     c_r = pattern_isotropic(zeta_rx)
     received = c_r[0].conj() * e0 + c_r[1].conj() * e1
-    a = (lam / (4.0 * math.pi)) * received / (C0 * tau)
+    # spreading: 1/(total length) along specular chains; 1/(rho_Q d_{Q+1})
+    # for a path ending in a diffuse reflection
+    d_last = torch.linalg.norm(rx - prev, dim=-1)
+    length = torch.where(diffuse_end, rho * d_last, C0 * tau)
+    a = (lam / (4.0 * math.pi)) * received / length
     u = torch.tensor(ula_axis, dtype=f64)
     psi = math.pi * _dot(k1, u.expand(P, 3))
     return a, psi

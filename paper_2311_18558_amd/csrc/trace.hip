@@ -9,6 +9,15 @@
 // adjoint, the per-interaction basis changes, incoming fields and Fresnel
 // coefficients of the path (the depth bound is a template parameter so
 // these arrays stay in registers).
+//
+// A path may end in a diffuse reflection (kind 1 at its last interaction,
+// Sec. II-D-2, Eq. scattered_field with the Lambertian pattern
+// f_s = cos(theta_s)/pi, K_x = 0 and chi = 0):
+//   |E_s| = S |diag(r_perp, r_par) y| sqrt(cos(theta_i) dA f_s),
+// y the incoming field in the incidence basis; the scattered field is
+// (|E_s|, 0) in the basis (k_s x n, e_perp x k_s) and spreads as
+// 1/(rho d) with rho the unfolded length to the diffuse point and d the
+// distance to the Rx.  Elsewhere the kind is ignored (specular).
 #include <cmath>
 
 #include "api_common.h"
@@ -21,6 +30,7 @@ constexpr int kTraceAdjMaxBlocks = 1024;
 constexpr double kC0 = 299792458.0;
 constexpr double kEps0 = 8.8541878128e-12;
 constexpr double kPi = 3.14159265358979323846;
+constexpr float kInvPi = 0.318309886183790671538f;
 
 struct TraceArgs {
   int n_links, n_paths, n_mat;
@@ -31,6 +41,8 @@ struct TraceArgs {
   const float* rx_pos;
   const uint8_t* depth;
   const float *px, *py, *pz, *nx, *ny, *nz;
+  const uint8_t* kind;  // interaction kinds or null (all specular)
+  const float* dA;      // diffuse area elements (read where kind is 1)
   const uint16_t* mat;
   const double* tau;
   const float* raw;        // per-id raw parameters [n_mat*3] or null
@@ -154,6 +166,9 @@ struct Chain {
   float2 rperp[SAVE ? MAXD : 1], rpar[SAVE ? MAXD : 1], sroot[SAVE ? MAXD : 1];
   float cos_t[SAVE ? MAXD : 1];
   MatVal mv[SAVE ? MAXD : 1];
+  bool dif;    // the last interaction is diffuse
+  float G0;    // sqrt(cos(theta_i) dA f_s) of the diffuse interaction
+  float nv;    // |diag(r_perp, r_par) y| of the diffuse interaction
 };
 
 template <int MAXD, bool SAVE>
@@ -174,13 +189,18 @@ RTC_DEV void run_chain(const TraceArgs& A, const MatVal* tab, int64_t p, Chain<M
   float2 E0 = make_float2(A.cz_tx, 0.0f);
   float2 E1 = make_float2(A.sz_tx, 0.0f);
   v3 prev = tx;
+  float rho = 0.0f;  // unfolded length from the Tx
+  C.dif = false;
+  C.G0 = C.nv = 0.0f;
 #pragma unroll
   for (int j = 0; j < MAXD; ++j) {
     if (j < Q) {
       int64_t slot = (int64_t)j * A.n_paths + p;
       v3 s = load3(A.px, A.py, A.pz, slot);
       v3 n = load3(A.nx, A.ny, A.nz, slot);
-      v3 k_in = unit3(sub3(s, prev));
+      v3 seg = sub3(s, prev);
+      rho += sqrtf(dot3(seg, seg));
+      v3 k_in = unit3(seg);
       float D[4];
       v3 np, nq;
       float c = reflect_geometry(k_in, n, p_out, q_out, D, &np, &nq);
@@ -189,8 +209,27 @@ RTC_DEV void run_chain(const TraceArgs& A, const MatVal* tab, int64_t p, Chain<M
       MatVal mv = interaction_material(A, tab, slot);
       float2 rp, rl, sr;
       fresnel(mv.eta, c, &rp, &rl, &sr);
-      E0 = cscale(cmul(rp, y0), mv.R);
-      E1 = cscale(cmul(rl, y1), mv.R);
+      const bool dif = A.kind != nullptr && j == Q - 1 && A.kind[slot] == 1;
+      if (dif) {
+        v3 nf = dot3(k_in, n) > 0.0f ? scl3(n, -1.0f) : n;  // towards the incidence side
+        v3 k_s = unit3(sub3(rx, s));
+        float geo = c * A.dA[slot] * fmaxf(dot3(k_s, nf), 0.0f) * kInvPi;
+        float G0 = sqrtf(fmaxf(geo, 0.0f));
+        float nv = sqrtf(cabs2(cmul(rp, y0)) + cabs2(cmul(rl, y1)));
+        E0 = make_float2(mv.S * nv * G0, 0.0f);
+        E1 = make_float2(0.0f, 0.0f);
+        v3 cr = cross3(k_s, nf);
+        v3 e_perp = dot3(cr, cr) > 1e-12f ? cr : np;  // k_s along n: incidence e_perp
+        e_perp = unit3(sub3(e_perp, scl3(k_s, dot3(e_perp, k_s))));
+        np = e_perp;
+        nq = cross3(e_perp, k_s);
+        C.dif = true;
+        C.G0 = G0;
+        C.nv = nv;
+      } else {
+        E0 = cscale(cmul(rp, y0), mv.R);
+        E1 = cscale(cmul(rl, y1), mv.R);
+      }
       if constexpr (SAVE) {
         C.D[j][0] = D[0];
         C.D[j][1] = D[1];
@@ -218,8 +257,14 @@ RTC_DEV void run_chain(const TraceArgs& A, const MatVal* tab, int64_t p, Chain<M
   C.Dq[3] = dot3(ph, q_out);
   C.E0 = cadd(cscale(E0, C.Dq[0]), cscale(E1, C.Dq[1]));
   C.E1 = cadd(cscale(E0, C.Dq[2]), cscale(E1, C.Dq[3]));
-  // spreading of planar reflections with a point source: 1/(total length)
-  C.scale = (float)(A.lam4pi / (kC0 * A.tau[p]));
+  // spreading of planar reflections with a point source: 1/(total length);
+  // after a diffuse reflection 1/(rho d)
+  if (C.dif) {
+    v3 seg = sub3(rx, prev);
+    C.scale = (float)(A.lam4pi / ((double)rho * (double)sqrtf(dot3(seg, seg))));
+  } else {
+    C.scale = (float)(A.lam4pi / (kC0 * A.tau[p]));
+  }
 }
 
 template <int MAXD>
@@ -283,7 +328,39 @@ __global__ void __launch_bounds__(kTraceBlock)
       float2 w1 = make_float2(K * (A.cz_rx * C.Dq[1] + A.sz_rx * C.Dq[3]), 0.0f);
 #pragma unroll
       for (int j = MAXD - 1; j >= 0; --j) {
-        if (j < Q) {
+        if (j < Q && C.dif && j == Q - 1) {
+          // a = K q_R |E_s| is real, so dL/dx = Re(dL/da) da/dx.  With
+          // |E_s| = S G0 nv, nv = |v|, v = (r_perp y0, r_par y1):
+          //   d nv/d eta_re = Re(Z)/nv, d nv/d eta_im = -Im(Z)/nv,
+          //   Z = conj(r_perp) dr_perp/deta |y0|^2 + conj(r_par) dr_par/deta |y1|^2
+          // and d nv = Re(c^T dy) with c = (conj(v0) r_perp, conj(v1) r_par)/nv,
+          // which continues the sweep through the preceding interactions.
+          const float qR = A.cz_rx * C.Dq[0] + A.sz_rx * C.Dq[2];
+          const float gam = Ga.x * K * qR;
+          const float2 rp = C.rperp[j], rl = C.rpar[j], sq = C.sroot[j];
+          const float c = C.cos_t[j];
+          const float2 eta = C.mv[j].eta;
+          const float S = C.mv[j].S;
+          float2 cps = make_float2(c + sq.x, sq.y);
+          float2 d_perp = cdiv(make_float2(-c, 0.0f), cmul(sq, cmul(cps, cps)));
+          float sin2 = fmaf(-c, c, 1.0f);
+          float2 ecs = cadd(cscale(eta, c), sq);
+          float2 d_par = cdiv(cscale(make_float2(eta.x - 2.0f * sin2, eta.y), c),
+                              cmul(sq, cmul(ecs, ecs)));
+          const float2 Z = cadd(cscale(cmulc(rp, d_perp), cabs2(C.y0[j])),
+                                cscale(cmulc(rl, d_par), cabs2(C.y1[j])));
+          const float coef = C.nv > 0.0f ? gam * S * C.G0 / C.nv : 0.0f;
+          g_eps[j] = coef * Z.x;
+          g_sig[j] = coef * Z.y * A.inv_eps0w;
+          g_S[j] = gam * C.G0 * C.nv;
+          ids[j] = PER_ID ? (int)min((int)A.mat[(int64_t)j * A.n_paths + p], A.n_mat - 1) : 0;
+          const float inv_nv = C.nv > 0.0f ? 1.0f / C.nv : 0.0f;
+          const float2 c0 = cscale(cmul(cconj(cmul(rp, C.y0[j])), rp), inv_nv);
+          const float2 c1 = cscale(cmul(cconj(cmul(rl, C.y1[j])), rl), inv_nv);
+          w0 = cadd(cscale(c0, C.D[j][0]), cscale(c1, C.D[j][2]));
+          w1 = cadd(cscale(c0, C.D[j][1]), cscale(c1, C.D[j][3]));
+          Ga = make_float2(gam * S * C.G0, 0.0f);
+        } else if (j < Q) {
           float2 Aperp = cmul(w0, C.y0[j]);
           float2 Apar = cmul(w1, C.y1[j]);
           float2 rp = C.rperp[j], rl = C.rpar[j], s = C.sroot[j];
@@ -415,6 +492,8 @@ static TraceArgs make_args(const rtc_radio* r, const rtc_paths* P, const rtc_mat
   A.nx = P->nx;
   A.ny = P->ny;
   A.nz = P->nz;
+  A.kind = P->kind;
+  A.dA = P->dA;
   A.mat = P->mat;
   A.tau = P->tau;
   A.raw = M->raw;
@@ -461,8 +540,6 @@ extern "C" rtc_status rtc_trace_fields(const rtc_radio* radio, const rtc_paths* 
   if ((st = check_radio(radio, fn)) != RTC_OK) return st;
   if ((st = check_paths(paths, fn, true)) != RTC_OK) return st;
   if ((st = check_mats(mats, paths, fn)) != RTC_OK) return st;
-  RTC_REQUIRE(paths->kind == nullptr, RTC_ERR_UNSUPPORTED,
-              "%s: diffuse interactions (kind != NULL) are not supported by this build", fn);
   if (paths->n_paths == 0 || (a == nullptr && psi == nullptr)) return RTC_OK;
   RTC_REQUIRE(paths->n_links >= 1, RTC_ERR_SHAPE, "%s: n_paths > 0 needs n_links >= 1", fn);
   TraceArgs A = make_args(radio, paths, mats);
@@ -495,8 +572,6 @@ extern "C" rtc_status rtc_trace_fields_adjoint(const rtc_radio* radio, const rtc
   if ((st = check_radio(radio, fn)) != RTC_OK) return st;
   if ((st = check_paths(paths, fn, true)) != RTC_OK) return st;
   if ((st = check_mats(mats, paths, fn)) != RTC_OK) return st;
-  RTC_REQUIRE(paths->kind == nullptr, RTC_ERR_UNSUPPORTED,
-              "%s: diffuse interactions (kind != NULL) are not supported by this build", fn);
   RTC_REQUIRE(dLda != nullptr || paths->n_paths == 0, RTC_ERR_INVALID_ARG, "%s: dLda is NULL", fn);
   bool per_id = mats->raw != nullptr;
   RTC_REQUIRE(per_id ? (dLd_raw != nullptr && dLd_inter == nullptr)

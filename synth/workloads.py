@@ -8,6 +8,10 @@
             types), Tx at 2.5 m near the centre with a 32-element
             half-wavelength ULA along x, 16,384 Rx at 1-2 m height,
             specular depth <= 5, 1,024 subcarriers over 50 MHz at 3.5 GHz
+  diffuse   the scale floor with 2,048 Rx: specular paths up to fifth order
+            plus single-bounce Lambertian diffuse paths from stratified
+            surface samples (~0.35 per m^2), ~2,000 paths per link; 4,096
+            subcarriers over 100 MHz at 3.5 GHz, 32-element ULA
   adjoint   the scale floor and paths with hidden ground truth:
             materials with S ~ U[0, 0.5] and 32 complex element gains;
             14,336 training / 2,048 held-out Rx
@@ -16,6 +20,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
+from . import diffuse as _diffuse
 from . import imagemethod
 from .floorplan import indoor_floor
 from .params import Radio, draw_gains, draw_materials, materials_to_raw
@@ -74,6 +79,25 @@ def scale(seed=3, n_rx=16384, n_sc=1024, n_elem=32, max_depth=SCALE_DEPTH,
     return Workload("scale", store, radio, raw, np.ones(n_elem, np.complex64),
                     (plan.scene.aabb_min, plan.scene.aabb_max),
                     meta=dict(plan=plan, tris=plan.scene.n_tri, n_mat=n_mat))
+
+
+def diffuse(seed=3, n_rx=2048, n_sc=4096, bandwidth=100e6, n_elem=32, max_depth=SCALE_DEPTH,
+            n_rays=1 << 18, density=0.35) -> Workload:
+    """Per-link shape of a large scene with diffuse scattering (~2,000 paths
+    per link, 4,096 subcarriers) on the scale floor."""
+    plan, spec = _scale_geometry(seed, n_rx, max_depth, n_rays)
+    rng = np.random.default_rng(seed + 5)
+    samples = _diffuse.sample_floor(plan, density, rng)
+    tx = spec.tx_pos[0].astype(np.float64)
+    store = _diffuse.add_diffuse(spec, tx, samples,
+                                 lambda p, e: _diffuse.visible_floor(plan, p, e))
+    n_mat = plan.scene.n_mat
+    raw = materials_to_raw(*draw_materials(rng, n_mat, with_scattering=True))
+    radio = Radio(fc=3.5e9, bandwidth=bandwidth, n_sc=n_sc, n_elem=n_elem,
+                  ula_axis=(1.0, 0.0, 0.0))
+    return Workload("diffuse", store, radio, raw, draw_gains(rng, n_elem),
+                    (plan.scene.aabb_min, plan.scene.aabb_max),
+                    meta=dict(plan=plan, n_mat=n_mat, n_samples=len(samples[0])))
 
 
 def adjoint(seed=3, n_rx=16384, n_sc=1024, n_elem=32, max_depth=SCALE_DEPTH,

@@ -90,12 +90,18 @@ def array_workload(seed=99, n_rx=48, n_sc=1024, n_elem=32, max_depth=2, n_mat=1)
     return scene, store, raw, radio, g
 
 
-def multi_material_box(seed=5, n_rx=16, n_mat=3, max_depth=3):
+def multi_material_box_scene(n_mat=3):
     """Box room whose six faces carry material ids f % n_mat."""
-    rng = np.random.default_rng(seed)
     scene = box_room()
     scene.face_mat = (np.arange(scene.n_face) % n_mat).astype(np.int32)
     scene.n_mat = n_mat
+    return scene
+
+
+def multi_material_box(seed=5, n_rx=16, n_mat=3, max_depth=3):
+    """Box room whose six faces carry material ids f % n_mat."""
+    rng = np.random.default_rng(seed)
+    scene = multi_material_box_scene(n_mat)
     tx = uniform_points_in_box(rng, 1, scene.aabb_min, scene.aabb_max)[0]
     rxs = uniform_points_in_box(rng, n_rx, scene.aabb_min, scene.aabb_max)
     store = imagemethod.find_store(scene, tx, rxs, max_depth)
