@@ -32,7 +32,7 @@ namespace rtc {
 constexpr int kCfrWaves = 4;   // waves per workgroup (forward)
 constexpr int kCfrTiles = 8;   // 32-subcarrier tiles per wave (forward)
 constexpr int kAdjWaves = 4;   // waves per workgroup (adjoint)
-constexpr int kAdjTP = 1;      // 32-path tiles per wave (adjoint)
+constexpr int kAdjTP = 2;      // 32-path tiles per wave (adjoint)
 constexpr double kInv2Pi = 0.15915494309189533577;
 
 struct CfrArgs {
@@ -251,9 +251,14 @@ __device__ __forceinline__ void load8(const float2* row, int n, int N, bool vec,
 // Contraction of one wave over NT (1 or 2) consecutive 32-path tiles of link
 // l, starting at tile grp * kAdjTP; the caller picks NT = 1 for a link's
 // last wave when it holds a single tile, so no MFMA runs on empty tiles.
+// LDS home of a wave's B operands: [tile][VR h,m,l, VI h,m,l][lane], 16 B
+// per entry, read back once per chunk (they are constant over the wave, but
+// held in registers they would cost the occupancy of two waves per SIMD).
+typedef bf16x8 AdjVbuf[kAdjTP][6][64];
+
 template <int NT>
 __device__ __forceinline__ void adj_wave(const AdjArgs& A, int64_t w, int64_t l, int grp,
-                                         int lane) {
+                                         int lane, AdjVbuf& vbuf) {
   const int half = lane >> 5;
   const int col = lane & 31;
   const int64_t off0 = A.link_off[l];
@@ -271,7 +276,6 @@ __device__ __forceinline__ void adj_wave(const AdjArgs& A, int64_t w, int64_t l,
   // the lane's path in tile u (a, psi are read again in the epilogue)
   auto path_of = [&](int u) { return off0 + (int64_t)(grp * kAdjTP + u) * 32 + col; };
   double tv[NT];
-  Split3 VR[NT], VI[NT];
   float2 w16[NT];
 #pragma unroll
   for (int u = 0; u < NT; ++u) {
@@ -284,10 +288,18 @@ __device__ __forceinline__ void adj_wave(const AdjArgs& A, int64_t w, int64_t l,
       vr[j] = e.x;
       vi[j] = -e.y;
     }
-    VR[u] = split3(vr);
-    VI[u] = split3(vi);
+    const Split3 VR = split3(vr), VI = split3(vi);
+    vbuf[u][0][lane] = VR.h;
+    vbuf[u][1][lane] = VR.m;
+    vbuf[u][2][lane] = VR.l;
+    vbuf[u][3][lane] = VI.h;
+    vbuf[u][4][lane] = VI.m;
+    vbuf[u][5][lane] = VI.l;
     w16[u] = cconj(expm2pi_f64(16.0 * A.df * tv[u]));
   }
+  // each lane reads back only what it wrote: no barrier, but the compiler
+  // must not keep the values in registers
+  asm volatile("" ::: "memory");
   float2 da[NT];
 #pragma unroll
   for (int u = 0; u < NT; ++u) da[u] = make_float2(0.0f, 0.0f);
@@ -321,11 +333,19 @@ __device__ __forceinline__ void adj_wave(const AdjArgs& A, int64_t w, int64_t l,
       const bool anchor = (n0 & 63) == 0;  // FP64 re-anchor every 64 subcarriers
 #pragma unroll
       for (int u = 0; u < NT; ++u) {
+        asm volatile("" ::: "memory");  // reload V per chunk (see vbuf)
+        Split3 VR, VI;
+        VR.h = vbuf[u][0][lane];
+        VR.m = vbuf[u][1][lane];
+        VR.l = vbuf[u][2][lane];
+        VI.h = vbuf[u][3][lane];
+        VI.m = vbuf[u][4][lane];
+        VI.l = vbuf[u][5][lane];
         // P = dH V:  Re: hre vr - him vi,  Im: hre vi + him vr
-        floatx16 pr = mac6(HR, VR[u], floatx16{0});
-        floatx16 pim = mac6(HR, VI[u], floatx16{0});
-        pr = mac6(NHI, VI[u], pr);
-        pim = mac6(HI, VR[u], pim);
+        floatx16 pr = mac6(HR, VR, floatx16{0});
+        floatx16 pim = mac6(HR, VI, floatx16{0});
+        pr = mac6(NHI, VI, pr);
+        pim = mac6(HI, VR, pim);
         c[u] = anchor ? cconj(expm2pi_f64((A.f0 + (double)n0 * A.df) * tv[u]))
                       : cmul(c[u], w16[u]);
         const float2 cu = c[u];
@@ -334,8 +354,6 @@ __device__ __forceinline__ void adj_wave(const AdjArgs& A, int64_t w, int64_t l,
           gre[u][r] = fmaf(cu.x, pr[r], fmaf(-cu.y, pim[r], gre[u][r]));
           gim[u][r] = fmaf(cu.x, pim[r], fmaf(cu.y, pr[r], gim[u][r]));
         }
-        // one tile's product registers live at a time
-        __builtin_amdgcn_sched_barrier(0);
       }
     }
     // epilogue: rows m = mblk*32 + 8(r/4) + 4 half + r%4, column = path
@@ -403,6 +421,7 @@ __device__ __forceinline__ void adj_wave(const AdjArgs& A, int64_t w, int64_t l,
 }
 
 __global__ void __launch_bounds__(kAdjWaves * 64, 2) cfr_adjoint_kernel(AdjArgs A) {
+  __shared__ AdjVbuf vbuf[kAdjWaves];
   const int lane = threadIdx.x & 63;
   const int64_t w = (int64_t)blockIdx.x * kAdjWaves + (threadIdx.x >> 6);
   if (w >= A.max_waves) return;
@@ -427,14 +446,15 @@ __global__ void __launch_bounds__(kAdjWaves * 64, 2) cfr_adjoint_kernel(AdjArgs 
   const int64_t l = lo;
   const int grp = (int)(w - A.wave_off[l]);
   const int n_tiles = (int)((A.link_off[l + 1] - A.link_off[l] + 31) / 32);
+  AdjVbuf& vb = vbuf[threadIdx.x >> 6];
   if constexpr (kAdjTP == 2) {
     if (grp * kAdjTP + 1 < n_tiles)
-      adj_wave<2>(A, w, l, grp, lane);
+      adj_wave<2>(A, w, l, grp, lane, vb);
     else
-      adj_wave<1>(A, w, l, grp, lane);
+      adj_wave<1>(A, w, l, grp, lane, vb);
   } else {
     (void)n_tiles;
-    adj_wave<1>(A, w, l, grp, lane);
+    adj_wave<1>(A, w, l, grp, lane, vb);
   }
 }
 
