@@ -115,7 +115,7 @@ typedef struct {
  *  per-interaction (neural materials, Sec. III-D): per_inter = float
  *           [3 * max_depth*n_paths] holding the rows eps_r, sigma, S, each
  *           indexed like the per-interaction path arrays; raw = NULL.
- * n_mat <= 1024.  mu_r = 1 and the XPD coefficient does not enter specular
+ * n_mat <= 512.  mu_r = 1 and the XPD coefficient does not enter specular
  * reflection. */
 typedef struct {
   int32_t n_mat;

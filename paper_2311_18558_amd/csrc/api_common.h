@@ -37,7 +37,7 @@ rtc_status reduce_all(const double* rows, int64_t R, int K, double* tmp, double*
                       hipStream_t s, const char* fn);
 size_t reduce_tmp_doubles(int64_t R, int K);
 
-constexpr int kMaxMat = 1024;
+constexpr int kMaxMat = 512;
 constexpr int kMaxDepth = 8;
 constexpr int kMaxFFT = 4096;
 

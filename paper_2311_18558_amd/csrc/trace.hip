@@ -298,7 +298,8 @@ __global__ void __launch_bounds__(kTraceBlock)
   double* acc = reinterpret_cast<double*>(smem + ((A.raw ? A.n_mat : 0) * sizeof(MatVal) + 15) / 16 * 16);
   stage_materials(A, tab);
   if constexpr (PER_ID) {
-    for (int i = threadIdx.x; i < 3 * A.n_mat; i += blockDim.x) acc[i] = 0.0;
+    for (int i = threadIdx.x; i < 3 * A.n_mat * (int)(blockDim.x >> 6); i += blockDim.x)
+      acc[i] = 0.0;
     __syncthreads();
   }
   const int lane = threadIdx.x & 63;
@@ -408,9 +409,11 @@ __global__ void __launch_bounds__(kTraceBlock)
       // Segmented reduction by material id, deterministic: each wave walks
       // the distinct ids present in it in increasing order; for each id the
       // lanes' contributions (fixed order over j) are summed by a butterfly
-      // in FP64; waves add into the LDS table one after another.
-      for (int w = 0; w < n_waves; ++w) {
-        if (wave == w) {
+      // in FP64 and added to the wave's own LDS table (waves are summed in
+      // order at the end).
+      {
+        double* wacc = acc + wave * 3 * A.n_mat;
+        {
           int done_mask = 0;  // bit j set once interaction j is accounted
           while (true) {
             int cand = 0x7fffffff;
@@ -435,32 +438,45 @@ __global__ void __launch_bounds__(kTraceBlock)
             ss = wave_sum_f64(ss);
             sS = wave_sum_f64(sS);
             if (lane == 0) {
-              acc[3 * mmin + 0] += se;
-              acc[3 * mmin + 1] += ss;
-              acc[3 * mmin + 2] += sS;
+              wacc[3 * mmin + 0] += se;
+              wacc[3 * mmin + 1] += ss;
+              wacc[3 * mmin + 2] += sS;
             }
           }
         }
-        __syncthreads();
       }
     }
   }
   if constexpr (PER_ID) {
-    for (int i = threadIdx.x; i < 3 * A.n_mat; i += blockDim.x)
-      block_part[(int64_t)blockIdx.x * 3 * A.n_mat + i] = acc[i];
+    __syncthreads();
+    for (int i = threadIdx.x; i < 3 * A.n_mat; i += blockDim.x) {
+      double t = 0.0;
+      for (int w = 0; w < n_waves; ++w) t += acc[w * 3 * A.n_mat + i];
+      block_part[(int64_t)blockIdx.x * 3 * A.n_mat + i] = t;
+    }
   }
   (void)eps0w_inv;
 }
 
-// Sum the per-block partials in block order (FP64) and apply the raw
-// parameter transforms: d eps/du0 = eps - 1, d sigma/du1 = sigma,
-// dS/du2 = S (1 - S).
-__global__ void trace_adjoint_finish_kernel(const double* block_part, int n_blocks, int n_mat,
-                                            const float* raw, float* dLd_raw) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= 3 * n_mat) return;
+// Sum the per-block partials (FP64, fixed order: strided per thread, then a
+// tree over the workgroup) and apply the raw parameter transforms:
+// d eps/du0 = eps - 1, d sigma/du1 = sigma, dS/du2 = S (1 - S).
+// One workgroup of kTraceBlock threads per output.
+__global__ void __launch_bounds__(kTraceBlock)
+    trace_adjoint_finish_kernel(const double* block_part, int n_blocks, int n_mat,
+                                const float* raw, float* dLd_raw) {
+  __shared__ double red[kTraceBlock];
+  const int i = blockIdx.x;  // output index < 3 n_mat
   double s = 0.0;
-  for (int b = 0; b < n_blocks; ++b) s += block_part[(int64_t)b * 3 * n_mat + i];
+  for (int b = threadIdx.x; b < n_blocks; b += blockDim.x) s += block_part[(int64_t)b * 3 * n_mat + i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  s = red[0];
   int m = i / 3, c = i % 3;
   double u = (double)raw[3 * m + c];
   double d;
@@ -597,7 +613,7 @@ extern "C" rtc_status rtc_trace_fields_adjoint(const rtc_radio* radio, const rtc
                 "%s: n_paths > 0 needs n_links >= 1", fn);
   }
   size_t tab_bytes = ((per_id ? mats->n_mat : 0) * sizeof(MatVal) + 15) / 16 * 16;
-  size_t shm = tab_bytes + (per_id ? 3 * mats->n_mat * sizeof(double) : 0);
+  size_t shm = tab_bytes + (per_id ? (kTraceBlock / 64) * 3 * mats->n_mat * sizeof(double) : 0);
   double* part = reinterpret_cast<double*>(ws);
   switch (depth_bucket(paths->max_depth)) {
 #define RTC_CASE(D)                                                                            \
@@ -621,7 +637,7 @@ extern "C" rtc_status rtc_trace_fields_adjoint(const rtc_radio* radio, const rtc
   if ((st = check_launch(fn)) != RTC_OK) return st;
   if (per_id) {
     int n = 3 * mats->n_mat;
-    hipLaunchKernelGGL(trace_adjoint_finish_kernel, dim3((n + 255) / 256), dim3(256), 0, s, part,
+    hipLaunchKernelGGL(trace_adjoint_finish_kernel, dim3(n), dim3(kTraceBlock), 0, s, part,
                        (int)blocks, mats->n_mat, mats->raw, dLd_raw);
     return check_launch(fn);
   }
