@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define RTC_ABI_VERSION 2
+#define RTC_ABI_VERSION 3
 
 typedef enum {
   RTC_OK = 0,
@@ -132,7 +132,8 @@ typedef enum {
   RTC_OP_CFR_LOSS = 1,
   RTC_OP_CFR_ADJOINT = 2,
   RTC_OP_TRACE_FIELDS_ADJOINT = 3,
-  RTC_OP_CFR_TARGET_STATS = 4
+  RTC_OP_CFR_TARGET_STATS = 4,
+  RTC_OP_PAPER_LOSS = 5
 } rtc_op;
 
 /* Bytes of device workspace `op` needs for n_links links (CFR rows are
@@ -185,6 +186,58 @@ rtc_status rtc_cfr_loss(const rtc_radio* radio, int32_t n_links, const void* H,
                         const void* H_tgt, const double* tgt_stats, const float* p_tgt,
                         float w_coh, float w_pdp, double* loss, void* dLdH, void* ws,
                         size_t ws_bytes, void* stream);
+
+/* CIR statistics of the paper's loss (Sec. III-E, Eqs. delay_spread and
+ * channel_gain), one per row (link l, element m) of H, c64
+ * [n_links, n_elem, n_sc].  The row's CIR is the centred 1/sqrt(N) IDFT of
+ * Sec. II-A with taps l = -N/2 .. N/2-1 (a path of delay tau lands at
+ * l = tau W, W = n_sc * df_hz); p_l = |h[l]|^2,
+ *   P       = sum_l p_l                                   (total gain)
+ *   tau_RMS = sqrt(sum_l (l - tbar)^2 p_l / P) / W        (seconds)
+ * with tbar = sum_l l p_l / P.  A row with P = 0 gets tau_RMS = 0.
+ * stats: device double [n_links * n_elem][2] = {P, tau_RMS}.  n_sc must be
+ * a power of two, 2 <= n_sc <= 4096.  No workspace. */
+rtc_status rtc_cir_stats(const rtc_radio* radio, int32_t n_links, const void* H, double* stats,
+                         void* stream);
+
+/* The paper's calibration loss (Sec. III-E, Eqs. loss and smape) averaged
+ * over the batch as in Algorithm 1, every CIR row being one example:
+ *   L = (1/B) sum_b [ w_tau l(tau_b, tau^_b) + w_gain l(alpha P_b, P^_b) ]
+ * with B = n_links * n_elem, l(x, y) = |x - y| / (x + y) (0 when x + y = 0),
+ * (P_b, tau_b) = tgt_stats (rtc_cir_stats of the measured CFRs) and
+ * (P^_b, tau^_b) the statistics of H.
+ * alpha: device double [2] = {alpha, number of updates so far}, the scale of
+ *   the measurements (Sec. III-F).  With update_alpha != 0 it is first
+ *   advanced by one step of Eq. scaling_param: alpha^ = sum_b P_b P^_b /
+ *   sum_b P_b^2 over this batch (Eq. alpha_hat; P^_b = sum_n |H_n|^2), then
+ *   alpha = alpha^ on the first update (alpha_0 = alpha^_1) and
+ *   delta * alpha + (1 - delta) * alpha^ afterwards, delta in [0, 1]; if
+ *   sum_b P_b^2 = 0 alpha is left unchanged.  With update_alpha = 0 the
+ *   stored alpha is used as it is ({1, 0}: unscaled measurements).
+ *   alpha is a constant of the gradient (estimated, not learned).
+ * loss: device double [3] = {L, mean l of tau, mean l of gain}.
+ * pred_stats: device double [B][2] = {P^_b, tau^_b}, or NULL.
+ * dLdH: c64 like H, or NULL; it may alias H (in place).  Where l has its
+ *   kink (x = y) its derivative is taken as 0, and a row whose delay
+ *   profile has zero variance gets no delay-spread gradient.
+ * ws: rtc_workspace_size(RTC_OP_PAPER_LOSS, ...) bytes.  n_sc as for
+ *   rtc_cir_stats. */
+rtc_status rtc_paper_loss(const rtc_radio* radio, int32_t n_links, const void* H,
+                          const double* tgt_stats, double* alpha, int32_t update_alpha,
+                          double delta, float w_tau, float w_gain, double* loss,
+                          double* pred_stats, void* dLdH, void* ws, size_t ws_bytes,
+                          void* stream);
+
+/* Evaluation metrics of Sec. IV-C per measurement point (link): with the
+ * gains and delay spreads of its n_elem rows averaged,
+ *   ALE = |10 log10(scale * Pbar) - 10 log10(Pbar^)|     (dB)
+ *   RAE = |taubar - taubar^| / taubar
+ * meas, pred: device double [n_links * n_elem][2] = {P, tau_RMS} (from
+ * rtc_cir_stats); scale: device double (for example alpha[0] of
+ * rtc_paper_loss) or NULL for 1.  out: device double [n_links][2] =
+ * {ALE, RAE}.  Zero averages give inf or NaN as IEEE arithmetic does. */
+rtc_status rtc_eval_ale_rae(int32_t n_links, int32_t n_elem, const double* meas,
+                            const double* pred, const double* scale, double* out, void* stream);
 
 /* Adjoint of rtc_cfr:
  *   G[m, i]  = sum_n dLdH[l(i), m, n] exp(+j 2 pi f_n tau_i)

@@ -13,7 +13,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB_PATH = os.path.join(HERE, "librtcal.so")
 
-SOURCES = ["api.hip", "trace.hip", "cfr.hip", "loss.hip", "adam.hip", "mlp.hip"]
+SOURCES = ["api.hip", "trace.hip", "cfr.hip", "loss.hip", "paper_loss.hip", "adam.hip",
+           "mlp.hip"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950",

@@ -72,6 +72,7 @@ size_t ws_cfr_loss(const rtc_radio* r, int32_t n_links);
 size_t ws_cfr_adjoint(const rtc_radio* r, int32_t n_links, int32_t n_paths);
 size_t ws_trace_adjoint(int32_t n_paths, int32_t n_mat);
 size_t ws_target_stats(const rtc_radio* r, int32_t n_links);
+size_t ws_paper_loss(const rtc_radio* r, int32_t n_links);
 }  // namespace rtc
 
 extern "C" {
@@ -92,6 +93,8 @@ size_t rtc_workspace_size(int op, const rtc_radio* radio, int32_t n_links, int32
       return rtc::ws_trace_adjoint(n_paths, n_mat);
     case RTC_OP_CFR_TARGET_STATS:
       return radio ? rtc::ws_target_stats(radio, n_links) : 0;
+    case RTC_OP_PAPER_LOSS:
+      return radio ? rtc::ws_paper_loss(radio, n_links) : 0;
     default:
       return 0;
   }

@@ -28,6 +28,7 @@ RTC_OP_CFR_LOSS = 1
 RTC_OP_CFR_ADJOINT = 2
 RTC_OP_TRACE_FIELDS_ADJOINT = 3
 RTC_OP_CFR_TARGET_STATS = 4
+RTC_OP_PAPER_LOSS = 5
 
 
 class Radio(ctypes.Structure):
@@ -64,6 +65,10 @@ _SIGS = {
                                             c_vp, c_size, c_vp]),
     "rtc_cfr_loss": (ctypes.c_int, [ctypes.POINTER(Radio), c_i32, c_vp, c_vp, c_vp, c_vp, c_f32,
                                     c_f32, c_vp, c_vp, c_vp, c_size, c_vp]),
+    "rtc_cir_stats": (ctypes.c_int, [ctypes.POINTER(Radio), c_i32, c_vp, c_vp, c_vp]),
+    "rtc_paper_loss": (ctypes.c_int, [ctypes.POINTER(Radio), c_i32, c_vp, c_vp, c_vp, c_i32, c_f64,
+                                      c_f32, c_f32, c_vp, c_vp, c_vp, c_vp, c_size, c_vp]),
+    "rtc_eval_ale_rae": (ctypes.c_int, [c_i32, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "rtc_cfr_adjoint": (ctypes.c_int, [ctypes.POINTER(Radio), ctypes.POINTER(Paths), c_vp, c_vp,
                                        c_vp, c_vp, c_vp, c_vp, c_vp, c_size, c_vp]),
     "rtc_trace_fields_adjoint": (ctypes.c_int, [ctypes.POINTER(Radio), ctypes.POINTER(Paths),
@@ -229,6 +234,27 @@ def cfr_loss(radio, n_links, H, H_tgt, tgt_stats, w_coh, w_pdp, loss, dLdH, ws, 
     _check(load().rtc_cfr_loss(ctypes.byref(radio), n_links, _ptr(H), _ptr(H_tgt), _ptr(tgt_stats),
                                _ptr(p_tgt), float(w_coh), float(w_pdp), _ptr(loss), _ptr(dLdH),
                                _ptr(ws), ws.numel(), _stream(stream)), "rtc_cfr_loss")
+
+
+def cir_stats(radio, n_links, H, stats, stream=None):
+    """stats: float64 [n_links*n_elem, 2] receiving {P, tau_RMS} per CIR row."""
+    _check(load().rtc_cir_stats(ctypes.byref(radio), n_links, _ptr(H), _ptr(stats),
+                                _stream(stream)), "rtc_cir_stats")
+
+
+def paper_loss(radio, n_links, H, tgt_stats, alpha, loss, dLdH, ws, update_alpha=False,
+               delta=0.99, w_tau=1.0, w_gain=1.0, pred_stats=None, stream=None):
+    """alpha: float64 [2] device state {alpha, updates}; loss: float64 [3]."""
+    _check(load().rtc_paper_loss(ctypes.byref(radio), n_links, _ptr(H), _ptr(tgt_stats),
+                                 _ptr(alpha), int(bool(update_alpha)), float(delta), float(w_tau),
+                                 float(w_gain), _ptr(loss), _ptr(pred_stats), _ptr(dLdH),
+                                 _ptr(ws), ws.numel(), _stream(stream)), "rtc_paper_loss")
+
+
+def eval_ale_rae(n_links, n_elem, meas, pred, out, scale=None, stream=None):
+    """out: float64 [n_links, 2] receiving {ALE (dB), RAE} per link."""
+    _check(load().rtc_eval_ale_rae(int(n_links), int(n_elem), _ptr(meas), _ptr(pred), _ptr(scale),
+                                   _ptr(out), _stream(stream)), "rtc_eval_ale_rae")
 
 
 def cfr_adjoint(radio, paths, a, psi, g, dLdH, dLda, dLdg, ws, stream=None):

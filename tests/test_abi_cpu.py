@@ -109,3 +109,31 @@ def test_workspace_sizes(lib):
     assert n_adj >= 512 * 32 * 16
     assert lib.workspace_size(lib.RTC_OP_TRACE_FIELDS_ADJOINT, r, 512, 100000, 10) > 0
     assert lib.workspace_size(99, r, 1, 1) == 0
+
+
+def test_paper_loss_argument_checks(lib):
+    so = lib.load()
+    r = lib.make_radio(3.5e9, 1e5, 200, 1)
+    st = so.rtc_cir_stats(ctypes.byref(r), 4, ctypes.c_void_p(16), ctypes.c_void_p(32), None)
+    assert st == -6 and b"power of two" in so.rtc_last_error()
+    r = _radio(lib)
+    st = so.rtc_cir_stats(ctypes.byref(r), 0, ctypes.c_void_p(16), ctypes.c_void_p(32), None)
+    assert st == -2 and b"n_links" in so.rtc_last_error()
+    st = so.rtc_cir_stats(ctypes.byref(r), 4, None, ctypes.c_void_p(32), None)
+    assert st == -1
+    p = ctypes.c_void_p(16)
+    st = so.rtc_paper_loss(ctypes.byref(r), 4, p, p, p, 1, 1.5, 1.0, 1.0, p, None, None, p,
+                           1 << 20, None)
+    assert st == -1 and b"delta" in so.rtc_last_error()
+    st = so.rtc_paper_loss(ctypes.byref(r), 4, p, p, p, 1, 0.9, 1.0, 1.0, p, None, None, p, 8,
+                           None)
+    assert st == -4 and b"workspace" in so.rtc_last_error()
+    st = so.rtc_paper_loss(ctypes.byref(r), 4, p, None, p, 0, 0.9, 1.0, 1.0, p, None, None, p,
+                           1 << 20, None)
+    assert st == -1 and b"tgt_stats" in so.rtc_last_error()
+    st = so.rtc_eval_ale_rae(3, 0, p, p, None, p, None)
+    assert st == -2
+    st = so.rtc_eval_ale_rae(3, 2, p, None, None, p, None)
+    assert st == -1
+    n = lib.workspace_size(lib.RTC_OP_PAPER_LOSS, r, 512, 0)
+    assert n >= 512 * 4 * 2 * 8
