@@ -13,6 +13,8 @@ Prints ONE JSON line (rank 0):
                  BF16 peak / 6 split products); its FP32-matrix-peak fraction
                  is given beside it
   cpu_baseline   the FP64 oracle on a bounded sample of links, host cores
+  paper_loss_step  the same step with the paper's own loss (SMAPE of RMS
+                 delay spread and gain, moving-average measurement scale)
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
        python bench.py --copy-probe ...      also runs a 2 GiB device copy
                                              first (HBM counter calibration)
@@ -118,9 +120,46 @@ def diffuse_bench(steps=3, warmup=1):
            "cfr_adjoint_tflops": round(fl / (per["cfr_adjoint"] * 1e-3) / 1e12, 2),
            "trace_fields_paths_per_s": round(P / (per["trace_fields"] * 1e-3), 1),
            "trace_fields_adjoint_paths_per_s": round(P / (per["trace_fields_adjoint"] * 1e-3), 1)}
+    out["paper_loss_step"] = paper_loss_step(st, radio, w, raw0, H_tgt, min(args.steps, 5))
     del pipe, H_tgt
     torch.cuda.empty_cache()
     return out
+
+
+def paper_loss_step(st, radio, w, raw0, H_tgt, steps, warmup=1):
+    """The same step with the paper's own loss (SMAPE of RMS delay spread and
+    gain per CIR row) and the moving-average measurement scale in place of
+    the workload loss: per-stage times over `steps` steps."""
+    from paper_2311_18558_amd.pipeline import Pipeline
+    pipe = Pipeline(st, radio, w.raw, w.g, loss="paper", update_alpha=True, delta=0.99)
+    pipe.set_target(H_tgt)
+    pipe.raw.copy_(torch.tensor(raw0, device=pipe.dev))
+    for _ in range(warmup):
+        pipe.step()
+    torch.cuda.synchronize()
+    events = {}
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        pipe.step(events=events)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    per = {k: round(float(np.mean([a.elapsed_time(b) for a, b in v])), 4)
+           for k, v in events.items()}
+    L, M, N = st.n_links, radio.n_elem, radio.n_sc
+    # the gain pass for the scale estimate reads H once, the loss pass reads
+    # H and writes dL/dH: 24 bytes per tap
+    gbs = 24.0 * L * M * N / (per["paper_loss"] * 1e-3) / 1e9
+    res = {"steps": steps, "ms_per_step": round(ms, 4),
+           "taps_per_s": round(L * M * N / (ms * 1e-3), 1), "kernels_ms": per,
+           "paper_loss_gbs": round(gbs, 1), "loss": pipe.loss.cpu().tolist(),
+           "alpha": pipe.alpha[0].item()}
+    log(f"paper-loss step: {res}")
+    del pipe
+    torch.cuda.empty_cache()
+    return res
 
 
 def cpu_baseline(w, budget_s=15.0, max_links=8192):
@@ -368,6 +407,7 @@ def main():
         "loss": loss[0],
         "wall_s": round(wall, 3),
     }
+    out["paper_loss_step"] = paper_loss_step(st, radio, w, raw0, H_tgt, min(args.steps, 5))
     del pipe, H_tgt
     torch.cuda.empty_cache()
     if not args.no_diffuse:

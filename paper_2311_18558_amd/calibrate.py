@@ -5,6 +5,11 @@ in Sec. IV-B) on fixed paths, in two parametrisations:
             embeddings): raw [n_mat, 3] plus the complex element gains
   'neural'  neural materials (Sec. III-D): MLP weights plus the gains
 
+The loss is the workload loss (coherent + power-delay-profile NMSE) or, with
+loss="paper", the paper's own (Sec. III-E: SMAPE of RMS delay spread and gain
+per CIR row, against measurements scaled by the moving-average estimate of
+Sec. III-F when update_alpha is set).
+
 Every step of the method runs in librtcal; this module draws batches,
 stages their inputs (device gathers of the fixed path store and targets) and
 sequences the library calls on one stream.
@@ -35,8 +40,13 @@ def mlp_out_bias():
 
 class Calibrator:
     def __init__(self, dp, radio, H_all, mode, raw0=None, mlp_params0=None, g0=None,
-                 aabb=None, lr=0.01, lr_mlp=1e-3, lr_gain=None, device="cuda"):
+                 aabb=None, lr=0.01, lr_mlp=1e-3, lr_gain=None, device="cuda", loss="workload",
+                 update_alpha=False, delta=0.99):
+        if loss not in ("workload", "paper"):
+            raise ValueError(loss)
         self.dev = torch.device(device)
+        self.loss_kind, self.update_alpha, self.delta = loss, update_alpha, delta
+        self.alpha = torch.tensor([1.0, 0.0], dtype=torch.float64, device=self.dev)
         self.dp = dp
         self.radio = lib.radio_from(radio)
         self.H_all = H_all
@@ -64,6 +74,12 @@ class Calibrator:
             raise ValueError(mode)
         self.dparams = torch.empty_like(self.params)
         self._bufs = {}
+        if loss == "paper":
+            # per-row gain and RMS delay spread of every measured CFR, once
+            La = H_all.shape[0]
+            self.tgt_all = torch.empty((La * M, 2), dtype=torch.float64, device=self.dev)
+            lib.cir_stats(self.radio, La, H_all, self.tgt_all)
+            self.tgt_all = self.tgt_all.view(La, M, 2)
 
     def _buf(self, name, shape, dtype):
         b = self._bufs.get(name)
@@ -107,11 +123,16 @@ class Calibrator:
         L, P = b.n_links, b.n_paths
         M, N = self.radio.n_elem, self.radio.n_sc
         H = self._buf("H", (L, M, N), torch.complex64)
-        H_t = self.H_all[links]
         mats, aux, a, psi = self.forward(b, H)
         loss = self._buf("loss", (3,), torch.float64)
-        lib.cfr_loss(self.radio, L, H, H_t, None, 1.0, 1.0, loss, H,
-                     self._ws(lib.RTC_OP_CFR_LOSS, L, P))
+        if self.loss_kind == "paper":
+            tgt = self.tgt_all[links].reshape(-1, 2)
+            lib.paper_loss(self.radio, L, H, tgt, self.alpha, loss, H,
+                           self._ws(lib.RTC_OP_PAPER_LOSS, L, P), update_alpha=self.update_alpha,
+                           delta=self.delta)
+        else:
+            lib.cfr_loss(self.radio, L, H, self.H_all[links], None, 1.0, 1.0, loss, H,
+                         self._ws(lib.RTC_OP_CFR_LOSS, L, P))
         dLda = self._buf("dLda", (P,), torch.complex64)
         dLdg = self._buf("dLdg", (M,), torch.complex64)
         lib.cfr_adjoint(self.radio, b, a, psi, self.g, H, dLda, dLdg,
@@ -155,6 +176,35 @@ class Calibrator:
             num += loss[1].item() * zc
             den += zc
         return num / den
+
+
+    def paper_metrics(self, links, chunk=512):
+        """Held-out paper loss (current alpha, no update) and the Sec. IV-C
+        metrics: mean ALE (dB) and mean RAE over `links`; requires
+        loss="paper"."""
+        M, N = self.radio.n_elem, self.radio.n_sc
+        tot = {"loss": 0.0, "ale": 0.0, "rae": 0.0}
+        n = 0
+        for i in range(0, len(links), chunk):
+            ls = links[i:i + chunk]
+            b, _ = lib.subset_links(self.dp, ls)
+            H = self._buf("Hn", (b.n_links, M, N), torch.complex64)
+            self.forward(b, H)
+            tgt = self.tgt_all[ls].reshape(-1, 2)
+            pred = self._buf("pred", (b.n_links * M, 2), torch.float64)
+            loss = self._buf("lossn", (3,), torch.float64)
+            lib.paper_loss(self.radio, b.n_links, H, tgt, self.alpha, loss, None,
+                           self._ws(lib.RTC_OP_PAPER_LOSS, b.n_links, b.n_paths),
+                           pred_stats=pred)
+            m = self._buf("metrics", (b.n_links, 2), torch.float64)
+            lib.eval_ale_rae(b.n_links, M, tgt, pred, m,
+                             scale=self.alpha[:1] if self.update_alpha else None)
+            k = b.n_links
+            tot["loss"] += loss[0].item() * k
+            tot["ale"] += m[:, 0].sum().item()
+            tot["rae"] += m[:, 1].sum().item()
+            n += k
+        return {k: v / n for k, v in tot.items()}
 
 
 def targets(dp, radio, raw=None, per_inter=None, g=None, device="cuda", chunk=2048):

@@ -1,9 +1,13 @@
 """One calibration step of the hot path with preallocated device buffers.
 
-    trace_fields -> cfr -> cfr_loss (dL/dH in place) -> cfr_adjoint
+    trace_fields -> cfr -> loss (dL/dH in place) -> cfr_adjoint
                  -> trace_fields_adjoint -> Adam
 
-(Algorithm 1 of the paper with the workload loss, per-material-id mode.)
+(Algorithm 1 of the paper, per-material-id mode.)  The loss is either the
+workload loss (coherent + power-delay-profile NMSE, loss="workload") or the
+paper's own (loss="paper": SMAPE of RMS delay spread and gain per CIR row,
+Sec. III-E, with the moving-average measurement scale of Sec. III-F when
+update_alpha is set).
 Every step runs in the library's kernels; this module only owns buffers,
 workspaces and the order of calls, all on one stream.
 """
@@ -14,7 +18,12 @@ from . import lib
 
 
 class Pipeline:
-    def __init__(self, store, radio, raw0, g0, device="cuda", stream=None):
+    def __init__(self, store, radio, raw0, g0, device="cuda", stream=None, loss="workload",
+                 update_alpha=False, delta=0.99):
+        if loss not in ("workload", "paper"):
+            raise ValueError(loss)
+        self.loss_kind = loss
+        self.update_alpha, self.delta = update_alpha, delta
         self.dev = torch.device(device)
         self.stream = stream
         self.paths = store if isinstance(store, lib.DevicePaths) else lib.DevicePaths(store, self.dev)
@@ -32,7 +41,10 @@ class Pipeline:
         self.dLda = torch.empty(P, dtype=torch.complex64, device=self.dev)
         self.dLdg = torch.empty(M, dtype=torch.complex64, device=self.dev)
         self.draw = torch.empty_like(self.raw)
-        self.ws_loss = lib.workspace(lib.RTC_OP_CFR_LOSS, self.radio, L, P, 1, self.dev)
+        op = lib.RTC_OP_CFR_LOSS if loss == "workload" else lib.RTC_OP_PAPER_LOSS
+        self.ws_loss = lib.workspace(op, self.radio, L, P, 1, self.dev)
+        # measurement scale state {alpha, updates} (paper loss)
+        self.alpha = torch.tensor([1.0, 0.0], dtype=torch.float64, device=self.dev)
         self.ws_adj = lib.workspace(lib.RTC_OP_CFR_ADJOINT, self.radio, L, P, 1, self.dev)
         self.ws_tr = lib.workspace(lib.RTC_OP_TRACE_FIELDS_ADJOINT, self.radio, L, P,
                                    self.n_mat, self.dev)
@@ -57,16 +69,28 @@ class Pipeline:
                 self.H if out is None else out, self.stream)
 
     def set_target(self, H_tgt):
-        """Targets for the loss; their energies and power delay profiles are
-        computed once here (they do not change while calibrating on this
-        batch)."""
+        """Targets for the loss; what the loss needs of them is computed once
+        here (they do not change while calibrating on this batch): energies
+        and power delay profiles (workload loss) or per-row gain and RMS
+        delay spread (paper loss)."""
         self.H_tgt = H_tgt
+        if self.loss_kind == "paper":
+            self.tgt_stats = torch.empty((self.L * self.M, 2), dtype=torch.float64,
+                                         device=self.dev)
+            lib.cir_stats(self.radio, self.L, H_tgt, self.tgt_stats, self.stream)
+            self.alpha.copy_(torch.tensor([1.0, 0.0], dtype=torch.float64))
+            return
         self.tgt_stats = torch.empty(2, dtype=torch.float64, device=self.dev)
         self.p_tgt = torch.empty(H_tgt.shape, dtype=torch.float32, device=self.dev)
         lib.cfr_target_stats(self.radio, self.L, H_tgt, self.tgt_stats, self.ws_loss, self.stream,
                              p_tgt=self.p_tgt)
 
     def loss_and_grad(self):
+        if self.loss_kind == "paper":
+            lib.paper_loss(self.radio, self.L, self.H, self.tgt_stats, self.alpha, self.loss,
+                           self.H, self.ws_loss, update_alpha=self.update_alpha,
+                           delta=self.delta, stream=self.stream)
+            return
         lib.cfr_loss(self.radio, self.L, self.H, self.H_tgt, self.tgt_stats, 1.0, 1.0,
                      self.loss, self.H, self.ws_loss, self.stream, p_tgt=self.p_tgt)
 
@@ -86,14 +110,17 @@ class Pipeline:
             lib.adam_step(self.g_real, self.dLdg_real, self.m_g, self.v_g, self.t, lr=lr,
                           stream=self.stream)
 
-    STAGES = ("trace_fields", "cfr", "cfr_loss", "cfr_adjoint", "trace_fields_adjoint", "adam")
+    @property
+    def stages(self):
+        loss = "cfr_loss" if self.loss_kind == "workload" else "paper_loss"
+        return ("trace_fields", "cfr", loss, "cfr_adjoint", "trace_fields_adjoint", "adam")
 
     def step(self, lr=0.01, events=None):
         """One full calibration step.  `events`, if given, maps stage name
         to a list that receives (start, end) CUDA events per stage."""
         fns = (self.trace, self.cfr, self.loss_and_grad, self.cfr_adjoint, self.trace_adjoint,
                lambda: self.adam(lr))
-        for name, fn in zip(self.STAGES, fns):
+        for name, fn in zip(self.stages, fns):
             if events is None:
                 fn()
             else:

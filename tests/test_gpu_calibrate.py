@@ -58,3 +58,44 @@ def test_learned_field_beats_plain(gpu_lib, small):
     print(res)
     assert res["learned_reached_plain_nmse"]
     assert res["learned_heldout_nmse_at_plain_steps"] < res["plain_heldout_nmse"]
+
+
+def test_paper_loss_calibration_with_unknown_scale(gpu_lib, small):
+    """Algorithm 1 with the paper's own loss (SMAPE of RMS delay spread and
+    gain per CIR row) on measurements that are the method's own CFRs at the
+    true materials, scaled by an unknown common factor: the moving-average
+    scale estimate finds the factor, and the held-out loss and ALE fall.
+    The element gains are held at their true values (trained together with
+    alpha the overall level would be unidentifiable)."""
+    import math
+    from paper_2311_18558_amd import lib
+    from paper_2311_18558_amd.calibrate import Calibrator, raw_prior, targets
+    w = small
+    say("paper-loss calibration with an unknown measurement scale")
+    dp = lib.DevicePaths(w.store)
+    c = 0.25  # measured gains = c x true gains
+    H = targets(dp, w.radio, raw=w.raw, g=w.g) * math.sqrt(c)
+    held = torch.tensor(w.meta["heldout"], device="cuda")
+    train = torch.tensor(w.meta["train"], device="cuda")
+    # at the truth: alpha^ = 1 / c on the first step, the loss vanishes
+    gt = Calibrator(dp, w.radio, H, "per_id", raw0=w.raw, g0=w.g, lr=0.0, lr_gain=0.0,
+                    loss="paper", update_alpha=True, delta=0.9)
+    gt.step(train[:128])
+    a0 = gt.alpha[0].item()
+    m_gt = gt.paper_metrics(held)
+    say(f"  truth: alpha {a0:.6f}, held-out {m_gt}")
+    assert abs(a0 - 1.0 / c) <= 1e-5 / c
+    assert m_gt["loss"] <= 1e-5 and m_gt["ale"] <= 1e-4
+    cal = Calibrator(dp, w.radio, H, "per_id", raw0=raw_prior(w.meta["n_mat"]), g0=w.g,
+                     lr_gain=0.0, loss="paper", update_alpha=True, delta=0.9)
+    cal.step(train[:128], update=False)
+    m0 = cal.paper_metrics(held)
+    rng = np.random.default_rng(1)
+    for _ in range(400):
+        cal.step(train[torch.tensor(rng.choice(len(train), 128, replace=False), device="cuda")])
+    m1 = cal.paper_metrics(held)
+    a1 = cal.alpha[0].item()
+    say(f"  held-out before {m0}, after {m1}; alpha {a1:.4f} (true {1 / c})")
+    assert m1["loss"] < 0.3 * m0["loss"]
+    assert m1["ale"] < 0.3 * m0["ale"]
+    assert abs(a1 * c - 1.0) < 0.1
