@@ -120,7 +120,6 @@ def diffuse_bench(steps=3, warmup=1):
            "cfr_adjoint_tflops": round(fl / (per["cfr_adjoint"] * 1e-3) / 1e12, 2),
            "trace_fields_paths_per_s": round(P / (per["trace_fields"] * 1e-3), 1),
            "trace_fields_adjoint_paths_per_s": round(P / (per["trace_fields_adjoint"] * 1e-3), 1)}
-    out["paper_loss_step"] = paper_loss_step(st, radio, w, raw0, H_tgt, min(args.steps, 5))
     del pipe, H_tgt
     torch.cuda.empty_cache()
     return out

@@ -52,7 +52,7 @@ typedef enum {
 } rtc_status;
 
 /* OFDM grid and antennas.  Subcarrier n (0..n_sc-1) is at
- *   f_n = fc_hz + (n - n_sc/2) * df_hz                     (Sec. II-A)
+ *   f_n = fc_hz + (n - floor(n_sc/2)) * df_hz              (Sec. II-A)
  * The Tx is a uniform linear array of n_elem isotropic elements with
  * half-wavelength spacing along the unit vector ula_axis, centred on the Tx
  * position; the Rx is one isotropic element.  zeta_tx / zeta_rx are the

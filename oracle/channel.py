@@ -2,7 +2,7 @@
 
   * CFR as a sum over paths, Eq. (cfr_cont): H(f) = sum_i a_i e^{-j 2 pi f tau_i}
   * discrete OFDM CFR, Sec. II-A: H[n] = H(f_c + n df), n = -N/2 .. N/2-1,
-    stored at index n + N/2
+    stored at index n + N/2 (odd N: n = -(N-1)/2 .. (N-1)/2)
   * CIR by the centred N-point IDFT with 1/sqrt(N), Sec. II-A; the power
     delay profile p_l = |h[l]|^2 (Eq. delay_spread's p_l)
   * workload loss: coherent NMSE + power-delay-profile NMSE, each normalised
@@ -17,9 +17,11 @@ from .em import c128, f64
 
 
 def subcarrier_freqs(fc, bandwidth, n_sc):
-    """f_n = fc + (n - N/2) * W/N for storage index n = 0..N-1."""
+    """f_n = fc + (n - floor(N/2)) * W/N for storage index n = 0..N-1 (for
+    the even N of Sec. II-A, n - N/2 = -N/2 .. N/2-1; for odd N the carrier
+    is the middle subcarrier)."""
     n = torch.arange(n_sc, dtype=f64)
-    return fc + (n - n_sc / 2) * (bandwidth / n_sc)
+    return fc + (n - (n_sc // 2)) * (bandwidth / n_sc)
 
 
 def array_coefficients(a, psi, g):

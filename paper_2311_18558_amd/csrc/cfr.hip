@@ -9,11 +9,16 @@
 // per real product, FP32 accumulation; see split_bf16.h), which keeps FP32
 // accuracy at the BF16 instruction rate.  A lane holds eight k values of its
 // row (A) or column (B): in the forward product k runs over paths, so lane l
-// generates B for row l%32 and E for column l%32 over paths 8(l/32)..+7 of a
-// 16-path chunk; the complex product takes four real products,
-//     Re H += B_re E_re + (-B_im) E_im,   Im H += B_re E_im + B_im E_re.
-// The subcarrier phase f_n tau_i (thousands of cycles) is reduced in FP64;
-// within a wave, tile t+1 is tile t times exp(-j 2 pi 32 df tau_i).
+// generates the A operand for element row l%32 and the B operand for
+// column l%32 over paths 8(l/32)..+7 of a 16-path chunk.
+//
+// The forward product uses the symmetry of the subcarrier grid about its
+// midpoint: the exponentials of the subcarriers at offsets +t and -t from
+// it are conjugate up to a common per-path phase, which moves into the A
+// operand, so a complex-by-real product gives both subcarriers of a pair
+// (see cfr_pair_tile).  The subcarrier phases (thousands of cycles) are
+// reduced in FP64; within a wave, pair tile t+1 is tile t times
+// exp(-j 2 pi 32 df tau_i).
 //
 // The adjoint G[m, i] = sum_n dLdH[m, n] conj(E[i, n]) is the same kind of
 // product with the subcarriers as the contraction axis: lane l reads eight
@@ -30,49 +35,55 @@
 namespace rtc {
 
 constexpr int kCfrWaves = 4;   // waves per workgroup (forward)
-constexpr int kCfrTiles = 8;   // 32-subcarrier tiles per wave (forward)
+constexpr int kCfrPairTiles = 4;  // tiles of 32 subcarrier pairs per wave (forward)
 constexpr int kAdjWaves = 4;   // waves per workgroup (adjoint)
 constexpr int kAdjTP = 2;      // 32-path tiles per wave (adjoint)
 constexpr double kInv2Pi = 0.15915494309189533577;
 
 struct CfrArgs {
   int n_links, M, N;
-  int n_mblk, n_nchunk;
+  int n_mblk, n_qchunk;
+  int Q;        // subcarrier pairs, ceil(N/2)
   const int64_t* link_off;
   const float2* a;
   const float* psi;
   const double* tau;
   const float2* g;
-  double f0;    // frequency of subcarrier 0
+  double fref;  // midpoint of the grid, f0 + (N-1)/2 df
+  double t_off; // t of pair 0: 1/2 for even N, 0 for odd N
   double df;    // subcarrier spacing
   double cm;    // (M-1)/2
 };
 
-// Four accumulator chains advance together (two tiles, real and imaginary
-// parts), so consecutive MFMAs are independent.
-RTC_DEV void cfr_tile_pair(const Split3& BR, const Split3& BI, const Split3& NBI,
-                           const Split3& ER0, const Split3& EI0, const Split3& ER1,
-                           const Split3& EI1, floatx16& re0, floatx16& im0, floatx16& re1,
-                           floatx16& im1) {
-  re0 = mac6(BR, ER0, re0);
-  im0 = mac6(BR, EI0, im0);
-  re1 = mac6(BR, ER1, re1);
-  im1 = mac6(BR, EI1, im1);
-  re0 = mac6(NBI, EI0, re0);
-  im0 = mac6(BI, ER0, im0);
-  re1 = mac6(NBI, EI1, re1);
-  im1 = mac6(BI, ER1, im1);
+// Conjugate pairs of subcarriers.  The grid f_n = f0 + n df is symmetric
+// about its midpoint f_ref = f0 + (N-1)/2 df, and with t = n - (N-1)/2
+//     E[i, n] = c_i u_i(t),  c_i = exp(-j 2 pi f_ref tau_i),
+//     u_i(t) = exp(-j 2 pi t df tau_i),  u_i(-t) = conj(u_i(t)).
+// Pair q (0 <= q < ceil(N/2)) joins n_hi = floor(N/2) + q and
+// n_lo = N - 1 - n_hi (t = +-t_q); with A'[m, i] = B[m, i] c_i,
+//     X = sum_i A' Re u_i(t_q),  Y = sum_i A' Im u_i(t_q)      (complex)
+//     H[m, n_hi] = X + j Y,      H[m, n_lo] = X - j Y,
+// so one complex-by-real product (four real products, as one complex
+// product took before) yields two subcarriers, and only the real and
+// imaginary parts of u are split.  For odd N pair 0 is the middle
+// subcarrier alone (t = 0, Y = 0).
+RTC_DEV void cfr_pair_tile(const Split3& AR, const Split3& AI, const Split3& UR,
+                           const Split3& UI, floatx16& xr, floatx16& xi, floatx16& yr,
+                           floatx16& yi) {
+  xr = mac6(AR, UR, xr);
+  xi = mac6(AI, UR, xi);
+  yr = mac6(AR, UI, yr);
+  yi = mac6(AI, UI, yi);
 }
 
-// One wave per (link, 32-row element block, kCfrTiles x 32 subcarriers).
+// One wave per (link, 32-row element block, kCfrPairTiles x 32 pairs).
 __global__ void __launch_bounds__(kCfrWaves * 64) cfr_kernel(CfrArgs A, float2* __restrict__ H) {
-  static_assert(kCfrTiles % 2 == 0, "tiles are processed in pairs");
   const int lane = threadIdx.x & 63;
   const int half = lane >> 5;
   const int col = lane & 31;
   const int64_t wt = (int64_t)blockIdx.x * kCfrWaves + (threadIdx.x >> 6);
-  const int nchunk = (int)(wt % A.n_nchunk);
-  const int64_t rest = wt / A.n_nchunk;
+  const int qchunk = (int)(wt % A.n_qchunk);
+  const int64_t rest = wt / A.n_qchunk;
   const int mblk = (int)(rest % A.n_mblk);
   const int64_t l = rest / A.n_mblk;
   if (l >= A.n_links) return;
@@ -80,18 +91,18 @@ __global__ void __launch_bounds__(kCfrWaves * 64) cfr_kernel(CfrArgs A, float2* 
   const int m = mblk * 32 + col;
   const float2 gm = m < A.M ? A.g[m] : make_float2(0.0f, 0.0f);
   const double mc_cyc = ((double)m - A.cm) * kInv2Pi;
-  const int n_base = nchunk * 32 * kCfrTiles;
-  const double f_lane = A.f0 + (double)(n_base + col) * A.df;
+  const int q_base = qchunk * 32 * kCfrPairTiles;
+  // t of the lane's pair column in tile 0, in subcarrier spacings
+  const double t_lane_df = ((double)(q_base + col) + A.t_off) * A.df;
   const double df32 = 32.0 * A.df;
   const int64_t off0 = A.link_off[l];
   const int64_t off1 = A.link_off[l + 1];
 
-  floatx16 acc_re[kCfrTiles], acc_im[kCfrTiles];
+  floatx16 acc[kCfrPairTiles][4];
 #pragma unroll
-  for (int t = 0; t < kCfrTiles; ++t) {
-    acc_re[t] = floatx16{0};
-    acc_im[t] = floatx16{0};
-  }
+  for (int t = 0; t < kCfrPairTiles; ++t)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[t][k] = floatx16{0};
 
   // The lane's eight paths of a 16-path chunk.  Software pipeline: while
   // the MFMAs of chunk k run, the wave loads the path data of chunk k+1 and
@@ -110,29 +121,31 @@ __global__ void __launch_bounds__(kCfrWaves * 64) cfr_kernel(CfrArgs A, float2* 
       pt[j] = A.tau[pc];
     }
   };
-  // A operand B[m, i] = a_i g_m exp(j psi_i (m - c)); B operand anchor
-  // E[i, n] at the lane's subcarrier of tile 0 and the tile step w_i
+  // A operand A'[m, i] = a_i g_m exp(j psi_i (m - c)) c_i; B operand anchor
+  // u_i at the lane's pair column of tile 0 and the tile step
+  // w_i = exp(-j 2 pi 32 df tau_i)
   auto operands = [&](const float2 (&pa)[8], const float (&pp)[8], const double (&pt)[8],
-                      float (&br)[8], float (&bi)[8], float2 (&ev)[8], float2 (&wv)[8]) {
+                      float (&ar)[8], float (&ai)[8], float2 (&uv)[8], float2 (&wv)[8]) {
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const float2 arr = expm2pi_f64(-(double)pp[j] * mc_cyc);
-      const float2 b = cmul(cmul(pa[j], gm), arr);
-      br[j] = b.x;
-      bi[j] = b.y;
-      ev[j] = expm2pi_f64(f_lane * pt[j]);
+      // exp(j psi_i (m - c)) c_i as one phase, in cycles
+      const float2 ph = expm2pi_f64(fma(A.fref, pt[j], -(double)pp[j] * mc_cyc));
+      const float2 b = cmul(cmul(pa[j], gm), ph);
+      ar[j] = b.x;
+      ai[j] = b.y;
+      uv[j] = expm2pi_f64(t_lane_df * pt[j]);
       wv[j] = expm2pi_f64(df32 * pt[j]);
     }
   };
   if (off0 < off1) {
-    float br[8], bi[8];
-    float2 ev[8], wv[8];
+    float ar[8], ai[8];
+    float2 uv[8], wv[8];
     {
       float2 pa[8];
       float pp[8];
       double pt[8];
       fetch(off0, pa, pp, pt);
-      operands(pa, pp, pt, br, bi, ev, wv);
+      operands(pa, pp, pt, ar, ai, uv, wv);
     }
     for (int64_t c0 = off0; c0 < off1; c0 += 16) {
       // next chunk (a clamped, unused load past the last chunk)
@@ -140,36 +153,40 @@ __global__ void __launch_bounds__(kCfrWaves * 64) cfr_kernel(CfrArgs A, float2* 
       float pp[8];
       double pt[8];
       fetch(c0 + 16, pa, pp, pt);
-      const Split3 BR = split3(br), BI = split3(bi), NBI = neg3(BI);
+      const Split3 AR = split3(ar), AI = split3(ai);
 #pragma unroll
-      for (int t = 0; t < kCfrTiles; t += 2) {
-        float er0[8], ei0[8], er1[8], ei1[8];
+      for (int t = 0; t < kCfrPairTiles; ++t) {
+        float ur[8], ui[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-          if (t > 0) ev[j] = cmul(ev[j], wv[j]);
-          er0[j] = ev[j].x;
-          ei0[j] = ev[j].y;
-          ev[j] = cmul(ev[j], wv[j]);
-          er1[j] = ev[j].x;
-          ei1[j] = ev[j].y;
+          if (t > 0) uv[j] = cmul(uv[j], wv[j]);
+          ur[j] = uv[j].x;
+          ui[j] = uv[j].y;
         }
-        const Split3 ER0 = split3(er0), EI0 = split3(ei0);
-        const Split3 ER1 = split3(er1), EI1 = split3(ei1);
-        cfr_tile_pair(BR, BI, NBI, ER0, EI0, ER1, EI1, acc_re[t], acc_im[t], acc_re[t + 1],
-                      acc_im[t + 1]);
+        const Split3 UR = split3(ur), UI = split3(ui);
+        cfr_pair_tile(AR, AI, UR, UI, acc[t][0], acc[t][1], acc[t][2], acc[t][3]);
       }
-      operands(pa, pp, pt, br, bi, ev, wv);
+      operands(pa, pp, pt, ar, ai, uv, wv);
     }
   }
 
   float2* Hl = H + (int64_t)l * A.M * A.N;
 #pragma unroll
-  for (int t = 0; t < kCfrTiles; ++t) {
-    const int n = n_base + t * 32 + col;
+  for (int t = 0; t < kCfrPairTiles; ++t) {
+    const int q = q_base + t * 32 + col;
+    const int n_hi = A.N / 2 + q;
+    const int n_lo = A.N - 1 - n_hi;
+    const bool ok = q < A.Q;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int row = mblk * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
-      if (row < A.M && n < A.N) Hl[(int64_t)row * A.N + n] = make_float2(acc_re[t][r], acc_im[t][r]);
+      if (ok && row < A.M) {
+        const float xr = acc[t][0][r], xi = acc[t][1][r];
+        const float yr = acc[t][2][r], yi = acc[t][3][r];
+        float2* Hr = Hl + (int64_t)row * A.N;
+        Hr[n_hi] = make_float2(xr - yi, xi + yr);
+        if (n_lo != n_hi) Hr[n_lo] = make_float2(xr + yi, xi - yr);
+      }
     }
   }
 }
@@ -182,7 +199,7 @@ __global__ void __launch_bounds__(kCfrWaves * 64) cfr_kernel(CfrArgs A, float2* 
 // reads a contiguous run of its own row (16-byte loads) and advances its
 // exponential by exp(-j 2 pi df tau) from an FP64 anchor per half-chunk.
 struct AdjArgs {
-  int n_links, M, N;
+  int n_links, M, N, Q;
   int64_t max_waves;
   const int64_t* link_off;
   const int64_t* wave_off;  // [n_links + 1] exclusive scan of waves per link
@@ -193,7 +210,7 @@ struct AdjArgs {
   const float2* dH;
   float2* dLda;    // may be null
   double* g_part;  // [max_waves][M][2] per-wave dL/dg partials, or null
-  double f0, df, cm;
+  double fref, t_off, df, cm;  // grid midpoint, t of pair 0, spacing, (M-1)/2
 };
 
 __device__ __forceinline__ int adj_waves_of(const int64_t* off, int l) {
@@ -248,58 +265,67 @@ __device__ __forceinline__ void load8(const float2* row, int n, int N, bool vec,
   }
 }
 
+// Eight dL/dH values of a row at subcarriers n_lo(q) = N - 1 - floor(N/2) - q
+// for pairs q = q1 .. q1+7 (a descending run of the row; zero where q >= Q,
+// for a padding row, and for the middle subcarrier of odd N, which pairs
+// with itself and is counted on the n_hi side).
+__device__ __forceinline__ void load8_lo(const float2* row, int q1, int N, int Q, bool vec,
+                                         bool ok, float2 (&h)[8]) {
+  const int n_top = N - 1 - N / 2 - q1;  // n_lo(q1), the highest address
+  if (ok && vec && q1 + 7 < Q && q1 > 0) {
+    const float4* p = reinterpret_cast<const float4*>(row + (n_top - 7));
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float4 x = p[k];
+      h[7 - 2 * k] = make_float2(x.x, x.y);
+      h[6 - 2 * k] = make_float2(x.z, x.w);
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int q = q1 + j;
+      const bool use = ok && q < Q && !((N & 1) && q == 0);
+      h[j] = use ? row[n_top - j] : make_float2(0.0f, 0.0f);
+    }
+  }
+}
+
 // Contraction of one wave over NT (1 or 2) consecutive 32-path tiles of link
 // l, starting at tile grp * kAdjTP; the caller picks NT = 1 for a link's
 // last wave when it holds a single tile, so no MFMA runs on empty tiles.
-// LDS home of a wave's B operands: [tile][VR h,m,l, VI h,m,l][lane], 16 B
-// per entry, read back once per chunk (they are constant over the wave, but
-// held in registers they would cost the occupancy of two waves per SIMD).
-typedef bf16x8 AdjVbuf[kAdjTP][6][64];
-
+//
+// Conjugate pairs of subcarriers (as in the forward product): with c_p =
+// exp(-j 2 pi f_ref tau_p) and u_p(t) = exp(-j 2 pi t df tau_p),
+// conj(E[p, n_hi]) = conj(c_p) conj(u_p(t_q)) and conj(E[p, n_lo]) =
+// conj(c_p) u_p(t_q), so
+//     G[m, p] = conj(c_p) sum_q (S[m, q] Re u_p(t_q) - j D[m, q] Im u_p(t_q))
+// with S = dH[., n_hi] + dH[., n_lo] and D = dH[., n_hi] - dH[., n_lo]: two
+// complex-by-real products per 16 pairs (32 subcarriers), accumulated over
+// the row in the matrix cores, and the path phase conj(c_p) applied once.
 template <int NT>
 __device__ __forceinline__ void adj_wave(const AdjArgs& A, int64_t w, int64_t l, int grp,
-                                         int lane, AdjVbuf& vbuf) {
+                                         int lane) {
   const int half = lane >> 5;
   const int col = lane & 31;
   const int64_t off0 = A.link_off[l];
   const int64_t off1 = A.link_off[l + 1];
   const int n_mblk = (A.M + 31) / 32;
-  const bool vec = (A.N & 1) == 0 && (reinterpret_cast<uintptr_t>(A.dH) & 15) == 0;
-  const float2* dHl = A.dH + l * (int64_t)A.M * A.N;
+  const int N = A.N, Q = A.Q, nh = A.N / 2;
+  // 16-byte loads need aligned rows and runs starting at even subcarriers
+  const bool vec = (N & 3) == 0 && (reinterpret_cast<uintptr_t>(A.dH) & 15) == 0;
+  const float2* dHl = A.dH + l * (int64_t)A.M * N;
 
-  // Per 16-subcarrier chunk starting at n0, conj(E[p, n0 + k]) =
-  // c_p(n0) v_p(k) with c_p(n0) = exp(+j 2 pi f_n0 tau_p) and
-  // v_p(k) = exp(+j 2 pi k df tau_p).  The B operand V[k, p] = v_p(k) is the
-  // same for every chunk, so it is generated and split once; each chunk's
-  // MFMA product P = dH_chunk V is rotated by the lane's c_p (the result
-  // column is the lane's path) and added to G in FP32.
   // the lane's path in tile u (a, psi are read again in the epilogue)
   auto path_of = [&](int u) { return off0 + (int64_t)(grp * kAdjTP + u) * 32 + col; };
   double tv[NT];
-  float2 w16[NT];
+  float2 v1[NT], v16[NT];
 #pragma unroll
   for (int u = 0; u < NT; ++u) {
     const int64_t p = path_of(u);
     tv[u] = p < off1 ? A.tau[p] : 0.0;
-    float vr[8], vi[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const float2 e = expm2pi_f64((double)(8 * half + j) * A.df * tv[u]);
-      vr[j] = e.x;
-      vi[j] = -e.y;
-    }
-    const Split3 VR = split3(vr), VI = split3(vi);
-    vbuf[u][0][lane] = VR.h;
-    vbuf[u][1][lane] = VR.m;
-    vbuf[u][2][lane] = VR.l;
-    vbuf[u][3][lane] = VI.h;
-    vbuf[u][4][lane] = VI.m;
-    vbuf[u][5][lane] = VI.l;
-    w16[u] = cconj(expm2pi_f64(16.0 * A.df * tv[u]));
+    v1[u] = expm2pi_f64(A.df * tv[u]);
+    v16[u] = expm2pi_f64(16.0 * A.df * tv[u]);
   }
-  // each lane reads back only what it wrote: no barrier, but the compiler
-  // must not keep the values in registers
-  asm volatile("" ::: "memory");
   float2 da[NT];
 #pragma unroll
   for (int u = 0; u < NT; ++u) da[u] = make_float2(0.0f, 0.0f);
@@ -307,52 +333,60 @@ __device__ __forceinline__ void adj_wave(const AdjArgs& A, int64_t w, int64_t l,
   for (int mblk = 0; mblk < n_mblk; ++mblk) {
     const int row = mblk * 32 + col;
     const bool row_ok = row < A.M;
-    const float2* rp = dHl + (int64_t)(row_ok ? row : 0) * A.N;
+    const float2* rp = dHl + (int64_t)(row_ok ? row : 0) * N;
+    // G~ = X - j Y accumulated directly:
+    //   Re G~ += S_re Re u + D_im Im u,  Im G~ += S_im Re u - D_re Im u
     floatx16 gre[NT], gim[NT];
-    float2 c[NT];
 #pragma unroll
     for (int u = 0; u < NT; ++u) {
       gre[u] = floatx16{0};
       gim[u] = floatx16{0};
-      c[u] = make_float2(1.0f, 0.0f);
     }
-    // 16-subcarrier chunks: lane l holds subcarriers n0 + 8(l/32) + j of its
-    // dL/dH row (A operand); the next chunk's values are loaded while the
-    // current chunk's MFMAs run
-    float2 hv[8];
-    load8(rp, 8 * half, A.N, vec, row_ok, hv);
-    for (int n0 = 0; n0 < A.N; n0 += 16) {
-      float hr[8], hi[8];
+    // 16-pair chunks: lane l holds pairs q0 + 8(l/32) + j of its dL/dH row
+    // (A operand); the next chunk's values are loaded while the current
+    // chunk's MFMAs run.  u_p is anchored in FP64 at the start of every
+    // 64-pair group and advanced by exp(-j 2 pi 16 df tau_p) per chunk.
+    float2 hv[8], lv[8];
+    load8(rp, nh + 8 * half, N, vec, row_ok, hv);
+    load8_lo(rp, 8 * half, N, Q, vec, row_ok, lv);
+    for (int g0 = 0; g0 < Q; g0 += 64) {
+      float2 uf[NT];  // u_p(t) at the lane's first pair of the chunk
+      const double t_first = (double)(g0 + 8 * half) + A.t_off;
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        hr[j] = hv[j].x;
-        hi[j] = hv[j].y;
-      }
-      if (n0 + 16 < A.N) load8(rp, n0 + 16 + 8 * half, A.N, vec, row_ok, hv);
-      const Split3 HR = split3(hr), HI = split3(hi), NHI = neg3(HI);
-      const bool anchor = (n0 & 63) == 0;  // FP64 re-anchor every 64 subcarriers
+      for (int u = 0; u < NT; ++u) uf[u] = expm2pi_f64(t_first * A.df * tv[u]);
 #pragma unroll
-      for (int u = 0; u < NT; ++u) {
-        asm volatile("" ::: "memory");  // reload V per chunk (see vbuf)
-        Split3 VR, VI;
-        VR.h = vbuf[u][0][lane];
-        VR.m = vbuf[u][1][lane];
-        VR.l = vbuf[u][2][lane];
-        VI.h = vbuf[u][3][lane];
-        VI.m = vbuf[u][4][lane];
-        VI.l = vbuf[u][5][lane];
-        // P = dH V:  Re: hre vr - him vi,  Im: hre vi + him vr
-        floatx16 pr = mac6(HR, VR, floatx16{0});
-        floatx16 pim = mac6(HR, VI, floatx16{0});
-        pr = mac6(NHI, VI, pr);
-        pim = mac6(HI, VR, pim);
-        c[u] = anchor ? cconj(expm2pi_f64((A.f0 + (double)n0 * A.df) * tv[u]))
-                      : cmul(c[u], w16[u]);
-        const float2 cu = c[u];
+      for (int k = 0; k < 4; ++k) {
+        const int q0 = g0 + 16 * k;
+        if (q0 >= Q) break;
+        float sr[8], si[8], ndr[8], di[8];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          gre[u][r] = fmaf(cu.x, pr[r], fmaf(-cu.y, pim[r], gre[u][r]));
-          gim[u][r] = fmaf(cu.x, pim[r], fmaf(cu.y, pr[r], gim[u][r]));
+        for (int j = 0; j < 8; ++j) {
+          sr[j] = hv[j].x + lv[j].x;
+          si[j] = hv[j].y + lv[j].y;
+          ndr[j] = lv[j].x - hv[j].x;
+          di[j] = hv[j].y - lv[j].y;
+        }
+        if (q0 + 16 < Q) {
+          load8(rp, nh + q0 + 16 + 8 * half, N, vec, row_ok, hv);
+          load8_lo(rp, q0 + 16 + 8 * half, N, Q, vec, row_ok, lv);
+        }
+        const Split3 SR = split3(sr), SI = split3(si), NDR = split3(ndr), DI = split3(di);
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+          if (k > 0) uf[u] = cmul(uf[u], v16[u]);
+          float ur[8], ui[8];
+          float2 e = uf[u];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            if (j > 0) e = cmul(e, v1[u]);
+            ur[j] = e.x;
+            ui[j] = e.y;
+          }
+          const Split3 UR = split3(ur), UI = split3(ui);
+          gre[u] = mac6(SR, UR, gre[u]);
+          gim[u] = mac6(SI, UR, gim[u]);
+          gre[u] = mac6(DI, UI, gre[u]);
+          gim[u] = mac6(NDR, UI, gim[u]);
         }
       }
     }
@@ -363,6 +397,7 @@ __device__ __forceinline__ void adj_wave(const AdjArgs& A, int64_t w, int64_t l,
       const bool ok = p < off1;
       const float2 ai = ok ? A.a[p] : make_float2(0.0f, 0.0f);
       const double psi_cyc = (double)(ok ? A.psi[p] : 0.0f) * kInv2Pi;
+      const float2 cc = cconj(expm2pi_f64(A.fref * tv[u]));  // conj(c_p)
       float gacc_re[16], gacc_im[16];
 #pragma unroll
       for (int grp4 = 0; grp4 < 4; ++grp4) {
@@ -374,7 +409,7 @@ __device__ __forceinline__ void adj_wave(const AdjArgs& A, int64_t w, int64_t l,
           const int r = grp4 * 4 + q;
           const int mrow = mrow0 + q;
           if (q > 0) ph = cmul(ph, step);
-          float2 G = make_float2(gre[u][r], gim[u][r]);
+          const float2 G = cmul(cc, make_float2(gre[u][r], gim[u][r]));  // conj(c_p) G~
           float2 gm = mrow < A.M ? A.g[mrow] : make_float2(0.0f, 0.0f);
           float2 Gph = cmul(G, ph);
           da[u] = cadd(da[u], cmulc(gm, Gph));
@@ -421,7 +456,6 @@ __device__ __forceinline__ void adj_wave(const AdjArgs& A, int64_t w, int64_t l,
 }
 
 __global__ void __launch_bounds__(kAdjWaves * 64, 2) cfr_adjoint_kernel(AdjArgs A) {
-  __shared__ AdjVbuf vbuf[kAdjWaves];
   const int lane = threadIdx.x & 63;
   const int64_t w = (int64_t)blockIdx.x * kAdjWaves + (threadIdx.x >> 6);
   if (w >= A.max_waves) return;
@@ -446,15 +480,14 @@ __global__ void __launch_bounds__(kAdjWaves * 64, 2) cfr_adjoint_kernel(AdjArgs 
   const int64_t l = lo;
   const int grp = (int)(w - A.wave_off[l]);
   const int n_tiles = (int)((A.link_off[l + 1] - A.link_off[l] + 31) / 32);
-  AdjVbuf& vb = vbuf[threadIdx.x >> 6];
   if constexpr (kAdjTP == 2) {
     if (grp * kAdjTP + 1 < n_tiles)
-      adj_wave<2>(A, w, l, grp, lane, vb);
+      adj_wave<2>(A, w, l, grp, lane);
     else
-      adj_wave<1>(A, w, l, grp, lane, vb);
+      adj_wave<1>(A, w, l, grp, lane);
   } else {
     (void)n_tiles;
-    adj_wave<1>(A, w, l, grp, lane, vb);
+    adj_wave<1>(A, w, l, grp, lane);
   }
 }
 
@@ -501,16 +534,18 @@ extern "C" rtc_status rtc_cfr(const rtc_radio* radio, const rtc_paths* paths, co
   A.M = radio->n_elem;
   A.N = radio->n_sc;
   A.n_mblk = (A.M + 31) / 32;
-  A.n_nchunk = (A.N + 32 * kCfrTiles - 1) / (32 * kCfrTiles);
+  A.Q = (A.N + 1) / 2;
+  A.n_qchunk = (A.Q + 32 * kCfrPairTiles - 1) / (32 * kCfrPairTiles);
   A.link_off = paths->link_off;
   A.a = reinterpret_cast<const float2*>(a);
   A.psi = psi;
   A.tau = paths->tau;
   A.g = reinterpret_cast<const float2*>(g);
-  A.f0 = subcarrier0(radio);
+  A.fref = subcarrier0(radio) + 0.5 * (double)(A.N - 1) * radio->df_hz;
+  A.t_off = (A.N % 2 == 0) ? 0.5 : 0.0;
   A.df = radio->df_hz;
   A.cm = 0.5 * (double)(radio->n_elem - 1);
-  int64_t waves = (int64_t)A.n_links * A.n_mblk * A.n_nchunk;
+  int64_t waves = (int64_t)A.n_links * A.n_mblk * A.n_qchunk;
   int64_t blocks = (waves + kCfrWaves - 1) / kCfrWaves;
   RTC_REQUIRE(blocks < (1ll << 31), RTC_ERR_RANGE, "%s: problem too large for one launch", fn);
   hipLaunchKernelGGL(cfr_kernel, dim3((unsigned)blocks), dim3(kCfrWaves * 64), 0,
@@ -562,7 +597,9 @@ extern "C" rtc_status rtc_cfr_adjoint(const rtc_radio* radio, const rtc_paths* p
   A.dLda = reinterpret_cast<float2*>(dLda);
   double* gpart = reinterpret_cast<double*>(wave_off + (paths->n_links + 1));
   A.g_part = dLdg ? gpart : nullptr;
-  A.f0 = subcarrier0(radio);
+  A.Q = (A.N + 1) / 2;
+  A.fref = subcarrier0(radio) + 0.5 * (double)(A.N - 1) * radio->df_hz;
+  A.t_off = (A.N % 2 == 0) ? 0.5 : 0.0;
   A.df = radio->df_hz;
   A.cm = 0.5 * (double)(radio->n_elem - 1);
   hipLaunchKernelGGL(adj_wave_scan_kernel, dim3(1), dim3(1024), 0, s, paths->link_off,

@@ -14,9 +14,10 @@ import numpy as np
 class Radio:
     """OFDM grid and antenna configuration.
 
-    Subcarrier n (storage index 0..n_sc-1) sits at f_n = fc + (n - n_sc/2)*df
+    Subcarrier n (storage index 0..n_sc-1) sits at f_n = fc + (n - n_sc//2)*df
     with df = bandwidth / n_sc (Sec. II-A, discrete CFR: n runs from -N/2 to
-    N/2-1 around the carrier, W = N*df).  The Tx is a uniform linear array of
+    N/2-1 around the carrier, W = N*df; for odd N the carrier is the middle
+    subcarrier).  The Tx is a uniform linear array of
     n_elem isotropic elements with half-wavelength spacing along `ula_axis`,
     centred on the Tx position; the Rx is one isotropic element.  zeta_* are
     polarisation slant angles (Sec. II-B, polarisation model), 0 = vertical.
@@ -35,7 +36,7 @@ class Radio:
 
     def freqs(self) -> np.ndarray:
         n = np.arange(self.n_sc, dtype=np.float64)
-        return self.fc + (n - self.n_sc / 2) * self.df
+        return self.fc + (n - self.n_sc // 2) * self.df
 
 
 def draw_materials(rng: np.random.Generator, n_mat: int, with_scattering: bool):

@@ -150,6 +150,34 @@ def test_cfr_parity(rl, case):
     assert err <= 1e-5, err
 
 
+@pytest.mark.parametrize("n_sc,n_elem", [(1, 3), (2, 1), (3, 5), (37, 33), (255, 8),
+                                         (257, 32), (1023, 2), (1280, 64)])
+def test_cfr_grid_sizes(rl, n_sc, n_elem):
+    """Odd and even subcarrier counts (conjugate pairs about the grid's
+    midpoint; for odd N the middle subcarrier alone; ragged pair tiles) and
+    element counts beyond one 32-row block."""
+    _, st, raw, _, _ = tiny_workload(seed=77, n_rx=12, max_depth=2)
+    rng = np.random.default_rng(n_sc * 100 + n_elem)
+    radio = Radio(fc=3.5e9, bandwidth=50e6, n_sc=n_sc, n_elem=n_elem, ula_axis=(0.0, 0.6, 0.8))
+    g = (rng.uniform(0.8, 1.2, n_elem) * np.exp(1j * rng.uniform(-1, 1, n_elem))).astype(
+        np.complex64)
+    a_ref, psi_ref = o_trace_id(st, torch.tensor(raw, dtype=f64), radio.fc,
+                                ula_axis=radio.ula_axis)
+    a32, p32 = a_ref.to(torch.complex64), psi_ref.to(torch.float32)
+    g32 = torch.tensor(g)
+    H_ref = och.cfr(st.link_off, st.tau, a32.to(c128), p32.to(f64), g32.to(c128), _freqs(radio))
+    say(f"cfr grid N={n_sc} M={n_elem}")
+    dp = rl.DevicePaths(st)
+    H = torch.full((st.n_links, n_elem, n_sc), float("nan"), dtype=torch.complex64,
+                   device="cuda")
+    rl.cfr(_radio_c(rl, radio), dp, a32.cuda(), p32.cuda(), g32.cuda(), H)
+    torch.cuda.synchronize()
+    assert not torch.isnan(torch.view_as_real(H)).any(), "every tap is written"
+    err = _link_rel_err(H.cpu(), H_ref)
+    say(f"  max per-link relative error {err:.2e}")
+    assert err <= 1e-5, err
+
+
 @pytest.mark.parametrize("case", list(CASES))
 def test_forward_end_to_end(rl, case):
     st, raw, radio, g = CASES[case]
