@@ -43,7 +43,8 @@ PEAK_SPLIT_TFLOPS = PEAK_BF16_MATRIX_TFLOPS / SPLIT_PRODUCTS
 PEAK_HBM_GBS = 8000.0
 COPY_PROBE_BYTES = 2 << 30
 # sources whose change invalidates the committed HBM counter figures
-HOT_SOURCES = ["cfr.hip", "split_bf16.h", "dev_common.h", "api_common.h"]
+HOT_SOURCES = ["cfr.hip", "split_bf16.h", "dev_common.h", "api_common.h", "loss.hip",
+               "paper_loss.hip", "fft_wave.h", "fft_block.h"]
 
 
 def log(msg):
@@ -66,12 +67,32 @@ def kernel_work(name, L, M, N, P, D):
     if name in ("cfr", "cfr_adjoint"):
         return 8.0 * M * N * P, 8.0 * taps + 20.0 * P
     if name == "cfr_loss":
-        return 0.0, 24.0 * taps
+        # H, H* and the target PDP in, dL/dH out
+        return 0.0, 28.0 * taps
     if name in ("trace_fields", "trace_fields_adjoint"):
         # per interaction: point, normal (24 B) + material id (2 B); per path
         # depth (1 B) + tau (8 B); out: a (8 B) + psi (4 B) or in: dL/da
         return 0.0, P * (26.0 * D + 9.0 + 12.0)
     return 0.0, 0.0
+
+
+MFMA_FLOPS = 2 * 32 * 32 * 16  # one v_mfma_f32_32x32x16_bf16
+
+
+def mfma_issued(name, link_off, M, N):
+    """BF16 MFMA instructions one launch of the CFR kernels issues: 24 per
+    (16 paths, 32 subcarrier pairs, 32 elements) in the forward product and
+    per (32 paths, 16 pairs, 32 elements) in the adjoint; the forward wave
+    covers 4 pair tiles, padding included."""
+    cnt = np.diff(np.asarray(link_off, np.int64))
+    mblk = -(-M // 32)
+    Q = (N + 1) // 2
+    if name == "cfr":
+        qchunks = -(-Q // 128)
+        return int((-(-cnt // 16)).sum()) * mblk * qchunks * 4 * 24
+    if name == "cfr_adjoint":
+        return int((-(-cnt // 32)).sum()) * mblk * (-(-Q // 16)) * 24
+    return 0
 
 
 def diffuse_bench(steps=3, warmup=1):
@@ -269,7 +290,9 @@ def summarize_traffic(fetch_csv, write_csv):
     out = {"source_sha": hot_source_sha(), "copy_probe_bytes": COPY_PROBE_BYTES,
            "fetch_scale": sf, "write_scale": sw, "kernels": {}}
     names = {"rtc::cfr_kernel": "cfr", "rtc::cfr_adjoint_kernel": "cfr_adjoint",
-             "rtc::cfr_loss_wave_kernel<10, true>": "cfr_loss"}
+             "rtc::cfr_loss_wave_kernel<10, true>": "cfr_loss",
+             "rtc::paper_loss_wave_kernel<10, true>": "paper_loss",
+             "rtc::gain_products_kernel": "gain_products"}
     lines = ["| kernel | dispatches | FETCH_SIZE (GB) | WRITE_SIZE (GB) | HBM read (GB) "
              "| HBM write (GB) |", "|---|---:|---:|---:|---:|---:|"]
     for k, short in names.items():
@@ -371,6 +394,11 @@ def main():
                 "peak_basis": f"dense BF16 {PEAK_BF16_MATRIX_TFLOPS:.0f} TFLOP/s / "
                               f"{SPLIT_PRODUCTS} split products (FP32-accurate)",
                 "fp32_matrix_peak_frac": round(achieved / PEAK_FP32_MATRIX_TFLOPS, 4)}
+    # what the matrix cores execute: the conjugate-pair form issues half the
+    # BF16 products of the direct one, so this is below frac
+    issued = mfma_issued(hot, st.link_off, M, N) * MFMA_FLOPS / (per_kernel[hot] * 1e-3) / 1e12
+    roofline["mfma_bf16_issued_tflops"] = round(issued, 1)
+    roofline["mfma_bf16_frac"] = round(issued / PEAK_BF16_MATRIX_TFLOPS, 4)
     kernels = {}
     for k, ms in per_kernel.items():
         fl_k, by_k = kernel_work(k, L, M, N, P, D)
