@@ -109,7 +109,9 @@ __global__ void __launch_bounds__(kCfrWaves * 64) cfr_kernel(CfrArgs A, float2* 
   // generates its operands (the FP64-reduced exponentials), so the matrix
   // cores are not idle during that VALU work.  Loads clamp to the link's
   // last path (always a valid address) and padding paths get a = 0.
-  auto fetch = [&](int64_t c0, float2 (&pa)[8], float (&pp)[8], double (&pt)[8]) {
+  // tm: tau of path 8 half + (col & 7), whose tile step this lane computes
+  // for the others (the step depends on the path alone)
+  auto fetch = [&](int64_t c0, float2 (&pa)[8], float (&pp)[8], double (&pt)[8], double& tm) {
     const int64_t p0 = c0 + 8 * half;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
@@ -120,12 +122,16 @@ __global__ void __launch_bounds__(kCfrWaves * 64) cfr_kernel(CfrArgs A, float2* 
       pp[j] = A.psi[pc];
       pt[j] = A.tau[pc];
     }
+    const int64_t pm = p0 + (col & 7);
+    tm = A.tau[pm < off1 ? pm : off1 - 1];
   };
   // A operand A'[m, i] = a_i g_m exp(j psi_i (m - c)) c_i; B operand anchor
   // u_i at the lane's pair column of tile 0 and the tile step
-  // w_i = exp(-j 2 pi 32 df tau_i)
+  // w_i = exp(-j 2 pi 32 df tau_i), read from the lane that computed it
   auto operands = [&](const float2 (&pa)[8], const float (&pp)[8], const double (&pt)[8],
-                      float (&ar)[8], float (&ai)[8], float2 (&uv)[8], float2 (&wv)[8]) {
+                      double tm, float (&ar)[8], float (&ai)[8], float2 (&uv)[8],
+                      float2 (&wv)[8]) {
+    const float2 wm = expm2pi_f64(df32 * tm);
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       // exp(j psi_i (m - c)) c_i as one phase, in cycles
@@ -134,7 +140,8 @@ __global__ void __launch_bounds__(kCfrWaves * 64) cfr_kernel(CfrArgs A, float2* 
       ar[j] = b.x;
       ai[j] = b.y;
       uv[j] = expm2pi_f64(t_lane_df * pt[j]);
-      wv[j] = expm2pi_f64(df32 * pt[j]);
+      const int src = (lane & 32) + j;
+      wv[j] = make_float2(__shfl(wm.x, src, 64), __shfl(wm.y, src, 64));
     }
   };
   if (off0 < off1) {
@@ -143,16 +150,16 @@ __global__ void __launch_bounds__(kCfrWaves * 64) cfr_kernel(CfrArgs A, float2* 
     {
       float2 pa[8];
       float pp[8];
-      double pt[8];
-      fetch(off0, pa, pp, pt);
-      operands(pa, pp, pt, ar, ai, uv, wv);
+      double pt[8], tm;
+      fetch(off0, pa, pp, pt, tm);
+      operands(pa, pp, pt, tm, ar, ai, uv, wv);
     }
     for (int64_t c0 = off0; c0 < off1; c0 += 16) {
       // next chunk (a clamped, unused load past the last chunk)
       float2 pa[8];
       float pp[8];
-      double pt[8];
-      fetch(c0 + 16, pa, pp, pt);
+      double pt[8], tm;
+      fetch(c0 + 16, pa, pp, pt, tm);
       const Split3 AR = split3(ar), AI = split3(ai);
 #pragma unroll
       for (int t = 0; t < kCfrPairTiles; ++t) {
@@ -166,7 +173,7 @@ __global__ void __launch_bounds__(kCfrWaves * 64) cfr_kernel(CfrArgs A, float2* 
         const Split3 UR = split3(ur), UI = split3(ui);
         cfr_pair_tile(AR, AI, UR, UI, acc[t][0], acc[t][1], acc[t][2], acc[t][3]);
       }
-      operands(pa, pp, pt, ar, ai, uv, wv);
+      operands(pa, pp, pt, tm, ar, ai, uv, wv);
     }
   }
 
@@ -370,7 +377,8 @@ __device__ __forceinline__ void adj_wave(const AdjArgs& A, int64_t w, int64_t l,
           load8(rp, nh + q0 + 16 + 8 * half, N, vec, row_ok, hv);
           load8_lo(rp, q0 + 16 + 8 * half, N, Q, vec, row_ok, lv);
         }
-        const Split3 SR = split3(sr), SI = split3(si), NDR = split3(ndr), DI = split3(di);
+        const Split3 SR = split3(sr), SI = split3(si);
+        const Split3 NDR = split3(ndr), DI = split3(di);
 #pragma unroll
         for (int u = 0; u < NT; ++u) {
           if (k > 0) uf[u] = cmul(uf[u], v16[u]);
