@@ -131,15 +131,15 @@ __global__ void __launch_bounds__(kCfrWaves * 64) cfr_kernel(CfrArgs A, float2* 
   auto operands = [&](const float2 (&pa)[8], const float (&pp)[8], const double (&pt)[8],
                       double tm, float (&ar)[8], float (&ai)[8], float2 (&uv)[8],
                       float2 (&wv)[8]) {
-    const float2 wm = expm2pi_f64(df32 * tm);
+    const float2 wm = expm2pi_f64_hw(df32 * tm);
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       // exp(j psi_i (m - c)) c_i as one phase, in cycles
-      const float2 ph = expm2pi_f64(fma(A.fref, pt[j], -(double)pp[j] * mc_cyc));
+      const float2 ph = expm2pi_f64_hw(fma(A.fref, pt[j], -(double)pp[j] * mc_cyc));
       const float2 b = cmul(cmul(pa[j], gm), ph);
       ar[j] = b.x;
       ai[j] = b.y;
-      uv[j] = expm2pi_f64(t_lane_df * pt[j]);
+      uv[j] = expm2pi_f64_hw(t_lane_df * pt[j]);
       const int src = (lane & 32) + j;
       wv[j] = make_float2(__shfl(wm.x, src, 64), __shfl(wm.y, src, 64));
     }
@@ -330,8 +330,8 @@ __device__ __forceinline__ void adj_wave(const AdjArgs& A, int64_t w, int64_t l,
   for (int u = 0; u < NT; ++u) {
     const int64_t p = path_of(u);
     tv[u] = p < off1 ? A.tau[p] : 0.0;
-    v1[u] = expm2pi_f64(A.df * tv[u]);
-    v16[u] = expm2pi_f64(16.0 * A.df * tv[u]);
+    v1[u] = expm2pi_f64_hw(A.df * tv[u]);
+    v16[u] = expm2pi_f64_hw(16.0 * A.df * tv[u]);
   }
   float2 da[NT];
 #pragma unroll
@@ -360,7 +360,7 @@ __device__ __forceinline__ void adj_wave(const AdjArgs& A, int64_t w, int64_t l,
       float2 uf[NT];  // u_p(t) at the lane's first pair of the chunk
       const double t_first = (double)(g0 + 8 * half) + A.t_off;
 #pragma unroll
-      for (int u = 0; u < NT; ++u) uf[u] = expm2pi_f64(t_first * A.df * tv[u]);
+      for (int u = 0; u < NT; ++u) uf[u] = expm2pi_f64_hw(t_first * A.df * tv[u]);
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const int q0 = g0 + 16 * k;
@@ -405,13 +405,13 @@ __device__ __forceinline__ void adj_wave(const AdjArgs& A, int64_t w, int64_t l,
       const bool ok = p < off1;
       const float2 ai = ok ? A.a[p] : make_float2(0.0f, 0.0f);
       const double psi_cyc = (double)(ok ? A.psi[p] : 0.0f) * kInv2Pi;
-      const float2 cc = cconj(expm2pi_f64(A.fref * tv[u]));  // conj(c_p)
+      const float2 cc = cconj(expm2pi_f64_hw(A.fref * tv[u]));  // conj(c_p)
       float gacc_re[16], gacc_im[16];
 #pragma unroll
       for (int grp4 = 0; grp4 < 4; ++grp4) {
         const int mrow0 = mblk * 32 + 8 * grp4 + 4 * half;
-        float2 ph = expm2pi_f64(psi_cyc * ((double)mrow0 - A.cm));  // exp(-j psi (m - c))
-        const float2 step = expm2pi_f64(psi_cyc);
+        float2 ph = expm2pi_f64_hw(psi_cyc * ((double)mrow0 - A.cm));  // exp(-j psi (m - c))
+        const float2 step = expm2pi_f64_hw(psi_cyc);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int r = grp4 * 4 + q;

@@ -116,6 +116,17 @@ RTC_DEV float2 expm2pi_f64(double x) {
   return make_float2(c, -s);
 }
 
+// exp(-j 2 pi x) for an FP64 phase in cycles on the transcendental unit:
+// v_fract_f64 reduces to [0, 1) exactly (a result that would round to 1 is
+// returned as the largest double below it, the same phase), the remainder
+// is rounded to FP32 and v_sin_f32 / v_cos_f32 take it in revolutions
+// (measured on the device: max abs error 1.3e-7 over 2^20 points of
+// [0, 1), against ~6e-8 for sincos2pi, at two instructions instead of ~20).
+RTC_DEV float2 expm2pi_f64_hw(double x) {
+  const float f = (float)__builtin_amdgcn_fract(x);
+  return make_float2(__builtin_amdgcn_cosf(f), -__builtin_amdgcn_sinf(f));
+}
+
 // exp(+j 2 pi x) for an FP32 phase in cycles.
 RTC_DEV float2 expp2pi(float x) {
   float fr = x - floorf(x);
