@@ -354,8 +354,29 @@ __device__ __forceinline__ void adj_wave(const AdjArgs& A, int64_t w, int64_t l,
     // chunk's MFMAs run.  u_p is anchored in FP64 at the start of every
     // 64-pair group and advanced by exp(-j 2 pi 16 df tau_p) per chunk.
     float2 hv[8], lv[8];
-    load8(rp, nh + 8 * half, N, vec, row_ok, hv);
-    load8_lo(rp, 8 * half, N, Q, vec, row_ok, lv);
+    // a chunk's runs: with aligned rows and a whole chunk (a condition the
+    // same for every lane) eight 16-byte loads, lanes of rows past M reading
+    // row 0 (their products are discarded); otherwise element loads with
+    // the checks of load8 / load8_lo
+    auto load_chunk = [&](int qs) {
+      if (vec && qs + 16 <= Q) {
+        const int q1 = qs + 8 * half;
+        const float4* hi4 = reinterpret_cast<const float4*>(rp + nh + q1);
+        const float4* lo4 = reinterpret_cast<const float4*>(rp + (N - 8 - nh - q1));
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float4 x = hi4[r], y = lo4[r];
+          hv[2 * r] = make_float2(x.x, x.y);
+          hv[2 * r + 1] = make_float2(x.z, x.w);
+          lv[7 - 2 * r] = make_float2(y.x, y.y);
+          lv[6 - 2 * r] = make_float2(y.z, y.w);
+        }
+      } else {
+        load8(rp, nh + qs + 8 * half, N, false, row_ok, hv);
+        load8_lo(rp, qs + 8 * half, N, Q, false, row_ok, lv);
+      }
+    };
+    load_chunk(0);
     for (int g0 = 0; g0 < Q; g0 += 64) {
       float2 uf[NT];  // u_p(t) at the lane's first pair of the chunk
       const double t_first = (double)(g0 + 8 * half) + A.t_off;
@@ -373,10 +394,7 @@ __device__ __forceinline__ void adj_wave(const AdjArgs& A, int64_t w, int64_t l,
           ndr[j] = lv[j].x - hv[j].x;
           di[j] = hv[j].y - lv[j].y;
         }
-        if (q0 + 16 < Q) {
-          load8(rp, nh + q0 + 16 + 8 * half, N, vec, row_ok, hv);
-          load8_lo(rp, q0 + 16 + 8 * half, N, Q, vec, row_ok, lv);
-        }
+        if (q0 + 16 < Q) load_chunk(q0 + 16);
         const Split3 SR = split3(sr), SI = split3(si);
         const Split3 NDR = split3(ndr), DI = split3(di);
 #pragma unroll
