@@ -189,7 +189,8 @@ __global__ void __launch_bounds__(64)
       for (int i = 0; i < JZ; ++i) {
         const int j = lane + 64 * i;
 #pragma unroll
-        for (int r = 0; r < RZ; ++r) pt[i][r] = j < BZ ? ps[j + r * BZ] : 0.0f;
+        for (int r = 0; r < RZ; ++r)
+          pt[i][r] = (BZ % 64 == 0 || j < BZ) ? ps[j + r * BZ] : 0.0f;
       }
     } else {
       float2 vt[JA][RA], xt[JZ][RZ];
@@ -198,7 +199,7 @@ __global__ void __launch_bounds__(64)
         const int j = lane + 64 * i;
 #pragma unroll
         for (int r = 0; r < RA; ++r)
-          vt[i][r] = j < BA ? ts[j + r * BA] : make_float2(0.0f, 0.0f);
+          vt[i][r] = (BA % 64 == 0 || j < BA) ? ts[j + r * BA] : make_float2(0.0f, 0.0f);
       }
       fft_full<LOGN, +1, +1>(vt, xt, b0, b1, lane);
 #pragma unroll
@@ -213,8 +214,8 @@ __global__ void __launch_bounds__(64)
       const int j = lane + 64 * i;
 #pragma unroll
       for (int r = 0; r < RA; ++r) {
-        const float2 h = j < BA ? hs[j + r * BA] : make_float2(0.0f, 0.0f);
-        const float2 t = j < BA ? ts[j + r * BA] : make_float2(0.0f, 0.0f);
+        const float2 h = (BA % 64 == 0 || j < BA) ? hs[j + r * BA] : make_float2(0.0f, 0.0f);
+        const float2 t = (BA % 64 == 0 || j < BA) ? ts[j + r * BA] : make_float2(0.0f, 0.0f);
         vh[i][r] = h;
         diff[i][r] = csub(h, t);
         ec += cabs2(diff[i][r]);
@@ -227,7 +228,7 @@ __global__ void __launch_bounds__(64)
 #pragma unroll
     for (int i = 0; i < JZ; ++i) {
       const int j = lane + 64 * i;
-      if (j < BZ) {
+      if (BZ % 64 == 0 || j < BZ) {
 #pragma unroll
         for (int r = 0; r < RZ; ++r) {
           const float p = cabs2(xh[i][r]) * invN;
@@ -255,7 +256,7 @@ __global__ void __launch_bounds__(64)
 #pragma unroll
       for (int i = 0; i < JA; ++i) {
         const int j = lane + 64 * i;
-        if (j < BA) {
+        if (BA % 64 == 0 || j < BA) {
 #pragma unroll
           for (int r = 0; r < RA; ++r) out[j + r * BA] = cadd(cscale(diff[i][r], gc), G[i][r]);
         }
@@ -285,7 +286,7 @@ __global__ void __launch_bounds__(64)
 #pragma unroll
     for (int i = 0; i < JA; ++i) {
       const int j = lane + 64 * i;
-      if (j < BA) {
+      if (BA % 64 == 0 || j < BA) {
 #pragma unroll
         for (int r = 0; r < RA; ++r) {
           vt[i][r] = ts[j + r * BA];
@@ -299,7 +300,7 @@ __global__ void __launch_bounds__(64)
 #pragma unroll
     for (int i = 0; i < JZ; ++i) {
       const int j = lane + 64 * i;
-      if (j < BZ) {
+      if (BZ % 64 == 0 || j < BZ) {
 #pragma unroll
         for (int r = 0; r < RZ; ++r) {
           const float pt = cabs2(xt[i][r]) * invN;

@@ -104,7 +104,8 @@ __global__ void __launch_bounds__(64)
     for (int i = 0; i < JA; ++i) {
       const int j = lane + 64 * i;
 #pragma unroll
-      for (int r = 0; r < RA; ++r) vh[i][r] = j < BA ? hs[j + r * BA] : make_float2(0.0f, 0.0f);
+      for (int r = 0; r < RA; ++r)
+        vh[i][r] = (BA % 64 == 0 || j < BA) ? hs[j + r * BA] : make_float2(0.0f, 0.0f);
     }
     float2 xh[JZ][RZ];
     fft_full<LOGN, +1, +1>(vh, xh, b0, b1, lane);
@@ -112,7 +113,7 @@ __global__ void __launch_bounds__(64)
 #pragma unroll
     for (int i = 0; i < JZ; ++i) {
       const int j = lane + 64 * i;
-      if (j < BZ) {
+      if (BZ % 64 == 0 || j < BZ) {
 #pragma unroll
         for (int r = 0; r < RZ; ++r) {
           const float p = cabs2(xh[i][r]) * invN;
@@ -129,7 +130,7 @@ __global__ void __launch_bounds__(64)
 #pragma unroll
     for (int i = 0; i < JZ; ++i) {
       const int j = lane + 64 * i;
-      if (j < BZ) {
+      if (BZ % 64 == 0 || j < BZ) {
 #pragma unroll
         for (int r = 0; r < RZ; ++r) {
           const float d = centred_tap(j + r * BZ, N) - tb;
@@ -163,7 +164,7 @@ __global__ void __launch_bounds__(64)
 #pragma unroll
         for (int i = 0; i < JA; ++i) {
           const int j = lane + 64 * i;
-          if (j < BA) {
+          if (BA % 64 == 0 || j < BA) {
 #pragma unroll
             for (int r = 0; r < RA; ++r) out[j + r * BA] = G[i][r];
           }
