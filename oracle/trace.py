@@ -105,19 +105,21 @@ def _sqrt0(x):
                        torch.zeros_like(x))
 
 
-def diffuse_step(E, p_out, q_out, k_in, n, eta, S, dA, k_s):
-    """One diffuse reflection (Eq. scattered_field, Lambertian pattern,
-    K_x = 0, chi = 0), without the spreading factors (the caller divides by
-    rho_Q d_{Q+1}).
+def diffuse_step(E, p_out, q_out, k_in, n, eta, S, dA, k_s, pattern=None, kx=None):
+    """One diffuse reflection (Eq. scattered_field, chi = 0), without the
+    spreading factors (the caller divides by rho_Q d_{Q+1}).
 
     E: complex [...,2] field in the outgoing basis (p_out, q_out) of the
     previous process; k_in: incident direction; n: stored unit normal;
     eta: complex permittivity; S: scattering coefficient; dA: area element;
-    k_s: scattered direction.  Returns (E_out, e_perp_s, e_par_s)."""
+    k_s: scattered direction; pattern: f_s(k_in, k_s, n) with n on the
+    incidence side, or None for the Lambertian cos(theta_s)/pi; kx: K_x, or
+    None for 0.  Returns (E_out, e_perp_s, e_par_s)."""
     flip = _dot(k_in, n) > 0
     n = torch.where(flip[..., None], -n, n)
     cos_i = -_dot(k_in, n)
     cos_s = _dot(k_s, n)
+    f_s = lambertian_pattern(cos_s) if pattern is None else pattern(k_in, k_s, n)
     cr = torch.cross(k_in, n, dim=-1)
     crn = torch.linalg.norm(cr, dim=-1, keepdim=True)
     alt = p_out - _dot(p_out, k_in)[..., None] * k_in
@@ -130,7 +132,7 @@ def diffuse_step(E, p_out, q_out, k_in, n, eta, S, dA, k_s):
     r_perp, r_par = fresnel(eta, cos_i)
     # Gamma |E_in| = |diag(r_perp, r_par) y|
     g_norm = _sqrt0(torch.abs(r_perp * y0) ** 2 + torch.abs(r_par * y1) ** 2)
-    amp = S * g_norm * _sqrt0(torch.clamp(cos_i, min=0.0) * dA * lambertian_pattern(cos_s))
+    amp = S * g_norm * _sqrt0(torch.clamp(cos_i, min=0.0) * dA * f_s)
     # outgoing basis from (k_s, n)
     cs = torch.cross(k_s, n, dim=-1)
     csn = torch.linalg.norm(cs, dim=-1, keepdim=True)
@@ -139,7 +141,11 @@ def diffuse_step(E, p_out, q_out, k_in, n, eta, S, dA, k_s):
     small_s = csn < 1e-7
     e_perp_s = torch.where(small_s, alt_s, cs / torch.where(small_s, torch.ones_like(csn), csn))
     e_par_s = torch.cross(e_perp_s, k_s, dim=-1)
-    E_out = torch.stack([amp.to(c128), torch.zeros_like(amp).to(c128)], dim=-1)
+    if kx is None:
+        E_out = torch.stack([amp.to(c128), torch.zeros_like(amp).to(c128)], dim=-1)
+    else:
+        E_out = torch.stack([(amp * _sqrt0(1.0 - kx)).to(c128), (amp * _sqrt0(kx)).to(c128)],
+                            dim=-1)
     return E_out, e_perp_s, e_par_s
 
 
@@ -171,12 +177,16 @@ def departure_direction(store, sel=None):
 
 
 def trace_fields(store, eps_r, sigma, s, fc, zeta_tx=0.0, zeta_rx=0.0,
-                 ula_axis=(1.0, 0.0, 0.0), sel=None):
+                 ula_axis=(1.0, 0.0, 0.0), sel=None, tx_gain=None, kx=None, pattern=None):
     """Path coefficients a_i and array phase steps psi_i.
 
     eps_r, sigma, s: per-interaction material values, float64 tensors of
     shape [max_depth, P] (P = len(sel)), may require grad.  Slots beyond a
-    path's depth are ignored.  Returns (a complex128 [P], psi float64 [P])."""
+    path's depth are ignored.  Optional: tx_gain, a callable r -> G(r) on
+    unit departure directions (Sec. III-A; isotropic if None); kx [D, P]
+    K_x per interaction; pattern(k, k_in, k_s, n) -> f_s for interaction
+    slot k (Lambertian if None).  Returns (a complex128 [P], psi float64
+    [P])."""
     sel = np.arange(store.n_paths) if sel is None else np.asarray(sel)
     tx, rx, depth, pts, nrm, _, tau, kind, dA = _gather_paths(store, sel)
     P = len(sel)
@@ -186,6 +196,9 @@ def trace_fields(store, eps_r, sigma, s, fc, zeta_tx=0.0, zeta_rx=0.0,
     k1 = _unit(first - tx)
     p_out, q_out = spherical_basis(k1)
     E = pattern_isotropic(zeta_tx).expand(P, 2).clone()
+    if tx_gain is not None:
+        # C = sqrt(G) [cos zeta, sin zeta] (Eq. polarization_model)
+        E = E * _sqrt0(tx_gain(k1)).to(c128)[:, None]
     prev = tx
     rho = torch.zeros(P, dtype=f64)  # unfolded length from the Tx
     diffuse_end = torch.zeros(P, dtype=torch.bool)
@@ -208,8 +221,10 @@ def trace_fields(store, eps_r, sigma, s, fc, zeta_tx=0.0, zeta_rx=0.0,
             rx_k = torch.where(dif[:, None], rx, s_k + 2.0 * n_k + up)
             k_s = _unit(rx_k - s_k)
             s_dif = torch.where(dif, s[k], torch.zeros_like(s[k]))
+            pat_k = None if pattern is None else (lambda a, b, c, k=k: pattern(k, a, b, c))
             E_d, ep_d, eq_d = diffuse_step(E, p_out, q_out, k_in, n_k, eta, s_dif,
-                                           torch.where(dif, dA[k], torch.ones_like(dA[k])), k_s)
+                                           torch.where(dif, dA[k], torch.ones_like(dA[k])), k_s,
+                                           pattern=pat_k, kx=None if kx is None else kx[k])
             E_new = torch.where(dif[:, None], E_d, E_new)
             e_perp = torch.where(dif[:, None], ep_d, e_perp)
             e_par_out = torch.where(dif[:, None], eq_d, e_par_out)
@@ -248,11 +263,33 @@ def per_interaction_from_ids(store, table, sel=None):
     return torch.stack(rows)
 
 
-def trace_fields_per_id(store, raw, fc, sel=None, **kw):
+def trace_fields_per_id(store, raw, fc, sel=None, tx_raw=None, n_vmf=0, pat_raw=None,
+                        backscatter=None, **kw):
     """Per-material-id mode: raw [n_mat, 3] -> (eps_r, sigma, S) by the
-    Sec. III-C transforms, gathered per interaction, then trace_fields."""
+    Sec. III-C transforms, gathered per interaction, then trace_fields.
+
+    Optional: tx_raw [1 + 5 n_vmf], the raw trainable Tx gain (Sec. III-A);
+    pat_raw [n_mat, 6], per material the raw K_x and trainable scattering
+    pattern (Sec. III-B); or backscatter = (kx [n_mat], alpha_r, alpha_s,
+    Lam [n_mat]), the backscattering-lobe pattern (Eq.
+    backscattering_model) with its K_x, for ground truth."""
+    from . import patterns as pt
     eps_r, sigma, s = materials_from_raw(raw)
-    return trace_fields(store,
-                        per_interaction_from_ids(store, eps_r, sel),
-                        per_interaction_from_ids(store, sigma, sel),
-                        per_interaction_from_ids(store, s, sel), fc, sel=sel, **kw)
+    gather = lambda t: per_interaction_from_ids(store, t, sel)  # noqa: E731
+    if tx_raw is not None:
+        eta, w, lam, mu = pt.vmf_from_raw(tx_raw, n_vmf)
+        kw["tx_gain"] = lambda r: pt.vmf_gain(r, eta, w, lam, mu)
+    if pat_raw is not None:
+        kx, w3, lam2, lam3 = pt.pattern_from_raw(torch.as_tensor(pat_raw, dtype=f64))
+        kx_i, w_i = gather(kx), torch.stack([gather(w3[:, c]) for c in range(3)], -1)
+        l2_i, l3_i = gather(lam2), gather(lam3)
+        kw["kx"] = kx_i
+        kw["pattern"] = lambda k, k_in, k_s, n: pt.trainable_pattern(k_in, k_s, n, w_i[k],
+                                                                     l2_i[k], l3_i[k])
+    elif backscatter is not None:
+        kx, a_r, a_s, Lam = backscatter
+        kw["kx"] = gather(torch.as_tensor(kx, dtype=f64))
+        Lam_i = gather(torch.as_tensor(Lam, dtype=f64))
+        kw["pattern"] = lambda k, k_in, k_s, n: pt.backscatter_pattern(k_in, k_s, n, a_r, a_s,
+                                                                       Lam_i[k])
+    return trace_fields(store, gather(eps_r), gather(sigma), gather(s), fc, sel=sel, **kw)
