@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define RTC_ABI_VERSION 3
+#define RTC_ABI_VERSION 4
 
 typedef enum {
   RTC_OK = 0,
@@ -123,6 +123,32 @@ typedef struct {
   const float* per_inter;
 } rtc_materials;
 
+/* Trainable antenna and scattering patterns and cross-polarisation
+ * (optional; see rtc_trace_fields_pat).  Members may be NULL / 0:
+ *  n_vmf, tx_raw: the Tx gain of Sec. III-A, a mixture of n_vmf <= 8
+ *           spherical Gaussians, G(k) = 4 pi eta sum_i (w_i/a_i) e^{lam_i mu_i.k}
+ *           with a_i = (2 pi/lam_i)(e^{lam_i} - e^{-lam_i}) (the factor 4 pi
+ *           makes the gain integrate to 4 pi eta, Eq. atenna_normalization);
+ *           tx_raw = float [1 + 5 n_vmf]: eta = logistic(r0), w = softmax of
+ *           n_vmf logits, lam = exp of n_vmf values, then n_vmf mean
+ *           directions as 3-vectors of any length (normalised).  The Tx
+ *           pattern is sqrt(G) (cos zeta_tx, sin zeta_tx) (Eq.
+ *           polarization_model) for every array element.  n_vmf = 0: isotropic.
+ *  mat_raw: float [n_mat * 6], per material id: K_x = logistic(q0), the
+ *           weights (w1, w2, w3) = softmax(q1, q2, q3), lam_2 = exp(q4),
+ *           lam_3 = exp(q5) of the trainable scattering pattern (Sec. III-B,
+ *           Eq. trainable_scattering_pattern): a Lambertian lobe and lobes
+ *           about the backscatter direction -k_in and the specular
+ *           direction, each normalised by Meder's hemispherical integral for
+ *           an axis at the incidence angle.  At a diffuse reflection the
+ *           field is |E_s| (sqrt(1 - K_x), sqrt(K_x)) with this f_s.  NULL:
+ *           Lambertian and K_x = 0. */
+typedef struct {
+  int32_t n_vmf;
+  const float* tx_raw;
+  const float* mat_raw;
+} rtc_patterns;
+
 /* Library version and the last error message of the calling thread. */
 int rtc_abi_version(void);
 const char* rtc_last_error(void);
@@ -133,7 +159,8 @@ typedef enum {
   RTC_OP_CFR_ADJOINT = 2,
   RTC_OP_TRACE_FIELDS_ADJOINT = 3,
   RTC_OP_CFR_TARGET_STATS = 4,
-  RTC_OP_PAPER_LOSS = 5
+  RTC_OP_PAPER_LOSS = 5,
+  RTC_OP_TRACE_FIELDS_ADJOINT_PAT = 6
 } rtc_op;
 
 /* Bytes of device workspace `op` needs for n_links links (CFR rows are
@@ -152,6 +179,12 @@ size_t rtc_workspace_size(int op, const rtc_radio* radio, int32_t n_links, int32
  * Either output pointer may be NULL. */
 rtc_status rtc_trace_fields(const rtc_radio* radio, const rtc_paths* paths,
                             const rtc_materials* mats, void* a, float* psi, void* stream);
+
+/* rtc_trace_fields with trainable patterns (rtc_patterns; NULL gives
+ * rtc_trace_fields). */
+rtc_status rtc_trace_fields_pat(const rtc_radio* radio, const rtc_paths* paths,
+                                const rtc_materials* mats, const rtc_patterns* pats, void* a,
+                                float* psi, void* stream);
 
 /* Channel frequency response (Eq. cfr_cont, discrete form of Sec. II-A):
  *   H[l, m, n] = sum_{i in link l} a_i g_m exp(j psi_i (m - (M-1)/2))
@@ -261,6 +294,22 @@ rtc_status rtc_trace_fields_adjoint(const rtc_radio* radio, const rtc_paths* pat
                                     const rtc_materials* mats, const void* dLda,
                                     float* dLd_raw, float* dLd_inter, void* ws, size_t ws_bytes,
                                     void* stream);
+
+/* Adjoint of rtc_trace_fields_pat: as rtc_trace_fields_adjoint, plus
+ *   dLd_tx  float [1 + 5 n_vmf] gradient w.r.t. tx_raw, or NULL
+ *           (needs n_vmf > 0; either material mode)
+ *   dLd_pat float [n_mat * 6] gradient w.r.t. mat_raw, or NULL (needs
+ *           mat_raw and per-id materials; RTC_ERR_UNSUPPORTED with
+ *           per-interaction materials)
+ * The workspace, rtc_workspace_size(RTC_OP_TRACE_FIELDS_ADJOINT_PAT, ...),
+ * is required whenever a per-id, Tx or pattern gradient is asked for.  All
+ * reductions are in FP64 in a fixed order.  Where the diffuse field is zero
+ * (f_s = 0) the pattern gradient is 0. */
+rtc_status rtc_trace_fields_adjoint_pat(const rtc_radio* radio, const rtc_paths* paths,
+                                        const rtc_materials* mats, const rtc_patterns* pats,
+                                        const void* dLda, float* dLd_raw, float* dLd_inter,
+                                        float* dLd_tx, float* dLd_pat, void* ws, size_t ws_bytes,
+                                        void* stream);
 
 /* Neural materials (Sec. III-D): per point p, p_bar = (p - aabb_center) *
  * inv_extent (inv_extent = 1 / longest edge of the scene's axis-aligned

@@ -18,6 +18,19 @@
 // (|E_s|, 0) in the basis (k_s x n, e_perp x k_s) and spreads as
 // 1/(rho d) with rho the unfolded length to the diffuse point and d the
 // distance to the Rx.  Elsewhere the kind is ignored (specular).
+//
+// Optional trainable patterns (rtc_patterns):
+//  * Tx gain (Sec. III-A) G(k) = 4 pi eta sum_i (w_i/a_i) e^{lam_i mu_i.k}
+//    = eta sum_i w_i c_i e^{lam_i (mu_i.k - 1)}, c_i = 2 lam_i/(1 - e^{-2 lam_i}),
+//    the Tx field sqrt(G) (cos zeta, sin zeta) (Eq. polarization_model);
+//  * per material K_x and the trainable scattering pattern of Eq.
+//    trainable_scattering_pattern at a diffuse reflection:
+//      f_s = w1 cos(theta_s)/pi + w2 e^{lam2 (k_s.k_b - 1)}/a(lam2)
+//            + w3 e^{lam3 (k_s.k_r - 1)}/a(lam3),
+//    k_b = -k_in, k_r the specular direction, a(lam) the hemispherical
+//    integral of the shifted lobe by Meder's interpolation for an axis at
+//    cos(beta) = cos(theta_i) (both axes make that angle with the normal);
+//    the scattered field is |E_s| (sqrt(1 - K_x), sqrt(K_x)).
 #include <cmath>
 
 #include "api_common.h"
@@ -47,6 +60,10 @@ struct TraceArgs {
   const double* tau;
   const float* raw;        // per-id raw parameters [n_mat*3] or null
   const float* per_inter;  // [3*DP] or null
+  int n_vmf;               // Tx gain mixtures (0: isotropic)
+  const float* tx_raw;     // [1 + 5 n_vmf] or null
+  const float* pat_raw;    // [n_mat_pat * 6] per material K_x and pattern, or null
+  int n_mat_pat;           // materials of pat_raw
   float inv_eps0w;         // 1/(eps0 * omega_c)
   double lam4pi;           // lambda_c / (4 pi)
   float cz_tx, sz_tx, cz_rx, sz_rx;
@@ -102,6 +119,130 @@ RTC_DEV MatVal interaction_material(const TraceArgs& A, const MatVal* tab, int64
   int m = A.mat[slot];
   m = m < A.n_mat ? m : A.n_mat - 1;
   return tab[m];
+}
+
+// ------------------------------------------------------------- patterns
+constexpr int kMaxVmf = 8;
+constexpr int kTxGrad = 1 + 5 * kMaxVmf;  // eta, w, lam, mu (3 each)
+constexpr int kPatGrad = 6;               // K_x (raw), w1..w3, lam2, lam3
+
+struct VmfTab {
+  int M;
+  float eta;
+  float w[kMaxVmf], lam[kMaxVmf], c[kMaxVmf], mu[kMaxVmf][3];
+};
+
+struct PatVal {
+  float kx, w1, w2, w3, lam2, lam3;
+};
+
+RTC_DEV float logistic(float u) { return 1.0f / (1.0f + expf(-u)); }
+
+// Raw Tx parameters -> table (one thread): eta = logistic, w = softmax,
+// lam = exp, mu = normalised.
+RTC_DEV void vmf_from_raw(const float* r, int M, VmfTab* t) {
+  t->M = M;
+  t->eta = logistic(r[0]);
+  float mx = -INFINITY;
+  for (int i = 0; i < M; ++i) mx = fmaxf(mx, r[1 + i]);
+  float sum = 0.0f;
+  for (int i = 0; i < M; ++i) sum += expf(r[1 + i] - mx);
+  for (int i = 0; i < M; ++i) {
+    t->w[i] = expf(r[1 + i] - mx) / sum;
+    const float lam = expf(r[1 + M + i]);
+    t->lam[i] = lam;
+    t->c[i] = (float)(2.0 * (double)lam / -expm1(-2.0 * (double)lam));
+    const float m0 = r[1 + 2 * M + 3 * i], m1 = r[2 + 2 * M + 3 * i], m2 = r[3 + 2 * M + 3 * i];
+    const float inv = 1.0f / sqrtf(m0 * m0 + m1 * m1 + m2 * m2);
+    t->mu[i][0] = m0 * inv;
+    t->mu[i][1] = m1 * inv;
+    t->mu[i][2] = m2 * inv;
+  }
+}
+
+RTC_DEV float vmf_gain(const VmfTab& t, v3 k) {
+  float g = 0.0f;
+  for (int i = 0; i < t.M; ++i) {
+    const float cmu = t.mu[i][0] * k.x + t.mu[i][1] * k.y + t.mu[i][2] * k.z;
+    g = fmaf(t.w[i] * t.c[i], expf(t.lam[i] * (cmu - 1.0f)), g);
+  }
+  return t.eta * g;
+}
+
+RTC_DEV PatVal pattern_from_raw(const float* r, int m) {
+  const float* q = r + 6 * m;
+  PatVal v;
+  v.kx = logistic(q[0]);
+  const float mx = fmaxf(q[1], fmaxf(q[2], q[3]));
+  const float e1 = expf(q[1] - mx), e2 = expf(q[2] - mx), e3 = expf(q[3] - mx);
+  const float inv = 1.0f / (e1 + e2 + e3);
+  v.w1 = e1 * inv;
+  v.w2 = e2 * inv;
+  v.w3 = e3 * inv;
+  v.lam2 = expf(q[4]);
+  v.lam3 = expf(q[5]);
+  return v;
+}
+
+// Meder's hemispherical integral of e^{lam (v.axis - 1)} for an axis at
+// cos(beta) = x from the normal, and d ln(a)/d lam:
+//   a = (2 pi/lam)(1 - E)(E + s (1 - E)),  E = e^{-lam},
+//   s = (1 - e^{-t(1+x)}) / ((1 - e^{-t})(1 + e^{-t x})),
+//   t = sqrt(lam)(1.6988 lam^2 + 10.8438 lam)/(lam^2 + 6.2201 lam + 10.2415).
+RTC_DEV double hemi_norm(double lam, double x, double* dlog) {
+  const double P = 1.6988 * lam * lam + 10.8438 * lam;
+  const double Qd = lam * lam + 6.2201 * lam + 10.2415;
+  const double t = sqrt(lam) * P / Qd;
+  const double a1 = -expm1(-t * (1.0 + x)), b1 = -expm1(-t), e1 = exp(-t * x);
+  const double s = a1 / (b1 * (1.0 + e1));
+  const double E = exp(-lam), omE = -expm1(-lam);
+  const double inner = E + s * omE;
+  const double a = (2.0 * kPi / lam) * omE * inner;
+  if (dlog) {
+    const double dt = t * (0.5 / lam + (3.3976 * lam + 10.8438) / P - (2.0 * lam + 6.2201) / Qd);
+    const double dlns_dt = (1.0 + x) * exp(-t * (1.0 + x)) / a1 - exp(-t) / b1 + x * e1 / (1.0 + e1);
+    const double ds = s * dlns_dt * dt;
+    *dlog = -1.0 / lam + E / omE + (-E + ds * omE + s * E) / inner;
+  }
+  return a;
+}
+
+// Pattern value at a diffuse interaction and what its derivatives need.
+struct PatEval {
+  float f;            // f_s
+  float cos_s, L2, L3;  // Lambertian factor and the two normalised lobes
+  float d2, d3;       // (k_s.axis - 1) - d ln a/d lam for each lobe
+};
+
+RTC_DEV PatEval eval_pattern(const PatVal& pv, v3 k_in, v3 k_s, v3 nf, float cos_i) {
+  PatEval e;
+  const float cs = dot3(k_s, nf);
+  const v3 k_r = add3(k_in, scl3(nf, 2.0f * cos_i));
+  const float c2 = -dot3(k_s, k_in), c3 = dot3(k_s, k_r);
+  double dl2, dl3;
+  const double a2 = hemi_norm((double)pv.lam2, (double)cos_i, &dl2);
+  const double a3 = hemi_norm((double)pv.lam3, (double)cos_i, &dl3);
+  e.cos_s = cs > 0.0f ? cs * kInvPi : 0.0f;
+  e.L2 = cs > 0.0f ? (float)(exp((double)pv.lam2 * ((double)c2 - 1.0)) / a2) : 0.0f;
+  e.L3 = cs > 0.0f ? (float)(exp((double)pv.lam3 * ((double)c3 - 1.0)) / a3) : 0.0f;
+  e.d2 = (float)((double)c2 - 1.0 - dl2);
+  e.d3 = (float)((double)c3 - 1.0 - dl3);
+  e.f = pv.w1 * e.cos_s + pv.w2 * e.L2 + pv.w3 * e.L3;
+  return e;
+}
+
+// Stage the Tx table and the per-material pattern table (all threads call).
+RTC_DEV void stage_patterns(const TraceArgs& A, VmfTab* vt, PatVal* pt) {
+  if (A.n_vmf > 0 && threadIdx.x == 0) vmf_from_raw(A.tx_raw, A.n_vmf, vt);
+  if (A.pat_raw) {
+    for (int m = threadIdx.x; m < A.n_mat_pat; m += blockDim.x) pt[m] = pattern_from_raw(A.pat_raw, m);
+  }
+  __syncthreads();
+}
+
+RTC_DEV int pat_id(const TraceArgs& A, int64_t slot) {
+  int m = A.mat[slot];
+  return m < A.n_mat_pat ? m : A.n_mat_pat - 1;
 }
 
 // Fresnel coefficients (Eqs. fresnel-1/-2) for permittivity eta at
@@ -169,10 +310,16 @@ struct Chain {
   bool dif;    // the last interaction is diffuse
   float G0;    // sqrt(cos(theta_i) dA f_s) of the diffuse interaction
   float nv;    // |diag(r_perp, r_par) y| of the diffuse interaction
+  float G;     // Tx gain at k1 (1 for the isotropic Tx)
+  float f;     // f_s of the diffuse interaction
+  int pid;     // its pattern material
+  PatVal pv;   // its pattern
+  PatEval pe;
 };
 
 template <int MAXD, bool SAVE>
-RTC_DEV void run_chain(const TraceArgs& A, const MatVal* tab, int64_t p, Chain<MAXD, SAVE>& C) {
+RTC_DEV void run_chain(const TraceArgs& A, const MatVal* tab, const VmfTab* vt, const PatVal* ptab,
+                       int64_t p, Chain<MAXD, SAVE>& C) {
   int l = find_link(A.link_off, A.n_links, p);
   v3 tx = v3{A.tx_pos[3 * l], A.tx_pos[3 * l + 1], A.tx_pos[3 * l + 2]};
   v3 rx = v3{A.rx_pos[3 * l], A.rx_pos[3 * l + 1], A.rx_pos[3 * l + 2]};
@@ -185,9 +332,18 @@ RTC_DEV void run_chain(const TraceArgs& A, const MatVal* tab, int64_t p, Chain<M
   C.k1 = k1;
   v3 p_out, q_out;
   sph_basis(k1, &p_out, &q_out);
-  // Tx pattern: isotropic, slant angle zeta (Sec. II-B)
+  // Tx pattern: sqrt(G) (cos zeta, sin zeta) (Sec. II-B), G = 1 isotropic
   float2 E0 = make_float2(A.cz_tx, 0.0f);
   float2 E1 = make_float2(A.sz_tx, 0.0f);
+  C.G = 1.0f;
+  if (A.n_vmf > 0) {
+    C.G = vmf_gain(*vt, k1);
+    const float sg = sqrtf(fmaxf(C.G, 0.0f));
+    E0.x *= sg;
+    E1.x *= sg;
+  }
+  C.f = 0.0f;
+  C.pid = 0;
   v3 prev = tx;
   float rho = 0.0f;  // unfolded length from the Tx
   C.dif = false;
@@ -213,11 +369,22 @@ RTC_DEV void run_chain(const TraceArgs& A, const MatVal* tab, int64_t p, Chain<M
       if (dif) {
         v3 nf = dot3(k_in, n) > 0.0f ? scl3(n, -1.0f) : n;  // towards the incidence side
         v3 k_s = unit3(sub3(rx, s));
-        float geo = c * A.dA[slot] * fmaxf(dot3(k_s, nf), 0.0f) * kInvPi;
+        float f = fmaxf(dot3(k_s, nf), 0.0f) * kInvPi;  // Lambertian
+        float kx = 0.0f;
+        if (A.pat_raw) {
+          C.pid = pat_id(A, slot);
+          C.pv = ptab[C.pid];
+          C.pe = eval_pattern(C.pv, k_in, k_s, nf, c);
+          f = C.pe.f;
+          kx = C.pv.kx;
+        }
+        C.f = f;
+        float geo = c * A.dA[slot] * f;
         float G0 = sqrtf(fmaxf(geo, 0.0f));
         float nv = sqrtf(cabs2(cmul(rp, y0)) + cabs2(cmul(rl, y1)));
-        E0 = make_float2(mv.S * nv * G0, 0.0f);
-        E1 = make_float2(0.0f, 0.0f);
+        const float As = mv.S * nv * G0;
+        E0 = make_float2(As * sqrtf(1.0f - kx), 0.0f);
+        E1 = make_float2(As * sqrtf(kx), 0.0f);
         v3 cr = cross3(k_s, nf);
         v3 e_perp = dot3(cr, cr) > 1e-12f ? cr : np;  // k_s along n: incidence e_perp
         e_perp = unit3(sub3(e_perp, scl3(k_s, dot3(e_perp, k_s))));
@@ -267,15 +434,44 @@ RTC_DEV void run_chain(const TraceArgs& A, const MatVal* tab, int64_t p, Chain<M
   }
 }
 
+// Dynamic LDS of the trace kernels: material table | Tx table | pattern
+// table | (adjoint) per-wave accumulators, each 16-byte aligned.
+struct TraceLds {
+  MatVal* tab;
+  VmfTab* vt;
+  PatVal* pt;
+  double* acc;
+};
+RTC_DEV size_t align16(size_t n) { return (n + 15) / 16 * 16; }
+inline size_t align16h(size_t n) { return (n + 15) / 16 * 16; }
+inline size_t trace_lds_fixed(const TraceArgs& A) {
+  return align16h((A.raw ? A.n_mat : 0) * sizeof(MatVal)) + align16h(sizeof(VmfTab)) +
+         align16h((A.pat_raw ? A.n_mat_pat : 0) * sizeof(PatVal));
+}
+RTC_DEV TraceLds trace_lds(const TraceArgs& A, unsigned char* smem) {
+  TraceLds L;
+  size_t o = 0;
+  L.tab = reinterpret_cast<MatVal*>(smem + o);
+  o += align16((A.raw ? A.n_mat : 0) * sizeof(MatVal));
+  L.vt = reinterpret_cast<VmfTab*>(smem + o);
+  o += align16(sizeof(VmfTab));
+  L.pt = reinterpret_cast<PatVal*>(smem + o);
+  o += align16((A.pat_raw ? A.n_mat_pat : 0) * sizeof(PatVal));
+  L.acc = reinterpret_cast<double*>(smem + o);
+  return L;
+}
+
 template <int MAXD>
 __global__ void __launch_bounds__(kTraceBlock) trace_fields_kernel(TraceArgs A, float2* a,
                                                                     float* psi) {
-  extern __shared__ MatVal tab[];
-  stage_materials(A, tab);
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_f[];
+  const TraceLds Ls = trace_lds(A, smem_f);
+  stage_materials(A, Ls.tab);
+  stage_patterns(A, Ls.vt, Ls.pt);
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= A.n_paths) return;
   Chain<MAXD, false> C;
-  run_chain<MAXD, false>(A, tab, p, C);
+  run_chain<MAXD, false>(A, Ls.tab, Ls.vt, Ls.pt, p, C);
   // C_R^H E with a real (isotropic, slant zeta) Rx pattern
   float2 recv = cadd(cscale(C.E0, A.cz_rx), cscale(C.E1, A.sz_rx));
   if (a) a[p] = cscale(recv, C.scale);
@@ -289,17 +485,25 @@ __global__ void __launch_bounds__(kTraceBlock) trace_fields_kernel(TraceArgs A, 
 // with y_j the incoming field in the interaction basis.  With the
 // holomorphic chain rule dL/deta = conj(da/deta) dL/da, and for real
 // parameters dL/dx = Re(conj(da/dx) dL/da).
+// Layout of the reduced gradients (per-wave LDS rows, per-block partials):
+// [3 n_mat] materials (per-id mode) | [6 n_mat_pat] patterns | [kTxGrad] Tx,
+// sections present as requested (GradLayout).
+struct GradLayout {
+  int mat, pat, tx, stride;  // offsets of the sections (-1 absent), row length
+};
+
 template <int MAXD, bool PER_ID>
 __global__ void __launch_bounds__(kTraceBlock)
     trace_fields_adjoint_kernel(TraceArgs A, const float2* dLda, float* dLd_inter,
-                                double* block_part) {
-  extern __shared__ unsigned char smem[];
-  MatVal* tab = reinterpret_cast<MatVal*>(smem);
-  double* acc = reinterpret_cast<double*>(smem + ((A.raw ? A.n_mat : 0) * sizeof(MatVal) + 15) / 16 * 16);
+                                double* block_part, GradLayout GL) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const TraceLds Ls = trace_lds(A, smem);
+  MatVal* tab = Ls.tab;
+  double* acc = Ls.acc;
   stage_materials(A, tab);
-  if constexpr (PER_ID) {
-    for (int i = threadIdx.x; i < 3 * A.n_mat * (int)(blockDim.x >> 6); i += blockDim.x)
-      acc[i] = 0.0;
+  stage_patterns(A, Ls.vt, Ls.pt);
+  if (GL.stride > 0) {
+    for (int i = threadIdx.x; i < GL.stride * (int)(blockDim.x >> 6); i += blockDim.x) acc[i] = 0.0;
     __syncthreads();
   }
   const int lane = threadIdx.x & 63;
@@ -313,6 +517,14 @@ __global__ void __launch_bounds__(kTraceBlock)
     float g_eps[MAXD], g_sig[MAXD], g_S[MAXD];
     int ids[MAXD];
     int Q = 0;
+    // pattern gradients of the path's diffuse interaction (at most one):
+    // raw K_x, then w1..w3, lam2, lam3 in natural coordinates
+    float g_pat[kPatGrad];
+    int pat_m = 0x7fffffff;
+#pragma unroll
+    for (int k = 0; k < kPatGrad; ++k) g_pat[k] = 0.0f;
+    float gG = 0.0f;  // dL/dG of the Tx gain
+    v3 k1 = v3{0.0f, 0.0f, 1.0f};
 #pragma unroll
     for (int j = 0; j < MAXD; ++j) {
       g_eps[j] = g_sig[j] = g_S[j] = 0.0f;
@@ -320,9 +532,16 @@ __global__ void __launch_bounds__(kTraceBlock)
     }
     if (valid) {
       Chain<MAXD, true> C;
-      run_chain<MAXD, true>(A, tab, p, C);
+      run_chain<MAXD, true>(A, tab, Ls.vt, Ls.pt, p, C);
       Q = C.Q;
       float2 Ga = dLda[p];
+      k1 = C.k1;
+      if (GL.tx >= 0 && C.G > 0.0f) {
+        // a is proportional to sqrt(G): dL/dG = Re(conj(a) dL/da) / (2 G)
+        const float2 recv = cadd(cscale(C.E0, A.cz_rx), cscale(C.E1, A.sz_rx));
+        const float2 av = cscale(recv, C.scale);
+        gG = (av.x * Ga.x + av.y * Ga.y) / (2.0f * C.G);
+      }
       // w^T = K c_R^T D_{Q+1}  (real at the start)
       float K = C.scale;
       float2 w0 = make_float2(K * (A.cz_rx * C.Dq[0] + A.sz_rx * C.Dq[2]), 0.0f);
@@ -336,8 +555,28 @@ __global__ void __launch_bounds__(kTraceBlock)
           //   Z = conj(r_perp) dr_perp/deta |y0|^2 + conj(r_par) dr_par/deta |y1|^2
           // and d nv = Re(c^T dy) with c = (conj(v0) r_perp, conj(v1) r_par)/nv,
           // which continues the sweep through the preceding interactions.
-          const float qR = A.cz_rx * C.Dq[0] + A.sz_rx * C.Dq[2];
+          // the scattered field is |E_s| (sqrt(1 - K_x), sqrt(K_x)) and a =
+          // K (qR0 sqrt(1 - K_x) + qR1 sqrt(K_x)) |E_s|
+          const float qR0 = A.cz_rx * C.Dq[0] + A.sz_rx * C.Dq[2];
+          const float qR1 = A.cz_rx * C.Dq[1] + A.sz_rx * C.Dq[3];
+          const float kx = A.pat_raw ? C.pv.kx : 0.0f;
+          const float sk0 = sqrtf(1.0f - kx), sk1 = sqrtf(kx);
+          const float qR = qR0 * sk0 + qR1 * sk1;
           const float gam = Ga.x * K * qR;
+          if (GL.pat >= 0) {
+            // d a/du_kx with K_x = logistic(u): K |E_s| K_x (1 - K_x)
+            //   (-qR0 / (2 sqrt(1 - K_x)) + qR1 / (2 sqrt(K_x)))
+            const float As = C.mv[j].S * C.G0 * C.nv;
+            g_pat[0] = Ga.x * K * As * 0.5f * (-qR0 * kx * sk0 + qR1 * (1.0f - kx) * sk1);
+            // |E_s| grows as sqrt(f_s): dL/df = gam |E_s| / (2 f)
+            const float dLdf = C.f > 0.0f ? gam * As / (2.0f * C.f) : 0.0f;
+            g_pat[1] = dLdf * C.pe.cos_s;
+            g_pat[2] = dLdf * C.pe.L2;
+            g_pat[3] = dLdf * C.pe.L3;
+            g_pat[4] = dLdf * C.pv.w2 * C.pe.L2 * C.pe.d2;
+            g_pat[5] = dLdf * C.pv.w3 * C.pe.L3 * C.pe.d3;
+            pat_m = C.pid;
+          }
           const float2 rp = C.rperp[j], rl = C.rpar[j], sq = C.sroot[j];
           const float c = C.cos_t[j];
           const float2 eta = C.mv[j].eta;
@@ -412,7 +651,7 @@ __global__ void __launch_bounds__(kTraceBlock)
       // in FP64 and added to the wave's own LDS table (waves are summed in
       // order at the end).
       {
-        double* wacc = acc + wave * 3 * A.n_mat;
+        double* wacc = acc + wave * GL.stride + GL.mat;
         {
           int done_mask = 0;  // bit j set once interaction j is accounted
           while (true) {
@@ -446,52 +685,158 @@ __global__ void __launch_bounds__(kTraceBlock)
         }
       }
     }
+    if (GL.pat >= 0) {
+      // the same deterministic walk over the pattern ids of the wave
+      double* wacc = acc + wave * GL.stride + GL.pat;
+      bool done = !valid || pat_m == 0x7fffffff;
+      while (true) {
+        int mmin = done ? 0x7fffffff : pat_m;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) mmin = min(mmin, __shfl_xor(mmin, o, 64));
+        if (mmin == 0x7fffffff) break;
+        const bool mine = !done && pat_m == mmin;
+#pragma unroll
+        for (int k = 0; k < kPatGrad; ++k) {
+          const double v = wave_sum_f64(mine ? (double)g_pat[k] : 0.0);
+          if (lane == 0) wacc[kPatGrad * mmin + k] += v;
+        }
+        if (mine) done = true;
+      }
+    }
+    if (GL.tx >= 0) {
+      // natural Tx gradients of this path, summed over the wave in order:
+      //   eta: G/eta,  w_i: eta c_i e_i,  lam_i: eta w_i c_i e_i ((mu_i.k - 1)
+      //   + d ln c_i/d lam_i),  mu_i: eta w_i c_i e_i lam_i k
+      const VmfTab& vt = *Ls.vt;
+      const int M = vt.M;
+      double* wacc = acc + wave * GL.stride + GL.tx;
+      const float eta = vt.eta;
+      double t_eta = 0.0;
+      for (int i = 0; i < M; ++i) {
+        const float cmu = vt.mu[i][0] * k1.x + vt.mu[i][1] * k1.y + vt.mu[i][2] * k1.z;
+        const float ce = vt.c[i] * expf(vt.lam[i] * (cmu - 1.0f));
+        t_eta += (double)(vt.w[i] * ce);
+        const double lam = (double)vt.lam[i];
+        const float dlnc = (float)(1.0 / lam - 2.0 * exp(-2.0 * lam) / -expm1(-2.0 * lam));
+        const float gw = gG * eta * ce;
+        const float gl = gw * vt.w[i] * ((cmu - 1.0f) + dlnc);
+        const float gm = gw * vt.w[i] * vt.lam[i];
+        const double s_w = wave_sum_f64((double)gw);
+        const double s_l = wave_sum_f64((double)gl);
+        const double s_m0 = wave_sum_f64((double)(gm * k1.x));
+        const double s_m1 = wave_sum_f64((double)(gm * k1.y));
+        const double s_m2 = wave_sum_f64((double)(gm * k1.z));
+        if (lane == 0) {
+          wacc[1 + i] += s_w;
+          wacc[1 + M + i] += s_l;
+          wacc[1 + 2 * M + 3 * i + 0] += s_m0;
+          wacc[1 + 2 * M + 3 * i + 1] += s_m1;
+          wacc[1 + 2 * M + 3 * i + 2] += s_m2;
+        }
+      }
+      const double s_eta = wave_sum_f64((double)gG * t_eta);
+      if (lane == 0) wacc[0] += s_eta;
+    }
   }
-  if constexpr (PER_ID) {
+  if (GL.stride > 0) {
     __syncthreads();
-    for (int i = threadIdx.x; i < 3 * A.n_mat; i += blockDim.x) {
+    for (int i = threadIdx.x; i < GL.stride; i += blockDim.x) {
       double t = 0.0;
-      for (int w = 0; w < n_waves; ++w) t += acc[w * 3 * A.n_mat + i];
-      block_part[(int64_t)blockIdx.x * 3 * A.n_mat + i] = t;
+      for (int w = 0; w < n_waves; ++w) t += acc[w * GL.stride + i];
+      block_part[(int64_t)blockIdx.x * GL.stride + i] = t;
     }
   }
   (void)eps0w_inv;
 }
 
 // Sum the per-block partials (FP64, fixed order: strided per thread, then a
-// tree over the workgroup) and apply the raw parameter transforms:
-// d eps/du0 = eps - 1, d sigma/du1 = sigma, dS/du2 = S (1 - S).
-// One workgroup of kTraceBlock threads per output.
+// tree over the workgroup).  One workgroup of kTraceBlock threads per
+// output.
 __global__ void __launch_bounds__(kTraceBlock)
-    trace_adjoint_finish_kernel(const double* block_part, int n_blocks, int n_mat,
-                                const float* raw, float* dLd_raw) {
+    trace_adjoint_reduce_kernel(const double* block_part, int n_blocks, int stride, double* tot) {
   __shared__ double red[kTraceBlock];
-  const int i = blockIdx.x;  // output index < 3 n_mat
+  const int i = blockIdx.x;
   double s = 0.0;
-  for (int b = threadIdx.x; b < n_blocks; b += blockDim.x) s += block_part[(int64_t)b * 3 * n_mat + i];
+  for (int b = threadIdx.x; b < n_blocks; b += blockDim.x) s += block_part[(int64_t)b * stride + i];
   red[threadIdx.x] = s;
   __syncthreads();
   for (int h = blockDim.x / 2; h > 0; h >>= 1) {
     if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
     __syncthreads();
   }
-  if (threadIdx.x != 0) return;
-  s = red[0];
-  int m = i / 3, c = i % 3;
-  double u = (double)raw[3 * m + c];
-  double d;
-  if (c == 0)
-    d = exp(u);
-  else if (c == 1)
-    d = exp(u);
-  else {
-    double S = 1.0 / (1.0 + exp(-u));
-    d = S * (1.0 - S);
-  }
-  dLd_raw[i] = (float)(s * d);
+  if (threadIdx.x == 0) tot[i] = red[0];
 }
 
-static TraceArgs make_args(const rtc_radio* r, const rtc_paths* P, const rtc_materials* M) {
+// Raw-parameter transforms of the reduced gradients (one workgroup):
+//   materials: d eps/du0 = eps - 1, d sigma/du1 = sigma, dS/du2 = S (1 - S);
+//   patterns: K_x already raw; softmax weights dL/dq_j = w_j (g_j - sum_i
+//   w_i g_i); lam = exp(q): dL/dq = lam g;
+//   Tx: eta = logistic, softmax weights, lam = exp, mu = m/|m|:
+//   dL/dm = (g - (mu.g) mu)/|m|.
+__global__ void trace_adjoint_transform_kernel(const double* tot, GradLayout GL, int n_mat,
+                                               const float* raw, int n_mat_pat,
+                                               const float* pat_raw, int n_vmf,
+                                               const float* tx_raw, float* dLd_raw,
+                                               float* dLd_pat, float* dLd_tx) {
+  if (GL.mat >= 0 && dLd_raw) {
+    for (int i = threadIdx.x; i < 3 * n_mat; i += blockDim.x) {
+      const int m = i / 3, c = i % 3;
+      const double u = (double)raw[3 * m + c];
+      double d;
+      if (c < 2) {
+        d = exp(u);
+      } else {
+        const double S = 1.0 / (1.0 + exp(-u));
+        d = S * (1.0 - S);
+      }
+      dLd_raw[i] = (float)(tot[GL.mat + i] * d);
+    }
+  }
+  if (GL.pat >= 0 && dLd_pat) {
+    for (int m = threadIdx.x; m < n_mat_pat; m += blockDim.x) {
+      const float* q = pat_raw + 6 * m;
+      const double* g = tot + GL.pat + 6 * m;
+      const double mx = fmax((double)q[1], fmax((double)q[2], (double)q[3]));
+      double w[3], sw = 0.0;
+      for (int j = 0; j < 3; ++j) sw += (w[j] = exp((double)q[1 + j] - mx));
+      double dot = 0.0;
+      for (int j = 0; j < 3; ++j) dot += (w[j] /= sw) * g[1 + j];
+      dLd_pat[6 * m + 0] = (float)g[0];
+      for (int j = 0; j < 3; ++j) dLd_pat[6 * m + 1 + j] = (float)(w[j] * (g[1 + j] - dot));
+      dLd_pat[6 * m + 4] = (float)(exp((double)q[4]) * g[4]);
+      dLd_pat[6 * m + 5] = (float)(exp((double)q[5]) * g[5]);
+    }
+  }
+  if (GL.tx >= 0 && dLd_tx && threadIdx.x == 0) {
+    const int M = n_vmf;
+    const double* g = tot + GL.tx;
+    const double eta = 1.0 / (1.0 + exp(-(double)tx_raw[0]));
+    dLd_tx[0] = (float)(eta * (1.0 - eta) * g[0]);
+    double mx = -INFINITY;
+    for (int i = 0; i < M; ++i) mx = fmax(mx, (double)tx_raw[1 + i]);
+    double sw = 0.0;
+    for (int i = 0; i < M; ++i) sw += exp((double)tx_raw[1 + i] - mx);
+    double dot = 0.0;
+    for (int i = 0; i < M; ++i) dot += exp((double)tx_raw[1 + i] - mx) / sw * g[1 + i];
+    for (int i = 0; i < M; ++i) {
+      const double wi = exp((double)tx_raw[1 + i] - mx) / sw;
+      dLd_tx[1 + i] = (float)(wi * (g[1 + i] - dot));
+      dLd_tx[1 + M + i] = (float)(exp((double)tx_raw[1 + M + i]) * g[1 + M + i]);
+      const double m0 = tx_raw[1 + 2 * M + 3 * i], m1 = tx_raw[2 + 2 * M + 3 * i],
+                   m2 = tx_raw[3 + 2 * M + 3 * i];
+      const double nm = sqrt(m0 * m0 + m1 * m1 + m2 * m2);
+      const double u0 = m0 / nm, u1 = m1 / nm, u2 = m2 / nm;
+      const double g0 = g[1 + 2 * M + 3 * i], g1 = g[2 + 2 * M + 3 * i], g2 = g[3 + 2 * M + 3 * i];
+      const double ug = u0 * g0 + u1 * g1 + u2 * g2;
+      dLd_tx[1 + 2 * M + 3 * i + 0] = (float)((g0 - ug * u0) / nm);
+      dLd_tx[1 + 2 * M + 3 * i + 1] = (float)((g1 - ug * u1) / nm);
+      dLd_tx[1 + 2 * M + 3 * i + 2] = (float)((g2 - ug * u2) / nm);
+    }
+  }
+}
+
+static TraceArgs make_args(const rtc_radio* r, const rtc_paths* P, const rtc_materials* M,
+                           const rtc_patterns* pat) {
   TraceArgs A;
   A.n_links = P->n_links;
   A.n_paths = P->n_paths;
@@ -514,6 +859,10 @@ static TraceArgs make_args(const rtc_radio* r, const rtc_paths* P, const rtc_mat
   A.tau = P->tau;
   A.raw = M->raw;
   A.per_inter = M->per_inter;
+  A.n_vmf = (pat && pat->tx_raw) ? pat->n_vmf : 0;
+  A.tx_raw = pat ? pat->tx_raw : nullptr;
+  A.pat_raw = pat ? pat->mat_raw : nullptr;
+  A.n_mat_pat = M->n_mat > 0 ? M->n_mat : 1;
   double omega = 2.0 * kPi * r->fc_hz;
   A.inv_eps0w = (float)(1.0 / (kEps0 * omega));
   A.lam4pi = (kC0 / r->fc_hz) / (4.0 * kPi);
@@ -536,31 +885,72 @@ static int depth_bucket(int d) {
   return 8;
 }
 
-size_t ws_trace_adjoint(int32_t n_paths, int32_t n_mat) {
-  if (n_mat < 1) n_mat = 1;
+static int64_t adj_blocks(int32_t n_paths) {
   int64_t blocks = ((int64_t)n_paths + kTraceBlock - 1) / kTraceBlock;
   if (blocks > kTraceAdjMaxBlocks) blocks = kTraceAdjMaxBlocks;
-  if (blocks < 1) blocks = 1;
-  return (size_t)blocks * 3 * n_mat * sizeof(double);
+  return blocks < 1 ? 1 : blocks;
+}
+
+// Gradient sections: materials (per-id), patterns, Tx (sizes for the
+// workspace use the largest Tx section, kTxGrad).
+static GradLayout grad_layout(bool mat, int n_mat, bool pat, int n_mat_pat, bool tx) {
+  GradLayout g;
+  int o = 0;
+  g.mat = mat ? o : -1;
+  o += mat ? 3 * n_mat : 0;
+  g.pat = pat ? o : -1;
+  o += pat ? kPatGrad * n_mat_pat : 0;
+  g.tx = tx ? o : -1;
+  o += tx ? kTxGrad : 0;
+  g.stride = o;
+  return g;
+}
+
+static size_t ws_for(int32_t n_paths, const GradLayout& g) {
+  if (g.stride == 0) return 0;
+  return (size_t)(adj_blocks(n_paths) + 1) * g.stride * sizeof(double);
+}
+
+size_t ws_trace_adjoint(int32_t n_paths, int32_t n_mat) {
+  if (n_mat < 1) n_mat = 1;
+  return ws_for(n_paths, grad_layout(true, n_mat, false, 0, false));
+}
+
+// Workspace for every gradient the pattern variant can produce.
+size_t ws_trace_adjoint_pat(int32_t n_paths, int32_t n_mat) {
+  if (n_mat < 1) n_mat = 1;
+  return ws_for(n_paths, grad_layout(true, n_mat, true, n_mat, true));
+}
+
+static rtc_status check_patterns(const rtc_patterns* pat, const rtc_materials* m, const char* fn) {
+  if (!pat) return RTC_OK;
+  RTC_REQUIRE(pat->n_vmf >= 0 && pat->n_vmf <= kMaxVmf, RTC_ERR_RANGE,
+              "%s: n_vmf must be in [0, %d]", fn, kMaxVmf);
+  RTC_REQUIRE(pat->n_vmf == 0 || pat->tx_raw != nullptr, RTC_ERR_INVALID_ARG,
+              "%s: tx_raw is required when n_vmf > 0", fn);
+  RTC_REQUIRE(!pat->mat_raw || m->n_mat >= 1, RTC_ERR_SHAPE,
+              "%s: mat_raw needs n_mat >= 1 materials", fn);
+  return RTC_OK;
 }
 
 }  // namespace rtc
 
 using namespace rtc;
 
-extern "C" rtc_status rtc_trace_fields(const rtc_radio* radio, const rtc_paths* paths,
-                                       const rtc_materials* mats, void* a, float* psi,
-                                       void* stream) {
+extern "C" rtc_status rtc_trace_fields_pat(const rtc_radio* radio, const rtc_paths* paths,
+                                           const rtc_materials* mats, const rtc_patterns* pats,
+                                           void* a, float* psi, void* stream) {
   const char* fn = "rtc_trace_fields";
   rtc_status st;
   if ((st = check_radio(radio, fn)) != RTC_OK) return st;
   if ((st = check_paths(paths, fn, true)) != RTC_OK) return st;
   if ((st = check_mats(mats, paths, fn)) != RTC_OK) return st;
+  if ((st = check_patterns(pats, mats, fn)) != RTC_OK) return st;
   if (paths->n_paths == 0 || (a == nullptr && psi == nullptr)) return RTC_OK;
   RTC_REQUIRE(paths->n_links >= 1, RTC_ERR_SHAPE, "%s: n_paths > 0 needs n_links >= 1", fn);
-  TraceArgs A = make_args(radio, paths, mats);
+  TraceArgs A = make_args(radio, paths, mats, pats);
   dim3 grid((paths->n_paths + kTraceBlock - 1) / kTraceBlock);
-  size_t shm = (mats->raw ? mats->n_mat : 0) * sizeof(MatVal);
+  size_t shm = trace_lds_fixed(A);
   hipStream_t s = as_stream(stream);
   switch (depth_bucket(paths->max_depth)) {
 #define RTC_CASE(D)                                                                          \
@@ -579,15 +969,22 @@ extern "C" rtc_status rtc_trace_fields(const rtc_radio* radio, const rtc_paths* 
   return check_launch(fn);
 }
 
-extern "C" rtc_status rtc_trace_fields_adjoint(const rtc_radio* radio, const rtc_paths* paths,
-                                               const rtc_materials* mats, const void* dLda,
-                                               float* dLd_raw, float* dLd_inter, void* ws,
-                                               size_t ws_bytes, void* stream) {
+extern "C" rtc_status rtc_trace_fields(const rtc_radio* radio, const rtc_paths* paths,
+                                       const rtc_materials* mats, void* a, float* psi,
+                                       void* stream) {
+  return rtc_trace_fields_pat(radio, paths, mats, nullptr, a, psi, stream);
+}
+
+extern "C" rtc_status rtc_trace_fields_adjoint_pat(
+    const rtc_radio* radio, const rtc_paths* paths, const rtc_materials* mats,
+    const rtc_patterns* pats, const void* dLda, float* dLd_raw, float* dLd_inter, float* dLd_tx,
+    float* dLd_pat, void* ws, size_t ws_bytes, void* stream) {
   const char* fn = "rtc_trace_fields_adjoint";
   rtc_status st;
   if ((st = check_radio(radio, fn)) != RTC_OK) return st;
   if ((st = check_paths(paths, fn, true)) != RTC_OK) return st;
   if ((st = check_mats(mats, paths, fn)) != RTC_OK) return st;
+  if ((st = check_patterns(pats, mats, fn)) != RTC_OK) return st;
   RTC_REQUIRE(dLda != nullptr || paths->n_paths == 0, RTC_ERR_INVALID_ARG, "%s: dLda is NULL", fn);
   bool per_id = mats->raw != nullptr;
   RTC_REQUIRE(per_id ? (dLd_raw != nullptr && dLd_inter == nullptr)
@@ -596,35 +993,44 @@ extern "C" rtc_status rtc_trace_fields_adjoint(const rtc_radio* radio, const rtc
               "%s: per-id mode needs dLd_raw (and dLd_inter NULL); per-interaction mode the "
               "reverse",
               fn);
+  const bool want_tx = dLd_tx != nullptr;
+  const bool want_pat = dLd_pat != nullptr;
+  RTC_REQUIRE(!want_tx || (pats && pats->n_vmf > 0), RTC_ERR_INVALID_ARG,
+              "%s: dLd_tx needs a Tx gain (n_vmf > 0)", fn);
+  RTC_REQUIRE(!want_pat || (pats && pats->mat_raw), RTC_ERR_INVALID_ARG,
+              "%s: dLd_pat needs mat_raw", fn);
+  RTC_REQUIRE(!want_pat || per_id, RTC_ERR_UNSUPPORTED,
+              "%s: pattern gradients need per-id materials", fn);
   hipStream_t s = as_stream(stream);
-  TraceArgs A = make_args(radio, paths, mats);
+  TraceArgs A = make_args(radio, paths, mats, pats);
+  const GradLayout GL = grad_layout(per_id, A.n_mat, want_pat, A.n_mat_pat, want_tx);
   int64_t blocks = ((int64_t)paths->n_paths + kTraceBlock - 1) / kTraceBlock;
-  if (per_id) {
-    size_t need = ws_trace_adjoint(paths->n_paths, mats->n_mat);
+  if (GL.stride > 0) {
+    size_t need = ws_for(paths->n_paths, GL);
     RTC_REQUIRE(ws != nullptr && ws_bytes >= need, RTC_ERR_WORKSPACE,
                 "%s: workspace of %zu bytes required", fn, need);
-    if (blocks > kTraceAdjMaxBlocks) blocks = kTraceAdjMaxBlocks;
-    if (blocks < 1) blocks = 1;
+    blocks = adj_blocks(paths->n_paths);
   } else if (paths->n_paths == 0) {
     return RTC_OK;
   }
-  if (paths->n_paths > 0 || per_id) {
+  if (paths->n_paths > 0 || GL.stride > 0) {
     RTC_REQUIRE(paths->n_links >= 1 || paths->n_paths == 0, RTC_ERR_SHAPE,
                 "%s: n_paths > 0 needs n_links >= 1", fn);
   }
-  size_t tab_bytes = ((per_id ? mats->n_mat : 0) * sizeof(MatVal) + 15) / 16 * 16;
-  size_t shm = tab_bytes + (per_id ? (kTraceBlock / 64) * 3 * mats->n_mat * sizeof(double) : 0);
+  size_t shm = trace_lds_fixed(A) + (size_t)(kTraceBlock / 64) * GL.stride * sizeof(double);
+  RTC_REQUIRE(shm <= 160 * 1024, RTC_ERR_RANGE,
+              "%s: %zu bytes of LDS needed (too many materials for the gradients asked)", fn, shm);
   double* part = reinterpret_cast<double*>(ws);
   switch (depth_bucket(paths->max_depth)) {
 #define RTC_CASE(D)                                                                            \
   case D:                                                                                      \
     if (per_id)                                                                                \
       hipLaunchKernelGGL((trace_fields_adjoint_kernel<D, true>), dim3(blocks), dim3(kTraceBlock), \
-                         shm, s, A, reinterpret_cast<const float2*>(dLda), nullptr, part);     \
+                         shm, s, A, reinterpret_cast<const float2*>(dLda), nullptr, part, GL); \
     else                                                                                       \
       hipLaunchKernelGGL((trace_fields_adjoint_kernel<D, false>), dim3(blocks),                \
                          dim3(kTraceBlock), shm, s, A, reinterpret_cast<const float2*>(dLda),  \
-                         dLd_inter, nullptr);                                                  \
+                         dLd_inter, part, GL);                                                 \
     break;
     RTC_CASE(1)
     RTC_CASE(2)
@@ -635,11 +1041,23 @@ extern "C" rtc_status rtc_trace_fields_adjoint(const rtc_radio* radio, const rtc
 #undef RTC_CASE
   }
   if ((st = check_launch(fn)) != RTC_OK) return st;
-  if (per_id) {
-    int n = 3 * mats->n_mat;
-    hipLaunchKernelGGL(trace_adjoint_finish_kernel, dim3(n), dim3(kTraceBlock), 0, s, part,
-                       (int)blocks, mats->n_mat, mats->raw, dLd_raw);
+  if (GL.stride > 0) {
+    double* tot = part + blocks * GL.stride;
+    hipLaunchKernelGGL(trace_adjoint_reduce_kernel, dim3(GL.stride), dim3(kTraceBlock), 0, s, part,
+                       (int)blocks, GL.stride, tot);
+    if ((st = check_launch(fn)) != RTC_OK) return st;
+    hipLaunchKernelGGL(trace_adjoint_transform_kernel, dim3(1), dim3(kTraceBlock), 0, s, tot, GL,
+                       A.n_mat, mats->raw, A.n_mat_pat, A.pat_raw, A.n_vmf, A.tx_raw, dLd_raw,
+                       dLd_pat, dLd_tx);
     return check_launch(fn);
   }
   return RTC_OK;
+}
+
+extern "C" rtc_status rtc_trace_fields_adjoint(const rtc_radio* radio, const rtc_paths* paths,
+                                               const rtc_materials* mats, const void* dLda,
+                                               float* dLd_raw, float* dLd_inter, void* ws,
+                                               size_t ws_bytes, void* stream) {
+  return rtc_trace_fields_adjoint_pat(radio, paths, mats, nullptr, dLda, dLd_raw, dLd_inter,
+                                      nullptr, nullptr, ws, ws_bytes, stream);
 }

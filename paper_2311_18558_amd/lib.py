@@ -29,6 +29,7 @@ RTC_OP_CFR_ADJOINT = 2
 RTC_OP_TRACE_FIELDS_ADJOINT = 3
 RTC_OP_CFR_TARGET_STATS = 4
 RTC_OP_PAPER_LOSS = 5
+RTC_OP_TRACE_FIELDS_ADJOINT_PAT = 6
 
 
 class Radio(ctypes.Structure):
@@ -47,6 +48,10 @@ class Materials(ctypes.Structure):
     _fields_ = [("n_mat", c_i32), ("raw", c_vp), ("per_inter", c_vp)]
 
 
+class Patterns(ctypes.Structure):
+    _fields_ = [("n_vmf", c_i32), ("tx_raw", c_vp), ("mat_raw", c_vp)]
+
+
 class Mlp(ctypes.Structure):
     _fields_ = [("params", c_vp), ("aabb_center", c_f32 * 3), ("inv_extent", c_f32),
                 ("n_freq", c_i32), ("width", c_i32), ("n_hidden", c_i32)]
@@ -59,6 +64,13 @@ _SIGS = {
     "rtc_workspace_size": (c_size, [ctypes.c_int, ctypes.POINTER(Radio), c_i32, c_i32, c_i32]),
     "rtc_trace_fields": (ctypes.c_int, [ctypes.POINTER(Radio), ctypes.POINTER(Paths),
                                         ctypes.POINTER(Materials), c_vp, c_vp, c_vp]),
+    "rtc_trace_fields_pat": (ctypes.c_int, [ctypes.POINTER(Radio), ctypes.POINTER(Paths),
+                                            ctypes.POINTER(Materials), ctypes.POINTER(Patterns),
+                                            c_vp, c_vp, c_vp]),
+    "rtc_trace_fields_adjoint_pat": (ctypes.c_int, [ctypes.POINTER(Radio), ctypes.POINTER(Paths),
+                                                    ctypes.POINTER(Materials),
+                                                    ctypes.POINTER(Patterns), c_vp, c_vp, c_vp,
+                                                    c_vp, c_vp, c_vp, c_size, c_vp]),
     "rtc_cfr": (ctypes.c_int, [ctypes.POINTER(Radio), ctypes.POINTER(Paths), c_vp, c_vp, c_vp,
                                c_vp, c_vp]),
     "rtc_cfr_target_stats": (ctypes.c_int, [ctypes.POINTER(Radio), c_i32, c_vp, c_vp, c_vp,
@@ -214,6 +226,33 @@ def workspace(op, radio, n_links, n_paths, n_mat=1, device="cuda"):
 def trace_fields(radio, paths, mats, a, psi, stream=None):
     _check(load().rtc_trace_fields(ctypes.byref(radio), ctypes.byref(paths.c), ctypes.byref(mats),
                                    _ptr(a), _ptr(psi), _stream(stream)), "rtc_trace_fields")
+
+
+def patterns(n_vmf=0, tx_raw=None, mat_raw=None):
+    """Descriptor of the trainable patterns (keeps references to the
+    device tensors)."""
+    p = Patterns()
+    p.n_vmf = int(n_vmf)
+    p.tx_raw = None if tx_raw is None else tx_raw.data_ptr()
+    p.mat_raw = None if mat_raw is None else mat_raw.data_ptr()
+    p._keep = (tx_raw, mat_raw)
+    return p
+
+
+def trace_fields_pat(radio, paths, mats, pats, a, psi, stream=None):
+    _check(load().rtc_trace_fields_pat(ctypes.byref(radio), ctypes.byref(paths.c),
+                                       ctypes.byref(mats),
+                                       None if pats is None else ctypes.byref(pats), _ptr(a),
+                                       _ptr(psi), _stream(stream)), "rtc_trace_fields_pat")
+
+
+def trace_fields_adjoint_pat(radio, paths, mats, pats, dLda, dLd_raw, dLd_inter, dLd_tx, dLd_pat,
+                             ws, stream=None):
+    _check(load().rtc_trace_fields_adjoint_pat(
+        ctypes.byref(radio), ctypes.byref(paths.c), ctypes.byref(mats),
+        None if pats is None else ctypes.byref(pats), _ptr(dLda), _ptr(dLd_raw), _ptr(dLd_inter),
+        _ptr(dLd_tx), _ptr(dLd_pat), _ptr(ws), 0 if ws is None else ws.numel(), _stream(stream)),
+        "rtc_trace_fields_adjoint_pat")
 
 
 def cfr(radio, paths, a, psi, g, H, stream=None):

@@ -137,3 +137,45 @@ def test_paper_loss_argument_checks(lib):
     assert st == -1
     n = lib.workspace_size(lib.RTC_OP_PAPER_LOSS, r, 512, 0)
     assert n >= 512 * 4 * 2 * 8
+
+
+def test_pattern_argument_checks(lib):
+    so = lib.load()
+    r = _radio(lib)
+    p = lib.Paths()
+    p.n_links, p.n_paths, p.max_depth = 1, 1, 0
+    p.link_off = p.tx_pos = p.rx_pos = p.depth = p.tau = 16
+    m = lib.Materials()
+    m.n_mat, m.raw = 2, 16
+    pat = lib.Patterns()
+    pat.n_vmf = 9
+    st = so.rtc_trace_fields_pat(ctypes.byref(r), ctypes.byref(p), ctypes.byref(m),
+                                 ctypes.byref(pat), None, None, None)
+    assert st == -3 and b"n_vmf" in so.rtc_last_error()
+    pat.n_vmf = 2
+    st = so.rtc_trace_fields_pat(ctypes.byref(r), ctypes.byref(p), ctypes.byref(m),
+                                 ctypes.byref(pat), None, None, None)
+    assert st == -1 and b"tx_raw" in so.rtc_last_error()
+    pat.n_vmf = 0
+    q = ctypes.c_void_p(16)
+    # a Tx gradient without a Tx gain
+    st = so.rtc_trace_fields_adjoint_pat(ctypes.byref(r), ctypes.byref(p), ctypes.byref(m),
+                                         ctypes.byref(pat), q, q, None, q, None, q, 1 << 20, None)
+    assert st == -1 and b"dLd_tx" in so.rtc_last_error()
+    # pattern gradients without mat_raw, then with per-interaction materials
+    st = so.rtc_trace_fields_adjoint_pat(ctypes.byref(r), ctypes.byref(p), ctypes.byref(m),
+                                         ctypes.byref(pat), q, q, None, None, q, q, 1 << 20, None)
+    assert st == -1 and b"mat_raw" in so.rtc_last_error()
+    pat.mat_raw = 16
+    mi = lib.Materials()
+    mi.n_mat, mi.per_inter = 1, 16
+    st = so.rtc_trace_fields_adjoint_pat(ctypes.byref(r), ctypes.byref(p), ctypes.byref(mi),
+                                         ctypes.byref(pat), q, None, q, None, q, q, 1 << 20, None)
+    assert st == -6 and b"per-id" in so.rtc_last_error()
+    # workspace too small for the pattern gradients
+    st = so.rtc_trace_fields_adjoint_pat(ctypes.byref(r), ctypes.byref(p), ctypes.byref(m),
+                                         ctypes.byref(pat), q, q, None, None, q, q, 8, None)
+    assert st == -4 and b"workspace" in so.rtc_last_error()
+    n0 = lib.workspace_size(lib.RTC_OP_TRACE_FIELDS_ADJOINT, r, 4, 1000, 3)
+    n1 = lib.workspace_size(lib.RTC_OP_TRACE_FIELDS_ADJOINT_PAT, r, 4, 1000, 3)
+    assert n1 > n0 > 0
