@@ -30,6 +30,25 @@ def materials_from_raw(raw):
     return eps_r, sigma, s
 
 
+def embedding_readout(v, W):
+    """Sec. III-C: the scalars v . w_j of every material and embedding.
+    v [L] is the read-out vector shared by all materials, W [n_mat, 4, L]
+    holds each material's embeddings w_1 .. w_4.  Returns u [n_mat, 4]."""
+    return torch.as_tensor(W, dtype=f64) @ torch.as_tensor(v, dtype=f64)
+
+
+def materials_from_embeddings(v, W):
+    """Eqs. trainable_materials_1-4: sigma = exp(v.w_1), eps_r = 1 +
+    exp(v.w_2), S = logistic(v.w_3), K_x = logistic(v.w_4).  Returns
+    (eps_r, sigma, S, K_x), each [n_mat]."""
+    u = embedding_readout(v, W)
+    sigma = torch.exp(u[:, 0])
+    eps_r = 1.0 + torch.exp(u[:, 1])
+    s = 1.0 / (1.0 + torch.exp(-u[:, 2]))
+    kx = 1.0 / (1.0 + torch.exp(-u[:, 3]))
+    return eps_r, sigma, s, kx
+
+
 def specular_amplitude(s):
     """R = sqrt(1 - S^2): the specularly reflected amplitude fraction
     (Sec. II-D)."""
