@@ -182,6 +182,67 @@ def paper_loss_step(st, radio, w, raw0, H_tgt, steps, warmup=1):
     return res
 
 
+def recovery_bench(steps=200, warmup=5):
+    """Step rate of the synthetic recovery experiment's calibration step
+    (Sec. IV-B shape on the stand-in hallway: 256 Tx, 1 Rx antenna, specular
+    up to third order + single-bounce diffuse paths, 1,024 subcarriers):
+    trainable L = 30 embeddings, scattering patterns and an M = 3 Tx gain,
+    the paper's loss, Adam, every link per step.  The targets here are the
+    library's own forward at other parameters (only the time is reported)."""
+    import math
+    from paper_2311_18558_amd import lib as rl
+    from paper_2311_18558_amd.calibrate import Calibrator
+    from synth import workloads
+    t0 = time.time()
+    w = workloads.recovery()
+    st = w.store
+    log(f"workload recovery: {st.n_links} links, {st.n_paths} paths, "
+        f"generated in {time.time() - t0:.1f}s")
+    dp = rl.DevicePaths(st)
+    rng = np.random.default_rng(0)
+    L = 30
+    v0 = rng.normal(size=L)
+    W0 = rng.normal(size=(3, 4, L)) * 0.1 / math.sqrt(L)
+    pat0 = np.zeros((3, 6))
+    pat0[:, 4:] = math.log(5.0)
+    tx0 = np.concatenate([[0.0], np.zeros(3), np.zeros(3), rng.normal(size=9)])
+    # targets: the same model at the ground-truth materials and Tx gain
+    gt_pat = np.zeros((3, 6), np.float32)
+    gt_pat[:, 0] = np.log(w.meta["kx"] / (1 - w.meta["kx"]))
+    raw_d = torch.tensor(w.raw, device="cuda")
+    a = torch.empty(st.n_paths, dtype=torch.complex64, device="cuda")
+    psi = torch.empty(st.n_paths, dtype=torch.float32, device="cuda")
+    H = torch.empty((st.n_links, 1, w.radio.n_sc), dtype=torch.complex64, device="cuda")
+    rc = rl.radio_from(w.radio)
+    pats = rl.patterns(3, torch.tensor(w.meta["tx_raw"], device="cuda"),
+                       torch.tensor(gt_pat, device="cuda"))
+    rl.trace_fields_pat(rc, dp, rl.materials_per_id(raw_d), pats, a, psi)
+    rl.cfr(rc, dp, a, psi, torch.ones(1, dtype=torch.complex64, device="cuda"), H)
+    cal = Calibrator(dp, w.radio, H, "embed", embed0=(v0, W0), n_vmf=3, tx_raw0=tx0,
+                     pat_raw0=pat0, lr=0.01, lr_gain=0.0, loss="paper")
+    links = torch.arange(st.n_links, device="cuda")
+    for _ in range(warmup):
+        cal.step(links)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        cal.step(links)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    out = {"workload": "stand-in hallway 24 x 6 x 3 m, 256 Tx, 1 Rx antenna, specular up to "
+                       "3rd order + single-bounce diffuse, 1,024 subcarriers over 50 MHz",
+           "links": st.n_links, "paths": st.n_paths, "steps": steps, "ms_per_step": round(ms, 3),
+           "steps_per_s": round(1e3 / ms, 1),
+           "seconds_for_3000_steps": round(3.0 * ms, 2)}
+    log(f"recovery step: {out}")
+    del cal, H, dp
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(w, budget_s=15.0, max_links=8192):
     """The FP64 oracle (forward, loss, reverse-mode gradient) on whole
     links of the same workload until `budget_s` of CPU time is spent."""
@@ -322,6 +383,8 @@ def main():
     ap.add_argument("--calib-steps", type=int, default=3000)
     ap.add_argument("--no-diffuse", action="store_true",
                     help="skip the diffuse-scattering workload line")
+    ap.add_argument("--no-recovery", action="store_true",
+                    help="skip the synthetic-recovery step-rate line")
     ap.add_argument("--copy-probe", action="store_true",
                     help="start with a 2 GiB device copy (counter calibration)")
     ap.add_argument("--traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -439,6 +502,8 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_diffuse:
         out["diffuse"] = diffuse_bench()
+    if not args.no_recovery:
+        out["recovery"] = recovery_bench()
     if not args.no_calib:
         out["calib"] = calib_compare(w, args.calib_steps)
     if not args.no_cpu_baseline:

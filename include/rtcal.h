@@ -311,6 +311,30 @@ rtc_status rtc_trace_fields_adjoint_pat(const rtc_radio* radio, const rtc_paths*
                                         float* dLd_tx, float* dLd_pat, void* ws, size_t ws_bytes,
                                         void* stream);
 
+/* Material embeddings (Sec. III-C, Eqs. trainable_materials_1-4): every
+ * material m has four embeddings w_1 .. w_4 in R^L, and one read-out vector
+ * v in R^L is shared by all materials; u_{m,j} = v . w_{m,j} gives
+ * sigma = e^{u_1}, eps_r = 1 + e^{u_2}, S = logistic(u_3), K_x = logistic(u_4).
+ *   v  float [L], W float [n_mat, 4, L] row-major, W[m, j-1, :] = w_j of
+ *      material m (paper order: sigma, eps_r, S, K_x); 1 <= n_mat <= 4096,
+ *      1 <= L <= 1024
+ *   raw     float [n_mat * 3], the per-id layout of rtc_materials:
+ *           raw[3m] = u_2 (eps_r), raw[3m+1] = u_1 (sigma), raw[3m+2] = u_3 (S)
+ *   pat_raw float [n_mat * 6] (rtc_patterns.mat_raw) or NULL:
+ *           pat_raw[6m] = u_4 (the K_x logit); its other columns are not touched
+ * Each u is an FP64 sum rounded once to float. */
+rtc_status rtc_embed_readout(int32_t n_mat, int32_t L, const float* v, const float* W, float* raw,
+                             float* pat_raw, void* stream);
+
+/* Backward of rtc_embed_readout: dLd_raw float [n_mat * 3] (required) and
+ * dLd_pat float [n_mat * 6] or NULL (only column 0, dL/du_4, is read; NULL
+ * counts as 0) give dL/du; writes dLd_v float [L] = sum_{m,j} W[m,j,:] dL/du_{m,j}
+ * (FP64 sums in a fixed order) and dLd_W float [n_mat, 4, L] = v dL/du_{m,j}.
+ * Outputs are overwritten; either may be NULL. */
+rtc_status rtc_embed_readout_backward(int32_t n_mat, int32_t L, const float* v, const float* W,
+                                      const float* dLd_raw, const float* dLd_pat, float* dLd_v,
+                                      float* dLd_W, void* stream);
+
 /* Neural materials (Sec. III-D): per point p, p_bar = (p - aabb_center) *
  * inv_extent (inv_extent = 1 / longest edge of the scene's axis-aligned
  * bounding box, so p_bar lies in [-1/2, 1/2]^3); input features

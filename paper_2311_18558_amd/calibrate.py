@@ -4,6 +4,13 @@ in Sec. IV-B) on fixed paths, in two parametrisations:
   'per_id'  trainable materials per class (Sec. III-C, one-dimensional
             embeddings): raw [n_mat, 3] plus the complex element gains
   'neural'  neural materials (Sec. III-D): MLP weights plus the gains
+  'embed'   material embeddings of dimension L with a shared read-out
+            vector (Sec. III-C, Eqs. trainable_materials_1-4)
+
+Optionally (per_id and embed) the trainable Tx gain (Sec. III-A) and the
+trainable scattering pattern with K_x per material (Sec. III-B) are
+calibrated with the materials; in embed mode K_x comes from the fourth
+embedding.
 
 The loss is the workload loss (coherent + power-delay-profile NMSE) or, with
 loss="paper", the paper's own (Sec. III-E: SMAPE of RMS delay spread and gain
@@ -41,9 +48,17 @@ def mlp_out_bias():
 class Calibrator:
     def __init__(self, dp, radio, H_all, mode, raw0=None, mlp_params0=None, g0=None,
                  aabb=None, lr=0.01, lr_mlp=1e-3, lr_gain=None, device="cuda", loss="workload",
-                 update_alpha=False, delta=0.99):
+                 update_alpha=False, delta=0.99, embed0=None, n_vmf=0, tx_raw0=None,
+                 pat_raw0=None):
+        """embed0 = (v [L], W [n_mat, 4, L]) for mode 'embed'; n_vmf, tx_raw0
+        [1 + 5 n_vmf] the initial raw Tx gain; pat_raw0 [n_mat, 6] the
+        initial raw scattering patterns (see rtc_patterns)."""
         if loss not in ("workload", "paper"):
             raise ValueError(loss)
+        if mode not in ("per_id", "neural", "embed"):
+            raise ValueError(mode)
+        if mode == "neural" and pat_raw0 is not None:
+            raise ValueError("scattering patterns are calibrated per material (per_id, embed)")
         self.dev = torch.device(device)
         self.loss_kind, self.update_alpha, self.delta = loss, update_alpha, delta
         self.alpha = torch.tensor([1.0, 0.0], dtype=torch.float64, device=self.dev)
@@ -59,20 +74,45 @@ class Calibrator:
         self.lr, self.lr_mlp = lr, lr_mlp
         self.lr_gain = lr if lr_gain is None else lr_gain
         self.t = 0
+        # one flat FP32 parameter vector: [materials or MLP | patterns | Tx gain]
+        segs = []
         if mode == "per_id":
-            self.raw = torch.tensor(raw0, device=self.dev)
-            self.mats = lib.materials_per_id(self.raw)
-            self.m_p = torch.zeros_like(self.raw)
-            self.v_p = torch.zeros_like(self.raw)
-            self.params = self.raw
-        elif mode == "neural":
-            self.params = torch.tensor(mlp_params0, device=self.dev)
-            self.net = lib.make_mlp(self.params, *aabb)
-            self.m_p = torch.zeros_like(self.params)
-            self.v_p = torch.zeros_like(self.params)
+            segs.append(("raw", np.asarray(raw0, np.float32)))
+        elif mode == "embed":
+            segs += [("v", np.asarray(embed0[0], np.float32)),
+                     ("W", np.asarray(embed0[1], np.float32))]
         else:
-            raise ValueError(mode)
-        self.dparams = torch.empty_like(self.params)
+            segs.append(("mlp", np.asarray(mlp_params0, np.float32)))
+        self.n_main = sum(a.size for _, a in segs)
+        if pat_raw0 is not None:
+            segs.append(("pat", np.asarray(pat_raw0, np.float32)))
+        self.n_vmf = int(n_vmf)
+        if self.n_vmf:
+            segs.append(("tx", np.asarray(tx_raw0, np.float32)))
+        flat = np.concatenate([a.reshape(-1) for _, a in segs])
+        self.params = torch.tensor(flat, device=self.dev)
+        self.dparams = torch.zeros_like(self.params)
+        self.P, self.G = {}, {}
+        o = 0
+        for name, a in segs:
+            self.P[name] = self.params[o:o + a.size].view(a.shape)
+            self.G[name] = self.dparams[o:o + a.size].view(a.shape)
+            o += a.size
+        self.m_p = torch.zeros_like(self.params)
+        self.v_p = torch.zeros_like(self.params)
+        if mode == "per_id":
+            self.raw = self.P["raw"]
+        elif mode == "embed":
+            self.raw = torch.empty((self.P["W"].shape[0], 3), dtype=torch.float32,
+                                   device=self.dev)
+            self.draw = torch.empty_like(self.raw)
+        if mode != "neural":
+            self.mats = lib.materials_per_id(self.raw)
+        else:
+            self.net = lib.make_mlp(self.P["mlp"], *aabb)
+        self.with_patterns = pat_raw0 is not None or self.n_vmf > 0
+        self.pats = (lib.patterns(self.n_vmf, self.P.get("tx"), self.P.get("pat"))
+                     if self.with_patterns else None)
         self._bufs = {}
         if loss == "paper":
             # per-row gain and RMS delay spread of every measured CFR, once
@@ -96,7 +136,9 @@ class Calibrator:
     def _materials(self, b):
         """Per-interaction materials of batch paths b (neural mode) or the
         per-id descriptor."""
-        if self.mode == "per_id":
+        if self.mode == "embed":
+            lib.embed_readout(self.P["v"], self.P["W"], self.raw, self.P.get("pat"))
+        if self.mode != "neural":
             return self.mats, None
         Q = b.max_depth * b.n_paths
         per = self._buf("per", (3, Q), torch.float32)
@@ -111,7 +153,7 @@ class Calibrator:
         P = b.n_paths
         a = self._buf("a", (P,), torch.complex64)
         psi = self._buf("psi", (P,), torch.float32)
-        lib.trace_fields(self.radio, b, mats, a, psi)
+        lib.trace_fields_pat(self.radio, b, mats, self.pats, a, psi)
         lib.cfr(self.radio, b, a, psi, self.g, H_out)
         return mats, aux, a, psi
 
@@ -137,25 +179,64 @@ class Calibrator:
         dLdg = self._buf("dLdg", (M,), torch.complex64)
         lib.cfr_adjoint(self.radio, b, a, psi, self.g, H, dLda, dLdg,
                         self._ws(lib.RTC_OP_CFR_ADJOINT, L, P))
-        if self.mode == "per_id":
-            lib.trace_fields_adjoint(self.radio, b, mats, dLda, self.dparams, None,
-                                     self._ws(lib.RTC_OP_TRACE_FIELDS_ADJOINT, L, P,
-                                              self.raw.shape[0]))
+        op = (lib.RTC_OP_TRACE_FIELDS_ADJOINT_PAT if self.with_patterns
+              else lib.RTC_OP_TRACE_FIELDS_ADJOINT)
+        if self.mode != "neural":
+            draw = self.G["raw"] if self.mode == "per_id" else self.draw
+            lib.trace_fields_adjoint_pat(self.radio, b, mats, self.pats, dLda, draw, None,
+                                         self.G.get("tx"), self.G.get("pat"),
+                                         self._ws(op, L, P, self.raw.shape[0]))
+            if self.mode == "embed":
+                lib.embed_readout_backward(self.P["v"], self.P["W"], self.draw, self.G.get("pat"),
+                                           self.G["v"], self.G["W"])
         else:
             Q, saved, ws = aux
             dint = self._buf("dint", (3, Q), torch.float32)
-            lib.trace_fields_adjoint(self.radio, b, mats, dLda, None, dint, None)
-            lib.mlp_backward(self.net, Q, dint, saved, self.dparams, ws)
+            lib.trace_fields_adjoint_pat(self.radio, b, mats, self.pats, dLda, None, dint,
+                                         self.G.get("tx"), None,
+                                         self._ws(op, L, P) if self.n_vmf else None)
+            lib.mlp_backward(self.net, Q, dint, saved, self.G["mlp"], ws)
         self.dLdg = dLdg
         if not update:
             return loss
         self.t += 1
-        lr = self.lr if self.mode == "per_id" else self.lr_mlp
-        lib.adam_step(self.params, self.dparams, self.m_p, self.v_p, self.t, lr=lr)
+        n = self.n_main
+        lr = self.lr_mlp if self.mode == "neural" else self.lr
+        lib.adam_step(self.params[:n], self.dparams[:n], self.m_p[:n], self.v_p[:n], self.t, lr=lr)
+        if self.params.numel() > n:
+            lib.adam_step(self.params[n:], self.dparams[n:], self.m_p[n:], self.v_p[n:], self.t,
+                          lr=self.lr)
         if self.lr_gain > 0:
             lib.adam_step(self.g_real, torch.view_as_real(dLdg), self.m_g, self.v_g, self.t,
                           lr=self.lr_gain)
         return loss
+
+    def learned(self):
+        """Current materials, patterns and Tx gain as host values: dict with
+        eps_r, sigma, S [n_mat] (per_id, embed), K_x, w [n_mat, 3], lam2,
+        lam3 (with patterns) and eta, w_tx, lam_tx, mu_tx (with a Tx gain).
+        Only host arithmetic on copies of the device parameters."""
+        out = {}
+        if self.mode == "embed":
+            lib.embed_readout(self.P["v"], self.P["W"], self.raw, self.P.get("pat"))
+        if self.mode != "neural":
+            r = self.raw.double().cpu().numpy()
+            out.update(eps_r=1.0 + np.exp(r[:, 0]), sigma=np.exp(r[:, 1]),
+                       S=1.0 / (1.0 + np.exp(-r[:, 2])))
+        if "pat" in self.P:
+            q = self.P["pat"].double().cpu().numpy()
+            e = np.exp(q[:, 1:4] - q[:, 1:4].max(1, keepdims=True))
+            out.update(K_x=1.0 / (1.0 + np.exp(-q[:, 0])), w=e / e.sum(1, keepdims=True),
+                       lam2=np.exp(q[:, 4]), lam3=np.exp(q[:, 5]))
+        if self.n_vmf:
+            t = self.P["tx"].double().cpu().numpy()
+            K = self.n_vmf
+            e = np.exp(t[1:1 + K] - t[1:1 + K].max())
+            mu = t[1 + 2 * K:1 + 5 * K].reshape(K, 3)
+            out.update(eta=1.0 / (1.0 + np.exp(-t[0])), w_tx=e / e.sum(),
+                       lam_tx=np.exp(t[1 + K:1 + 2 * K]),
+                       mu_tx=mu / np.linalg.norm(mu, axis=1, keepdims=True))
+        return out
 
     def nmse(self, links, chunk=512):
         """Held-out CFR NMSE = sum|H - H*|^2 / sum|H*|^2 over `links`."""

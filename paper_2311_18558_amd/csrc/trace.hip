@@ -317,7 +317,9 @@ struct Chain {
   PatEval pe;
 };
 
-template <int MAXD, bool SAVE>
+// PAT: the trainable Tx gain and scattering patterns are compiled in (the
+// plain chain keeps its register budget without them).
+template <int MAXD, bool SAVE, bool PAT>
 RTC_DEV void run_chain(const TraceArgs& A, const MatVal* tab, const VmfTab* vt, const PatVal* ptab,
                        int64_t p, Chain<MAXD, SAVE>& C) {
   int l = find_link(A.link_off, A.n_links, p);
@@ -336,7 +338,7 @@ RTC_DEV void run_chain(const TraceArgs& A, const MatVal* tab, const VmfTab* vt, 
   float2 E0 = make_float2(A.cz_tx, 0.0f);
   float2 E1 = make_float2(A.sz_tx, 0.0f);
   C.G = 1.0f;
-  if (A.n_vmf > 0) {
+  if (PAT && A.n_vmf > 0) {
     C.G = vmf_gain(*vt, k1);
     const float sg = sqrtf(fmaxf(C.G, 0.0f));
     E0.x *= sg;
@@ -371,7 +373,7 @@ RTC_DEV void run_chain(const TraceArgs& A, const MatVal* tab, const VmfTab* vt, 
         v3 k_s = unit3(sub3(rx, s));
         float f = fmaxf(dot3(k_s, nf), 0.0f) * kInvPi;  // Lambertian
         float kx = 0.0f;
-        if (A.pat_raw) {
+        if (PAT && A.pat_raw) {
           C.pid = pat_id(A, slot);
           C.pv = ptab[C.pid];
           C.pe = eval_pattern(C.pv, k_in, k_s, nf, c);
@@ -461,17 +463,17 @@ RTC_DEV TraceLds trace_lds(const TraceArgs& A, unsigned char* smem) {
   return L;
 }
 
-template <int MAXD>
+template <int MAXD, bool PAT>
 __global__ void __launch_bounds__(kTraceBlock) trace_fields_kernel(TraceArgs A, float2* a,
                                                                     float* psi) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_f[];
   const TraceLds Ls = trace_lds(A, smem_f);
   stage_materials(A, Ls.tab);
-  stage_patterns(A, Ls.vt, Ls.pt);
+  if constexpr (PAT) stage_patterns(A, Ls.vt, Ls.pt);
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= A.n_paths) return;
   Chain<MAXD, false> C;
-  run_chain<MAXD, false>(A, Ls.tab, Ls.vt, Ls.pt, p, C);
+  run_chain<MAXD, false, PAT>(A, Ls.tab, Ls.vt, Ls.pt, p, C);
   // C_R^H E with a real (isotropic, slant zeta) Rx pattern
   float2 recv = cadd(cscale(C.E0, A.cz_rx), cscale(C.E1, A.sz_rx));
   if (a) a[p] = cscale(recv, C.scale);
@@ -492,7 +494,7 @@ struct GradLayout {
   int mat, pat, tx, stride;  // offsets of the sections (-1 absent), row length
 };
 
-template <int MAXD, bool PER_ID>
+template <int MAXD, bool PER_ID, bool PAT>
 __global__ void __launch_bounds__(kTraceBlock)
     trace_fields_adjoint_kernel(TraceArgs A, const float2* dLda, float* dLd_inter,
                                 double* block_part, GradLayout GL) {
@@ -501,7 +503,7 @@ __global__ void __launch_bounds__(kTraceBlock)
   MatVal* tab = Ls.tab;
   double* acc = Ls.acc;
   stage_materials(A, tab);
-  stage_patterns(A, Ls.vt, Ls.pt);
+  if constexpr (PAT) stage_patterns(A, Ls.vt, Ls.pt);
   if (GL.stride > 0) {
     for (int i = threadIdx.x; i < GL.stride * (int)(blockDim.x >> 6); i += blockDim.x) acc[i] = 0.0;
     __syncthreads();
@@ -532,11 +534,11 @@ __global__ void __launch_bounds__(kTraceBlock)
     }
     if (valid) {
       Chain<MAXD, true> C;
-      run_chain<MAXD, true>(A, tab, Ls.vt, Ls.pt, p, C);
+      run_chain<MAXD, true, PAT>(A, tab, Ls.vt, Ls.pt, p, C);
       Q = C.Q;
       float2 Ga = dLda[p];
       k1 = C.k1;
-      if (GL.tx >= 0 && C.G > 0.0f) {
+      if (PAT && GL.tx >= 0 && C.G > 0.0f) {
         // a is proportional to sqrt(G): dL/dG = Re(conj(a) dL/da) / (2 G)
         const float2 recv = cadd(cscale(C.E0, A.cz_rx), cscale(C.E1, A.sz_rx));
         const float2 av = cscale(recv, C.scale);
@@ -559,11 +561,11 @@ __global__ void __launch_bounds__(kTraceBlock)
           // K (qR0 sqrt(1 - K_x) + qR1 sqrt(K_x)) |E_s|
           const float qR0 = A.cz_rx * C.Dq[0] + A.sz_rx * C.Dq[2];
           const float qR1 = A.cz_rx * C.Dq[1] + A.sz_rx * C.Dq[3];
-          const float kx = A.pat_raw ? C.pv.kx : 0.0f;
+          const float kx = (PAT && A.pat_raw) ? C.pv.kx : 0.0f;
           const float sk0 = sqrtf(1.0f - kx), sk1 = sqrtf(kx);
           const float qR = qR0 * sk0 + qR1 * sk1;
           const float gam = Ga.x * K * qR;
-          if (GL.pat >= 0) {
+          if (PAT && GL.pat >= 0) {
             // d a/du_kx with K_x = logistic(u): K |E_s| K_x (1 - K_x)
             //   (-qR0 / (2 sqrt(1 - K_x)) + qR1 / (2 sqrt(K_x)))
             const float As = C.mv[j].S * C.G0 * C.nv;
@@ -685,7 +687,7 @@ __global__ void __launch_bounds__(kTraceBlock)
         }
       }
     }
-    if (GL.pat >= 0) {
+    if (PAT && GL.pat >= 0) {
       // the same deterministic walk over the pattern ids of the wave
       double* wacc = acc + wave * GL.stride + GL.pat;
       bool done = !valid || pat_m == 0x7fffffff;
@@ -703,7 +705,7 @@ __global__ void __launch_bounds__(kTraceBlock)
         if (mine) done = true;
       }
     }
-    if (GL.tx >= 0) {
+    if (PAT && GL.tx >= 0) {
       // natural Tx gradients of this path, summed over the wave in order:
       //   eta: G/eta,  w_i: eta c_i e_i,  lam_i: eta w_i c_i e_i ((mu_i.k - 1)
       //   + d ln c_i/d lam_i),  mu_i: eta w_i c_i e_i lam_i k
@@ -952,11 +954,16 @@ extern "C" rtc_status rtc_trace_fields_pat(const rtc_radio* radio, const rtc_pat
   dim3 grid((paths->n_paths + kTraceBlock - 1) / kTraceBlock);
   size_t shm = trace_lds_fixed(A);
   hipStream_t s = as_stream(stream);
+  const bool pat = A.n_vmf > 0 || A.pat_raw != nullptr;
   switch (depth_bucket(paths->max_depth)) {
 #define RTC_CASE(D)                                                                          \
   case D:                                                                                    \
-    hipLaunchKernelGGL(trace_fields_kernel<D>, grid, dim3(kTraceBlock), shm, s, A,           \
-                       reinterpret_cast<float2*>(a), psi);                                   \
+    if (pat)                                                                                 \
+      hipLaunchKernelGGL((trace_fields_kernel<D, true>), grid, dim3(kTraceBlock), shm, s, A, \
+                         reinterpret_cast<float2*>(a), psi);                                 \
+    else                                                                                     \
+      hipLaunchKernelGGL((trace_fields_kernel<D, false>), grid, dim3(kTraceBlock), shm, s,   \
+                         A, reinterpret_cast<float2*>(a), psi);                              \
     break;
     RTC_CASE(1)
     RTC_CASE(2)
@@ -1021,16 +1028,26 @@ extern "C" rtc_status rtc_trace_fields_adjoint_pat(
   RTC_REQUIRE(shm <= 160 * 1024, RTC_ERR_RANGE,
               "%s: %zu bytes of LDS needed (too many materials for the gradients asked)", fn, shm);
   double* part = reinterpret_cast<double*>(ws);
+  const float2* g_a = reinterpret_cast<const float2*>(dLda);
+  // the pattern code is compiled in only when the forward used patterns
+  const bool pat = A.n_vmf > 0 || A.pat_raw != nullptr;
   switch (depth_bucket(paths->max_depth)) {
-#define RTC_CASE(D)                                                                            \
-  case D:                                                                                      \
-    if (per_id)                                                                                \
-      hipLaunchKernelGGL((trace_fields_adjoint_kernel<D, true>), dim3(blocks), dim3(kTraceBlock), \
-                         shm, s, A, reinterpret_cast<const float2*>(dLda), nullptr, part, GL); \
-    else                                                                                       \
-      hipLaunchKernelGGL((trace_fields_adjoint_kernel<D, false>), dim3(blocks),                \
-                         dim3(kTraceBlock), shm, s, A, reinterpret_cast<const float2*>(dLda),  \
-                         dLd_inter, part, GL);                                                 \
+#define RTC_LAUNCH(D, ID, PAT, DINT)                                                          \
+  hipLaunchKernelGGL((trace_fields_adjoint_kernel<D, ID, PAT>), dim3(blocks), dim3(kTraceBlock), \
+                     shm, s, A, g_a, DINT, part, GL)
+#define RTC_CASE(D)                                                                           \
+  case D:                                                                                     \
+    if (per_id) {                                                                             \
+      if (pat)                                                                                \
+        RTC_LAUNCH(D, true, true, nullptr);                                                   \
+      else                                                                                    \
+        RTC_LAUNCH(D, true, false, nullptr);                                                  \
+    } else {                                                                                  \
+      if (pat)                                                                                \
+        RTC_LAUNCH(D, false, true, dLd_inter);                                                \
+      else                                                                                    \
+        RTC_LAUNCH(D, false, false, dLd_inter);                                               \
+    }                                                                                         \
     break;
     RTC_CASE(1)
     RTC_CASE(2)
@@ -1039,6 +1056,7 @@ extern "C" rtc_status rtc_trace_fields_adjoint_pat(
     RTC_CASE(6)
     RTC_CASE(8)
 #undef RTC_CASE
+#undef RTC_LAUNCH
   }
   if ((st = check_launch(fn)) != RTC_OK) return st;
   if (GL.stride > 0) {

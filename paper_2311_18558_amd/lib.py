@@ -67,6 +67,9 @@ _SIGS = {
     "rtc_trace_fields_pat": (ctypes.c_int, [ctypes.POINTER(Radio), ctypes.POINTER(Paths),
                                             ctypes.POINTER(Materials), ctypes.POINTER(Patterns),
                                             c_vp, c_vp, c_vp]),
+    "rtc_embed_readout": (ctypes.c_int, [c_i32, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "rtc_embed_readout_backward": (ctypes.c_int, [c_i32, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp,
+                                                  c_vp, c_vp]),
     "rtc_trace_fields_adjoint_pat": (ctypes.c_int, [ctypes.POINTER(Radio), ctypes.POINTER(Paths),
                                                     ctypes.POINTER(Materials),
                                                     ctypes.POINTER(Patterns), c_vp, c_vp, c_vp,
@@ -253,6 +256,21 @@ def trace_fields_adjoint_pat(radio, paths, mats, pats, dLda, dLd_raw, dLd_inter,
         None if pats is None else ctypes.byref(pats), _ptr(dLda), _ptr(dLd_raw), _ptr(dLd_inter),
         _ptr(dLd_tx), _ptr(dLd_pat), _ptr(ws), 0 if ws is None else ws.numel(), _stream(stream)),
         "rtc_trace_fields_adjoint_pat")
+
+
+def embed_readout(v, W, raw, pat_raw=None, stream=None):
+    """v float32 [L], W float32 [n_mat, 4, L] -> raw [n_mat, 3] (and column 0
+    of pat_raw [n_mat, 6], the K_x logit)."""
+    n_mat, _, L = W.shape
+    _check(load().rtc_embed_readout(n_mat, L, _ptr(v), _ptr(W), _ptr(raw), _ptr(pat_raw),
+                                    _stream(stream)), "rtc_embed_readout")
+
+
+def embed_readout_backward(v, W, dLd_raw, dLd_pat, dLd_v, dLd_W, stream=None):
+    n_mat, _, L = W.shape
+    _check(load().rtc_embed_readout_backward(n_mat, L, _ptr(v), _ptr(W), _ptr(dLd_raw),
+                                             _ptr(dLd_pat), _ptr(dLd_v), _ptr(dLd_W),
+                                             _stream(stream)), "rtc_embed_readout_backward")
 
 
 def cfr(radio, paths, a, psi, g, H, stream=None):

@@ -39,6 +39,27 @@ def sample_triangles(scene, per_tri, rng):
             face.astype(np.int64), np.repeat(area / per_tri, per_tri))
 
 
+def sample_triangles_density(scene, density, rng):
+    """Stratified points on every triangle of a Scene, about `density` per
+    square metre (at least one per triangle); each stands for an equal
+    share of its triangle's area.  Same outputs as sample_triangles."""
+    a, b, c = scene.tri[:, 0], scene.tri[:, 1], scene.tri[:, 2]
+    area = 0.5 * np.linalg.norm(np.cross(b - a, c - a), axis=1)
+    cnt = np.maximum(1, np.round(area * density).astype(np.int64))
+    out_p, out_f, out_dA = [], [], []
+    for t in range(scene.n_tri):
+        n = int(cnt[t])
+        r1 = (np.arange(n) + rng.uniform(size=n)) / n
+        r2 = rng.uniform(size=n)
+        sq = np.sqrt(r1)[:, None]
+        out_p.append((1 - sq) * a[t] + sq * (1 - r2[:, None]) * b[t] + sq * r2[:, None] * c[t])
+        out_f.append(np.full(n, scene.tri_face[t], np.int64))
+        out_dA.append(np.full(n, area[t] / n))
+    face = np.concatenate(out_f)
+    return (np.concatenate(out_p), scene.face_normal[face], scene.face_mat[face].astype(np.int64),
+            face, np.concatenate(out_dA))
+
+
 def sample_floor(plan, density, rng):
     """Stratified jittered grid on every face of a FloorPlan (wall box sides,
     floor and ceiling), about `density` points per square metre (at least
@@ -127,17 +148,25 @@ def visible_floor(plan, pts, a, eps=1e-6):
 def add_diffuse(store, tx, samples, visible_fn, max_links_chunk=64):
     """A new store with every link's single-bounce diffuse paths appended
     after its specular paths.  samples = (pts, nrm, mat, face, dA) from a
-    sampler; visible_fn(pts, endpoint) -> bool per point."""
+    sampler; visible_fn(pts, endpoint) -> bool per point.  tx: the common
+    Tx position of all links, or None to take each link's own."""
     pts, nrm, mat, face, dA = samples
-    tx = np.asarray(tx, np.float64)
     rx_all = store.rx_pos.astype(np.float64)
     L = store.n_links
-    # Tx side: same for every link
-    tx_rep = np.repeat(tx[None], len(pts), 0)
-    vis_tx = visible_fn(pts, tx)
+    per_tx = tx is None
+    if per_tx:
+        tx_all = store.tx_pos.astype(np.float64)
+    else:
+        # Tx side: same for every link
+        tx = np.asarray(tx, np.float64)
+        tx_all = np.repeat(tx[None], L, 0)
+        vis_tx = visible_fn(pts, tx)
     per_link = []
     for l in range(L):
         rx = rx_all[l]
+        if per_tx:
+            vis_tx = visible_fn(pts, tx_all[l])
+        tx_rep = np.repeat(tx_all[l][None], len(pts), 0)
         cand = vis_tx & _same_side(pts, nrm, tx_rep, np.repeat(rx[None], len(pts), 0))
         idx = np.nonzero(cand)[0]
         if len(idx):
@@ -188,7 +217,8 @@ def add_diffuse(store, tx, samples, visible_fn, max_links_chunk=64):
     P_face[dst_d] = face[didx]
     s = pts[didx]
     rx_d = rx_all[dlink]
-    tau[dst_d] = (np.linalg.norm(s - tx[None], axis=1) + np.linalg.norm(rx_d - s, axis=1)) / C0
+    tx_d = tx_all[dlink]
+    tau[dst_d] = (np.linalg.norm(s - tx_d, axis=1) + np.linalg.norm(rx_d - s, axis=1)) / C0
     return PathStore(n_links=L, n_paths=P, max_depth=D, link_off=off, tx_pos=store.tx_pos.copy(),
                      rx_pos=store.rx_pos.copy(), depth=depth, kind=kind, pts=P_pts, nrm=P_nrm,
                      mat=P_mat, dA=P_dA, tau=tau, face=P_face)

@@ -12,6 +12,14 @@
             plus single-bounce Lambertian diffuse paths from stratified
             surface samples (~0.35 per m^2), ~2,000 paths per link; 4,096
             subcarriers over 100 MHz at 3.5 GHz, 32-element ULA
+  recovery  stand-in for the synthetic dataset of Sec. IV-B: a straight
+            hallway 24 x 6 x 3 m (floor, walls and ceiling as three
+            materials), one Rx antenna near one end at 2 m, 256 Tx at random
+            points; specular paths up to third order plus single-bounce
+            diffuse paths from ~1 sample per m^2 of surface; 1,024
+            subcarriers over 50 MHz at 3.438 GHz; ground truth of Table I
+            with the backscattering-lobe pattern (alpha_r = 5, alpha_s = 8,
+            Lambda = 0.8) and a three-lobe Tx gain
   adjoint   the scale floor and paths with hidden ground truth:
             materials with S ~ U[0, 0.5] and 32 complex element gains;
             14,336 training / 2,048 held-out Rx
@@ -25,7 +33,7 @@ from . import imagemethod
 from .floorplan import indoor_floor
 from .params import Radio, draw_gains, draw_materials, materials_to_raw
 from .pathfind import find_store
-from .scene import box_room, uniform_points_in_box
+from .scene import SceneBuilder, box_room, uniform_points_in_box
 from .store import PathStore
 
 # Floor recipe of the scale workload: two rooms with wide openings.  With
@@ -156,3 +164,56 @@ def learned(seed=3, n_rx=16384, **kw) -> Workload:
     w.name = "learned"
     w.meta["per_inter"] = spatial_field(w.store, w.meta["plan"], w.raw, seed + 11, w.aabb)
     return w
+
+
+# Table I of the paper: floor (concrete), walls (plasterboard), ceiling
+# (ceiling board); columns eps_r, sigma [S/m], S, K_x.
+TABLE_I = np.array([[5.24, 0.121, 0.3, 0.2],
+                    [2.73, 0.027, 0.5, 0.4],
+                    [1.48, 0.004, 0.8, 0.3]])
+# Backscattering-lobe pattern of the synthetic dataset: alpha_r, alpha_s, Lambda
+RECOVERY_LOBES = (5, 8, 0.8)
+# Ground-truth Tx gain, a member of the trainable family (M = 3): radiation
+# efficiency 0.9, weights (0.6, 0.25, 0.15), concentrations (6, 2, 10) and
+# mean directions along the hallway, upwards and across it.
+RECOVERY_TX = dict(eta=0.9, w=(0.6, 0.25, 0.15), lam=(6.0, 2.0, 10.0),
+                   mu=((-1.0, 0.0, 0.0), (0.0, 0.0, 1.0), (0.6, 0.8, 0.0)))
+
+
+def vmf_to_raw(eta, w, lam, mu):
+    """Raw Tx-gain vector [1 + 5M] (logistic, softmax logits, log, 3-vectors)."""
+    w = np.asarray(w, np.float64)
+    mu = np.asarray(mu, np.float64)
+    return np.concatenate([[np.log(eta / (1.0 - eta))], np.log(w), np.log(lam),
+                           mu.reshape(-1)]).astype(np.float32)
+
+
+def hallway_scene(size=(24.0, 6.0, 3.0)):
+    """Straight hallway [0,sx]x[0,sy]x[0,sz]: material 0 the floor, 1 the
+    four walls, 2 the ceiling."""
+    b = SceneBuilder()
+    b.add_box((0.0, 0.0, 0.0), size, 1)
+    sc = b.build(n_mat=3)
+    nz = sc.face_normal[:, 2]
+    sc.face_mat = np.where(nz > 0.5, 0, np.where(nz < -0.5, 2, 1)).astype(np.int32)
+    return sc
+
+
+def recovery(seed=7, n_tx=256, size=(24.0, 6.0, 3.0), density=1.0, max_depth=3, n_sc=1024,
+             fc=3.438e9, bandwidth=50e6) -> Workload:
+    rng = np.random.default_rng(seed)
+    scene = hallway_scene(size)
+    rx = np.array([1.0, size[1] / 2, 2.0])
+    txs = np.stack([rng.uniform(0.5, size[0] - 0.5, n_tx), rng.uniform(0.5, size[1] - 0.5, n_tx),
+                    rng.uniform(0.5, 2.5, n_tx)], 1)
+    links = [imagemethod.find_paths(scene, t, rx, max_depth) for t in txs]
+    spec = imagemethod.pack(links, list(txs), [rx] * n_tx, max_depth)
+    samples = _diffuse.sample_triangles_density(scene, density, rng)
+    # a convex room: every sample point sees every Tx and the Rx
+    store = _diffuse.add_diffuse(spec, None, samples, lambda p, e: np.ones(len(p), bool))
+    raw = materials_to_raw(TABLE_I[:, 0], TABLE_I[:, 1], TABLE_I[:, 2])
+    radio = Radio(fc=fc, bandwidth=bandwidth, n_sc=n_sc, n_elem=1)
+    meta = dict(kx=TABLE_I[:, 3].copy(), lobes=RECOVERY_LOBES, n_vmf=3,
+                tx_raw=vmf_to_raw(**RECOVERY_TX), table=TABLE_I.copy())
+    return Workload("recovery", store, radio, raw, np.ones(1, np.complex64),
+                    (scene.aabb_min, scene.aabb_max), meta)

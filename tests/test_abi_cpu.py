@@ -179,3 +179,18 @@ def test_pattern_argument_checks(lib):
     n0 = lib.workspace_size(lib.RTC_OP_TRACE_FIELDS_ADJOINT, r, 4, 1000, 3)
     n1 = lib.workspace_size(lib.RTC_OP_TRACE_FIELDS_ADJOINT_PAT, r, 4, 1000, 3)
     assert n1 > n0 > 0
+
+
+def test_embed_argument_checks(lib):
+    so = lib.load()
+    q = ctypes.c_void_p(16)
+    st = so.rtc_embed_readout(0, 30, q, q, q, None, None)
+    assert st == -3 and b"n_mat" in so.rtc_last_error()
+    st = so.rtc_embed_readout(3, 1025, q, q, q, None, None)
+    assert st == -3 and b"L must" in so.rtc_last_error()
+    st = so.rtc_embed_readout(3, 30, None, q, q, None, None)
+    assert st == -1
+    st = so.rtc_embed_readout(3, 30, q, q, None, None, None)
+    assert st == -1 and b"raw" in so.rtc_last_error()
+    st = so.rtc_embed_readout_backward(3, 30, q, q, None, None, q, q, None)
+    assert st == -1 and b"dLd_raw" in so.rtc_last_error()
