@@ -1,0 +1,244 @@
+"""Pins of the oracle's edge diffraction (Sec. II-E, the UTD of Kouyoumjian
+and Pathak with Luebbers' finite-conductivity coefficients): the transition
+function against a Fourier-integral quadrature and its small/large-argument
+forms, Sommerfeld's exact half-plane solution, Keller's closed-form limit,
+continuity of the total field across shadow and reflection boundaries
+(perfect and lossy wedges), reciprocity, the three-dimensional dyadic
+against the scalar forms, and central differences in the face materials."""
+import math
+
+import numpy as np
+import pytest
+import torch
+from scipy.integrate import quad
+
+from oracle import diffraction as dif
+from oracle.em import fresnel
+
+f64 = torch.float64
+c128 = torch.complex128
+
+
+def _c(z):
+    return torch.tensor(complex(z), dtype=c128)
+
+
+def _tail_quad(x):
+    """int_{sqrt(x)}^inf e^{-j t^2} dt = int_x^inf e^{-j v} / (2 sqrt(v)) dv
+    by QUADPACK's Fourier-integral rule."""
+    f = lambda v: 0.5 / math.sqrt(v)  # noqa: E731
+    re, _ = quad(f, x, np.inf, weight="cos", wvar=1.0)
+    im, _ = quad(f, x, np.inf, weight="sin", wvar=1.0)
+    return re - 1j * im
+
+
+@pytest.mark.parametrize("x", [0.05, 0.7, 2.0, 9.0, 40.0])
+def test_transition_function_against_quadrature(x):
+    ref = 2j * math.sqrt(x) * np.exp(1j * x) * _tail_quad(x)
+    got = complex(dif.transition_function(torch.tensor([x], dtype=f64))[0])
+    assert abs(got - ref) <= 1e-8 * abs(ref)  # QUADPACK reaches ~1e-9
+
+
+def test_transition_function_limits():
+    # large argument: F ~ 1 + j/(2x) - 3/(4x^2) - 15j/(8x^3)
+    for x in (300.0, 3000.0):
+        got = complex(dif.transition_function(torch.tensor([x], dtype=f64))[0])
+        ref = 1 + 0.5j / x - 0.75 / x ** 2 - 15j / (8 * x ** 3)
+        assert abs(got - ref) <= 2.0 * 105 / (16 * x ** 4) + 1e-12  # + the tail's rounding
+    # small argument: F ~ [sqrt(pi x) - 2 x e^{j pi/4} - (2/3) x^2 e^{-j pi/4}] e^{j(pi/4 + x)}
+    for x in (1e-4, 1e-3):
+        got = complex(dif.transition_function(torch.tensor([x], dtype=f64))[0])
+        ref = ((math.sqrt(math.pi * x) - 2 * x * np.exp(1j * math.pi / 4)
+                - (2.0 / 3.0) * x ** 2 * np.exp(-1j * math.pi / 4)) * np.exp(1j * (math.pi / 4 + x)))
+        assert abs(got - ref) <= 2.0 * x ** 2.5
+    assert complex(dif.transition_function(torch.tensor([0.0], dtype=f64))[0]) == 0
+
+
+def _G(a):
+    """Sommerfeld's Fresnel-integral factor (e^{j pi/4}/sqrt(pi)) int_a^inf
+    e^{-j t^2} dt for real a (1 deep in the lit region, 0 in the shadow)."""
+    full = math.sqrt(math.pi) * np.exp(-1j * math.pi / 4)
+    t = _tail_quad(a * a) if a != 0 else full / 2
+    val = t if a >= 0 else full - t
+    return np.exp(1j * math.pi / 4) / math.sqrt(math.pi) * val
+
+
+def _half_plane_exact(k_rho, phi, phi_p, sign):
+    """Exact total field of a perfectly conducting half-plane (face at
+    phi = 0 and 2 pi) under a unit plane wave from phi_p; sign = -1 soft,
+    +1 hard; time convention e^{+j w t}."""
+    rt = math.sqrt(2 * k_rho)
+    ui = np.exp(1j * k_rho * math.cos(phi - phi_p)) * _G(-rt * math.cos((phi - phi_p) / 2))
+    ur = np.exp(1j * k_rho * math.cos(phi + phi_p)) * _G(-rt * math.cos((phi + phi_p) / 2))
+    return ui + sign * ur
+
+
+def _go_2d(k, rho, phi, phi_p, n, gamma0, gamman):
+    """Geometrical optics under a unit plane wave from phi_p: the incident
+    wave and the reflections from face 0 and face n where they exist."""
+    u = 0j
+    if abs(phi - phi_p) < math.pi:
+        u += np.exp(1j * k * rho * math.cos(phi - phi_p))
+    if phi + phi_p < math.pi:  # reflection from face 0
+        u += complex(gamma0) * np.exp(1j * k * rho * math.cos(phi + phi_p))
+    if phi + phi_p > (2 * n - 1) * math.pi:  # reflection from face n
+        u += complex(gamman) * np.exp(1j * k * rho * math.cos(2 * n * math.pi - phi - phi_p))
+    return u
+
+
+def _utd_total_2d(k, rho, phi, phi_p, n, R0, Rn):
+    """UTD total field in a plane normal to the edge under a unit plane wave:
+    geometrical optics with the face coefficients R0, Rn plus the diffracted
+    field D e^{-j k rho} / sqrt(rho) with L = rho."""
+    u = _go_2d(k, rho, phi, phi_p, n, R0, Rn)
+    D = dif.utd_coefficients(phi, phi_p, math.pi / 2, rho, float(n), k, _c(R0), _c(Rn))
+    return u + complex(D) * np.exp(-1j * k * rho) / math.sqrt(rho)
+
+
+@pytest.mark.parametrize("sign", [-1.0, 1.0])
+def test_half_plane_against_sommerfeld(sign):
+    """n = 2, perfect conductor, plane-wave incidence: there the UTD total
+    field is the exact solution, near the shadow and reflection boundaries
+    too (agreement to the quadrature's accuracy, ~1e-6; a wrong sign, index
+    or argument anywhere in D leaves errors of order 0.1)."""
+    k = 1.0
+    phi_p = 1.0
+    phis = [0.3, 1.0, 1.9, 2.13, 2.2, 3.0, 4.0, 4.12, 4.2, 5.5, 6.1]
+    errs = []
+    for k_rho in (50.0, 800.0):
+        e = max(abs(_utd_total_2d(k, k_rho, ph, phi_p, 2.0, sign, sign)
+                    - _half_plane_exact(k_rho, ph, phi_p, sign)) for ph in phis)
+        errs.append(e)
+    assert max(errs) <= 1e-5, errs
+
+
+@pytest.mark.parametrize("n", [1.5, 1.8])
+def test_far_from_boundaries_gtd_limit(n):
+    k = 50.0
+    L = 1e5
+    for phi, phi_p in ((0.4, 2.2), (2.5, 0.3), (n * math.pi - 0.2, 1.1)):
+        for R0, Rn in ((-1.0, -1.0), (1.0, 1.0), (0.3 - 0.2j, -0.5 + 0.1j)):
+            u = dif.utd_coefficients(phi, phi_p, 1.1, L, n, k, _c(R0), _c(Rn))
+            g = dif.gtd_coefficients(phi, phi_p, 1.1, n, k, _c(R0), _c(Rn))
+            assert abs(complex(u) / complex(g) - 1) <= 1e-4
+
+
+@pytest.mark.parametrize("n", [1.5, 1.75, 2.0])
+@pytest.mark.parametrize("pol", ["soft", "hard", "lossy_soft", "lossy_hard"])
+def test_total_field_continuous_across_boundaries(n, pol):
+    """Geometrical optics jumps at the incident shadow boundary phi = phi' +
+    pi and at the reflection boundary phi = pi - phi'; the diffracted field
+    jumps by the opposite amount.  For the lossy wedge the reflected field
+    carries the Fresnel coefficient at the grazing angle phi', the one
+    Luebbers' R0 uses."""
+    k, rho, phi_p = 2.0, 7.0, 0.9
+    if pol.startswith("lossy"):
+        eta = torch.tensor(4.0 - 0.7j, dtype=c128)
+        rs, rh = fresnel(eta, torch.tensor(math.sin(phi_p), dtype=f64))
+        R0 = complex(rs if pol == "lossy_soft" else rh)
+        Rn = -1.0 if pol == "lossy_soft" else 1.0
+    else:
+        R0 = Rn = -1.0 if pol == "soft" else 1.0
+    for b in (phi_p + math.pi, math.pi - phi_p):
+        if b >= n * math.pi:
+            continue
+        d = 1e-7
+        lo = _utd_total_2d(k, rho, b - d, phi_p, n, R0, Rn)
+        hi = _utd_total_2d(k, rho, b + d, phi_p, n, R0, Rn)
+        assert abs(hi - lo) <= 1e-4, (b, abs(hi - lo))
+        # while the diffracted field alone jumps by order one there
+        dlo = lo - _go_2d(k, rho, b - d, phi_p, n, R0, Rn)
+        dhi = hi - _go_2d(k, rho, b + d, phi_p, n, R0, Rn)
+        assert abs(dhi - dlo) >= 0.1
+
+
+def test_reciprocity_perfect_conductor():
+    k, L = 3.0, 4.0
+    for n in (1.5, 2.0):
+        for phi, phi_p in ((0.3, 2.0), (1.2, 3.9), (4.0, 0.5)):
+            if max(phi, phi_p) >= n * math.pi:
+                continue
+            for R in (-1.0, 1.0):
+                a = dif.utd_coefficients(phi, phi_p, 0.8, L, n, k, _c(R), _c(R))
+                b = dif.utd_coefficients(phi_p, phi, 0.8, L, n, k, _c(R), _c(R))
+                assert abs(complex(a) - complex(b)) <= 1e-12 * abs(complex(a))
+
+
+def test_dyadic_matches_scalar_forms():
+    """Normal incidence on an edge along z: the diffracted E_z is D_s times
+    the incident E_z (soft), and the diffracted H_z = (s x E)/eta0 . z is D_h
+    times the incident H_z (hard)."""
+    e = torch.tensor([0.0, 0.0, 1.0], dtype=f64)
+    n0 = torch.tensor([0.0, 1.0, 0.0], dtype=f64)  # face 0 along +x, free space above
+    q = torch.zeros(3, dtype=f64)
+    src = torch.tensor([-3.0, 4.0, 0.0], dtype=f64)
+    obs = torch.tensor([-2.0, -1.5, 0.0], dtype=f64)
+    geo = dif.edge_geometry(src, q, obs, e, n0)
+    assert abs(geo["phi_p"].item() - math.atan2(4.0, -3.0)) < 1e-12
+    assert abs(geo["phi"].item() - (2 * math.pi + math.atan2(-1.5, -2.0))) < 1e-12
+    n = 2.0
+    k = 10.0
+    eta = torch.tensor(5.0 - 1.0j, dtype=c128)
+    # incident field in an arbitrary basis transverse to s_in
+    s_in = geo["s_in"]
+    p_out = torch.cross(s_in, e, dim=-1)
+    p_out = p_out / torch.linalg.norm(p_out)
+    q_out = torch.cross(s_in, p_out, dim=-1)
+    for Ein in (torch.tensor([1.0 + 0j, 0j], dtype=c128), torch.tensor([0j, 1.0 + 0j], dtype=c128)):
+        E_out, Ds, Dh = dif.diffraction_step(Ein, p_out, q_out, geo, n, k, eta, eta)
+        vin = Ein[0] * p_out.to(c128) + Ein[1] * q_out.to(c128)
+        vout = E_out[0] * geo["beta_out"].to(c128) + E_out[1] * geo["phi_out"].to(c128)
+        assert abs(complex(vout[2]) - complex(Ds * vin[2])) <= 1e-12
+        h_in = torch.cross(s_in.to(c128), vin, dim=-1)[2]
+        h_out = torch.cross(geo["s_out"].to(c128), vout, dim=-1)[2]
+        assert abs(complex(h_out) - complex(Dh * h_in)) <= 1e-12
+
+
+def test_keller_cone_and_oblique_angles():
+    """A point on the edge where the rays make equal angles with it (Keller's
+    principle of the shortest path) gives s'.e = s.e."""
+    e = torch.tensor([0.0, 0.0, 1.0], dtype=f64)
+    n0 = torch.tensor([1.0, 0.0, 0.0], dtype=f64)
+    src = torch.tensor([3.0, 1.0, 0.5], dtype=f64)
+    obs = torch.tensor([-2.0, -4.0, 2.5], dtype=f64)
+    d1 = math.hypot(3.0, 1.0)
+    d2 = math.hypot(2.0, 4.0)
+    z = 0.5 + (2.5 - 0.5) * d1 / (d1 + d2)
+    geo = dif.edge_geometry(src, torch.tensor([0.0, 0.0, z], dtype=f64), obs, e, n0)
+    assert abs(torch.dot(geo["s_in"], e).item() - torch.dot(geo["s_out"], e).item()) < 1e-12
+    # the edge-fixed bases are orthonormal and transverse
+    for b, p, s in ((geo["beta_in"], geo["phi_in"], geo["s_in"]),
+                    (geo["beta_out"], geo["phi_out"], geo["s_out"])):
+        M = torch.stack([b, p, s])
+        assert torch.allclose(M @ M.T, torch.eye(3, dtype=f64), atol=1e-12)
+
+
+def test_face_material_gradients_central_differences():
+    e = torch.tensor([0.0, 0.0, 1.0], dtype=f64)
+    n0 = torch.tensor([0.0, 1.0, 0.0], dtype=f64)
+    geo = dif.edge_geometry(torch.tensor([-3.0, 4.0, 0.4], dtype=f64), torch.zeros(3, dtype=f64),
+                            torch.tensor([-2.0, -1.5, 1.1], dtype=f64), e, n0)
+    n, k = 1.5, 20.0
+    assert 0 < geo["phi_p"].item() < n * math.pi and 0 < geo["phi"].item() < n * math.pi
+    p_out = torch.tensor([0.0, 0.0, 1.0], dtype=f64)
+    q_out = torch.cross(geo["s_in"], p_out, dim=-1)
+    q_out = q_out / torch.linalg.norm(q_out)
+    p_out = torch.cross(q_out, geo["s_in"], dim=-1)
+    Ein = torch.tensor([0.6 + 0.2j, -0.3 + 0.5j], dtype=c128)
+    w = torch.tensor([0.7 - 0.4j, 0.2 + 0.9j], dtype=c128)
+
+    def f(e0, en):
+        E, _, _ = dif.diffraction_step(Ein, p_out, q_out, geo, n, k,
+                                       torch.complex(e0, torch.tensor(-0.8, dtype=f64)),
+                                       torch.complex(en, torch.tensor(-0.3, dtype=f64)))
+        return (w.conj() * E).sum().real
+
+    e0 = torch.tensor(4.0, dtype=f64, requires_grad=True)
+    en = torch.tensor(2.5, dtype=f64, requires_grad=True)
+    g0, gn = torch.autograd.grad(f(e0, en), (e0, en))
+    h = 1e-6
+    fd0 = (f(e0.detach() + h, en.detach()) - f(e0.detach() - h, en.detach())) / (2 * h)
+    fdn = (f(e0.detach(), en.detach() + h) - f(e0.detach(), en.detach() - h)) / (2 * h)
+    assert abs(g0.item() - fd0.item()) <= 1e-7 * (1 + abs(fd0.item()))
+    assert abs(gn.item() - fdn.item()) <= 1e-7 * (1 + abs(fdn.item()))
+    assert abs(g0.item()) > 1e-6 and abs(gn.item()) > 1e-6
