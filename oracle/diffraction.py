@@ -38,7 +38,11 @@ finite-conductivity coefficients in three dimensions are taken from the
 rays, cos(theta0) = sin(beta0) |sin phi'| and cos(thetan) = sin(beta0)
 |sin(n pi - phi)| (Luebbers' angles phi' and n pi - phi at normal incidence);
 the scattering coefficient S does not enter diffraction; in per-interaction
-mode both faces take the interaction's values.
+mode both faces take the interaction's values.  Luebbers' coefficients act
+on the edge-fixed (soft, hard) components, which are the face's (TE, TM)
+components only at normal incidence on the edge: for oblique rays on lossy
+faces the total field keeps a small jump at the reflection boundaries (the
+heuristic's own, pinned in the tests).
 """
 import math
 

@@ -22,6 +22,16 @@ with rho_Q the unfolded length from the Tx to the diffuse point (the
 incoming wave's spreading) and d_{Q+1} the distance to the Rx (the
 scattered spherical wave's).
 
+A first-order edge diffraction (Sec. II-E; store kind 2, the path's only
+interaction, the stored normal that of face 0 on the free-space side) takes
+the incident field into the edge-fixed basis, applies diag(-D_s, -D_h) of
+oracle.diffraction with the face materials of the interaction (face 0) and
+of the store's face-n id, and ends in the diffracted edge-fixed basis:
+
+  a = lambda/(4 pi) * C_R^H D_2 E / sqrt(s' s (s + s'))
+
+(the incident spherical wave's 1/s' times the spreading sqrt(s'/(s(s+s')))).
+
 Readings (the paper is silent or cites without printing):
   * spreading: planar reflectors and a point source give A^r = rho/(rho+d),
     whose product with 1/d_1 telescopes to 1/(total length) = 1/(c tau);
@@ -176,8 +186,21 @@ def departure_direction(store, sel=None):
     return _unit(first - tx)
 
 
+def _gather_edges(store, sel):
+    """Edge direction [P,3], wedge n [P] and face-n material [P] of the
+    selected paths (zeros where the store has no diffraction paths)."""
+    if store.edge is None:
+        P = len(sel)
+        return (torch.zeros((P, 3), dtype=f64), torch.zeros(P, dtype=f64),
+                torch.zeros(P, dtype=torch.int64))
+    e = torch.tensor(store.edge[:3, sel].T, dtype=f64)
+    return e, torch.tensor(store.edge[3, sel], dtype=f64), torch.tensor(
+        store.mat_n[sel].astype(np.int64))
+
+
 def trace_fields(store, eps_r, sigma, s, fc, zeta_tx=0.0, zeta_rx=0.0,
-                 ula_axis=(1.0, 0.0, 0.0), sel=None, tx_gain=None, kx=None, pattern=None):
+                 ula_axis=(1.0, 0.0, 0.0), sel=None, tx_gain=None, kx=None, pattern=None,
+                 eps_n=None, sigma_n=None):
     """Path coefficients a_i and array phase steps psi_i.
 
     eps_r, sigma, s: per-interaction material values, float64 tensors of
@@ -185,8 +208,9 @@ def trace_fields(store, eps_r, sigma, s, fc, zeta_tx=0.0, zeta_rx=0.0,
     path's depth are ignored.  Optional: tx_gain, a callable r -> G(r) on
     unit departure directions (Sec. III-A; isotropic if None); kx [D, P]
     K_x per interaction; pattern(k, k_in, k_s, n) -> f_s for interaction
-    slot k (Lambertian if None).  Returns (a complex128 [P], psi float64
-    [P])."""
+    slot k (Lambertian if None); eps_n, sigma_n [P]: the material of face n
+    of a diffracting wedge (default: the interaction's own, slot 0).
+    Returns (a complex128 [P], psi float64 [P])."""
     sel = np.arange(store.n_paths) if sel is None else np.asarray(sel)
     tx, rx, depth, pts, nrm, _, tau, kind, dA = _gather_paths(store, sel)
     P = len(sel)
@@ -202,6 +226,8 @@ def trace_fields(store, eps_r, sigma, s, fc, zeta_tx=0.0, zeta_rx=0.0,
     prev = tx
     rho = torch.zeros(P, dtype=f64)  # unfolded length from the Tx
     diffuse_end = torch.zeros(P, dtype=torch.bool)
+    diffracted = torch.zeros(P, dtype=torch.bool)
+    spread_d = torch.ones(P, dtype=f64)
     up = torch.tensor([0.0, 0.0, 1.0], dtype=f64).expand(P, 3)
     xhat = torch.tensor([1.0, 0.0, 0.0], dtype=f64).expand(P, 3)
     for k in range(D):
@@ -229,6 +255,28 @@ def trace_fields(store, eps_r, sigma, s, fc, zeta_tx=0.0, zeta_rx=0.0,
             e_perp = torch.where(dif[:, None], ep_d, e_perp)
             e_par_out = torch.where(dif[:, None], eq_d, e_par_out)
             diffuse_end = diffuse_end | dif
+        # first-order edge diffraction (Sec. II-E): the path's one interaction
+        dfr = act & (kind[k] == 2) & (depth == 1) if k == 0 else None
+        if dfr is not None and bool(dfr.any()):
+            from . import diffraction as odf
+            e_all, n_all, _ = _gather_edges(store, sel)
+            # stand-in wedge geometry for the other lanes keeps the graph finite
+            sd = lambda v, alt: torch.where(dfr[:, None], v, torch.tensor(alt, dtype=f64))  # noqa: E731
+            geo = odf.edge_geometry(sd(prev, [-3.0, 4.0, 0.4]), sd(s_k, [0.0, 0.0, 0.0]),
+                                    sd(rx, [-2.0, -1.5, 1.1]), sd(e_all, [0.0, 0.0, 1.0]),
+                                    sd(n_k, [0.0, 1.0, 0.0]))
+            n_w = torch.where(dfr, n_all, torch.full_like(n_all, 1.5))
+            eta_n = eta if eps_n is None else permittivity(eps_n, sigma_n, fc)
+            E_w, _, _ = odf.diffraction_step(E, p_out, q_out, geo, n_w, 2.0 * math.pi / lam,
+                                             eta, eta_n)
+            E_new = torch.where(dfr[:, None], E_w, E_new)
+            e_perp = torch.where(dfr[:, None], geo["beta_out"], e_perp)
+            e_par_out = torch.where(dfr[:, None], geo["phi_out"], e_par_out)
+            # spherical-wave spreading: (1/s') sqrt(s' / (s (s + s')))
+            sp = geo["s_p"]
+            so = geo["s"]
+            spread_d = torch.where(dfr, torch.sqrt(sp * so * (sp + so)), spread_d)
+            diffracted = diffracted | dfr
         E = torch.where(act[:, None], E_new, E)
         p_out = torch.where(act[:, None], e_perp, p_out)
         q_out = torch.where(act[:, None], e_par_out, q_out)
@@ -244,6 +292,7 @@ def trace_fields(store, eps_r, sigma, s, fc, zeta_tx=0.0, zeta_rx=0.0,
     # for a path ending in a diffuse reflection
     d_last = torch.linalg.norm(rx - prev, dim=-1)
     length = torch.where(diffuse_end, rho * d_last, C0 * tau)
+    length = torch.where(diffracted, spread_d, length)
     a = (lam / (4.0 * math.pi)) * received / length
     u = torch.tensor(ula_axis, dtype=f64)
     psi = math.pi * _dot(k1, u.expand(P, 3))
@@ -292,4 +341,8 @@ def trace_fields_per_id(store, raw, fc, sel=None, tx_raw=None, n_vmf=0, pat_raw=
         Lam_i = gather(torch.as_tensor(Lam, dtype=f64))
         kw["pattern"] = lambda k, k_in, k_s, n: pt.backscatter_pattern(k_in, k_s, n, a_r, a_s,
                                                                        Lam_i[k])
+    if store.edge is not None:
+        sel_ = np.arange(store.n_paths) if sel is None else np.asarray(sel)
+        mn = torch.tensor(store.mat_n[sel_].astype(np.int64))
+        kw["eps_n"], kw["sigma_n"] = eps_r[mn], sigma[mn]
     return trace_fields(store, gather(eps_r), gather(sigma), gather(s), fc, sel=sel, **kw)

@@ -199,6 +199,12 @@ def add_diffuse(store, tx, samples, visible_fn, max_links_chunk=64):
     tau = np.zeros(P, np.float64)
     depth[dst_s] = store.depth
     tau[dst_s] = store.tau
+    edge = mat_n = None
+    if store.edge is not None:
+        edge = np.zeros((4, P), np.float32)
+        mat_n = np.zeros(P, np.uint16)
+        edge[:, dst_s] = store.edge
+        mat_n[dst_s] = store.mat_n
     for k in range(int(store.max_depth)):
         src = k * P0 + np.arange(P0)
         dst = k * P + dst_s
@@ -221,4 +227,4 @@ def add_diffuse(store, tx, samples, visible_fn, max_links_chunk=64):
     tau[dst_d] = (np.linalg.norm(s - tx_d, axis=1) + np.linalg.norm(rx_d - s, axis=1)) / C0
     return PathStore(n_links=L, n_paths=P, max_depth=D, link_off=off, tx_pos=store.tx_pos.copy(),
                      rx_pos=store.rx_pos.copy(), depth=depth, kind=kind, pts=P_pts, nrm=P_nrm,
-                     mat=P_mat, dA=P_dA, tau=tau, face=P_face)
+                     mat=P_mat, dA=P_dA, tau=tau, face=P_face, edge=edge, mat_n=mat_n)

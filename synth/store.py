@@ -14,6 +14,7 @@ import numpy as np
 
 KIND_SPECULAR = 0
 KIND_DIFFUSE = 1
+KIND_DIFFRACTION = 2  # first-order edge diffraction (the path's only interaction)
 
 
 @dataclass
@@ -32,6 +33,12 @@ class PathStore:
     dA: np.ndarray         # float32 [max_depth*n_paths] (diffuse area, else 0)
     tau: np.ndarray        # float64 [n_paths] seconds
     face: np.ndarray       # int32 [max_depth*n_paths] face ids (bookkeeping)
+    # first-order diffraction paths (kind 2 in slot 0; their point is on the
+    # edge, nrm the normal of face 0 and mat its material): unit edge
+    # direction e with n0 x e pointing into face 0, and the wedge's n
+    # (exterior angle n pi); the material of face n.  None without such paths.
+    edge: np.ndarray = None   # float32 [4, n_paths] (ex, ey, ez, n), zeros elsewhere
+    mat_n: np.ndarray = None  # uint16 [n_paths]
 
     def link_of_path(self) -> np.ndarray:
         cnt = np.diff(self.link_off)
@@ -61,15 +68,18 @@ class PathStore:
             depth=self.depth[sel].copy(), kind=self.kind[idx].copy(),
             pts=self.pts[:, idx].copy(), nrm=self.nrm[:, idx].copy(),
             mat=self.mat[idx].copy(), dA=self.dA[idx].copy(),
-            tau=self.tau[sel].copy(), face=self.face[idx].copy())
+            tau=self.tau[sel].copy(), face=self.face[idx].copy(),
+            edge=None if self.edge is None else self.edge[:, sel].copy(),
+            mat_n=None if self.mat_n is None else self.mat_n[sel].copy())
 
     def save(self, path):
-        np.savez(path, **{k: getattr(self, k) for k in self.__dataclass_fields__})
+        np.savez(path, **{k: getattr(self, k) for k in self.__dataclass_fields__
+                          if getattr(self, k) is not None})
 
     @staticmethod
     def load(path) -> "PathStore":
         z = np.load(path, allow_pickle=False)
-        kw = {k: z[k] for k in PathStore.__dataclass_fields__}
+        kw = {k: z[k] for k in PathStore.__dataclass_fields__ if k in z}
         for k in ("n_links", "n_paths", "max_depth"):
             kw[k] = int(kw[k])
         return PathStore(**kw)
@@ -79,7 +89,8 @@ def pack(links_paths, tx_list, rx_list, max_depth: int, geom_dtype=np.float32) -
     """Build a store from per-link python lists of path records.
 
     Each path record is a dict with keys 'points' [Q,3] f64, 'normals' [Q,3],
-    'mats' [Q], 'faces' [Q], 'kinds' [Q], 'dA' [Q], 'length' (metres, f64).
+    'mats' [Q], 'faces' [Q], 'kinds' [Q], 'dA' [Q], 'length' (metres, f64),
+    and for a diffraction path 'edge' (ex, ey, ez, n) and 'mat_n'.
     geom_dtype other than float32 is for tests that need exact geometry;
     the GPU library takes float32 only.
     """
@@ -98,11 +109,17 @@ def pack(links_paths, tx_list, rx_list, max_depth: int, geom_dtype=np.float32) -
     dA = np.zeros(D * P, np.float32)
     face = np.full(D * P, -1, np.int32)
     tau = np.zeros(P, np.float64)
+    has_edge = any("edge" in rec for lp in links_paths for rec in lp)
+    edge = np.zeros((4, P), np.float32) if has_edge else None
+    mat_n = np.zeros(P, np.uint16) if has_edge else None
     p = 0
     for lp in links_paths:
         for rec in lp:
             q = len(rec["mats"])
             depth[p] = q
+            if "edge" in rec:
+                edge[:, p] = rec["edge"]
+                mat_n[p] = rec["mat_n"]
             for k in range(q):
                 i = k * P + p
                 pts[:, i] = rec["points"][k]
@@ -117,4 +134,4 @@ def pack(links_paths, tx_list, rx_list, max_depth: int, geom_dtype=np.float32) -
                      tx_pos=np.asarray(tx_list, geom_dtype).reshape(n_links, 3),
                      rx_pos=np.asarray(rx_list, geom_dtype).reshape(n_links, 3),
                      depth=depth, kind=kind, pts=pts, nrm=nrm, mat=mat, dA=dA,
-                     tau=tau, face=face)
+                     tau=tau, face=face, edge=edge, mat_n=mat_n)
