@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define RTC_ABI_VERSION 4
+#define RTC_ABI_VERSION 5
 
 typedef enum {
   RTC_OK = 0,
@@ -77,8 +77,8 @@ typedef struct {
  *   tx_pos, rx_pos : float [n_links*3]   link end points (metres)
  *   depth          : uint8 [n_paths]     number of interactions Q <= max_depth
  *   kind           : uint8 [max_depth*n_paths] 0 = specular reflection,
- *                    1 = diffuse (Lambertian) reflection; may be NULL (all
- *                    specular)
+ *                    1 = diffuse (Lambertian) reflection, 2 = edge
+ *                    diffraction (see edge); may be NULL (all specular)
  *   px,py,pz       : float [max_depth*n_paths] interaction points s_j
  *   nx,ny,nz       : float [max_depth*n_paths] surface unit normals (either
  *                    orientation)
@@ -86,6 +86,22 @@ typedef struct {
  *                    interactions; may be NULL when kind is NULL
  *   mat            : uint16 [max_depth*n_paths] material class ids
  *   tau            : double [n_paths] path delays (seconds), total length / c
+ *   edge, mat_n    : first-order edge diffraction (Sec. II-E), or NULL: a path
+ *                    of depth 1 whose interaction has kind 2 is diffracted at
+ *                    the point s_1 on a wedge edge; its normal must be that of
+ *                    face 0 on the free-space side and its mat that of face 0.
+ *                    edge = float [4*n_paths], rows (ex, ey, ez, n): the unit
+ *                    edge direction e with n0 x e pointing from the edge into
+ *                    face 0, and n with exterior wedge angle n pi (0 < n <= 2);
+ *                    mat_n = uint16 [n_paths] the material of face n (needed
+ *                    with per-id materials; per-interaction materials give
+ *                    both faces the interaction's values).  Only diffraction
+ *                    paths' entries are read.  kind 2 without edge, or at any
+ *                    other slot, is a specular reflection.  The coefficient
+ *                    is the UTD of Kouyoumjian and Pathak with Luebbers'
+ *                    finite-conductivity face coefficients (Fresnel r_perp,
+ *                    r_par at the rays' grazing angles), spreading
+ *                    sqrt(s'/(s (s + s'))); tau is (s' + s)/c.
  */
 typedef struct {
   int32_t n_links;
@@ -105,6 +121,8 @@ typedef struct {
   const float* dA;
   const uint16_t* mat;
   const double* tau;
+  const float* edge;
+  const uint16_t* mat_n;
 } rtc_paths;
 
 /* Materials, in exactly one of two modes.

@@ -256,7 +256,8 @@ def trace_fields(store, eps_r, sigma, s, fc, zeta_tx=0.0, zeta_rx=0.0,
             e_par_out = torch.where(dif[:, None], eq_d, e_par_out)
             diffuse_end = diffuse_end | dif
         # first-order edge diffraction (Sec. II-E): the path's one interaction
-        dfr = act & (kind[k] == 2) & (depth == 1) if k == 0 else None
+        dfr = (act & (kind[k] == 2) & (depth == 1)
+               if k == 0 and store.edge is not None else None)
         if dfr is not None and bool(dfr.any()):
             from . import diffraction as odf
             e_all, n_all, _ = _gather_edges(store, sel)

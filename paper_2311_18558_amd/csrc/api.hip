@@ -46,6 +46,8 @@ rtc_status check_paths(const rtc_paths* p, const char* fn, bool need_geometry) {
                   fn);
       RTC_REQUIRE(p->kind == nullptr || p->dA != nullptr, RTC_ERR_INVALID_ARG,
                   "%s: dA is required when kind is given", fn);
+      RTC_REQUIRE(p->edge == nullptr || p->kind != nullptr, RTC_ERR_INVALID_ARG,
+                  "%s: edge needs kind (diffraction paths are kind 2)", fn);
     }
   }
   return RTC_OK;
@@ -58,8 +60,9 @@ rtc_status check_mats(const rtc_materials* m, const rtc_paths* p, const char* fn
   if (m->raw) {
     RTC_REQUIRE(m->n_mat >= 1 && m->n_mat <= kMaxMat, RTC_ERR_RANGE,
                 "%s: n_mat must be in [1, %d]", fn, kMaxMat);
+    RTC_REQUIRE(p->edge == nullptr || p->mat_n != nullptr || p->n_paths == 0,
+                RTC_ERR_INVALID_ARG, "%s: per-id materials with edge need mat_n", fn);
   }
-  (void)p;
   return RTC_OK;
 }
 

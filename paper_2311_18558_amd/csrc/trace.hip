@@ -34,6 +34,7 @@
 #include <cmath>
 
 #include "api_common.h"
+#include "utd.h"
 #include "dev_common.h"
 
 namespace rtc {
@@ -64,6 +65,9 @@ struct TraceArgs {
   const float* tx_raw;     // [1 + 5 n_vmf] or null
   const float* pat_raw;    // [n_mat_pat * 6] per material K_x and pattern, or null
   int n_mat_pat;           // materials of pat_raw
+  const float* edge;       // [4 * n_paths] edge direction and wedge n of diffraction paths, or null
+  const uint16_t* mat_n;   // [n_paths] material of face n, or null
+  double k0;               // carrier wavenumber 2 pi / lambda_c
   float inv_eps0w;         // 1/(eps0 * omega_c)
   double lam4pi;           // lambda_c / (4 pi)
   float cz_tx, sz_tx, cz_rx, sz_rx;
@@ -315,11 +319,115 @@ struct Chain {
   int pid;     // its pattern material
   PatVal pv;   // its pattern
   PatEval pe;
+  // first-order edge diffraction (the path's only interaction)
+  bool dfr;
+  float2 yb, yp;   // incident field in the edge-fixed basis (beta', phi')
+  float2 W2, W3;   // pre * (face-0 term), pre * (face-n term) of D
+  float c0, cn;    // incidence cosines of Luebbers' face coefficients
+  MatVal mvn;      // material of face n
+  float dscale;    // lambda/(4 pi) / sqrt(s' s (s + s'))
 };
 
-// PAT: the trainable Tx gain and scattering patterns are compiled in (the
-// plain chain keeps its register budget without them).
-template <int MAXD, bool SAVE, bool PAT>
+// Diffraction at an edge point (Sec. II-E): geometry in FP64 from the
+// stored FP32 points, the UTD terms of utd.h, Luebbers' face coefficients
+// (Fresnel r_perp for the soft, r_par for the hard polarisation) and the
+// field into the diffracted edge-fixed basis.  E0, E1: the incident field in
+// (p_out, q_out); on return the diffracted one in (np, nq) = (beta_hat,
+// phi_hat).
+template <int MAXD, bool SAVE>
+RTC_DEV void diffract(const TraceArgs& A, v3 tx, v3 q, v3 rx, v3 n0f, int64_t p, MatVal mv0,
+                      MatVal mvn, v3 p_out, v3 q_out, float2& E0, float2& E1, v3* np, v3* nq,
+                      Chain<MAXD, SAVE>& C) {
+  const int64_t P = A.n_paths;
+  double e[3] = {A.edge[p], A.edge[P + p], A.edge[2 * P + p]};
+  const double nw = A.edge[3 * P + p];
+  double n0[3] = {n0f.x, n0f.y, n0f.z};
+  auto dotd = [](const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; };
+  auto crossd = [](const double* a, const double* b, double* o) {
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+  };
+  auto normd = [&](double* a) {
+    const double r = 1.0 / sqrt(dotd(a, a));
+    a[0] *= r;
+    a[1] *= r;
+    a[2] *= r;
+  };
+  normd(e);
+  normd(n0);
+  double si[3] = {(double)q.x - tx.x, (double)q.y - tx.y, (double)q.z - tx.z};
+  double so[3] = {(double)rx.x - q.x, (double)rx.y - q.y, (double)rx.z - q.z};
+  const double sp = sqrt(dotd(si, si)), sd = sqrt(dotd(so, so));
+  normd(si);
+  normd(so);
+  double t0[3], pi_[3], bi[3], po[3], bo[3];
+  crossd(n0, e, t0);
+  crossd(e, si, pi_);
+  normd(pi_);
+  pi_[0] = -pi_[0];
+  pi_[1] = -pi_[1];
+  pi_[2] = -pi_[2];
+  crossd(pi_, si, bi);
+  crossd(e, so, po);
+  normd(po);
+  crossd(po, so, bo);
+  // angles about the edge from face 0 towards its normal, in [0, 2 pi)
+  auto angle = [&](const double* d, double sgn) {
+    const double de = sgn * dotd(d, e);
+    const double x = sgn * dotd(d, t0) - de * dotd(e, t0);
+    const double y = sgn * dotd(d, n0) - de * dotd(e, n0);
+    double a = atan2(y, x);
+    return a < 0.0 ? a + 2.0 * kUtdPi : a;
+  };
+  const double phip = angle(si, -1.0), phi = angle(so, 1.0);
+  const double cb = dotd(so, e);
+  const double sb = sqrt(fmax(1.0 - cb * cb, 0.0));
+  const double L = sd * sp * sb * sb / (sd + sp);
+  Cd T[4];
+  utd_terms(phi, phip, nw, A.k0 * L, T);
+  // pre = -e^{-j pi/4} / (2 n sqrt(2 pi k) sin beta0)
+  const double pm = -kSqrtHalf / (2.0 * nw * sqrt(2.0 * kUtdPi * A.k0) * sb);
+  const Cd pre = cd(pm, -pm);
+  float2 W[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const Cd w = cd_mul(pre, T[i]);
+    W[i] = make_float2((float)w.x, (float)w.y);
+  }
+  const float c0 = (float)(sb * fabs(sin(phip)));
+  const float cn = (float)(sb * fabs(sin(nw * kUtdPi - phi)));
+  float2 r0s, r0h, rns, rnh, sq;
+  fresnel(mv0.eta, c0, &r0s, &r0h, &sq);
+  fresnel(mvn.eta, cn, &rns, &rnh, &sq);
+  const float2 W01 = cadd(W[0], W[1]);
+  const float2 Ds = cadd(W01, cadd(cmul(r0s, W[2]), cmul(rns, W[3])));
+  const float2 Dh = cadd(W01, cadd(cmul(r0h, W[2]), cmul(rnh, W[3])));
+  const v3 bif = v3{(float)bi[0], (float)bi[1], (float)bi[2]};
+  const v3 pif = v3{(float)pi_[0], (float)pi_[1], (float)pi_[2]};
+  const float2 yb = cadd(cscale(E0, dot3(bif, p_out)), cscale(E1, dot3(bif, q_out)));
+  const float2 yp = cadd(cscale(E0, dot3(pif, p_out)), cscale(E1, dot3(pif, q_out)));
+  E0 = cscale(cmul(Ds, yb), -1.0f);
+  E1 = cscale(cmul(Dh, yp), -1.0f);
+  *np = v3{(float)bo[0], (float)bo[1], (float)bo[2]};
+  *nq = v3{(float)po[0], (float)po[1], (float)po[2]};
+  C.dfr = true;
+  C.dscale = (float)(A.lam4pi / sqrt(sp * sd * (sp + sd)));
+  if constexpr (SAVE) {
+    C.yb = yb;
+    C.yp = yp;
+    C.W2 = W[2];
+    C.W3 = W[3];
+    C.c0 = c0;
+    C.cn = cn;
+    C.mvn = mvn;
+  }
+}
+
+// EXT: the optional physics is compiled in -- the trainable Tx gain and
+// scattering patterns, and edge diffraction (the plain chain keeps its
+// register budget without them).
+template <int MAXD, bool SAVE, bool EXT>
 RTC_DEV void run_chain(const TraceArgs& A, const MatVal* tab, const VmfTab* vt, const PatVal* ptab,
                        int64_t p, Chain<MAXD, SAVE>& C) {
   int l = find_link(A.link_off, A.n_links, p);
@@ -338,7 +446,7 @@ RTC_DEV void run_chain(const TraceArgs& A, const MatVal* tab, const VmfTab* vt, 
   float2 E0 = make_float2(A.cz_tx, 0.0f);
   float2 E1 = make_float2(A.sz_tx, 0.0f);
   C.G = 1.0f;
-  if (PAT && A.n_vmf > 0) {
+  if (EXT && A.n_vmf > 0) {
     C.G = vmf_gain(*vt, k1);
     const float sg = sqrtf(fmaxf(C.G, 0.0f));
     E0.x *= sg;
@@ -349,6 +457,7 @@ RTC_DEV void run_chain(const TraceArgs& A, const MatVal* tab, const VmfTab* vt, 
   v3 prev = tx;
   float rho = 0.0f;  // unfolded length from the Tx
   C.dif = false;
+  C.dfr = false;
   C.G0 = C.nv = 0.0f;
 #pragma unroll
   for (int j = 0; j < MAXD; ++j) {
@@ -368,12 +477,21 @@ RTC_DEV void run_chain(const TraceArgs& A, const MatVal* tab, const VmfTab* vt, 
       float2 rp, rl, sr;
       fresnel(mv.eta, c, &rp, &rl, &sr);
       const bool dif = A.kind != nullptr && j == Q - 1 && A.kind[slot] == 1;
-      if (dif) {
+      const bool dfr = EXT && A.edge != nullptr && A.kind != nullptr && j == 0 && Q == 1 &&
+                       A.kind[slot] == 2;
+      if (dfr) {
+        MatVal mvn = mv;
+        if (A.raw) {
+          int mn = A.mat_n[p];
+          mvn = tab[mn < A.n_mat ? mn : A.n_mat - 1];
+        }
+        diffract<MAXD, SAVE>(A, tx, s, rx, n, p, mv, mvn, p_out, q_out, E0, E1, &np, &nq, C);
+      } else if (dif) {
         v3 nf = dot3(k_in, n) > 0.0f ? scl3(n, -1.0f) : n;  // towards the incidence side
         v3 k_s = unit3(sub3(rx, s));
         float f = fmaxf(dot3(k_s, nf), 0.0f) * kInvPi;  // Lambertian
         float kx = 0.0f;
-        if (PAT && A.pat_raw) {
+        if (EXT && A.pat_raw) {
           C.pid = pat_id(A, slot);
           C.pv = ptab[C.pid];
           C.pe = eval_pattern(C.pv, k_in, k_s, nf, c);
@@ -431,6 +549,8 @@ RTC_DEV void run_chain(const TraceArgs& A, const MatVal* tab, const VmfTab* vt, 
   if (C.dif) {
     v3 seg = sub3(rx, prev);
     C.scale = (float)(A.lam4pi / ((double)rho * (double)sqrtf(dot3(seg, seg))));
+  } else if (C.dfr) {
+    C.scale = C.dscale;
   } else {
     C.scale = (float)(A.lam4pi / (kC0 * A.tau[p]));
   }
@@ -463,17 +583,17 @@ RTC_DEV TraceLds trace_lds(const TraceArgs& A, unsigned char* smem) {
   return L;
 }
 
-template <int MAXD, bool PAT>
+template <int MAXD, bool EXT>
 __global__ void __launch_bounds__(kTraceBlock) trace_fields_kernel(TraceArgs A, float2* a,
                                                                     float* psi) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_f[];
   const TraceLds Ls = trace_lds(A, smem_f);
   stage_materials(A, Ls.tab);
-  if constexpr (PAT) stage_patterns(A, Ls.vt, Ls.pt);
+  if constexpr (EXT) stage_patterns(A, Ls.vt, Ls.pt);
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= A.n_paths) return;
   Chain<MAXD, false> C;
-  run_chain<MAXD, false, PAT>(A, Ls.tab, Ls.vt, Ls.pt, p, C);
+  run_chain<MAXD, false, EXT>(A, Ls.tab, Ls.vt, Ls.pt, p, C);
   // C_R^H E with a real (isotropic, slant zeta) Rx pattern
   float2 recv = cadd(cscale(C.E0, A.cz_rx), cscale(C.E1, A.sz_rx));
   if (a) a[p] = cscale(recv, C.scale);
@@ -494,7 +614,7 @@ struct GradLayout {
   int mat, pat, tx, stride;  // offsets of the sections (-1 absent), row length
 };
 
-template <int MAXD, bool PER_ID, bool PAT>
+template <int MAXD, bool PER_ID, bool EXT>
 __global__ void __launch_bounds__(kTraceBlock)
     trace_fields_adjoint_kernel(TraceArgs A, const float2* dLda, float* dLd_inter,
                                 double* block_part, GradLayout GL) {
@@ -503,7 +623,7 @@ __global__ void __launch_bounds__(kTraceBlock)
   MatVal* tab = Ls.tab;
   double* acc = Ls.acc;
   stage_materials(A, tab);
-  if constexpr (PAT) stage_patterns(A, Ls.vt, Ls.pt);
+  if constexpr (EXT) stage_patterns(A, Ls.vt, Ls.pt);
   if (GL.stride > 0) {
     for (int i = threadIdx.x; i < GL.stride * (int)(blockDim.x >> 6); i += blockDim.x) acc[i] = 0.0;
     __syncthreads();
@@ -519,6 +639,7 @@ __global__ void __launch_bounds__(kTraceBlock)
     float g_eps[MAXD], g_sig[MAXD], g_S[MAXD];
     int ids[MAXD];
     int Q = 0;
+    bool dfr_path = false;
     // pattern gradients of the path's diffuse interaction (at most one):
     // raw K_x, then w1..w3, lam2, lam3 in natural coordinates
     float g_pat[kPatGrad];
@@ -534,11 +655,12 @@ __global__ void __launch_bounds__(kTraceBlock)
     }
     if (valid) {
       Chain<MAXD, true> C;
-      run_chain<MAXD, true, PAT>(A, tab, Ls.vt, Ls.pt, p, C);
+      run_chain<MAXD, true, EXT>(A, tab, Ls.vt, Ls.pt, p, C);
       Q = C.Q;
       float2 Ga = dLda[p];
+      dfr_path = C.dfr;
       k1 = C.k1;
-      if (PAT && GL.tx >= 0 && C.G > 0.0f) {
+      if (EXT && GL.tx >= 0 && C.G > 0.0f) {
         // a is proportional to sqrt(G): dL/dG = Re(conj(a) dL/da) / (2 G)
         const float2 recv = cadd(cscale(C.E0, A.cz_rx), cscale(C.E1, A.sz_rx));
         const float2 av = cscale(recv, C.scale);
@@ -550,7 +672,52 @@ __global__ void __launch_bounds__(kTraceBlock)
       float2 w1 = make_float2(K * (A.cz_rx * C.Dq[1] + A.sz_rx * C.Dq[3]), 0.0f);
 #pragma unroll
       for (int j = MAXD - 1; j >= 0; --j) {
-        if (j < Q && C.dif && j == Q - 1) {
+        if (EXT && j == 0 && C.dfr) {
+          // a = w0 (-D_s yb) + w1 (-D_h yp) with D = W01 + R0 W2 + Rn W3:
+          // da/deta_0 = -(w0 yb dR0s/deta + w1 yp dR0h/deta) W2, likewise
+          // face n with W3 (the covector w is real here: Q = 1)
+          float2 r_s, r_h, sq;
+          float2 dts, dth, dns, dnh;
+          {
+            const float c = C.c0;
+            const float2 eta = C.mv[0].eta;
+            fresnel(eta, c, &r_s, &r_h, &sq);
+            const float2 cps = make_float2(c + sq.x, sq.y);
+            dts = cdiv(make_float2(-c, 0.0f), cmul(sq, cmul(cps, cps)));
+            const float2 ecs = cadd(cscale(eta, c), sq);
+            dth = cdiv(cscale(make_float2(eta.x - 2.0f * fmaf(-c, c, 1.0f), eta.y), c),
+                       cmul(sq, cmul(ecs, ecs)));
+          }
+          {
+            const float c = C.cn;
+            const float2 eta = C.mvn.eta;
+            fresnel(eta, c, &r_s, &r_h, &sq);
+            const float2 cps = make_float2(c + sq.x, sq.y);
+            dns = cdiv(make_float2(-c, 0.0f), cmul(sq, cmul(cps, cps)));
+            const float2 ecs = cadd(cscale(eta, c), sq);
+            dnh = cdiv(cscale(make_float2(eta.x - 2.0f * fmaf(-c, c, 1.0f), eta.y), c),
+                       cmul(sq, cmul(ecs, ecs)));
+          }
+          const float2 ub = cscale(C.yb, -w0.x), up = cscale(C.yp, -w1.x);
+          const float2 da0 = cmul(cadd(cmul(ub, dts), cmul(up, dth)), C.W2);
+          const float2 dan = cmul(cadd(cmul(ub, dns), cmul(up, dnh)), C.W3);
+          const float2 G0 = cmulc(da0, Ga);  // conj(da/deta) dL/da
+          const float2 Gn = cmulc(dan, Ga);
+          g_eps[0] = G0.x;
+          g_sig[0] = -G0.y * A.inv_eps0w;
+          g_S[0] = 0.0f;
+          ids[0] = PER_ID ? (int)min((int)A.mat[p], A.n_mat - 1) : 0;
+          if constexpr (PER_ID && MAXD >= 2) {
+            g_eps[1] = Gn.x;
+            g_sig[1] = -Gn.y * A.inv_eps0w;
+            g_S[1] = 0.0f;
+            ids[1] = (int)min((int)A.mat_n[p], A.n_mat - 1);
+          } else {
+            // per-interaction materials: both faces take the interaction's
+            g_eps[0] += Gn.x;
+            g_sig[0] += -Gn.y * A.inv_eps0w;
+          }
+        } else if (j < Q && C.dif && j == Q - 1) {
           // a = K q_R |E_s| is real, so dL/dx = Re(dL/da) da/dx.  With
           // |E_s| = S G0 nv, nv = |v|, v = (r_perp y0, r_par y1):
           //   d nv/d eta_re = Re(Z)/nv, d nv/d eta_im = -Im(Z)/nv,
@@ -561,11 +728,11 @@ __global__ void __launch_bounds__(kTraceBlock)
           // K (qR0 sqrt(1 - K_x) + qR1 sqrt(K_x)) |E_s|
           const float qR0 = A.cz_rx * C.Dq[0] + A.sz_rx * C.Dq[2];
           const float qR1 = A.cz_rx * C.Dq[1] + A.sz_rx * C.Dq[3];
-          const float kx = (PAT && A.pat_raw) ? C.pv.kx : 0.0f;
+          const float kx = (EXT && A.pat_raw) ? C.pv.kx : 0.0f;
           const float sk0 = sqrtf(1.0f - kx), sk1 = sqrtf(kx);
           const float qR = qR0 * sk0 + qR1 * sk1;
           const float gam = Ga.x * K * qR;
-          if (PAT && GL.pat >= 0) {
+          if (EXT && GL.pat >= 0) {
             // d a/du_kx with K_x = logistic(u): K |E_s| K_x (1 - K_x)
             //   (-qR0 / (2 sqrt(1 - K_x)) + qR1 / (2 sqrt(K_x)))
             const float As = C.mv[j].S * C.G0 * C.nv;
@@ -647,6 +814,8 @@ __global__ void __launch_bounds__(kTraceBlock)
         }
       }
     } else {
+      // a diffraction path carries its face-n gradient in slot 1
+      if (EXT && dfr_path) Q = 2;
       // Segmented reduction by material id, deterministic: each wave walks
       // the distinct ids present in it in increasing order; for each id the
       // lanes' contributions (fixed order over j) are summed by a butterfly
@@ -687,7 +856,7 @@ __global__ void __launch_bounds__(kTraceBlock)
         }
       }
     }
-    if (PAT && GL.pat >= 0) {
+    if (EXT && GL.pat >= 0) {
       // the same deterministic walk over the pattern ids of the wave
       double* wacc = acc + wave * GL.stride + GL.pat;
       bool done = !valid || pat_m == 0x7fffffff;
@@ -705,7 +874,7 @@ __global__ void __launch_bounds__(kTraceBlock)
         if (mine) done = true;
       }
     }
-    if (PAT && GL.tx >= 0) {
+    if (EXT && GL.tx >= 0) {
       // natural Tx gradients of this path, summed over the wave in order:
       //   eta: G/eta,  w_i: eta c_i e_i,  lam_i: eta w_i c_i e_i ((mu_i.k - 1)
       //   + d ln c_i/d lam_i),  mu_i: eta w_i c_i e_i lam_i k
@@ -865,6 +1034,9 @@ static TraceArgs make_args(const rtc_radio* r, const rtc_paths* P, const rtc_mat
   A.tx_raw = pat ? pat->tx_raw : nullptr;
   A.pat_raw = pat ? pat->mat_raw : nullptr;
   A.n_mat_pat = M->n_mat > 0 ? M->n_mat : 1;
+  A.edge = P->edge;
+  A.mat_n = P->mat_n;
+  A.k0 = 2.0 * kPi * r->fc_hz / kC0;
   double omega = 2.0 * kPi * r->fc_hz;
   A.inv_eps0w = (float)(1.0 / (kEps0 * omega));
   A.lam4pi = (kC0 / r->fc_hz) / (4.0 * kPi);
@@ -954,7 +1126,7 @@ extern "C" rtc_status rtc_trace_fields_pat(const rtc_radio* radio, const rtc_pat
   dim3 grid((paths->n_paths + kTraceBlock - 1) / kTraceBlock);
   size_t shm = trace_lds_fixed(A);
   hipStream_t s = as_stream(stream);
-  const bool pat = A.n_vmf > 0 || A.pat_raw != nullptr;
+  const bool pat = A.n_vmf > 0 || A.pat_raw != nullptr || A.edge != nullptr;
   switch (depth_bucket(paths->max_depth)) {
 #define RTC_CASE(D)                                                                          \
   case D:                                                                                    \
@@ -1029,11 +1201,12 @@ extern "C" rtc_status rtc_trace_fields_adjoint_pat(
               "%s: %zu bytes of LDS needed (too many materials for the gradients asked)", fn, shm);
   double* part = reinterpret_cast<double*>(ws);
   const float2* g_a = reinterpret_cast<const float2*>(dLda);
-  // the pattern code is compiled in only when the forward used patterns
-  const bool pat = A.n_vmf > 0 || A.pat_raw != nullptr;
-  switch (depth_bucket(paths->max_depth)) {
-#define RTC_LAUNCH(D, ID, PAT, DINT)                                                          \
-  hipLaunchKernelGGL((trace_fields_adjoint_kernel<D, ID, PAT>), dim3(blocks), dim3(kTraceBlock), \
+  // the optional physics is compiled in only when the paths or patterns use it
+  const bool pat = A.n_vmf > 0 || A.pat_raw != nullptr || A.edge != nullptr;
+  // diffraction paths keep their face-n gradient in a second slot
+  switch (depth_bucket(paths->edge && per_id && paths->max_depth < 2 ? 2 : paths->max_depth)) {
+#define RTC_LAUNCH(D, ID, EXT, DINT)                                                          \
+  hipLaunchKernelGGL((trace_fields_adjoint_kernel<D, ID, EXT>), dim3(blocks), dim3(kTraceBlock), \
                      shm, s, A, g_a, DINT, part, GL)
 #define RTC_CASE(D)                                                                           \
   case D:                                                                                     \

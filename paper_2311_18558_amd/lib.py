@@ -41,7 +41,8 @@ class Paths(ctypes.Structure):
     _fields_ = [("n_links", c_i32), ("n_paths", c_i32), ("max_depth", c_i32),
                 ("link_off", c_vp), ("tx_pos", c_vp), ("rx_pos", c_vp), ("depth", c_vp),
                 ("kind", c_vp), ("px", c_vp), ("py", c_vp), ("pz", c_vp), ("nx", c_vp),
-                ("ny", c_vp), ("nz", c_vp), ("dA", c_vp), ("mat", c_vp), ("tau", c_vp)]
+                ("ny", c_vp), ("nz", c_vp), ("dA", c_vp), ("mat", c_vp), ("tau", c_vp),
+                ("edge", c_vp), ("mat_n", c_vp)]
 
 
 class Materials(ctypes.Structure):
@@ -178,6 +179,9 @@ class DevicePaths:
         has_diffuse = bool(np.any(store.kind != 0))
         self.kind = t(store.kind, torch.uint8) if has_diffuse else None
         self.dA = t(store.dA, torch.float32) if has_diffuse else None
+        has_edge = getattr(store, "edge", None) is not None
+        self.edge = t(store.edge, torch.float32) if has_edge else None
+        self.mat_n = t(store.mat_n.astype(np.int16), torch.int16) if has_edge else None
         s = Paths()
         s.n_links, s.n_paths, s.max_depth = self.n_links, self.n_paths, self.max_depth
         s.link_off = self.link_off.data_ptr()
@@ -193,6 +197,8 @@ class DevicePaths:
         s.nx, s.ny, s.nz = base_n, base_n + 4 * DP, base_n + 8 * DP
         s.mat = self.mat.data_ptr()
         s.tau = self.tau.data_ptr()
+        s.edge = self.edge.data_ptr() if has_edge else None
+        s.mat_n = self.mat_n.data_ptr() if has_edge else None
         self.c = s
 
 
@@ -407,6 +413,8 @@ def subset_links(dp, links):
     b.tau = dp.tau[idx].contiguous()
     b.kind = dp.kind[slot].contiguous() if dp.kind is not None else None
     b.dA = dp.dA[slot].contiguous() if dp.dA is not None else None
+    b.edge = dp.edge[:, idx].contiguous() if dp.edge is not None else None
+    b.mat_n = dp.mat_n[idx].contiguous() if dp.mat_n is not None else None
     s = Paths()
     s.n_links, s.n_paths, s.max_depth = b.n_links, Pb, D
     s.link_off = b.link_off.data_ptr()
@@ -421,5 +429,7 @@ def subset_links(dp, links):
     s.nx, s.ny, s.nz = bn, bn + 4 * DPb, bn + 8 * DPb
     s.mat = b.mat.data_ptr()
     s.tau = b.tau.data_ptr()
+    s.edge = b.edge.data_ptr() if b.edge is not None else None
+    s.mat_n = b.mat_n.data_ptr() if b.mat_n is not None else None
     b.c = s
     return b, slot

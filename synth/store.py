@@ -135,3 +135,44 @@ def pack(links_paths, tx_list, rx_list, max_depth: int, geom_dtype=np.float32) -
                      rx_pos=np.asarray(rx_list, geom_dtype).reshape(n_links, 3),
                      depth=depth, kind=kind, pts=pts, nrm=nrm, mat=mat, dA=dA,
                      tau=tau, face=face, edge=edge, mat_n=mat_n)
+
+
+def merge_links(a: PathStore, b: PathStore) -> PathStore:
+    """A store whose link l holds a's paths of link l followed by b's (the
+    two stores describe the same links; interaction slots padded to the
+    larger depth)."""
+    assert a.n_links == b.n_links
+    L = a.n_links
+    D = max(int(a.max_depth), int(b.max_depth))
+    ca, cb = a.paths_per_link(), b.paths_per_link()
+    off = np.zeros(L + 1, np.int64)
+    off[1:] = np.cumsum(ca + cb)
+    P = int(off[-1])
+    la, lb = a.link_of_path(), b.link_of_path()
+    dst_a = off[la] + (np.arange(a.n_paths) - a.link_off[la])
+    dst_b = off[lb] + ca[lb] + (np.arange(b.n_paths) - b.link_off[lb])
+    gd = a.pts.dtype
+    out = dict(depth=np.zeros(P, np.uint8), kind=np.zeros(D * P, np.uint8),
+               pts=np.zeros((3, D * P), gd), nrm=np.zeros((3, D * P), gd),
+               mat=np.zeros(D * P, np.uint16), dA=np.zeros(D * P, np.float32),
+               face=np.full(D * P, -1, np.int32), tau=np.zeros(P, np.float64))
+    has_edge = a.edge is not None or b.edge is not None
+    edge = np.zeros((4, P), np.float32) if has_edge else None
+    mat_n = np.zeros(P, np.uint16) if has_edge else None
+    for s, dst in ((a, dst_a), (b, dst_b)):
+        out["depth"][dst] = s.depth
+        out["tau"][dst] = s.tau
+        for k in range(int(s.max_depth)):
+            src = k * s.n_paths + np.arange(s.n_paths)
+            d = k * P + dst
+            out["kind"][d] = s.kind[src]
+            out["pts"][:, d] = s.pts[:, src]
+            out["nrm"][:, d] = s.nrm[:, src]
+            out["mat"][d] = s.mat[src]
+            out["dA"][d] = s.dA[src]
+            out["face"][d] = s.face[src]
+        if s.edge is not None:
+            edge[:, dst] = s.edge
+            mat_n[dst] = s.mat_n
+    return PathStore(n_links=L, n_paths=P, max_depth=D, link_off=off, tx_pos=a.tx_pos.copy(),
+                     rx_pos=a.rx_pos.copy(), edge=edge, mat_n=mat_n, **out)
