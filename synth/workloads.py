@@ -14,9 +14,11 @@
             subcarriers over 100 MHz at 3.5 GHz, 32-element ULA
   recovery  stand-in for the synthetic dataset of Sec. IV-B: a straight
             hallway 24 x 6 x 3 m (floor, walls and ceiling as three
-            materials), one Rx antenna near one end at 2 m, 256 Tx at random
-            points; specular paths up to third order plus single-bounce
-            diffuse paths from ~1 sample per m^2 of surface; 1,024
+            materials) with a 1.2 m square pillar of the wall material, one
+            Rx antenna near one end at 2 m, 256 Tx at random points;
+            specular paths up to third order, single-bounce diffuse paths
+            from ~1 sample per m^2 of surface and first-order diffraction at
+            the pillar's corners; 1,024
             subcarriers over 50 MHz at 3.438 GHz; ground truth of Table I
             with the backscattering-lobe pattern (alpha_r = 5, alpha_s = 8,
             Lambda = 0.8) and a three-lobe Tx gain
@@ -188,32 +190,58 @@ def vmf_to_raw(eta, w, lam, mu):
                            mu.reshape(-1)]).astype(np.float32)
 
 
-def hallway_scene(size=(24.0, 6.0, 3.0)):
+def hallway_scene(size=(24.0, 6.0, 3.0), pillar=None):
     """Straight hallway [0,sx]x[0,sy]x[0,sz]: material 0 the floor, 1 the
-    four walls, 2 the ceiling."""
+    four walls, 2 the ceiling; optionally a floor-to-ceiling pillar (x0, y0,
+    x1, y1) of the wall material, whose four vertical corners diffract."""
     b = SceneBuilder()
     b.add_box((0.0, 0.0, 0.0), size, 1)
+    if pillar is not None:
+        x0, y0, x1, y1 = pillar
+        b.add_box((x0, y0, 0.0), (x1, y1, size[2]), 1, skip=("-z", "+z"))
     sc = b.build(n_mat=3)
     nz = sc.face_normal[:, 2]
     sc.face_mat = np.where(nz > 0.5, 0, np.where(nz < -0.5, 2, 1)).astype(np.int32)
     return sc
 
 
+RECOVERY_PILLAR = (11.4, 2.4, 12.6, 3.6)
+
+
 def recovery(seed=7, n_tx=256, size=(24.0, 6.0, 3.0), density=1.0, max_depth=3, n_sc=1024,
-             fc=3.438e9, bandwidth=50e6) -> Workload:
+             fc=3.438e9, bandwidth=50e6, pillar=RECOVERY_PILLAR) -> Workload:
+    from types import SimpleNamespace
+    from . import diffract as _diffract
     rng = np.random.default_rng(seed)
-    scene = hallway_scene(size)
+    scene = hallway_scene(size, pillar)
     rx = np.array([1.0, size[1] / 2, 2.0])
     txs = np.stack([rng.uniform(0.5, size[0] - 0.5, n_tx), rng.uniform(0.5, size[1] - 0.5, n_tx),
                     rng.uniform(0.5, 2.5, n_tx)], 1)
+    if pillar is not None:
+        # no Tx inside or against the pillar
+        x0, y0, x1, y1 = pillar
+        inside = ((txs[:, 0] > x0 - 0.3) & (txs[:, 0] < x1 + 0.3) &
+                  (txs[:, 1] > y0 - 0.3) & (txs[:, 1] < y1 + 0.3))
+        txs[inside, 0] = np.where(txs[inside, 0] < 0.5 * (x0 + x1), x0 - 0.6, x1 + 0.6)
     links = [imagemethod.find_paths(scene, t, rx, max_depth) for t in txs]
     spec = imagemethod.pack(links, list(txs), [rx] * n_tx, max_depth)
     samples = _diffuse.sample_triangles_density(scene, density, rng)
-    # a convex room: every sample point sees every Tx and the Rx
-    store = _diffuse.add_diffuse(spec, None, samples, lambda p, e: np.ones(len(p), bool))
+    if pillar is None:
+        # a convex room: every sample point sees every Tx and the Rx
+        store = _diffuse.add_diffuse(spec, None, samples, lambda p, e: np.ones(len(p), bool))
+    else:
+        # the pillar spans floor to ceiling: a segment between interior points
+        # is blocked exactly when its floor-plan projection enters the pillar;
+        # its four vertical corners (wall material) diffract.  Its faces are
+        # the scene's last four, in the order -x, +x, -y, +y.
+        box = SimpleNamespace(boxes=np.asarray([pillar], np.float64), box_mat=np.array([1]),
+                              box_face0=np.array([scene.n_face - 4]))
+        store = _diffuse.add_diffuse(spec, None, samples,
+                                     lambda p, e: _diffuse.visible_floor(box, p, e))
+        store = _diffract.add_diffraction(store, box, _diffract.floor_edges(box))
     raw = materials_to_raw(TABLE_I[:, 0], TABLE_I[:, 1], TABLE_I[:, 2])
     radio = Radio(fc=fc, bandwidth=bandwidth, n_sc=n_sc, n_elem=1)
     meta = dict(kx=TABLE_I[:, 3].copy(), lobes=RECOVERY_LOBES, n_vmf=3,
-                tx_raw=vmf_to_raw(**RECOVERY_TX), table=TABLE_I.copy())
+                tx_raw=vmf_to_raw(**RECOVERY_TX), table=TABLE_I.copy(), pillar=pillar)
     return Workload("recovery", store, radio, raw, np.ones(1, np.complex64),
                     (scene.aabb_min, scene.aabb_max), meta)

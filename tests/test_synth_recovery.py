@@ -1,7 +1,8 @@
-"""The recovery workload's geometry: a convex hallway, so every link has all
-1 + 6 + 18 + 38 specular images up to third order and every surface sample
-as a diffuse path; per-link Tx positions in the diffuse delays; the Table I
-ground truth in the raw layout."""
+"""The recovery workload's geometry: without its pillar a convex hallway, so
+every link has all 1 + 6 + 18 + 38 specular images up to third order and
+every surface sample as a diffuse path; per-link Tx positions in the
+diffuse delays; the Table I ground truth in the raw layout; with the pillar,
+blocked paths and first-order diffraction at its corners."""
 import numpy as np
 import pytest
 
@@ -13,7 +14,7 @@ C0 = 299792458.0
 
 @pytest.fixture(scope="module")
 def small():
-    return recovery(seed=3, n_tx=6, density=0.25, n_sc=64)
+    return recovery(seed=3, n_tx=6, density=0.25, n_sc=64, pillar=None)
 
 
 def test_path_counts(small):
@@ -69,3 +70,21 @@ def test_tx_raw_roundtrip():
     w = np.exp(t[1:4]) / np.exp(t[1:4]).sum()
     assert np.allclose(w, (0.6, 0.25, 0.15), rtol=1e-6)
     assert np.allclose(np.exp(t[4:7]), (6, 2, 10), rtol=1e-6)
+
+
+def test_pillar_blocks_and_diffracts():
+    from synth.store import KIND_DIFFRACTION
+    w = recovery(seed=3, n_tx=12, density=0.25, n_sc=64)
+    st = w.store
+    P = st.n_paths
+    kind = st.kind[:P]
+    assert (kind == KIND_DIFFRACTION).sum() >= 6
+    x0, y0, x1, y1 = w.meta["pillar"]
+    d = np.nonzero(kind == KIND_DIFFRACTION)[0]
+    q = st.pts[:, d]
+    on_corner = (np.isclose(q[0], x0) | np.isclose(q[0], x1)) & (np.isclose(q[1], y0) |
+                                                               np.isclose(q[1], y1))
+    assert on_corner.all() and np.all(st.mat_n[d] == 1) and np.all(st.mat[d] == 1)
+    # fewer specular images than the full set of the empty hallway
+    spec = (kind == 0)
+    assert spec.sum() < 63 * st.n_links
