@@ -408,6 +408,17 @@ rtc_status rtc_adam_step(float* param, const float* grad, float* m, float* v, in
                          int32_t step, float lr, float beta1, float beta2, float eps,
                          void* stream);
 
+/* rtc_adam_step with the step count in device memory, for callers that
+ * record the calibration step into a HIP graph: step is a device int32
+ * holding the number of updates already made; this update uses t = *step + 1
+ * in its bias corrections, and with advance != 0 a kernel ordered after the
+ * update increments *step (several parameter groups of one optimiser step
+ * pass advance = 0 but in the last call).  No host synchronisation, no
+ * allocation, no memset. */
+rtc_status rtc_adam_step_dev(float* param, const float* grad, float* m, float* v, int64_t n,
+                             int32_t* step, int32_t advance, float lr, float beta1, float beta2,
+                             float eps, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

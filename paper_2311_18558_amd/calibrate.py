@@ -74,6 +74,10 @@ class Calibrator:
         self.lr, self.lr_mlp = lr, lr_mlp
         self.lr_gain = lr if lr_gain is None else lr_gain
         self.t = 0
+        # Adam's step count lives on the device so that a recorded graph
+        # advances it on replay
+        self.step_dev = torch.zeros(1, dtype=torch.int32, device=self.dev)
+        self._none = torch.zeros(0, dtype=torch.float32, device=self.dev)
         # one flat FP32 parameter vector: [materials or MLP | patterns | Tx gain]
         segs = []
         if mode == "per_id":
@@ -157,11 +161,13 @@ class Calibrator:
         lib.cfr(self.radio, b, a, psi, self.g, H_out)
         return mats, aux, a, psi
 
-    def step(self, links, update=True):
+    def step(self, links, update=True, batch=None):
         """One iteration of Algorithm 1 on the batch `links`; returns the
         loss terms as a device float64 [3] tensor.  With update=False only
-        the loss and the gradients (self.dparams, self.dLdg) are formed."""
-        b, _ = lib.subset_links(self.dp, links)
+        the loss and the gradients (self.dparams, self.dLdg) are formed.
+        batch: the gathered paths of `links` (lib.subset_links), if the
+        caller has them (no host synchronisation is left then)."""
+        b = lib.subset_links(self.dp, links)[0] if batch is None else batch
         L, P = b.n_links, b.n_paths
         M, N = self.radio.n_elem, self.radio.n_sc
         H = self._buf("H", (L, M, N), torch.complex64)
@@ -202,14 +208,51 @@ class Calibrator:
         self.t += 1
         n = self.n_main
         lr = self.lr_mlp if self.mode == "neural" else self.lr
-        lib.adam_step(self.params[:n], self.dparams[:n], self.m_p[:n], self.v_p[:n], self.t, lr=lr)
+        lib.adam_step_dev(self.params[:n], self.dparams[:n], self.m_p[:n], self.v_p[:n],
+                          self.step_dev, False, lr=lr)
         if self.params.numel() > n:
-            lib.adam_step(self.params[n:], self.dparams[n:], self.m_p[n:], self.v_p[n:], self.t,
-                          lr=self.lr)
+            lib.adam_step_dev(self.params[n:], self.dparams[n:], self.m_p[n:], self.v_p[n:],
+                              self.step_dev, False, lr=self.lr)
         if self.lr_gain > 0:
-            lib.adam_step(self.g_real, torch.view_as_real(dLdg), self.m_g, self.v_g, self.t,
-                          lr=self.lr_gain)
+            lib.adam_step_dev(self.g_real, torch.view_as_real(dLdg), self.m_g, self.v_g,
+                              self.step_dev, False, lr=self.lr_gain)
+        # one optimiser step: advance the shared step count once
+        lib.adam_step_dev(self._none, self._none, self._none, self._none, self.step_dev, True)
         return loss
+
+    def _state(self):
+        return [self.params, self.m_p, self.v_p, self.g_real, self.m_g, self.v_g, self.step_dev,
+                self.alpha]
+
+    def record(self, links, warmup=2):
+        """One step on the fixed batch `links` recorded into a HIP graph
+        (torch.cuda.CUDAGraph): every stage is a library kernel launched on
+        the capture stream, with no host synchronisation, allocation or
+        memset inside.  `warmup` eager steps on a side stream first (buffers
+        and workspaces are allocated there); the parameters and optimiser
+        state are then restored, so replay k of the graph is step k of the
+        calibration.  Returns (graph, loss) with loss the device tensor each
+        replay overwrites."""
+        links = torch.as_tensor(links, device=self.dev)
+        batch = lib.subset_links(self.dp, links)[0]
+        saved = [t.clone() for t in self._state()]
+        t0 = self.t
+        side = torch.cuda.Stream(device=self.dev)
+        side.wait_stream(torch.cuda.current_stream(self.dev))
+        with torch.cuda.stream(side):
+            for _ in range(warmup):
+                self.step(links, batch=batch)
+        torch.cuda.current_stream(self.dev).wait_stream(side)
+        torch.cuda.synchronize(self.dev)
+        for dst, src in zip(self._state(), saved):
+            dst.copy_(src)
+        self.t = t0
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            loss = self.step(links, batch=batch)
+        self.t = t0  # recording ran no step
+        self._graph_keep = (batch, links)
+        return graph, loss
 
     def learned(self):
         """Current materials, patterns and Tx gain as host values: dict with

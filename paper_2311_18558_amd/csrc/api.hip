@@ -28,6 +28,20 @@ rtc_status check_radio(const rtc_radio* r, const char* fn) {
   return RTC_OK;
 }
 
+__global__ void zero_floats_kernel(float* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0f;
+}
+
+rtc_status zero_floats(float* p, int64_t n_floats, hipStream_t s, const char* fn) {
+  if (n_floats <= 0) return RTC_OK;
+  int64_t blocks = (n_floats + 255) / 256;
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(zero_floats_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, n_floats);
+  return check_launch(fn);
+}
+
 rtc_status check_paths(const rtc_paths* p, const char* fn, bool need_geometry) {
   RTC_REQUIRE(p != nullptr, RTC_ERR_INVALID_ARG, "%s: paths is NULL", fn);
   RTC_REQUIRE(p->n_links >= 0 && p->n_paths >= 0, RTC_ERR_SHAPE,

@@ -31,6 +31,10 @@ rtc_status check_mats(const rtc_materials* m, const rtc_paths* p, const char* fn
 
 inline bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
 
+// Zero n_floats floats on the stream with a fill kernel (not a memset node:
+// the entry points stay safe to record into a HIP graph).
+rtc_status zero_floats(float* p, int64_t n_floats, hipStream_t s, const char* fn);
+
 // Fixed-order reduction of a [R][K] double array over rows into dst[K]
 // (device), using tmp (reduce_tmp_doubles(R, K) doubles of device memory).
 rtc_status reduce_all(const double* rows, int64_t R, int K, double* tmp, double* dst,

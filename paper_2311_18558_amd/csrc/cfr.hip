@@ -599,12 +599,7 @@ extern "C" rtc_status rtc_cfr_adjoint(const rtc_radio* radio, const rtc_paths* p
                 "%s: workspace of %zu bytes required", fn, need);
   }
   if (paths->n_links == 0) {
-    if (dLdg) {
-      if (hipMemsetAsync(dLdg, 0, sizeof(float2) * radio->n_elem, s) != hipSuccess) {
-        set_error("%s: hipMemsetAsync failed", fn);
-        return RTC_ERR_HIP;
-      }
-    }
+    if (dLdg) return zero_floats(reinterpret_cast<float*>(dLdg), 2 * (int64_t)radio->n_elem, s, fn);
     return RTC_OK;
   }
   AdjArgs A;

@@ -485,13 +485,7 @@ rtc_status rtc_mlp_backward(const rtc_mlp* net, int64_t n_points, const float* d
   RTC_REQUIRE(n_points >= 0, RTC_ERR_SHAPE, "%s: n_points must be >= 0", fn);
   RTC_REQUIRE(dLdparams, RTC_ERR_INVALID_ARG, "%s: dLdparams is required", fn);
   hipStream_t s = as_stream(stream);
-  if (n_points == 0) {
-    if (hipMemsetAsync(dLdparams, 0, sizeof(float) * kMlpParams, s) != hipSuccess) {
-      set_error("%s: hipMemsetAsync failed", fn);
-      return RTC_ERR_HIP;
-    }
-    return RTC_OK;
-  }
+  if (n_points == 0) return zero_floats(dLdparams, kMlpParams, s, fn);
   RTC_REQUIRE(dLdout && saved, RTC_ERR_INVALID_ARG, "%s: dLdout and saved are required", fn);
   size_t need = rtc_mlp_workspace_size(n_points);
   RTC_REQUIRE(ws && ws_bytes >= need, RTC_ERR_WORKSPACE, "%s: workspace of %zu bytes required",
@@ -531,11 +525,9 @@ rtc_status rtc_mlp_backward(const rtc_mlp* net, int64_t n_points, const float* d
   RTC_REQUIRE(n_slices <= kMlpSlices, RTC_ERR_RANGE, "%s: internal slicing error", fn);
   if (n_slices < kMlpSlices) {
     // unused slices contribute zero
-    if (hipMemsetAsync(part + (int64_t)n_slices * kMlpParams, 0,
-                       sizeof(float) * (size_t)(kMlpSlices - n_slices) * kMlpParams, s) != hipSuccess) {
-      set_error("%s: hipMemsetAsync failed", fn);
-      return RTC_ERR_HIP;
-    }
+    if ((st = zero_floats(part + (int64_t)n_slices * kMlpParams,
+                          (int64_t)(kMlpSlices - n_slices) * kMlpParams, s, fn)) != RTC_OK)
+      return st;
   }
   hipLaunchKernelGGL(mlp_wgrad_kernel, dim3(n_slices, 60), dim3(64), 0, s, G);
   if ((st = check_launch(fn)) != RTC_OK) return st;

@@ -92,6 +92,8 @@ _SIGS = {
                                                 c_vp, c_size, c_vp]),
     "rtc_adam_step": (ctypes.c_int, [c_vp, c_vp, c_vp, c_vp, c_i64, c_i32, c_f32, c_f32, c_f32,
                                      c_f32, c_vp]),
+    "rtc_adam_step_dev": (ctypes.c_int, [c_vp, c_vp, c_vp, c_vp, c_i64, c_vp, c_i32, c_f32,
+                                         c_f32, c_f32, c_f32, c_vp]),
     "rtc_mlp_n_params": (c_i32, []),
     "rtc_mlp_saved_size": (c_size, [c_i64]),
     "rtc_mlp_workspace_size": (c_size, [c_i64]),
@@ -339,6 +341,15 @@ def adam_step(param, grad, m, v, step, lr=0.01, beta1=0.9, beta2=0.999, eps=1e-8
     _check(load().rtc_adam_step(_ptr(param), _ptr(grad), _ptr(m), _ptr(v), param.numel(),
                                 int(step), float(lr), float(beta1), float(beta2), float(eps),
                                 _stream(stream)), "rtc_adam_step")
+
+
+def adam_step_dev(param, grad, m, v, step, advance, lr=0.01, beta1=0.9, beta2=0.999, eps=1e-8,
+                  stream=None):
+    """step: int32 device counter of updates made (see rtc_adam_step_dev)."""
+    _check(load().rtc_adam_step_dev(_ptr(param), _ptr(grad), _ptr(m), _ptr(v), param.numel(),
+                                    _ptr(step), int(bool(advance)), float(lr), float(beta1),
+                                    float(beta2), float(eps), _stream(stream)),
+           "rtc_adam_step_dev")
 
 
 # ------------------------------------------------------------ neural materials

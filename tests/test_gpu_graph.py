@@ -1,0 +1,93 @@
+"""The calibration step recorded into a HIP graph: every replay equals the
+eager step it stands for, bit for bit, across several replays with eager
+work and synchronisations between them (per-id materials with element gains
+and the workload loss; embeddings, patterns and Tx gain with the paper loss
+and its scale update; neural materials)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from synth import diffuse
+from synth.params import Radio, draw_gains
+from tests.helpers import multi_material_box, multi_material_box_scene
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu-step] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def setup(gpu_lib):
+    from paper_2311_18558_amd import lib
+    st, raw = multi_material_box(seed=8, n_rx=12, max_depth=2)
+    samples = diffuse.sample_triangles(multi_material_box_scene(), 2, np.random.default_rng(8))
+    st = diffuse.add_diffuse(st, st.tx_pos[0].astype(np.float64), samples,
+                             lambda p, e: np.ones(len(p), bool))
+    radio = Radio(fc=3.5e9, bandwidth=50e6, n_sc=256, n_elem=4, ula_axis=(1.0, 0.0, 0.0))
+    g = draw_gains(np.random.default_rng(3), 4)
+    dp = lib.DevicePaths(st)
+    # targets: the library's forward at the raw materials
+    rc = lib.radio_from(radio)
+    a = torch.empty(st.n_paths, dtype=torch.complex64, device="cuda")
+    psi = torch.empty(st.n_paths, dtype=torch.float32, device="cuda")
+    lib.trace_fields(rc, dp, lib.materials_per_id(torch.tensor(raw, device="cuda")), a, psi)
+    H = torch.empty((st.n_links, 4, 256), dtype=torch.complex64, device="cuda")
+    lib.cfr(rc, dp, a, psi, torch.tensor(g, device="cuda"), H)
+    torch.cuda.synchronize()
+    return lib, st, dp, radio, raw, g, H
+
+
+def _make(setup, kind):
+    from paper_2311_18558_amd.calibrate import Calibrator, mlp_out_bias
+    lib, st, dp, radio, raw, g, H = setup
+    rng = np.random.default_rng(5)
+    if kind == "per_id":
+        raw0 = (raw + rng.normal(scale=0.3, size=raw.shape)).astype(np.float32)
+        return Calibrator(dp, radio, H, "per_id", raw0=raw0, lr=0.01)
+    if kind == "embed":
+        L = 8
+        return Calibrator(dp, radio, H, "embed",
+                          embed0=(rng.normal(size=L), rng.normal(size=(3, 4, L)) * 0.1),
+                          n_vmf=2, tx_raw0=np.concatenate([[0.0], np.zeros(4), rng.normal(size=6)]),
+                          pat_raw0=np.tile([0.0, 0.0, 0.0, 0.0, math.log(4.0), math.log(4.0)],
+                                           (3, 1)),
+                          lr=0.01, lr_gain=0.0, loss="paper", update_alpha=True, delta=0.9)
+    from synth.params import mlp_init
+    lo = st.pts.reshape(3, -1).min(1) - 0.1
+    hi = st.pts.reshape(3, -1).max(1) + 0.1
+    return Calibrator(dp, radio, H, "neural", mlp_params0=mlp_init(rng, mlp_out_bias()),
+                      aabb=(lo, hi), lr=0.01, lr_mlp=1e-3)
+
+
+@pytest.mark.parametrize("kind", ["per_id", "embed", "neural"])
+def test_graph_replays_match_eager_steps(setup, kind):
+    lib, st, *_ = setup
+    links = torch.arange(st.n_links, device="cuda")
+    eager = _make(setup, kind)
+    graphed = _make(setup, kind)
+    say(f"graph {kind}: recording")
+    graph, loss_g = graphed.record(links)
+    torch.cuda.synchronize()
+    assert torch.equal(graphed.params, eager.params), "recording changed the parameters"
+    for k in range(5):
+        loss_e = eager.step(links)
+        graph.replay()
+        torch.cuda.synchronize()
+        # eager work between replays
+        _ = (graphed.params * 2.0).sum().item()
+        same = torch.equal(graphed.params, eager.params) and torch.equal(loss_g, loss_e)
+        say(f"  replay {k}: loss {loss_g[0].item():.6e} (eager {loss_e[0].item():.6e}), "
+            f"identical {same}")
+        assert same, k
+        assert torch.equal(graphed.step_dev, eager.step_dev)
+        if kind == "embed":
+            assert torch.equal(graphed.alpha, eager.alpha)
+        if kind == "per_id":
+            assert torch.equal(graphed.g, eager.g)
+    assert int(graphed.step_dev.item()) == 5
