@@ -419,6 +419,11 @@ rtc_status rtc_adam_step_dev(float* param, const float* grad, float* m, float* v
                              int32_t* step, int32_t advance, float lr, float beta1, float beta2,
                              float eps, void* stream);
 
+/* y[i] += alpha * x[i] for float32 arrays of length n: accumulation of
+ * gradients over batches that one optimiser step streams through (the
+ * per-batch entry points overwrite their outputs). */
+rtc_status rtc_axpy(float* y, const float* x, float alpha, int64_t n, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -43,6 +43,14 @@ __global__ void adam_dev_kernel(float* __restrict__ p, const float* __restrict__
   }
 }
 
+// y += alpha x (gradient accumulation over batches)
+__global__ void axpy_kernel(float* __restrict__ y, const float* __restrict__ x, float alpha,
+                            int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = fmaf(alpha, x[i], y[i]);
+}
+
 __global__ void advance_step_kernel(int32_t* step) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *step += 1;
 }
@@ -93,5 +101,17 @@ extern "C" rtc_status rtc_adam_step(float* param, const float* grad, float* m, f
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(adam_kernel, dim3((unsigned)blocks), dim3(256), 0, as_stream(stream), param,
                      grad, m, v, n, lr, beta1, beta2, eps, (float)(1.0 / bc1), (float)(1.0 / bc2));
+  return check_launch(fn);
+}
+
+extern "C" rtc_status rtc_axpy(float* y, const float* x, float alpha, int64_t n, void* stream) {
+  const char* fn = "rtc_axpy";
+  RTC_REQUIRE(n >= 0, RTC_ERR_SHAPE, "%s: n must be >= 0", fn);
+  if (n == 0) return RTC_OK;
+  RTC_REQUIRE(y && x, RTC_ERR_INVALID_ARG, "%s: NULL array", fn);
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(axpy_kernel, dim3((unsigned)blocks), dim3(256), 0, as_stream(stream), y, x,
+                     alpha, n);
   return check_launch(fn);
 }

@@ -94,6 +94,7 @@ _SIGS = {
                                      c_f32, c_vp]),
     "rtc_adam_step_dev": (ctypes.c_int, [c_vp, c_vp, c_vp, c_vp, c_i64, c_vp, c_i32, c_f32,
                                          c_f32, c_f32, c_f32, c_vp]),
+    "rtc_axpy": (ctypes.c_int, [c_vp, c_vp, c_f32, c_i64, c_vp]),
     "rtc_mlp_n_params": (c_i32, []),
     "rtc_mlp_saved_size": (c_size, [c_i64]),
     "rtc_mlp_workspace_size": (c_size, [c_i64]),
@@ -350,6 +351,41 @@ def adam_step_dev(param, grad, m, v, step, advance, lr=0.01, beta1=0.9, beta2=0.
                                     _ptr(step), int(bool(advance)), float(lr), float(beta1),
                                     float(beta2), float(eps), _stream(stream)),
            "rtc_adam_step_dev")
+
+
+def axpy(y, x, alpha=1.0, stream=None):
+    """y += alpha x (float32 device tensors of equal size)."""
+    assert y.numel() == x.numel()
+    _check(load().rtc_axpy(_ptr(y), _ptr(x), float(alpha), y.numel(), _stream(stream)), "rtc_axpy")
+
+
+def replicate_paths(dp, device=None):
+    """A device copy of a DevicePaths (its own memory): input staging for
+    stores made of repeated link sets."""
+    b = DevicePaths.__new__(DevicePaths)
+    for k in ("n_links", "n_paths", "max_depth"):
+        setattr(b, k, getattr(dp, k))
+    for k in ("link_off", "tx_pos", "rx_pos", "depth", "pts", "nrm", "mat", "tau", "kind", "dA",
+              "edge", "mat_n"):
+        v = getattr(dp, k, None)
+        setattr(b, k, None if v is None else v.clone())
+    s = Paths()
+    s.n_links, s.n_paths, s.max_depth = b.n_links, b.n_paths, b.max_depth
+    s.link_off, s.tx_pos, s.rx_pos = (b.link_off.data_ptr(), b.tx_pos.data_ptr(),
+                                      b.rx_pos.data_ptr())
+    s.depth = b.depth.data_ptr()
+    s.kind = None if b.kind is None else b.kind.data_ptr()
+    s.dA = None if b.dA is None else b.dA.data_ptr()
+    DP = b.max_depth * b.n_paths
+    bp, bn = b.pts.data_ptr(), b.nrm.data_ptr()
+    s.px, s.py, s.pz = bp, bp + 4 * DP, bp + 8 * DP
+    s.nx, s.ny, s.nz = bn, bn + 4 * DP, bn + 8 * DP
+    s.mat = b.mat.data_ptr()
+    s.tau = b.tau.data_ptr()
+    s.edge = None if b.edge is None else b.edge.data_ptr()
+    s.mat_n = None if b.mat_n is None else b.mat_n.data_ptr()
+    b.c = s
+    return b
 
 
 # ------------------------------------------------------------ neural materials
