@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define RTC_ABI_VERSION 5
+#define RTC_ABI_VERSION 6
 
 typedef enum {
   RTC_OK = 0,
@@ -131,14 +131,22 @@ typedef struct {
  *           (the trainable-material parametrisation of Sec. III-C with
  *           one-dimensional embeddings and unit read-out); per_inter = NULL.
  *  per-interaction (neural materials, Sec. III-D): per_inter = float
- *           [3 * max_depth*n_paths] holding the rows eps_r, sigma, S, each
- *           indexed like the per-interaction path arrays; raw = NULL.
+ *           [3 * R] holding the rows eps_r, sigma, S of length R; raw = NULL.
+ *           With inter_idx = NULL the rows are indexed like the
+ *           per-interaction path arrays (R = max_depth*n_paths).  Otherwise
+ *           inter_idx = int32 [max_depth*n_paths] maps every used slot
+ *           (k < depth[p]) to its row 0 .. n_inter-1 (R = n_inter; unused
+ *           slots are not read), so that only used interactions are stored
+ *           and evaluated; rtc_trace_fields_adjoint then writes dLd_inter in
+ *           the same compact rows.
  * n_mat <= 512.  mu_r = 1 and the XPD coefficient does not enter specular
  * reflection. */
 typedef struct {
   int32_t n_mat;
   const float* raw;
   const float* per_inter;
+  const int32_t* inter_idx;
+  int64_t n_inter;
 } rtc_materials;
 
 /* Trainable antenna and scattering patterns and cross-polarisation
@@ -304,9 +312,10 @@ rtc_status rtc_cfr_adjoint(const rtc_radio* radio, const rtc_paths* paths, const
 /* Adjoint of rtc_trace_fields: from dLda (c64 [n_paths]) to
  *   per-id mode:          dLd_raw  float [n_mat*3], gradient w.r.t. the raw
  *                         parameters u (overwritten, FP64-accumulated)
- *   per-interaction mode: dLd_inter float [3 * max_depth*n_paths], rows
- *                         dL/d eps_r, dL/d sigma, dL/d S per interaction
- *                         (slots beyond a path's depth are set to 0)
+ *   per-interaction mode: dLd_inter float [3 * R], rows dL/d eps_r,
+ *                         dL/d sigma, dL/d S per interaction in the rows of
+ *                         rtc_materials.per_inter (without inter_idx, slots
+ *                         beyond a path's depth are set to 0)
  * The unused output must be NULL. */
 rtc_status rtc_trace_fields_adjoint(const rtc_radio* radio, const rtc_paths* paths,
                                     const rtc_materials* mats, const void* dLda,

@@ -144,13 +144,16 @@ class Calibrator:
             lib.embed_readout(self.P["v"], self.P["W"], self.raw, self.P.get("pat"))
         if self.mode != "neural":
             return self.mats, None
-        Q = b.max_depth * b.n_paths
+        # the network is evaluated at the batch's used interaction slots only
+        comp = getattr(b, "compact", None)
+        if comp is None:
+            comp = b.compact = lib.compact_interactions(b)
+        idx, Q, pts = comp
         per = self._buf("per", (3, Q), torch.float32)
         saved = self._buf("saved", (int(lib.load().rtc_mlp_saved_size(Q)),), torch.uint8)
         ws = self._buf("mlpws", (int(lib.load().rtc_mlp_workspace_size(Q)),), torch.uint8)
-        pts = b.pts
         lib.mlp_forward(self.net, Q, pts[0], pts[1], pts[2], per, saved, ws)
-        return lib.materials_per_interaction(per), (Q, saved, ws)
+        return lib.materials_per_interaction(per, (idx, Q)), (Q, saved, ws)
 
     def forward(self, b, H_out):
         mats, aux = self._materials(b)
@@ -235,6 +238,8 @@ class Calibrator:
         replay overwrites."""
         links = torch.as_tensor(links, device=self.dev)
         batch = lib.subset_links(self.dp, links)[0]
+        if self.mode == "neural":
+            batch.compact = lib.compact_interactions(batch)
         saved = [t.clone() for t in self._state()]
         t0 = self.t
         side = torch.cuda.Stream(device=self.dev)

@@ -71,6 +71,10 @@ rtc_status check_mats(const rtc_materials* m, const rtc_paths* p, const char* fn
   RTC_REQUIRE(m != nullptr, RTC_ERR_INVALID_ARG, "%s: materials is NULL", fn);
   RTC_REQUIRE((m->raw == nullptr) != (m->per_inter == nullptr), RTC_ERR_INVALID_ARG,
               "%s: exactly one of materials.raw and materials.per_inter must be set", fn);
+  if (m->per_inter && m->inter_idx) {
+    RTC_REQUIRE(m->n_inter >= 0 && m->n_inter <= (int64_t)p->max_depth * p->n_paths,
+                RTC_ERR_SHAPE, "%s: n_inter must be in [0, max_depth * n_paths]", fn);
+  }
   if (m->raw) {
     RTC_REQUIRE(m->n_mat >= 1 && m->n_mat <= kMaxMat, RTC_ERR_RANGE,
                 "%s: n_mat must be in [1, %d]", fn, kMaxMat);

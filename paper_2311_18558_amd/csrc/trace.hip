@@ -60,7 +60,9 @@ struct TraceArgs {
   const uint16_t* mat;
   const double* tau;
   const float* raw;        // per-id raw parameters [n_mat*3] or null
-  const float* per_inter;  // [3*DP] or null
+  const float* per_inter;  // [3*RS] or null
+  const int32_t* inter_idx;  // slot -> row of per_inter (compact rows), or null (row = slot)
+  int64_t RS;              // row length of per_inter and dLd_inter
   int n_vmf;               // Tx gain mixtures (0: isotropic)
   const float* tx_raw;     // [1 + 5 n_vmf] or null
   const float* pat_raw;    // [n_mat_pat * 6] per material K_x and pattern, or null
@@ -117,7 +119,8 @@ RTC_DEV void stage_materials(const TraceArgs& A, MatVal* tab) {
 
 RTC_DEV MatVal interaction_material(const TraceArgs& A, const MatVal* tab, int64_t slot) {
   if (A.per_inter) {
-    return make_mat(A.per_inter[slot], A.per_inter[A.DP + slot], A.per_inter[2 * A.DP + slot],
+    const int64_t r = A.inter_idx ? (int64_t)A.inter_idx[slot] : slot;
+    return make_mat(A.per_inter[r], A.per_inter[A.RS + r], A.per_inter[2 * A.RS + r],
                     A.inv_eps0w);
   }
   int m = A.mat[slot];
@@ -807,10 +810,12 @@ __global__ void __launch_bounds__(kTraceBlock)
         for (int j = 0; j < MAXD; ++j) {
           if (j >= A.max_depth) break;  // the template bound may exceed the store's
           int64_t slot = (int64_t)j * A.n_paths + p;
-          // slots past the depth get zeros
-          dLd_inter[slot] = g_eps[j];
-          dLd_inter[A.DP + slot] = g_sig[j];
-          dLd_inter[2 * A.DP + slot] = g_S[j];
+          // compact rows: used slots only; otherwise slots past the depth get zeros
+          if (A.inter_idx && j >= Q) continue;
+          const int64_t r = A.inter_idx ? (int64_t)A.inter_idx[slot] : slot;
+          dLd_inter[r] = g_eps[j];
+          dLd_inter[A.RS + r] = g_sig[j];
+          dLd_inter[2 * A.RS + r] = g_S[j];
         }
       }
     } else {
@@ -1030,6 +1035,8 @@ static TraceArgs make_args(const rtc_radio* r, const rtc_paths* P, const rtc_mat
   A.tau = P->tau;
   A.raw = M->raw;
   A.per_inter = M->per_inter;
+  A.inter_idx = M->per_inter ? M->inter_idx : nullptr;
+  A.RS = A.inter_idx ? M->n_inter : A.DP;
   A.n_vmf = (pat && pat->tx_raw) ? pat->n_vmf : 0;
   A.tx_raw = pat ? pat->tx_raw : nullptr;
   A.pat_raw = pat ? pat->mat_raw : nullptr;

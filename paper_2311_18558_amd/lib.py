@@ -46,7 +46,8 @@ class Paths(ctypes.Structure):
 
 
 class Materials(ctypes.Structure):
-    _fields_ = [("n_mat", c_i32), ("raw", c_vp), ("per_inter", c_vp)]
+    _fields_ = [("n_mat", c_i32), ("raw", c_vp), ("per_inter", c_vp), ("inter_idx", c_vp),
+                ("n_inter", c_i64)]
 
 
 class Patterns(ctypes.Structure):
@@ -216,13 +217,34 @@ def materials_per_id(raw):
     return m
 
 
-def materials_per_interaction(per_inter):
+def materials_per_interaction(per_inter, compact=None):
+    """per_inter: float32 [3, R] rows eps_r, sigma, S.  compact: the
+    (inter_idx, n_inter) of compact_interactions for rows of used slots
+    only, or None for rows indexed like the path slots."""
     m = Materials()
     m.n_mat = 1
     m.raw = None
     m.per_inter = per_inter.data_ptr()
-    m._keep = per_inter
+    if compact is not None:
+        m.inter_idx = compact[0].data_ptr()
+        m.n_inter = int(compact[1])
+    m._keep = (per_inter, compact)
     return m
+
+
+def compact_interactions(dp):
+    """Rows for the used interaction slots (k < depth[p]) of a DevicePaths,
+    in slot order: returns (inter_idx int32 [D*P] with -1 for unused slots,
+    n_inter, points float32 [3, n_inter]).  Input staging (index operations
+    on the fixed geometry, once per path set)."""
+    D, P = dp.max_depth, dp.n_paths
+    used = (torch.arange(D, device=dp.depth.device)[:, None]
+            < dp.depth.to(torch.int64)[None, :]).reshape(-1)
+    n_inter = int(used.sum().item())
+    idx = torch.full((D * P,), -1, dtype=torch.int32, device=used.device)
+    idx[used] = torch.arange(n_inter, dtype=torch.int32, device=used.device)
+    pts = dp.pts[:, used].contiguous()
+    return idx, n_inter, pts
 
 
 def workspace_size(op, radio, n_links, n_paths, n_mat=1):

@@ -37,7 +37,10 @@ class StreamedCalibration:
         self.rows_total = sum(b.n_links for b in self.batches) * M
         Lmax = max(b.n_links for b in self.batches)
         Pmax = max(b.n_paths for b in self.batches)
-        Qmax = max(b.n_paths * b.max_depth for b in self.batches)
+        # neural materials are evaluated at the used interaction slots only
+        self.compact = ([lib.compact_interactions(b) for b in self.batches]
+                        if mode == "neural" else None)
+        Qmax = max(c[1] for c in self.compact) if self.compact else 0
         self.a = torch.empty(Pmax, dtype=torch.complex64, device=self.dev)
         self.psi = torch.empty(Pmax, dtype=torch.float32, device=self.dev)
         self.dLda = torch.empty(Pmax, dtype=torch.complex64, device=self.dev)
@@ -88,14 +91,13 @@ class StreamedCalibration:
             self.targets.append(t)
 
     # ------------------------------------------------------------- step
-    def _materials(self, b):
+    def _materials(self, i):
         if self.mode == "per_id":
             return self.mats, None
-        Q = b.max_depth * b.n_paths
+        idx, Q, pts = self.compact[i]
         per = self.per[:3 * Q].view(3, Q)
-        pts = b.pts
         lib.mlp_forward(self.net, Q, pts[0], pts[1], pts[2], per, self.saved, self.mlp_ws)
-        return lib.materials_per_interaction(per), Q
+        return lib.materials_per_interaction(per, (idx, Q)), Q
 
     def batch_step(self, i, events=None):
         """Forward, weighted paper loss and reverse pass of batch i; the
@@ -104,7 +106,7 @@ class StreamedCalibration:
         M, N = self.radio.n_elem, self.radio.n_sc
         H = self.H[:b.n_links * M * N]
         w = float(b.n_links * M) / self.rows_total
-        mats, Q = self._materials(b)
+        mats, Q = self._materials(i)
         lib.trace_fields(self.radio, b, mats, self.a, self.psi)
         lib.cfr(self.radio, b, self.a, self.psi, self.g, H)
         lib.paper_loss(self.radio, b.n_links, H, self.targets[i], self.alpha, self.loss_rows[i],

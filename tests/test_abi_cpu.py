@@ -194,3 +194,16 @@ def test_embed_argument_checks(lib):
     assert st == -1 and b"raw" in so.rtc_last_error()
     st = so.rtc_embed_readout_backward(3, 30, q, q, None, None, q, q, None)
     assert st == -1 and b"dLd_raw" in so.rtc_last_error()
+
+
+def test_compact_rows_argument_check(lib):
+    so = lib.load()
+    r = _radio(lib)
+    p = lib.Paths()
+    p.n_links, p.n_paths, p.max_depth = 1, 4, 2
+    p.link_off = p.tx_pos = p.rx_pos = p.depth = p.tau = 16
+    p.px = p.py = p.pz = p.nx = p.ny = p.nz = p.mat = 16
+    m = lib.Materials()
+    m.n_mat, m.per_inter, m.inter_idx, m.n_inter = 1, 16, 16, 9
+    st = so.rtc_trace_fields(ctypes.byref(r), ctypes.byref(p), ctypes.byref(m), None, None, None)
+    assert st == -2 and b"n_inter" in so.rtc_last_error()
