@@ -67,8 +67,8 @@ def kernel_work(name, L, M, N, P, D):
     if name in ("cfr", "cfr_adjoint"):
         return 8.0 * M * N * P, 8.0 * taps + 20.0 * P
     if name == "cfr_loss":
-        # H, H* and the target PDP in, dL/dH out
-        return 0.0, 28.0 * taps
+        # H and H* in (the target PDP formed from H*), dL/dH out
+        return 0.0, 24.0 * taps
     if name in ("trace_fields", "trace_fields_adjoint"):
         # per interaction: point, normal (24 B) + material id (2 B); per path
         # depth (1 B) + tau (8 B); out: a (8 B) + psi (4 B) or in: dL/da
@@ -420,7 +420,7 @@ def summarize_traffic(fetch_csv, write_csv):
     out = {"source_sha": hot_source_sha(), "copy_probe_bytes": COPY_PROBE_BYTES,
            "fetch_scale": sf, "write_scale": sw, "kernels": {}}
     names = {"rtc::cfr_kernel": "cfr", "rtc::cfr_adjoint_kernel": "cfr_adjoint",
-             "rtc::cfr_loss_wave_kernel<10, true>": "cfr_loss",
+             "rtc::cfr_loss_wave_kernel<10, false>": "cfr_loss",
              "rtc::paper_loss_wave_kernel<10, true>": "paper_loss",
              "rtc::gain_products_kernel": "gain_products"}
     lines = ["| kernel | dispatches | FETCH_SIZE (GB) | WRITE_SIZE (GB) | HBM read (GB) "
