@@ -427,10 +427,10 @@ RTC_DEV void diffract(const TraceArgs& A, v3 tx, v3 q, v3 rx, v3 n0f, int64_t p,
   }
 }
 
-// EXT: the optional physics is compiled in -- the trainable Tx gain and
-// scattering patterns, and edge diffraction (the plain chain keeps its
-// register budget without them).
-template <int MAXD, bool SAVE, bool EXT>
+// PAT: the trainable Tx gain and scattering patterns are compiled in; DFR:
+// edge diffraction is (the plain chain keeps its register budget without
+// them; diffraction paths, depth 1, run in their own shallow instance).
+template <int MAXD, bool SAVE, bool PAT, bool DFR>
 RTC_DEV void run_chain(const TraceArgs& A, const MatVal* tab, const VmfTab* vt, const PatVal* ptab,
                        int64_t p, Chain<MAXD, SAVE>& C) {
   int l = find_link(A.link_off, A.n_links, p);
@@ -449,7 +449,7 @@ RTC_DEV void run_chain(const TraceArgs& A, const MatVal* tab, const VmfTab* vt, 
   float2 E0 = make_float2(A.cz_tx, 0.0f);
   float2 E1 = make_float2(A.sz_tx, 0.0f);
   C.G = 1.0f;
-  if (EXT && A.n_vmf > 0) {
+  if (PAT && A.n_vmf > 0) {
     C.G = vmf_gain(*vt, k1);
     const float sg = sqrtf(fmaxf(C.G, 0.0f));
     E0.x *= sg;
@@ -480,7 +480,7 @@ RTC_DEV void run_chain(const TraceArgs& A, const MatVal* tab, const VmfTab* vt, 
       float2 rp, rl, sr;
       fresnel(mv.eta, c, &rp, &rl, &sr);
       const bool dif = A.kind != nullptr && j == Q - 1 && A.kind[slot] == 1;
-      const bool dfr = EXT && A.edge != nullptr && A.kind != nullptr && j == 0 && Q == 1 &&
+      const bool dfr = DFR && A.edge != nullptr && A.kind != nullptr && j == 0 && Q == 1 &&
                        A.kind[slot] == 2;
       if (dfr) {
         MatVal mvn = mv;
@@ -494,7 +494,7 @@ RTC_DEV void run_chain(const TraceArgs& A, const MatVal* tab, const VmfTab* vt, 
         v3 k_s = unit3(sub3(rx, s));
         float f = fmaxf(dot3(k_s, nf), 0.0f) * kInvPi;  // Lambertian
         float kx = 0.0f;
-        if (EXT && A.pat_raw) {
+        if (PAT && A.pat_raw) {
           C.pid = pat_id(A, slot);
           C.pv = ptab[C.pid];
           C.pe = eval_pattern(C.pv, k_in, k_s, nf, c);
@@ -586,17 +586,25 @@ RTC_DEV TraceLds trace_lds(const TraceArgs& A, unsigned char* smem) {
   return L;
 }
 
-template <int MAXD, bool EXT>
+// A first-order diffraction path: depth 1 with kind 2 in its only slot.
+RTC_DEV bool is_dfr_path(const TraceArgs& A, int64_t p) {
+  return A.edge != nullptr && A.kind != nullptr && A.depth[p] == 1 && A.kind[p] == 2;
+}
+
+// Forward.  With diffraction paths in the store (A.edge), the DFR instance
+// handles exactly those and the others skip them.
+template <int MAXD, bool PAT, bool DFR>
 __global__ void __launch_bounds__(kTraceBlock) trace_fields_kernel(TraceArgs A, float2* a,
                                                                     float* psi) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_f[];
   const TraceLds Ls = trace_lds(A, smem_f);
   stage_materials(A, Ls.tab);
-  if constexpr (EXT) stage_patterns(A, Ls.vt, Ls.pt);
+  if constexpr (PAT) stage_patterns(A, Ls.vt, Ls.pt);
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= A.n_paths) return;
+  if (A.edge != nullptr && is_dfr_path(A, p) != DFR) return;
   Chain<MAXD, false> C;
-  run_chain<MAXD, false, EXT>(A, Ls.tab, Ls.vt, Ls.pt, p, C);
+  run_chain<MAXD, false, PAT, DFR>(A, Ls.tab, Ls.vt, Ls.pt, p, C);
   // C_R^H E with a real (isotropic, slant zeta) Rx pattern
   float2 recv = cadd(cscale(C.E0, A.cz_rx), cscale(C.E1, A.sz_rx));
   if (a) a[p] = cscale(recv, C.scale);
@@ -617,7 +625,7 @@ struct GradLayout {
   int mat, pat, tx, stride;  // offsets of the sections (-1 absent), row length
 };
 
-template <int MAXD, bool PER_ID, bool EXT>
+template <int MAXD, bool PER_ID, bool PAT, bool DFR>
 __global__ void __launch_bounds__(kTraceBlock)
     trace_fields_adjoint_kernel(TraceArgs A, const float2* dLda, float* dLd_inter,
                                 double* block_part, GradLayout GL) {
@@ -626,7 +634,7 @@ __global__ void __launch_bounds__(kTraceBlock)
   MatVal* tab = Ls.tab;
   double* acc = Ls.acc;
   stage_materials(A, tab);
-  if constexpr (EXT) stage_patterns(A, Ls.vt, Ls.pt);
+  if constexpr (PAT) stage_patterns(A, Ls.vt, Ls.pt);
   if (GL.stride > 0) {
     for (int i = threadIdx.x; i < GL.stride * (int)(blockDim.x >> 6); i += blockDim.x) acc[i] = 0.0;
     __syncthreads();
@@ -639,6 +647,8 @@ __global__ void __launch_bounds__(kTraceBlock)
        base += (int64_t)gridDim.x * blockDim.x) {
     int64_t p = base + threadIdx.x;
     bool valid = p < A.n_paths;
+    // with diffraction paths in the store the DFR instance takes exactly those
+    if (valid && A.edge != nullptr) valid = is_dfr_path(A, p) == DFR;
     float g_eps[MAXD], g_sig[MAXD], g_S[MAXD];
     int ids[MAXD];
     int Q = 0;
@@ -658,12 +668,12 @@ __global__ void __launch_bounds__(kTraceBlock)
     }
     if (valid) {
       Chain<MAXD, true> C;
-      run_chain<MAXD, true, EXT>(A, tab, Ls.vt, Ls.pt, p, C);
+      run_chain<MAXD, true, PAT, DFR>(A, tab, Ls.vt, Ls.pt, p, C);
       Q = C.Q;
       float2 Ga = dLda[p];
       dfr_path = C.dfr;
       k1 = C.k1;
-      if (EXT && GL.tx >= 0 && C.G > 0.0f) {
+      if (PAT && GL.tx >= 0 && C.G > 0.0f) {
         // a is proportional to sqrt(G): dL/dG = Re(conj(a) dL/da) / (2 G)
         const float2 recv = cadd(cscale(C.E0, A.cz_rx), cscale(C.E1, A.sz_rx));
         const float2 av = cscale(recv, C.scale);
@@ -675,7 +685,7 @@ __global__ void __launch_bounds__(kTraceBlock)
       float2 w1 = make_float2(K * (A.cz_rx * C.Dq[1] + A.sz_rx * C.Dq[3]), 0.0f);
 #pragma unroll
       for (int j = MAXD - 1; j >= 0; --j) {
-        if (EXT && j == 0 && C.dfr) {
+        if (DFR && j == 0 && C.dfr) {
           // a = w0 (-D_s yb) + w1 (-D_h yp) with D = W01 + R0 W2 + Rn W3:
           // da/deta_0 = -(w0 yb dR0s/deta + w1 yp dR0h/deta) W2, likewise
           // face n with W3 (the covector w is real here: Q = 1)
@@ -731,11 +741,11 @@ __global__ void __launch_bounds__(kTraceBlock)
           // K (qR0 sqrt(1 - K_x) + qR1 sqrt(K_x)) |E_s|
           const float qR0 = A.cz_rx * C.Dq[0] + A.sz_rx * C.Dq[2];
           const float qR1 = A.cz_rx * C.Dq[1] + A.sz_rx * C.Dq[3];
-          const float kx = (EXT && A.pat_raw) ? C.pv.kx : 0.0f;
+          const float kx = (PAT && A.pat_raw) ? C.pv.kx : 0.0f;
           const float sk0 = sqrtf(1.0f - kx), sk1 = sqrtf(kx);
           const float qR = qR0 * sk0 + qR1 * sk1;
           const float gam = Ga.x * K * qR;
-          if (EXT && GL.pat >= 0) {
+          if (PAT && GL.pat >= 0) {
             // d a/du_kx with K_x = logistic(u): K |E_s| K_x (1 - K_x)
             //   (-qR0 / (2 sqrt(1 - K_x)) + qR1 / (2 sqrt(K_x)))
             const float As = C.mv[j].S * C.G0 * C.nv;
@@ -817,10 +827,20 @@ __global__ void __launch_bounds__(kTraceBlock)
           dLd_inter[A.RS + r] = g_sig[j];
           dLd_inter[2 * A.RS + r] = g_S[j];
         }
+        if constexpr (DFR) {
+          // the shallow instance's slots end at MAXD: the rest of the rows get zeros
+          if (!A.inter_idx)
+            for (int j = MAXD; j < A.max_depth; ++j) {
+              const int64_t slot = (int64_t)j * A.n_paths + p;
+              dLd_inter[slot] = 0.0f;
+              dLd_inter[A.RS + slot] = 0.0f;
+              dLd_inter[2 * A.RS + slot] = 0.0f;
+            }
+        }
       }
     } else {
       // a diffraction path carries its face-n gradient in slot 1
-      if (EXT && dfr_path) Q = 2;
+      if (DFR && dfr_path) Q = 2;
       // Segmented reduction by material id, deterministic: each wave walks
       // the distinct ids present in it in increasing order; for each id the
       // lanes' contributions (fixed order over j) are summed by a butterfly
@@ -861,7 +881,7 @@ __global__ void __launch_bounds__(kTraceBlock)
         }
       }
     }
-    if (EXT && GL.pat >= 0) {
+    if (PAT && GL.pat >= 0) {
       // the same deterministic walk over the pattern ids of the wave
       double* wacc = acc + wave * GL.stride + GL.pat;
       bool done = !valid || pat_m == 0x7fffffff;
@@ -879,7 +899,7 @@ __global__ void __launch_bounds__(kTraceBlock)
         if (mine) done = true;
       }
     }
-    if (EXT && GL.tx >= 0) {
+    if (PAT && GL.tx >= 0) {
       // natural Tx gradients of this path, summed over the wave in order:
       //   eta: G/eta,  w_i: eta c_i e_i,  lam_i: eta w_i c_i e_i ((mu_i.k - 1)
       //   + d ln c_i/d lam_i),  mu_i: eta w_i c_i e_i lam_i k
@@ -1089,7 +1109,8 @@ static GradLayout grad_layout(bool mat, int n_mat, bool pat, int n_mat_pat, bool
 
 static size_t ws_for(int32_t n_paths, const GradLayout& g) {
   if (g.stride == 0) return 0;
-  return (size_t)(adj_blocks(n_paths) + 1) * g.stride * sizeof(double);
+  // per-block partials of the main and the diffraction launch, then the sums
+  return (size_t)(2 * adj_blocks(n_paths) + 1) * g.stride * sizeof(double);
 }
 
 size_t ws_trace_adjoint(int32_t n_paths, int32_t n_mat) {
@@ -1133,16 +1154,17 @@ extern "C" rtc_status rtc_trace_fields_pat(const rtc_radio* radio, const rtc_pat
   dim3 grid((paths->n_paths + kTraceBlock - 1) / kTraceBlock);
   size_t shm = trace_lds_fixed(A);
   hipStream_t s = as_stream(stream);
-  const bool pat = A.n_vmf > 0 || A.pat_raw != nullptr || A.edge != nullptr;
+  const bool pat = A.n_vmf > 0 || A.pat_raw != nullptr;
+  float2* a2 = reinterpret_cast<float2*>(a);
   switch (depth_bucket(paths->max_depth)) {
 #define RTC_CASE(D)                                                                          \
   case D:                                                                                    \
     if (pat)                                                                                 \
-      hipLaunchKernelGGL((trace_fields_kernel<D, true>), grid, dim3(kTraceBlock), shm, s, A, \
-                         reinterpret_cast<float2*>(a), psi);                                 \
+      hipLaunchKernelGGL((trace_fields_kernel<D, true, false>), grid, dim3(kTraceBlock), shm, \
+                         s, A, a2, psi);                                                     \
     else                                                                                     \
-      hipLaunchKernelGGL((trace_fields_kernel<D, false>), grid, dim3(kTraceBlock), shm, s,   \
-                         A, reinterpret_cast<float2*>(a), psi);                              \
+      hipLaunchKernelGGL((trace_fields_kernel<D, false, false>), grid, dim3(kTraceBlock),    \
+                         shm, s, A, a2, psi);                                                \
     break;
     RTC_CASE(1)
     RTC_CASE(2)
@@ -1151,6 +1173,16 @@ extern "C" rtc_status rtc_trace_fields_pat(const rtc_radio* radio, const rtc_pat
     RTC_CASE(6)
     RTC_CASE(8)
 #undef RTC_CASE
+  }
+  if (A.edge) {
+    if ((st = check_launch(fn)) != RTC_OK) return st;
+    // the diffraction paths (depth 1) in their own instance
+    if (pat)
+      hipLaunchKernelGGL((trace_fields_kernel<2, true, true>), grid, dim3(kTraceBlock), shm, s, A,
+                         a2, psi);
+    else
+      hipLaunchKernelGGL((trace_fields_kernel<2, false, true>), grid, dim3(kTraceBlock), shm, s,
+                         A, a2, psi);
   }
   return check_launch(fn);
 }
@@ -1208,13 +1240,15 @@ extern "C" rtc_status rtc_trace_fields_adjoint_pat(
               "%s: %zu bytes of LDS needed (too many materials for the gradients asked)", fn, shm);
   double* part = reinterpret_cast<double*>(ws);
   const float2* g_a = reinterpret_cast<const float2*>(dLda);
-  // the optional physics is compiled in only when the paths or patterns use it
-  const bool pat = A.n_vmf > 0 || A.pat_raw != nullptr || A.edge != nullptr;
-  // diffraction paths keep their face-n gradient in a second slot
-  switch (depth_bucket(paths->edge && per_id && paths->max_depth < 2 ? 2 : paths->max_depth)) {
-#define RTC_LAUNCH(D, ID, EXT, DINT)                                                          \
-  hipLaunchKernelGGL((trace_fields_adjoint_kernel<D, ID, EXT>), dim3(blocks), dim3(kTraceBlock), \
-                     shm, s, A, g_a, DINT, part, GL)
+  // the optional physics is compiled in only when the paths or patterns use
+  // it; diffraction paths (depth 1) run in their own instance, whose
+  // per-block partials follow the main launch's (face n in a second slot)
+  const bool pat = A.n_vmf > 0 || A.pat_raw != nullptr;
+  double* part2 = part + blocks * GL.stride;
+  switch (depth_bucket(paths->max_depth)) {
+#define RTC_LAUNCH(D, ID, PAT, DINT)                                                          \
+  hipLaunchKernelGGL((trace_fields_adjoint_kernel<D, ID, PAT, false>), dim3(blocks),          \
+                     dim3(kTraceBlock), shm, s, A, g_a, DINT, part, GL)
 #define RTC_CASE(D)                                                                           \
   case D:                                                                                     \
     if (per_id) {                                                                             \
@@ -1239,10 +1273,30 @@ extern "C" rtc_status rtc_trace_fields_adjoint_pat(
 #undef RTC_LAUNCH
   }
   if ((st = check_launch(fn)) != RTC_OK) return st;
+  int64_t rows = blocks;
+  if (A.edge) {
+#define RTC_DLAUNCH(ID, PAT, DINT)                                                            \
+  hipLaunchKernelGGL((trace_fields_adjoint_kernel<2, ID, PAT, true>), dim3(blocks),           \
+                     dim3(kTraceBlock), shm, s, A, g_a, DINT, part2, GL)
+    if (per_id) {
+      if (pat)
+        RTC_DLAUNCH(true, true, nullptr);
+      else
+        RTC_DLAUNCH(true, false, nullptr);
+    } else {
+      if (pat)
+        RTC_DLAUNCH(false, true, dLd_inter);
+      else
+        RTC_DLAUNCH(false, false, dLd_inter);
+    }
+#undef RTC_DLAUNCH
+    if ((st = check_launch(fn)) != RTC_OK) return st;
+    rows = 2 * blocks;
+  }
   if (GL.stride > 0) {
-    double* tot = part + blocks * GL.stride;
+    double* tot = part + rows * GL.stride;
     hipLaunchKernelGGL(trace_adjoint_reduce_kernel, dim3(GL.stride), dim3(kTraceBlock), 0, s, part,
-                       (int)blocks, GL.stride, tot);
+                       (int)rows, GL.stride, tot);
     if ((st = check_launch(fn)) != RTC_OK) return st;
     hipLaunchKernelGGL(trace_adjoint_transform_kernel, dim3(1), dim3(kTraceBlock), 0, s, tot, GL,
                        A.n_mat, mats->raw, A.n_mat_pat, A.pat_raw, A.n_vmf, A.tx_raw, dLd_raw,
