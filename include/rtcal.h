@@ -186,13 +186,42 @@ typedef enum {
   RTC_OP_TRACE_FIELDS_ADJOINT = 3,
   RTC_OP_CFR_TARGET_STATS = 4,
   RTC_OP_PAPER_LOSS = 5,
-  RTC_OP_TRACE_FIELDS_ADJOINT_PAT = 6
+  RTC_OP_TRACE_FIELDS_ADJOINT_PAT = 6,
+  RTC_OP_VALIDATE_PATHS = 7
 } rtc_op;
 
 /* Bytes of device workspace `op` needs for n_links links (CFR rows are
  * n_links * radio->n_elem) and n_paths paths.  0 on invalid input. */
 size_t rtc_workspace_size(int op, const rtc_radio* radio, int32_t n_links, int32_t n_paths,
                           int32_t n_mat);
+
+/* Device-side check of a path store (the contract of rtc_paths): counts of
+ * violations per category into counts = device int64 [RTC_N_VALIDATE],
+ * deterministic (no atomics).  Categories: link_off not a CSR of n_paths
+ * (RTC_VAL_LINK_OFF), depth above max_depth (RTC_VAL_DEPTH), a material id
+ * of a used slot (or mat_n of a diffraction path) >= n_mat, when n_mat > 0
+ * (RTC_VAL_MAT), kind above 2 (RTC_VAL_KIND), tau not finite and positive
+ * (RTC_VAL_TAU), a normal or edge direction not of unit length within 1 %
+ * (RTC_VAL_UNIT), a non-finite point or end point (RTC_VAL_NONFINITE), a
+ * negative or non-finite dA of a diffuse slot or a wedge n outside (0, 2]
+ * (RTC_VAL_RANGE).  ws: rtc_workspace_size(RTC_OP_VALIDATE_PATHS, ...)
+ * bytes.  The field kernels clamp material ids and read no entry outside the
+ * arrays, so an invalid store yields wrong values, not faults; this names
+ * what is wrong (the Python binding runs it on every upload when the
+ * environment sets RTCAL_DEBUG=1). */
+enum {
+  RTC_VAL_LINK_OFF = 0,
+  RTC_VAL_DEPTH = 1,
+  RTC_VAL_MAT = 2,
+  RTC_VAL_KIND = 3,
+  RTC_VAL_TAU = 4,
+  RTC_VAL_UNIT = 5,
+  RTC_VAL_NONFINITE = 6,
+  RTC_VAL_RANGE = 7,
+  RTC_N_VALIDATE = 8
+};
+rtc_status rtc_validate_paths(const rtc_paths* paths, int32_t n_mat, int64_t* counts, void* ws,
+                              size_t ws_bytes, void* stream);
 
 /* Per-path field computation (Sec. II-C transfer chain, Sec. II-D-1
  * specular reflection with the Fresnel coefficients of Eqs. fresnel-1/-2,

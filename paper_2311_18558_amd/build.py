@@ -14,7 +14,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB_PATH = os.path.join(HERE, "librtcal.so")
 
 SOURCES = ["api.hip", "trace.hip", "cfr.hip", "loss.hip", "paper_loss.hip", "adam.hip",
-           "mlp.hip", "embed.hip"]
+           "mlp.hip", "embed.hip",
+           "validate.hip"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950",

@@ -223,6 +223,30 @@ class Calibrator:
         lib.adam_step_dev(self._none, self._none, self._none, self._none, self.step_dev, True)
         return loss
 
+    def save(self, path):
+        """Checkpoint: parameters, Adam moments and step count, element
+        gains and their moments, the measurement scale, to an .npz file
+        (plain arrays; load() restores them bit for bit)."""
+        host = {k: t.detach().cpu().numpy() for k, t in
+                zip(("params", "m_p", "v_p", "g_real", "m_g", "v_g", "step_dev", "alpha"),
+                    self._state())}
+        np.savez(path, t=np.array(self.t), mode=np.array(self.mode), **host)
+
+    def load(self, path):
+        """Restore a checkpoint written by save() into a calibrator built
+        with the same configuration (shapes are checked)."""
+        z = np.load(path, allow_pickle=False)
+        if str(z["mode"]) != self.mode:
+            raise ValueError(f"checkpoint of mode {z['mode']}, calibrator of mode {self.mode}")
+        for name, dst in zip(("params", "m_p", "v_p", "g_real", "m_g", "v_g", "step_dev", "alpha"),
+                             self._state()):
+            src = torch.from_numpy(z[name])
+            if src.shape != dst.shape:
+                raise ValueError(f"{name}: checkpoint shape {tuple(src.shape)}, "
+                                 f"calibrator {tuple(dst.shape)}")
+            dst.copy_(src.to(dst.device))
+        self.t = int(z["t"])
+
     def _state(self):
         return [self.params, self.m_p, self.v_p, self.g_real, self.m_g, self.v_g, self.step_dev,
                 self.alpha]

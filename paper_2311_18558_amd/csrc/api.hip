@@ -94,6 +94,7 @@ size_t ws_cfr_adjoint(const rtc_radio* r, int32_t n_links, int32_t n_paths);
 size_t ws_trace_adjoint(int32_t n_paths, int32_t n_mat);
 size_t ws_target_stats(const rtc_radio* r, int32_t n_links);
 size_t ws_paper_loss(const rtc_radio* r, int32_t n_links);
+size_t ws_validate_paths();
 size_t ws_trace_adjoint_pat(int32_t n_paths, int32_t n_mat);
 }  // namespace rtc
 
@@ -119,6 +120,8 @@ size_t rtc_workspace_size(int op, const rtc_radio* radio, int32_t n_links, int32
       return radio ? rtc::ws_paper_loss(radio, n_links) : 0;
     case RTC_OP_TRACE_FIELDS_ADJOINT_PAT:
       return rtc::ws_trace_adjoint_pat(n_paths, n_mat);
+    case RTC_OP_VALIDATE_PATHS:
+      return rtc::ws_validate_paths();
     default:
       return 0;
   }

@@ -96,6 +96,8 @@ _SIGS = {
     "rtc_adam_step_dev": (ctypes.c_int, [c_vp, c_vp, c_vp, c_vp, c_i64, c_vp, c_i32, c_f32,
                                          c_f32, c_f32, c_f32, c_vp]),
     "rtc_axpy": (ctypes.c_int, [c_vp, c_vp, c_f32, c_i64, c_vp]),
+    "rtc_validate_paths": (ctypes.c_int, [ctypes.POINTER(Paths), c_i32, c_vp, c_vp, c_size,
+                                          c_vp]),
     "rtc_mlp_n_params": (c_i32, []),
     "rtc_mlp_saved_size": (c_size, [c_i64]),
     "rtc_mlp_workspace_size": (c_size, [c_i64]),
@@ -204,6 +206,33 @@ class DevicePaths:
         s.edge = self.edge.data_ptr() if has_edge else None
         s.mat_n = self.mat_n.data_ptr() if has_edge else None
         self.c = s
+        if os.environ.get("RTCAL_DEBUG", "0") not in ("", "0"):
+            check_paths(self)
+
+
+RTC_OP_VALIDATE_PATHS = 7
+VALIDATE_NAMES = ("link_off", "depth", "material id", "kind", "tau", "unit vector",
+                  "non-finite coordinate", "dA or wedge n")
+
+
+def validate_paths(paths, n_mat=0, stream=None):
+    """Violation counts per category (host dict) of a device path store
+    (rtc_validate_paths; synchronises the stream)."""
+    dev = paths.link_off.device
+    counts = torch.zeros(8, dtype=torch.int64, device=dev)
+    n = int(load().rtc_workspace_size(RTC_OP_VALIDATE_PATHS, None, 0, 0, 0))
+    ws = torch.empty(max(n, 8), dtype=torch.uint8, device=dev)
+    _check(load().rtc_validate_paths(ctypes.byref(paths.c), int(n_mat), _ptr(counts), _ptr(ws),
+                                     ws.numel(), _stream(stream)), "rtc_validate_paths")
+    return dict(zip(VALIDATE_NAMES, counts.cpu().tolist()))
+
+
+def check_paths(paths, n_mat=0):
+    """Raise if the device-side check finds violations (RTCAL_DEBUG=1 runs it
+    on every DevicePaths upload)."""
+    bad = {k: v for k, v in validate_paths(paths, n_mat).items() if v}
+    if bad:
+        raise RuntimeError(f"invalid path store: {bad}")
 
 
 def materials_per_id(raw):
@@ -248,7 +277,8 @@ def compact_interactions(dp):
 
 
 def workspace_size(op, radio, n_links, n_paths, n_mat=1):
-    return int(load().rtc_workspace_size(op, ctypes.byref(radio), n_links, n_paths, n_mat))
+    rp = None if radio is None else ctypes.byref(radio)
+    return int(load().rtc_workspace_size(op, rp, n_links, n_paths, n_mat))
 
 
 def workspace(op, radio, n_links, n_paths, n_mat=1, device="cuda"):

@@ -207,3 +207,17 @@ def test_compact_rows_argument_check(lib):
     m.n_mat, m.per_inter, m.inter_idx, m.n_inter = 1, 16, 16, 9
     st = so.rtc_trace_fields(ctypes.byref(r), ctypes.byref(p), ctypes.byref(m), None, None, None)
     assert st == -2 and b"n_inter" in so.rtc_last_error()
+
+
+def test_validate_argument_checks(lib):
+    so = lib.load()
+    p = lib.Paths()
+    p.n_links, p.n_paths, p.max_depth = 1, 1, 1
+    p.link_off = p.tx_pos = p.rx_pos = p.depth = p.tau = 16
+    p.px = p.py = p.pz = p.nx = p.ny = p.nz = p.mat = 16
+    q = ctypes.c_void_p(16)
+    st = so.rtc_validate_paths(ctypes.byref(p), 3, None, q, 1 << 20, None)
+    assert st == -1 and b"counts" in so.rtc_last_error()
+    st = so.rtc_validate_paths(ctypes.byref(p), 3, q, q, 8, None)
+    assert st == -4 and b"workspace" in so.rtc_last_error()
+    assert lib.workspace_size(lib.RTC_OP_VALIDATE_PATHS, None, 0, 0, 0) > 0

@@ -91,3 +91,28 @@ def test_graph_replays_match_eager_steps(setup, kind):
         if kind == "per_id":
             assert torch.equal(graphed.g, eager.g)
     assert int(graphed.step_dev.item()) == 5
+
+
+@pytest.mark.parametrize("kind", ["per_id", "embed"])
+def test_checkpoint_resume_is_bitwise(setup, kind, tmp_path):
+    """N steps straight equal N/2 steps, a checkpoint written and read back
+    into a fresh calibrator, and N/2 more steps, bit for bit."""
+    lib, st, *_ = setup
+    links = torch.arange(st.n_links, device="cuda")
+    straight = _make(setup, kind)
+    for _ in range(6):
+        straight.step(links)
+    first = _make(setup, kind)
+    for _ in range(3):
+        first.step(links)
+    path = tmp_path / "ckpt.npz"
+    first.save(path)
+    resumed = _make(setup, kind)
+    resumed.load(path)
+    for _ in range(3):
+        resumed.step(links)
+    torch.cuda.synchronize()
+    assert torch.equal(resumed.params, straight.params)
+    assert torch.equal(resumed.m_p, straight.m_p) and torch.equal(resumed.v_p, straight.v_p)
+    assert torch.equal(resumed.alpha, straight.alpha)
+    assert int(resumed.step_dev.item()) == 6 and resumed.t == 6
