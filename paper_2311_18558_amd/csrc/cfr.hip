@@ -30,6 +30,7 @@
 
 #include "api_common.h"
 #include "dev_common.h"
+#include "fft_block.h"
 #include "split_bf16.h"
 
 namespace rtc {
@@ -220,21 +221,22 @@ struct AdjArgs {
   double fref, t_off, df, cm;  // grid midpoint, t of pair 0, spacing, (M-1)/2
 };
 
-__device__ __forceinline__ int adj_waves_of(const int64_t* off, int l) {
+// Work units of link l: ceil(P_l / unit) (unit = 32 kAdjTP paths for the
+// matrix-core adjoint's waves, kM1Block paths for the single-element one).
+__device__ __forceinline__ int adj_waves_of(const int64_t* off, int l, int unit) {
   const int64_t P = off[l + 1] - off[l];
-  const int64_t tiles = (P + 31) / 32;
-  return (int)((tiles + kAdjTP - 1) / kAdjTP);
+  return (int)((P + unit - 1) / unit);
 }
 
-// Exclusive scan of waves per link (one block, fixed order).
+// Exclusive scan of work units per link (one block, fixed order).
 __global__ void __launch_bounds__(1024) adj_wave_scan_kernel(const int64_t* link_off, int n_links,
-                                                              int64_t* wave_off) {
+                                                              int unit, int64_t* wave_off) {
   __shared__ int64_t part[1024];
   const int t = threadIdx.x;
   const int per = (n_links + 1023) / 1024;
   const int l0 = t * per, l1 = min(n_links, l0 + per);
   int64_t s = 0;
-  for (int l = l0; l < l1; ++l) s += adj_waves_of(link_off, l);
+  for (int l = l0; l < l1; ++l) s += adj_waves_of(link_off, l, unit);
   part[t] = s;
   __syncthreads();
   if (t == 0) {
@@ -249,7 +251,7 @@ __global__ void __launch_bounds__(1024) adj_wave_scan_kernel(const int64_t* link
   int64_t acc = part[t];
   for (int l = l0; l < l1; ++l) {
     wave_off[l] = acc;
-    acc += adj_waves_of(link_off, l);
+    acc += adj_waves_of(link_off, l, unit);
   }
   if (t == 1023) wave_off[n_links] = acc;
 }
@@ -517,6 +519,118 @@ __global__ void __launch_bounds__(kAdjWaves * 64, 2) cfr_adjoint_kernel(AdjArgs 
   }
 }
 
+// ------------------------------------------------- one array element (M = 1)
+// With a single element there is no matrix product (a row of the product
+// is all there is), so these kernels run on the vector units: the forward
+// takes a thread per subcarrier pair and a link's paths from LDS (staged per
+// 256 paths: A' = a g c_p and df tau_p); the adjoint takes a thread per path
+// and the link's pair sums S, D of dL/dH from LDS.  Conjugate pairs as in
+// the matrix-core kernels; the subcarrier phase of every (path, pair) is
+// reduced in FP64 in the forward, and advanced by exp(-j 2 pi df tau) and
+// re-anchored in FP64 every 64 pairs in the adjoint.
+constexpr int kM1Block = 256;
+
+__global__ void __launch_bounds__(kM1Block) cfr_m1_kernel(CfrArgs A, float2* __restrict__ H) {
+  __shared__ float2 sa[kM1Block];   // A' = a g c_p
+  __shared__ double sw[kM1Block];   // df tau_p
+  const int64_t l = blockIdx.x / A.n_qchunk;
+  const int q = (int)(blockIdx.x % A.n_qchunk) * kM1Block + threadIdx.x;
+  const int64_t off0 = A.link_off[l], off1 = A.link_off[l + 1];
+  const float2 g0 = A.g[0];
+  const double t = (double)q + A.t_off;
+  float2 X = make_float2(0.0f, 0.0f), Y = make_float2(0.0f, 0.0f);
+  for (int64_t c0 = off0; c0 < off1; c0 += kM1Block) {
+    const int n = (int)min((int64_t)kM1Block, off1 - c0);
+    __syncthreads();
+    if ((int)threadIdx.x < n) {
+      const int64_t p = c0 + threadIdx.x;
+      const double tau = A.tau[p];
+      sa[threadIdx.x] = cmul(cmul(A.a[p], g0), expm2pi_f64_hw(A.fref * tau));
+      sw[threadIdx.x] = A.df * tau;
+    }
+    __syncthreads();
+    for (int i = 0; i < n; ++i) {
+      const float2 u = expm2pi_f64_hw(t * sw[i]);  // u_p(t_q)
+      const float2 ap = sa[i];
+      X.x = fmaf(ap.x, u.x, X.x);
+      X.y = fmaf(ap.y, u.x, X.y);
+      Y.x = fmaf(ap.x, u.y, Y.x);
+      Y.y = fmaf(ap.y, u.y, Y.y);
+    }
+  }
+  if (q < A.Q) {
+    float2* row = H + l * (int64_t)A.N;
+    const int n_hi = A.N / 2 + q, n_lo = A.N - 1 - n_hi;
+    row[n_hi] = make_float2(X.x - Y.y, X.y + Y.x);  // X + jY
+    if (n_lo != n_hi) row[n_lo] = make_float2(X.x + Y.y, X.y - Y.x);  // X - jY
+  }
+}
+
+__global__ void __launch_bounds__(kM1Block) cfr_adjoint_m1_kernel(AdjArgs A) {
+  __shared__ float4 sd[kM1Block];   // (S, D) of kM1Block pairs
+  __shared__ double red[kM1Block / 64];
+  const int64_t w = blockIdx.x;
+  const int64_t total = A.wave_off[A.n_links];
+  if (w >= total) {
+    // surplus workgroup: its dL/dg partial row is zero
+    if (A.g_part && threadIdx.x < 2) A.g_part[w * 2 + threadIdx.x] = 0.0;
+    return;
+  }
+  int lo = 0, hi = A.n_links - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (A.wave_off[mid] <= w)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const int64_t l = lo;
+  const int64_t off1 = A.link_off[l + 1];
+  const int64_t p = A.link_off[l] + (w - A.wave_off[l]) * kM1Block + threadIdx.x;
+  const bool ok = p < off1;
+  const double tau = ok ? A.tau[p] : 0.0;
+  const float2 v1 = expm2pi_f64_hw(A.df * tau);
+  const float2* row = A.dH + l * (int64_t)A.N;
+  const int N = A.N, Q = A.Q, nh = N / 2;
+  float gre = 0.0f, gim = 0.0f;  // G~ = X - jY, accumulated as in adj_wave
+  float2 u = make_float2(1.0f, 0.0f);
+  for (int q0 = 0; q0 < Q; q0 += kM1Block) {
+    const int nq = min(kM1Block, Q - q0);
+    __syncthreads();
+    if ((int)threadIdx.x < nq) {
+      const int q = q0 + threadIdx.x;
+      const float2 hv = row[nh + q];
+      const bool mid = (N & 1) && q == 0;  // the middle subcarrier pairs with itself
+      const float2 lv = mid ? make_float2(0.0f, 0.0f) : row[N - 1 - nh - q];
+      sd[threadIdx.x] = make_float4(hv.x + lv.x, hv.y + lv.y, hv.x - lv.x, hv.y - lv.y);
+    }
+    __syncthreads();
+    for (int j = 0; j < nq; ++j) {
+      if ((j & 63) == 0) u = expm2pi_f64_hw(((double)(q0 + j) + A.t_off) * A.df * tau);
+      const float4 v = sd[j];
+      // Re G~ += S_re Re u + D_im Im u,  Im G~ += S_im Re u - D_re Im u
+      gre = fmaf(v.x, u.x, fmaf(v.w, u.y, gre));
+      gim = fmaf(v.y, u.x, fmaf(-v.z, u.y, gim));
+      u = cmul(u, v1);
+    }
+  }
+  float2 da = make_float2(0.0f, 0.0f), dg = make_float2(0.0f, 0.0f);
+  if (ok) {
+    const float2 G = cmul(cconj(expm2pi_f64_hw(A.fref * tau)), make_float2(gre, gim));
+    da = cmulc(A.g[0], G);      // conj(g) G
+    dg = cmulc(A.a[p], G);      // conj(a_p) G
+    if (A.dLda) A.dLda[p] = da;
+  }
+  if (A.g_part) {
+    const double sr = block_sum_f64((double)dg.x, red);
+    const double si = block_sum_f64((double)dg.y, red);
+    if (threadIdx.x == 0) {
+      A.g_part[w * 2 + 0] = sr;
+      A.g_part[w * 2 + 1] = si;
+    }
+  }
+}
+
 __global__ void to_c64_kernel(const double* v, int M, float2* out) {
   int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m < M) out[m] = make_float2((float)v[2 * m], (float)v[2 * m + 1]);
@@ -571,6 +685,15 @@ extern "C" rtc_status rtc_cfr(const rtc_radio* radio, const rtc_paths* paths, co
   A.t_off = (A.N % 2 == 0) ? 0.5 : 0.0;
   A.df = radio->df_hz;
   A.cm = 0.5 * (double)(radio->n_elem - 1);
+  if (A.M == 1) {
+    // one element: no matrix product to form; a thread per subcarrier pair
+    A.n_qchunk = (A.Q + kM1Block - 1) / kM1Block;
+    const int64_t blocks = (int64_t)A.n_links * A.n_qchunk;
+    RTC_REQUIRE(blocks < (1ll << 31), RTC_ERR_RANGE, "%s: problem too large for one launch", fn);
+    hipLaunchKernelGGL(cfr_m1_kernel, dim3((unsigned)blocks), dim3(kM1Block), 0,
+                       as_stream(stream), A, reinterpret_cast<float2*>(H));
+    return check_launch(fn);
+  }
   int64_t waves = (int64_t)A.n_links * A.n_mblk * A.n_qchunk;
   int64_t blocks = (waves + kCfrWaves - 1) / kCfrWaves;
   RTC_REQUIRE(blocks < (1ll << 31), RTC_ERR_RANGE, "%s: problem too large for one launch", fn);
@@ -623,19 +746,32 @@ extern "C" rtc_status rtc_cfr_adjoint(const rtc_radio* radio, const rtc_paths* p
   A.t_off = (A.N % 2 == 0) ? 0.5 : 0.0;
   A.df = radio->df_hz;
   A.cm = 0.5 * (double)(radio->n_elem - 1);
+  const bool m1 = radio->n_elem == 1;
   hipLaunchKernelGGL(adj_wave_scan_kernel, dim3(1), dim3(1024), 0, s, paths->link_off,
-                     paths->n_links, wave_off);
+                     paths->n_links, m1 ? kM1Block : 32 * kAdjTP, wave_off);
   if ((st = check_launch(fn)) != RTC_OK) return st;
-  const int64_t blocks = (A.max_waves + kAdjWaves - 1) / kAdjWaves;
-  RTC_REQUIRE(blocks < (1ll << 31), RTC_ERR_RANGE, "%s: problem too large for one launch", fn);
-  hipLaunchKernelGGL(cfr_adjoint_kernel, dim3((unsigned)blocks), dim3(kAdjWaves * 64), 0, s, A);
+  // partial dL/dg rows the launch writes (every one, surplus ones as zeros)
+  int64_t part_rows = A.max_waves;
+  if (m1) {
+    // one workgroup per (link, kM1Block paths): at most n_paths / kM1Block +
+    // n_links of them, within the max_waves partial rows
+    const int64_t blocks = (int64_t)paths->n_paths / kM1Block + paths->n_links + 1;
+    part_rows = blocks;
+    RTC_REQUIRE(blocks <= A.max_waves && blocks < (1ll << 31), RTC_ERR_RANGE,
+                "%s: problem too large for one launch", fn);
+    hipLaunchKernelGGL(cfr_adjoint_m1_kernel, dim3((unsigned)blocks), dim3(kM1Block), 0, s, A);
+  } else {
+    const int64_t blocks = (A.max_waves + kAdjWaves - 1) / kAdjWaves;
+    RTC_REQUIRE(blocks < (1ll << 31), RTC_ERR_RANGE, "%s: problem too large for one launch", fn);
+    hipLaunchKernelGGL(cfr_adjoint_kernel, dim3((unsigned)blocks), dim3(kAdjWaves * 64), 0, s, A);
+  }
   if ((st = check_launch(fn)) != RTC_OK) return st;
   if (dLdg) {
     // dL/dg_m = sum over waves (links in order) of the partials, fixed order, FP64
     const int K = 2 * A.M;
     double* tmp = A.g_part + A.max_waves * K;
     double* red = tmp + reduce_tmp_doubles(A.max_waves, K);
-    if ((st = reduce_all(A.g_part, A.max_waves, K, tmp, red, s, fn)) != RTC_OK) return st;
+    if ((st = reduce_all(A.g_part, part_rows, K, tmp, red, s, fn)) != RTC_OK) return st;
     hipLaunchKernelGGL(to_c64_kernel, dim3((A.M + 63) / 64), dim3(64), 0, s, red, A.M,
                        reinterpret_cast<float2*>(dLdg));
     return check_launch(fn);
