@@ -8,10 +8,11 @@ up to fifth order, ~186 paths per link), inputs resident in HBM.
 Prints ONE JSON line (rank 0):
   value          CFR taps/s (taps = links x elements x subcarriers per step)
   roofline       dominant kernel's algorithmic FLOP/s (8 M N P per launch) from
-                 HIP events on the launch stream, against the ceiling of an
-                 FP32-accurate contraction on the BF16 matrix cores (dense
-                 BF16 peak / 6 split products); its FP32-matrix-peak fraction
-                 is given beside it
+                 HIP events on the launch stream, against the ceiling of its
+                 split contraction on the FP16 matrix cores (dense peak / 3
+                 partial products of the two-way FP16 split, ~2^-22 relative
+                 error per product); its FP32-matrix-peak fraction is given
+                 beside it
   cpu_baseline   the FP64 oracle on a bounded sample of links, host cores
   paper_loss_step  the same step with the paper's own loss (SMAPE of RMS
                  delay spread and gain, moving-average measurement scale)
@@ -37,13 +38,13 @@ import numpy as np  # noqa: E402
 import torch  # noqa: E402
 
 PEAK_FP32_MATRIX_TFLOPS = 157.3  # MI355X dense FP32 MFMA
-PEAK_BF16_MATRIX_TFLOPS = 2500.0  # MI355X dense BF16 MFMA
-SPLIT_PRODUCTS = 6  # BF16 partial products per FP32-accurate product
-PEAK_SPLIT_TFLOPS = PEAK_BF16_MATRIX_TFLOPS / SPLIT_PRODUCTS
+PEAK_F16_MATRIX_TFLOPS = 2500.0  # MI355X dense FP16 / BF16 MFMA
+SPLIT_PRODUCTS = 3  # FP16 partial products per real product (two-way split)
+PEAK_SPLIT_TFLOPS = PEAK_F16_MATRIX_TFLOPS / SPLIT_PRODUCTS
 PEAK_HBM_GBS = 8000.0
 COPY_PROBE_BYTES = 2 << 30
 # sources whose change invalidates the committed HBM counter figures
-HOT_SOURCES = ["cfr.hip", "split_bf16.h", "dev_common.h", "api_common.h", "loss.hip",
+HOT_SOURCES = ["cfr.hip", "split_f16.h", "dev_common.h", "api_common.h", "loss.hip",
                "paper_loss.hip", "fft_wave.h", "fft_block.h"]
 
 
@@ -76,11 +77,11 @@ def kernel_work(name, L, M, N, P, D):
     return 0.0, 0.0
 
 
-MFMA_FLOPS = 2 * 32 * 32 * 16  # one v_mfma_f32_32x32x16_bf16
+MFMA_FLOPS = 2 * 32 * 32 * 16  # one v_mfma_f32_32x32x16_f16
 
 
 def mfma_issued(name, link_off, M, N):
-    """BF16 MFMA instructions one launch of the CFR kernels issues: 24 per
+    """FP16 MFMA instructions one launch of the CFR kernels issues: 12 per
     (16 paths, 32 subcarrier pairs, 32 elements) in the forward product and
     per (32 paths, 16 pairs, 32 elements) in the adjoint; the forward wave
     covers 4 pair tiles, padding included."""
@@ -89,9 +90,9 @@ def mfma_issued(name, link_off, M, N):
     Q = (N + 1) // 2
     if name == "cfr":
         qchunks = -(-Q // 128)
-        return int((-(-cnt // 16)).sum()) * mblk * qchunks * 4 * 24
+        return int((-(-cnt // 16)).sum()) * mblk * qchunks * 4 * 12
     if name == "cfr_adjoint":
-        return int((-(-cnt // 32)).sum()) * mblk * (-(-Q // 16)) * 24
+        return int((-(-cnt // 32)).sum()) * mblk * (-(-Q // 16)) * 12
     return 0
 
 
@@ -525,14 +526,15 @@ def main():
     roofline = {"bound": "mfma", "kernel": hot, "achieved": round(achieved, 2),
                 "peak": round(PEAK_SPLIT_TFLOPS, 1), "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_SPLIT_TFLOPS, 4), "traffic": traffic,
-                "peak_basis": f"dense BF16 {PEAK_BF16_MATRIX_TFLOPS:.0f} TFLOP/s / "
-                              f"{SPLIT_PRODUCTS} split products (FP32-accurate)",
+                "peak_basis": f"dense FP16 {PEAK_F16_MATRIX_TFLOPS:.0f} TFLOP/s / "
+                              f"{SPLIT_PRODUCTS} split products (two-way FP16 split, "
+                              f"~2^-22 relative error per product)",
                 "fp32_matrix_peak_frac": round(achieved / PEAK_FP32_MATRIX_TFLOPS, 4)}
     # what the matrix cores execute: the conjugate-pair form issues half the
-    # BF16 products of the direct one, so this is below frac
+    # products of the direct one, so this is below frac
     issued = mfma_issued(hot, st.link_off, M, N) * MFMA_FLOPS / (per_kernel[hot] * 1e-3) / 1e12
-    roofline["mfma_bf16_issued_tflops"] = round(issued, 1)
-    roofline["mfma_bf16_frac"] = round(issued / PEAK_BF16_MATRIX_TFLOPS, 4)
+    roofline["mfma_issued_tflops"] = round(issued, 1)
+    roofline["mfma_issued_frac"] = round(issued / PEAK_F16_MATRIX_TFLOPS, 4)
     kernels = {}
     for k, ms in per_kernel.items():
         fl_k, by_k = kernel_work(k, L, M, N, P, D)

@@ -5,12 +5,16 @@
 //     B[m, i] = a_i g_m exp(j psi_i (m - c)),  E[i, n] = exp(-j 2 pi f_n tau_i),
 // with M elements, N subcarriers and P_l paths (Eq. cfr_cont, Sec. II-A).
 // Both operands are generated in registers and fed to
-// v_mfma_f32_32x32x16_bf16 as three-way BF16 splits (six partial products
-// per real product, FP32 accumulation; see split_bf16.h), which keeps FP32
-// accuracy at the BF16 instruction rate.  A lane holds eight k values of its
-// row (A) or column (B): in the forward product k runs over paths, so lane l
-// generates the A operand for element row l%32 and the B operand for
-// column l%32 over paths 8(l/32)..+7 of a 16-path chunk.
+// v_mfma_f32_32x32x16_f16 as two-way FP16 splits with FP32 accumulation
+// (three partial products per real product, ~2^-22 relative error per
+// product; split_f16.h).  The exponentials are unit-modulus; the other
+// operand is brought into FP16's range by a power-of-two scale, exact both
+// ways: per link from its largest path coefficient in the forward product,
+// per wave from the running maximum of the dL/dH values read so far in the
+// adjoint.  A lane holds eight k values of its row (A) or column (B): in the
+// forward product k runs over paths, so lane l generates the A operand for
+// element row l%32 and the B operand for column l%32 over paths
+// 8(l/32)..+7 of a 16-path chunk.
 //
 // The forward product uses the symmetry of the subcarrier grid about its
 // midpoint: the exponentials of the subcarriers at offsets +t and -t from
@@ -22,16 +26,13 @@
 //
 // The adjoint G[m, i] = sum_n dLdH[m, n] conj(E[i, n]) is the same kind of
 // product with the subcarriers as the contraction axis: lane l reads eight
-// consecutive subcarriers of its dL/dH row.  Within a 16-subcarrier chunk
-// conj(E) factors into a per-chunk phase of the path times a pattern that is
-// the same for every chunk, so the B operand is split once per wave and the
-// per-chunk phase is applied to the FP32 product (see adj_wave).
+// consecutive subcarrier pairs of its dL/dH row (see adj_wave).
 #include <cmath>
 
 #include "api_common.h"
 #include "dev_common.h"
 #include "fft_block.h"
-#include "split_bf16.h"
+#include "split_f16.h"
 
 namespace rtc {
 
@@ -68,13 +69,38 @@ struct CfrArgs {
 // product took before) yields two subcarriers, and only the real and
 // imaginary parts of u are split.  For odd N pair 0 is the middle
 // subcarrier alone (t = 0, Y = 0).
-RTC_DEV void cfr_pair_tile(const Split3& AR, const Split3& AI, const Split3& UR,
-                           const Split3& UI, floatx16& xr, floatx16& xi, floatx16& yr,
+RTC_DEV void cfr_pair_tile(const Split2& AR, const Split2& AI, const Split2& UR,
+                           const Split2& UI, floatx16& xr, floatx16& xi, floatx16& yr,
                            floatx16& yi) {
-  xr = mac6(AR, UR, xr);
-  xi = mac6(AI, UR, xi);
-  yr = mac6(AR, UI, yr);
-  yi = mac6(AI, UI, yi);
+  xr = mac3(AR, UR, xr);
+  xi = mac3(AI, UR, xi);
+  yr = mac3(AR, UI, yr);
+  yi = mac3(AI, UI, yi);
+}
+
+RTC_DEV float wave_max_f32(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Power-of-two scale that brings the A operand of link [off0, off1) into
+// FP16's range: |Re|, |Im| of a_i g_m exp(j phase) are at most |a_i| |g_m|
+// <= 2 max(|Re a|, |Im a|) max(|Re g|, |Im g|) =: b < 2^e, and the scale
+// 2^(14 - e) puts every value below 2^14 (FP16 holds up to 65504), so
+// values down to 2^-28 of the largest stay normal.  A zero link gets 1;
+// the exponent is clamped so the scale and its inverse are finite FP32.
+RTC_DEV int cfr_link_scale_exp(const float2* a, int64_t off0, int64_t off1, float2 gm, int lane) {
+  float am = 0.0f;
+  for (int64_t p = off0 + lane; p < off1; p += 64) {
+    const float2 v = a[p];
+    am = fmaxf(am, fmaxf(fabsf(v.x), fabsf(v.y)));
+  }
+  am = wave_max_f32(am);
+  const float gx = wave_max_f32(fmaxf(fabsf(gm.x), fabsf(gm.y)));
+  int e = 0;
+  frexpf(2.0f * am * gx, &e);  // b = f 2^e, 0.5 <= f < 1
+  return min(max(e, -100), 100);
 }
 
 // One wave per (link, 32-row element block, kCfrPairTiles x 32 pairs).
@@ -90,7 +116,7 @@ __global__ void __launch_bounds__(kCfrWaves * 64) cfr_kernel(CfrArgs A, float2* 
   if (l >= A.n_links) return;
 
   const int m = mblk * 32 + col;
-  const float2 gm = m < A.M ? A.g[m] : make_float2(0.0f, 0.0f);
+  const float2 g_row = m < A.M ? A.g[m] : make_float2(0.0f, 0.0f);
   const double mc_cyc = ((double)m - A.cm) * kInv2Pi;
   const int q_base = qchunk * 32 * kCfrPairTiles;
   // t of the lane's pair column in tile 0, in subcarrier spacings
@@ -98,6 +124,10 @@ __global__ void __launch_bounds__(kCfrWaves * 64) cfr_kernel(CfrArgs A, float2* 
   const double df32 = 32.0 * A.df;
   const int64_t off0 = A.link_off[l];
   const int64_t off1 = A.link_off[l + 1];
+  // the A operand carries the link's scale 2^sx (exact), removed on output
+  const int sx = 14 - cfr_link_scale_exp(A.a, off0, off1, g_row, lane);
+  const float2 gm = make_float2(ldexpf(g_row.x, sx), ldexpf(g_row.y, sx));
+  const float unscale = ldexpf(1.0f, -sx);
 
   floatx16 acc[kCfrPairTiles][4];
 #pragma unroll
@@ -161,7 +191,7 @@ __global__ void __launch_bounds__(kCfrWaves * 64) cfr_kernel(CfrArgs A, float2* 
       float pp[8];
       double pt[8], tm;
       fetch(c0 + 16, pa, pp, pt, tm);
-      const Split3 AR = split3(ar), AI = split3(ai);
+      const Split2 AR = split2(ar), AI = split2(ai);
 #pragma unroll
       for (int t = 0; t < kCfrPairTiles; ++t) {
         float ur[8], ui[8];
@@ -171,7 +201,7 @@ __global__ void __launch_bounds__(kCfrWaves * 64) cfr_kernel(CfrArgs A, float2* 
           ur[j] = uv[j].x;
           ui[j] = uv[j].y;
         }
-        const Split3 UR = split3(ur), UI = split3(ui);
+        const Split2 UR = split2(ur), UI = split2(ui);
         cfr_pair_tile(AR, AI, UR, UI, acc[t][0], acc[t][1], acc[t][2], acc[t][3]);
       }
       operands(pa, pp, pt, tm, ar, ai, uv, wv);
@@ -189,8 +219,8 @@ __global__ void __launch_bounds__(kCfrWaves * 64) cfr_kernel(CfrArgs A, float2* 
     for (int r = 0; r < 16; ++r) {
       const int row = mblk * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
       if (ok && row < A.M) {
-        const float xr = acc[t][0][r], xi = acc[t][1][r];
-        const float yr = acc[t][2][r], yi = acc[t][3][r];
+        const float xr = acc[t][0][r] * unscale, xi = acc[t][1][r] * unscale;
+        const float yr = acc[t][2][r] * unscale, yi = acc[t][3][r] * unscale;
         float2* Hr = Hl + (int64_t)row * A.N;
         Hr[n_hi] = make_float2(xr - yi, xi + yr);
         if (n_lo != n_hi) Hr[n_lo] = make_float2(xr + yi, xi - yr);
@@ -221,37 +251,48 @@ struct AdjArgs {
   double fref, t_off, df, cm;  // grid midpoint, t of pair 0, spacing, (M-1)/2
 };
 
-// Work units of link l: ceil(P_l / unit) (unit = 32 kAdjTP paths for the
-// matrix-core adjoint's waves, kM1Block paths for the single-element one).
-__device__ __forceinline__ int adj_waves_of(const int64_t* off, int l, int unit) {
-  const int64_t P = off[l + 1] - off[l];
-  return (int)((P + unit - 1) / unit);
-}
-
-// Exclusive scan of work units per link (one block, fixed order).
+// Exclusive scan of work units per link, ceil(P_l / unit) (unit = 32 kAdjTP
+// paths for the matrix-core adjoint's waves, kM1Block paths for the
+// single-element one); one block, thread t owns a contiguous run of links.
 __global__ void __launch_bounds__(1024) adj_wave_scan_kernel(const int64_t* link_off, int n_links,
                                                               int unit, int64_t* wave_off) {
   __shared__ int64_t part[1024];
   const int t = threadIdx.x;
   const int per = (n_links + 1023) / 1024;
   const int l0 = t * per, l1 = min(n_links, l0 + per);
+  // the thread's links in batches of eight (independent loads in flight)
+  auto batch = [&](int l, int (&units)[8]) {
+    int64_t o[9];
+#pragma unroll
+    for (int j = 0; j <= 8; ++j) o[j] = link_off[min(l + j, l1)];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) units[j] = (int)((o[j + 1] - o[j] + unit - 1) / unit);
+  };
   int64_t s = 0;
-  for (int l = l0; l < l1; ++l) s += adj_waves_of(link_off, l, unit);
+  for (int l = l0; l < l1; l += 8) {
+    int units[8];
+    batch(l, units);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s += units[j];
+  }
+  // inclusive scan of the 1024 thread totals (Hillis-Steele, fixed order)
   part[t] = s;
   __syncthreads();
-  if (t == 0) {
-    int64_t acc = 0;
-    for (int i = 0; i < 1024; ++i) {
-      int64_t v = part[i];
-      part[i] = acc;
-      acc += v;
-    }
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int64_t add = t >= o ? part[t - o] : 0;
+    __syncthreads();
+    part[t] += add;
+    __syncthreads();
   }
-  __syncthreads();
-  int64_t acc = part[t];
-  for (int l = l0; l < l1; ++l) {
-    wave_off[l] = acc;
-    acc += adj_waves_of(link_off, l, unit);
+  int64_t acc = part[t] - s;  // exclusive
+  for (int l = l0; l < l1; l += 8) {
+    int units[8];
+    batch(l, units);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      if (l + j < l1) wave_off[l + j] = acc;
+      acc += units[j];
+    }
   }
   if (t == 1023) wave_off[n_links] = acc;
 }
@@ -351,6 +392,14 @@ __device__ __forceinline__ void adj_wave(const AdjArgs& A, int64_t w, int64_t l,
       gre[u] = floatx16{0};
       gim[u] = floatx16{0};
     }
+    // The A operand (sums and differences of dL/dH) carries the wave-wide
+    // scale 2^sx: every value read so far is below lim = 2^(14 - sx), so
+    // scaled it stays below 2^14 (FP16 holds up to 65504) and values down to
+    // 2^-28 of the largest keep all their bits.  A chunk reaching lim lowers
+    // the scale and multiplies the accumulators by the same power of two
+    // (exact); lim = 0 until the first nonzero chunk.
+    int sx = 0;
+    float lim = 0.0f;
     // 16-pair chunks: lane l holds pairs q0 + 8(l/32) + j of its dL/dH row
     // (A operand); the next chunk's values are loaded while the current
     // chunk's MFMAs run.  u_p is anchored in FP64 at the start of every
@@ -397,8 +446,37 @@ __device__ __forceinline__ void adj_wave(const AdjArgs& A, int64_t w, int64_t l,
           di[j] = hv[j].y - lv[j].y;
         }
         if (q0 + 16 < Q) load_chunk(q0 + 16);
-        const Split3 SR = split3(sr), SI = split3(si);
-        const Split3 NDR = split3(ndr), DI = split3(di);
+        float mx = 0.0f;
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          mx = fmaxf(mx, fmaxf(fmaxf(fabsf(sr[j]), fabsf(si[j])),
+                               fmaxf(fabsf(ndr[j]), fabsf(di[j]))));
+        mx = wave_max_f32(mx);
+        if (mx > 0.0f && mx >= lim) {  // the same on every lane
+          int e = 0;
+          frexpf(mx, &e);  // mx < 2^e
+          e = min(max(e, -100), 100);
+          if (lim > 0.0f) {
+            const float f = ldexpf(1.0f, (14 - e) - sx);
+#pragma unroll
+            for (int u = 0; u < NT; ++u) {
+              gre[u] *= f;
+              gim[u] *= f;
+            }
+          }
+          sx = 14 - e;
+          lim = ldexpf(1.0f, e);
+        }
+        const float sc = ldexpf(1.0f, sx);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          sr[j] *= sc;
+          si[j] *= sc;
+          ndr[j] *= sc;
+          di[j] *= sc;
+        }
+        const Split2 SR = split2(sr), SI = split2(si);
+        const Split2 NDR = split2(ndr), DI = split2(di);
 #pragma unroll
         for (int u = 0; u < NT; ++u) {
           if (k > 0) uf[u] = cmul(uf[u], v16[u]);
@@ -410,17 +488,20 @@ __device__ __forceinline__ void adj_wave(const AdjArgs& A, int64_t w, int64_t l,
             ur[j] = e.x;
             ui[j] = e.y;
           }
-          const Split3 UR = split3(ur), UI = split3(ui);
-          gre[u] = mac6(SR, UR, gre[u]);
-          gim[u] = mac6(SI, UR, gim[u]);
-          gre[u] = mac6(DI, UI, gre[u]);
-          gim[u] = mac6(NDR, UI, gim[u]);
+          const Split2 UR = split2(ur), UI = split2(ui);
+          gre[u] = mac3(SR, UR, gre[u]);
+          gim[u] = mac3(SI, UR, gim[u]);
+          gre[u] = mac3(DI, UI, gre[u]);
+          gim[u] = mac3(NDR, UI, gim[u]);
         }
       }
     }
     // epilogue: rows m = mblk*32 + 8(r/4) + 4 half + r%4, column = path
+    const float unscale = ldexpf(1.0f, -sx);
 #pragma unroll
     for (int u = 0; u < NT; ++u) {
+      gre[u] *= unscale;
+      gim[u] *= unscale;
       const int64_t p = path_of(u);
       const bool ok = p < off1;
       const float2 ai = ok ? A.a[p] : make_float2(0.0f, 0.0f);

@@ -25,7 +25,7 @@ namespace rtc {
 constexpr int kLossBlock = 256;
 constexpr int kLossMaxPerThread = kMaxFFT / kLossBlock;  // 16
 constexpr int kRedBlock = 256;
-constexpr int kRedChunk = 4096;  // rows per first-level reduction block
+constexpr int kRedChunk = 64;  // rows per reduction block (first two levels)
 
 // Target statistics per row: {sum |H*|^2, sum (p*)^2}; with Pt also p*.
 __global__ void __launch_bounds__(kLossBlock)
@@ -318,17 +318,37 @@ __global__ void __launch_bounds__(64)
   }
 }
 
-// Fixed-order reduction of [R][K] doubles into [ceil(R/kRedChunk)][K].
+// Fixed-order reduction of [R][K] doubles: block b sums rows
+// [b C, min(R, (b + 1) C)) into out[b][K].  For K <= kRedBlock thread t
+// takes column t % K on row lane t / K (a row is read by K neighbouring
+// threads) and the lanes' partial sums are added in lane order; wider rows
+// are walked column by column by one thread each.
 __global__ void __launch_bounds__(kRedBlock)
-    reduce_rows_kernel(const double* in, int64_t R, int K, double* out) {
-  __shared__ double red[kRedBlock / 64];
-  const int64_t r0 = (int64_t)blockIdx.x * kRedChunk;
-  const int64_t r1 = r0 + kRedChunk < R ? r0 + kRedChunk : R;
-  for (int c = 0; c < K; ++c) {
-    double v = 0.0;
-    for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) v += in[r * K + c];
-    double s = block_sum_f64(v, red);
-    if (threadIdx.x == 0) out[(int64_t)blockIdx.x * K + c] = s;
+    reduce_rows_kernel(const double* in, int64_t R, int K, int64_t C, double* out) {
+  __shared__ double part[kRedBlock];
+  const int64_t r0 = (int64_t)blockIdx.x * C;
+  const int64_t r1 = r0 + C < R ? r0 + C : R;
+  const int t = threadIdx.x;
+  double* dst = out + (int64_t)blockIdx.x * K;
+  if (K > kRedBlock) {
+    for (int c = t; c < K; c += kRedBlock) {
+      double v = 0.0;
+      for (int64_t r = r0; r < r1; ++r) v += in[r * K + c];
+      dst[c] = v;
+    }
+    return;
+  }
+  const int lanes = kRedBlock / K;
+  const int c = t % K, lane = t / K;
+  double v = 0.0;
+  if (lane < lanes)
+    for (int64_t r = r0 + lane; r < r1; r += lanes) v += in[r * K + c];
+  part[t] = v;
+  __syncthreads();
+  if (t < K) {
+    double s = 0.0;
+    for (int i = 0; i < lanes; ++i) s += part[i * K + t];
+    dst[t] = s;
   }
 }
 
@@ -365,17 +385,19 @@ size_t reduce_tmp_doubles(int64_t R, int K) {
 
 rtc_status reduce_all(const double* rows, int64_t R, int K, double* tmp, double* dst,
                       hipStream_t s, const char* fn) {
+  const int64_t C = kRedChunk;
   int64_t R1 = n_red1(R);
-  hipLaunchKernelGGL(reduce_rows_kernel, dim3((unsigned)R1), dim3(kRedBlock), 0, s, rows, R, K,
+  hipLaunchKernelGGL(reduce_rows_kernel, dim3((unsigned)R1), dim3(kRedBlock), 0, s, rows, R, K, C,
                      R1 == 1 ? dst : tmp);
   rtc_status st = check_launch(fn);
   if (st != RTC_OK || R1 == 1) return st;
   int64_t R2 = n_red1(R1);
   double* tmp2 = tmp + R1 * K;
-  hipLaunchKernelGGL(reduce_rows_kernel, dim3((unsigned)R2), dim3(kRedBlock), 0, s, tmp, R1, K,
+  hipLaunchKernelGGL(reduce_rows_kernel, dim3((unsigned)R2), dim3(kRedBlock), 0, s, tmp, R1, K, C,
                      R2 == 1 ? dst : tmp2);
   if ((st = check_launch(fn)) != RTC_OK || R2 == 1) return st;
-  hipLaunchKernelGGL(reduce_rows_kernel, dim3(1), dim3(kRedBlock), 0, s, tmp2, R2, K, dst);
+  // the last level is one block over all R2 rows, whatever their number
+  hipLaunchKernelGGL(reduce_rows_kernel, dim3(1), dim3(kRedBlock), 0, s, tmp2, R2, K, R2, dst);
   return check_launch(fn);
 }
 

@@ -178,6 +178,46 @@ def test_cfr_grid_sizes(rl, n_sc, n_elem):
     assert err <= 1e-5, err
 
 
+@pytest.mark.parametrize("a_exp,g_exp", [(-20, 0), (-6, -3), (0, 3), (9, 0), (15, -3)])
+def test_cfr_amplitude_range(rl, a_exp, g_exp):
+    """The forward product runs its A operand (a_i g_m times a phase) in
+    FP16 parts under a per-link power-of-two scale: amplitudes and element
+    gains far from one, links that differ by up to 1e8 from each other, a
+    1e8 spread of path amplitudes within a link, and an all-zero link, all
+    against the FP64 direct sum of the same FP32 inputs."""
+    _, st, raw, _, _ = tiny_workload(seed=91, n_rx=10, max_depth=3)
+    radio = Radio(fc=3.5e9, bandwidth=50e6, n_sc=300, n_elem=32, ula_axis=(0.0, 0.6, 0.8))
+    rng = np.random.default_rng(1000 + 10 * a_exp + g_exp)
+    a_ref, psi_ref = o_trace_id(st, torch.tensor(raw, dtype=f64), radio.fc,
+                                ula_axis=radio.ula_axis)
+    a = a_ref.clone()
+    off = st.link_off
+    for l in range(st.n_links):
+        lo, hi = int(off[l]), int(off[l + 1])
+        if l == 3:
+            a[lo:hi] = 0  # a link whose paths all vanish
+            continue
+        link_scale = 10.0 ** (a_exp + 8.0 * l / (st.n_links - 1) - 4.0)
+        spread = 10.0 ** (-8.0 * torch.arange(hi - lo, dtype=f64) / max(hi - lo - 1, 1))
+        a[lo:hi] = a[lo:hi] / a[lo:hi].abs().max().clamp_min(1e-300) * spread * link_scale
+    g = (10.0 ** g_exp * rng.uniform(0.5, 2.0, 32) * np.exp(1j * rng.uniform(-3, 3, 32))).astype(
+        np.complex64)
+    a32, p32, g32 = a.to(torch.complex64), psi_ref.to(torch.float32), torch.tensor(g)
+    assert torch.isfinite(torch.view_as_real(a32)).all()
+    H_ref = och.cfr(st.link_off, st.tau, a32.to(c128), p32.to(f64), g32.to(c128), _freqs(radio))
+    say(f"cfr amplitude range a 1e{a_exp} g 1e{g_exp}")
+    dp = rl.DevicePaths(st)
+    H = torch.full((st.n_links, 32, 300), float("nan"), dtype=torch.complex64, device="cuda")
+    rl.cfr(_radio_c(rl, radio), dp, a32.cuda(), p32.cuda(), g32.cuda(), H)
+    torch.cuda.synchronize()
+    Hc = H.cpu()
+    assert torch.isfinite(torch.view_as_real(Hc)).all()
+    assert torch.all(Hc[3] == 0)
+    err = _link_rel_err(Hc, H_ref)
+    say(f"  max per-link relative error {err:.2e}")
+    assert err <= 1e-5, err
+
+
 @pytest.mark.parametrize("case", list(CASES))
 def test_forward_end_to_end(rl, case):
     st, raw, radio, g = CASES[case]
@@ -316,6 +356,59 @@ def test_cfr_adjoint_parity(rl, case):
         say(f"cfr_adjoint {case}: dL/da error {ea:.2e} (max per link {per:.2e})")
         assert per <= 1e-5, per
     eg = (torch.linalg.norm(dLdg.cpu().to(c128) - dg_ref) / torch.linalg.norm(dg_ref)).item()
+    assert eg <= 1e-5, eg
+
+
+@pytest.mark.parametrize("scale", [1e-30, 1e-8, 1.0, 1e25])
+def test_cfr_adjoint_value_range(rl, scale):
+    """The adjoint runs dL/dH in FP16 parts under a wave-wide power-of-two
+    scale that follows the largest value read so far: magnitudes that rise
+    by 1e6 along the subcarrier pairs (the scale is lowered and the partial
+    sums rescaled several times), fall by 1e6, start with zero chunks, an
+    all-zero link, element rows 1e4 apart, and overall scales from 1e-30 to
+    1e25, against the FP64 autograd of the direct sum."""
+    _, st, raw, _, _ = tiny_workload(seed=92, n_rx=6, max_depth=3)
+    radio = Radio(fc=3.5e9, bandwidth=50e6, n_sc=300, n_elem=32, ula_axis=(0.0, 0.6, 0.8))
+    L, M, N = st.n_links, radio.n_elem, radio.n_sc
+    rng = np.random.default_rng(5)
+    a_ref, psi_ref = o_trace_id(st, torch.tensor(raw, dtype=f64), radio.fc,
+                                ula_axis=radio.ula_axis)
+    a32, p32 = a_ref.to(torch.complex64), psi_ref.to(torch.float32)
+    g32 = torch.tensor((rng.uniform(0.5, 2.0, M) * np.exp(1j * rng.uniform(-3, 3, M))).astype(
+        np.complex64))
+    z = rng.normal(size=(L, M, N)) + 1j * rng.normal(size=(L, M, N))
+    dist = np.abs(np.arange(N) - (N - 1) / 2) / (N / 2)  # 0 at the grid's middle, ~1 at its ends
+    prof = np.ones((L, N))
+    prof[0] = 10.0 ** (6 * dist - 6)   # rising along the pairs
+    prof[1] = 10.0 ** (-6 * dist)      # falling
+    prof[2] = np.where(dist < 0.5, 0.0, 1.0)  # zero chunks first
+    prof[3] = 0.0                      # all zero
+    rows = 10.0 ** (-4.0 * np.arange(M) / (M - 1))
+    dH = torch.tensor((z * prof[:, None, :] * rows[None, :, None] * scale).astype(np.complex64))
+    assert torch.isfinite(torch.view_as_real(dH)).all()
+    a64 = a32.to(c128).requires_grad_(True)
+    g64 = g32.to(c128).requires_grad_(True)
+    H = och.cfr(st.link_off, st.tau, a64, p32.to(f64), g64, _freqs(radio))
+    da_ref, dg_ref = torch.autograd.grad(H, (a64, g64), grad_outputs=dH.to(c128))
+    say(f"cfr_adjoint value range scale {scale:g}")
+    dp = rl.DevicePaths(st)
+    rc = _radio_c(rl, radio)
+    ws = rl.workspace(rl.RTC_OP_CFR_ADJOINT, rc, L, st.n_paths)
+    dLda = torch.full((st.n_paths,), float("nan"), dtype=torch.complex64, device="cuda")
+    dLdg = torch.empty(M, dtype=torch.complex64, device="cuda")
+    rl.cfr_adjoint(rc, dp, a32.cuda(), p32.cuda(), g32.cuda(), dH.cuda(), dLda, dLdg, ws)
+    torch.cuda.synchronize()
+    da = dLda.cpu().to(c128)
+    assert torch.isfinite(torch.view_as_real(da)).all()
+    lo, hi = int(st.link_off[3]), int(st.link_off[4])
+    assert torch.all(da[lo:hi] == 0), "an all-zero dL/dH link gives exact zeros"
+    keep = torch.ones(st.n_paths, dtype=torch.bool)
+    keep[lo:hi] = False
+    per = _per_link_rel(da[keep], da_ref[keep],
+                        np.concatenate([st.link_off[:4], st.link_off[5:] - (hi - lo)]))
+    eg = (torch.linalg.norm(dLdg.cpu().to(c128) - dg_ref) / torch.linalg.norm(dg_ref)).item()
+    say(f"  dL/da max per-link error {per:.2e}, dL/dg error {eg:.2e}")
+    assert per <= 1e-5, per
     assert eg <= 1e-5, eg
 
 
