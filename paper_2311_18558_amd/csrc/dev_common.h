@@ -106,16 +106,6 @@ RTC_DEV void sincos2pi(float x, float* s_out, float* c_out) {
   *c_out = c;
 }
 
-// exp(-j 2 pi x) for an FP64 phase x in cycles: frac taken in FP64 (exact),
-// the remainder rounded to FP32 and evaluated by sincos2pi.
-RTC_DEV float2 expm2pi_f64(double x) {
-  double fr = x - floor(x);
-  float f = (float)fr;
-  float s, c;
-  sincos2pi(f, &s, &c);
-  return make_float2(c, -s);
-}
-
 // exp(-j 2 pi x) for an FP64 phase in cycles on the transcendental unit:
 // v_fract_f64 reduces to [0, 1) exactly (a result that would round to 1 is
 // returned as the largest double below it, the same phase), the remainder
@@ -125,14 +115,6 @@ RTC_DEV float2 expm2pi_f64(double x) {
 RTC_DEV float2 expm2pi_f64_hw(double x) {
   const float f = (float)__builtin_amdgcn_fract(x);
   return make_float2(__builtin_amdgcn_cosf(f), -__builtin_amdgcn_sinf(f));
-}
-
-// exp(+j 2 pi x) for an FP32 phase in cycles.
-RTC_DEV float2 expp2pi(float x) {
-  float fr = x - floorf(x);
-  float s, c;
-  sincos2pi(fr, &s, &c);
-  return make_float2(c, s);
 }
 
 // --------------------------------------------------------------- reductions

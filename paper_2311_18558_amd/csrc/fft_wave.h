@@ -131,9 +131,10 @@ template <int R, int SIGN>
 RTC_DEV void fft_twiddle(float2* v, int j, int Ns) {
   if (Ns == 1) return;
   const int k = j % Ns;
-  float s, c;
-  sincos2pi((float)k / (float)(Ns * R), &s, &c);  // exact fraction for powers of two
-  const float2 w = make_float2(c, SIGN * s);
+  // k / (Ns R) is an exact fraction in [0, 1) (powers of two); the
+  // transcendental unit takes it in revolutions
+  const float x = (float)k / (float)(Ns * R);
+  const float2 w = make_float2(__builtin_amdgcn_cosf(x), SIGN * __builtin_amdgcn_sinf(x));
   float2 wr = w;
 #pragma unroll
   for (int r = 1; r < R; ++r) {
