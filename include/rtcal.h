@@ -245,7 +245,11 @@ rtc_status rtc_trace_fields_pat(const rtc_radio* radio, const rtc_paths* paths,
  *   H[l, m, n] = sum_{i in link l} a_i g_m exp(j psi_i (m - (M-1)/2))
  *                                  exp(-j 2 pi f_n tau_i)
  * a: c64 [n_paths], psi: float [n_paths], g: c64 [n_elem] element gains,
- * H: c64 [n_links, n_elem, n_sc] (fully overwritten). */
+ * H: c64 [n_links, n_elem, n_sc] (fully overwritten).  Accuracy: the sum
+ * runs on the FP16 matrix cores as two-part splits (~2^-22 relative error
+ * per product, FP32 accumulation) under an exact power-of-two scale per
+ * link, so any finite FP32 a and g work; measured per-link relative error
+ * against an FP64 direct sum ~3e-7. */
 rtc_status rtc_cfr(const rtc_radio* radio, const rtc_paths* paths, const void* a,
                    const float* psi, const void* g, void* H, void* stream);
 
@@ -333,7 +337,9 @@ rtc_status rtc_eval_ale_rae(int32_t n_links, int32_t n_elem, const double* meas,
  *   dLdg[m]  = sum_i G[m, i] conj(a_i exp(j psi_i (m - c)))      c64 [n_elem]
  * with c = (M-1)/2.  dLdg is reduced over all links in FP64 in a fixed
  * order.  Either output may be NULL; the workspace
- * (rtc_workspace_size(RTC_OP_CFR_ADJOINT, ...)) is always required. */
+ * (rtc_workspace_size(RTC_OP_CFR_ADJOINT, ...)) is always required.
+ * Accuracy as rtc_cfr: FP16 two-part splits, dL/dH under a power-of-two
+ * scale that follows the largest value read, for any finite FP32 input. */
 rtc_status rtc_cfr_adjoint(const rtc_radio* radio, const rtc_paths* paths, const void* a,
                            const float* psi, const void* g, const void* dLdH, void* dLda,
                            void* dLdg, void* ws, size_t ws_bytes, void* stream);
