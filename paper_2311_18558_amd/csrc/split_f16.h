@@ -39,15 +39,28 @@ RTC_DEV unsigned pack_f16(float a, float b) {
   return __builtin_bit_cast(unsigned, v);
 }
 
+// x - h with h the low (LO) or high FP16 half of w, in one v_fma_mix_f32
+// (x * 1 - h, one rounding of an exactly representable difference) instead
+// of a conversion and a subtraction.
+template <bool LO>
+RTC_DEV float sub_f16(float x, unsigned w) {
+  float r;
+  if constexpr (LO)
+    asm("v_fma_mix_f32 %0, %1, 1.0, -%2 op_sel_hi:[0,0,1]" : "=v"(r) : "v"(x), "v"(w));
+  else
+    asm("v_fma_mix_f32 %0, %1, 1.0, -%2 op_sel:[0,0,1] op_sel_hi:[0,0,1]" : "=v"(r)
+        : "v"(x), "v"(w));
+  return r;
+}
+
 RTC_DEV Split2 split2(const float (&x)[8]) {
   u32x4 H, L;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const float a = x[2 * j], b = x[2 * j + 1];
     const unsigned wh = pack_f16(a, b);
-    const halfx2 hv = __builtin_bit_cast(halfx2, wh);
     H[j] = wh;
-    L[j] = pack_f16(a - (float)hv[0], b - (float)hv[1]);
+    L[j] = pack_f16(sub_f16<true>(a, wh), sub_f16<false>(b, wh));
   }
   Split2 s;
   s.h = __builtin_bit_cast(halfx8, H);
