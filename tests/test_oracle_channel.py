@@ -178,3 +178,84 @@ def test_adam_matches_library_optimizer():
         opt.step()
         p, m, v = adam_step(p, gr, m, v, t)
         assert np.allclose(p, pt.detach().numpy(), rtol=1e-14, atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# Values of the workload loss and the held-out NMSE, fixed by hand.
+#
+# A row H*[n] = A exp(-j 2 pi n k / N) is one path at integer tap k: the
+# centred IDFT with 1/sqrt(N) of Sec. II-A puts all of its energy N|A|^2 in
+# one tap, so p* is N|A|^2 at one tap and 0 elsewhere.  These rows make every
+# sum of the loss a closed form: a normaliser taken from the prediction,
+# per row instead of over the batch, or without the squares would change
+# the values below.
+
+def _tap_row(N, amp, k):
+    n = torch.arange(N, dtype=f64)
+    return amp * torch.exp(-2j * math.pi * n * k / N).to(c128)
+
+
+def test_loss_scaled_target_closed_form():
+    """H = c H*: L_coh = |c - 1|^2 and L_pdp = (|c|^2 - 1)^2 for any H*."""
+    rng = np.random.default_rng(11)
+    Ht = torch.tensor(rng.normal(size=(3, 2, 64)) + 1j * rng.normal(size=(3, 2, 64)), dtype=c128)
+    for c in (1.0, 0.5, 1.7 - 0.4j, -1.0, 1j, 0.0):
+        L, coh, inc = channel.cfr_loss(c * Ht, Ht)
+        assert abs(coh.item() - abs(c - 1) ** 2) < 1e-13
+        assert abs(inc.item() - (abs(c) ** 2 - 1) ** 2) < 1e-12
+        assert abs(L.item() - (abs(c - 1) ** 2 + (abs(c) ** 2 - 1) ** 2)) < 1e-12
+        assert abs(channel.nmse(c * Ht, Ht).item() - abs(c - 1) ** 2) < 1e-13
+    # weights multiply the two terms
+    L, coh, inc = channel.cfr_loss(0.5 * Ht, Ht, w_coh=3.0, w_pdp=0.25)
+    assert abs(L.item() - (3.0 * 0.25 + 0.25 * 0.75 ** 2)) < 1e-13
+
+
+def test_loss_zero_prediction_is_one_plus_one():
+    rng = np.random.default_rng(12)
+    Ht = torch.tensor(rng.normal(size=(2, 3, 32)) + 1j * rng.normal(size=(2, 3, 32)), dtype=c128)
+    L, coh, inc = channel.cfr_loss(torch.zeros_like(Ht), Ht)
+    assert abs(coh.item() - 1.0) < 1e-15 and abs(inc.item() - 1.0) < 1e-15
+    assert abs(L.item() - 2.0) < 1e-15
+    assert abs(channel.nmse(torch.zeros_like(Ht), Ht).item() - 1.0) < 1e-15
+
+
+def test_loss_single_tap_rows_by_hand():
+    """A spurious second path B at tap k1 next to the target's path A at
+    tap k0: sum|H - H*|^2 = N|B|^2 against sum|H*|^2 = N|A|^2, and the PDPs
+    differ by N|B|^2 at tap k1 only, against sum (p*)^2 = (N|A|^2)^2."""
+    N = 128
+    A, B = 0.8 - 0.3j, 0.25 + 0.1j
+    Ht = _tap_row(N, A, 9).reshape(1, 1, N)
+    H = Ht + _tap_row(N, B, 40).reshape(1, 1, N)
+    # the PDP itself: N |A|^2 at tap 9, N |B|^2 at tap 40
+    p = channel.pdp(H)[0, 0]
+    assert abs(p[9].item() - N * abs(A) ** 2) < 1e-12 and abs(p[40].item() - N * abs(B) ** 2) < 1e-12
+    assert torch.sum(p).item() == pytest.approx(N * (abs(A) ** 2 + abs(B) ** 2), rel=1e-14)
+    L, coh, inc = channel.cfr_loss(H, Ht)
+    assert coh.item() == pytest.approx(abs(B) ** 2 / abs(A) ** 2, rel=1e-13)
+    # normalised by the target's sum (p*)^2: |B|^4/|A|^4 (the prediction's
+    # sum p^2 would give |B|^4/(|A|^4 + |B|^4))
+    assert inc.item() == pytest.approx(abs(B) ** 4 / abs(A) ** 4, rel=1e-12)
+    assert channel.nmse(H, Ht).item() == pytest.approx(abs(B) ** 2 / abs(A) ** 2, rel=1e-13)
+
+
+def test_loss_normalised_over_the_batch():
+    """Two rows of unequal target energy: each term is one ratio of sums
+    over the whole batch, not a mean of per-row ratios."""
+    N = 64
+    A0, A1 = 2.0, 0.5 + 0.5j          # target energies N*4 and N*0.5
+    c0, c1 = 1.1, 0.6j                # H = c H* row by row
+    Ht = torch.stack([_tap_row(N, A0, 3), _tap_row(N, A1, 20)]).reshape(2, 1, N)
+    H = torch.stack([c0 * Ht[0], c1 * Ht[1]])
+    E0, E1 = N * abs(A0) ** 2, N * abs(A1) ** 2          # sum |H*|^2 per row
+    Q0, Q1 = (N * abs(A0) ** 2) ** 2, (N * abs(A1) ** 2) ** 2  # sum (p*)^2 per row
+    coh_ref = (abs(c0 - 1) ** 2 * E0 + abs(c1 - 1) ** 2 * E1) / (E0 + E1)
+    inc_ref = ((abs(c0) ** 2 - 1) ** 2 * Q0 + (abs(c1) ** 2 - 1) ** 2 * Q1) / (Q0 + Q1)
+    L, coh, inc = channel.cfr_loss(H, Ht)
+    assert coh.item() == pytest.approx(coh_ref, rel=1e-13)
+    assert inc.item() == pytest.approx(inc_ref, rel=1e-12)
+    assert L.item() == pytest.approx(coh_ref + inc_ref, rel=1e-12)
+    # the per-row mean differs markedly here
+    per_row = 0.5 * (abs(c0 - 1) ** 2 + abs(c1 - 1) ** 2)
+    assert abs(per_row - coh_ref) > 0.1
+    assert channel.nmse(H, Ht).item() == pytest.approx(coh_ref, rel=1e-13)
