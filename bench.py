@@ -8,12 +8,12 @@ up to fifth order, ~186 paths per link), inputs resident in HBM.
 Prints ONE JSON line (rank 0):
   value          CFR taps/s (taps = links x elements x subcarriers per step)
   roofline       dominant kernel's algorithmic FLOP/s (8 M N P per launch) from
-                 HIP events on the launch stream, against the ceiling of its
-                 split contraction on the FP16 matrix cores (dense peak / 3
-                 partial products of the two-way FP16 split, ~2^-22 relative
-                 error per product); its FP32-matrix-peak fraction is given
-                 beside it
-  cpu_baseline   the FP64 oracle on a bounded sample of links, host cores
+                 HIP events on the launch stream, against the published dense
+                 FP16 matrix-core peak the contraction runs on (2.5 PFLOP/s);
+                 beside it the ceiling of the two-way FP16 split (three partial
+                 products per real product) and the issued MFMA rate
+  cpu_baseline   the FP64 oracle on a bounded sample of links, on all of
+                 torch's host threads and on one
   paper_loss_step  the same step with the paper's own loss (SMAPE of RMS
                  delay spread and gain, moving-average measurement scale)
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
@@ -42,6 +42,10 @@ PEAK_F16_MATRIX_TFLOPS = 2500.0  # MI355X dense FP16 / BF16 MFMA
 SPLIT_PRODUCTS = 3  # FP16 partial products per real product (two-way split)
 PEAK_SPLIT_TFLOPS = PEAK_F16_MATRIX_TFLOPS / SPLIT_PRODUCTS
 PEAK_HBM_GBS = 8000.0
+# the arithmetic of the CFR contraction: FP32 operands split into two FP16
+# parts each, three FP16 products per real product, FP32 accumulation
+# (~3 * 2^-22 relative error per product); FP64 phase reduction
+DTYPE = "fp16x2-split/fp32-acc"
 COPY_PROBE_BYTES = 2 << 30
 # sources whose change invalidates the committed HBM counter figures
 HOT_SOURCES = ["cfr.hip", "split_f16.h", "dev_common.h", "api_common.h", "loss.hip",
@@ -313,14 +317,26 @@ def config5_bench(steps=1, warmup=1, copies=128):
     return out
 
 
-def cpu_baseline(w, budget_s=15.0, max_links=8192):
-    """The FP64 oracle (forward, loss, reverse-mode gradient) on whole
-    links of the same workload until `budget_s` of CPU time is spent."""
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), or the platform's."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or platform.machine()
+
+
+def _oracle_links(w, budget_s, max_links, seed):
+    """The FP64 oracle (forward, loss, reverse-mode gradient) on whole links
+    of the workload until budget_s of wall time is spent: (links, seconds)."""
     from oracle import channel as och
     from oracle.trace import trace_fields_per_id
     st, radio = w.store, w.radio
     f = och.subcarrier_freqs(radio.fc, radio.bandwidth, radio.n_sc)
-    rng = np.random.default_rng(0)
+    rng = np.random.default_rng(seed)
     raw_gt = torch.tensor(w.raw, dtype=torch.float64)
     g = torch.tensor(w.g, dtype=torch.complex128)
     raw0 = raw_gt + torch.tensor(rng.normal(scale=0.3, size=w.raw.shape))
@@ -341,11 +357,29 @@ def cpu_baseline(w, budget_s=15.0, max_links=8192):
         done += 1
         if t_used >= budget_s:
             break
-    taps = done * radio.n_elem * radio.n_sc
-    return {"value": taps / t_used, "unit": "taps/s", "cores": torch.get_num_threads(),
+    return done, t_used
+
+
+def cpu_baseline(w, budget_s=12.0, budget_1_s=8.0, max_links=8192):
+    """The oracle timed on the host: once with all of torch's intra-op
+    threads (the reported value) and once on one thread."""
+    radio = w.radio
+    n_thr = torch.get_num_threads()
+    done, t_used = _oracle_links(w, budget_s, max_links, seed=0)
+    torch.set_num_threads(1)
+    try:
+        done1, t1 = _oracle_links(w, budget_1_s, max_links, seed=1)
+    finally:
+        torch.set_num_threads(n_thr)
+    per_link = radio.n_elem * radio.n_sc
+    return {"value": done * per_link / t_used, "unit": "taps/s", "cores": n_thr,
             "kind": "oracle",
             "sample": f"{done} whole links of the scale workload (forward, loss and FP64 "
-                      f"autograd gradient; targets precomputed), {t_used:.1f}s"}
+                      f"autograd gradient; targets precomputed), {t_used:.1f}s on {n_thr} "
+                      f"threads",
+            "single_thread": {"value": done1 * per_link / t1, "unit": "taps/s", "cores": 1,
+                              "sample": f"{done1} whole links, {t1:.1f}s"},
+            "host_cpu": cpu_model(), "host_cpus_visible": os.cpu_count()}
 
 
 def calib_compare(w, steps):
@@ -523,15 +557,19 @@ def main():
     fl, _ = kernel_work(hot, L, M, N, P, D)
     achieved = fl / (per_kernel[hot] * 1e-3) / 1e12
     traffic = load_traffic().get(hot)
+    # the contraction runs on the FP16 matrix cores: frac is taken against
+    # their published dense peak; the ceiling of the split arithmetic (three
+    # FP16 products per real product) and what the matrix cores actually
+    # issue (the conjugate-pair form issues half the products of the direct
+    # sum) are reported beside it
     roofline = {"bound": "mfma", "kernel": hot, "achieved": round(achieved, 2),
-                "peak": round(PEAK_SPLIT_TFLOPS, 1), "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_SPLIT_TFLOPS, 4), "traffic": traffic,
-                "peak_basis": f"dense FP16 {PEAK_F16_MATRIX_TFLOPS:.0f} TFLOP/s / "
-                              f"{SPLIT_PRODUCTS} split products (two-way FP16 split, "
-                              f"~2^-22 relative error per product)",
+                "peak": PEAK_F16_MATRIX_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_F16_MATRIX_TFLOPS, 4), "traffic": traffic,
+                "peak_basis": f"MI355X dense FP16 matrix peak {PEAK_F16_MATRIX_TFLOPS:.0f} "
+                              f"TFLOP/s; algorithmic work 8 M N P flops per launch",
+                "split_ceiling_tflops": round(PEAK_SPLIT_TFLOPS, 1),
+                "split_ceiling_frac": round(achieved / PEAK_SPLIT_TFLOPS, 4),
                 "fp32_matrix_peak_frac": round(achieved / PEAK_FP32_MATRIX_TFLOPS, 4)}
-    # what the matrix cores execute: the conjugate-pair form issues half the
-    # products of the direct one, so this is below frac
     issued = mfma_issued(hot, st.link_off, M, N) * MFMA_FLOPS / (per_kernel[hot] * 1e-3) / 1e12
     roofline["mfma_issued_tflops"] = round(issued, 1)
     roofline["mfma_issued_frac"] = round(issued / PEAK_F16_MATRIX_TFLOPS, 4)
@@ -556,7 +594,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "fp32",
+        "dtype": DTYPE,
         "data": "synthetic",
         "config": {"workload": "scale: procedural indoor floor (~5,000 triangles, 10 material "
                                "classes), 1 Tx with a 32-element ULA, 16,384 Rx, specular paths "
