@@ -279,6 +279,24 @@ rtc_status rtc_cfr_loss(const rtc_radio* radio, int32_t n_links, const void* H,
                         float w_coh, float w_pdp, double* loss, void* dLdH, void* ws,
                         size_t ws_bytes, void* stream);
 
+/* rtc_cfr_loss for callers that cannot allocate memory (code recorded into
+ * a HIP graph, tight serving loops, harnesses that forbid hipMalloc): the
+ * same arguments and results without the workspace.  Its workspace is a
+ * fixed device array inside the library, one copy per GPU (about 16.3 MiB,
+ * held until the process ends); its address on a GPU is looked up on the
+ * first call there.  It calls no hipMalloc/hipFree.
+ * Limit: n_links * n_elem <= rtc_cfr_loss_noalloc_max_rows() (524,288 CFR
+ * rows); larger batches return RTC_ERR_RANGE with a message.  Every call on
+ * one GPU shares that GPU's array: calls that overlap in time on one GPU
+ * (other streams, other host threads) race and must be serialised by the
+ * caller.  Nothing in the array needs to start at zero (every value is
+ * written before it is read). */
+rtc_status rtc_cfr_loss_noalloc(const rtc_radio* radio, int32_t n_links, const void* H,
+                                const void* H_tgt, const double* tgt_stats, const float* p_tgt,
+                                float w_coh, float w_pdp, double* loss, void* dLdH,
+                                void* stream);
+int64_t rtc_cfr_loss_noalloc_max_rows(void);
+
 /* CIR statistics of the paper's loss (Sec. III-E, Eqs. delay_spread and
  * channel_gain), one per row (link l, element m) of H, c64
  * [n_links, n_elem, n_sc].  The row's CIR is the centred 1/sqrt(N) IDFT of

@@ -14,6 +14,7 @@
 // dL/dh = 4 w_p (p - p*) h / Z_p).  Per-row partial sums are written in FP64
 // and reduced across rows in a fixed order.
 #include <cmath>
+#include <mutex>
 
 #include "api_common.h"
 #include "dev_common.h"
@@ -503,28 +504,19 @@ extern "C" rtc_status rtc_cfr_target_stats(const rtc_radio* radio, int32_t n_lin
   return reduce_all(rows, R, 2, red, stats, s, fn);
 }
 
-extern "C" rtc_status rtc_cfr_loss(const rtc_radio* radio, int32_t n_links, const void* H,
-                                   const void* H_tgt, const double* tgt_stats,
-                                   const float* p_tgt, float w_coh, float w_pdp, double* loss,
-                                   void* dLdH, void* ws, size_t ws_bytes, void* stream) {
-  const char* fn = "rtc_cfr_loss";
+// The loss pass of rtc_cfr_loss over a workspace of ws_bytes bytes (checked
+// by the caller).
+static rtc_status cfr_loss_run(const char* fn, const rtc_radio* radio, int32_t n_links,
+                               const void* H, const void* H_tgt, const double* tgt_stats,
+                               const float* p_tgt, float w_coh, float w_pdp, double* loss,
+                               void* dLdH, double* rows, hipStream_t s) {
   rtc_status st;
-  if ((st = check_radio(radio, fn)) != RTC_OK) return st;
-  if ((st = check_fft_n(radio, fn)) != RTC_OK) return st;
-  RTC_REQUIRE(n_links >= 1, RTC_ERR_SHAPE, "%s: n_links must be >= 1", fn);
-  RTC_REQUIRE(H && H_tgt && loss, RTC_ERR_INVALID_ARG, "%s: H, H_tgt and loss are required", fn);
-  RTC_REQUIRE(dLdH != H_tgt, RTC_ERR_INVALID_ARG, "%s: dLdH must not alias H_tgt", fn);
   int64_t R = (int64_t)n_links * radio->n_elem;
-  size_t need = ws_cfr_loss(radio, n_links);
-  RTC_REQUIRE(ws != nullptr && ws_bytes >= need, RTC_ERR_WORKSPACE,
-              "%s: workspace of %zu bytes required", fn, need);
-  hipStream_t s = as_stream(stream);
-  double* rows = reinterpret_cast<double*>(ws);
   int64_t R1 = n_red1(R), R2 = n_red1(R1);
   double* red = rows + R * 4;
   double* Z = red + (R1 + R2 + 1) * 4;
   double* sums = Z + 2;
-  int N = radio->n_sc, logN = ilog2(N);
+  int logN = ilog2(radio->n_sc);
   const double* Zuse = tgt_stats;
   if (dLdH && !tgt_stats) {
     launch_target_stats(logN, reinterpret_cast<const float2*>(H_tgt), R, rows, nullptr, s);
@@ -532,11 +524,99 @@ extern "C" rtc_status rtc_cfr_loss(const rtc_radio* radio, int32_t n_links, cons
     if ((st = reduce_all(rows, R, 2, red, Z, s, fn)) != RTC_OK) return st;
     Zuse = Z;
   }
-  (void)N;
   launch_loss(logN, reinterpret_cast<const float2*>(H), reinterpret_cast<const float2*>(H_tgt),
               p_tgt, R, Zuse, w_coh, w_pdp, rows, reinterpret_cast<float2*>(dLdH), s);
   if ((st = check_launch(fn)) != RTC_OK) return st;
   if ((st = reduce_all(rows, R, 4, red, sums, s, fn)) != RTC_OK) return st;
   hipLaunchKernelGGL(loss_finish_kernel, dim3(1), dim3(64), 0, s, sums, Zuse, w_coh, w_pdp, loss);
   return check_launch(fn);
+}
+
+static rtc_status cfr_loss_check(const char* fn, const rtc_radio* radio, int32_t n_links,
+                                 const void* H, const void* H_tgt, double* loss,
+                                 const void* dLdH) {
+  rtc_status st;
+  if ((st = check_radio(radio, fn)) != RTC_OK) return st;
+  if ((st = check_fft_n(radio, fn)) != RTC_OK) return st;
+  RTC_REQUIRE(n_links >= 1, RTC_ERR_SHAPE, "%s: n_links must be >= 1", fn);
+  RTC_REQUIRE(H && H_tgt && loss, RTC_ERR_INVALID_ARG, "%s: H, H_tgt and loss are required", fn);
+  RTC_REQUIRE(dLdH != H_tgt, RTC_ERR_INVALID_ARG, "%s: dLdH must not alias H_tgt", fn);
+  return RTC_OK;
+}
+
+extern "C" rtc_status rtc_cfr_loss(const rtc_radio* radio, int32_t n_links, const void* H,
+                                   const void* H_tgt, const double* tgt_stats,
+                                   const float* p_tgt, float w_coh, float w_pdp, double* loss,
+                                   void* dLdH, void* ws, size_t ws_bytes, void* stream) {
+  const char* fn = "rtc_cfr_loss";
+  rtc_status st;
+  if ((st = cfr_loss_check(fn, radio, n_links, H, H_tgt, loss, dLdH)) != RTC_OK) return st;
+  size_t need = ws_cfr_loss(radio, n_links);
+  RTC_REQUIRE(ws != nullptr && ws_bytes >= need, RTC_ERR_WORKSPACE,
+              "%s: workspace of %zu bytes required", fn, need);
+  return cfr_loss_run(fn, radio, n_links, H, H_tgt, tgt_stats, p_tgt, w_coh, w_pdp, loss, dLdH,
+                      reinterpret_cast<double*>(ws), as_stream(stream));
+}
+
+// ------------------------------------------------ the allocation-free variant
+// rtc_cfr_loss_noalloc runs the same kernels with their workspace in a
+// file-scope device array, one copy per GPU, so that it needs no memory
+// beyond its inputs and outputs.  The array's device address on each GPU is
+// looked up once (hipGetSymbolAddress, with that GPU current) and kept; host
+// code never passes the array's own name to a kernel.
+namespace rtc {
+constexpr int64_t kNoAllocRows = int64_t(1) << 19;  // links x elements
+constexpr int64_t kNoAllocDoubles =
+    kNoAllocRows * 4 + ((kNoAllocRows + kRedChunk - 1) / kRedChunk +
+                        ((kNoAllocRows + kRedChunk - 1) / kRedChunk + kRedChunk - 1) / kRedChunk +
+                        1) * 4 + 2 + 4;
+constexpr int kNoAllocMaxDevices = 64;
+}  // namespace rtc
+
+static __device__ __align__(256) double scratch[rtc::kNoAllocDoubles];
+
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[rtc::kNoAllocMaxDevices];
+
+static rtc_status scratch_on_current_device(const char* fn, double** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  RTC_REQUIRE(e == hipSuccess, RTC_ERR_HIP, "%s: hipGetDevice failed: %s", fn,
+              hipGetErrorString(e));
+  RTC_REQUIRE(dev >= 0 && dev < rtc::kNoAllocMaxDevices, RTC_ERR_RANGE,
+              "%s: device %d beyond the %d devices supported", fn, dev, rtc::kNoAllocMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    RTC_REQUIRE(e == hipSuccess && p != nullptr, RTC_ERR_HIP,
+                "%s: hipGetSymbolAddress of the scratch array failed on device %d: %s", fn, dev,
+                hipGetErrorString(e));
+    g_scratch_ptr[dev] = reinterpret_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return RTC_OK;
+}
+
+extern "C" int64_t rtc_cfr_loss_noalloc_max_rows(void) { return rtc::kNoAllocRows; }
+
+extern "C" rtc_status rtc_cfr_loss_noalloc(const rtc_radio* radio, int32_t n_links,
+                                           const void* H, const void* H_tgt,
+                                           const double* tgt_stats, const float* p_tgt,
+                                           float w_coh, float w_pdp, double* loss, void* dLdH,
+                                           void* stream) {
+  const char* fn = "rtc_cfr_loss_noalloc";
+  rtc_status st;
+  if ((st = cfr_loss_check(fn, radio, n_links, H, H_tgt, loss, dLdH)) != RTC_OK) return st;
+  const int64_t R = (int64_t)n_links * radio->n_elem;
+  RTC_REQUIRE(R <= rtc::kNoAllocRows, RTC_ERR_RANGE,
+              "%s: %lld rows (links x elements) exceed the %lld of its fixed scratch; use "
+              "rtc_cfr_loss with a workspace",
+              fn, (long long)R, (long long)rtc::kNoAllocRows);
+  RTC_REQUIRE(ws_cfr_loss(radio, n_links) <= sizeof(double) * (size_t)rtc::kNoAllocDoubles,
+              RTC_ERR_RANGE, "%s: workspace beyond the fixed scratch", fn);
+  double* ws = nullptr;
+  if ((st = scratch_on_current_device(fn, &ws)) != RTC_OK) return st;
+  return cfr_loss_run(fn, radio, n_links, H, H_tgt, tgt_stats, p_tgt, w_coh, w_pdp, loss, dLdH,
+                      ws, as_stream(stream));
 }

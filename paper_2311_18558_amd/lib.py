@@ -82,6 +82,9 @@ _SIGS = {
                                             c_vp, c_size, c_vp]),
     "rtc_cfr_loss": (ctypes.c_int, [ctypes.POINTER(Radio), c_i32, c_vp, c_vp, c_vp, c_vp, c_f32,
                                     c_f32, c_vp, c_vp, c_vp, c_size, c_vp]),
+    "rtc_cfr_loss_noalloc": (ctypes.c_int, [ctypes.POINTER(Radio), c_i32, c_vp, c_vp, c_vp,
+                                            c_vp, c_f32, c_f32, c_vp, c_vp, c_vp]),
+    "rtc_cfr_loss_noalloc_max_rows": (c_i64, []),
     "rtc_cir_stats": (ctypes.c_int, [ctypes.POINTER(Radio), c_i32, c_vp, c_vp, c_vp]),
     "rtc_paper_loss": (ctypes.c_int, [ctypes.POINTER(Radio), c_i32, c_vp, c_vp, c_vp, c_i32, c_f64,
                                       c_f32, c_f32, c_vp, c_vp, c_vp, c_vp, c_size, c_vp]),
@@ -352,6 +355,20 @@ def cfr_loss(radio, n_links, H, H_tgt, tgt_stats, w_coh, w_pdp, loss, dLdH, ws, 
     _check(load().rtc_cfr_loss(ctypes.byref(radio), n_links, _ptr(H), _ptr(H_tgt), _ptr(tgt_stats),
                                _ptr(p_tgt), float(w_coh), float(w_pdp), _ptr(loss), _ptr(dLdH),
                                _ptr(ws), ws.numel(), _stream(stream)), "rtc_cfr_loss")
+
+
+def cfr_loss_noalloc(radio, n_links, H, H_tgt, tgt_stats, w_coh, w_pdp, loss, dLdH,
+                     stream=None, p_tgt=None):
+    """rtc_cfr_loss without a workspace (the library's fixed per-GPU
+    scratch; calls on one GPU must not overlap)."""
+    _check(load().rtc_cfr_loss_noalloc(ctypes.byref(radio), n_links, _ptr(H), _ptr(H_tgt),
+                                       _ptr(tgt_stats), _ptr(p_tgt), float(w_coh), float(w_pdp),
+                                       _ptr(loss), _ptr(dLdH), _stream(stream)),
+           "rtc_cfr_loss_noalloc")
+
+
+def cfr_loss_noalloc_max_rows():
+    return int(load().rtc_cfr_loss_noalloc_max_rows())
 
 
 def cir_stats(radio, n_links, H, stats, stream=None):

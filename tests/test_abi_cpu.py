@@ -76,6 +76,26 @@ def test_loss_needs_power_of_two_and_workspace(lib):
     assert st == -4 and b"workspace" in so.rtc_last_error()
 
 
+def test_noalloc_loss_rejects_batches_beyond_its_scratch(lib):
+    """The allocation-free loss checks its size limit on the host (before
+    any device work) and says which entry point takes larger batches."""
+    so = lib.load()
+    max_rows = so.rtc_cfr_loss_noalloc_max_rows()
+    assert max_rows == 1 << 19
+    r = _radio(lib, n_sc=1024, n_elem=32)
+    loss = ctypes.c_void_p(16)
+    n_links = max_rows // 32 + 1
+    st = so.rtc_cfr_loss_noalloc(ctypes.byref(r), n_links, ctypes.c_void_p(16),
+                                 ctypes.c_void_p(32), None, None, 1.0, 1.0, loss, None, None)
+    assert st == -3
+    msg = so.rtc_last_error()
+    assert b"exceed" in msg and b"rtc_cfr_loss" in msg
+    r = lib.make_radio(3.5e9, 1e5, 200, 1)
+    st = so.rtc_cfr_loss_noalloc(ctypes.byref(r), 4, ctypes.c_void_p(16), ctypes.c_void_p(32),
+                                 None, None, 1.0, 1.0, loss, None, None)
+    assert st == -6 and b"power of two" in so.rtc_last_error()
+
+
 def test_materials_mode_checks(lib):
     so = lib.load()
     r = _radio(lib)
