@@ -1,9 +1,11 @@
 """Benchmark of the calibration hot path on one MI355X.
 
-One step = trace_fields -> cfr -> cfr_loss (dL/dH in place) -> cfr_adjoint
--> trace_fields_adjoint -> Adam, over the whole `scale` workload (indoor
-floor, 16,384 Rx links x 32 Tx elements x 1,024 subcarriers, specular paths
-up to fifth order, ~186 paths per link), inputs resident in HBM.
+One step = trace_fields -> cfr_loss_adjoint (CFR, workload loss and CFR
+adjoint in one pass per link, H and dL/dH on chip) -> trace_fields_adjoint
+-> Adam, over the whole `scale` workload (indoor floor, 16,384 Rx links x 32
+Tx elements x 1,024 subcarriers, specular paths up to fifth order, ~186
+paths per link), inputs resident in HBM.  The same step with cfr, cfr_loss
+and cfr_adjoint as separate calls is reported beside it.
 
 Prints ONE JSON line (rank 0):
   value          CFR taps/s (taps = links x elements x subcarriers per step)
@@ -74,6 +76,10 @@ def kernel_work(name, L, M, N, P, D):
     if name == "cfr_loss":
         # H and H* in (the target PDP formed from H*), dL/dH out
         return 0.0, 24.0 * taps
+    if name == "cfr_loss_adjoint":
+        # forward and adjoint contractions; H* and the stored target PDP in
+        # (12 B per tap), the path data in and dL/da out
+        return 16.0 * M * N * P, 12.0 * taps + 28.0 * P
     if name in ("trace_fields", "trace_fields_adjoint"):
         # per interaction: point, normal (24 B) + material id (2 B); per path
         # depth (1 B) + tau (8 B); out: a (8 B) + psi (4 B) or in: dL/da
@@ -97,6 +103,9 @@ def mfma_issued(name, link_off, M, N):
         return int((-(-cnt // 16)).sum()) * mblk * qchunks * 4 * 12
     if name == "cfr_adjoint":
         return int((-(-cnt // 32)).sum()) * mblk * (-(-Q // 16)) * 12
+    if name == "cfr_loss_adjoint":
+        # the fused pass runs both products in the same tilings
+        return mfma_issued("cfr", link_off, M, N) + mfma_issued("cfr_adjoint", link_off, M, N)
     return 0
 
 
@@ -149,6 +158,34 @@ def diffuse_bench(steps=3, warmup=1):
     del pipe, H_tgt
     torch.cuda.empty_cache()
     return out
+
+
+def separate_calls_step(st, radio, w, raw0, H_tgt, steps, warmup=1):
+    """The same step with cfr, cfr_loss and cfr_adjoint as three library
+    calls (H and dL/dH through HBM) instead of the fused pass."""
+    from paper_2311_18558_amd.pipeline import Pipeline
+    pipe = Pipeline(st, radio, w.raw, w.g, fused=False)
+    pipe.set_target(H_tgt)
+    pipe.raw.copy_(torch.tensor(raw0, device=pipe.dev))
+    for _ in range(warmup):
+        pipe.step()
+    torch.cuda.synchronize()
+    events = {}
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        pipe.step(events=events)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    per = {k: round(float(np.mean([a.elapsed_time(b) for a, b in v])), 4)
+           for k, v in events.items()}
+    res = {"steps": steps, "ms_per_step": round(ms, 4), "kernels_ms": per}
+    log(f"separate-calls step: {res}")
+    del pipe
+    torch.cuda.empty_cache()
+    return res
 
 
 def paper_loss_step(st, radio, w, raw0, H_tgt, steps, warmup=1):
@@ -553,7 +590,10 @@ def main():
 
     taps = L * M * N
     value = taps / (ms_step * 1e-3)
-    hot = max(("cfr", "cfr_adjoint"), key=lambda k: per_kernel[k])
+    if pipe.fused:
+        hot = "cfr_loss_adjoint"
+    else:
+        hot = max(("cfr", "cfr_adjoint"), key=lambda k: per_kernel[k])
     fl, _ = kernel_work(hot, L, M, N, P, D)
     achieved = fl / (per_kernel[hot] * 1e-3) / 1e12
     traffic = load_traffic().get(hot)
@@ -566,7 +606,9 @@ def main():
                 "peak": PEAK_F16_MATRIX_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_F16_MATRIX_TFLOPS, 4), "traffic": traffic,
                 "peak_basis": f"MI355X dense FP16 matrix peak {PEAK_F16_MATRIX_TFLOPS:.0f} "
-                              f"TFLOP/s; algorithmic work 8 M N P flops per launch",
+                              f"TFLOP/s; algorithmic work "
+                              f"{'16' if hot == 'cfr_loss_adjoint' else '8'} M N P flops "
+                              f"per launch",
                 "split_ceiling_tflops": round(PEAK_SPLIT_TFLOPS, 1),
                 "split_ceiling_frac": round(achieved / PEAK_SPLIT_TFLOPS, 4),
                 "fp32_matrix_peak_frac": round(achieved / PEAK_FP32_MATRIX_TFLOPS, 4)}
@@ -602,12 +644,16 @@ def main():
                    "links": L, "elements": M, "subcarriers": N, "paths": P,
                    "paths_per_link": round(P / L, 1), "max_depth": D},
         "roofline": roofline,
-        "hot_path_tflops": round(fwd_adj_flops / ((per_kernel["cfr"] + per_kernel["cfr_adjoint"])
-                                                   * 1e-3) / 1e12, 2),
+        "hot_path_tflops": round(fwd_adj_flops / (
+            (per_kernel["cfr_loss_adjoint"] if pipe.fused
+             else per_kernel["cfr"] + per_kernel["cfr_adjoint"]) * 1e-3) / 1e12, 2),
         "kernels": kernels,
         "loss": loss[0],
         "wall_s": round(wall, 3),
     }
+    if pipe.fused:
+        out["separate_calls_step"] = separate_calls_step(st, radio, w, raw0, H_tgt,
+                                                         min(args.steps, 5))
     out["paper_loss_step"] = paper_loss_step(st, radio, w, raw0, H_tgt, min(args.steps, 5))
     del pipe, H_tgt
     torch.cuda.empty_cache()

@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define RTC_ABI_VERSION 6
+#define RTC_ABI_VERSION 7
 
 typedef enum {
   RTC_OK = 0,
@@ -187,7 +187,8 @@ typedef enum {
   RTC_OP_CFR_TARGET_STATS = 4,
   RTC_OP_PAPER_LOSS = 5,
   RTC_OP_TRACE_FIELDS_ADJOINT_PAT = 6,
-  RTC_OP_VALIDATE_PATHS = 7
+  RTC_OP_VALIDATE_PATHS = 7,
+  RTC_OP_CFR_LOSS_ADJOINT = 8
 } rtc_op;
 
 /* Bytes of device workspace `op` needs for n_links links (CFR rows are
@@ -361,6 +362,30 @@ rtc_status rtc_eval_ale_rae(int32_t n_links, int32_t n_elem, const double* meas,
 rtc_status rtc_cfr_adjoint(const rtc_radio* radio, const rtc_paths* paths, const void* a,
                            const float* psi, const void* g, const void* dLdH, void* dLda,
                            void* dLdg, void* ws, size_t ws_bytes, void* stream);
+
+/* rtc_cfr, rtc_cfr_loss and rtc_cfr_adjoint as one pass per link, with H
+ * and dL/dH kept on chip (never written to memory):
+ *   H     = the CFR of rtc_cfr (Eq. cfr_cont at the subcarriers of
+ *           Sec. II-A), FP16 two-part splits as there
+ *   loss  = the workload loss of rtc_cfr_loss, device double [3] =
+ *           {L, coherent term, PDP term}
+ *   dLda, dLdg = rtc_cfr_adjoint applied to dL/dH of that loss (either may
+ *           be NULL); dLdg reduced over the links in FP64, fixed order.
+ * The targets' statistics come precomputed: tgt_stats (device double [2])
+ * and p_tgt (target PDP, float [n_links * n_elem * n_sc]) from
+ * rtc_cfr_target_stats of the same H_tgt (c64 [n_links, n_elem, n_sc]).
+ * Shapes: 1 <= n_elem <= 32 and n_sc of 256, 512 or 1024 (a link's whole
+ * CFR, 32 x 1024 subcarriers, fits one workgroup's registers); others return
+ * RTC_ERR_UNSUPPORTED (use the three separate calls).  dL/dH enters the
+ * adjoint under one power-of-two scale per link (its largest value below
+ * 2^14), exact both ways.
+ * ws: rtc_workspace_size(RTC_OP_CFR_LOSS_ADJOINT, radio, n_links, ...)
+ * bytes. */
+rtc_status rtc_cfr_loss_adjoint(const rtc_radio* radio, const rtc_paths* paths, const void* a,
+                                const float* psi, const void* g, const void* H_tgt,
+                                const double* tgt_stats, const float* p_tgt, float w_coh,
+                                float w_pdp, double* loss, void* dLda, void* dLdg, void* ws,
+                                size_t ws_bytes, void* stream);
 
 /* Adjoint of rtc_trace_fields: from dLda (c64 [n_paths]) to
  *   per-id mode:          dLd_raw  float [n_mat*3], gradient w.r.t. the raw

@@ -73,6 +73,15 @@ def pdp(H):
     return N * torch.abs(torch.fft.ifft(H, dim=-1)) ** 2
 
 
+def cfr_loss_sums(H, H_tgt):
+    """The four sums of the workload loss over a batch [B, M, N]:
+    (sum |H - H*|^2, sum |H*|^2, sum (p - p*)^2, sum (p*)^2)."""
+    p = pdp(H)
+    pt = pdp(H_tgt)
+    return (torch.sum(torch.abs(H - H_tgt) ** 2), torch.sum(torch.abs(H_tgt) ** 2),
+            torch.sum((p - pt) ** 2), torch.sum(pt ** 2))
+
+
 def cfr_loss(H, H_tgt, w_coh=1.0, w_pdp=1.0):
     """Coherent + incoherent CFR loss over a batch [B, M, N]:
 
@@ -81,10 +90,9 @@ def cfr_loss(H, H_tgt, w_coh=1.0, w_pdp=1.0):
         L = w_coh L_coh + w_pdp L_pdp
 
     Returns (L, L_coh, L_pdp) as float64 scalars."""
-    coh = torch.sum(torch.abs(H - H_tgt) ** 2) / torch.sum(torch.abs(H_tgt) ** 2)
-    p = pdp(H)
-    pt = pdp(H_tgt)
-    inc = torch.sum((p - pt) ** 2) / torch.sum(pt ** 2)
+    e_coh, z_coh, e_pdp, z_pdp = cfr_loss_sums(H, H_tgt)
+    coh = e_coh / z_coh
+    inc = e_pdp / z_pdp
     return w_coh * coh + w_pdp * inc, coh, inc
 
 

@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB_PATH = os.path.join(HERE, "librtcal.so")
 
-SOURCES = ["api.hip", "trace.hip", "cfr.hip", "loss.hip", "paper_loss.hip", "adam.hip",
+SOURCES = ["api.hip", "trace.hip", "cfr.hip", "fused.hip", "loss.hip", "paper_loss.hip", "adam.hip",
            "mlp.hip", "embed.hip",
            "validate.hip"]
 

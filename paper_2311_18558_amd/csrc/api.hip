@@ -96,6 +96,7 @@ size_t ws_target_stats(const rtc_radio* r, int32_t n_links);
 size_t ws_paper_loss(const rtc_radio* r, int32_t n_links);
 size_t ws_validate_paths();
 size_t ws_trace_adjoint_pat(int32_t n_paths, int32_t n_mat);
+size_t ws_cfr_loss_adjoint(const rtc_radio* r, int32_t n_links);
 }  // namespace rtc
 
 extern "C" {
@@ -122,6 +123,8 @@ size_t rtc_workspace_size(int op, const rtc_radio* radio, int32_t n_links, int32
       return rtc::ws_trace_adjoint_pat(n_paths, n_mat);
     case RTC_OP_VALIDATE_PATHS:
       return rtc::ws_validate_paths();
+    case RTC_OP_CFR_LOSS_ADJOINT:
+      return radio ? rtc::ws_cfr_loss_adjoint(radio, n_links) : 0;
     default:
       return 0;
   }

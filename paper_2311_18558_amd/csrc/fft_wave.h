@@ -176,6 +176,22 @@ RTC_DEV void fft_pass_l2r(const float2* in, float2 (*v)[R], int Ns, int lane) {
   }
 }
 
+// Ordering of the LDS exchanges between passes.  BlockSync: a workgroup
+// barrier (a one-wave workgroup, or every wave of the workgroup transforming
+// at the same time).  WaveSync: the wave's own buffers only; LDS operations
+// of one wave complete in issue order, so keeping the compiler from moving
+// them across the exchange is all that is needed.
+struct BlockSync {
+  static RTC_DEV void sync() { __syncthreads(); }
+};
+struct WaveSync {
+  static RTC_DEV void sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+};
+
 // Radix and Ns of position P in a pass sequence: ORDER = +1 runs the radices
 // as fft_radix lists them, ORDER = -1 in reverse.
 template <int LOGN, int ORDER, int P>
@@ -192,7 +208,7 @@ constexpr int seq_ns() {
 
 // Pass P (1 <= P <= npass-2): LDS -> LDS, ping-ponging b0/b1 (pass 0
 // writes b0), then the following middle passes.
-template <int LOGN, int SIGN, int ORDER, int P>
+template <int LOGN, int SIGN, int ORDER, int P, class SY = BlockSync>
 RTC_DEV void fft_mid(float2* b0, float2* b1, int lane) {
   constexpr int NP = fft_npass(LOGN);
   if constexpr (P <= NP - 2) {
@@ -201,7 +217,7 @@ RTC_DEV void fft_mid(float2* b0, float2* b1, int lane) {
     constexpr int NS = seq_ns<LOGN, ORDER, P>();
     const float2* in = ((P - 1) & 1) ? b1 : b0;
     float2* out = (P & 1) ? b1 : b0;
-    __syncthreads();
+    SY::sync();
     float2 v[fft_bpl(N, R)][R];
     fft_pass_l2r<N, R, SIGN>(in, v, NS, lane);
 #pragma unroll
@@ -213,7 +229,7 @@ RTC_DEV void fft_mid(float2* b0, float2* b1, int lane) {
         for (int r = 0; r < R; ++r) out[lds_pad(d + r * NS)] = v[i][r];
       }
     }
-    fft_mid<LOGN, SIGN, ORDER, P + 1>(b0, b1, lane);
+    fft_mid<LOGN, SIGN, ORDER, P + 1, SY>(b0, b1, lane);
   }
 }
 
@@ -221,7 +237,7 @@ RTC_DEV void fft_mid(float2* b0, float2* b1, int lane) {
 // 64 i, element r = x[j + r N/R_first]); vout receives the last pass's
 // outputs (element r of butterfly j = X[j + r N/R_last]).  b0, b1: two LDS
 // buffers of fft_lds_len(N) values.
-template <int LOGN, int SIGN, int ORDER, int J0, int R0, int JL, int RL>
+template <int LOGN, int SIGN, int ORDER, class SY = BlockSync, int J0, int R0, int JL, int RL>
 RTC_DEV void fft_full(float2 (&vin)[J0][R0], float2 (&vout)[JL][RL], float2* b0, float2* b1,
                       int lane) {
   constexpr int N = 1 << LOGN;
@@ -240,12 +256,12 @@ RTC_DEV void fft_full(float2 (&vin)[J0][R0], float2 (&vout)[JL][RL], float2* b0,
     }
   } else {
     fft_pass_r2l<N, R0, SIGN>(vin, b0, 1, lane);
-    fft_mid<LOGN, SIGN, ORDER, 1>(b0, b1, lane);
+    fft_mid<LOGN, SIGN, ORDER, 1, SY>(b0, b1, lane);
     constexpr int PL = NP - 1;
     const float2* in = ((PL - 1) & 1) ? b1 : b0;
-    __syncthreads();
+    SY::sync();
     fft_pass_l2r<N, RL, SIGN>(in, vout, seq_ns<LOGN, ORDER, PL>(), lane);
-    __syncthreads();
+    SY::sync();
   }
 }
 

@@ -1,0 +1,669 @@
+// The calibration step's channel part fused per link: CFR synthesis, the
+// workload loss with its gradient dL/dH, and the CFR adjoint, with H and
+// dL/dH kept on chip (registers and LDS) from the product that forms them to
+// the product that consumes them.
+//
+// One workgroup owns one link: NW = N/256 waves, wave w the 128 subcarrier
+// pairs q in [128 w, 128 w + 128) of all M <= 32 elements (the conjugate
+// pairs of cfr.hip: pair q joins n_hi = N/2 + q and n_lo = N/2 - 1 - q).
+//
+//  1. Forward product (Eq. cfr_cont at the discrete subcarriers of
+//     Sec. II-A) as in cfr_kernel, with the MFMA operands swapped so the
+//     accumulators hold H transposed: lane l%32 is the element m, the
+//     register is the pair.  This is the layout the adjoint's product
+//     takes its dL/dH operand in, so no transpose is needed between them.
+//  2. Loss (coherent + power-delay-profile NMSE, normalised by the target
+//     statistics of the batch), per group of 8 element rows: the lanes of
+//     those rows write H in subcarrier order to LDS, each wave takes rows of
+//     the group through the one-wave FFT (tap domain, PDP, gradient, inverse
+//     FFT; targets H* and p* read from HBM), and writes dL/dH back in place;
+//     the owning lanes read their pairs back as S = dH[n_hi] + dH[n_lo] and
+//     D = dH[n_hi] - dH[n_lo], into the registers H occupied.
+//  3. Adjoint product G[m, p] = sum_q (S Re u_p(t_q) - j D Im u_p(t_q)) for
+//     each 32-path tile of the link, each wave over its own pairs: dL/dH is
+//     split into FP16 parts once (one power-of-two scale for the link, from
+//     its largest value), so per tile only the exponentials are generated;
+//     the waves' partial G meet in LDS and one wave (rotating) applies the
+//     path phase, array phases and gains: dL/da per path, dL/dg summed over
+//     the link's tiles in order (LDS, FP64), one row per link.
+// The loss partials {sum|H-H*|^2, sum|H*|^2, sum(p-p*)^2, sum(p*)^2} of each
+// (link, wave) and the per-link dL/dg rows are reduced across the batch in a
+// fixed order.
+#include <cmath>
+
+#include "api_common.h"
+#include "cfr_common.h"
+#include "dev_common.h"
+#include "fft_wave.h"
+#include "split_f16.h"
+
+namespace rtc {
+
+template <int LOGN>
+struct Fz {
+  static constexpr int N = 1 << LOGN;
+  static constexpr int Q = N / 2;         // subcarrier pairs
+  static constexpr int TPW = 4;           // 32-pair tiles per wave
+  static constexpr int NW = Q / (32 * TPW);
+  static constexpr int NCH = 2 * TPW;     // 16-pair chunks per wave
+  static constexpr int GROUP = 8;         // element rows per loss group
+  static constexpr int RPW = GROUP / NW;  // rows per wave per group
+  static constexpr int LDQ = Q + 16;      // LDS row stride (float4 per pair)
+  static_assert(NW >= 1 && GROUP % NW == 0, "1 to 8 waves");
+  static constexpr int ROW_BYTES = (GROUP * LDQ + 16) * 16;
+  static constexpr int GBUF_FLOATS = 64 * 32;  // one wave's partial G
+  static constexpr int GBUF_BYTES = 2 * NW * GBUF_FLOATS * 4;
+  static constexpr int SMEM = ROW_BYTES > GBUF_BYTES ? ROW_BYTES : GBUF_BYTES;
+};
+
+struct FusedArgs {
+  int n_links, M;
+  const int64_t* link_off;
+  const float2* a;
+  const float* psi;
+  const double* tau;
+  const float2* g;
+  const float2* Ht;  // targets c64 [L, M, N]
+  const float* Pt;   // target PDP f32 [L, M, N] (natural tap order)
+  const double* Z;   // {sum |H*|^2, sum (p*)^2} over the batch
+  float w_coh, w_pdp;
+  double fref, t_off, df, cm;  // grid midpoint, t of pair 0, spacing, (M-1)/2
+  double* row_out;  // [L*NW][4] loss partials per link and wave
+  float2* dLda;     // [P] or null
+  double* g_part;   // [L][M][2] per-link dL/dg, or null
+};
+
+// Start of element row rl's pair slots in the LDS row buffer: rows a stride
+// of Q + 16 slots apart plus a shift that puts the 8 rows and the two lane
+// halves of a register's writes on distinct banks.
+RTC_DEV int row_slot0(int rl, int ldq) { return rl * ldq + (rl & 3) + 8 * (rl >> 2); }
+
+// Loss of one CFR row whose pair accumulators sit in LDS, in place.  Slot q
+// of `row` holds {Re X, Im X, Re Y, Im Y} of pair q (unscaled by `us`), so
+// H[N/2 + q] = X + jY and H[N/2 - 1 - q] = X - jY; on return it holds the
+// adjoint's operands {Re S, Im S, -Re D, Im D}, S = dH[N/2 + q] +
+// dH[N/2 - 1 - q], D = dH[N/2 + q] - dH[N/2 - 1 - q].  One wave; b0, b1 its
+// own FFT buffers.  The loss arithmetic is that of cfr_loss_wave_kernel with
+// a precomputed target PDP (loss.hip).  Element n = j + BA r of the first
+// FFT pass (lane j < BA) is pair j + BA (r - 8) (upper half, r >= 8) or
+// BA - 1 - j + BA (7 - r) (lower half) -- the mirror n -> N - 1 - n is lane
+// BA - 1 - j, register 15 - r.
+// Target data of one CFR row in the layouts the row's loss reads them in:
+// H* at the first FFT pass's elements, p* at the last pass's.
+template <int LOGN>
+struct RowTargets {
+  static constexpr int NP = fft_npass(LOGN);
+  static constexpr int RZ = fft_radix(LOGN, NP - 1);
+  static constexpr int JZ = fft_bpl(1 << LOGN, RZ);
+  float2 t[16];
+  float p[JZ][RZ];
+};
+
+template <int LOGN>
+__device__ __forceinline__ void load_row_targets(const FusedArgs& A, int64_t ridx, int lane,
+                                                 RowTargets<LOGN>& T) {
+  constexpr int N = 1 << LOGN;
+  constexpr int BA = N / 16, BZ = N / RowTargets<LOGN>::RZ;
+  const float2* ts = A.Ht + ridx * N;
+  const float* ps = A.Pt + ridx * N;
+#pragma unroll
+  for (int r = 0; r < 16; ++r)
+    T.t[r] = (BA == 64 || lane < BA) ? ts[lane + r * BA] : make_float2(0.0f, 0.0f);
+#pragma unroll
+  for (int i = 0; i < RowTargets<LOGN>::JZ; ++i) {
+    const int jj = lane + 64 * i;
+#pragma unroll
+    for (int r = 0; r < RowTargets<LOGN>::RZ; ++r)
+      T.p[i][r] = (BZ % 64 == 0 || jj < BZ) ? ps[jj + r * BZ] : 0.0f;
+  }
+}
+
+// Loss of one CFR row whose pair accumulators sit in LDS, in place.  Slot q
+// of `row` holds {Re X, Im X, Re Y, Im Y} of pair q (unscaled by `us`), so
+// H[N/2 + q] = X + jY and H[N/2 - 1 - q] = X - jY; on return it holds the
+// adjoint's operands {Re S, Im S, -Re D, Im D}, S = dH[N/2 + q] +
+// dH[N/2 - 1 - q], D = dH[N/2 + q] - dH[N/2 - 1 - q].  One wave; b0, b1 its
+// own FFT buffers; the row's four loss sums are added to `sums` (per lane,
+// FP64).  The loss arithmetic is that of cfr_loss_wave_kernel with a
+// precomputed target PDP (loss.hip).  Element n = j + BA r of the first FFT
+// pass (lane j < BA) is pair j + BA (r - 8) (upper half, r >= 8) or
+// BA - 1 - j + BA (7 - r) (lower half) -- the mirror n -> N - 1 - n is lane
+// BA - 1 - j, register 15 - r.
+template <int LOGN>
+__device__ __forceinline__ void fused_loss_row(float4* row, const RowTargets<LOGN>& T, float us,
+                                               float2* b0, float2* b1, float gc, float gp,
+                                               double (&sums)[4], int lane_in) {
+  // the FFT twiddles depend on the lane and the pass only; an opaque lane
+  // index keeps the compiler from holding them across rows (and the group
+  // loop), where they would take registers the loop needs
+  int lane = lane_in;
+  asm volatile("" : "+v"(lane));
+  constexpr int N = 1 << LOGN;
+  constexpr int NP = fft_npass(LOGN);
+  constexpr int RA = fft_radix(LOGN, 0), RZ = fft_radix(LOGN, NP - 1);
+  constexpr int JA = fft_bpl(N, RA), JZ = fft_bpl(N, RZ);
+  constexpr int BA = N / RA, BZ = N / RZ;
+  static_assert(RA == 16 && JA == 1 && BA <= 64, "first pass: one radix-16 butterfly per lane");
+  const float invN = 1.0f / (float)N;
+  const int j = lane;
+  const bool act = BA == 64 || j < BA;
+  float2 vh[1][16], diff[16];
+  float ec = 0.0f, et = 0.0f;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    float2 h = make_float2(0.0f, 0.0f);
+    if (act) {
+      if (r >= 8) {
+        const float4 v = row[j + BA * (r - 8)];
+        h = make_float2((v.x - v.w) * us, (v.y + v.z) * us);  // X + jY
+      } else {
+        const float4 v = row[BA - 1 - j + BA * (7 - r)];
+        h = make_float2((v.x + v.w) * us, (v.y - v.z) * us);  // X - jY
+      }
+    }
+    vh[0][r] = h;
+    diff[r] = csub(h, T.t[r]);
+    ec += cabs2(diff[r]);
+    et += cabs2(T.t[r]);
+  }
+  float2 xh[JZ][RZ];
+  fft_full<LOGN, +1, +1, WaveSync>(vh, xh, b0, b1, lane);
+  float ep = 0.0f, eq = 0.0f;
+#pragma unroll
+  for (int i = 0; i < JZ; ++i) {
+    const int jj = lane + 64 * i;
+    if (BZ % 64 == 0 || jj < BZ) {
+#pragma unroll
+      for (int r = 0; r < RZ; ++r) {
+        const float p = cabs2(xh[i][r]) * invN;
+        const float d = p - T.p[i][r];
+        ep += d * d;
+        eq += T.p[i][r] * T.p[i][r];
+        xh[i][r] = cscale(xh[i][r], gp * d);  // gradient source
+      }
+    }
+  }
+  sums[0] += (double)ec;
+  sums[1] += (double)et;
+  sums[2] += (double)ep;
+  sums[3] += (double)eq;
+  float2 G[1][16];
+  fft_full<LOGN, -1, -1, WaveSync>(xh, G, b0, b1, lane);
+  // dL/dH = gc (H - H*) + G; pair slot j + BA r' takes its upper element
+  // from this lane (register r' + 8) and its lower one from the mirror lane
+  // (register 7 - r')
+  float2 dh[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) dh[r] = cadd(cscale(diff[r], gc), G[0][r]);
+  const int mir = BA - 1 - j;
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const float2 hi = dh[r + 8];
+    const float2 lo = make_float2(__shfl(dh[7 - r].x, mir, 64), __shfl(dh[7 - r].y, mir, 64));
+    if (act)
+      row[j + BA * r] = make_float4(hi.x + lo.x, hi.y + lo.y, lo.x - hi.x, hi.y - lo.y);
+  }
+}
+
+template <int LOGN>
+__global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs A) {
+  using F = Fz<LOGN>;
+  constexpr int N = F::N, NW = F::NW, TPW = F::TPW, NCH = F::NCH;
+  __shared__ __align__(16) char smem[F::SMEM];
+  __shared__ float2 fb[NW][2][fft_lds_len(N)];
+  __shared__ float wmax[NW];
+  __shared__ float2 dabuf[2][NW * 32];
+  float4* rowbuf = reinterpret_cast<float4*>(smem);
+  float* gbuf = reinterpret_cast<float*>(smem);
+
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int half = lane >> 5;
+  const int col = lane & 31;
+  const int64_t l = blockIdx.x;
+  const int M = A.M;
+  const int64_t off0 = A.link_off[l];
+  const int64_t off1 = A.link_off[l + 1];
+  const int q_base = wv * 32 * TPW;
+  // targets of the wave's first loss row, loaded while the forward runs
+  RowTargets<LOGN> cur;
+  if (wv < M) load_row_targets<LOGN>(A, l * M + wv, lane, cur);
+
+  // ------------------------------------------------------------ 1. forward
+  // lane: element m = col (B operand A'), pair column col of each tile (A
+  // operand u); acc[t][*] register r holds pair q_base + 32 t + 8 (r/4) +
+  // 4 half + r%4 of element col: X = (acc0, acc1), Y = (acc2, acc3)
+  floatx16 acc[TPW][4];
+  float unscale = 1.0f;  // the forward operand's link scale, removed in the loss
+#pragma unroll
+  for (int t = 0; t < TPW; ++t)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[t][k] = floatx16{0};
+  {
+    const int m = col;
+    const float2 g_row = m < M ? A.g[m] : make_float2(0.0f, 0.0f);
+    const double mc_cyc = ((double)m - A.cm) * kInv2Pi;
+    const double t_lane_df = ((double)(q_base + col) + A.t_off) * A.df;
+    const double df32 = 32.0 * A.df;
+    const int sx = 14 - cfr_link_scale_exp(A.a, off0, off1, g_row, lane);
+    const float2 gm = make_float2(ldexpf(g_row.x, sx), ldexpf(g_row.y, sx));
+    auto fetch = [&](int64_t c0, float2 (&pa)[8], float (&pp)[8], double (&pt)[8], double& tm) {
+      const int64_t p0 = c0 + 8 * half;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int64_t p = p0 + j;
+        const int64_t pc = p < off1 ? p : off1 - 1;
+        const float2 av = A.a[pc];
+        pa[j] = p < off1 ? av : make_float2(0.0f, 0.0f);
+        pp[j] = A.psi[pc];
+        pt[j] = A.tau[pc];
+      }
+      const int64_t pm = p0 + (col & 7);
+      tm = A.tau[pm < off1 ? pm : off1 - 1];
+    };
+    auto operands = [&](const float2 (&pa)[8], const float (&pp)[8], const double (&pt)[8],
+                        double tm, float (&ar)[8], float (&ai)[8], float2 (&uv)[8],
+                        float2 (&wvv)[8]) {
+      const float2 wm = expm2pi_f64_hw(df32 * tm);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const float2 ph = expm2pi_f64_hw(fma(A.fref, pt[j], -(double)pp[j] * mc_cyc));
+        const float2 b = cmul(cmul(pa[j], gm), ph);
+        ar[j] = b.x;
+        ai[j] = b.y;
+        uv[j] = expm2pi_f64_hw(t_lane_df * pt[j]);
+        const int src = (lane & 32) + j;
+        wvv[j] = make_float2(__shfl(wm.x, src, 64), __shfl(wm.y, src, 64));
+      }
+    };
+    if (off0 < off1) {
+      float ar[8], ai[8];
+      float2 uv[8], wvv[8];
+      {
+        float2 pa[8];
+        float pp[8];
+        double pt[8], tm;
+        fetch(off0, pa, pp, pt, tm);
+        operands(pa, pp, pt, tm, ar, ai, uv, wvv);
+      }
+      for (int64_t c0 = off0; c0 < off1; c0 += 16) {
+        float2 pa[8];
+        float pp[8];
+        double pt[8], tm;
+        fetch(c0 + 16, pa, pp, pt, tm);
+        const Split2 AR = split2(ar), AI = split2(ai);
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) {
+          float ur[8], ui[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            if (t > 0) uv[j] = cmul(uv[j], wvv[j]);
+            ur[j] = uv[j].x;
+            ui[j] = uv[j].y;
+          }
+          const Split2 UR = split2(ur), UI = split2(ui);
+          acc[t][0] = mac3(UR, AR, acc[t][0]);
+          acc[t][1] = mac3(UR, AI, acc[t][1]);
+          acc[t][2] = mac3(UI, AR, acc[t][2]);
+          acc[t][3] = mac3(UI, AI, acc[t][3]);
+        }
+        operands(pa, pp, pt, tm, ar, ai, uv, wvv);
+      }
+    }
+    unscale = ldexpf(1.0f, -sx);
+  }
+
+  // --------------------------------------------------------------- 2. loss
+  // the wave's rows: k -> element row 8 (k / RPW) + wv + NW (k % RPW); the
+  // rows that exist (< M) are a prefix.  Row k + 1's targets load while row
+  // k is transformed (row 0's during the forward product).
+  const float gc = (float)(2.0 * (double)A.w_coh / A.Z[0]);
+  const float gp = (float)(4.0 * (double)A.w_pdp / (A.Z[1] * (double)N));
+  const int n_groups = (M + 7) >> 3;
+  auto row_of = [&](int k) { return 8 * (k / F::RPW) + wv + NW * (k % F::RPW); };
+  double sums[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int grp = 0; grp < n_groups; ++grp) {
+    __syncthreads();  // the previous group's read-back is done
+    if ((col >> 3) == grp) {
+      float4* row = rowbuf + row_slot0(col & 7, F::LDQ);
+#pragma unroll
+      for (int t = 0; t < TPW; ++t)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int q = q_base + 32 * t + 8 * (r >> 2) + 4 * half + (r & 3);
+          row[q] = make_float4(acc[t][0][r], acc[t][1][r], acc[t][2][r], acc[t][3][r]);
+        }
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int i = 0; i < F::RPW; ++i) {
+      const int k = grp * F::RPW + i;
+      const int mrow = row_of(k);
+      if (mrow < M) {
+        RowTargets<LOGN> nxt;
+        const int mnext = row_of(k + 1);
+        if (mnext < M) load_row_targets<LOGN>(A, l * M + mnext, lane, nxt);
+        fused_loss_row<LOGN>(rowbuf + row_slot0(mrow & 7, F::LDQ), cur, unscale, fb[wv][0],
+                             fb[wv][1], gc, gp, sums, lane);
+        cur = nxt;
+      }
+    }
+    __syncthreads();
+    if ((col >> 3) == grp) {
+      // rows m >= M hold X = Y = 0 (zero gains), read back as zero operands
+      const float4* row = rowbuf + row_slot0(col & 7, F::LDQ);
+#pragma unroll
+      for (int t = 0; t < TPW; ++t)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int q = q_base + 32 * t + 8 * (r >> 2) + 4 * half + (r & 3);
+          const float4 v = row[q];
+          acc[t][0][r] = v.x;  // Re S
+          acc[t][1][r] = v.y;  // Im S
+          acc[t][2][r] = v.z;  // -Re D
+          acc[t][3][r] = v.w;  // Im D
+        }
+    }
+  }
+  // the wave's loss sums over its rows: lanes in a fixed butterfly order
+#pragma unroll
+  for (int k = 0; k < 4; ++k) sums[k] = wave_sum_f64(sums[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) A.row_out[(l * NW + wv) * 4 + k] = sums[k];
+  }
+
+  // ------------------------------------------------------------ 3. adjoint
+  // one power-of-two scale for the link's dL/dH operand: its largest value
+  // below 2^14 (exact both ways; values down to 2^-28 of it keep all bits)
+  float mx = 0.0f;
+#pragma unroll
+  for (int t = 0; t < TPW; ++t)
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) mx = fmaxf(mx, fabsf(acc[t][k][r]));
+  mx = wave_max_f32(mx);
+  if (lane == 0) wmax[wv] = mx;
+  __syncthreads();
+  mx = wmax[0];
+#pragma unroll
+  for (int w = 1; w < NW; ++w) mx = fmaxf(mx, wmax[w]);
+  int sxa = 0;
+  if (mx > 0.0f) {
+    int e = 0;
+    frexpf(mx, &e);
+    sxa = 14 - min(max(e, -100), 100);
+  }
+  const float sca = ldexpf(1.0f, sxa);
+  const float unsca = ldexpf(1.0f, -sxa);
+  // chunk c (16 pairs): tile c/2, registers 8 (c%2) .. +7; k slot (half, j)
+  // is pair q_base + 16 c + 8 (j/4) + 4 half + j%4
+  Split2 SR[NCH], SI[NCH], NDR[NCH], DI[NCH];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    float sr[8], si[8], nd[8], di[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int r = 8 * (c & 1) + j;
+      sr[j] = acc[c >> 1][0][r] * sca;
+      si[j] = acc[c >> 1][1][r] * sca;
+      nd[j] = acc[c >> 1][2][r] * sca;
+      di[j] = acc[c >> 1][3][r] * sca;
+    }
+    SR[c] = split2(sr);
+    SI[c] = split2(si);
+    NDR[c] = split2(nd);
+    DI[c] = split2(di);
+  }
+
+  // The epilogue of a tile is split over the waves by element rows: wave w
+  // takes the row groups g4 in [G4W w, G4W (w + 1)) (rows 8 g4 + 4 half +
+  // 0..3, registers 4 g4 .. 4 g4 + 3 of G).  Its dL/dg rows accumulate in
+  // the wave's registers (FP64, tiles in order); its share of dL/da goes to
+  // LDS and the wave that finishes the tile adds the waves' shares in order
+  // after the next barrier.
+  constexpr int G4W = 4 / NW;
+  double dgw[G4W][4][2];
+#pragma unroll
+  for (int a = 0; a < G4W; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) dgw[a][b][0] = dgw[a][b][1] = 0.0;
+  auto finish_da = [&](int T) {
+    // dL/da of tile T: the waves' shares in wave order (half 0 lanes)
+    const float2* db = dabuf[T & 1];
+    const int64_t p = off0 + 32 * (int64_t)T + col;
+    if (half == 0 && p < off1 && A.dLda) {
+      float2 d = db[col];
+#pragma unroll
+      for (int w = 1; w < NW; ++w) d = cadd(d, db[w * 32 + col]);
+      A.dLda[p] = d;
+    }
+  };
+  const int n_tiles = (int)((off1 - off0 + 31) >> 5);
+  for (int T = 0; T < n_tiles; ++T) {
+    const int64_t p = off0 + 32 * (int64_t)T + col;
+    const bool ok = p < off1;
+    const double tau = ok ? A.tau[p] : 0.0;
+    const float2 v1 = expm2pi_f64_hw(A.df * tau);
+    const float2 v8 = expm2pi_f64_hw(8.0 * A.df * tau);
+    const float2 v16 = expm2pi_f64_hw(16.0 * A.df * tau);
+    // G~ = X - jY: Re G~ += S_re Re u + D_im Im u, Im G~ += S_im Re u - D_re Im u
+    floatx16 gre = floatx16{0}, gim = floatx16{0};
+    float2 e0 = make_float2(1.0f, 0.0f);
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      // u_p at the lane's first pair of the chunk: FP64 anchor every 64 pairs
+      if ((c & 3) == 0)
+        e0 = expm2pi_f64_hw(((double)(q_base + 16 * c + 4 * half) + A.t_off) * A.df * tau);
+      else
+        e0 = cmul(e0, v16);
+      float ur[8], ui[8];
+      float2 e = e0, f = cmul(e0, v8);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (j > 0) {
+          e = cmul(e, v1);
+          f = cmul(f, v1);
+        }
+        ur[j] = e.x;
+        ui[j] = e.y;
+        ur[j + 4] = f.x;
+        ui[j + 4] = f.y;
+      }
+      const Split2 UR = split2(ur), UI = split2(ui);
+      gre = mac3(SR[c], UR, gre);
+      gim = mac3(SI[c], UR, gim);
+      gre = mac3(DI[c], UI, gre);
+      gim = mac3(NDR[c], UI, gim);
+    }
+    // the waves' partial sums over their pairs meet in LDS (two buffers,
+    // alternating by tile; register r at float r*64 + lane, conflict-free)
+    float* gb = gbuf + ((T & 1) * NW + wv) * F::GBUF_FLOATS;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      gb[r * 64 + lane] = gre[r];
+      gb[(16 + r) * 64 + lane] = gim[r];
+    }
+    __syncthreads();
+    if (T > 0 && wv == (T - 1) % NW) finish_da(T - 1);
+    // this wave's rows of the tile: rows m = 8 g4 + 4 half + qq, column = path
+    const float* g0 = gbuf + (T & 1) * NW * F::GBUF_FLOATS;
+    const float2 ai = ok ? A.a[p] : make_float2(0.0f, 0.0f);
+    const double psi_cyc = (double)(ok ? A.psi[p] : 0.0f) * kInv2Pi;
+    const float2 cc = cconj(expm2pi_f64_hw(A.fref * tau));  // conj(c_p)
+    const float2 step = expm2pi_f64_hw(psi_cyc);
+    float2 da = make_float2(0.0f, 0.0f);
+#pragma unroll
+    for (int a = 0; a < G4W; ++a) {
+      const int g4 = G4W * wv + a;
+      const int mrow0 = 8 * g4 + 4 * half;
+      float2 ph = expm2pi_f64_hw(psi_cyc * ((double)mrow0 - A.cm));  // exp(-j psi (m - c))
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq) {
+        const int r = 4 * g4 + qq;
+        const int mrow = mrow0 + qq;
+        float gr = 0.0f, gi = 0.0f;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+          gr += g0[w * F::GBUF_FLOATS + r * 64 + lane];
+          gi += g0[w * F::GBUF_FLOATS + (16 + r) * 64 + lane];
+        }
+        if (qq > 0) ph = cmul(ph, step);
+        const float2 G = cmul(cc, make_float2(gr * unsca, gi * unsca));
+        const float2 gmv = mrow < M ? A.g[mrow] : make_float2(0.0f, 0.0f);
+        const float2 Gph = cmul(G, ph);
+        da = cadd(da, cmulc(gmv, Gph));
+        // dL/dg: sum over the 32 paths of this half (fixed butterfly)
+        float2 tg = cmulc(ai, Gph);
+#pragma unroll
+        for (int o = 16; o >= 1; o >>= 1) {
+          tg.x += __shfl_xor(tg.x, o, 64);
+          tg.y += __shfl_xor(tg.y, o, 64);
+        }
+        dgw[a][qq][0] += (double)tg.x;
+        dgw[a][qq][1] += (double)tg.y;
+      }
+    }
+    // the wave's share of dL/da: both halves (their rows) added
+    da.x += __shfl_xor(da.x, 32, 64);
+    da.y += __shfl_xor(da.y, 32, 64);
+    if (half == 0) dabuf[T & 1][wv * 32 + col] = da;
+  }
+  __syncthreads();  // the last tile's shares are in LDS; every epilogue is done
+  if (n_tiles > 0 && wv == (n_tiles - 1) % NW) finish_da(n_tiles - 1);
+  if (A.g_part) {
+    // this wave's dL/dg rows of the link (disjoint across waves)
+    if (col == 0) {
+#pragma unroll
+      for (int a = 0; a < G4W; ++a)
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) {
+          const int mrow = 8 * (G4W * wv + a) + 4 * half + qq;
+          if (mrow < M) {
+            A.g_part[(l * M + mrow) * 2 + 0] = dgw[a][qq][0];
+            A.g_part[(l * M + mrow) * 2 + 1] = dgw[a][qq][1];
+          }
+        }
+    }
+  }
+}
+
+__global__ void fused_finish_kernel(const double* sums, const double* Z, float w_coh,
+                                    float w_pdp, double* loss) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double coh = sums[0] / Z[0];
+  const double pdp = sums[2] / Z[1];
+  loss[0] = (double)w_coh * coh + (double)w_pdp * pdp;
+  loss[1] = coh;
+  loss[2] = pdp;
+}
+
+__global__ void fused_to_c64_kernel(const double* v, int M, float2* out) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m < M) out[m] = make_float2((float)v[2 * m], (float)v[2 * m + 1]);
+}
+
+bool fused_supported(const rtc_radio* r) {
+  return r->n_elem >= 1 && r->n_elem <= 32 &&
+         (r->n_sc == 256 || r->n_sc == 512 || r->n_sc == 1024);
+}
+
+// waves per workgroup of the fused kernel for n_sc subcarriers
+static int fused_waves(int n_sc) { return n_sc / 256; }
+
+// Workspace: loss partials [L*NW][4] | their reduction tmp | sums [4] |
+// per-link dL/dg [L][M][2] | its reduction tmp | reduced [M][2] (doubles).
+size_t ws_cfr_loss_adjoint(const rtc_radio* r, int32_t n_links) {
+  if (!fused_supported(r)) return 0;
+  const int64_t L = n_links > 0 ? n_links : 1;
+  const int64_t R = L * fused_waves(r->n_sc);
+  const int K = 2 * r->n_elem;
+  return (size_t)(R * 4 + reduce_tmp_doubles(R, 4) + 4 + L * K + reduce_tmp_doubles(L, K) + K) *
+         sizeof(double);
+}
+
+}  // namespace rtc
+
+using namespace rtc;
+
+extern "C" rtc_status rtc_cfr_loss_adjoint(const rtc_radio* radio, const rtc_paths* paths,
+                                           const void* a, const float* psi, const void* g,
+                                           const void* H_tgt, const double* tgt_stats,
+                                           const float* p_tgt, float w_coh, float w_pdp,
+                                           double* loss, void* dLda, void* dLdg, void* ws,
+                                           size_t ws_bytes, void* stream) {
+  const char* fn = "rtc_cfr_loss_adjoint";
+  rtc_status st;
+  if ((st = check_radio(radio, fn)) != RTC_OK) return st;
+  if ((st = check_paths(paths, fn, false)) != RTC_OK) return st;
+  RTC_REQUIRE(fused_supported(radio), RTC_ERR_UNSUPPORTED,
+              "%s: needs 1 <= n_elem <= 32 and n_sc of 256, 512 or 1024 (got %d, %d); use "
+              "rtc_cfr, rtc_cfr_loss and rtc_cfr_adjoint",
+              fn, radio->n_elem, radio->n_sc);
+  RTC_REQUIRE(paths->n_links >= 1, RTC_ERR_SHAPE, "%s: n_links must be >= 1", fn);
+  RTC_REQUIRE(g != nullptr, RTC_ERR_INVALID_ARG, "%s: g is NULL", fn);
+  RTC_REQUIRE((a != nullptr && psi != nullptr) || paths->n_paths == 0, RTC_ERR_INVALID_ARG,
+              "%s: a and psi are required", fn);
+  RTC_REQUIRE(H_tgt && tgt_stats && p_tgt && loss, RTC_ERR_INVALID_ARG,
+              "%s: H_tgt, tgt_stats, p_tgt and loss are required", fn);
+  const size_t need = ws_cfr_loss_adjoint(radio, paths->n_links);
+  RTC_REQUIRE(ws != nullptr && ws_bytes >= need, RTC_ERR_WORKSPACE,
+              "%s: workspace of %zu bytes required", fn, need);
+  hipStream_t s = as_stream(stream);
+  const int64_t L = paths->n_links;
+  const int M = radio->n_elem, N = radio->n_sc;
+  const int64_t R = L * fused_waves(N);
+  const int K = 2 * M;
+  double* rows = reinterpret_cast<double*>(ws);
+  double* rtmp = rows + R * 4;
+  double* sums = rtmp + reduce_tmp_doubles(R, 4);
+  double* gpart = sums + 4;
+  double* gtmp = gpart + L * K;
+  double* gred = gtmp + reduce_tmp_doubles(L, K);
+
+  FusedArgs A;
+  A.n_links = paths->n_links;
+  A.M = M;
+  A.link_off = paths->link_off;
+  A.a = reinterpret_cast<const float2*>(a);
+  A.psi = psi;
+  A.tau = paths->tau;
+  A.g = reinterpret_cast<const float2*>(g);
+  A.Ht = reinterpret_cast<const float2*>(H_tgt);
+  A.Pt = p_tgt;
+  A.Z = tgt_stats;
+  A.w_coh = w_coh;
+  A.w_pdp = w_pdp;
+  const double f0 = radio->fc_hz - (double)(N / 2) * radio->df_hz;
+  A.fref = f0 + 0.5 * (double)(N - 1) * radio->df_hz;
+  A.t_off = 0.5;  // N even
+  A.df = radio->df_hz;
+  A.cm = 0.5 * (double)(M - 1);
+  A.row_out = rows;
+  A.dLda = reinterpret_cast<float2*>(dLda);
+  A.g_part = dLdg ? gpart : nullptr;
+  switch (N) {
+    case 256:
+      hipLaunchKernelGGL(cfr_fused_kernel<8>, dim3((unsigned)L), dim3(Fz<8>::NW * 64), 0, s, A);
+      break;
+    case 512:
+      hipLaunchKernelGGL(cfr_fused_kernel<9>, dim3((unsigned)L), dim3(Fz<9>::NW * 64), 0, s, A);
+      break;
+    default:
+      hipLaunchKernelGGL(cfr_fused_kernel<10>, dim3((unsigned)L), dim3(Fz<10>::NW * 64), 0, s,
+                         A);
+  }
+  if ((st = check_launch(fn)) != RTC_OK) return st;
+  if ((st = reduce_all(rows, R, 4, rtmp, sums, s, fn)) != RTC_OK) return st;
+  hipLaunchKernelGGL(fused_finish_kernel, dim3(1), dim3(64), 0, s, sums, tgt_stats, w_coh, w_pdp,
+                     loss);
+  if ((st = check_launch(fn)) != RTC_OK) return st;
+  if (dLdg) {
+    if ((st = reduce_all(gpart, L, K, gtmp, gred, s, fn)) != RTC_OK) return st;
+    hipLaunchKernelGGL(fused_to_c64_kernel, dim3((M + 63) / 64), dim3(64), 0, s, gred, M,
+                       reinterpret_cast<float2*>(dLdg));
+    return check_launch(fn);
+  }
+  return RTC_OK;
+}

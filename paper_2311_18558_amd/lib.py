@@ -30,6 +30,7 @@ RTC_OP_TRACE_FIELDS_ADJOINT = 3
 RTC_OP_CFR_TARGET_STATS = 4
 RTC_OP_PAPER_LOSS = 5
 RTC_OP_TRACE_FIELDS_ADJOINT_PAT = 6
+RTC_OP_CFR_LOSS_ADJOINT = 8
 
 
 class Radio(ctypes.Structure):
@@ -91,6 +92,9 @@ _SIGS = {
     "rtc_eval_ale_rae": (ctypes.c_int, [c_i32, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "rtc_cfr_adjoint": (ctypes.c_int, [ctypes.POINTER(Radio), ctypes.POINTER(Paths), c_vp, c_vp,
                                        c_vp, c_vp, c_vp, c_vp, c_vp, c_size, c_vp]),
+    "rtc_cfr_loss_adjoint": (ctypes.c_int, [ctypes.POINTER(Radio), ctypes.POINTER(Paths), c_vp,
+                                            c_vp, c_vp, c_vp, c_vp, c_vp, c_f32, c_f32, c_vp,
+                                            c_vp, c_vp, c_vp, c_size, c_vp]),
     "rtc_trace_fields_adjoint": (ctypes.c_int, [ctypes.POINTER(Radio), ctypes.POINTER(Paths),
                                                 ctypes.POINTER(Materials), c_vp, c_vp, c_vp,
                                                 c_vp, c_size, c_vp]),
@@ -397,6 +401,23 @@ def cfr_adjoint(radio, paths, a, psi, g, dLdH, dLda, dLdg, ws, stream=None):
                                   _ptr(g), _ptr(dLdH), _ptr(dLda), _ptr(dLdg), _ptr(ws),
                                   0 if ws is None else ws.numel(), _stream(stream)),
            "rtc_cfr_adjoint")
+
+
+def fused_supported(radio):
+    """Shapes rtc_cfr_loss_adjoint takes (others: the three separate calls)."""
+    return 1 <= radio.n_elem <= 32 and radio.n_sc in (256, 512, 1024)
+
+
+def cfr_loss_adjoint(radio, paths, a, psi, g, H_tgt, tgt_stats, p_tgt, w_coh, w_pdp, loss,
+                     dLda, dLdg, ws, stream=None):
+    """CFR, workload loss and CFR adjoint in one pass per link (H and dL/dH
+    stay on chip); tgt_stats and p_tgt from cfr_target_stats of H_tgt."""
+    _check(load().rtc_cfr_loss_adjoint(ctypes.byref(radio), ctypes.byref(paths.c), _ptr(a),
+                                       _ptr(psi), _ptr(g), _ptr(H_tgt), _ptr(tgt_stats),
+                                       _ptr(p_tgt), float(w_coh), float(w_pdp), _ptr(loss),
+                                       _ptr(dLda), _ptr(dLdg), _ptr(ws),
+                                       0 if ws is None else ws.numel(), _stream(stream)),
+           "rtc_cfr_loss_adjoint")
 
 
 def trace_fields_adjoint(radio, paths, mats, dLda, dLd_raw, dLd_inter, ws, stream=None):

@@ -3,6 +3,11 @@
     trace_fields -> cfr -> loss (dL/dH in place) -> cfr_adjoint
                  -> trace_fields_adjoint -> Adam
 
+With the workload loss at shapes the fused pass takes (up to 32 elements,
+256 to 1,024 subcarriers) cfr, loss and cfr_adjoint are one library call,
+rtc_cfr_loss_adjoint, and H and dL/dH never leave the chip (fused=False keeps
+the three calls).
+
 (Algorithm 1 of the paper, per-material-id mode.)  The loss is either the
 workload loss (coherent + power-delay-profile NMSE, loss="workload") or the
 paper's own (loss="paper": SMAPE of RMS delay spread and gain per CIR row,
@@ -19,7 +24,7 @@ from . import lib
 
 class Pipeline:
     def __init__(self, store, radio, raw0, g0, device="cuda", stream=None, loss="workload",
-                 update_alpha=False, delta=0.99):
+                 update_alpha=False, delta=0.99, fused=True):
         if loss not in ("workload", "paper"):
             raise ValueError(loss)
         self.loss_kind = loss
@@ -31,12 +36,17 @@ class Pipeline:
         L, P = self.paths.n_links, self.paths.n_paths
         M, N = self.radio.n_elem, self.radio.n_sc
         self.L, self.P, self.M, self.N = L, P, M, N
+        self.fused = bool(fused) and loss == "workload" and lib.fused_supported(self.radio)
         self.raw = torch.tensor(np.asarray(raw0, np.float32), device=self.dev)
         self.g = torch.tensor(np.asarray(g0, np.complex64), device=self.dev)
         self.n_mat = self.raw.shape[0]
         self.a = torch.empty(P, dtype=torch.complex64, device=self.dev)
         self.psi = torch.empty(P, dtype=torch.float32, device=self.dev)
+        # H (and dL/dH in place) only exists outside the fused pass; the fused
+        # step keeps a buffer for forward evaluations (targets, metrics)
         self.H = torch.empty((L, M, N), dtype=torch.complex64, device=self.dev)
+        self.ws_fused = (lib.workspace(lib.RTC_OP_CFR_LOSS_ADJOINT, self.radio, L, P, 1, self.dev)
+                         if self.fused else None)
         self.loss = torch.zeros(3, dtype=torch.float64, device=self.dev)
         self.dLda = torch.empty(P, dtype=torch.complex64, device=self.dev)
         self.dLdg = torch.empty(M, dtype=torch.complex64, device=self.dev)
@@ -80,12 +90,15 @@ class Pipeline:
             lib.cir_stats(self.radio, self.L, H_tgt, self.tgt_stats, self.stream)
             self.alpha.copy_(torch.tensor([1.0, 0.0], dtype=torch.float64))
             return
-        # the loss reads H* for its coherent term anyway and forms p* from it
-        # with one more transform per row (24 B per tap instead of 28 with a
-        # stored p*, and measured faster)
+        # the separate loss reads H* for its coherent term anyway and forms p*
+        # from it with one more transform per row (24 B per tap instead of 28
+        # with a stored p*, and measured faster); the fused pass takes p*
+        # stored
         self.tgt_stats = torch.empty(2, dtype=torch.float64, device=self.dev)
-        self.p_tgt = None
-        lib.cfr_target_stats(self.radio, self.L, H_tgt, self.tgt_stats, self.ws_loss, self.stream)
+        self.p_tgt = (torch.empty((self.L, self.M, self.N), dtype=torch.float32, device=self.dev)
+                      if self.fused else None)
+        lib.cfr_target_stats(self.radio, self.L, H_tgt, self.tgt_stats, self.ws_loss, self.stream,
+                             p_tgt=self.p_tgt)
 
     def loss_and_grad(self):
         if self.loss_kind == "paper":
@@ -95,6 +108,11 @@ class Pipeline:
             return
         lib.cfr_loss(self.radio, self.L, self.H, self.H_tgt, self.tgt_stats, 1.0, 1.0,
                      self.loss, self.H, self.ws_loss, self.stream, p_tgt=self.p_tgt)
+
+    def cfr_loss_adjoint(self):
+        lib.cfr_loss_adjoint(self.radio, self.paths, self.a, self.psi, self.g, self.H_tgt,
+                             self.tgt_stats, self.p_tgt, 1.0, 1.0, self.loss, self.dLda,
+                             self.dLdg, self.ws_fused, self.stream)
 
     def cfr_adjoint(self):
         lib.cfr_adjoint(self.radio, self.paths, self.a, self.psi, self.g, self.H, self.dLda,
@@ -114,14 +132,19 @@ class Pipeline:
 
     @property
     def stages(self):
+        if self.fused:
+            return ("trace_fields", "cfr_loss_adjoint", "trace_fields_adjoint", "adam")
         loss = "cfr_loss" if self.loss_kind == "workload" else "paper_loss"
         return ("trace_fields", "cfr", loss, "cfr_adjoint", "trace_fields_adjoint", "adam")
 
     def step(self, lr=0.01, events=None):
         """One full calibration step.  `events`, if given, maps stage name
         to a list that receives (start, end) CUDA events per stage."""
-        fns = (self.trace, self.cfr, self.loss_and_grad, self.cfr_adjoint, self.trace_adjoint,
-               lambda: self.adam(lr))
+        if self.fused:
+            fns = (self.trace, self.cfr_loss_adjoint, self.trace_adjoint, lambda: self.adam(lr))
+        else:
+            fns = (self.trace, self.cfr, self.loss_and_grad, self.cfr_adjoint, self.trace_adjoint,
+                   lambda: self.adam(lr))
         for name, fn in zip(self.stages, fns):
             if events is None:
                 fn()

@@ -107,3 +107,27 @@ def mlp_init(rng: np.random.Generator, out_bias=(0.0, 0.0, 0.0)) -> np.ndarray:
         else:
             parts.append(rng.uniform(-bound, bound, o))
     return np.concatenate(parts).astype(np.float32)
+
+
+def draw_path_coefficients(rng: np.random.Generator, tau: np.ndarray, fc: float):
+    """Seeded stand-ins for per-path coefficients, for tests of the stages
+    after the field computation at sizes where computing the fields is not
+    the point: a_i with magnitude lambda/(4 pi c tau_i) times U[0.05, 1] and
+    a uniform phase, psi_i uniform in [-pi, pi].  Returns (a complex64 [P],
+    psi float32 [P])."""
+    c0 = 299792458.0
+    tau = np.asarray(tau, np.float64)
+    amp = (c0 / fc) / (4.0 * np.pi * c0 * tau) * rng.uniform(0.05, 1.0, tau.shape)
+    a = amp * np.exp(1j * rng.uniform(0.0, 2.0 * np.pi, tau.shape))
+    psi = rng.uniform(-np.pi, np.pi, tau.shape)
+    return a.astype(np.complex64), psi.astype(np.float32)
+
+
+def draw_target_cfr(rng: np.random.Generator, link_power: np.ndarray, n_elem: int, n_sc: int):
+    """Seeded stand-in target CFRs c64 [L, n_elem, n_sc]: circular Gaussian
+    entries whose variance per link is link_power[l]."""
+    L = len(link_power)
+    s = np.sqrt(np.asarray(link_power, np.float64) / 2.0)[:, None, None]
+    re = rng.standard_normal((L, n_elem, n_sc), dtype=np.float32)
+    im = rng.standard_normal((L, n_elem, n_sc), dtype=np.float32)
+    return ((re + 1j * im) * s).astype(np.complex64)

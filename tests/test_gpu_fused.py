@@ -1,0 +1,243 @@
+"""GPU parity of the fused channel pass (rtc_cfr_loss_adjoint: CFR, workload
+loss, CFR adjoint in one pass per link) against the FP64 oracle's
+reverse-mode gradient, and against the library's three separate entry
+points on the same inputs.
+
+Inputs are the oracle's path coefficients (small cases) or seeded stand-ins
+(full-size case); targets are the oracle's CFRs at other materials and gains
+(small cases) or seeded stand-ins.  Tolerances: loss terms <= 1e-5
+relative; dL/da normwise over all paths <= 3e-5 and per link <= 1e-4;
+dL/dg <= 3e-5 (the gradient contract is 1e-3)."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import channel as och
+from oracle.trace import trace_fields_per_id as o_trace_id
+from synth.params import Radio, draw_path_coefficients, draw_target_cfr
+from tests.helpers import array_workload, multi_material_box, ragged_subset, tiny_workload
+
+pytestmark = pytest.mark.gpu
+f64 = torch.float64
+c128 = torch.complex128
+
+
+def say(msg):
+    print(f"[gpu-step] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rl(gpu_lib):
+    from paper_2311_18558_amd import lib
+    return lib
+
+
+def _floor_case():
+    from synth.floorplan import indoor_floor
+    from synth.pathfind import find_store
+    plan = indoor_floor(6, width=14.0, depth=10.0, min_room=4.0, max_rooms=2, open_frac=0.6,
+                        n_pillars=1, target_tris=600)
+    rng = np.random.default_rng(6)
+    st = find_store(plan, plan.sample_points(rng, 1, 2.4, 2.6)[0],
+                    plan.sample_points(rng, 24, 1.0, 2.0), 5, n_rays=1 << 16)
+    from synth.params import draw_materials, materials_to_raw
+    raw = materials_to_raw(*draw_materials(rng, plan.scene.n_mat, with_scattering=True))
+    return st, raw
+
+
+def _gains(rng, M):
+    return (rng.uniform(0.8, 1.2, M) * np.exp(1j * rng.uniform(-0.7, 0.7, M))).astype(np.complex64)
+
+
+def _cases():
+    out = {}
+    _, st, raw, _, _ = array_workload()
+    rng = np.random.default_rng(3)
+    out["box_m32_n1024"] = (st, raw, Radio(fc=3.5e9, bandwidth=50e6, n_sc=1024, n_elem=32,
+                                           ula_axis=(0.6, 0.8, 0.0)), _gains(rng, 32))
+    st5, raw5 = _floor_case()
+    out["floor_depth5_m8_n512"] = (st5, raw5, Radio(fc=3.5e9, bandwidth=50e6, n_sc=512,
+                                                    n_elem=8), _gains(rng, 8))
+    out["floor_depth5_m32_n1024"] = (st5, raw5, Radio(fc=3.5e9, bandwidth=50e6, n_sc=1024,
+                                                      n_elem=32), _gains(rng, 32))
+    st4, raw4 = multi_material_box()
+    out["multimat_m4_n256"] = (st4, raw4, Radio(fc=3.5e9, bandwidth=50e6, n_sc=256, n_elem=4),
+                               _gains(rng, 4))
+    out["ragged_m7_n512"] = (ragged_subset(st, np.random.default_rng(17)), raw,
+                             Radio(fc=3.5e9, bandwidth=50e6, n_sc=512, n_elem=7,
+                                   ula_axis=(0.0, 1.0, 0.0)), _gains(rng, 7))
+    _, st1, raw1, _, _ = tiny_workload()
+    out["tiny_m1_n256"] = (st1, raw1, Radio(fc=3.5e9, bandwidth=50e6, n_sc=256, n_elem=1),
+                           _gains(rng, 1))
+    return out
+
+
+CASES = _cases()
+
+
+def _targets(st, raw, radio, g):
+    """Oracle CFR at shifted materials and gains (the hidden truth)."""
+    raw_t = np.array(raw, np.float64)
+    raw_t[:, 0] += 0.35
+    raw_t[:, 1] -= 0.3
+    g_t = np.asarray(g, np.complex128) * np.exp(0.15j) * 1.05
+    a_t, p_t = o_trace_id(st, torch.tensor(raw_t), radio.fc, ula_axis=radio.ula_axis)
+    f = och.subcarrier_freqs(radio.fc, radio.bandwidth, radio.n_sc)
+    return och.cfr(st.link_off, st.tau, a_t, p_t, torch.tensor(g_t), f).to(torch.complex64)
+
+
+def _run_both(rl, st, radio, a32, p32, g32, Ht, w=(1.0, 1.0)):
+    """Fused and separate entry points on the same device inputs."""
+    L, M, N, P = st.n_links, radio.n_elem, radio.n_sc, st.n_paths
+    dp = rl.DevicePaths(st)
+    rc = rl.radio_from(radio)
+    a, psi, g = a32.cuda(), p32.cuda(), g32.cuda()
+    Htd = Ht.cuda()
+    stats = torch.empty(2, dtype=torch.float64, device="cuda")
+    p_tgt = torch.empty((L, M, N), dtype=torch.float32, device="cuda")
+    rl.cfr_target_stats(rc, L, Htd, stats, rl.workspace(rl.RTC_OP_CFR_TARGET_STATS, rc, L, P),
+                        p_tgt=p_tgt)
+    loss = torch.full((3,), float("nan"), dtype=torch.float64, device="cuda")
+    dLda = torch.full((P,), float("nan"), dtype=torch.complex64, device="cuda")
+    dLdg = torch.full((M,), float("nan"), dtype=torch.complex64, device="cuda")
+    ws = rl.workspace(rl.RTC_OP_CFR_LOSS_ADJOINT, rc, L, P)
+    rl.cfr_loss_adjoint(rc, dp, a, psi, g, Htd, stats, p_tgt, w[0], w[1], loss, dLda, dLdg, ws)
+    # the same through the three separate calls
+    H = torch.empty((L, M, N), dtype=torch.complex64, device="cuda")
+    rl.cfr(rc, dp, a, psi, g, H)
+    loss2 = torch.empty(3, dtype=torch.float64, device="cuda")
+    rl.cfr_loss(rc, L, H, Htd, stats, w[0], w[1], loss2, H,
+                rl.workspace(rl.RTC_OP_CFR_LOSS, rc, L, P), p_tgt=p_tgt)
+    dLda2 = torch.empty(P, dtype=torch.complex64, device="cuda")
+    dLdg2 = torch.empty(M, dtype=torch.complex64, device="cuda")
+    rl.cfr_adjoint(rc, dp, a, psi, g, H, dLda2, dLdg2,
+                   rl.workspace(rl.RTC_OP_CFR_ADJOINT, rc, L, P))
+    torch.cuda.synchronize()
+    return ((loss.cpu(), dLda.cpu().to(c128), dLdg.cpu().to(c128)),
+            (loss2.cpu(), dLda2.cpu().to(c128), dLdg2.cpu().to(c128)))
+
+
+def _rel(x, ref):
+    return (torch.linalg.norm(x - ref) / torch.linalg.norm(ref)).item()
+
+
+def _per_link(x, ref, link_off):
+    worst = 0.0
+    for l in range(len(link_off) - 1):
+        lo, hi = int(link_off[l]), int(link_off[l + 1])
+        if hi > lo and torch.linalg.norm(ref[lo:hi]) > 0:
+            worst = max(worst, _rel(x[lo:hi], ref[lo:hi]))
+    return worst
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_fused_against_oracle(rl, case):
+    st, raw, radio, g = CASES[case]
+    say(f"fused {case}: L={st.n_links} P={st.n_paths} M={radio.n_elem} N={radio.n_sc}")
+    a_ref, psi_ref = o_trace_id(st, torch.tensor(raw, dtype=f64), radio.fc,
+                                ula_axis=radio.ula_axis)
+    a32, p32 = a_ref.to(torch.complex64), psi_ref.to(torch.float32)
+    g32 = torch.tensor(g)
+    Ht = _targets(st, raw, radio, g)
+    w = (0.8, 1.3)
+    (loss, da, dg), (loss2, da2, dg2) = _run_both(rl, st, radio, a32, p32, g32, Ht, w)
+    # oracle: the same inputs in FP64, reverse mode
+    a64 = a32.to(c128).requires_grad_(True)
+    g64 = g32.to(c128).requires_grad_(True)
+    f = och.subcarrier_freqs(radio.fc, radio.bandwidth, radio.n_sc)
+    H = och.cfr(st.link_off, st.tau, a64, p32.to(f64), g64, f)
+    tot, coh, inc = och.cfr_loss(H, Ht.to(c128), w_coh=w[0], w_pdp=w[1])
+    da_ref, dg_ref = torch.autograd.grad(tot, (a64, g64))
+    for got, ref in zip(loss.tolist(), (tot.item(), coh.item(), inc.item())):
+        assert abs(got - ref) <= 1e-5 * abs(ref), (got, ref)
+    e_a, e_al, e_g = _rel(da, da_ref), _per_link(da, da_ref, st.link_off), _rel(dg, dg_ref)
+    e_a2, e_g2 = _rel(da2, da_ref), _rel(dg2, dg_ref)
+    say(f"fused {case}: dL/da {e_a:.2e} (per link {e_al:.2e}), dL/dg {e_g:.2e}; "
+        f"separate calls {e_a2:.2e}, {e_g2:.2e}; fused vs separate {_rel(da, da2):.2e}")
+    assert e_a <= 3e-5 and e_al <= 1e-4 and e_g <= 3e-5, (e_a, e_al, e_g)
+    # links without paths get no gradient entries; every path gets one
+    assert torch.isfinite(da).all()
+    # and the separate calls agree with it
+    for x, y in zip(loss.tolist(), loss2.tolist()):
+        assert abs(x - y) <= 1e-5 * abs(y)
+    assert _rel(da, da2) <= 3e-5 and _rel(dg, dg2) <= 3e-5
+
+
+def test_fused_without_outputs_and_refusals(rl):
+    """dLda and dLdg are optional; unsupported shapes are refused on the
+    host with RTC_ERR_UNSUPPORTED and a message naming the separate calls."""
+    st, raw, radio, g = CASES["multimat_m4_n256"]
+    L, M, N, P = st.n_links, radio.n_elem, radio.n_sc, st.n_paths
+    a_ref, psi_ref = o_trace_id(st, torch.tensor(raw, dtype=f64), radio.fc,
+                                ula_axis=radio.ula_axis)
+    a, psi, gd = a_ref.to(torch.complex64).cuda(), psi_ref.float().cuda(), torch.tensor(g).cuda()
+    Ht = _targets(st, raw, radio, g).cuda()
+    dp = rl.DevicePaths(st)
+    rc = rl.radio_from(radio)
+    stats = torch.empty(2, dtype=torch.float64, device="cuda")
+    p_tgt = torch.empty((L, M, N), dtype=torch.float32, device="cuda")
+    rl.cfr_target_stats(rc, L, Ht, stats, rl.workspace(rl.RTC_OP_CFR_TARGET_STATS, rc, L, P),
+                        p_tgt=p_tgt)
+    ws = rl.workspace(rl.RTC_OP_CFR_LOSS_ADJOINT, rc, L, P)
+    l1 = torch.empty(3, dtype=torch.float64, device="cuda")
+    l2 = torch.empty(3, dtype=torch.float64, device="cuda")
+    dLda = torch.empty(P, dtype=torch.complex64, device="cuda")
+    rl.cfr_loss_adjoint(rc, dp, a, psi, gd, Ht, stats, p_tgt, 1.0, 1.0, l1, dLda, None, ws)
+    rl.cfr_loss_adjoint(rc, dp, a, psi, gd, Ht, stats, p_tgt, 1.0, 1.0, l2, None, None, ws)
+    torch.cuda.synchronize()
+    assert torch.equal(l1.cpu(), l2.cpu())
+    for bad in (dict(n_sc=2048, n_elem=4), dict(n_sc=256, n_elem=33), dict(n_sc=128, n_elem=4)):
+        rb = rl.make_radio(3.5e9, 50e6 / bad["n_sc"], bad["n_sc"], bad["n_elem"])
+        assert not rl.fused_supported(rb)
+        with pytest.raises(RuntimeError, match="rtc_cfr_loss_adjoint.*separate|use rtc_cfr"):
+            rl.cfr_loss_adjoint(rb, dp, a, psi, gd, Ht, stats, p_tgt, 1.0, 1.0, l1, None, None,
+                                ws)
+
+
+def test_fused_full_scale_sampled_links(rl):
+    """The scale workload's shape (16,384 links x 32 elements x 1,024
+    subcarriers, 3.05 M paths) in the launch configuration the bench times,
+    with seeded stand-in coefficients and targets: 12 sampled links' dL/da
+    against the oracle's gradient (the batch normalisers from the oracle's
+    own sums over all targets), and every output against the separate
+    calls."""
+    from synth import workloads
+    w = workloads.scale()
+    st, radio = w.store, w.radio
+    L, M, N, P = st.n_links, radio.n_elem, radio.n_sc, st.n_paths
+    rng = np.random.default_rng(77)
+    a32, p32 = draw_path_coefficients(rng, st.tau, radio.fc)
+    power = np.add.reduceat(np.abs(a32.astype(np.complex128)) ** 2, st.link_off[:-1]) \
+        if P else np.zeros(L)
+    power[np.diff(st.link_off) == 0] = 1e-12
+    Ht = draw_target_cfr(rng, power, M, N)
+    say(f"fused full scale: L={L} P={P}")
+    (loss, da, dg), (loss2, da2, dg2) = _run_both(
+        rl, st, radio, torch.tensor(a32), torch.tensor(p32), torch.tensor(w.g), torch.tensor(Ht))
+    # batch normalisers by the oracle, in chunks of rows
+    zc, zp = 0.0, 0.0
+    Ht_rows = Ht.reshape(-1, N)
+    for r0 in range(0, Ht_rows.shape[0], 8192):
+        blk = torch.tensor(Ht_rows[r0:r0 + 8192]).to(c128)
+        zc += torch.sum(torch.abs(blk) ** 2).item()
+        zp += torch.sum(och.pdp(blk) ** 2).item()
+    links = np.sort(rng.choice(L, 12, replace=False))
+    sel = np.concatenate([np.arange(st.link_off[l], st.link_off[l + 1]) for l in links])
+    off = np.concatenate([[0], np.cumsum(np.diff(st.link_off)[links])])
+    a64 = torch.tensor(a32[sel]).to(c128).requires_grad_(True)
+    f = och.subcarrier_freqs(radio.fc, radio.bandwidth, radio.n_sc)
+    H = och.cfr(off, st.tau[sel], a64, torch.tensor(p32[sel]).double(),
+                torch.tensor(w.g).to(c128), f)
+    e_c, _, e_p, _ = och.cfr_loss_sums(H, torch.tensor(Ht[links]).to(c128))
+    (da_ref,) = torch.autograd.grad(e_c / zc + e_p / zp, a64)
+    worst = _per_link(da[sel], da_ref, off)
+    say(f"fused full scale: sampled links dL/da max per-link error {worst:.2e}; "
+        f"fused vs separate dL/da {_rel(da, da2):.2e}, dL/dg {_rel(dg, dg2):.2e}, "
+        f"loss {loss.tolist()} vs {loss2.tolist()}")
+    assert worst <= 1e-4
+    assert _rel(da, da2) <= 3e-5 and _rel(dg, dg2) <= 3e-5
+    for x, y in zip(loss.tolist(), loss2.tolist()):
+        assert abs(x - y) <= 1e-5 * abs(y)
