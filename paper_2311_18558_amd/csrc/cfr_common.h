@@ -8,6 +8,26 @@ namespace rtc {
 
 constexpr double kInv2Pi = 0.15915494309189533577;
 
+// v of lane (lane ^ O) within each 32-lane half, O < 32: ds_swizzle in its
+// bit mode (and mask 0x1f, xor mask O) takes the pattern as an immediate, so
+// no per-lane address is formed (or held in a register)
+template <int O>
+RTC_DEV float swz_xor(float v) {
+  static_assert(O > 0 && O < 32, "within a 32-lane half");
+  return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), (O << 10) | 0x1f));
+}
+
+// Butterfly sum over the 32 lanes of each half-wave (fixed order; every
+// lane of the half gets its half's total).
+RTC_DEV float half_sum_f32(float v) {
+  v += swz_xor<16>(v);
+  v += swz_xor<8>(v);
+  v += swz_xor<4>(v);
+  v += swz_xor<2>(v);
+  v += swz_xor<1>(v);
+  return v;
+}
+
 RTC_DEV float wave_max_f32(float v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));

@@ -26,9 +26,8 @@
 //     the waves' partial G meet in LDS and one wave (rotating) applies the
 //     path phase, array phases and gains: dL/da per path, dL/dg summed over
 //     the link's tiles in order (LDS, FP64), one row per link.
-// The loss partials {sum|H-H*|^2, sum|H*|^2, sum(p-p*)^2, sum(p*)^2} of each
-// (link, wave) and the per-link dL/dg rows are reduced across the batch in a
-// fixed order.
+// The loss sums {sum|H-H*|^2, sum(p-p*)^2} of each (link, wave) and the
+// per-link dL/dg rows are reduced across the batch in a fixed order.
 #include <cmath>
 
 #include "api_common.h"
@@ -68,7 +67,7 @@ struct FusedArgs {
   const double* Z;   // {sum |H*|^2, sum (p*)^2} over the batch
   float w_coh, w_pdp;
   double fref, t_off, df, cm;  // grid midpoint, t of pair 0, spacing, (M-1)/2
-  double* row_out;  // [L*NW][4] loss partials per link and wave
+  double* row_out;  // [L*NW][2] loss sums per link and wave
   float2* dLda;     // [P] or null
   double* g_part;   // [L][M][2] per-link dL/dg, or null
 };
@@ -123,8 +122,9 @@ __device__ __forceinline__ void load_row_targets(const FusedArgs& A, int64_t rid
 // H[N/2 + q] = X + jY and H[N/2 - 1 - q] = X - jY; on return it holds the
 // adjoint's operands {Re S, Im S, -Re D, Im D}, S = dH[N/2 + q] +
 // dH[N/2 - 1 - q], D = dH[N/2 + q] - dH[N/2 - 1 - q].  One wave; b0, b1 its
-// own FFT buffers; the row's four loss sums are added to `sums` (per lane,
-// FP64).  The loss arithmetic is that of cfr_loss_wave_kernel with a
+// own FFT buffers; the row's two loss sums, sum |H - H*|^2 and
+// sum (p - p*)^2, are added to `sums` (per lane, FP64; the normalisers come
+// from the targets' statistics).  The loss arithmetic is that of cfr_loss_wave_kernel with a
 // precomputed target PDP (loss.hip).  Element n = j + BA r of the first FFT
 // pass (lane j < BA) is pair j + BA (r - 8) (upper half, r >= 8) or
 // BA - 1 - j + BA (7 - r) (lower half) -- the mirror n -> N - 1 - n is lane
@@ -132,7 +132,7 @@ __device__ __forceinline__ void load_row_targets(const FusedArgs& A, int64_t rid
 template <int LOGN>
 __device__ __forceinline__ void fused_loss_row(float4* row, const RowTargets<LOGN>& T, float us,
                                                float2* b0, float2* b1, float gc, float gp,
-                                               double (&sums)[4], int lane_in) {
+                                               double (&sums)[2], int lane_in) {
   // the FFT twiddles depend on the lane and the pass only; an opaque lane
   // index keeps the compiler from holding them across rows (and the group
   // loop), where they would take registers the loop needs
@@ -148,7 +148,7 @@ __device__ __forceinline__ void fused_loss_row(float4* row, const RowTargets<LOG
   const int j = lane;
   const bool act = BA == 64 || j < BA;
   float2 vh[1][16], diff[16];
-  float ec = 0.0f, et = 0.0f;
+  float ec = 0.0f;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     float2 h = make_float2(0.0f, 0.0f);
@@ -164,11 +164,10 @@ __device__ __forceinline__ void fused_loss_row(float4* row, const RowTargets<LOG
     vh[0][r] = h;
     diff[r] = csub(h, T.t[r]);
     ec += cabs2(diff[r]);
-    et += cabs2(T.t[r]);
   }
   float2 xh[JZ][RZ];
   fft_full<LOGN, +1, +1, WaveSync>(vh, xh, b0, b1, lane);
-  float ep = 0.0f, eq = 0.0f;
+  float ep = 0.0f;
 #pragma unroll
   for (int i = 0; i < JZ; ++i) {
     const int jj = lane + 64 * i;
@@ -178,15 +177,12 @@ __device__ __forceinline__ void fused_loss_row(float4* row, const RowTargets<LOG
         const float p = cabs2(xh[i][r]) * invN;
         const float d = p - T.p[i][r];
         ep += d * d;
-        eq += T.p[i][r] * T.p[i][r];
         xh[i][r] = cscale(xh[i][r], gp * d);  // gradient source
       }
     }
   }
   sums[0] += (double)ec;
-  sums[1] += (double)et;
-  sums[2] += (double)ep;
-  sums[3] += (double)eq;
+  sums[1] += (double)ep;
   float2 G[1][16];
   fft_full<LOGN, -1, -1, WaveSync>(xh, G, b0, b1, lane);
   // dL/dH = gc (H - H*) + G; pair slot j + BA r' takes its upper element
@@ -212,7 +208,7 @@ __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs 
   __shared__ __align__(16) char smem[F::SMEM];
   __shared__ float2 fb[NW][2][fft_lds_len(N)];
   __shared__ float wmax[NW];
-  __shared__ float2 dabuf[2][NW * 32];
+  __shared__ float2 dabuf[2][NW * 64];
   float4* rowbuf = reinterpret_cast<float4*>(smem);
   float* gbuf = reinterpret_cast<float*>(smem);
 
@@ -321,7 +317,7 @@ __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs 
   const float gp = (float)(4.0 * (double)A.w_pdp / (A.Z[1] * (double)N));
   const int n_groups = (M + 7) >> 3;
   auto row_of = [&](int k) { return 8 * (k / F::RPW) + wv + NW * (k % F::RPW); };
-  double sums[4] = {0.0, 0.0, 0.0, 0.0};
+  double sums[2] = {0.0, 0.0};
   for (int grp = 0; grp < n_groups; ++grp) {
     __syncthreads();  // the previous group's read-back is done
     if ((col >> 3) == grp) {
@@ -367,10 +363,10 @@ __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs 
   }
   // the wave's loss sums over its rows: lanes in a fixed butterfly order
 #pragma unroll
-  for (int k = 0; k < 4; ++k) sums[k] = wave_sum_f64(sums[k]);
+  for (int k = 0; k < 2; ++k) sums[k] = wave_sum_f64(sums[k]);
   if (lane == 0) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) A.row_out[(l * NW + wv) * 4 + k] = sums[k];
+    for (int k = 0; k < 2; ++k) A.row_out[(l * NW + wv) * 2 + k] = sums[k];
   }
 
   // ------------------------------------------------------------ 3. adjoint
@@ -420,9 +416,9 @@ __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs 
   // The epilogue of a tile is split over the waves by element rows: wave w
   // takes the row groups g4 in [G4W w, G4W (w + 1)) (rows 8 g4 + 4 half +
   // 0..3, registers 4 g4 .. 4 g4 + 3 of G).  Its dL/dg rows accumulate in
-  // the wave's registers (FP64, tiles in order); its share of dL/da goes to
-  // LDS and the wave that finishes the tile adds the waves' shares in order
-  // after the next barrier.
+  // the wave's registers (FP64, tiles in order); each half-wave's share of
+  // dL/da goes to LDS and the wave that finishes the tile adds the shares in
+  // order after the next barrier.
   constexpr int G4W = 4 / NW;
   double dgw[G4W][4][2];
 #pragma unroll
@@ -430,13 +426,13 @@ __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs 
 #pragma unroll
     for (int b = 0; b < 4; ++b) dgw[a][b][0] = dgw[a][b][1] = 0.0;
   auto finish_da = [&](int T) {
-    // dL/da of tile T: the waves' shares in wave order (half 0 lanes)
+    // dL/da of tile T: the shares of the waves' half-waves, in order
     const float2* db = dabuf[T & 1];
     const int64_t p = off0 + 32 * (int64_t)T + col;
     if (half == 0 && p < off1 && A.dLda) {
-      float2 d = db[col];
+      float2 d = cadd(db[col], db[32 + col]);
 #pragma unroll
-      for (int w = 1; w < NW; ++w) d = cadd(d, db[w * 32 + col]);
+      for (int w = 1; w < NW; ++w) d = cadd(d, cadd(db[w * 64 + col], db[w * 64 + 32 + col]));
       A.dLda[p] = d;
     }
   };
@@ -515,20 +511,14 @@ __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs 
         const float2 Gph = cmul(G, ph);
         da = cadd(da, cmulc(gmv, Gph));
         // dL/dg: sum over the 32 paths of this half (fixed butterfly)
-        float2 tg = cmulc(ai, Gph);
-#pragma unroll
-        for (int o = 16; o >= 1; o >>= 1) {
-          tg.x += __shfl_xor(tg.x, o, 64);
-          tg.y += __shfl_xor(tg.y, o, 64);
-        }
-        dgw[a][qq][0] += (double)tg.x;
-        dgw[a][qq][1] += (double)tg.y;
+        const float2 tg = cmulc(ai, Gph);
+        dgw[a][qq][0] += (double)half_sum_f32(tg.x);
+        dgw[a][qq][1] += (double)half_sum_f32(tg.y);
       }
     }
-    // the wave's share of dL/da: both halves (their rows) added
-    da.x += __shfl_xor(da.x, 32, 64);
-    da.y += __shfl_xor(da.y, 32, 64);
-    if (half == 0) dabuf[T & 1][wv * 32 + col] = da;
+    // the half-wave's share of dL/da (its rows of the path), added in order
+    // by the wave that finishes the tile
+    dabuf[T & 1][wv * 64 + lane] = da;
   }
   __syncthreads();  // the last tile's shares are in LDS; every epilogue is done
   if (n_tiles > 0 && wv == (n_tiles - 1) % NW) finish_da(n_tiles - 1);
@@ -553,7 +543,7 @@ __global__ void fused_finish_kernel(const double* sums, const double* Z, float w
                                     float w_pdp, double* loss) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const double coh = sums[0] / Z[0];
-  const double pdp = sums[2] / Z[1];
+  const double pdp = sums[1] / Z[1];
   loss[0] = (double)w_coh * coh + (double)w_pdp * pdp;
   loss[1] = coh;
   loss[2] = pdp;
@@ -572,14 +562,14 @@ bool fused_supported(const rtc_radio* r) {
 // waves per workgroup of the fused kernel for n_sc subcarriers
 static int fused_waves(int n_sc) { return n_sc / 256; }
 
-// Workspace: loss partials [L*NW][4] | their reduction tmp | sums [4] |
+// Workspace: loss sums [L*NW][2] | their reduction tmp | sums [2] |
 // per-link dL/dg [L][M][2] | its reduction tmp | reduced [M][2] (doubles).
 size_t ws_cfr_loss_adjoint(const rtc_radio* r, int32_t n_links) {
   if (!fused_supported(r)) return 0;
   const int64_t L = n_links > 0 ? n_links : 1;
   const int64_t R = L * fused_waves(r->n_sc);
   const int K = 2 * r->n_elem;
-  return (size_t)(R * 4 + reduce_tmp_doubles(R, 4) + 4 + L * K + reduce_tmp_doubles(L, K) + K) *
+  return (size_t)(R * 2 + reduce_tmp_doubles(R, 2) + 2 + L * K + reduce_tmp_doubles(L, K) + K) *
          sizeof(double);
 }
 
@@ -616,9 +606,9 @@ extern "C" rtc_status rtc_cfr_loss_adjoint(const rtc_radio* radio, const rtc_pat
   const int64_t R = L * fused_waves(N);
   const int K = 2 * M;
   double* rows = reinterpret_cast<double*>(ws);
-  double* rtmp = rows + R * 4;
-  double* sums = rtmp + reduce_tmp_doubles(R, 4);
-  double* gpart = sums + 4;
+  double* rtmp = rows + R * 2;
+  double* sums = rtmp + reduce_tmp_doubles(R, 2);
+  double* gpart = sums + 2;
   double* gtmp = gpart + L * K;
   double* gred = gtmp + reduce_tmp_doubles(L, K);
 
@@ -655,7 +645,7 @@ extern "C" rtc_status rtc_cfr_loss_adjoint(const rtc_radio* radio, const rtc_pat
                          A);
   }
   if ((st = check_launch(fn)) != RTC_OK) return st;
-  if ((st = reduce_all(rows, R, 4, rtmp, sums, s, fn)) != RTC_OK) return st;
+  if ((st = reduce_all(rows, R, 2, rtmp, sums, s, fn)) != RTC_OK) return st;
   hipLaunchKernelGGL(fused_finish_kernel, dim3(1), dim3(64), 0, s, sums, tgt_stats, w_coh, w_pdp,
                      loss);
   if ((st = check_launch(fn)) != RTC_OK) return st;
