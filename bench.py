@@ -50,8 +50,8 @@ PEAK_HBM_GBS = 8000.0
 DTYPE = "fp16x2-split/fp32-acc"
 COPY_PROBE_BYTES = 2 << 30
 # sources whose change invalidates the committed HBM counter figures
-HOT_SOURCES = ["cfr.hip", "split_f16.h", "dev_common.h", "api_common.h", "loss.hip",
-               "paper_loss.hip", "fft_wave.h", "fft_block.h"]
+HOT_SOURCES = ["cfr.hip", "fused.hip", "cfr_common.h", "split_f16.h", "dev_common.h",
+               "api_common.h", "loss.hip", "paper_loss.hip", "fft_wave.h"]
 
 
 def log(msg):

@@ -31,7 +31,6 @@
 
 #include "api_common.h"
 #include "dev_common.h"
-#include "fft_block.h"
 #include "cfr_common.h"
 #include "split_f16.h"
 

@@ -130,3 +130,17 @@ RTC_DEV float wave_sum_f32(float v) {
   for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
+
+// Sum of a double over the block in a fixed order (wave butterfly, then the
+// waves in index order).  All threads must call; result valid on thread 0.
+RTC_DEV double block_sum_f64(double v, double* red) {
+  v = wave_sum_f64(v);
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+  __syncthreads();
+  return s;
+}

@@ -10,7 +10,6 @@
 // sums rounded once, so that the result does not depend on the launch.
 #include "api_common.h"
 #include "dev_common.h"
-#include "fft_block.h"
 
 namespace rtc {
 

@@ -1,11 +1,14 @@
-// One-wave FFTs of length N = 2^LOGN (2..4096) for the CFR loss.
+// Register FFTs of length N = 2^LOGN (2..4096) for the CFR losses: one
+// wave per transform up to N = 1024, T = N/16 threads (one radix-16
+// butterfly each per pass) beyond.
 //
 // Stockham autosort formulation: pass p (radix R, Ns = product of the radices
 // before it) takes butterfly j (0 <= j < N/R), reads x[j + r N/R], multiplies
 // element r by exp(+-j 2 pi r (j mod Ns) / (Ns R)), applies an R-point DFT
 // and writes element r to (j / Ns) Ns R + (j mod Ns) + r Ns.  After the last
 // pass the output is in natural order.  Radices are 16 while possible, then
-// the remaining 2, 4 or 8.  Butterfly j of every pass belongs to lane j mod 64.
+// the remaining 2, 4 or 8.  Butterfly j of every pass belongs to thread
+// j mod T of the T threads that share the transform (T = 64: one wave).
 //
 // Two properties let the loss keep data in registers between transforms:
 //  * the first pass (Ns = 1) reads x[j + r N/R0] and the last pass leaves
@@ -122,15 +125,49 @@ RTC_DEV void dft(float2* v) {
   if constexpr (R == 16) dft16<SIGN>(v);
 }
 
-// Butterflies per lane for a pass of radix R over N points.
-constexpr int fft_bpl(int n, int r) { return (n / r + 63) / 64; }
+// Threads that share a transform of length 2^logn in the loss kernels: one
+// wave up to 1024 points, then one radix-16 butterfly per thread.
+constexpr int fft_threads(int logn) { return logn <= 10 ? 64 : (1 << logn) / 16; }
+
+// Butterflies per thread for a pass of radix R over N points, T threads.
+constexpr int fft_bpl(int n, int r, int t = 64) { return (n / r + t - 1) / t; }
 
 // Twiddle of pass (Ns, R) for butterfly j: element r times w^r,
-// w = exp(SIGN j 2 pi (j mod Ns) / (Ns R)).
-template <int R, int SIGN>
+// w = exp(SIGN j 2 pi (j mod Ns) / (Ns R)).  Up to 1024 points w comes from
+// the transcendental unit and its powers by recurrence; beyond (ACC), where
+// the longer recurrences of radix-8 and -16 passes would multiply w's error
+// by up to 15 (and the losses of long rows are sensitive to it), w and w^4
+// are evaluated by polynomial (sincos2pi) and w^(4a+b) = (w^4)^a w^b with
+// a, b <= 3, so no power is more than a few products from an evaluated
+// value.
+template <int R, int SIGN, bool ACC = false>
 RTC_DEV void fft_twiddle(float2* v, int j, int Ns) {
   if (Ns == 1) return;
   const int k = j % Ns;
+  if constexpr (ACC) {
+    constexpr int NB = R < 4 ? R : 4, NA = R < 4 ? 1 : R / 4;
+    const float x = (float)k / (float)(Ns * R);  // exact, as is 4x
+    float2 p[4], q[4];
+    float s1, c1;
+    sincos2pi(x, &s1, &c1);
+    p[1] = make_float2(c1, SIGN * s1);
+#pragma unroll
+    for (int b = 2; b < NB; ++b) p[b] = cmul(p[b - 1], p[1]);
+    if constexpr (NA > 1) {
+      float s4, c4;
+      sincos2pi(4.0f * x, &s4, &c4);
+      q[1] = make_float2(c4, SIGN * s4);
+#pragma unroll
+      for (int a = 2; a < NA; ++a) q[a] = cmul(q[a - 1], q[1]);
+    }
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+      const int a = r / NB, b = r % NB;
+      const float2 wr = a == 0 ? p[b] : (b == 0 ? q[a] : cmul(q[a], p[b]));
+      v[r] = cmul(v[r], wr);
+    }
+    return;
+  }
   // k / (Ns R) is an exact fraction in [0, 1) (powers of two); the
   // transcendental unit takes it in revolutions
   const float x = (float)k / (float)(Ns * R);
@@ -143,15 +180,15 @@ RTC_DEV void fft_twiddle(float2* v, int j, int Ns) {
   }
 }
 
-// Pass from registers (v[i][r] of butterfly j = lane + 64 i) to LDS `out`.
-template <int N, int R, int SIGN>
+// Pass from registers (v[i][r] of butterfly j = lane + T i) to LDS `out`.
+template <int N, int R, int SIGN, int T = 64>
 RTC_DEV void fft_pass_r2l(float2 (*v)[R], float2* out, int Ns, int lane) {
   constexpr int B = N / R;
 #pragma unroll
-  for (int i = 0; i < fft_bpl(N, R); ++i) {
-    const int j = lane + 64 * i;
+  for (int i = 0; i < fft_bpl(N, R, T); ++i) {
+    const int j = lane + T * i;
     if (j < B) {
-      fft_twiddle<R, SIGN>(v[i], j, Ns);
+      fft_twiddle<R, SIGN, (N > 1024)>(v[i], j, Ns);
       dft<R, SIGN>(v[i]);
       const int d = (j / Ns) * Ns * R + (j % Ns);
 #pragma unroll
@@ -161,16 +198,16 @@ RTC_DEV void fft_pass_r2l(float2 (*v)[R], float2* out, int Ns, int lane) {
 }
 
 // Pass from LDS `in` to registers v[i][r] (no store).
-template <int N, int R, int SIGN>
+template <int N, int R, int SIGN, int T = 64>
 RTC_DEV void fft_pass_l2r(const float2* in, float2 (*v)[R], int Ns, int lane) {
   constexpr int B = N / R;
 #pragma unroll
-  for (int i = 0; i < fft_bpl(N, R); ++i) {
-    const int j = lane + 64 * i;
+  for (int i = 0; i < fft_bpl(N, R, T); ++i) {
+    const int j = lane + T * i;
     if (j < B) {
 #pragma unroll
       for (int r = 0; r < R; ++r) v[i][r] = in[lds_pad(j + r * B)];
-      fft_twiddle<R, SIGN>(v[i], j, Ns);
+      fft_twiddle<R, SIGN, (N > 1024)>(v[i], j, Ns);
       dft<R, SIGN>(v[i]);
     }
   }
@@ -208,7 +245,7 @@ constexpr int seq_ns() {
 
 // Pass P (1 <= P <= npass-2): LDS -> LDS, ping-ponging b0/b1 (pass 0
 // writes b0), then the following middle passes.
-template <int LOGN, int SIGN, int ORDER, int P, class SY = BlockSync>
+template <int LOGN, int SIGN, int ORDER, int P, class SY = BlockSync, int T = 64>
 RTC_DEV void fft_mid(float2* b0, float2* b1, int lane) {
   constexpr int NP = fft_npass(LOGN);
   if constexpr (P <= NP - 2) {
@@ -218,50 +255,70 @@ RTC_DEV void fft_mid(float2* b0, float2* b1, int lane) {
     const float2* in = ((P - 1) & 1) ? b1 : b0;
     float2* out = (P & 1) ? b1 : b0;
     SY::sync();
-    float2 v[fft_bpl(N, R)][R];
-    fft_pass_l2r<N, R, SIGN>(in, v, NS, lane);
+    float2 v[fft_bpl(N, R, T)][R];
+    fft_pass_l2r<N, R, SIGN, T>(in, v, NS, lane);
 #pragma unroll
-    for (int i = 0; i < fft_bpl(N, R); ++i) {
-      const int j = lane + 64 * i;
+    for (int i = 0; i < fft_bpl(N, R, T); ++i) {
+      const int j = lane + T * i;
       if (j < N / R) {
         const int d = (j / NS) * NS * R + (j % NS);
 #pragma unroll
         for (int r = 0; r < R; ++r) out[lds_pad(d + r * NS)] = v[i][r];
       }
     }
-    fft_mid<LOGN, SIGN, ORDER, P + 1, SY>(b0, b1, lane);
+    fft_mid<LOGN, SIGN, ORDER, P + 1, SY, T>(b0, b1, lane);
   }
 }
 
 // Whole transform: vin holds the first pass's inputs (butterfly j = lane +
-// 64 i, element r = x[j + r N/R_first]); vout receives the last pass's
+// T i, element r = x[j + r N/R_first]); vout receives the last pass's
 // outputs (element r of butterfly j = X[j + r N/R_last]).  b0, b1: two LDS
-// buffers of fft_lds_len(N) values.
-template <int LOGN, int SIGN, int ORDER, class SY = BlockSync, int J0, int R0, int JL, int RL>
+// buffers of fft_lds_len(N) values; lane = the thread's index among the T.
+template <int LOGN, int SIGN, int ORDER, class SY = BlockSync, int T = 64, int J0, int R0,
+          int JL, int RL>
 RTC_DEV void fft_full(float2 (&vin)[J0][R0], float2 (&vout)[JL][RL], float2* b0, float2* b1,
                       int lane) {
   constexpr int N = 1 << LOGN;
   constexpr int NP = fft_npass(LOGN);
   static_assert(R0 == seq_radix<LOGN, ORDER, 0>(), "first-pass layout");
   static_assert(RL == seq_radix<LOGN, ORDER, NP - 1>(), "last-pass layout");
-  static_assert(J0 == fft_bpl(N, R0) && JL == fft_bpl(N, RL), "butterflies per lane");
+  static_assert(J0 == fft_bpl(N, R0, T) && JL == fft_bpl(N, RL, T), "butterflies per thread");
   if constexpr (NP == 1) {
 #pragma unroll
-    for (int i = 0; i < fft_bpl(N, R0); ++i) {
-      if (lane + 64 * i < N / R0) {
+    for (int i = 0; i < fft_bpl(N, R0, T); ++i) {
+      if (lane + T * i < N / R0) {
         dft<R0, SIGN>(vin[i]);
 #pragma unroll
         for (int r = 0; r < R0; ++r) vout[i][r] = vin[i][r];
       }
     }
   } else {
-    fft_pass_r2l<N, R0, SIGN>(vin, b0, 1, lane);
-    fft_mid<LOGN, SIGN, ORDER, 1, SY>(b0, b1, lane);
+    fft_pass_r2l<N, R0, SIGN, T>(vin, b0, 1, lane);
+    fft_mid<LOGN, SIGN, ORDER, 1, SY, T>(b0, b1, lane);
     constexpr int PL = NP - 1;
     const float2* in = ((PL - 1) & 1) ? b1 : b0;
     SY::sync();
-    fft_pass_l2r<N, RL, SIGN>(in, vout, seq_ns<LOGN, ORDER, PL>(), lane);
+    fft_pass_l2r<N, RL, SIGN, T>(in, vout, seq_ns<LOGN, ORDER, PL>(), lane);
     SY::sync();
+  }
+}
+
+// Sum of a double over the T threads of a transform in a fixed order (wave
+// butterflies, then the waves in index order); every thread gets the total.
+// red: T/64 doubles of LDS (unused for T = 64).
+template <int T>
+RTC_DEV double group_sum_f64(double v, double* red) {
+  v = wave_sum_f64(v);
+  if constexpr (T == 64) {
+    return v;
+  } else {
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = red[0];
+#pragma unroll
+    for (int w = 1; w < T / 64; ++w) s += red[w];
+    __syncthreads();
+    return s;
   }
 }
 

@@ -1,11 +1,11 @@
 // Coherent + power-delay-profile CFR loss and its gradient dL/dH.
 //
-// One workgroup per CFR row (link l, element m) at a time, grid-striding over
-// rows.  A row of N subcarriers (and its target) is transformed in LDS by a
-// radix-2 FFT to the CIR taps of the centred 1/sqrt(N) IDFT (Sec. II-A);
-// the power delay profile is p_l = |h[l]|^2 = |X_l|^2 / N with X the
-// unnormalised inverse DFT (the centring multiplies taps by unit-modulus
-// factors and reorders them, which changes neither |.|^2 nor the sums).
+// The threads of one row (one wave up to 1024 subcarriers, N/16 beyond)
+// transform it to the CIR taps of the centred 1/sqrt(N) IDFT (Sec. II-A) with
+// a register Stockham FFT (fft_wave.h); the power delay profile is
+// p_l = |h[l]|^2 = |X_l|^2 / N with X the unnormalised inverse DFT (the
+// centring multiplies taps by unit-modulus factors and reorders them, which
+// changes neither |.|^2 nor the sums).
 //
 // With Z_c = sum|H*|^2 and Z_p = sum (p*)^2 over the batch,
 //   L = w_c sum|H - H*|^2 / Z_c + w_p sum (p - p*)^2 / Z_p
@@ -18,159 +18,35 @@
 
 #include "api_common.h"
 #include "dev_common.h"
-#include "fft_block.h"
 #include "fft_wave.h"
 
 namespace rtc {
 
-constexpr int kLossBlock = 256;
-constexpr int kLossMaxPerThread = kMaxFFT / kLossBlock;  // 16
 constexpr int kRedBlock = 256;
 constexpr int kRedChunk = 64;  // rows per reduction block (first two levels)
 
-// Target statistics per row: {sum |H*|^2, sum (p*)^2}; with Pt also p*.
-__global__ void __launch_bounds__(kLossBlock)
-    target_stats_kernel(const float2* __restrict__ Ht, int64_t n_rows, int N, int logN,
-                        double* row_out, float* Pt) {
-  extern __shared__ float2 sm[];
-  float2* tw = sm;
-  float2* xt = sm + N / 2;
-  __shared__ double red[kLossBlock / 64];
-  make_twiddles(tw, N);
-  const float invN = 1.0f / (float)N;
-  for (int64_t row = blockIdx.x; row < n_rows; row += gridDim.x) {
-    const float2* src = Ht + row * N;
-    float e = 0.0f;
-    for (int n = threadIdx.x; n < N; n += blockDim.x) {
-      float2 v = src[n];
-      e += cabs2(v);
-      xt[bitrev(n, logN)] = v;
-    }
-    __syncthreads();
-    fft_lds<+1>(xt, tw, N, logN);
-    float q = 0.0f;
-    for (int k = threadIdx.x; k < N; k += blockDim.x) {
-      float p = cabs2(xt[k]) * invN;
-      q += p * p;
-      if (Pt) Pt[row * N + k] = p;
-    }
-    double se = block_sum_f64((double)e, red);
-    double sq = block_sum_f64((double)q, red);
-    if (threadIdx.x == 0) {
-      row_out[row * 2 + 0] = se;
-      row_out[row * 2 + 1] = sq;
-    }
-    __syncthreads();
-  }
-}
-
-// Main per-row pass.  Z (device, 2 doubles) holds the batch normalisers when
-// dLdH is requested; row_out gets {sum|H-H*|^2, sum|H*|^2, sum(p-p*)^2,
-// sum(p*)^2}.
-__global__ void __launch_bounds__(kLossBlock)
-    cfr_loss_kernel(const float2* H, const float2* __restrict__ Ht, int64_t n_rows, int N,
-                    int logN, const double* Z, float w_coh, float w_pdp, double* row_out,
-                    float2* dLdH) {
-  extern __shared__ float2 sm[];
-  float2* tw = sm;
-  float2* x = sm + N / 2;
-  float2* xt = x + N;
-  __shared__ double red[kLossBlock / 64];
-  make_twiddles(tw, N);
-  const float invN = 1.0f / (float)N;
-  float gc = 0.0f, gp = 0.0f;
-  if (dLdH) {
-    gc = (float)(2.0 * (double)w_coh / Z[0]);
-    gp = (float)(4.0 * (double)w_pdp / (Z[1] * (double)N));
-  }
-  for (int64_t row = blockIdx.x; row < n_rows; row += gridDim.x) {
-    const float2* hs = H + row * N;
-    const float2* ts = Ht + row * N;
-    float2 diff[kLossMaxPerThread];
-    float ec = 0.0f, et = 0.0f;
-#pragma unroll
-    for (int u = 0; u < kLossMaxPerThread; ++u) {
-      const int n = threadIdx.x + u * kLossBlock;
-      if (n < N) {
-        float2 h = hs[n];
-        float2 t = ts[n];
-        diff[u] = csub(h, t);
-        ec += cabs2(diff[u]);
-        et += cabs2(t);
-        const int br = bitrev(n, logN);
-        x[br] = h;
-        xt[br] = t;
-      }
-    }
-    __syncthreads();
-    fft_lds<+1>(x, tw, N, logN);
-    fft_lds<+1>(xt, tw, N, logN);
-    float ep = 0.0f, eq = 0.0f;
-    // p - p* per tap; the gradient source 4 w_p (p - p*) X / (N Z_p) is
-    // written bit-reversed into xt (each tap k is read and written by the
-    // same thread; the barrier below separates it from the FFT)
-    float2 gsrc[kLossMaxPerThread];
-#pragma unroll
-    for (int u = 0; u < kLossMaxPerThread; ++u) {
-      const int k = threadIdx.x + u * kLossBlock;
-      if (k < N) {
-        float p = cabs2(x[k]) * invN;
-        float pt = cabs2(xt[k]) * invN;
-        float d = p - pt;
-        ep += d * d;
-        eq += pt * pt;
-        gsrc[u] = cscale(x[k], gp * d);
-      }
-    }
-    double s1 = block_sum_f64((double)ec, red);
-    double s2 = block_sum_f64((double)et, red);
-    double s3 = block_sum_f64((double)ep, red);
-    double s4 = block_sum_f64((double)eq, red);
-    if (threadIdx.x == 0) {
-      row_out[row * 4 + 0] = s1;
-      row_out[row * 4 + 1] = s2;
-      row_out[row * 4 + 2] = s3;
-      row_out[row * 4 + 3] = s4;
-    }
-    if (dLdH) {
-#pragma unroll
-      for (int u = 0; u < kLossMaxPerThread; ++u) {
-        const int k = threadIdx.x + u * kLossBlock;
-        if (k < N) x[bitrev(k, logN)] = gsrc[u];
-      }
-      __syncthreads();
-      fft_lds<-1>(x, tw, N, logN);
-      float2* out = dLdH + row * N;
-#pragma unroll
-      for (int u = 0; u < kLossMaxPerThread; ++u) {
-        const int n = threadIdx.x + u * kLossBlock;
-        if (n < N) out[n] = cadd(cscale(diff[u], gc), x[n]);
-      }
-    }
-    __syncthreads();
-  }
-}
-
-// ----------------------------------------------------------- one-wave rows
-// For N <= 1024 one wave owns a row: the H and H* rows are read straight
-// into the first FFT pass, the last inverse pass leaves the taps in
-// dL/dH in the row's natural order, next to H - H* kept from the load.  The
-// Stockham passes ping-pong between two LDS row buffers.  With PT the target
-// PDP comes precomputed (p_tgt from the target statistics) instead of from a
-// transform of H*.
-constexpr int kWaveMaxLogN = 10;
+// ------------------------------------------------------- register-FFT rows
+// T = fft_threads(LOGN) threads own a row: one wave up to N = 1024, N/16
+// threads (one radix-16 butterfly each per pass) beyond.  The H and H* rows
+// are read straight into the first FFT pass, the last inverse pass leaves
+// the taps in dL/dH in the row's natural order, next to H - H* kept from the
+// load.  The Stockham passes ping-pong between two LDS row buffers.  With PT
+// the target PDP comes precomputed (p_tgt from the target statistics)
+// instead of from a transform of H*.
 
 template <int LOGN, bool PT>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(fft_threads(LOGN))
     cfr_loss_wave_kernel(const float2* H, const float2* __restrict__ Ht,
                          const float* __restrict__ Pt, int64_t n_rows, const double* Z,
                          float w_coh, float w_pdp, double* row_out, float2* dLdH) {
   constexpr int N = 1 << LOGN;
   constexpr int NP = fft_npass(LOGN);
   constexpr int RA = fft_radix(LOGN, 0), RZ = fft_radix(LOGN, NP - 1);
-  constexpr int JA = fft_bpl(N, RA), JZ = fft_bpl(N, RZ);
+  constexpr int T = fft_threads(LOGN);
+  constexpr int JA = fft_bpl(N, RA, T), JZ = fft_bpl(N, RZ, T);
   constexpr int BA = N / RA, BZ = N / RZ;
   __shared__ float2 b0[fft_lds_len(N)], b1[fft_lds_len(N)];
+  __shared__ double red[T / 64];
   const float invN = 1.0f / (float)N;
   float gc = 0.0f, gp = 0.0f;
   if (dLdH) {
@@ -188,21 +64,21 @@ __global__ void __launch_bounds__(64)
       const float* ps = Pt + row * N;
 #pragma unroll
       for (int i = 0; i < JZ; ++i) {
-        const int j = lane + 64 * i;
+        const int j = lane + T * i;
 #pragma unroll
         for (int r = 0; r < RZ; ++r)
-          pt[i][r] = (BZ % 64 == 0 || j < BZ) ? ps[j + r * BZ] : 0.0f;
+          pt[i][r] = (BZ % T == 0 || j < BZ) ? ps[j + r * BZ] : 0.0f;
       }
     } else {
       float2 vt[JA][RA], xt[JZ][RZ];
 #pragma unroll
       for (int i = 0; i < JA; ++i) {
-        const int j = lane + 64 * i;
+        const int j = lane + T * i;
 #pragma unroll
         for (int r = 0; r < RA; ++r)
-          vt[i][r] = (BA % 64 == 0 || j < BA) ? ts[j + r * BA] : make_float2(0.0f, 0.0f);
+          vt[i][r] = (BA % T == 0 || j < BA) ? ts[j + r * BA] : make_float2(0.0f, 0.0f);
       }
-      fft_full<LOGN, +1, +1>(vt, xt, b0, b1, lane);
+      fft_full<LOGN, +1, +1, BlockSync, T>(vt, xt, b0, b1, lane);
 #pragma unroll
       for (int i = 0; i < JZ; ++i) {
 #pragma unroll
@@ -212,11 +88,11 @@ __global__ void __launch_bounds__(64)
     float2 vh[JA][RA], diff[JA][RA];
 #pragma unroll
     for (int i = 0; i < JA; ++i) {
-      const int j = lane + 64 * i;
+      const int j = lane + T * i;
 #pragma unroll
       for (int r = 0; r < RA; ++r) {
-        const float2 h = (BA % 64 == 0 || j < BA) ? hs[j + r * BA] : make_float2(0.0f, 0.0f);
-        const float2 t = (BA % 64 == 0 || j < BA) ? ts[j + r * BA] : make_float2(0.0f, 0.0f);
+        const float2 h = (BA % T == 0 || j < BA) ? hs[j + r * BA] : make_float2(0.0f, 0.0f);
+        const float2 t = (BA % T == 0 || j < BA) ? ts[j + r * BA] : make_float2(0.0f, 0.0f);
         vh[i][r] = h;
         diff[i][r] = csub(h, t);
         ec += cabs2(diff[i][r]);
@@ -224,12 +100,12 @@ __global__ void __launch_bounds__(64)
       }
     }
     float2 xh[JZ][RZ];
-    fft_full<LOGN, +1, +1>(vh, xh, b0, b1, lane);
+    fft_full<LOGN, +1, +1, BlockSync, T>(vh, xh, b0, b1, lane);
     float ep = 0.0f, eq = 0.0f;
 #pragma unroll
     for (int i = 0; i < JZ; ++i) {
-      const int j = lane + 64 * i;
-      if (BZ % 64 == 0 || j < BZ) {
+      const int j = lane + T * i;
+      if (BZ % T == 0 || j < BZ) {
 #pragma unroll
         for (int r = 0; r < RZ; ++r) {
           const float p = cabs2(xh[i][r]) * invN;
@@ -240,10 +116,10 @@ __global__ void __launch_bounds__(64)
         }
       }
     }
-    double s1 = wave_sum_f64((double)ec);
-    double s2 = wave_sum_f64((double)et);
-    double s3 = wave_sum_f64((double)ep);
-    double s4 = wave_sum_f64((double)eq);
+    double s1 = group_sum_f64<T>((double)ec, red);
+    double s2 = group_sum_f64<T>((double)et, red);
+    double s3 = group_sum_f64<T>((double)ep, red);
+    double s4 = group_sum_f64<T>((double)eq, red);
     if (lane == 0) {
       row_out[row * 4 + 0] = s1;
       row_out[row * 4 + 1] = s2;
@@ -252,12 +128,12 @@ __global__ void __launch_bounds__(64)
     }
     if (dLdH) {
       float2 G[JA][RA];
-      fft_full<LOGN, -1, -1>(xh, G, b0, b1, lane);
+      fft_full<LOGN, -1, -1, BlockSync, T>(xh, G, b0, b1, lane);
       float2* out = dLdH + row * N;
 #pragma unroll
       for (int i = 0; i < JA; ++i) {
-        const int j = lane + 64 * i;
-        if (BA % 64 == 0 || j < BA) {
+        const int j = lane + T * i;
+        if (BA % T == 0 || j < BA) {
 #pragma unroll
           for (int r = 0; r < RA; ++r) out[j + r * BA] = cadd(cscale(diff[i][r], gc), G[i][r]);
         }
@@ -269,15 +145,17 @@ __global__ void __launch_bounds__(64)
 // Target statistics per row {sum |H*|^2, sum (p*)^2}; with Pt also the
 // target PDP p* (natural tap order) for later loss calls.
 template <int LOGN>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(fft_threads(LOGN))
     target_stats_wave_kernel(const float2* __restrict__ Ht, int64_t n_rows, double* row_out,
                              float* Pt) {
   constexpr int N = 1 << LOGN;
   constexpr int NP = fft_npass(LOGN);
   constexpr int RA = fft_radix(LOGN, 0), RZ = fft_radix(LOGN, NP - 1);
-  constexpr int JA = fft_bpl(N, RA), JZ = fft_bpl(N, RZ);
+  constexpr int T = fft_threads(LOGN);
+  constexpr int JA = fft_bpl(N, RA, T), JZ = fft_bpl(N, RZ, T);
   constexpr int BA = N / RA, BZ = N / RZ;
   __shared__ float2 b0[fft_lds_len(N)], b1[fft_lds_len(N)];
+  __shared__ double red[T / 64];
   const int lane = threadIdx.x;
   const float invN = 1.0f / (float)N;
   for (int64_t row = blockIdx.x; row < n_rows; row += gridDim.x) {
@@ -286,8 +164,8 @@ __global__ void __launch_bounds__(64)
     float et = 0.0f;
 #pragma unroll
     for (int i = 0; i < JA; ++i) {
-      const int j = lane + 64 * i;
-      if (BA % 64 == 0 || j < BA) {
+      const int j = lane + T * i;
+      if (BA % T == 0 || j < BA) {
 #pragma unroll
         for (int r = 0; r < RA; ++r) {
           vt[i][r] = ts[j + r * BA];
@@ -296,12 +174,12 @@ __global__ void __launch_bounds__(64)
       }
     }
     float2 xt[JZ][RZ];
-    fft_full<LOGN, +1, +1>(vt, xt, b0, b1, lane);
+    fft_full<LOGN, +1, +1, BlockSync, T>(vt, xt, b0, b1, lane);
     float eq = 0.0f;
 #pragma unroll
     for (int i = 0; i < JZ; ++i) {
-      const int j = lane + 64 * i;
-      if (BZ % 64 == 0 || j < BZ) {
+      const int j = lane + T * i;
+      if (BZ % T == 0 || j < BZ) {
 #pragma unroll
         for (int r = 0; r < RZ; ++r) {
           const float pt = cabs2(xt[i][r]) * invN;
@@ -310,8 +188,8 @@ __global__ void __launch_bounds__(64)
         }
       }
     }
-    double se = wave_sum_f64((double)et);
-    double sq = wave_sum_f64((double)eq);
+    double se = group_sum_f64<T>((double)et, red);
+    double sq = group_sum_f64<T>((double)eq, red);
     if (lane == 0) {
       row_out[row * 2 + 0] = se;
       row_out[row * 2 + 1] = sq;
@@ -415,11 +293,6 @@ size_t ws_cfr_loss(const rtc_radio* r, int32_t n_links) {
 
 size_t ws_target_stats(const rtc_radio* r, int32_t n_links) { return ws_cfr_loss(r, n_links); }
 
-static unsigned row_grid(int64_t R) {
-  int64_t g = R < 8192 ? R : 8192;
-  return (unsigned)(g > 0 ? g : 1);
-}
-
 static unsigned wave_grid(int64_t R) {
   int64_t g = R < 40960 ? R : 40960;
   return (unsigned)(g > 0 ? g : 1);
@@ -427,47 +300,40 @@ static unsigned wave_grid(int64_t R) {
 
 static void launch_target_stats(int logN, const float2* Ht, int64_t R, double* rows, float* Pt,
                                 hipStream_t s) {
-  int N = 1 << logN;
   switch (logN) {
 #define RTC_TS(L)                                                                            \
   case L:                                                                                    \
-    hipLaunchKernelGGL(target_stats_wave_kernel<L>, dim3(wave_grid(R)), dim3(64), 0, s, Ht, \
-                       R, rows, Pt);                                                         \
+    hipLaunchKernelGGL(target_stats_wave_kernel<L>, dim3(wave_grid(R)),                      \
+                       dim3(fft_threads(L)), 0, s, Ht, R, rows, Pt);                         \
     return;
     RTC_TS(1) RTC_TS(2) RTC_TS(3) RTC_TS(4) RTC_TS(5) RTC_TS(6) RTC_TS(7) RTC_TS(8) RTC_TS(9)
-    RTC_TS(10)
+    RTC_TS(10) RTC_TS(11) RTC_TS(12)
 #undef RTC_TS
-    default: {
-      size_t shm = (size_t)(N / 2 + N) * sizeof(float2);
-      hipLaunchKernelGGL(target_stats_kernel, dim3(row_grid(R)), dim3(kLossBlock), shm, s, Ht, R,
-                         N, logN, rows, Pt);
-    }
+    default:
+      return;  // n_sc is checked by the entry points
   }
 }
 
-// The transform-per-row kernel for N > 1024 recomputes p* from H* (Pt unused).
 static void launch_loss(int logN, const float2* H, const float2* Ht, const float* Pt, int64_t R,
                         const double* Z, float w_coh, float w_pdp, double* rows, float2* dLdH,
                         hipStream_t s) {
-  int N = 1 << logN;
   switch (logN) {
-#define RTC_LW(L)                                                                               \
-  case L:                                                                                       \
-    if (Pt)                                                                                     \
-      hipLaunchKernelGGL((cfr_loss_wave_kernel<L, true>), dim3(wave_grid(R)), dim3(64), 0, s, H, \
-                         Ht, Pt, R, Z, w_coh, w_pdp, rows, dLdH);                               \
-    else                                                                                        \
-      hipLaunchKernelGGL((cfr_loss_wave_kernel<L, false>), dim3(wave_grid(R)), dim3(64), 0, s,   \
-                         H, Ht, Pt, R, Z, w_coh, w_pdp, rows, dLdH);                            \
+#define RTC_LW(L)                                                                             \
+  case L:                                                                                     \
+    if (Pt)                                                                                   \
+      hipLaunchKernelGGL((cfr_loss_wave_kernel<L, true>), dim3(wave_grid(R)),                 \
+                         dim3(fft_threads(L)), 0, s, H, Ht, Pt, R, Z, w_coh, w_pdp, rows,     \
+                         dLdH);                                                               \
+    else                                                                                      \
+      hipLaunchKernelGGL((cfr_loss_wave_kernel<L, false>), dim3(wave_grid(R)),                \
+                         dim3(fft_threads(L)), 0, s, H, Ht, Pt, R, Z, w_coh, w_pdp, rows,     \
+                         dLdH);                                                               \
     return;
     RTC_LW(1) RTC_LW(2) RTC_LW(3) RTC_LW(4) RTC_LW(5) RTC_LW(6) RTC_LW(7) RTC_LW(8) RTC_LW(9)
-    RTC_LW(10)
+    RTC_LW(10) RTC_LW(11) RTC_LW(12)
 #undef RTC_LW
-    default: {
-      size_t shm = (size_t)(N / 2 + 2 * N) * sizeof(float2);
-      hipLaunchKernelGGL(cfr_loss_kernel, dim3(row_grid(R)), dim3(kLossBlock), shm, s, H, Ht, R, N,
-                         logN, Z, w_coh, w_pdp, rows, dLdH);
-    }
+    default:
+      return;  // n_sc is checked by the entry points
   }
 }
 

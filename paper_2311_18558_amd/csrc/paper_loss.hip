@@ -24,14 +24,10 @@
 
 #include "api_common.h"
 #include "dev_common.h"
-#include "fft_block.h"
 #include "fft_wave.h"
 
 namespace rtc {
 
-constexpr int kPlBlock = 256;
-constexpr int kPlMaxPerThread = kMaxFFT / kPlBlock;  // 16
-constexpr int kPlWaveMaxLogN = 10;
 
 struct PaperLossArgs {
   const double* tgt;    // [R][2] measured {P, tau_RMS}; loss only
@@ -81,18 +77,21 @@ RTC_DEV RowGrad row_loss(const PaperLossArgs& A, int64_t row, double alpha, doub
   return RowGrad{(float)(2.0 * c0 / N), (float)(2.0 * c1 / N)};
 }
 
-// ----------------------------------------------------------- one-wave rows
-// N <= 1024: one wave owns a row; the row is read straight into the first
-// FFT pass and the gradient's transform leaves dL/dH in natural order.
+// ------------------------------------------------------- register-FFT rows
+// T = fft_threads(LOGN) threads own a row (one wave up to N = 1024, N/16
+// beyond); the row is read straight into the first FFT pass and the
+// gradient's transform leaves dL/dH in natural order.
 template <int LOGN, bool LOSS>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(fft_threads(LOGN))
     paper_loss_wave_kernel(const float2* H, int64_t n_rows, PaperLossArgs A) {
   constexpr int N = 1 << LOGN;
   constexpr int NP = fft_npass(LOGN);
   constexpr int RA = fft_radix(LOGN, 0), RZ = fft_radix(LOGN, NP - 1);
-  constexpr int JA = fft_bpl(N, RA), JZ = fft_bpl(N, RZ);
+  constexpr int T = fft_threads(LOGN);
+  constexpr int JA = fft_bpl(N, RA, T), JZ = fft_bpl(N, RZ, T);
   constexpr int BA = N / RA, BZ = N / RZ;
   __shared__ float2 b0[fft_lds_len(N)], b1[fft_lds_len(N)];
+  __shared__ double red[T / 64];
   const float invN = 1.0f / (float)N;
   const double alpha = LOSS ? A.alpha[0] : 1.0;
   for (int64_t row = blockIdx.x; row < n_rows; row += gridDim.x) {
@@ -102,18 +101,18 @@ __global__ void __launch_bounds__(64)
     float2 vh[JA][RA];
 #pragma unroll
     for (int i = 0; i < JA; ++i) {
-      const int j = lane + 64 * i;
+      const int j = lane + T * i;
 #pragma unroll
       for (int r = 0; r < RA; ++r)
-        vh[i][r] = (BA % 64 == 0 || j < BA) ? hs[j + r * BA] : make_float2(0.0f, 0.0f);
+        vh[i][r] = (BA % T == 0 || j < BA) ? hs[j + r * BA] : make_float2(0.0f, 0.0f);
     }
     float2 xh[JZ][RZ];
-    fft_full<LOGN, +1, +1>(vh, xh, b0, b1, lane);
+    fft_full<LOGN, +1, +1, BlockSync, T>(vh, xh, b0, b1, lane);
     float s0 = 0.0f, s1 = 0.0f;
 #pragma unroll
     for (int i = 0; i < JZ; ++i) {
-      const int j = lane + 64 * i;
-      if (BZ % 64 == 0 || j < BZ) {
+      const int j = lane + T * i;
+      if (BZ % T == 0 || j < BZ) {
 #pragma unroll
         for (int r = 0; r < RZ; ++r) {
           const float p = cabs2(xh[i][r]) * invN;
@@ -122,15 +121,15 @@ __global__ void __launch_bounds__(64)
         }
       }
     }
-    const double S0 = wave_sum_f64((double)s0);
-    const double S1 = wave_sum_f64((double)s1);
+    const double S0 = group_sum_f64<T>((double)s0, red);
+    const double S1 = group_sum_f64<T>((double)s1, red);
     const double tbar = S0 > 0.0 ? S1 / S0 : 0.0;
     const float tb = (float)tbar;
     float s2 = 0.0f;
 #pragma unroll
     for (int i = 0; i < JZ; ++i) {
-      const int j = lane + 64 * i;
-      if (BZ % 64 == 0 || j < BZ) {
+      const int j = lane + T * i;
+      if (BZ % T == 0 || j < BZ) {
 #pragma unroll
         for (int r = 0; r < RZ; ++r) {
           const float d = centred_tap(j + r * BZ, N) - tb;
@@ -138,7 +137,7 @@ __global__ void __launch_bounds__(64)
         }
       }
     }
-    const double S2 = wave_sum_f64((double)s2);
+    const double S2 = group_sum_f64<T>((double)s2, red);
     const double v = S0 > 0.0 ? S2 / S0 : 0.0;
     const double tau_hat = sqrt(v) * A.inv_W;
     if (A.pred && lane == 0) {
@@ -151,7 +150,7 @@ __global__ void __launch_bounds__(64)
         const float vf = (float)v;
 #pragma unroll
         for (int i = 0; i < JZ; ++i) {
-          const int j = lane + 64 * i;
+          const int j = lane + T * i;
 #pragma unroll
           for (int r = 0; r < RZ; ++r) {
             const float d = centred_tap(j + r * BZ, N) - tb;
@@ -159,94 +158,18 @@ __global__ void __launch_bounds__(64)
           }
         }
         float2 G[JA][RA];
-        fft_full<LOGN, -1, -1>(xh, G, b0, b1, lane);
+        fft_full<LOGN, -1, -1, BlockSync, T>(xh, G, b0, b1, lane);
         float2* out = A.dLdH + row * N;
 #pragma unroll
         for (int i = 0; i < JA; ++i) {
-          const int j = lane + 64 * i;
-          if (BA % 64 == 0 || j < BA) {
+          const int j = lane + T * i;
+          if (BA % T == 0 || j < BA) {
 #pragma unroll
             for (int r = 0; r < RA; ++r) out[j + r * BA] = G[i][r];
           }
         }
       }
     }
-  }
-}
-
-// ------------------------------------------------------ workgroup per row
-// N > 1024: a workgroup transforms one row at a time in LDS.
-template <bool LOSS>
-__global__ void __launch_bounds__(kPlBlock)
-    paper_loss_block_kernel(const float2* H, int64_t n_rows, int N, int logN, PaperLossArgs A) {
-  extern __shared__ float2 sm[];
-  float2* tw = sm;
-  float2* x = sm + N / 2;
-  __shared__ double red[kPlBlock / 64];
-  __shared__ double bc[3];
-  make_twiddles(tw, N);
-  const float invN = 1.0f / (float)N;
-  const double alpha = LOSS ? A.alpha[0] : 1.0;
-  for (int64_t row = blockIdx.x; row < n_rows; row += gridDim.x) {
-    const float2* hs = H + row * N;
-    for (int n = threadIdx.x; n < N; n += blockDim.x) x[bitrev(n, logN)] = hs[n];
-    __syncthreads();
-    fft_lds<+1>(x, tw, N, logN);
-    float s0 = 0.0f, s1 = 0.0f;
-    for (int k = threadIdx.x; k < N; k += blockDim.x) {
-      const float p = cabs2(x[k]) * invN;
-      s0 += p;
-      s1 = fmaf(centred_tap(k, N), p, s1);
-    }
-    const double S0r = block_sum_f64((double)s0, red);
-    const double S1r = block_sum_f64((double)s1, red);
-    if (threadIdx.x == 0) {
-      bc[0] = S0r;
-      bc[1] = S0r > 0.0 ? S1r / S0r : 0.0;
-    }
-    __syncthreads();
-    const double S0 = bc[0];
-    const float tb = (float)bc[1];
-    float s2 = 0.0f;
-    for (int k = threadIdx.x; k < N; k += blockDim.x) {
-      const float d = centred_tap(k, N) - tb;
-      s2 = fmaf(d * d, cabs2(x[k]) * invN, s2);
-    }
-    const double S2r = block_sum_f64((double)s2, red);
-    if (threadIdx.x == 0) bc[2] = S0 > 0.0 ? S2r / S0 : 0.0;
-    __syncthreads();
-    const double v = bc[2];
-    const double tau_hat = sqrt(v) * A.inv_W;
-    if (A.pred && threadIdx.x == 0) {
-      A.pred[row * 2 + 0] = S0;
-      A.pred[row * 2 + 1] = tau_hat;
-    }
-    if constexpr (LOSS) {
-      const RowGrad c = row_loss(A, row, alpha, S0, v, tau_hat, N, threadIdx.x == 0);
-      if (A.dLdH) {
-        const float vf = (float)v;
-        float2 g[kPlMaxPerThread];
-#pragma unroll
-        for (int u = 0; u < kPlMaxPerThread; ++u) {
-          const int k = threadIdx.x + u * kPlBlock;
-          if (k < N) {
-            const float d = centred_tap(k, N) - tb;
-            g[u] = cscale(x[k], fmaf(c.a1, fmaf(d, d, -vf), c.a0));
-          }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int u = 0; u < kPlMaxPerThread; ++u) {
-          const int k = threadIdx.x + u * kPlBlock;
-          if (k < N) x[bitrev(k, logN)] = g[u];
-        }
-        __syncthreads();
-        fft_lds<-1>(x, tw, N, logN);
-        float2* out = A.dLdH + row * N;
-        for (int n = threadIdx.x; n < N; n += blockDim.x) out[n] = x[n];
-      }
-    }
-    __syncthreads();
   }
 }
 
@@ -323,32 +246,22 @@ static unsigned pl_wave_grid(int64_t R) {
   return (unsigned)(g > 0 ? g : 1);
 }
 
-static unsigned pl_block_grid(int64_t R) {
-  int64_t g = R < 8192 ? R : 8192;
-  return (unsigned)(g > 0 ? g : 1);
-}
-
 template <bool LOSS>
 static void launch_paper_rows(int logN, const float2* H, int64_t R, const PaperLossArgs& A,
                               hipStream_t s) {
   switch (logN) {
 #define RTC_PL(L)                                                                            \
   case L:                                                                                    \
-    hipLaunchKernelGGL((paper_loss_wave_kernel<L, LOSS>), dim3(pl_wave_grid(R)), dim3(64), 0, \
-                       s, H, R, A);                                                          \
+    hipLaunchKernelGGL((paper_loss_wave_kernel<L, LOSS>), dim3(pl_wave_grid(R)),             \
+                       dim3(fft_threads(L)), 0, s, H, R, A);                                 \
     return;
     RTC_PL(1) RTC_PL(2) RTC_PL(3) RTC_PL(4) RTC_PL(5) RTC_PL(6) RTC_PL(7) RTC_PL(8) RTC_PL(9)
-    RTC_PL(10)
+    RTC_PL(10) RTC_PL(11) RTC_PL(12)
 #undef RTC_PL
-    default: {
-      const int N = 1 << logN;
-      const size_t shm = (size_t)(N / 2 + N) * sizeof(float2);
-      hipLaunchKernelGGL((paper_loss_block_kernel<LOSS>), dim3(pl_block_grid(R)), dim3(kPlBlock),
-                         shm, s, H, R, N, logN, A);
-    }
+    default:
+      return;  // n_sc is checked by the entry points
   }
 }
-static_assert(kPlWaveMaxLogN == 10, "wave kernels are instantiated up to N = 1024");
 
 // Workspace (doubles): rows[R*2] | reduction scratch | sums[2]
 size_t ws_paper_loss(const rtc_radio* r, int32_t n_links) {
