@@ -18,6 +18,10 @@ Prints ONE JSON line (rank 0):
                  torch's host threads and on one
   paper_loss_step  the same step with the paper's own loss (SMAPE of RMS
                  delay spread and gain, moving-average measurement scale)
+  large_scene    the streamed step on the urban block (4 Tx x 2,048 outdoor
+                 Rx, real specular + diffuse paths, ~2,000 per link, 4,096
+                 subcarriers, neural materials, the paper's loss); --config5
+                 runs it at full size, 4 Tx x 65,536 Rx
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
        python bench.py --copy-probe ...      also runs a 2 GiB device copy
                                              first (HBM counter calibration)
@@ -298,36 +302,39 @@ def recovery_bench(steps=200, warmup=5):
     return out
 
 
-def config5_bench(steps=1, warmup=1, copies=128):
-    """The large-scene configuration at full size, streamed in Rx batches:
-    4 Tx x 65,536 Rx = 262,144 links of ~2,356 paths (specular up to fifth
-    order + single-bounce diffuse), 32 elements, 4,096 subcarriers over
-    100 MHz, neural materials, the paper's loss.  Links are 128 device copies
-    of the 2,048 generated diffuse-workload links (all resident, each copy
-    one batch); targets from hidden per-id materials."""
+def large_scene_bench(n_rx=2048, batch=2048, steps=2, warmup=1):
+    """The large-scene configuration, streamed: the urban block (~100,000
+    triangles, 16 material classes), 4 Tx with 32-element ULAs, n_rx outdoor
+    Rx at 1.5 m per Tx, specular paths up to fifth order plus single-bounce
+    diffuse (real paths, generated batch by batch on the host and kept
+    resident on the device), 4,096 subcarriers over 100 MHz, neural
+    materials, the paper's loss; one batch per `batch` Rx of one Tx.  The
+    default is the bounded sample of 4 x 2,048 links; n_rx=65,536 is the
+    full configuration (262,144 links)."""
     from paper_2311_18558_amd import lib as rl
     from paper_2311_18558_amd.calibrate import mlp_out_bias
     from paper_2311_18558_amd.stream import StreamedCalibration
     from synth import workloads
     from synth.params import mlp_init
     t0 = time.time()
-    w = workloads.diffuse()
-    st, radio = w.store, w.radio
-    base = rl.DevicePaths(st)
-    batches = [base] + [rl.replicate_paths(base) for _ in range(copies - 1)]
-    torch.cuda.synchronize()
+    w = workloads.urban(n_rx=n_rx, batch=batch, lazy=True)
+    radio = w.radio
+    nb = w.meta["n_batches"]
+    batches = []
+    for i in range(nb):
+        batches.append(rl.DevicePaths(w.meta["batch"](i)))
+        if (i + 1) % 16 == 0 or i + 1 == nb:
+            log(f"large scene: {i + 1}/{nb} batches resident, "
+                f"{torch.cuda.memory_allocated() / 1e9:.1f} GB, {time.time() - t0:.0f}s")
+    gen_s = time.time() - t0
     L = sum(b.n_links for b in batches)
     P = sum(b.n_paths for b in batches)
-    log(f"config5: {L} links, {P} paths resident in {len(batches)} batches, "
-        f"{torch.cuda.memory_allocated() / 1e9:.1f} GB, {time.time() - t0:.1f}s")
-    lo = st.pts.reshape(3, -1).min(1) - 0.1
-    hi = st.pts.reshape(3, -1).max(1) + 0.1
     cal = StreamedCalibration(batches, radio, "neural",
                               mlp_params0=mlp_init(np.random.default_rng(5), mlp_out_bias()),
-                              aabb=(lo, hi), g0=w.g)
+                              aabb=w.aabb, g0=w.g)
     cal.set_targets(w.raw)
     torch.cuda.synchronize()
-    log(f"config5: targets ready, {torch.cuda.memory_allocated() / 1e9:.1f} GB allocated")
+    log(f"large scene: targets ready, {torch.cuda.memory_allocated() / 1e9:.1f} GB allocated")
     for _ in range(warmup):
         cal.step()
     torch.cuda.synchronize()
@@ -339,17 +346,25 @@ def config5_bench(steps=1, warmup=1, copies=128):
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
+    # stage split from one more step with events between the stages
+    events = {}
+    cal.step(events=events)
+    torch.cuda.synchronize()
+    stages = {k: round(sum(a.elapsed_time(b) for a, b in v), 2) for k, v in events.items()}
     M, N = radio.n_elem, radio.n_sc
-    out = {"workload": "large-scene configuration: 262,144 links (4 Tx x 65,536 Rx as 128 copies "
-                       "of 2,048 generated links), specular up to 5th order + single-bounce "
-                       "diffuse, 32-element ULA, 4,096 subcarriers over 100 MHz, neural "
-                       "materials, paper loss, streamed in 2,048-link batches",
-           "links": L, "paths": P, "taps": L * M * N, "steps": steps,
-           "ms_per_step": round(ms, 1), "taps_per_s": round(L * M * N / (ms * 1e-3), 1),
+    out = {"workload": f"large scene: urban block 400 x 400 m ({w.meta['tris']:,} triangles, "
+                       f"{w.meta['n_mat']} material classes), 4 Tx x {n_rx:,} outdoor Rx at 1.5 m, "
+                       "real specular paths up to 5th order + single-bounce diffuse, 32-element "
+                       "ULA, 4,096 subcarriers over 100 MHz, neural materials, paper loss, "
+                       f"streamed in {batch:,}-Rx batches",
+           "links": L, "paths": P, "paths_per_link": round(P / L, 1), "batches": nb,
+           "taps": L * M * N, "steps": steps, "ms_per_step": round(ms, 1),
+           "taps_per_s": round(L * M * N / (ms * 1e-3), 1),
+           "stage_ms": stages, "host_generation_s": round(gen_s, 1),
            "peak_hbm_gb": round(torch.cuda.max_memory_allocated() / 1e9, 1),
            "loss": loss.item()}
-    log(f"config5: {out}")
-    del cal, batches, base
+    log(f"large scene: {out}")
+    del cal, batches
     torch.cuda.empty_cache()
     return out
 
@@ -526,8 +541,10 @@ def main():
                     help="skip the diffuse-scattering workload line")
     ap.add_argument("--no-recovery", action="store_true",
                     help="skip the synthetic-recovery step-rate line")
+    ap.add_argument("--no-large-scene", action="store_true",
+                    help="skip the bounded large-scene line (4 Tx x 2,048 urban Rx)")
     ap.add_argument("--config5", action="store_true",
-                    help="also run the full-size large-scene configuration, streamed (~2 min)")
+                    help="run the large-scene line at full size, 4 Tx x 65,536 Rx (~5 min)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="start with a 2 GiB device copy (counter calibration)")
     ap.add_argument("--traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -662,7 +679,9 @@ def main():
     if not args.no_recovery:
         out["recovery"] = recovery_bench()
     if args.config5:
-        out["config5"] = config5_bench()
+        out["large_scene"] = large_scene_bench(n_rx=65536, steps=1)
+    elif not args.no_large_scene:
+        out["large_scene"] = large_scene_bench()
     if not args.no_calib:
         out["calib"] = calib_compare(w, args.calib_steps)
     if not args.no_cpu_baseline:

@@ -101,33 +101,64 @@ class StreamedCalibration:
 
     def batch_step(self, i, events=None):
         """Forward, weighted paper loss and reverse pass of batch i; the
-        parameter gradient is added to self.grad."""
+        parameter gradient is added to self.grad.  events: a dict that
+        collects (start, end) CUDA events per stage, or None."""
         b = self.batches[i]
         M, N = self.radio.n_elem, self.radio.n_sc
         H = self.H[:b.n_links * M * N]
         w = float(b.n_links * M) / self.rows_total
+        mark = _Marks(events)
+        mark("materials")
         mats, Q = self._materials(i)
+        mark("trace_fields")
         lib.trace_fields(self.radio, b, mats, self.a, self.psi)
+        mark("cfr")
         lib.cfr(self.radio, b, self.a, self.psi, self.g, H)
+        mark("paper_loss")
         lib.paper_loss(self.radio, b.n_links, H, self.targets[i], self.alpha, self.loss_rows[i],
                        H, self.ws, update_alpha=False, w_tau=w, w_gain=w)
+        mark("cfr_adjoint")
         lib.cfr_adjoint(self.radio, b, self.a, self.psi, self.g, H, self.dLda, None, self.ws)
+        mark("trace_fields_adjoint")
         if self.mode == "per_id":
             lib.trace_fields_adjoint(self.radio, b, mats, self.dLda, self.grad_b, None,
                                      self.ws_tr)
         else:
             dint = self.dint[:3 * Q].view(3, Q)
             lib.trace_fields_adjoint(self.radio, b, mats, self.dLda, None, dint, None)
+            mark("materials_backward")
             lib.mlp_backward(self.net, Q, dint, self.saved, self.grad_b, self.mlp_ws)
+        mark("axpy")
         lib.axpy(self.grad, self.grad_b)
+        mark(None)
 
-    def step(self, update=True):
+    def step(self, update=True, events=None):
         """One optimiser step over every batch; returns the loss L (device
         scalar: the sum of the batches' weighted losses)."""
         self.grad.zero_()
         for i in range(len(self.batches)):
-            self.batch_step(i)
+            self.batch_step(i, events)
         if update:
             lib.adam_step_dev(self.params, self.grad, self.m, self.v, self.step_dev, True,
                               lr=self.lr)
         return self.loss_rows[:, 0].sum()
+
+
+class _Marks:
+    """Stage timing on the current stream: mark(name) closes the open stage
+    and opens `name` (None closes only); events[name] collects (start, end)
+    pairs."""
+
+    def __init__(self, events):
+        self.events = events
+        self.open = None
+
+    def __call__(self, name):
+        if self.events is None:
+            return
+        e = torch.cuda.Event(enable_timing=True)
+        e.record()
+        if self.open is not None:
+            self.events.setdefault(self.open[0], []).append((self.open[1], e))
+        self.open = None if name is None else (name, e)
+

@@ -172,6 +172,16 @@ def add_diffuse(store, tx, samples, visible_fn, max_links_chunk=64):
         if len(idx):
             idx = idx[visible_fn(pts[idx], rx)]
         per_link.append(idx)
+    return append_diffuse(store, tx_all, samples, per_link)
+
+
+def append_diffuse(store, tx_all, samples, per_link):
+    """A new store with the single-bounce diffuse paths through samples
+    per_link[l] (sample indices, in order) appended after link l's specular
+    paths; tx_all [L, 3] the links' Tx positions."""
+    pts, nrm, mat, face, dA = samples
+    rx_all = store.rx_pos.astype(np.float64)
+    L = store.n_links
     cnt_d = np.array([len(i) for i in per_link], np.int64)
     cnt_s = store.paths_per_link()
     D = max(int(store.max_depth), 1)

@@ -31,29 +31,36 @@ def _load():
         lib = ctypes.CDLL(LIB)
         d, i, i64, vp = ctypes.c_double, ctypes.c_int, ctypes.c_int64, ctypes.c_void_p
         lib.pf_run.restype = i64
-        lib.pf_run.argtypes = [vp, i, d, d, d, d, d, i, i, i, i, vp, vp, i, i, i64, d, i]
+        lib.pf_run.argtypes = [vp, i, d, d, d, d, d, i, i, i, i, vp, vp, i, i, i64, d, i, d]
         lib.pf_fetch.restype = i
         lib.pf_fetch.argtypes = [i, vp, vp, vp, vp, vp, vp, vp]
         lib.pf_free.restype = None
+        lib.pd_run.restype = i64
+        lib.pd_run.argtypes = [vp, i, d, d, d, d, vp, vp, vp, i, vp, vp, i, i, d]
+        lib.pd_fetch.restype = i
+        lib.pd_fetch.argtypes = [vp, vp]
+        lib.pd_free.restype = None
         _lib = lib
     return _lib
 
 
 def find_store(plan, tx, rx, max_depth=3, n_rays=1 << 18, recv_factor=2.0,
-               n_threads=0) -> PathStore:
+               n_threads=0, cell=1.0) -> PathStore:
     """Specular paths from one Tx to every Rx in a FloorPlan (all walls span
-    floor to ceiling)."""
+    floor to ceiling; plan.height <= 0: open sky above walls taller than any
+    path, one ground reflection at most).  cell: the plan grid's cell size
+    (metres) for ray walks."""
     lib = _load()
     walls = np.ascontiguousarray(plan.wall_segments(), np.float64)
     tx = np.ascontiguousarray(np.asarray(tx, np.float64).reshape(3))
     rx = np.ascontiguousarray(np.asarray(rx, np.float64).reshape(-1, 3))
     n_rx = len(rx)
     fm = int(plan.scene.face_mat[plan.floor_face])
-    cm = int(plan.scene.face_mat[plan.ceil_face])
+    cm = int(plan.scene.face_mat[plan.ceil_face]) if plan.ceil_face >= 0 else 0
     P = lib.pf_run(walls.ctypes.data, len(walls), 0.0, 0.0, plan.width, plan.depth,
                    plan.height, fm, plan.floor_face, cm, plan.ceil_face, tx.ctypes.data,
                    rx.ctypes.data, n_rx, max_depth, int(n_rays), float(recv_factor),
-                   int(n_threads))
+                   int(n_threads), float(cell))
     if P < 0:
         raise RuntimeError(f"pf_run failed ({P})")
     D = max_depth
@@ -80,3 +87,30 @@ def find_store(plan, tx, rx, max_depth=3, n_rays=1 << 18, recv_factor=2.0,
                      rx_pos=rx.astype(np.float32), depth=depth,
                      kind=np.zeros(D * P, np.uint8), pts=pts, nrm=nrm, mat=mat,
                      dA=np.zeros(D * P, np.float32), tau=length / C0, face=face)
+
+
+def visible_samples(plan, tx, rx, pts, nrm, seg, n_threads=0, cell=1.0):
+    """Per Rx, the indices of the surface samples (pts, unit normals nrm,
+    [n, 3]; seg: the wall segment of plan.wall_segments() each lies on, -1
+    for the ground) that both tx and the Rx see from the samples' front side
+    in a 2.5-D plan (walls block by their floor-plan footprint).  Returns a
+    CSR (off int64 [n_rx + 1], idx int32)."""
+    lib = _load()
+    walls = np.ascontiguousarray(plan.wall_segments(), np.float64)
+    tx = np.ascontiguousarray(np.asarray(tx, np.float64).reshape(3))
+    rx = np.ascontiguousarray(np.asarray(rx, np.float64).reshape(-1, 3))
+    pts = np.ascontiguousarray(pts, np.float64)
+    nrm = np.ascontiguousarray(nrm, np.float64)
+    seg = np.ascontiguousarray(seg, np.int32)
+    n = lib.pd_run(walls.ctypes.data, len(walls), 0.0, 0.0, plan.width, plan.depth,
+                   pts.ctypes.data, nrm.ctypes.data, seg.ctypes.data, len(pts), tx.ctypes.data,
+                   rx.ctypes.data, len(rx), int(n_threads), float(cell))
+    if n < 0:
+        raise RuntimeError(f"pd_run failed ({n})")
+    off = np.zeros(len(rx) + 1, np.int64)
+    idx = np.zeros(int(n), np.int32)
+    st = lib.pd_fetch(off.ctypes.data, idx.ctypes.data)
+    lib.pd_free()
+    if st != 0:
+        raise RuntimeError("pd_fetch failed")
+    return off, idx

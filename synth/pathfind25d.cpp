@@ -1,6 +1,8 @@
 // Specular path finder for 2.5-D scenes: vertical, axis-aligned wall faces
 // spanning floor to ceiling, plus one floor plane (z = 0) and one ceiling
-// plane (z = H).  Such a scene's 3-D specular paths are exactly the 2-D
+// plane (z = H), or open sky above the walls (H <= 0: an urban block whose
+// buildings are taller than every path, which then has at most one ground
+// reflection).  Such a scene's 3-D specular paths are exactly the 2-D
 // specular paths of the floor plan (reflections off wall faces), each
 // combined with a sequence of floor/ceiling reflections obtained by
 // unfolding the vertical coordinate.
@@ -14,8 +16,14 @@
 // reflection point must fall inside its face, and every leg must be free of
 // wall faces.
 //
+// Single-bounce diffuse paths (pd_run): per Rx, the surface samples seen
+// from both the Tx and the Rx -- each on the front side of the sample's
+// surface, the plan segment between them free of wall faces other than the
+// sample's own.
+//
 // C ABI for ctypes: pf_run(...) computes and keeps the result, pf_count()
-// and pf_fetch(...) copy it out, pf_free() releases it.
+// and pf_fetch(...) copy it out, pf_free() releases it; pd_run / pd_fetch /
+// pd_free likewise for the diffuse samples.
 #include <omp.h>
 
 #include <algorithm>
@@ -77,6 +85,13 @@ struct Result {
 };
 
 Result* g_result = nullptr;
+
+struct Diffuse {
+  std::vector<int64_t> off;
+  std::vector<int32_t> idx;
+};
+
+Diffuse* g_diffuse = nullptr;
 
 inline double seg_coord_other(const Seg& s, double x, double y) { return s.axis == 0 ? y : x; }
 
@@ -270,15 +285,16 @@ extern "C" {
 int64_t pf_run(const double* walls, int n_seg, double x0, double y0, double x1, double y1,
                double H, int floor_mat, int floor_face, int ceil_mat, int ceil_face,
                const double* tx, const double* rx, int n_rx, int max_depth, int64_t n_rays,
-               double recv_factor, int n_threads) {
+               double recv_factor, int n_threads, double cell) {
   if (max_depth < 0 || max_depth > kMaxWalls) return -1;
   if (n_threads > 0) omp_set_num_threads(n_threads);
+  const bool open_sky = !(H > 0.0);
   std::vector<Seg> segs(n_seg);
   for (int i = 0; i < n_seg; ++i) {
     const double* w = walls + 7 * i;
     segs[i] = Seg{(int)w[0], w[1], w[2], w[3], w[4], (int)w[5], (int)w[6]};
   }
-  Grid g = build_grid(segs, x0, y0, x1, y1, 1.0);
+  Grid g = build_grid(segs, x0, y0, x1, y1, cell > 0.0 ? cell : 1.0);
   // Rx grid (CSR) for the reception test
   const double rcell = 1.0;
   Grid rg;
@@ -409,14 +425,19 @@ int64_t pf_run(const double* walls, int n_seg, double x0, double y0, double x1, 
         S += std::hypot(rxx - ax, rxy - ay);
       }
       // floor/ceiling sequences: kh reflections starting with the floor
-      // (first = 0) or the ceiling (first = 1)
-      for (int kh = 0; kh + k <= max_depth; ++kh) {
-        for (int first = 0; first < (kh == 0 ? 1 : 2); ++first) {
+      // (first = 0) or the ceiling (first = 1); under open sky at most one,
+      // off the ground
+      const int kh_max = open_sky ? std::min(1, max_depth - k) : max_depth - k;
+      for (int kh = 0; kh <= kh_max; ++kh) {
+        for (int first = 0; first < (kh == 0 || open_sky ? 1 : 2); ++first) {
           // unfolded Rx height and the crossed boundaries
           double zi;
           double bnd[8];
           if (kh == 0) {
             zi = rxz;
+          } else if (open_sky) {  // the ground's image of the Rx
+            zi = -rxz;
+            bnd[0] = 0.0;
           } else if (first == 0) {  // down: copies below z = 0
             // copy n (1..kh) spans [-nH, -(n-1)H]
             zi = (kh % 2 == 1) ? -(kh - 1) * H - rxz : -kh * H + rxz;
@@ -456,10 +477,16 @@ int64_t pf_run(const double* walls, int n_seg, double x0, double y0, double x1, 
               qy = ay + f * (by - ay);
             }
             double zu = zt + (zi - zt) * (s / S);
-            // fold the unfolded height back into [0, H]
-            double zf = std::fmod(zu, 2 * H);
-            if (zf < 0) zf += 2 * H;
-            if (zf > H) zf = 2 * H - zf;
+            // fold the unfolded height back into [0, H] (mirror at z = 0
+            // under open sky)
+            double zf;
+            if (open_sky) {
+              zf = std::fabs(zu);
+            } else {
+              zf = std::fmod(zu, 2 * H);
+              if (zf < 0) zf += 2 * H;
+              if (zf > H) zf = 2 * H - zf;
+            }
             if (take_wall) {
               const Seg& sg = segs[seq[a]];
               pr.pts[e][0] = (float)qx;
@@ -472,7 +499,8 @@ int64_t pf_run(const double* walls, int n_seg, double x0, double y0, double x1, 
               pr.face[e] = sg.face;
               ++a;
             } else {
-              bool is_floor = std::fabs(std::fmod(std::fabs(bnd[b]), 2 * H)) < 0.5 * H;
+              bool is_floor =
+                  open_sky || std::fabs(std::fmod(std::fabs(bnd[b]), 2 * H)) < 0.5 * H;
               pr.pts[e][0] = (float)qx;
               pr.pts[e][1] = (float)qy;
               pr.pts[e][2] = (float)(is_floor ? 0.0 : H);
@@ -538,6 +566,70 @@ int pf_fetch(int max_depth, int64_t* link_off, uint8_t* depth, float* pts, float
 void pf_free() {
   delete g_result;
   g_result = nullptr;
+}
+
+// Diffuse samples: points spts [n_s][3] with unit normals snrm [n_s][3] and
+// the wall segment they lie on, sseg [n_s] (-1 for ground samples, which
+// face +z).  For the Tx tx[3] and every Rx rx[n_rx][3], the samples with
+// both end points strictly on their front side and both plan segments free
+// of wall faces (other than the sample's own).  Returns the number of
+// (Rx, sample) pairs; pd_fetch copies the CSR (off [n_rx+1], idx).
+int64_t pd_run(const double* walls, int n_seg, double x0, double y0, double x1, double y1,
+               const double* spts, const double* snrm, const int* sseg, int n_s,
+               const double* tx, const double* rx, int n_rx, int n_threads, double cell) {
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+  std::vector<Seg> segs(n_seg);
+  for (int i = 0; i < n_seg; ++i) {
+    const double* w = walls + 7 * i;
+    segs[i] = Seg{(int)w[0], w[1], w[2], w[3], w[4], (int)w[5], (int)w[6]};
+  }
+  Grid g = build_grid(segs, x0, y0, x1, y1, cell > 0.0 ? cell : 1.0);
+  auto front = [&](int s, const double* e) {
+    const double* p = spts + 3 * s;
+    const double* n = snrm + 3 * s;
+    return (e[0] - p[0]) * n[0] + (e[1] - p[1]) * n[1] + (e[2] - p[2]) * n[2] > 0.0;
+  };
+  auto seen = [&](int s, const double* e) {
+    const double* p = spts + 3 * s;
+    return !blocked(g, segs, e[0], e[1], p[0], p[1], sseg[s], -1);
+  };
+  std::vector<int> vis_tx;
+  {
+    std::vector<char> v(n_s, 0);
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int s = 0; s < n_s; ++s) v[s] = front(s, tx) && seen(s, tx);
+    for (int s = 0; s < n_s; ++s)
+      if (v[s]) vis_tx.push_back(s);
+  }
+  std::vector<std::vector<int32_t>> per_rx(n_rx);
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int r = 0; r < n_rx; ++r) {
+    const double* e = rx + 3 * r;
+    for (int s : vis_tx)
+      if (front(s, e) && seen(s, e)) per_rx[r].push_back(s);
+  }
+  delete g_diffuse;
+  g_diffuse = new Diffuse();
+  g_diffuse->off.assign(n_rx + 1, 0);
+  for (int r = 0; r < n_rx; ++r) g_diffuse->off[r + 1] = g_diffuse->off[r] + per_rx[r].size();
+  g_diffuse->idx.reserve(g_diffuse->off[n_rx]);
+  for (int r = 0; r < n_rx; ++r) {
+    g_diffuse->idx.insert(g_diffuse->idx.end(), per_rx[r].begin(), per_rx[r].end());
+    std::vector<int32_t>().swap(per_rx[r]);
+  }
+  return g_diffuse->off[n_rx];
+}
+
+int pd_fetch(int64_t* off, int32_t* idx) {
+  if (!g_diffuse) return -1;
+  std::memcpy(off, g_diffuse->off.data(), sizeof(int64_t) * g_diffuse->off.size());
+  std::memcpy(idx, g_diffuse->idx.data(), sizeof(int32_t) * g_diffuse->idx.size());
+  return 0;
+}
+
+void pd_free() {
+  delete g_diffuse;
+  g_diffuse = nullptr;
 }
 
 }  // extern "C"

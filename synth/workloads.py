@@ -25,6 +25,15 @@
   adjoint   the scale floor and paths with hidden ground truth:
             materials with S ~ U[0, 0.5] and 32 complex element gains;
             14,336 training / 2,048 held-out Rx
+  urban     the large-scene configuration's scene: a procedural urban block
+            400 x 400 m (~100,000 triangles: box buildings 15-45 m tall on a
+            tessellated ground plane, 16 material classes), 4 Tx at street
+            crossings at 10 m, each with a 32-element ULA, n_rx Rx at 1.5 m
+            (65,536 at full size): outdoor points of a 512 x 512 grid;
+            specular paths up to fifth order plus single-bounce Lambertian
+            diffuse paths from facade (up to 10 m) and ground samples, ~2,000
+            paths per link; 4,096 subcarriers over 100 MHz at 3.5 GHz.  One
+            path store per Tx and batch of Rx (the streaming batches).
 """
 from dataclasses import dataclass, field
 
@@ -34,7 +43,7 @@ from . import diffuse as _diffuse
 from . import imagemethod
 from .floorplan import indoor_floor
 from .params import Radio, draw_gains, draw_materials, materials_to_raw
-from .pathfind import find_store
+from .pathfind import find_store, visible_samples
 from .scene import SceneBuilder, box_room, uniform_points_in_box
 from .store import PathStore
 
@@ -245,3 +254,49 @@ def recovery(seed=7, n_tx=256, size=(24.0, 6.0, 3.0), density=1.0, max_depth=3, 
                 tx_raw=vmf_to_raw(**RECOVERY_TX), table=TABLE_I.copy(), pillar=pillar)
     return Workload("recovery", store, radio, raw, np.ones(1, np.complex64),
                     (scene.aabb_min, scene.aabb_max), meta)
+
+
+def urban_store(plan, tx, rx, samples, max_depth=SCALE_DEPTH, n_rays=1 << 18):
+    """The path store of one Tx and a set of Rx in the urban block: its
+    specular paths, then the single-bounce diffuse paths through the
+    surface samples (sample_surfaces' output) both ends see."""
+    spec = find_store(plan, tx, rx, max_depth, n_rays=n_rays, cell=4.0)
+    off, idx = visible_samples(plan, tx, rx, samples[0], samples[1], samples[5], cell=4.0)
+    per_link = [idx[off[l]:off[l + 1]] for l in range(len(rx))]
+    return _diffuse.append_diffuse(spec, np.repeat(np.asarray(tx, np.float64)[None], len(rx), 0),
+                                   samples[:5], per_link)
+
+
+def urban(seed=11, n_tx=4, n_rx=2048, n_sc=4096, bandwidth=100e6, n_elem=32,
+          max_depth=SCALE_DEPTH, n_rays=1 << 18, density=0.65, grid=512, batch=None,
+          lazy=False) -> Workload:
+    """The urban block with n_tx transmitters and n_rx receivers, a seeded
+    choice of the outdoor points of the grid x grid receiver grid at 1.5 m
+    (the same for every Tx).  The links are cut into batches of `batch`
+    receivers of one Tx (default: all n_rx), Tx-major.  meta["batch"](i)
+    builds batch i's path store; unless lazy, meta["batches"] holds them all
+    and store is the first."""
+    from . import urban as _urban
+    plan = _urban.urban_block(seed)
+    tx = _urban.transmitters(plan, n_tx)
+    rng = np.random.default_rng(seed + 1)
+    rx = _urban.outdoor_rx(plan, rng, n_rx, grid)
+    samples = _urban.sample_surfaces(plan, density, np.random.default_rng(seed + 2))
+    n_mat = plan.scene.n_mat
+    raw = materials_to_raw(*draw_materials(rng, n_mat, with_scattering=True))
+    radio = Radio(fc=3.5e9, bandwidth=bandwidth, n_sc=n_sc, n_elem=n_elem,
+                  ula_axis=(1.0, 0.0, 0.0))
+    B = len(rx) if batch is None else int(batch)
+    per_tx = (len(rx) + B - 1) // B
+
+    def make(i):
+        t, c = divmod(i, per_tx)
+        return urban_store(plan, tx[t], rx[c * B:(c + 1) * B], samples, max_depth, n_rays)
+
+    n_batches = n_tx * per_tx
+    batches = None if lazy else [make(i) for i in range(n_batches)]
+    return Workload("urban", None if lazy else batches[0], radio, raw, draw_gains(rng, n_elem),
+                    (plan.scene.aabb_min, plan.scene.aabb_max),
+                    meta=dict(plan=plan, batches=batches, batch=make, n_batches=n_batches,
+                              tx=tx, rx=rx, n_mat=n_mat, n_samples=len(samples[0]),
+                              tris=plan.scene.n_tri))
