@@ -463,7 +463,8 @@ typedef struct {
 } rtc_mlp;
 
 int32_t rtc_mlp_n_params(void);
-/* Bytes of the buffer rtc_mlp_forward saves for rtc_mlp_backward. */
+/* Bytes of the buffer rtc_mlp_forward saves for rtc_mlp_backward (its
+ * layout is internal to the library). */
 size_t rtc_mlp_saved_size(int64_t n_points);
 /* Bytes of workspace rtc_mlp_forward (>= the packed weights) and
  * rtc_mlp_backward need; the same buffer serves both. */
@@ -481,7 +482,8 @@ rtc_status rtc_mlp_forward(const rtc_mlp* net, int64_t n_points, const float* px
 /* Backward: dLdout float [3*n_points] (rows dL/d eps_r, dL/d sigma, dL/d S,
  * as rtc_trace_fields_adjoint writes them) and the forward's saved buffer ->
  * dLdparams float [rtc_mlp_n_params()] (overwritten).  Weight gradients are
- * summed over points in fixed slices and the slices in a fixed order. */
+ * summed over points in fixed blocks of 128 and the blocks' partial sums in a
+ * fixed order, so the result depends only on the inputs. */
 rtc_status rtc_mlp_backward(const rtc_mlp* net, int64_t n_points, const float* dLdout,
                             const void* saved, float* dLdparams, void* ws, size_t ws_bytes,
                             void* stream);

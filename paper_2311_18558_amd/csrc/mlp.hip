@@ -9,11 +9,20 @@
 // l%32, so registers 8e..8e+7 of a tile are directly the next layer's
 // K-block (tile, e) when the K order inside that block is the permutation
 // kperm(c, h, j) = 32(c/2) + 16(c%2) + 8(j/4) + 4h + j%4 -- the weights are
-// packed in that order, so activations never leave the registers.
+// packed in that order, so activations never leave the registers.  The
+// layer inputs are saved for the backward exactly as they sit in the
+// registers (one 16-byte vector per lane and K-block, a wave's block of 32
+// points contiguous), so saving and reloading them are full-width accesses.
 //
-// Backward: deltas run the same way through the transposed weights;
-// weight gradients are a split-K product over points of feature-major BF16
-// deltas and activations, reduced over slices in a fixed order.
+// Backward: one fused kernel.  A workgroup of four waves takes 128 points at
+// a time; each wave reloads its 32 points' layer inputs and runs the deltas
+// down through the transposed weights (the same register layout as the
+// forward).  At every layer the four waves put that layer's output deltas
+// and inputs, transposed to feature rows x point columns, into LDS; then the
+// weight gradient is a product over the 128 points (the K dimension), and
+// each wave owns a quarter of every layer's 32 x 32 gradient tiles, kept in
+// registers for the whole run.  The workgroups' partial gradients are summed
+// in a fixed order.
 #include <cmath>
 
 #include "api_common.h"
@@ -32,7 +41,6 @@ constexpr int kMlpOut = 3;
 constexpr int kMlpFreq = 8;
 constexpr int kMlpParams = 56579;
 constexpr int kMlpWaves = 4;
-constexpr int kMlpSlices = 64;  // split-K slices for the weight gradients
 
 // parameter packing: W0 [128][51], b0, W1 [128][128], b1, W2, b2, W3, b3,
 // W4 [3][128], b4
@@ -115,15 +123,16 @@ __global__ void mlp_pack_kernel(const float* __restrict__ prm, uint16_t* __restr
 
 struct MlpArgs {
   int64_t n_points;
-  int64_t qpad;  // row stride of the feature-major saved arrays
+  int64_t qpad;  // points rounded up to 256 (saved-buffer geometry)
   const float *px, *py, *pz;
   float cx, cy, cz, inv_ext;
   const float* prm;          // FP32 master parameters
   const uint16_t* packed;    // BF16 operands
   float* out;                // [3][n_points]
-  // saved for the backward (feature-major, row stride qpad), or null
-  uint16_t* x0;              // [64][qpad]
-  uint16_t* hs;              // [4][128][qpad]  h1..h4
+  // saved for the backward, or null: layer inputs in the register layout
+  // ([block of 32 points][K-block][lane] x 8 BF16) and the FP32 outputs
+  bf16x8* x0;                // [qpad/32][4][64]
+  bf16x8* hs;                // [4][qpad/32][8][64]  h1..h4
   float* o;                  // [3][qpad] pre-transform outputs
 };
 
@@ -148,12 +157,20 @@ RTC_DEV float pe_feature(int f, const float pb[3]) {
   return (g & 1) ? co : s;
 }
 
+// saved-buffer offsets (in 16-byte vectors) of a wave block's K-block c
+RTC_DEV int64_t sv_x0(int64_t blk, int c, int lane) { return (blk * 4 + c) * 64 + lane; }
+RTC_DEV int64_t sv_h(int64_t nblk, int l, int64_t blk, int c, int lane) {
+  return (((int64_t)l * nblk + blk) * 8 + c) * 64 + lane;
+}
+
 __global__ void __launch_bounds__(kMlpWaves * 64) mlp_forward_kernel(MlpArgs A) {
   const int lane = threadIdx.x & 63;
   const int h = lane >> 5;
   const int pt = lane & 31;
-  const int64_t q0 = ((int64_t)blockIdx.x * kMlpWaves + (threadIdx.x >> 6)) * 32;
+  const int64_t blk = (int64_t)blockIdx.x * kMlpWaves + (threadIdx.x >> 6);
+  const int64_t q0 = blk * 32;
   if (q0 >= A.n_points) return;
+  const int64_t nblk = A.qpad / 32;
   const int64_t q = q0 + pt;
   const bool valid = q < A.n_points;
   float pb[3] = {0.0f, 0.0f, 0.0f};
@@ -170,11 +187,7 @@ __global__ void __launch_bounds__(kMlpWaves * 64) mlp_forward_kernel(MlpArgs A) 
 #pragma unroll
     for (int j = 0; j < 8; ++j) v[j] = pe_feature(16 * c + 8 * h + j, pb);
     xin[c] = pack8(v);
-    if (A.x0 && valid) {
-      const uint16_t* pv = reinterpret_cast<const uint16_t*>(&xin[c]);
-#pragma unroll
-      for (int j = 0; j < 8; ++j) A.x0[(int64_t)(16 * c + 8 * h + j) * A.qpad + q] = pv[j];
-    }
+    if (A.x0) A.x0[sv_x0(blk, c, lane)] = xin[c];
   }
 #pragma unroll
   for (int l = 0; l < 4; ++l) {
@@ -195,16 +208,10 @@ __global__ void __launch_bounds__(kMlpWaves * 64) mlp_forward_kernel(MlpArgs A) 
       for (int r = 0; r < 16; ++r) v[r] = fmaxf(acc[t][r] + b[32 * t + drow(r, h)], 0.0f);
       xin[2 * t] = pack8(v);
       xin[2 * t + 1] = pack8(v + 8);
-      if (A.hs && valid) {
-        const uint16_t* p0 = reinterpret_cast<const uint16_t*>(&xin[2 * t]);
-        const uint16_t* p1 = reinterpret_cast<const uint16_t*>(&xin[2 * t + 1]);
-        uint16_t* dst = A.hs + (int64_t)l * kMlpWidth * A.qpad;
+    }
+    if (A.hs) {
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
-          dst[(int64_t)(32 * t + drow(r, h)) * A.qpad + q] = p0[r];
-          dst[(int64_t)(32 * t + drow(r + 8, h)) * A.qpad + q] = p1[r];
-        }
-      }
+      for (int c = 0; c < 8; ++c) A.hs[sv_h(nblk, l, blk, c, lane)] = xin[c];
     }
   }
   floatx16 acc = floatx16{0};
@@ -225,171 +232,232 @@ __global__ void __launch_bounds__(kMlpWaves * 64) mlp_forward_kernel(MlpArgs A) 
   }
 }
 
-struct MlpBackArgs {
+constexpr int kBwdWaves = 4;
+constexpr int kBwdPts = 32 * kBwdWaves;  // points per workgroup step
+constexpr int kBwdLd = kBwdPts + 8;      // LDS row stride (BF16): conflict-free 16-byte reads
+constexpr int kBwdStage = 2 * 128 * kBwdLd;  // one layer: 128 delta rows, then 128 input rows
+constexpr int kMlpBwdBlocks = 256;       // workgroups (their partials are summed in order)
+
+struct MlpBwdArgs {
   int64_t n_points, qpad;
   const float* dout;        // [3][n_points] dL/d(eps_r, sigma, S)
   const uint16_t* packed;
-  const uint16_t* hs;       // [4][128][qpad]
+  const bf16x8* x0;         // saved layer inputs (layout of MlpArgs)
+  const bf16x8* hs;
   const float* o;           // [3][qpad]
-  uint16_t* dlt;            // [5][128][qpad]: delta of h1..h4 and (rows 0..2) of o
+  float* part;              // [gridDim.x][kMlpParams]
 };
 
-// Deltas: d_o = dL/do (output transforms), d_h4 = W4^T d_o * [h4 > 0], ...
-__global__ void __launch_bounds__(kMlpWaves * 64) mlp_delta_kernel(MlpBackArgs A) {
+// Transposed store of a wave's K-blocks (register layout, feature order
+// given by `feat`) into LDS rows = features, columns = the wave's 32 points.
+template <int NKB, bool KPERM>
+RTC_DEV void put_rows(uint16_t* rows, const bf16x8* v, int col, int h) {
+#pragma unroll
+  for (int c = 0; c < NKB; ++c) {
+    const u32x4 w = __builtin_bit_cast(u32x4, v[c]);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int f = KPERM ? kperm(c, h, j) : 16 * c + 8 * h + j;
+      rows[f * kBwdLd + col] = (uint16_t)(w[j >> 1] >> (16 * (j & 1)));
+    }
+  }
+}
+
+RTC_DEV bf16x8 lds_op(const uint16_t* rows, int row, int k0) {
+  return *reinterpret_cast<const bf16x8*>(rows + row * kBwdLd + k0);
+}
+
+RTC_DEV float bf_sum8(bf16x8 a) {
+  const u32x4 w = __builtin_bit_cast(u32x4, a);
+  float s = 0.0f;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) s += __uint_as_float(w[j] << 16) + __uint_as_float(w[j] & 0xFFFF0000u);
+  return s;
+}
+
+RTC_DEV bool bf_pos(bf16x8 v, int j) {
+  const u32x4 w = __builtin_bit_cast(u32x4, v);
+  const uint32_t b = (w[j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
+  return b != 0u && (b & 0x8000u) == 0u;
+}
+
+// global-memory pointer (keeps the weight loads global, not flat, after the
+// address has passed through an opaque copy)
+typedef const __attribute__((address_space(1))) bf16x8* GPtr;
+
+// d_in = W_l^T d_out * [h_l > 0] for one wave (register layout; blocks
+// beyond the points carry zero inputs, hence zero deltas).
+template <int L>
+RTC_DEV void delta_down(GPtr packed, const bf16x8* din, const bf16x8* hv, int lane, bf16x8* nxt) {
+  GPtr Wt = packed + bw_off(L) / 8;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    floatx16 acc = floatx16{0};
+#pragma unroll
+    for (int c = 0; c < bw_kb(L); ++c)
+      acc = mfma_bf16(Wt[(t * bw_kb(L) + c) * 64 + lane], din[c], acc);
+    float v[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = bf_pos(hv[2 * t + (r >> 3)], r & 7) ? acc[r] : 0.0f;
+    nxt[2 * t] = pack8(v);
+    nxt[2 * t + 1] = pack8(v + 8);
+  }
+}
+
+__global__ void __launch_bounds__(kBwdWaves * 64, 1) mlp_backward_kernel(MlpBwdArgs A) {
+  __shared__ __align__(16) uint16_t lds[2 * kBwdStage];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int h = lane >> 5;
-  const int pt = lane & 31;
-  const int64_t q0 = ((int64_t)blockIdx.x * kMlpWaves + (threadIdx.x >> 6)) * 32;
-  if (q0 >= A.qpad) return;
-  const int64_t q = q0 + pt;
-  const bool valid = q < A.n_points;
-  // d_o in the accumulator layout of a 3-row tile: rows 0..2 live in lanes
-  // h = 0, registers 0..2 (K-block 0, j = 0..2)
-  float dv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  if (h == 0 && valid) {
-    float o0 = A.o[q], o1 = A.o[A.qpad + q], o2 = A.o[2 * A.qpad + q];
-    float s2 = sigmoidf(o2);
-    dv[0] = A.dout[q] * sigmoidf(o0);                     // d eps/d o0
-    dv[1] = A.dout[A.n_points + q] * sigmoidf(o1);        // d sigma/d o1
-    dv[2] = A.dout[2 * A.n_points + q] * s2 * (1.0f - s2);  // d S/d o2
-  }
-  bf16x8 din[8];
-  din[0] = pack8(dv);
-  uint16_t* dst_o = A.dlt + 4 * (int64_t)kMlpWidth * A.qpad;
-  {
-    const uint16_t* p = reinterpret_cast<const uint16_t*>(&din[0]);
-    if (h == 0) {
-#pragma unroll
-      for (int r = 0; r < 3; ++r) dst_o[(int64_t)r * A.qpad + q] = valid ? p[r] : 0;
-    }
-  }
-#pragma unroll
-  for (int l = 4; l >= 1; --l) {
-    // d_h(l) = W_l^T d_(l+1) * relu'(h_l): rows = inputs of layer l
-    const uint16_t* Wt = A.packed + bw_off(l);
-    const uint16_t* hl = A.hs + (int64_t)(l - 1) * kMlpWidth * A.qpad;
-    uint16_t* dst = A.dlt + (int64_t)(l - 1) * kMlpWidth * A.qpad;
-    bf16x8 nxt[8];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      floatx16 acc = floatx16{0};
-#pragma unroll
-      for (int c = 0; c < bw_kb(l); ++c)
-        acc = mfma_bf16(load_op(Wt, (t * bw_kb(l) + c) * 64 + lane), din[c], acc);
-      float v[16];
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int n = 32 * t + drow(r, h);
-        uint16_t hb = valid ? hl[(int64_t)n * A.qpad + q] : 0;
-        v[r] = (valid && bf2f(hb) > 0.0f) ? acc[r] : 0.0f;
-      }
-      nxt[2 * t] = pack8(v);
-      nxt[2 * t + 1] = pack8(v + 8);
-      const uint16_t* p0 = reinterpret_cast<const uint16_t*>(&nxt[2 * t]);
-      const uint16_t* p1 = reinterpret_cast<const uint16_t*>(&nxt[2 * t + 1]);
-#pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        dst[(int64_t)(32 * t + drow(r, h)) * A.qpad + q] = p0[r];
-        dst[(int64_t)(32 * t + drow(r + 8, h)) * A.qpad + q] = p1[r];
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < 8; ++c) din[c] = nxt[c];
-  }
-}
-
-struct MlpGradArgs {
-  int64_t qpad;
-  int64_t slice;  // points per slice (multiple of 16)
-  const uint16_t* x0;   // [64][qpad]
-  const uint16_t* hs;   // [4][128][qpad]
-  const uint16_t* dlt;  // [5][128][qpad]
-  float* part;          // [kMlpSlices][kMlpParams]
-};
-
-// One wave per (slice, layer, out tile, in tile): dW[n_out][n_in] =
-// sum_points delta[n_out][q] x[n_in][q]; waves with in tile 0 also form
-// db[n_out] = sum_points delta[n_out][q].
-__global__ void __launch_bounds__(64) mlp_wgrad_kernel(MlpGradArgs A) {
-  const int lane = threadIdx.x;
-  const int h = lane >> 5;
   const int i = lane & 31;
-  const int s = blockIdx.x;
-  int pair = blockIdx.y;
-  // enumerate (layer, out tile, in tile): layer 0: 4 x 2, layers 1-3: 4 x 4, layer 4: 1 x 4
-  int l, to, ti;
-  if (pair < 8) {
-    l = 0;
-    to = pair >> 1;
-    ti = pair & 1;
-  } else if (pair < 56) {
-    l = 1 + (pair - 8) / 16;
-    to = ((pair - 8) % 16) >> 2;
-    ti = (pair - 8) & 3;
-  } else {
-    l = 4;
-    to = 0;
-    ti = pair - 56;
+  const int col = 32 * wave + i;
+  const int64_t nblk = A.qpad / 32;
+  const int64_t nstep = (A.n_points + kBwdPts - 1) / kBwdPts;
+  // this wave's gradient tiles: layers 1..3 (out tile = wave, in tiles 0..3),
+  // layer 0 (out tile = wave, in tiles 0..1), layer 4 (in tile = wave)
+  floatx16 g123[3][4], g0[2], g4;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) g123[a][b] = floatx16{0};
+  g0[0] = g0[1] = g4 = floatx16{0};
+  float gb[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};  // bias partial sums (rows of this lane)
+  const bf16x8 zero8 = __builtin_bit_cast(bf16x8, u32x4{0u, 0u, 0u, 0u});
+  int buf = 0;
+  for (int64_t stp = blockIdx.x; stp < nstep; stp += gridDim.x) {
+    // the packed weights are the same every step: an opaque copy of their
+    // address keeps their loads inside the loop (hoisted, they would hold
+    // hundreds of registers for the whole run)
+    GPtr pk = (GPtr)A.packed;
+    asm volatile("" : "+s"(pk));
+    const int64_t blk = stp * kBwdWaves + wave;
+    const bool live = blk * 32 < A.n_points;  // the forward saved this block
+    const int64_t q = blk * 32 + i;
+    const bool valid = q < A.n_points;
+    // blocks beyond the points lie inside the saved buffer (it is padded to
+    // 256 points) but were never written: their loads are replaced by zeros
+    bf16x8 hv[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const bf16x8 v = A.hs[sv_h(nblk, 3, blk, c, lane)];
+      hv[c] = live ? v : zero8;
+    }
+    // output deltas: rows 0..2 in lanes h = 0, registers 0..2 of K-block 0
+    bf16x8 din[8];
+    {
+      const int64_t qc = valid ? q : A.n_points - 1;
+      const float s0 = sigmoidf(A.o[qc]), s1 = sigmoidf(A.o[A.qpad + qc]);
+      const float s2 = sigmoidf(A.o[2 * A.qpad + qc]);
+      const bool on = h == 0 && valid;
+      float dv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      dv[0] = on ? A.dout[qc] * s0 : 0.0f;                             // d eps/d o0
+      dv[1] = on ? A.dout[A.n_points + qc] * s1 : 0.0f;                // d sigma/d o1
+      dv[2] = on ? A.dout[2 * A.n_points + qc] * s2 * (1.0f - s2) : 0.0f;  // d S/d o2
+      din[0] = pack8(dv);
+#pragma unroll
+      for (int c = 1; c < 8; ++c) din[c] = zero8;
+    }
+#pragma unroll
+    for (int s = 4; s >= 0; --s) {
+      uint16_t* Ds = lds + buf * kBwdStage;
+      uint16_t* Xs = Ds + 128 * kBwdLd;
+      // layer s: output deltas (rows) and inputs (rows) of this wave's points
+      if (s == 4) {
+        if (h == 0) {
+          const u32x4 w = __builtin_bit_cast(u32x4, din[0]);
+          Ds[0 * kBwdLd + col] = (uint16_t)(w[0] & 0xFFFFu);
+          Ds[1 * kBwdLd + col] = (uint16_t)(w[0] >> 16);
+          Ds[2 * kBwdLd + col] = (uint16_t)(w[1] & 0xFFFFu);
+        }
+      } else {
+        put_rows<8, true>(Ds, din, col, h);
+      }
+      if (s == 0) put_rows<4, false>(Xs, hv, col, h);
+      else put_rows<8, true>(Xs, hv, col, h);
+      // deltas one layer down while the others write
+      bf16x8 nxt[8];
+      if (s == 4) delta_down<4>(pk, din, hv, lane, nxt);
+      if (s == 3) delta_down<3>(pk, din, hv, lane, nxt);
+      if (s == 2) delta_down<2>(pk, din, hv, lane, nxt);
+      if (s == 1) delta_down<1>(pk, din, hv, lane, nxt);
+      // inputs of the next layer down
+      bf16x8 hn[8];
+      if (s >= 2) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          const bf16x8 v = A.hs[sv_h(nblk, s - 2, blk, c, lane)];
+          hn[c] = live ? v : zero8;
+        }
+      } else if (s == 1) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const bf16x8 v = A.x0[sv_x0(blk, c, lane)];
+          hn[c] = live ? v : zero8;
+        }
+#pragma unroll
+        for (int c = 4; c < 8; ++c) hn[c] = zero8;
+      }
+      __syncthreads();
+      // weight gradient of layer s over the workgroup's 128 points
+#pragma unroll
+      for (int k = 0; k < kBwdPts / 16; ++k) {
+        const int k0 = 16 * k + 8 * h;
+        if (s == 4) {
+          const bf16x8 a4 = lds_op(Ds, i < 3 ? i : 0, k0);
+          const bf16x8 a = i < 3 ? a4 : zero8;
+          g4 = mfma_bf16(a, lds_op(Xs, 32 * wave + i, k0), g4);
+          if (wave == 0) gb[4] += bf_sum8(a);
+        } else {
+          const bf16x8 a = lds_op(Ds, 32 * wave + i, k0);
+          gb[s] += bf_sum8(a);
+          if (s == 0) {
+#pragma unroll
+            for (int ti = 0; ti < 2; ++ti) g0[ti] = mfma_bf16(a, lds_op(Xs, 32 * ti + i, k0), g0[ti]);
+          } else {
+#pragma unroll
+            for (int ti = 0; ti < 4; ++ti)
+              g123[s - 1][ti] = mfma_bf16(a, lds_op(Xs, 32 * ti + i, k0), g123[s - 1][ti]);
+          }
+        }
+      }
+      // no barrier here: the next layer writes the other buffer, and this
+      // one is rewritten only after the next layer's barrier
+      buf ^= 1;
+      if (s >= 1) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          din[c] = nxt[c];
+          hv[c] = hn[c];
+        }
+      }
+    }
   }
-  // delta of layer l's outputs: l = 0..3 -> d_h(l+1) rows 0..127, l = 4 -> d_o
-  const uint16_t* D = A.dlt + (int64_t)(l == 4 ? 4 : l) * kMlpWidth * A.qpad;
-  // inputs of layer l: x0 for l = 0, else h_l
-  const uint16_t* X = l == 0 ? A.x0 : A.hs + (int64_t)(l - 1) * kMlpWidth * A.qpad;
-  const int nrow = 32 * to + i;
-  const int ncol = 32 * ti + i;
-  const bool row_ok = nrow < mlp_nout(l);
-  const int64_t p0 = (int64_t)s * A.slice;
-  // the last slice is clipped at qpad (p0 and qpad are multiples of 16)
-  const int64_t kend = p0 + A.slice <= A.qpad ? A.slice : A.qpad - p0;
-  floatx16 acc = floatx16{0};
-  floatx16 accb = floatx16{0};
-  bf16x8 ones;
-  {
-    float o8[8] = {1, 1, 1, 1, 1, 1, 1, 1};
-    ones = pack8(o8);
-  }
-  bf16x8 zero;
-  {
-    float z8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    zero = pack8(z8);
-  }
-  for (int64_t k = 0; k < kend; k += 16) {
-    const int64_t pq = p0 + k + 8 * h;
-    bf16x8 a = row_ok ? *reinterpret_cast<const bf16x8*>(D + (int64_t)nrow * A.qpad + pq) : zero;
-    bf16x8 b = *reinterpret_cast<const bf16x8*>(X + (int64_t)ncol * A.qpad + pq);
-    acc = mfma_bf16(a, b, acc);
-    if (ti == 0) accb = mfma_bf16(a, ones, accb);
-  }
-  float* out = A.part + (int64_t)s * kMlpParams;
+  // this workgroup's partial gradient
+  float* out = A.part + (int64_t)blockIdx.x * kMlpParams;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
-    const int no = 32 * to + drow(r, h);
-    const int ni = 32 * ti + i;
-    if (no < mlp_nout(l) && ni < mlp_nin(l)) out[mlp_off_w(l) + no * mlp_nin(l) + ni] = acc[r];
-    if (ti == 0 && i == 0 && no < mlp_nout(l)) out[mlp_off_b(l) + no] = accb[r];
+    const int no = 32 * wave + drow(r, h);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int ti = 0; ti < 4; ++ti)
+        out[mlp_off_w(a + 1) + no * kMlpWidth + 32 * ti + i] = g123[a][ti][r];
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+      if (32 * ti + i < kMlpIn) out[mlp_off_w(0) + no * kMlpIn + 32 * ti + i] = g0[ti][r];
+    const int n4 = drow(r, h);
+    if (n4 < kMlpOut) out[mlp_off_w(4) + n4 * kMlpWidth + 32 * wave + i] = g4[r];
+  }
+#pragma unroll
+  for (int l = 0; l < 5; ++l) gb[l] += __shfl_xor(gb[l], 32);
+  if (h == 0) {
+#pragma unroll
+    for (int l = 0; l < 4; ++l) out[mlp_off_b(l) + 32 * wave + i] = gb[l];
+    if (wave == 0 && i < kMlpOut) out[mlp_off_b(4) + i] = gb[4];
   }
 }
 
-// Zero the padded point columns [n, qpad) of the saved arrays (the split-K
-// weight-gradient products read them).
-__global__ void mlp_zero_tail_kernel(uint16_t* sv, int64_t n, int64_t qpad) {
-  const int64_t tail = qpad - n;
-  const int64_t rows16 = kMlpIn0 + 4 * kMlpWidth;
-  const int64_t total = (rows16 + 6) * tail;  // 6 = the three FP32 rows as 16-bit halves
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = i / tail, c = n + i % tail;
-    if (r < rows16) {
-      sv[r * qpad + c] = 0;
-    } else {
-      float* o = reinterpret_cast<float*>(sv + rows16 * qpad);
-      const int64_t fr = (r - rows16) >> 1;
-      if (((r - rows16) & 1) == 0) o[fr * qpad + c] = 0.0f;
-    }
-  }
-}
-
-// Sum the slice partials column-wise in slice order (FP64).
+// Sum the workgroup partials column-wise in workgroup order (FP64).
 __global__ void reduce_cols_kernel(const float* part, int R, int K, float* out) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= K) return;
@@ -416,9 +484,8 @@ size_t rtc_mlp_saved_size(int64_t n_points) {
 
 size_t rtc_mlp_workspace_size(int64_t n_points) {
   if (n_points < 0) return 0;
-  int64_t qp = qpad_of(n_points);
-  return (size_t)kPackedElems * sizeof(uint16_t) + (size_t)5 * kMlpWidth * qp * sizeof(uint16_t) +
-         (size_t)kMlpSlices * kMlpParams * sizeof(float) + 256;
+  return (size_t)kPackedElems * sizeof(uint16_t) + 256 +
+         (size_t)kMlpBwdBlocks * kMlpParams * sizeof(float);
 }
 
 rtc_status rtc_mlp_forward(const rtc_mlp* net, int64_t n_points, const float* px, const float* py,
@@ -459,15 +526,10 @@ rtc_status rtc_mlp_forward(const rtc_mlp* net, int64_t n_points, const float* px
   A.packed = packed;
   A.out = out;
   uint16_t* sv = reinterpret_cast<uint16_t*>(saved);
-  A.x0 = saved ? sv : nullptr;
-  A.hs = saved ? sv + (int64_t)kMlpIn0 * A.qpad : nullptr;
+  A.x0 = saved ? reinterpret_cast<bf16x8*>(sv) : nullptr;
+  A.hs = saved ? reinterpret_cast<bf16x8*>(sv + (int64_t)kMlpIn0 * A.qpad) : nullptr;
   A.o = saved ? reinterpret_cast<float*>(sv + (int64_t)(kMlpIn0 + 4 * kMlpWidth) * A.qpad)
               : nullptr;
-  if (saved && A.qpad > n_points) {
-    // padded point columns must hold zeros for the split-K products
-    hipLaunchKernelGGL(mlp_zero_tail_kernel, dim3(256), dim3(256), 0, s, sv, n_points, A.qpad);
-    if ((st = check_launch(fn)) != RTC_OK) return st;
-  }
   int64_t waves = (n_points + 31) / 32;
   int64_t blocks = (waves + kMlpWaves - 1) / kMlpWaves;
   hipLaunchKernelGGL(mlp_forward_kernel, dim3((unsigned)blocks), dim3(kMlpWaves * 64), 0, s, A);
@@ -492,47 +554,28 @@ rtc_status rtc_mlp_backward(const rtc_mlp* net, int64_t n_points, const float* d
               fn, need);
   const int64_t qp = qpad_of(n_points);
   uint16_t* packed = reinterpret_cast<uint16_t*>(ws);
-  uint16_t* dlt = packed + kPackedElems;
   float* part = reinterpret_cast<float*>(
-      (reinterpret_cast<uintptr_t>(dlt + (int64_t)5 * kMlpWidth * qp) + 255) & ~(uintptr_t)255);
+      (reinterpret_cast<uintptr_t>(packed + kPackedElems) + 255) & ~(uintptr_t)255);
   hipLaunchKernelGGL(mlp_pack_kernel, dim3((kPackedElems + 255) / 256), dim3(256), 0, s,
                      net->params, packed);
   rtc_status st;
   if ((st = check_launch(fn)) != RTC_OK) return st;
   const uint16_t* sv = reinterpret_cast<const uint16_t*>(saved);
-  MlpBackArgs B;
+  MlpBwdArgs B;
   B.n_points = n_points;
   B.qpad = qp;
   B.dout = dLdout;
   B.packed = packed;
-  B.hs = sv + (int64_t)kMlpIn0 * qp;
+  B.x0 = reinterpret_cast<const bf16x8*>(sv);
+  B.hs = reinterpret_cast<const bf16x8*>(sv + (int64_t)kMlpIn0 * qp);
   B.o = reinterpret_cast<const float*>(sv + (int64_t)(kMlpIn0 + 4 * kMlpWidth) * qp);
-  B.dlt = dlt;
-  int64_t waves = qp / 32;
-  hipLaunchKernelGGL(mlp_delta_kernel, dim3((unsigned)((waves + kMlpWaves - 1) / kMlpWaves)),
-                     dim3(kMlpWaves * 64), 0, s, B);
-  if ((st = check_launch(fn)) != RTC_OK) return st;
-  MlpGradArgs G;
-  G.qpad = qp;
-  G.slice = qp / kMlpSlices;  // qp is a multiple of 256, so slices are multiples of 4 ...
-  G.slice = (G.slice + 15) / 16 * 16;
-  G.x0 = sv;
-  G.hs = B.hs;
-  G.dlt = dlt;
-  G.part = part;
-  // slices must not run past qp: the last ones are clipped by construction
-  int n_slices = (int)((qp + G.slice - 1) / G.slice);
-  RTC_REQUIRE(n_slices <= kMlpSlices, RTC_ERR_RANGE, "%s: internal slicing error", fn);
-  if (n_slices < kMlpSlices) {
-    // unused slices contribute zero
-    if ((st = zero_floats(part + (int64_t)n_slices * kMlpParams,
-                          (int64_t)(kMlpSlices - n_slices) * kMlpParams, s, fn)) != RTC_OK)
-      return st;
-  }
-  hipLaunchKernelGGL(mlp_wgrad_kernel, dim3(n_slices, 60), dim3(64), 0, s, G);
+  B.part = part;
+  const int64_t nstep = (n_points + kBwdPts - 1) / kBwdPts;
+  const int nb = (int)(nstep < kMlpBwdBlocks ? nstep : kMlpBwdBlocks);
+  hipLaunchKernelGGL(mlp_backward_kernel, dim3(nb), dim3(kBwdWaves * 64), 0, s, B);
   if ((st = check_launch(fn)) != RTC_OK) return st;
   hipLaunchKernelGGL(reduce_cols_kernel, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, part,
-                     kMlpSlices, kMlpParams, dLdparams);
+                     nb, kMlpParams, dLdparams);
   return check_launch(fn);
 }
 
