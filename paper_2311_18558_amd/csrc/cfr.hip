@@ -540,9 +540,18 @@ __device__ __forceinline__ void adj_wave(const AdjArgs& A, int64_t w, int64_t l,
 
 __global__ void __launch_bounds__(kAdjWaves * 64, 2) cfr_adjoint_kernel(AdjArgs A) {
   const int lane = threadIdx.x & 63;
-  const int64_t w = (int64_t)blockIdx.x * kAdjWaves + (threadIdx.x >> 6);
-  if (w >= A.max_waves) return;
+  // XCD-aware order: workgroups go to the eight XCDs in turn, so the first
+  // 8 nb workgroups (nb = the workgroups of real waves per XCD) give XCD
+  // b % 8 the (b % 8)-th eighth of the real waves, in order; the waves of
+  // one link then sit on one XCD and share its L2 for the link's dL/dH,
+  // which they all read.  The surplus workgroups come after them (the grid
+  // is a multiple of eight workgroups, sized for the most waves possible).
   const int64_t total = A.wave_off[A.n_links];
+  const int64_t nb = ((total + kAdjWaves - 1) / kAdjWaves + 7) / 8;
+  const int64_t b = blockIdx.x, x = b & 7, bs = b >> 3;
+  const int64_t vb = bs < nb ? x * nb + bs : 8 * nb + (bs - nb) * 8 + x;
+  const int64_t w = vb * kAdjWaves + (threadIdx.x >> 6);
+  if (w >= A.max_waves) return;
   if (w >= total) {
     // surplus wave: its dL/dg partial row is zero
     if (A.g_part)
@@ -816,7 +825,8 @@ extern "C" rtc_status rtc_cfr_adjoint(const rtc_radio* radio, const rtc_paths* p
                 "%s: problem too large for one launch", fn);
     hipLaunchKernelGGL(cfr_adjoint_m1_kernel, dim3((unsigned)blocks), dim3(kM1Block), 0, s, A);
   } else {
-    const int64_t blocks = (A.max_waves + kAdjWaves - 1) / kAdjWaves;
+    // a multiple of eight workgroups (the kernel's XCD-aware order)
+    const int64_t blocks = ((A.max_waves + kAdjWaves - 1) / kAdjWaves + 7) / 8 * 8;
     RTC_REQUIRE(blocks < (1ll << 31), RTC_ERR_RANGE, "%s: problem too large for one launch", fn);
     hipLaunchKernelGGL(cfr_adjoint_kernel, dim3((unsigned)blocks), dim3(kAdjWaves * 64), 0, s, A);
   }

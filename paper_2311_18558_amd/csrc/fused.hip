@@ -95,25 +95,34 @@ struct RowTargets {
   static constexpr int RZ = fft_radix(LOGN, NP - 1);
   static constexpr int JZ = fft_bpl(1 << LOGN, RZ);
   float2 t[16];
-  float p[JZ][RZ];
 };
 
+// the row's target CFR (prefetched a row ahead) ...
 template <int LOGN>
 __device__ __forceinline__ void load_row_targets(const FusedArgs& A, int64_t ridx, int lane,
                                                  RowTargets<LOGN>& T) {
   constexpr int N = 1 << LOGN;
-  constexpr int BA = N / 16, BZ = N / RowTargets<LOGN>::RZ;
+  constexpr int BA = N / 16;
   const float2* ts = A.Ht + ridx * N;
-  const float* ps = A.Pt + ridx * N;
 #pragma unroll
   for (int r = 0; r < 16; ++r)
     T.t[r] = (BA == 64 || lane < BA) ? ts[lane + r * BA] : make_float2(0.0f, 0.0f);
+}
+
+// ... and its target PDP, loaded when the row starts (it is needed only
+// after the first transform)
+template <int LOGN>
+__device__ __forceinline__ void load_row_pdp(const float* Pt, int64_t ridx, int lane,
+                                             float (&p)[RowTargets<LOGN>::JZ][RowTargets<LOGN>::RZ]) {
+  constexpr int N = 1 << LOGN;
+  constexpr int BZ = N / RowTargets<LOGN>::RZ;
+  const float* ps = Pt + ridx * N;
 #pragma unroll
   for (int i = 0; i < RowTargets<LOGN>::JZ; ++i) {
     const int jj = lane + 64 * i;
 #pragma unroll
     for (int r = 0; r < RowTargets<LOGN>::RZ; ++r)
-      T.p[i][r] = (BZ % 64 == 0 || jj < BZ) ? ps[jj + r * BZ] : 0.0f;
+      p[i][r] = (BZ % 64 == 0 || jj < BZ) ? ps[jj + r * BZ] : 0.0f;
   }
 }
 
@@ -130,7 +139,8 @@ __device__ __forceinline__ void load_row_targets(const FusedArgs& A, int64_t rid
 // BA - 1 - j + BA (7 - r) (lower half) -- the mirror n -> N - 1 - n is lane
 // BA - 1 - j, register 15 - r.
 template <int LOGN>
-__device__ __forceinline__ void fused_loss_row(float4* row, const RowTargets<LOGN>& T, float us,
+__device__ __forceinline__ void fused_loss_row(float4* row, const RowTargets<LOGN>& T,
+                                               const float* Pt, int64_t ridx, float us,
                                                float2* b0, float2* b1, float gc, float gp,
                                                double (&sums)[2], int lane_in) {
   // the FFT twiddles depend on the lane and the pass only; an opaque lane
@@ -147,6 +157,8 @@ __device__ __forceinline__ void fused_loss_row(float4* row, const RowTargets<LOG
   const float invN = 1.0f / (float)N;
   const int j = lane;
   const bool act = BA == 64 || j < BA;
+  float tp[JZ][RZ];
+  load_row_pdp<LOGN>(Pt, ridx, lane, tp);
   float2 vh[1][16], diff[16];
   float ec = 0.0f;
 #pragma unroll
@@ -175,7 +187,7 @@ __device__ __forceinline__ void fused_loss_row(float4* row, const RowTargets<LOG
 #pragma unroll
       for (int r = 0; r < RZ; ++r) {
         const float p = cabs2(xh[i][r]) * invN;
-        const float d = p - T.p[i][r];
+        const float d = p - tp[i][r];
         ep += d * d;
         xh[i][r] = cscale(xh[i][r], gp * d);  // gradient source
       }
@@ -339,8 +351,8 @@ __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs 
         RowTargets<LOGN> nxt;
         const int mnext = row_of(k + 1);
         if (mnext < M) load_row_targets<LOGN>(A, l * M + mnext, lane, nxt);
-        fused_loss_row<LOGN>(rowbuf + row_slot0(mrow & 7, F::LDQ), cur, unscale, fb[wv][0],
-                             fb[wv][1], gc, gp, sums, lane);
+        fused_loss_row<LOGN>(rowbuf + row_slot0(mrow & 7, F::LDQ), cur, A.Pt, l * M + mrow,
+                             unscale, fb[wv][0], fb[wv][1], gc, gp, sums, lane);
         cur = nxt;
       }
     }
