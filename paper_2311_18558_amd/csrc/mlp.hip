@@ -2,7 +2,7 @@
 // (ReLU) -> 3, outputs eps_r = 1 + softplus, sigma = softplus, S = logistic,
 // on the BF16 matrix cores with FP32 accumulation.
 //
-// Forward: one wave per 32 points.  Activations are the B operand of
+// Forward: a wave per 32 points.  Activations are the B operand of
 // v_mfma_f32_32x32x16_bf16 (rows = neurons, columns = points): lane l holds
 // point l%32 and K slice 8(l/32)..+7.  The accumulator of a 32-neuron tile
 // holds, in register r of lane l, neuron 8(r/4) + 4(l/32) + r%4 of point
@@ -40,7 +40,6 @@ constexpr int kMlpWidth = 128;
 constexpr int kMlpOut = 3;
 constexpr int kMlpFreq = 8;
 constexpr int kMlpParams = 56579;
-constexpr int kMlpWaves = 4;
 
 // parameter packing: W0 [128][51], b0, W1 [128][128], b1, W2, b2, W3, b3,
 // W4 [3][128], b4
@@ -79,13 +78,13 @@ RTC_DEV uint16_t f2bf(float f) {
 }
 RTC_DEV float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
+// eight FP32 values rounded to BF16 (nearest even; v_cvt_pk_bf16_f32)
+typedef float float8v __attribute__((ext_vector_type(8)));
 RTC_DEV bf16x8 pack8(const float* v) {
-  u32x4 w;
-  w[0] = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
-  w[1] = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
-  w[2] = (uint32_t)f2bf(v[4]) | ((uint32_t)f2bf(v[5]) << 16);
-  w[3] = (uint32_t)f2bf(v[6]) | ((uint32_t)f2bf(v[7]) << 16);
-  return __builtin_bit_cast(bf16x8, w);
+  float8v f;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) f[j] = v[j];
+  return __builtin_convertvector(f, bf16x8);
 }
 
 RTC_DEV floatx16 mfma_bf16(bf16x8 a, bf16x8 b, floatx16 c) {
@@ -163,71 +162,97 @@ RTC_DEV int64_t sv_h(int64_t nblk, int l, int64_t blk, int c, int lane) {
   return (((int64_t)l * nblk + blk) * 8 + c) * 64 + lane;
 }
 
-__global__ void __launch_bounds__(kMlpWaves * 64) mlp_forward_kernel(MlpArgs A) {
+// Forward: persistent workgroups of kFwdWaves waves, one per CU.  The
+// packed weights (120 KB) and the biases go to LDS once; each wave then
+// takes blocks of 32 points in turn, its weight operands from LDS.
+constexpr int kFwdWaves = 8;
+constexpr int kFwdOps = fw_off(5) / 8;  // 16-byte weight operands
+constexpr int kFwdBias = 4 * kMlpWidth + kMlpOut;
+constexpr int kFwdBlocks = 256;
+
+__global__ void __launch_bounds__(kFwdWaves * 64, 1) mlp_forward_kernel(MlpArgs A) {
+  __shared__ bf16x8 wl[kFwdOps];
+  __shared__ float bl[kFwdBias];
+  {
+    const bf16x8* src = reinterpret_cast<const bf16x8*>(A.packed);
+    for (int i = threadIdx.x; i < kFwdOps; i += kFwdWaves * 64) wl[i] = src[i];
+    for (int i = threadIdx.x; i < kFwdBias; i += kFwdWaves * 64)
+      bl[i] = A.prm[i < 4 * kMlpWidth ? mlp_off_b(i / kMlpWidth) + i % kMlpWidth
+                                      : mlp_off_b(4) + i - 4 * kMlpWidth];
+  }
+  __syncthreads();
   const int lane = threadIdx.x & 63;
   const int h = lane >> 5;
   const int pt = lane & 31;
-  const int64_t blk = (int64_t)blockIdx.x * kMlpWaves + (threadIdx.x >> 6);
-  const int64_t q0 = blk * 32;
-  if (q0 >= A.n_points) return;
   const int64_t nblk = A.qpad / 32;
-  const int64_t q = q0 + pt;
-  const bool valid = q < A.n_points;
-  float pb[3] = {0.0f, 0.0f, 0.0f};
-  if (valid) {
-    pb[0] = (A.px[q] - A.cx) * A.inv_ext;
-    pb[1] = (A.py[q] - A.cy) * A.inv_ext;
-    pb[2] = (A.pz[q] - A.cz) * A.inv_ext;
-  }
-  // layer-0 input: K-block c holds features 16c + 8h + j
-  bf16x8 xin[8];
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    float v[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) v[j] = pe_feature(16 * c + 8 * h + j, pb);
-    xin[c] = pack8(v);
-    if (A.x0) A.x0[sv_x0(blk, c, lane)] = xin[c];
-  }
-#pragma unroll
-  for (int l = 0; l < 4; ++l) {
-    floatx16 acc[4];
-    const uint16_t* W = A.packed + fw_off(l);
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      acc[t] = floatx16{0};
-#pragma unroll
-      for (int c = 0; c < mlp_kb(l); ++c)
-        acc[t] = mfma_bf16(load_op(W, (t * mlp_kb(l) + c) * 64 + lane), xin[c], acc[t]);
+  const int64_t nreal = (A.n_points + 31) / 32;
+  for (int64_t blk = (int64_t)blockIdx.x * kFwdWaves + (threadIdx.x >> 6); blk < nreal;
+       blk += (int64_t)gridDim.x * kFwdWaves) {
+    // an opaque zero keeps the weight and bias reads inside the loop
+    // (hoisted, they would hold hundreds of registers)
+    int z = 0;
+    asm volatile("" : "+v"(z));
+    const bf16x8* W0 = wl + z;
+    const float* B0 = bl + z;
+    const int64_t q0 = blk * 32;
+    const int64_t q = q0 + pt;
+    const bool valid = q < A.n_points;
+    float pb[3] = {0.0f, 0.0f, 0.0f};
+    if (valid) {
+      pb[0] = (A.px[q] - A.cx) * A.inv_ext;
+      pb[1] = (A.py[q] - A.cy) * A.inv_ext;
+      pb[2] = (A.pz[q] - A.cz) * A.inv_ext;
     }
-    const float* b = A.prm + mlp_off_b(l);
+    // layer-0 input: K-block c holds features 16c + 8h + j
+    bf16x8 xin[8];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      float v[16];
+    for (int c = 0; c < 4; ++c) {
+      float v[8];
 #pragma unroll
-      for (int r = 0; r < 16; ++r) v[r] = fmaxf(acc[t][r] + b[32 * t + drow(r, h)], 0.0f);
-      xin[2 * t] = pack8(v);
-      xin[2 * t + 1] = pack8(v + 8);
+      for (int j = 0; j < 8; ++j) v[j] = pe_feature(16 * c + 8 * h + j, pb);
+      xin[c] = pack8(v);
+      if (A.x0) A.x0[sv_x0(blk, c, lane)] = xin[c];
     }
-    if (A.hs) {
 #pragma unroll
-      for (int c = 0; c < 8; ++c) A.hs[sv_h(nblk, l, blk, c, lane)] = xin[c];
+    for (int l = 0; l < 4; ++l) {
+      floatx16 acc[4];
+      const bf16x8* W = W0 + fw_off(l) / 8;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        acc[t] = floatx16{0};
+#pragma unroll
+        for (int c = 0; c < mlp_kb(l); ++c)
+          acc[t] = mfma_bf16(W[(t * mlp_kb(l) + c) * 64 + lane], xin[c], acc[t]);
+      }
+      const float* b = B0 + l * kMlpWidth;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        float v[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = fmaxf(acc[t][r] + b[32 * t + drow(r, h)], 0.0f);
+        xin[2 * t] = pack8(v);
+        xin[2 * t + 1] = pack8(v + 8);
+      }
+      if (A.hs) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) A.hs[sv_h(nblk, l, blk, c, lane)] = xin[c];
+      }
     }
-  }
-  floatx16 acc = floatx16{0};
-  const uint16_t* W4 = A.packed + fw_off(4);
+    floatx16 acc = floatx16{0};
+    const bf16x8* W4 = W0 + fw_off(4) / 8;
 #pragma unroll
-  for (int c = 0; c < 8; ++c) acc = mfma_bf16(load_op(W4, c * 64 + lane), xin[c], acc);
-  if (h == 0 && valid) {
-    const float* b4 = A.prm + mlp_off_b(4);
-    float o0 = acc[0] + b4[0], o1 = acc[1] + b4[1], o2 = acc[2] + b4[2];
-    A.out[q] = 1.0f + softplusf(o0);
-    A.out[A.n_points + q] = softplusf(o1);
-    A.out[2 * A.n_points + q] = sigmoidf(o2);
-    if (A.o) {
-      A.o[q] = o0;
-      A.o[A.qpad + q] = o1;
-      A.o[2 * A.qpad + q] = o2;
+    for (int c = 0; c < 8; ++c) acc = mfma_bf16(W4[c * 64 + lane], xin[c], acc);
+    if (h == 0 && valid) {
+      const float* b4 = B0 + 4 * kMlpWidth;
+      float o0 = acc[0] + b4[0], o1 = acc[1] + b4[1], o2 = acc[2] + b4[2];
+      A.out[q] = 1.0f + softplusf(o0);
+      A.out[A.n_points + q] = softplusf(o1);
+      A.out[2 * A.n_points + q] = sigmoidf(o2);
+      if (A.o) {
+        A.o[q] = o0;
+        A.o[A.qpad + q] = o1;
+        A.o[2 * A.qpad + q] = o2;
+      }
     }
   }
 }
@@ -530,9 +555,10 @@ rtc_status rtc_mlp_forward(const rtc_mlp* net, int64_t n_points, const float* px
   A.hs = saved ? reinterpret_cast<bf16x8*>(sv + (int64_t)kMlpIn0 * A.qpad) : nullptr;
   A.o = saved ? reinterpret_cast<float*>(sv + (int64_t)(kMlpIn0 + 4 * kMlpWidth) * A.qpad)
               : nullptr;
-  int64_t waves = (n_points + 31) / 32;
-  int64_t blocks = (waves + kMlpWaves - 1) / kMlpWaves;
-  hipLaunchKernelGGL(mlp_forward_kernel, dim3((unsigned)blocks), dim3(kMlpWaves * 64), 0, s, A);
+  const int64_t waves = (n_points + 31) / 32;
+  const int64_t need = (waves + kFwdWaves - 1) / kFwdWaves;
+  const int blocks = (int)(need < kFwdBlocks ? need : kFwdBlocks);
+  hipLaunchKernelGGL(mlp_forward_kernel, dim3(blocks), dim3(kFwdWaves * 64), 0, s, A);
   return check_launch(fn);
 }
 
