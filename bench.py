@@ -529,6 +529,58 @@ def summarize_traffic(fetch_csv, write_csv):
     print("\n".join(lines))
 
 
+def summarize_counters(*csvs):
+    """Per-kernel VALU / MFMA / LDS figures from rocprofv3 --pmc csv files
+    (any split of the counters over runs), averaged over the dispatches of
+    each (kernel, grid size); prints a markdown table.  GRBM_GUI_ACTIVE is
+    summed over the 8 XCDs (cycles = GRBM_GUI_ACTIVE / 8); a wave64 VALU
+    instruction takes 4 cycles of a 16-lane SIMD; 1,024 SIMDs."""
+    import collections
+    import csv
+    import re
+    per = collections.defaultdict(lambda: collections.defaultdict(list))
+    count = collections.Counter()
+    for path in csvs:
+        disp = collections.defaultdict(dict)
+        meta = {}
+        for r in csv.DictReader(open(path)):
+            d = int(r["Dispatch_Id"])
+            disp[d][r["Counter_Name"]] = disp[d].get(r["Counter_Name"], 0.0) + float(
+                r["Counter_Value"])
+            name = re.sub(r"\(.*", "", r["Kernel_Name"]).replace("void ", "")
+            meta[d] = (name, int(r["Grid_Size"]))
+        seen = collections.Counter(meta.values())
+        for key, n in seen.items():
+            count[key] = max(count[key], n)
+        for d, c in disp.items():
+            for k, v in c.items():
+                per[meta[d]][k].append(v)
+    simds = 1024
+    peak_per_cycle = PEAK_F16_MATRIX_TFLOPS * 1e12 / 2.4e9  # dense FP16 flops per clock
+    lines = ["| kernel | grid | dispatches | cycles (M) | VALU busy | MFMA busy | "
+             "MFMA flops issued / peak per cycle | VALU instr / wave | LDS instr / wave | "
+             "LDS bank-conflict cycles / LDS active |",
+             "|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    for (name, grid), c in sorted(per.items(), key=lambda kv: -np.mean(kv[1].get(
+            "GRBM_GUI_ACTIVE", [0]))):
+        a = {k: float(np.mean(v)) for k, v in c.items()}
+        cyc = a.get("GRBM_GUI_ACTIVE", 0.0) / 8.0
+        if cyc < 1e5:
+            continue
+        waves = a.get("SQ_WAVES", 0.0)
+        valu = 4.0 * a.get("SQ_INSTS_VALU", 0.0) / (simds * cyc)
+        mfma = a.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) / (simds * cyc)
+        mops = (a.get("SQ_INSTS_VALU_MFMA_MOPS_F16", 0.0)
+                + a.get("SQ_INSTS_VALU_MFMA_MOPS_BF16", 0.0)) * 512.0
+        lds_act = a.get("SQ_ACTIVE_INST_LDS", 0.0)
+        conf = a.get("SQ_LDS_BANK_CONFLICT", 0.0) / lds_act if lds_act else 0.0
+        lines.append(f"| `{name}` | {grid} | {count[(name, grid)]} | {cyc / 1e6:.2f} | "
+                     f"{valu:.2f} | {mfma:.2f} | {mops / cyc / peak_per_cycle:.3f} | "
+                     f"{a.get('SQ_INSTS_VALU', 0.0) / max(waves, 1):.0f} | "
+                     f"{a.get('SQ_INSTS_LDS', 0.0) / max(waves, 1):.0f} | {conf:.2f} |")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -550,9 +602,14 @@ def main():
                     help="start with a 2 GiB device copy (counter calibration)")
     ap.add_argument("--traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="summarise rocprofv3 FETCH_SIZE / WRITE_SIZE results and exit")
+    ap.add_argument("--counters", nargs="+", metavar="PMC_CSV",
+                    help="summarise rocprofv3 --pmc VALU / MFMA / LDS counters and exit")
     args = ap.parse_args()
     if args.traffic:
         summarize_traffic(*args.traffic)
+        return
+    if args.counters:
+        summarize_counters(*args.counters)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the hot path here is the one-GPU share of the "
