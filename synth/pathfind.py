@@ -16,10 +16,12 @@ _lib = None
 
 
 def build() -> str:
+    # a per-process temporary name: parallel test workers may build at once
+    tmp = f"{LIB}.tmp{os.getpid()}"
     cmd = ["g++", "-O3", "-march=x86-64-v2", "-std=c++17", "-fopenmp", "-fPIC", "-shared",
-           SRC, "-o", LIB + ".tmp"]
+           SRC, "-o", tmp]
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
+    os.replace(tmp, LIB)
     return LIB
 
 
