@@ -28,6 +28,12 @@ constexpr int fft_npass(int logn) { return logn / 4 + (logn % 4 != 0 ? 1 : 0); }
 // butterfly's R outputs contiguously (lane stride R values), which would put
 // every lane of a wave on the same bank; the pad spreads them.
 RTC_DEV constexpr int lds_pad(int i) { return i + (i >> 4); }
+// lds_pad(i + k S) = lds_pad(i) + lds_off(k S) wherever the passes use it:
+// for the reads i = j < B and S = B = N/R, for the writes i = d (below) and
+// S = Ns; in both cases the low four bits of i plus those of k S never carry
+// (S a multiple of 16, or S | 16 and i mod 16 + k S mod 16 < 16), so every
+// element's LDS slot is a per-lane base plus a compile-time offset.
+RTC_DEV constexpr int lds_off(int ks) { return ks + (ks >> 4); }
 constexpr int fft_lds_len(int n) { return n + n / 16; }
 // radix of pass p in the "inverse" order: 16, 16, ..., then the remainder
 constexpr int fft_radix(int logn, int p) {
@@ -190,9 +196,9 @@ RTC_DEV void fft_pass_r2l(float2 (*v)[R], float2* out, int Ns, int lane) {
     if (j < B) {
       fft_twiddle<R, SIGN, (N > 1024)>(v[i], j, Ns);
       dft<R, SIGN>(v[i]);
-      const int d = (j / Ns) * Ns * R + (j % Ns);
+      float2* o = out + lds_pad((j / Ns) * Ns * R + (j % Ns));
 #pragma unroll
-      for (int r = 0; r < R; ++r) out[lds_pad(d + r * Ns)] = v[i][r];
+      for (int r = 0; r < R; ++r) o[lds_off(r * Ns)] = v[i][r];
     }
   }
 }
@@ -205,8 +211,9 @@ RTC_DEV void fft_pass_l2r(const float2* in, float2 (*v)[R], int Ns, int lane) {
   for (int i = 0; i < fft_bpl(N, R, T); ++i) {
     const int j = lane + T * i;
     if (j < B) {
+      const float2* src = in + lds_pad(j);
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[i][r] = in[lds_pad(j + r * B)];
+      for (int r = 0; r < R; ++r) v[i][r] = src[lds_off(r * B)];
       fft_twiddle<R, SIGN, (N > 1024)>(v[i], j, Ns);
       dft<R, SIGN>(v[i]);
     }
@@ -261,9 +268,9 @@ RTC_DEV void fft_mid(float2* b0, float2* b1, int lane) {
     for (int i = 0; i < fft_bpl(N, R, T); ++i) {
       const int j = lane + T * i;
       if (j < N / R) {
-        const int d = (j / NS) * NS * R + (j % NS);
+        float2* o = out + lds_pad((j / NS) * NS * R + (j % NS));
 #pragma unroll
-        for (int r = 0; r < R; ++r) out[lds_pad(d + r * NS)] = v[i][r];
+        for (int r = 0; r < R; ++r) o[lds_off(r * NS)] = v[i][r];
       }
     }
     fft_mid<LOGN, SIGN, ORDER, P + 1, SY, T>(b0, b1, lane);
