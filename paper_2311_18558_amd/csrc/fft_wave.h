@@ -251,7 +251,7 @@ constexpr int seq_ns() {
 }
 
 // Pass P (1 <= P <= npass-2): LDS -> LDS, ping-ponging b0/b1 (pass 0
-// writes b0), then the following middle passes.
+// writes b0), then the following middle passes.  b0 == b1 runs in place.
 template <int LOGN, int SIGN, int ORDER, int P, class SY = BlockSync, int T = 64>
 RTC_DEV void fft_mid(float2* b0, float2* b1, int lane) {
   constexpr int NP = fft_npass(LOGN);
@@ -264,6 +264,7 @@ RTC_DEV void fft_mid(float2* b0, float2* b1, int lane) {
     SY::sync();
     float2 v[fft_bpl(N, R, T)][R];
     fft_pass_l2r<N, R, SIGN, T>(in, v, NS, lane);
+    if (in == out) SY::sync();  // one buffer: every read before any write
 #pragma unroll
     for (int i = 0; i < fft_bpl(N, R, T); ++i) {
       const int j = lane + T * i;

@@ -3,29 +3,40 @@
 // dL/dH kept on chip (registers and LDS) from the product that forms them to
 // the product that consumes them.
 //
-// One workgroup owns one link: NW = N/256 waves, wave w the 128 subcarrier
-// pairs q in [128 w, 128 w + 128) of all M <= 32 elements (the conjugate
-// pairs of cfr.hip: pair q joins n_hi = N/2 + q and n_lo = N/2 - 1 - q).
+// One workgroup owns one link: NW = N/128 waves (eight at 1,024
+// subcarriers, two per SIMD), wave w the 64 subcarrier pairs q in
+// [64 w, 64 w + 64) of all M <= 32 elements (the conjugate pairs of cfr.hip:
+// pair q joins n_hi = N/2 + q and n_lo = N/2 - 1 - q).  At two waves per
+// SIMD one wave's vector work overlaps the other's matrix products and
+// memory waits; a wave alone issues vector instructions at about two thirds
+// of the SIMD's rate.
 //
 //  1. Forward product (Eq. cfr_cont at the discrete subcarriers of
-//     Sec. II-A) as in cfr_kernel, with the MFMA operands swapped so the
-//     accumulators hold H transposed: lane l%32 is the element m, the
-//     register is the pair.  This is the layout the adjoint's product
-//     takes its dL/dH operand in, so no transpose is needed between them.
+//     Sec. II-A) with the MFMA operands swapped so the accumulators hold H
+//     transposed: lane l%32 is the element m, the register is the pair.  This
+//     is the layout the adjoint's product takes its dL/dH operand in, so no
+//     transpose is needed between them.  The path operand A'[i, m] =
+//     a_i g_m exp(j psi_i (m - c)) exp(-j 2 pi f_ref tau_i) is the same for
+//     every wave: the workgroup forms it once per stage of 64 paths, split
+//     into FP16 parts and stored in LDS in the MFMA's B-operand layout, and
+//     each wave reads it back with four 16-byte loads per 16 paths.  Each wave
+//     forms its own subcarrier operand exp(-j 2 pi t_q df tau_i) directly
+//     from FP64-reduced phases (no recurrence).
 //  2. Loss (coherent + power-delay-profile NMSE, normalised by the target
 //     statistics of the batch), per group of 8 element rows: the lanes of
-//     those rows write H in subcarrier order to LDS, each wave takes rows of
-//     the group through the one-wave FFT (tap domain, PDP, gradient, inverse
-//     FFT; targets H* and p* read from HBM), and writes dL/dH back in place;
-//     the owning lanes read their pairs back as S = dH[n_hi] + dH[n_lo] and
+//     those rows write H in pair order to LDS, each wave takes rows of the
+//     group through the one-wave FFT in place in the row's own slot (tap
+//     domain, PDP, gradient, inverse FFT; targets H* and p* read from HBM,
+//     H - H* parked in LDS), and writes dL/dH back to the slot; the owning
+//     lanes read their pairs back as S = dH[n_hi] + dH[n_lo] and
 //     D = dH[n_hi] - dH[n_lo], into the registers H occupied.
 //  3. Adjoint product G[m, p] = sum_q (S Re u_p(t_q) - j D Im u_p(t_q)) for
 //     each 32-path tile of the link, each wave over its own pairs: dL/dH is
 //     split into FP16 parts once (one power-of-two scale for the link, from
 //     its largest value), so per tile only the exponentials are generated;
-//     the waves' partial G meet in LDS and one wave (rotating) applies the
-//     path phase, array phases and gains: dL/da per path, dL/dg summed over
-//     the link's tiles in order (LDS, FP64), one row per link.
+//     the waves' partial G meet in LDS and each wave applies the path phase,
+//     array phases and gains to four element rows: dL/da per path, dL/dg
+//     summed over the link's tiles in order (FP64), one row per link.
 // The loss sums {sum|H-H*|^2, sum(p-p*)^2} of each (link, wave) and the
 // per-link dL/dg rows are reduced across the batch in a fixed order.
 #include <cmath>
@@ -42,17 +53,29 @@ template <int LOGN>
 struct Fz {
   static constexpr int N = 1 << LOGN;
   static constexpr int Q = N / 2;         // subcarrier pairs
-  static constexpr int TPW = 4;           // 32-pair tiles per wave
+  static constexpr int TPW = 2;           // 32-pair tiles per wave
   static constexpr int NW = Q / (32 * TPW);
   static constexpr int NCH = 2 * TPW;     // 16-pair chunks per wave
   static constexpr int GROUP = 8;         // element rows per loss group
   static constexpr int RPW = GROUP / NW;  // rows per wave per group
-  static constexpr int LDQ = Q + 16;      // LDS row stride (float4 per pair)
-  static_assert(NW >= 1 && GROUP % NW == 0, "1 to 8 waves");
+  static_assert(NW >= 1 && NW <= 8 && GROUP % NW == 0, "1 to 8 waves");
+  // loss: eight row slots of Q + Q/16 + 16 float4 (a slot is also its row's
+  // FFT buffer, N + N/16 float2 with the bank shift of row_slot0), then each
+  // wave's H - H* of its current row
+  static constexpr int LDQ = Q + Q / 16 + 16;
   static constexpr int ROW_BYTES = (GROUP * LDQ + 16) * 16;
-  static constexpr int GBUF_FLOATS = 64 * 32;  // one wave's partial G
+  static constexpr int DIFF_BYTES = NW * N * 8;
+  static constexpr int LOSS_BYTES = ROW_BYTES + DIFF_BYTES;
+  // adjoint: each wave's partial G of a tile, two tiles in flight
+  static constexpr int GBUF_FLOATS = 64 * 32;
   static constexpr int GBUF_BYTES = 2 * NW * GBUF_FLOATS * 4;
-  static constexpr int SMEM = ROW_BYTES > GBUF_BYTES ? ROW_BYTES : GBUF_BYTES;
+  // forward: one stage of 64 paths, the path operand in FP16 parts (4
+  // chunks x 4 parts x 64 lanes x 16 B) and the delays
+  static constexpr int ST_PATHS = 64;
+  static constexpr int ST_OPND_BYTES = (ST_PATHS / 16) * 4 * 64 * 16;
+  static constexpr int ST_BYTES = ST_OPND_BYTES + ST_PATHS * 8;
+  static constexpr int M2 = LOSS_BYTES > GBUF_BYTES ? LOSS_BYTES : GBUF_BYTES;
+  static constexpr int SMEM = M2 > ST_BYTES ? M2 : ST_BYTES;
 };
 
 struct FusedArgs {
@@ -72,21 +95,11 @@ struct FusedArgs {
   double* g_part;   // [L][M][2] per-link dL/dg, or null
 };
 
-// Start of element row rl's pair slots in the LDS row buffer: rows a stride
-// of Q + 16 slots apart plus a shift that puts the 8 rows and the two lane
-// halves of a register's writes on distinct banks.
+// Start of element row rl's pair slots in the LDS row buffer: rows LDQ
+// slots apart plus a shift that puts the 8 rows and the two lane halves of a
+// register's writes on distinct banks.
 RTC_DEV int row_slot0(int rl, int ldq) { return rl * ldq + (rl & 3) + 8 * (rl >> 2); }
 
-// Loss of one CFR row whose pair accumulators sit in LDS, in place.  Slot q
-// of `row` holds {Re X, Im X, Re Y, Im Y} of pair q (unscaled by `us`), so
-// H[N/2 + q] = X + jY and H[N/2 - 1 - q] = X - jY; on return it holds the
-// adjoint's operands {Re S, Im S, -Re D, Im D}, S = dH[N/2 + q] +
-// dH[N/2 - 1 - q], D = dH[N/2 + q] - dH[N/2 - 1 - q].  One wave; b0, b1 its
-// own FFT buffers.  The loss arithmetic is that of cfr_loss_wave_kernel with
-// a precomputed target PDP (loss.hip).  Element n = j + BA r of the first
-// FFT pass (lane j < BA) is pair j + BA (r - 8) (upper half, r >= 8) or
-// BA - 1 - j + BA (7 - r) (lower half) -- the mirror n -> N - 1 - n is lane
-// BA - 1 - j, register 15 - r.
 // Target data of one CFR row in the layouts the row's loss reads them in:
 // H* at the first FFT pass's elements, p* at the last pass's.
 template <int LOGN>
@@ -97,7 +110,7 @@ struct RowTargets {
   float2 t[16];
 };
 
-// the row's target CFR (prefetched a row ahead) ...
+// the row's target CFR ...
 template <int LOGN>
 __device__ __forceinline__ void load_row_targets(const FusedArgs& A, int64_t ridx, int lane,
                                                  RowTargets<LOGN>& T) {
@@ -130,18 +143,22 @@ __device__ __forceinline__ void load_row_pdp(const float* Pt, int64_t ridx, int 
 // of `row` holds {Re X, Im X, Re Y, Im Y} of pair q (unscaled by `us`), so
 // H[N/2 + q] = X + jY and H[N/2 - 1 - q] = X - jY; on return it holds the
 // adjoint's operands {Re S, Im S, -Re D, Im D}, S = dH[N/2 + q] +
-// dH[N/2 - 1 - q], D = dH[N/2 + q] - dH[N/2 - 1 - q].  One wave; b0, b1 its
-// own FFT buffers; the row's two loss sums, sum |H - H*|^2 and
-// sum (p - p*)^2, are added to `sums` (per lane, FP64; the normalisers come
-// from the targets' statistics).  The loss arithmetic is that of cfr_loss_wave_kernel with a
-// precomputed target PDP (loss.hip).  Element n = j + BA r of the first FFT
+// dH[N/2 - 1 - q], D = dH[N/2 + q] - dH[N/2 - 1 - q].  One wave; the slot is
+// also the FFT's buffer (each pass reads all its values before it writes,
+// and LDS operations of one wave complete in order, so one buffer serves
+// in place), `dbuf` (N values) holds H - H* across the transforms.  The
+// row's two loss sums, sum |H - H*|^2 and sum (p - p*)^2, are added to
+// `sums` (per lane, FP64; the normalisers come from the targets'
+// statistics).  The loss arithmetic is that of cfr_loss_wave_kernel with a
+// precomputed target PDP (loss.hip).  Lanes j >= N/16 (N < 1,024) hold no
+// elements and touch neither the slot nor dbuf.  Element n = j + BA r of the first FFT
 // pass (lane j < BA) is pair j + BA (r - 8) (upper half, r >= 8) or
 // BA - 1 - j + BA (7 - r) (lower half) -- the mirror n -> N - 1 - n is lane
 // BA - 1 - j, register 15 - r.
 template <int LOGN>
 __device__ __forceinline__ void fused_loss_row(float4* row, const RowTargets<LOGN>& T,
                                                const float* Pt, int64_t ridx, float us,
-                                               float2* b0, float2* b1, float gc, float gp,
+                                               float2* dbuf, float gc, float gp,
                                                double (&sums)[2], int lane_in) {
   // the FFT twiddles depend on the lane and the pass only; an opaque lane
   // index keeps the compiler from holding them across rows (and the group
@@ -159,7 +176,7 @@ __device__ __forceinline__ void fused_loss_row(float4* row, const RowTargets<LOG
   const bool act = BA == 64 || j < BA;
   float tp[JZ][RZ];
   load_row_pdp<LOGN>(Pt, ridx, lane, tp);
-  float2 vh[1][16], diff[16];
+  float2 vh[1][16];
   float ec = 0.0f;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
@@ -174,11 +191,14 @@ __device__ __forceinline__ void fused_loss_row(float4* row, const RowTargets<LOG
       }
     }
     vh[0][r] = h;
-    diff[r] = csub(h, T.t[r]);
-    ec += cabs2(diff[r]);
+    const float2 df = csub(h, T.t[r]);
+    ec += cabs2(df);
+    if (act) dbuf[r * BA + j] = df;
   }
+  float2* fb = reinterpret_cast<float2*>(row);
   float2 xh[JZ][RZ];
-  fft_full<LOGN, +1, +1, WaveSync>(vh, xh, b0, b1, lane);
+  WaveSync::sync();  // the row's reads are done before the transform writes
+  fft_full<LOGN, +1, +1, WaveSync>(vh, xh, fb, fb, lane);
   float ep = 0.0f;
 #pragma unroll
   for (int i = 0; i < JZ; ++i) {
@@ -196,13 +216,14 @@ __device__ __forceinline__ void fused_loss_row(float4* row, const RowTargets<LOG
   sums[0] += (double)ec;
   sums[1] += (double)ep;
   float2 G[1][16];
-  fft_full<LOGN, -1, -1, WaveSync>(xh, G, b0, b1, lane);
+  fft_full<LOGN, -1, -1, WaveSync>(xh, G, fb, fb, lane);
   // dL/dH = gc (H - H*) + G; pair slot j + BA r' takes its upper element
   // from this lane (register r' + 8) and its lower one from the mirror lane
   // (register 7 - r')
   float2 dh[16];
 #pragma unroll
-  for (int r = 0; r < 16; ++r) dh[r] = cadd(cscale(diff[r], gc), G[0][r]);
+  for (int r = 0; r < 16; ++r)
+    dh[r] = act ? cadd(cscale(dbuf[r * BA + j], gc), G[0][r]) : make_float2(0.0f, 0.0f);
   const int mir = BA - 1 - j;
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
@@ -217,8 +238,8 @@ template <int LOGN>
 __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs A) {
   using F = Fz<LOGN>;
   constexpr int N = F::N, NW = F::NW, TPW = F::TPW, NCH = F::NCH;
+  constexpr int NT = NW * 64;
   __shared__ __align__(16) char smem[F::SMEM];
-  __shared__ float2 fb[NW][2][fft_lds_len(N)];
   __shared__ float wmax[NW];
   __shared__ float2 dabuf[2][NW * 64];
   float4* rowbuf = reinterpret_cast<float4*>(smem);
@@ -233,9 +254,6 @@ __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs 
   const int64_t off0 = A.link_off[l];
   const int64_t off1 = A.link_off[l + 1];
   const int q_base = wv * 32 * TPW;
-  // targets of the wave's first loss row, loaded while the forward runs
-  RowTargets<LOGN> cur;
-  if (wv < M) load_row_targets<LOGN>(A, l * M + wv, lane, cur);
 
   // ------------------------------------------------------------ 1. forward
   // lane: element m = col (B operand A'), pair column col of each tile (A
@@ -248,66 +266,74 @@ __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs 
 #pragma unroll
     for (int k = 0; k < 4; ++k) acc[t][k] = floatx16{0};
   {
+    // the path operand: thread (m = col, path pair kp) forms A'[2 kp + e, m]
+    // for e = 0, 1 of each pass of 4 NW paths
     const int m = col;
     const float2 g_row = m < M ? A.g[m] : make_float2(0.0f, 0.0f);
     const double mc_cyc = ((double)m - A.cm) * kInv2Pi;
-    const double t_lane_df = ((double)(q_base + col) + A.t_off) * A.df;
-    const double df32 = 32.0 * A.df;
     const int sx = 14 - cfr_link_scale_exp(A.a, off0, off1, g_row, lane);
     const float2 gm = make_float2(ldexpf(g_row.x, sx), ldexpf(g_row.y, sx));
-    auto fetch = [&](int64_t c0, float2 (&pa)[8], float (&pp)[8], double (&pt)[8], double& tm) {
-      const int64_t p0 = c0 + 8 * half;
+    const int kp0 = threadIdx.x >> 5;  // path pair of the thread's first pass
+    constexpr int PPASS = 2 * (NT / 32);  // paths per pass
+    unsigned* opnd = reinterpret_cast<unsigned*>(smem);
+    double* tau_s = reinterpret_cast<double*>(smem + F::ST_OPND_BYTES);
+    // the wave's subcarrier phase slope per tile: t_q df for its lane's pair
+    double tq[TPW];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int64_t p = p0 + j;
-        const int64_t pc = p < off1 ? p : off1 - 1;
-        const float2 av = A.a[pc];
-        pa[j] = p < off1 ? av : make_float2(0.0f, 0.0f);
-        pp[j] = A.psi[pc];
-        pt[j] = A.tau[pc];
-      }
-      const int64_t pm = p0 + (col & 7);
-      tm = A.tau[pm < off1 ? pm : off1 - 1];
-    };
-    auto operands = [&](const float2 (&pa)[8], const float (&pp)[8], const double (&pt)[8],
-                        double tm, float (&ar)[8], float (&ai)[8], float2 (&uv)[8],
-                        float2 (&wvv)[8]) {
-      const float2 wm = expm2pi_f64_hw(df32 * tm);
+    for (int t = 0; t < TPW; ++t) tq[t] = ((double)(q_base + 32 * t + col) + A.t_off) * A.df;
+    for (int64_t s0 = off0; s0 < off1; s0 += F::ST_PATHS) {
+      __syncthreads();  // the previous stage's operands are consumed
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const float2 ph = expm2pi_f64_hw(fma(A.fref, pt[j], -(double)pp[j] * mc_cyc));
-        const float2 b = cmul(cmul(pa[j], gm), ph);
-        ar[j] = b.x;
-        ai[j] = b.y;
-        uv[j] = expm2pi_f64_hw(t_lane_df * pt[j]);
-        const int src = (lane & 32) + j;
-        wvv[j] = make_float2(__shfl(wm.x, src, 64), __shfl(wm.y, src, 64));
+      for (int ps = 0; ps < F::ST_PATHS / PPASS; ++ps) {
+        const int k = 2 * (kp0 + (NT / 32) * ps);  // first of the two paths (even)
+        float re[2], im[2];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int64_t p = s0 + k + e;
+          float2 b = make_float2(0.0f, 0.0f);
+          if (p < off1) {
+            const float2 ph = expm2pi_f64_hw(fma(A.fref, A.tau[p], -(double)A.psi[p] * mc_cyc));
+            b = cmul(cmul(A.a[p], gm), ph);
+          }
+          re[e] = b.x;
+          im[e] = b.y;
+        }
+        // B-operand slot: chunk c = k / 16, lane m + 32 ((k % 16) / 8),
+        // element (k % 8) of the part's 8-vector; parts re_h, re_l, im_h, im_l
+        const unsigned wr = pack_f16(re[0], re[1]);
+        const unsigned wi = pack_f16(im[0], im[1]);
+        const unsigned lr = pack_f16(sub_f16<true>(re[0], wr), sub_f16<false>(re[1], wr));
+        const unsigned li = pack_f16(sub_f16<true>(im[0], wi), sub_f16<false>(im[1], wi));
+        const int c = k >> 4;
+        const int sl = m + 32 * ((k & 15) >> 3);
+        const int w32 = (k & 7) >> 1;  // 32-bit word within the 16-byte vector
+        opnd[((c * 4 + 0) * 64 + sl) * 4 + w32] = wr;
+        opnd[((c * 4 + 1) * 64 + sl) * 4 + w32] = lr;
+        opnd[((c * 4 + 2) * 64 + sl) * 4 + w32] = wi;
+        opnd[((c * 4 + 3) * 64 + sl) * 4 + w32] = li;
       }
-    };
-    if (off0 < off1) {
-      float ar[8], ai[8];
-      float2 uv[8], wvv[8];
-      {
-        float2 pa[8];
-        float pp[8];
-        double pt[8], tm;
-        fetch(off0, pa, pp, pt, tm);
-        operands(pa, pp, pt, tm, ar, ai, uv, wvv);
+      if (threadIdx.x < F::ST_PATHS) {
+        const int64_t p = s0 + threadIdx.x;
+        tau_s[threadIdx.x] = p < off1 ? A.tau[p] : 0.0;  // zero operand rows: any finite phase
       }
-      for (int64_t c0 = off0; c0 < off1; c0 += 16) {
-        float2 pa[8];
-        float pp[8];
-        double pt[8], tm;
-        fetch(c0 + 16, pa, pp, pt, tm);
-        const Split2 AR = split2(ar), AI = split2(ai);
+      __syncthreads();
+      const int nch = (int)min((int64_t)(F::ST_PATHS / 16), (off1 - s0 + 15) >> 4);
+      for (int c = 0; c < nch; ++c) {
+        const u32x4* ob = reinterpret_cast<const u32x4*>(opnd) + (c * 4) * 64 + lane;
+        Split2 AR, AI;
+        AR.h = __builtin_bit_cast(halfx8, ob[0]);
+        AR.l = __builtin_bit_cast(halfx8, ob[64]);
+        AI.h = __builtin_bit_cast(halfx8, ob[128]);
+        AI.l = __builtin_bit_cast(halfx8, ob[192]);
+        const double* tp = tau_s + 16 * c + 8 * half;
 #pragma unroll
         for (int t = 0; t < TPW; ++t) {
           float ur[8], ui[8];
 #pragma unroll
           for (int j = 0; j < 8; ++j) {
-            if (t > 0) uv[j] = cmul(uv[j], wvv[j]);
-            ur[j] = uv[j].x;
-            ui[j] = uv[j].y;
+            const float2 u = expm2pi_f64_hw(tq[t] * tp[j]);
+            ur[j] = u.x;
+            ui[j] = u.y;
           }
           const Split2 UR = split2(ur), UI = split2(ui);
           acc[t][0] = mac3(UR, AR, acc[t][0]);
@@ -315,7 +341,6 @@ __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs 
           acc[t][2] = mac3(UI, AR, acc[t][2]);
           acc[t][3] = mac3(UI, AI, acc[t][3]);
         }
-        operands(pa, pp, pt, tm, ar, ai, uv, wvv);
       }
     }
     unscale = ldexpf(1.0f, -sx);
@@ -323,15 +348,15 @@ __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs 
 
   // --------------------------------------------------------------- 2. loss
   // the wave's rows: k -> element row 8 (k / RPW) + wv + NW (k % RPW); the
-  // rows that exist (< M) are a prefix.  Row k + 1's targets load while row
-  // k is transformed (row 0's during the forward product).
+  // rows that exist (< M) are a prefix
   const float gc = (float)(2.0 * (double)A.w_coh / A.Z[0]);
   const float gp = (float)(4.0 * (double)A.w_pdp / (A.Z[1] * (double)N));
   const int n_groups = (M + 7) >> 3;
   auto row_of = [&](int k) { return 8 * (k / F::RPW) + wv + NW * (k % F::RPW); };
+  float2* dbuf = reinterpret_cast<float2*>(smem + F::ROW_BYTES) + wv * N;
   double sums[2] = {0.0, 0.0};
   for (int grp = 0; grp < n_groups; ++grp) {
-    __syncthreads();  // the previous group's read-back is done
+    __syncthreads();  // the forward's stage buffer, or the previous group's read-back, is done
     if ((col >> 3) == grp) {
       float4* row = rowbuf + row_slot0(col & 7, F::LDQ);
 #pragma unroll
@@ -345,15 +370,12 @@ __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs 
     __syncthreads();
 #pragma unroll 1
     for (int i = 0; i < F::RPW; ++i) {
-      const int k = grp * F::RPW + i;
-      const int mrow = row_of(k);
+      const int mrow = row_of(grp * F::RPW + i);
       if (mrow < M) {
-        RowTargets<LOGN> nxt;
-        const int mnext = row_of(k + 1);
-        if (mnext < M) load_row_targets<LOGN>(A, l * M + mnext, lane, nxt);
-        fused_loss_row<LOGN>(rowbuf + row_slot0(mrow & 7, F::LDQ), cur, A.Pt, l * M + mrow,
-                             unscale, fb[wv][0], fb[wv][1], gc, gp, sums, lane);
-        cur = nxt;
+        RowTargets<LOGN> tg;
+        load_row_targets<LOGN>(A, l * M + mrow, lane, tg);
+        fused_loss_row<LOGN>(rowbuf + row_slot0(mrow & 7, F::LDQ), tg, A.Pt, l * M + mrow,
+                             unscale, dbuf, gc, gp, sums, lane);
       }
     }
     __syncthreads();
@@ -425,13 +447,16 @@ __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs 
     DI[c] = split2(di);
   }
 
-  // The epilogue of a tile is split over the waves by element rows: wave w
-  // takes the row groups g4 in [G4W w, G4W (w + 1)) (rows 8 g4 + 4 half +
-  // 0..3, registers 4 g4 .. 4 g4 + 3 of G).  Its dL/dg rows accumulate in
-  // the wave's registers (FP64, tiles in order); each half-wave's share of
-  // dL/da goes to LDS and the wave that finishes the tile adds the shares in
-  // order after the next barrier.
-  constexpr int G4W = 4 / NW;
+  // The epilogue of a tile is split over the waves by element rows: with up
+  // to four waves, wave w takes the row groups g4 in [G4W w, G4W (w + 1))
+  // (rows 8 g4 + 4 half + 0..3, registers 4 g4 .. 4 g4 + 3 of G); with eight,
+  // wave w takes rows 8 (w/2) + 4 (w%2) + 0..3, in the lanes of half w%2.
+  // Its dL/dg rows accumulate in the wave's registers (FP64, tiles in
+  // order); each half-wave's share of dL/da goes to LDS and the wave that
+  // finishes the tile adds the shares in order after the next barrier.
+  constexpr int G4W = NW <= 4 ? 4 / NW : 1;
+  const bool ep_act = NW <= 4 || half == (wv & 1);
+  auto g4_of = [&](int a) { return NW <= 4 ? G4W * wv + a : (wv >> 1); };
   double dgw[G4W][4][2];
 #pragma unroll
   for (int a = 0; a < G4W; ++a)
@@ -504,7 +529,7 @@ __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs 
     float2 da = make_float2(0.0f, 0.0f);
 #pragma unroll
     for (int a = 0; a < G4W; ++a) {
-      const int g4 = G4W * wv + a;
+      const int g4 = g4_of(a);
       const int mrow0 = 8 * g4 + 4 * half;
       float2 ph = expm2pi_f64_hw(psi_cyc * ((double)mrow0 - A.cm));  // exp(-j psi (m - c))
 #pragma unroll
@@ -530,18 +555,18 @@ __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs 
     }
     // the half-wave's share of dL/da (its rows of the path), added in order
     // by the wave that finishes the tile
-    dabuf[T & 1][wv * 64 + lane] = da;
+    dabuf[T & 1][wv * 64 + lane] = ep_act ? da : make_float2(0.0f, 0.0f);
   }
   __syncthreads();  // the last tile's shares are in LDS; every epilogue is done
   if (n_tiles > 0 && wv == (n_tiles - 1) % NW) finish_da(n_tiles - 1);
   if (A.g_part) {
     // this wave's dL/dg rows of the link (disjoint across waves)
-    if (col == 0) {
+    if (col == 0 && ep_act) {
 #pragma unroll
       for (int a = 0; a < G4W; ++a)
 #pragma unroll
         for (int qq = 0; qq < 4; ++qq) {
-          const int mrow = 8 * (G4W * wv + a) + 4 * half + qq;
+          const int mrow = 8 * g4_of(a) + 4 * half + qq;
           if (mrow < M) {
             A.g_part[(l * M + mrow) * 2 + 0] = dgw[a][qq][0];
             A.g_part[(l * M + mrow) * 2 + 1] = dgw[a][qq][1];
@@ -572,7 +597,7 @@ bool fused_supported(const rtc_radio* r) {
 }
 
 // waves per workgroup of the fused kernel for n_sc subcarriers
-static int fused_waves(int n_sc) { return n_sc / 256; }
+static int fused_waves(int n_sc) { return n_sc / 128; }
 
 // Workspace: loss sums [L*NW][2] | their reduction tmp | sums [2] |
 // per-link dL/dg [L][M][2] | its reduction tmp | reduced [M][2] (doubles).
