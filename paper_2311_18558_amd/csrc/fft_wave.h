@@ -186,15 +186,50 @@ RTC_DEV void fft_twiddle(float2* v, int j, int Ns) {
   }
 }
 
+// The same twiddles read from a table tw[k] = exp(+j 2 pi k / N), k < N
+// (LDS, filled by fft_tw_fill): w^r = tw[r (j mod Ns) N / (Ns R)] (index
+// below N), conjugated for SIGN < 0.  One read and one address add per
+// element instead of a product of the recurrence, and no error growth.
+template <int N, int R, int SIGN>
+RTC_DEV void fft_twiddle_tab(float2* v, int j, int Ns, const float2* tw) {
+  if (Ns == 1) return;
+  const int step = (j % Ns) * (N / (Ns * R));
+  int k = 0;
+#pragma unroll
+  for (int r = 1; r < R; ++r) {
+    k += step;
+    const float2 w = tw[k];
+    v[r] = SIGN > 0 ? cmul(v[r], w) : cmulc(w, v[r]);
+  }
+}
+
+template <int N>
+RTC_DEV void fft_tw_fill(float2* tw, int tid, int nthreads) {
+  for (int k = tid; k < N; k += nthreads) {
+    float s, c;
+    sincos2pi((float)k / (float)N, &s, &c);  // k / N exact
+    tw[k] = make_float2(c, s);
+  }
+}
+
+template <int N, int R, int SIGN, bool TAB>
+RTC_DEV void fft_twiddle_any(float2* v, int j, int Ns, const float2* tw) {
+  if constexpr (TAB)
+    fft_twiddle_tab<N, R, SIGN>(v, j, Ns, tw);
+  else
+    fft_twiddle<R, SIGN, (N > 1024)>(v, j, Ns);
+}
+
 // Pass from registers (v[i][r] of butterfly j = lane + T i) to LDS `out`.
-template <int N, int R, int SIGN, int T = 64>
-RTC_DEV void fft_pass_r2l(float2 (*v)[R], float2* out, int Ns, int lane) {
+template <int N, int R, int SIGN, int T = 64, bool TAB = false>
+RTC_DEV void fft_pass_r2l(float2 (*v)[R], float2* out, int Ns, int lane,
+                          const float2* tw = nullptr) {
   constexpr int B = N / R;
 #pragma unroll
   for (int i = 0; i < fft_bpl(N, R, T); ++i) {
     const int j = lane + T * i;
     if (j < B) {
-      fft_twiddle<R, SIGN, (N > 1024)>(v[i], j, Ns);
+      fft_twiddle_any<N, R, SIGN, TAB>(v[i], j, Ns, tw);
       dft<R, SIGN>(v[i]);
       float2* o = out + lds_pad((j / Ns) * Ns * R + (j % Ns));
 #pragma unroll
@@ -204,8 +239,9 @@ RTC_DEV void fft_pass_r2l(float2 (*v)[R], float2* out, int Ns, int lane) {
 }
 
 // Pass from LDS `in` to registers v[i][r] (no store).
-template <int N, int R, int SIGN, int T = 64>
-RTC_DEV void fft_pass_l2r(const float2* in, float2 (*v)[R], int Ns, int lane) {
+template <int N, int R, int SIGN, int T = 64, bool TAB = false>
+RTC_DEV void fft_pass_l2r(const float2* in, float2 (*v)[R], int Ns, int lane,
+                          const float2* tw = nullptr) {
   constexpr int B = N / R;
 #pragma unroll
   for (int i = 0; i < fft_bpl(N, R, T); ++i) {
@@ -214,7 +250,7 @@ RTC_DEV void fft_pass_l2r(const float2* in, float2 (*v)[R], int Ns, int lane) {
       const float2* src = in + lds_pad(j);
 #pragma unroll
       for (int r = 0; r < R; ++r) v[i][r] = src[lds_off(r * B)];
-      fft_twiddle<R, SIGN, (N > 1024)>(v[i], j, Ns);
+      fft_twiddle_any<N, R, SIGN, TAB>(v[i], j, Ns, tw);
       dft<R, SIGN>(v[i]);
     }
   }
@@ -252,8 +288,9 @@ constexpr int seq_ns() {
 
 // Pass P (1 <= P <= npass-2): LDS -> LDS, ping-ponging b0/b1 (pass 0
 // writes b0), then the following middle passes.  b0 == b1 runs in place.
-template <int LOGN, int SIGN, int ORDER, int P, class SY = BlockSync, int T = 64>
-RTC_DEV void fft_mid(float2* b0, float2* b1, int lane) {
+template <int LOGN, int SIGN, int ORDER, int P, class SY = BlockSync, int T = 64,
+          bool TAB = false>
+RTC_DEV void fft_mid(float2* b0, float2* b1, int lane, const float2* tw = nullptr) {
   constexpr int NP = fft_npass(LOGN);
   if constexpr (P <= NP - 2) {
     constexpr int N = 1 << LOGN;
@@ -263,7 +300,7 @@ RTC_DEV void fft_mid(float2* b0, float2* b1, int lane) {
     float2* out = (P & 1) ? b1 : b0;
     SY::sync();
     float2 v[fft_bpl(N, R, T)][R];
-    fft_pass_l2r<N, R, SIGN, T>(in, v, NS, lane);
+    fft_pass_l2r<N, R, SIGN, T, TAB>(in, v, NS, lane, tw);
     if (in == out) SY::sync();  // one buffer: every read before any write
 #pragma unroll
     for (int i = 0; i < fft_bpl(N, R, T); ++i) {
@@ -274,18 +311,19 @@ RTC_DEV void fft_mid(float2* b0, float2* b1, int lane) {
         for (int r = 0; r < R; ++r) o[lds_off(r * NS)] = v[i][r];
       }
     }
-    fft_mid<LOGN, SIGN, ORDER, P + 1, SY, T>(b0, b1, lane);
+    fft_mid<LOGN, SIGN, ORDER, P + 1, SY, T, TAB>(b0, b1, lane, tw);
   }
 }
 
 // Whole transform: vin holds the first pass's inputs (butterfly j = lane +
 // T i, element r = x[j + r N/R_first]); vout receives the last pass's
 // outputs (element r of butterfly j = X[j + r N/R_last]).  b0, b1: two LDS
-// buffers of fft_lds_len(N) values; lane = the thread's index among the T.
-template <int LOGN, int SIGN, int ORDER, class SY = BlockSync, int T = 64, int J0, int R0,
-          int JL, int RL>
+// buffers of fft_lds_len(N) values; lane = the thread's index among the T;
+// with TAB the twiddles come from the table tw (fft_twiddle_tab).
+template <int LOGN, int SIGN, int ORDER, class SY = BlockSync, int T = 64, bool TAB = false,
+          int J0, int R0, int JL, int RL>
 RTC_DEV void fft_full(float2 (&vin)[J0][R0], float2 (&vout)[JL][RL], float2* b0, float2* b1,
-                      int lane) {
+                      int lane, const float2* tw = nullptr) {
   constexpr int N = 1 << LOGN;
   constexpr int NP = fft_npass(LOGN);
   static_assert(R0 == seq_radix<LOGN, ORDER, 0>(), "first-pass layout");
@@ -301,12 +339,12 @@ RTC_DEV void fft_full(float2 (&vin)[J0][R0], float2 (&vout)[JL][RL], float2* b0,
       }
     }
   } else {
-    fft_pass_r2l<N, R0, SIGN, T>(vin, b0, 1, lane);
-    fft_mid<LOGN, SIGN, ORDER, 1, SY, T>(b0, b1, lane);
+    fft_pass_r2l<N, R0, SIGN, T, TAB>(vin, b0, 1, lane, tw);
+    fft_mid<LOGN, SIGN, ORDER, 1, SY, T, TAB>(b0, b1, lane, tw);
     constexpr int PL = NP - 1;
     const float2* in = ((PL - 1) & 1) ? b1 : b0;
     SY::sync();
-    fft_pass_l2r<N, RL, SIGN, T>(in, vout, seq_ns<LOGN, ORDER, PL>(), lane);
+    fft_pass_l2r<N, RL, SIGN, T, TAB>(in, vout, seq_ns<LOGN, ORDER, PL>(), lane, tw);
     SY::sync();
   }
 }

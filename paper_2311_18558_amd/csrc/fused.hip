@@ -146,7 +146,8 @@ __device__ __forceinline__ void load_row_pdp(const float* Pt, int64_t ridx, int 
 // dH[N/2 - 1 - q], D = dH[N/2 + q] - dH[N/2 - 1 - q].  One wave; the slot is
 // also the FFT's buffer (each pass reads all its values before it writes,
 // and LDS operations of one wave complete in order, so one buffer serves
-// in place), `dbuf` (N values) holds H - H* across the transforms.  The
+// in place), `dbuf` (N values) holds H - H* across the transforms, `tw` is
+// the twiddle table.  The
 // row's two loss sums, sum |H - H*|^2 and sum (p - p*)^2, are added to
 // `sums` (per lane, FP64; the normalisers come from the targets'
 // statistics).  The loss arithmetic is that of cfr_loss_wave_kernel with a
@@ -158,8 +159,8 @@ __device__ __forceinline__ void load_row_pdp(const float* Pt, int64_t ridx, int 
 template <int LOGN>
 __device__ __forceinline__ void fused_loss_row(float4* row, const RowTargets<LOGN>& T,
                                                const float* Pt, int64_t ridx, float us,
-                                               float2* dbuf, float gc, float gp,
-                                               double (&sums)[2], int lane_in) {
+                                               float2* dbuf, const float2* tw, float gc,
+                                               float gp, double (&sums)[2], int lane_in) {
   // the FFT twiddles depend on the lane and the pass only; an opaque lane
   // index keeps the compiler from holding them across rows (and the group
   // loop), where they would take registers the loop needs
@@ -198,7 +199,7 @@ __device__ __forceinline__ void fused_loss_row(float4* row, const RowTargets<LOG
   float2* fb = reinterpret_cast<float2*>(row);
   float2 xh[JZ][RZ];
   WaveSync::sync();  // the row's reads are done before the transform writes
-  fft_full<LOGN, +1, +1, WaveSync>(vh, xh, fb, fb, lane);
+  fft_full<LOGN, +1, +1, WaveSync, 64, true>(vh, xh, fb, fb, lane, tw);
   float ep = 0.0f;
 #pragma unroll
   for (int i = 0; i < JZ; ++i) {
@@ -216,7 +217,7 @@ __device__ __forceinline__ void fused_loss_row(float4* row, const RowTargets<LOG
   sums[0] += (double)ec;
   sums[1] += (double)ep;
   float2 G[1][16];
-  fft_full<LOGN, -1, -1, WaveSync>(xh, G, fb, fb, lane);
+  fft_full<LOGN, -1, -1, WaveSync, 64, true>(xh, G, fb, fb, lane, tw);
   // dL/dH = gc (H - H*) + G; pair slot j + BA r' takes its upper element
   // from this lane (register r' + 8) and its lower one from the mirror lane
   // (register 7 - r')
@@ -242,6 +243,7 @@ __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs 
   __shared__ __align__(16) char smem[F::SMEM];
   __shared__ float wmax[NW];
   __shared__ float2 dabuf[2][NW * 64];
+  __shared__ float2 twtab[N];  // FFT twiddles exp(j 2 pi k / N)
   float4* rowbuf = reinterpret_cast<float4*>(smem);
   float* gbuf = reinterpret_cast<float*>(smem);
 
@@ -254,6 +256,7 @@ __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs 
   const int64_t off0 = A.link_off[l];
   const int64_t off1 = A.link_off[l + 1];
   const int q_base = wv * 32 * TPW;
+  fft_tw_fill<N>(twtab, threadIdx.x, NT);  // read after the barriers below
 
   // ------------------------------------------------------------ 1. forward
   // lane: element m = col (B operand A'), pair column col of each tile (A
@@ -375,7 +378,7 @@ __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs 
         RowTargets<LOGN> tg;
         load_row_targets<LOGN>(A, l * M + mrow, lane, tg);
         fused_loss_row<LOGN>(rowbuf + row_slot0(mrow & 7, F::LDQ), tg, A.Pt, l * M + mrow,
-                             unscale, dbuf, gc, gp, sums, lane);
+                             unscale, dbuf, twtab, gc, gp, sums, lane);
       }
     }
     __syncthreads();
