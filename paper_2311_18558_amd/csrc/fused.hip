@@ -100,30 +100,32 @@ struct FusedArgs {
 // register's writes on distinct banks.
 RTC_DEV int row_slot0(int rl, int ldq) { return rl * ldq + (rl & 3) + 8 * (rl >> 2); }
 
-// Target data of one CFR row in the layouts the row's loss reads them in:
-// H* at the first FFT pass's elements, p* at the last pass's.
+// A row's target CFR H* straight from HBM into the wave's LDS buffer dbuf
+// (natural order, dbuf[n] = H*[n]), without passing through registers: N/128
+// direct-to-LDS loads of 16 bytes per lane, lane l of load i taking
+// H*[128 i + 2 l] and H*[128 i + 2 l + 1].  Issued a row ahead; the row's
+// first read of dbuf waits for them (the compiler counts the loads).
+template <int LOGN>
+__device__ __forceinline__ void prefetch_row_targets(const float2* Ht, int64_t ridx, float2* dbuf,
+                                                     int lane) {
+  constexpr int N = 1 << LOGN;
+  const float2* src = Ht + ridx * N + 2 * lane;
+#pragma unroll
+  for (int i = 0; i < N / 128; ++i)
+    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(src + 128 * i),
+                                     (__attribute__((address_space(3))) void*)(dbuf + 128 * i), 16,
+                                     0, 0);
+}
+
 template <int LOGN>
 struct RowTargets {
   static constexpr int NP = fft_npass(LOGN);
   static constexpr int RZ = fft_radix(LOGN, NP - 1);
   static constexpr int JZ = fft_bpl(1 << LOGN, RZ);
-  float2 t[16];
 };
 
-// the row's target CFR ...
-template <int LOGN>
-__device__ __forceinline__ void load_row_targets(const FusedArgs& A, int64_t ridx, int lane,
-                                                 RowTargets<LOGN>& T) {
-  constexpr int N = 1 << LOGN;
-  constexpr int BA = N / 16;
-  const float2* ts = A.Ht + ridx * N;
-#pragma unroll
-  for (int r = 0; r < 16; ++r)
-    T.t[r] = (BA == 64 || lane < BA) ? ts[lane + r * BA] : make_float2(0.0f, 0.0f);
-}
-
-// ... and its target PDP, loaded when the row starts (it is needed only
-// after the first transform)
+// The row's target PDP, loaded into registers when the row starts (it is
+// needed only after the first transform)
 template <int LOGN>
 __device__ __forceinline__ void load_row_pdp(const float* Pt, int64_t ridx, int lane,
                                              float (&p)[RowTargets<LOGN>::JZ][RowTargets<LOGN>::RZ]) {
@@ -146,8 +148,9 @@ __device__ __forceinline__ void load_row_pdp(const float* Pt, int64_t ridx, int 
 // dH[N/2 - 1 - q], D = dH[N/2 + q] - dH[N/2 - 1 - q].  One wave; the slot is
 // also the FFT's buffer (each pass reads all its values before it writes,
 // and LDS operations of one wave complete in order, so one buffer serves
-// in place), `dbuf` (N values) holds H - H* across the transforms, `tw` is
-// the twiddle table.  The
+// in place), `dbuf` (N values) comes in holding the row's H* (natural
+// order, prefetch_row_targets) and holds H - H* across the transforms, `tw`
+// is the twiddle table.  The
 // row's two loss sums, sum |H - H*|^2 and sum (p - p*)^2, are added to
 // `sums` (per lane, FP64; the normalisers come from the targets'
 // statistics).  The loss arithmetic is that of cfr_loss_wave_kernel with a
@@ -157,8 +160,8 @@ __device__ __forceinline__ void load_row_pdp(const float* Pt, int64_t ridx, int 
 // BA - 1 - j + BA (7 - r) (lower half) -- the mirror n -> N - 1 - n is lane
 // BA - 1 - j, register 15 - r.
 template <int LOGN>
-__device__ __forceinline__ void fused_loss_row(float4* row, const RowTargets<LOGN>& T,
-                                               const float* Pt, int64_t ridx, float us,
+__device__ __forceinline__ void fused_loss_row(float4* row, const float* Pt, int64_t ridx,
+                                               float us,
                                                float2* dbuf, const float2* tw, float gc,
                                                float gp, double (&sums)[2], int lane_in) {
   // the FFT twiddles depend on the lane and the pass only; an opaque lane
@@ -192,7 +195,7 @@ __device__ __forceinline__ void fused_loss_row(float4* row, const RowTargets<LOG
       }
     }
     vh[0][r] = h;
-    const float2 df = csub(h, T.t[r]);
+    const float2 df = csub(h, act ? dbuf[r * BA + j] : make_float2(0.0f, 0.0f));
     ec += cabs2(df);
     if (act) dbuf[r * BA + j] = df;
   }
@@ -257,6 +260,13 @@ __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs 
   const int64_t off1 = A.link_off[l + 1];
   const int q_base = wv * 32 * TPW;
   fft_tw_fill<N>(twtab, threadIdx.x, NT);  // read after the barriers below
+  // loss rows of this wave: k -> element row 8 (k / RPW) + wv + NW (k % RPW);
+  // the rows that exist (< M) are a prefix.  The first one's targets load
+  // into the wave's LDS buffer while the forward product runs (the buffer
+  // lies outside the forward's stage area).
+  auto row_of = [&](int k) { return 8 * (k / F::RPW) + wv + NW * (k % F::RPW); };
+  float2* dbuf = reinterpret_cast<float2*>(smem + F::ROW_BYTES) + wv * N;
+  if (row_of(0) < M) prefetch_row_targets<LOGN>(A.Ht, l * M + row_of(0), dbuf, lane);
 
   // ------------------------------------------------------------ 1. forward
   // lane: element m = col (B operand A'), pair column col of each tile (A
@@ -350,13 +360,9 @@ __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs 
   }
 
   // --------------------------------------------------------------- 2. loss
-  // the wave's rows: k -> element row 8 (k / RPW) + wv + NW (k % RPW); the
-  // rows that exist (< M) are a prefix
   const float gc = (float)(2.0 * (double)A.w_coh / A.Z[0]);
   const float gp = (float)(4.0 * (double)A.w_pdp / (A.Z[1] * (double)N));
   const int n_groups = (M + 7) >> 3;
-  auto row_of = [&](int k) { return 8 * (k / F::RPW) + wv + NW * (k % F::RPW); };
-  float2* dbuf = reinterpret_cast<float2*>(smem + F::ROW_BYTES) + wv * N;
   double sums[2] = {0.0, 0.0};
   for (int grp = 0; grp < n_groups; ++grp) {
     __syncthreads();  // the forward's stage buffer, or the previous group's read-back, is done
@@ -373,12 +379,14 @@ __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs 
     __syncthreads();
 #pragma unroll 1
     for (int i = 0; i < F::RPW; ++i) {
-      const int mrow = row_of(grp * F::RPW + i);
+      const int k = grp * F::RPW + i;
+      const int mrow = row_of(k);
       if (mrow < M) {
-        RowTargets<LOGN> tg;
-        load_row_targets<LOGN>(A, l * M + mrow, lane, tg);
-        fused_loss_row<LOGN>(rowbuf + row_slot0(mrow & 7, F::LDQ), tg, A.Pt, l * M + mrow,
+        fused_loss_row<LOGN>(rowbuf + row_slot0(mrow & 7, F::LDQ), A.Pt, l * M + mrow,
                              unscale, dbuf, twtab, gc, gp, sums, lane);
+        // the buffer's last reads are done: the next row's targets go in
+        const int mnext = row_of(k + 1);
+        if (mnext < M) prefetch_row_targets<LOGN>(A.Ht, l * M + mnext, dbuf, lane);
       }
     }
     __syncthreads();
@@ -477,10 +485,13 @@ __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs 
     }
   };
   const int n_tiles = (int)((off1 - off0 + 31) >> 5);
+  // the lane's path delay, a tile ahead (its phases start each tile)
+  double tau_nx = off0 + col < off1 ? A.tau[off0 + col] : 0.0;
   for (int T = 0; T < n_tiles; ++T) {
     const int64_t p = off0 + 32 * (int64_t)T + col;
     const bool ok = p < off1;
-    const double tau = ok ? A.tau[p] : 0.0;
+    const double tau = tau_nx;
+    tau_nx = p + 32 < off1 ? A.tau[p + 32] : 0.0;
     const float2 v1 = expm2pi_f64_hw(A.df * tau);
     const float2 v8 = expm2pi_f64_hw(8.0 * A.df * tau);
     const float2 v16 = expm2pi_f64_hw(16.0 * A.df * tau);
