@@ -12,21 +12,23 @@
 // ways: per link from its largest path coefficient in the forward product,
 // per wave from the running maximum of the dL/dH values read so far in the
 // adjoint.  A lane holds eight k values of its row (A) or column (B): in the
-// forward product k runs over paths, so lane l generates the A operand for
+// forward product k runs over paths, so lane l holds the A operand for
 // element row l%32 and the B operand for column l%32 over paths
-// 8(l/32)..+7 of a 16-path chunk.
+// 8(l/32)..+7 of a 16-path chunk.  The forward's A operand is the same for
+// every wave of a link and element block: the workgroup forms it once per
+// stage of paths and shares it through LDS.
 //
 // The forward product uses the symmetry of the subcarrier grid about its
 // midpoint: the exponentials of the subcarriers at offsets +t and -t from
 // it are conjugate up to a common per-path phase, which moves into the A
 // operand, so a complex-by-real product gives both subcarriers of a pair
 // (see cfr_pair_tile).  The subcarrier phases (thousands of cycles) are
-// reduced in FP64; within a wave, pair tile t+1 is tile t times
-// exp(-j 2 pi 32 df tau_i).
+// reduced in FP64 for every (pair, path) of the forward product.
 //
 // The adjoint G[m, i] = sum_n dLdH[m, n] conj(E[i, n]) is the same kind of
 // product with the subcarriers as the contraction axis: lane l reads eight
 // consecutive subcarrier pairs of its dL/dH row (see adj_wave).
+#include <algorithm>
 #include <cmath>
 
 #include "api_common.h"
@@ -36,8 +38,11 @@
 
 namespace rtc {
 
-constexpr int kCfrWaves = 4;   // waves per workgroup (forward)
-constexpr int kCfrPairTiles = 4;  // tiles of 32 subcarrier pairs per wave (forward)
+constexpr int kCfrWaves = 8;      // waves per workgroup at most (forward): two per SIMD
+constexpr int kCfrPairTiles = 2;  // tiles of 32 subcarrier pairs per wave (forward)
+constexpr int kCfrStage = 64;     // paths per stage of the shared path operand (forward)
+constexpr int kCfrOpndBytes = (kCfrStage / 16) * 4 * 64 * 16;  // FP16 parts, MFMA lane layout
+constexpr int kCfrStageBytes = kCfrOpndBytes + kCfrStage * 8;  // + the stage's delays
 constexpr int kAdjWaves = 4;   // waves per workgroup (adjoint)
 constexpr int kAdjTP = 2;      // 32-path tiles per wave (adjoint)
 
@@ -77,31 +82,39 @@ RTC_DEV void cfr_pair_tile(const Split2& AR, const Split2& AI, const Split2& UR,
   yi = mac3(AI, UI, yi);
 }
 
-// One wave per (link, 32-row element block, kCfrPairTiles x 32 pairs).
+// One workgroup of NW <= kCfrWaves waves per (link, 32-row element block,
+// NW x 64 subcarrier pairs): two waves per SIMD, each wave two 32-pair tiles.
+// Per stage of kCfrStage paths the workgroup forms the path operand A' once
+// (one (path pair, element) per thread), splits it into FP16 parts and stores
+// it in LDS in the lane layout of the MFMA operand; each wave reads it back
+// with four 16-byte loads per 16 paths and forms its subcarrier operand
+// u_i(t_q) directly from FP64-reduced phases (no recurrence, no shuffles).
 __global__ void __launch_bounds__(kCfrWaves * 64) cfr_kernel(CfrArgs A, float2* __restrict__ H) {
+  __shared__ __align__(16) char smem[kCfrStageBytes];
+  const int nt = blockDim.x;
   const int lane = threadIdx.x & 63;
   const int half = lane >> 5;
   const int col = lane & 31;
-  const int64_t wt = (int64_t)blockIdx.x * kCfrWaves + (threadIdx.x >> 6);
-  const int qchunk = (int)(wt % A.n_qchunk);
-  const int64_t rest = wt / A.n_qchunk;
+  const int wv = threadIdx.x >> 6;
+  const int64_t b = blockIdx.x;
+  const int qg = (int)(b % A.n_qchunk);
+  const int64_t rest = b / A.n_qchunk;
   const int mblk = (int)(rest % A.n_mblk);
   const int64_t l = rest / A.n_mblk;
-  if (l >= A.n_links) return;
-
+  const int q_base = (qg * (nt >> 6) + wv) * 32 * kCfrPairTiles;
   const int m = mblk * 32 + col;
   const float2 g_row = m < A.M ? A.g[m] : make_float2(0.0f, 0.0f);
   const double mc_cyc = ((double)m - A.cm) * kInv2Pi;
-  const int q_base = qchunk * 32 * kCfrPairTiles;
-  // t of the lane's pair column in tile 0, in subcarrier spacings
-  const double t_lane_df = ((double)(q_base + col) + A.t_off) * A.df;
-  const double df32 = 32.0 * A.df;
   const int64_t off0 = A.link_off[l];
   const int64_t off1 = A.link_off[l + 1];
   // the A operand carries the link's scale 2^sx (exact), removed on output
   const int sx = 14 - cfr_link_scale_exp(A.a, off0, off1, g_row, lane);
   const float2 gm = make_float2(ldexpf(g_row.x, sx), ldexpf(g_row.y, sx));
   const float unscale = ldexpf(1.0f, -sx);
+  // t_q df of the lane's pair column in each tile
+  double tq[kCfrPairTiles];
+#pragma unroll
+  for (int t = 0; t < kCfrPairTiles; ++t) tq[t] = ((double)(q_base + 32 * t + col) + A.t_off) * A.df;
 
   floatx16 acc[kCfrPairTiles][4];
 #pragma unroll
@@ -109,76 +122,66 @@ __global__ void __launch_bounds__(kCfrWaves * 64) cfr_kernel(CfrArgs A, float2* 
 #pragma unroll
     for (int k = 0; k < 4; ++k) acc[t][k] = floatx16{0};
 
-  // The lane's eight paths of a 16-path chunk.  Software pipeline: while
-  // the MFMAs of chunk k run, the wave loads the path data of chunk k+1 and
-  // generates its operands (the FP64-reduced exponentials), so the matrix
-  // cores are not idle during that VALU work.  Loads clamp to the link's
-  // last path (always a valid address) and padding paths get a = 0.
-  // tm: tau of path 8 half + (col & 7), whose tile step this lane computes
-  // for the others (the step depends on the path alone)
-  auto fetch = [&](int64_t c0, float2 (&pa)[8], float (&pp)[8], double (&pt)[8], double& tm) {
-    const int64_t p0 = c0 + 8 * half;
+  unsigned* opnd = reinterpret_cast<unsigned*>(smem);
+  double* tau_s = reinterpret_cast<double*>(smem + kCfrOpndBytes);
+  const int kp0 = threadIdx.x >> 5;  // path pair of the thread's first pass
+  const int ppass = 2 * (nt >> 5);   // paths per pass
+  for (int64_t s0 = off0; s0 < off1; s0 += kCfrStage) {
+    __syncthreads();  // the previous stage's operands are consumed
+    for (int k = 2 * kp0; k < kCfrStage; k += ppass) {
+      float re[2], im[2];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int64_t p = p0 + j;
-      const int64_t pc = p < off1 ? p : off1 - 1;
-      const float2 av = A.a[pc];
-      pa[j] = p < off1 ? av : make_float2(0.0f, 0.0f);
-      pp[j] = A.psi[pc];
-      pt[j] = A.tau[pc];
+      for (int e = 0; e < 2; ++e) {
+        const int64_t p = s0 + k + e;
+        float2 v = make_float2(0.0f, 0.0f);
+        if (p < off1) {
+          // exp(j psi_i (m - c)) c_i as one phase, in cycles
+          const float2 ph = expm2pi_f64_hw(fma(A.fref, A.tau[p], -(double)A.psi[p] * mc_cyc));
+          v = cmul(cmul(A.a[p], gm), ph);
+        }
+        re[e] = v.x;
+        im[e] = v.y;
+      }
+      // slot: chunk k / 16, lane (m % 32) + 32 ((k % 16) / 8), element k % 8
+      // of the part's 8-vector; parts re_h, re_l, im_h, im_l
+      const unsigned wr = pack_f16(re[0], re[1]);
+      const unsigned wi = pack_f16(im[0], im[1]);
+      const unsigned lr = pack_f16(sub_f16<true>(re[0], wr), sub_f16<false>(re[1], wr));
+      const unsigned li = pack_f16(sub_f16<true>(im[0], wi), sub_f16<false>(im[1], wi));
+      const int c = k >> 4;
+      const int sl = col + 32 * ((k & 15) >> 3);
+      const int w32 = (k & 7) >> 1;
+      opnd[((c * 4 + 0) * 64 + sl) * 4 + w32] = wr;
+      opnd[((c * 4 + 1) * 64 + sl) * 4 + w32] = lr;
+      opnd[((c * 4 + 2) * 64 + sl) * 4 + w32] = wi;
+      opnd[((c * 4 + 3) * 64 + sl) * 4 + w32] = li;
     }
-    const int64_t pm = p0 + (col & 7);
-    tm = A.tau[pm < off1 ? pm : off1 - 1];
-  };
-  // A operand A'[m, i] = a_i g_m exp(j psi_i (m - c)) c_i; B operand anchor
-  // u_i at the lane's pair column of tile 0 and the tile step
-  // w_i = exp(-j 2 pi 32 df tau_i), read from the lane that computed it
-  auto operands = [&](const float2 (&pa)[8], const float (&pp)[8], const double (&pt)[8],
-                      double tm, float (&ar)[8], float (&ai)[8], float2 (&uv)[8],
-                      float2 (&wv)[8]) {
-    const float2 wm = expm2pi_f64_hw(df32 * tm);
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      // exp(j psi_i (m - c)) c_i as one phase, in cycles
-      const float2 ph = expm2pi_f64_hw(fma(A.fref, pt[j], -(double)pp[j] * mc_cyc));
-      const float2 b = cmul(cmul(pa[j], gm), ph);
-      ar[j] = b.x;
-      ai[j] = b.y;
-      uv[j] = expm2pi_f64_hw(t_lane_df * pt[j]);
-      const int src = (lane & 32) + j;
-      wv[j] = make_float2(__shfl(wm.x, src, 64), __shfl(wm.y, src, 64));
+    for (int k = threadIdx.x; k < kCfrStage; k += nt) {
+      const int64_t p = s0 + k;
+      tau_s[k] = p < off1 ? A.tau[p] : 0.0;  // zero operand rows: any finite phase
     }
-  };
-  if (off0 < off1) {
-    float ar[8], ai[8];
-    float2 uv[8], wv[8];
-    {
-      float2 pa[8];
-      float pp[8];
-      double pt[8], tm;
-      fetch(off0, pa, pp, pt, tm);
-      operands(pa, pp, pt, tm, ar, ai, uv, wv);
-    }
-    for (int64_t c0 = off0; c0 < off1; c0 += 16) {
-      // next chunk (a clamped, unused load past the last chunk)
-      float2 pa[8];
-      float pp[8];
-      double pt[8], tm;
-      fetch(c0 + 16, pa, pp, pt, tm);
-      const Split2 AR = split2(ar), AI = split2(ai);
+    __syncthreads();
+    const int nch = (int)min((int64_t)(kCfrStage / 16), (off1 - s0 + 15) >> 4);
+    for (int c = 0; c < nch; ++c) {
+      const u32x4* ob = reinterpret_cast<const u32x4*>(opnd) + (c * 4) * 64 + lane;
+      Split2 AR, AI;
+      AR.h = __builtin_bit_cast(halfx8, ob[0]);
+      AR.l = __builtin_bit_cast(halfx8, ob[64]);
+      AI.h = __builtin_bit_cast(halfx8, ob[128]);
+      AI.l = __builtin_bit_cast(halfx8, ob[192]);
+      const double* tp = tau_s + 16 * c + 8 * half;
 #pragma unroll
       for (int t = 0; t < kCfrPairTiles; ++t) {
         float ur[8], ui[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-          if (t > 0) uv[j] = cmul(uv[j], wv[j]);
-          ur[j] = uv[j].x;
-          ui[j] = uv[j].y;
+          const float2 u = expm2pi_f64_hw(tq[t] * tp[j]);
+          ur[j] = u.x;
+          ui[j] = u.y;
         }
         const Split2 UR = split2(ur), UI = split2(ui);
         cfr_pair_tile(AR, AI, UR, UI, acc[t][0], acc[t][1], acc[t][2], acc[t][3]);
       }
-      operands(pa, pp, pt, tm, ar, ai, uv, wv);
     }
   }
 
@@ -739,7 +742,10 @@ extern "C" rtc_status rtc_cfr(const rtc_radio* radio, const rtc_paths* paths, co
   A.N = radio->n_sc;
   A.n_mblk = (A.M + 31) / 32;
   A.Q = (A.N + 1) / 2;
-  A.n_qchunk = (A.Q + 32 * kCfrPairTiles - 1) / (32 * kCfrPairTiles);
+  // waves per workgroup: enough for the pairs, at most kCfrWaves
+  const int pw = 32 * kCfrPairTiles;
+  const int nw = (int)std::min<int64_t>(kCfrWaves, (A.Q + pw - 1) / pw);
+  A.n_qchunk = (A.Q + nw * pw - 1) / (nw * pw);
   A.link_off = paths->link_off;
   A.a = reinterpret_cast<const float2*>(a);
   A.psi = psi;
@@ -758,11 +764,10 @@ extern "C" rtc_status rtc_cfr(const rtc_radio* radio, const rtc_paths* paths, co
                        as_stream(stream), A, reinterpret_cast<float2*>(H));
     return check_launch(fn);
   }
-  int64_t waves = (int64_t)A.n_links * A.n_mblk * A.n_qchunk;
-  int64_t blocks = (waves + kCfrWaves - 1) / kCfrWaves;
+  const int64_t blocks = (int64_t)A.n_links * A.n_mblk * A.n_qchunk;
   RTC_REQUIRE(blocks < (1ll << 31), RTC_ERR_RANGE, "%s: problem too large for one launch", fn);
-  hipLaunchKernelGGL(cfr_kernel, dim3((unsigned)blocks), dim3(kCfrWaves * 64), 0,
-                     as_stream(stream), A, reinterpret_cast<float2*>(H));
+  hipLaunchKernelGGL(cfr_kernel, dim3((unsigned)blocks), dim3(nw * 64), 0, as_stream(stream), A,
+                     reinterpret_cast<float2*>(H));
   return check_launch(fn);
 }
 
