@@ -143,9 +143,7 @@ __device__ __forceinline__ void load_row_pdp(const float* Pt, int64_t ridx, int 
 
 // Loss of one CFR row whose pair accumulators sit in LDS, in place.  Slot q
 // of `row` holds {Re X, Im X, Re Y, Im Y} of pair q (unscaled by `us`), so
-// H[N/2 + q] = X + jY and H[N/2 - 1 - q] = X - jY; on return it holds the
-// adjoint's operands {Re S, Im S, -Re D, Im D}, S = dH[N/2 + q] +
-// dH[N/2 - 1 - q], D = dH[N/2 + q] - dH[N/2 - 1 - q].  One wave; the slot is
+// H[N/2 + q] = X + jY and H[N/2 - 1 - q] = X - jY.  One wave; the slot is
 // also the FFT's buffer (each pass reads all its values before it writes,
 // and LDS operations of one wave complete in order, so one buffer serves
 // in place), `dbuf` (N values) comes in holding the row's H* (natural
@@ -153,8 +151,10 @@ __device__ __forceinline__ void load_row_pdp(const float* Pt, int64_t ridx, int 
 // is the twiddle table.  The
 // row's two loss sums, sum |H - H*|^2 and sum (p - p*)^2, are added to
 // `sums` (per lane, FP64; the normalisers come from the targets'
-// statistics).  The loss arithmetic is that of cfr_loss_wave_kernel with a
-// precomputed target PDP (loss.hip).  Lanes j >= N/16 (N < 1,024) hold no
+// statistics).  On return slot q holds {dL/dH[N/2 + q], dL/dH[N/2 - 1 - q]}
+// (the lanes that own the pair form S and D from them).  The loss
+// arithmetic is that of cfr_loss_wave_kernel with a precomputed target PDP
+// (loss.hip).  Lanes j >= N/16 (N < 1,024) hold no
 // elements and touch neither the slot nor dbuf.  Element n = j + BA r of the first FFT
 // pass (lane j < BA) is pair j + BA (r - 8) (upper half, r >= 8) or
 // BA - 1 - j + BA (7 - r) (lower half) -- the mirror n -> N - 1 - n is lane
@@ -221,20 +221,20 @@ __device__ __forceinline__ void fused_loss_row(float4* row, const float* Pt, int
   sums[1] += (double)ep;
   float2 G[1][16];
   fft_full<LOGN, -1, -1, WaveSync, 64, true>(xh, G, fb, fb, lane, tw);
-  // dL/dH = gc (H - H*) + G; pair slot j + BA r' takes its upper element
-  // from this lane (register r' + 8) and its lower one from the mirror lane
-  // (register 7 - r')
-  float2 dh[16];
+  // dL/dH = gc (H - H*) + G, each element into its pair's slot: the upper
+  // one (register r >= 8, pair j + BA (r - 8)) as the slot's first two
+  // floats, the lower one (r < 8, pair BA - 1 - j + BA (7 - r)) as its last
+  // two; the owners form S and D when they read the slots back
+  if (act) {
+    float2* half_slots = reinterpret_cast<float2*>(row);
 #pragma unroll
-  for (int r = 0; r < 16; ++r)
-    dh[r] = act ? cadd(cscale(dbuf[r * BA + j], gc), G[0][r]) : make_float2(0.0f, 0.0f);
-  const int mir = BA - 1 - j;
-#pragma unroll
-  for (int r = 0; r < 8; ++r) {
-    const float2 hi = dh[r + 8];
-    const float2 lo = make_float2(__shfl(dh[7 - r].x, mir, 64), __shfl(dh[7 - r].y, mir, 64));
-    if (act)
-      row[j + BA * r] = make_float4(hi.x + lo.x, hi.y + lo.y, lo.x - hi.x, hi.y - lo.y);
+    for (int r = 0; r < 16; ++r) {
+      const float2 dh = cadd(cscale(dbuf[r * BA + j], gc), G[0][r]);
+      if (r >= 8)
+        half_slots[2 * (j + BA * (r - 8))] = dh;
+      else
+        half_slots[2 * (BA - 1 - j + BA * (7 - r)) + 1] = dh;
+    }
   }
 }
 
@@ -391,7 +391,9 @@ __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs 
     }
     __syncthreads();
     if ((col >> 3) == grp) {
-      // rows m >= M hold X = Y = 0 (zero gains), read back as zero operands
+      // slot q: {dL/dH[N/2 + q], dL/dH[N/2 - 1 - q]} -> S = hi + lo,
+      // D = hi - lo; rows m >= M hold X = Y = 0 (zero gains), read back as
+      // zero operands
       const float4* row = rowbuf + row_slot0(col & 7, F::LDQ);
 #pragma unroll
       for (int t = 0; t < TPW; ++t)
@@ -399,10 +401,10 @@ __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs 
         for (int r = 0; r < 16; ++r) {
           const int q = q_base + 32 * t + 8 * (r >> 2) + 4 * half + (r & 3);
           const float4 v = row[q];
-          acc[t][0][r] = v.x;  // Re S
-          acc[t][1][r] = v.y;  // Im S
-          acc[t][2][r] = v.z;  // -Re D
-          acc[t][3][r] = v.w;  // Im D
+          acc[t][0][r] = v.x + v.z;  // Re S
+          acc[t][1][r] = v.y + v.w;  // Im S
+          acc[t][2][r] = v.z - v.x;  // -Re D
+          acc[t][3][r] = v.y - v.w;  // Im D
         }
     }
   }
