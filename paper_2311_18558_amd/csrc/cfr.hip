@@ -40,9 +40,8 @@ namespace rtc {
 
 constexpr int kCfrWaves = 8;      // waves per workgroup at most (forward): two per SIMD
 constexpr int kCfrPairTiles = 2;  // tiles of 32 subcarrier pairs per wave (forward)
-constexpr int kCfrStage = 64;     // paths per stage of the shared path operand (forward)
-constexpr int kCfrOpndBytes = (kCfrStage / 16) * 4 * 64 * 16;  // FP16 parts, MFMA lane layout
-constexpr int kCfrStageBytes = kCfrOpndBytes + kCfrStage * 8;  // + the stage's delays
+// the shared path operand's LDS stage at the largest workgroup (forward)
+constexpr int kCfrStageBytes = path_stage_bytes(kCfrWaves * 64);
 constexpr int kAdjWaves = 4;   // waves per workgroup (adjoint)
 constexpr int kAdjTP = 2;      // 32-path tiles per wave (adjoint)
 
@@ -84,11 +83,11 @@ RTC_DEV void cfr_pair_tile(const Split2& AR, const Split2& AI, const Split2& UR,
 
 // One workgroup of NW <= kCfrWaves waves per (link, 32-row element block,
 // NW x 64 subcarrier pairs): two waves per SIMD, each wave two 32-pair tiles.
-// Per stage of kCfrStage paths the workgroup forms the path operand A' once
-// (one (path pair, element) per thread), splits it into FP16 parts and stores
-// it in LDS in the lane layout of the MFMA operand; each wave reads it back
-// with four 16-byte loads per 16 paths and forms its subcarrier operand
-// u_i(t_q) directly from FP64-reduced phases (no recurrence, no shuffles).
+// Per stage of NW x 8 paths the workgroup forms the path operand A' once
+// (path_stage_store: four values per thread, FP16 parts in the MFMA lane
+// layout in LDS); each wave reads it back with four 16-byte loads per 16
+// paths and forms its subcarrier operand u_i(t_q) directly from FP64-reduced
+// phases (no recurrence, no shuffles).
 __global__ void __launch_bounds__(kCfrWaves * 64) cfr_kernel(CfrArgs A, float2* __restrict__ H) {
   __shared__ __align__(16) char smem[kCfrStageBytes];
   const int nt = blockDim.x;
@@ -123,52 +122,20 @@ __global__ void __launch_bounds__(kCfrWaves * 64) cfr_kernel(CfrArgs A, float2* 
     for (int k = 0; k < 4; ++k) acc[t][k] = floatx16{0};
 
   unsigned* opnd = reinterpret_cast<unsigned*>(smem);
-  double* tau_s = reinterpret_cast<double*>(smem + kCfrOpndBytes);
-  const int kp0 = threadIdx.x >> 5;  // path pair of the thread's first pass
-  const int ppass = 2 * (nt >> 5);   // paths per pass
-  for (int64_t s0 = off0; s0 < off1; s0 += kCfrStage) {
+  double* tau_s = reinterpret_cast<double*>(smem + path_stage_opnd_bytes(nt));
+  const int sp = path_stage_paths(nt);
+  PathFetch pf;
+  if (off0 < off1) path_fetch(A.a, A.psi, A.tau, off0, off1, nt, pf);
+  for (int64_t s0 = off0; s0 < off1; s0 += sp) {
     __syncthreads();  // the previous stage's operands are consumed
-    for (int k = 2 * kp0; k < kCfrStage; k += ppass) {
-      float re[2], im[2];
-#pragma unroll
-      for (int e = 0; e < 2; ++e) {
-        const int64_t p = s0 + k + e;
-        float2 v = make_float2(0.0f, 0.0f);
-        if (p < off1) {
-          // exp(j psi_i (m - c)) c_i as one phase, in cycles
-          const float2 ph = expm2pi_f64_hw(fma(A.fref, A.tau[p], -(double)A.psi[p] * mc_cyc));
-          v = cmul(cmul(A.a[p], gm), ph);
-        }
-        re[e] = v.x;
-        im[e] = v.y;
-      }
-      // slot: chunk k / 16, lane (m % 32) + 32 ((k % 16) / 8), element k % 8
-      // of the part's 8-vector; parts re_h, re_l, im_h, im_l
-      const unsigned wr = pack_f16(re[0], re[1]);
-      const unsigned wi = pack_f16(im[0], im[1]);
-      const unsigned lr = pack_f16(sub_f16<true>(re[0], wr), sub_f16<false>(re[1], wr));
-      const unsigned li = pack_f16(sub_f16<true>(im[0], wi), sub_f16<false>(im[1], wi));
-      const int c = k >> 4;
-      const int sl = col + 32 * ((k & 15) >> 3);
-      const int w32 = (k & 7) >> 1;
-      opnd[((c * 4 + 0) * 64 + sl) * 4 + w32] = wr;
-      opnd[((c * 4 + 1) * 64 + sl) * 4 + w32] = lr;
-      opnd[((c * 4 + 2) * 64 + sl) * 4 + w32] = wi;
-      opnd[((c * 4 + 3) * 64 + sl) * 4 + w32] = li;
-    }
-    for (int k = threadIdx.x; k < kCfrStage; k += nt) {
-      const int64_t p = s0 + k;
-      tau_s[k] = p < off1 ? A.tau[p] : 0.0;  // zero operand rows: any finite phase
-    }
+    path_stage_store(pf, s0, off1, nt, A.fref, mc_cyc, gm, col, opnd, tau_s);
     __syncthreads();
-    const int nch = (int)min((int64_t)(kCfrStage / 16), (off1 - s0 + 15) >> 4);
+    // the next stage's path data load while this stage's products run
+    if (s0 + sp < off1) path_fetch(A.a, A.psi, A.tau, s0 + sp, off1, nt, pf);
+    const int nch = (int)min((int64_t)(sp / 16), (off1 - s0 + 15) >> 4);
     for (int c = 0; c < nch; ++c) {
-      const u32x4* ob = reinterpret_cast<const u32x4*>(opnd) + (c * 4) * 64 + lane;
       Split2 AR, AI;
-      AR.h = __builtin_bit_cast(halfx8, ob[0]);
-      AR.l = __builtin_bit_cast(halfx8, ob[64]);
-      AI.h = __builtin_bit_cast(halfx8, ob[128]);
-      AI.l = __builtin_bit_cast(halfx8, ob[192]);
+      path_stage_read(opnd, c, lane, AR, AI);
       const double* tp = tau_s + 16 * c + 8 * half;
 #pragma unroll
       for (int t = 0; t < kCfrPairTiles; ++t) {
@@ -742,9 +709,11 @@ extern "C" rtc_status rtc_cfr(const rtc_radio* radio, const rtc_paths* paths, co
   A.N = radio->n_sc;
   A.n_mblk = (A.M + 31) / 32;
   A.Q = (A.N + 1) / 2;
-  // waves per workgroup: enough for the pairs, at most kCfrWaves
+  // waves per workgroup: enough for the pairs, at most kCfrWaves, and even
+  // (a stage of the shared path operand is 8 paths per wave, and the
+  // products take 16 at a time)
   const int pw = 32 * kCfrPairTiles;
-  const int nw = (int)std::min<int64_t>(kCfrWaves, (A.Q + pw - 1) / pw);
+  const int nw = (int)std::min<int64_t>(kCfrWaves, ((A.Q + pw - 1) / pw + 1) / 2 * 2);
   A.n_qchunk = (A.Q + nw * pw - 1) / (nw * pw);
   A.link_off = paths->link_off;
   A.a = reinterpret_cast<const float2*>(a);

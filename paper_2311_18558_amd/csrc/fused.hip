@@ -69,11 +69,11 @@ struct Fz {
   // adjoint: each wave's partial G of a tile, two tiles in flight
   static constexpr int GBUF_FLOATS = 64 * 32;
   static constexpr int GBUF_BYTES = 2 * NW * GBUF_FLOATS * 4;
-  // forward: one stage of 64 paths, the path operand in FP16 parts (4
-  // chunks x 4 parts x 64 lanes x 16 B) and the delays
-  static constexpr int ST_PATHS = 64;
-  static constexpr int ST_OPND_BYTES = (ST_PATHS / 16) * 4 * 64 * 16;
-  static constexpr int ST_BYTES = ST_OPND_BYTES + ST_PATHS * 8;
+  // forward: one stage of NW x 8 paths, the path operand in FP16 parts
+  // and the delays (path_stage_store)
+  static constexpr int ST_PATHS = path_stage_paths(NW * 64);
+  static constexpr int ST_OPND_BYTES = path_stage_opnd_bytes(NW * 64);
+  static constexpr int ST_BYTES = path_stage_bytes(NW * 64);
   static constexpr int M2 = LOSS_BYTES > GBUF_BYTES ? LOSS_BYTES : GBUF_BYTES;
   static constexpr int SMEM = M2 > ST_BYTES ? M2 : ST_BYTES;
 };
@@ -279,65 +279,30 @@ __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs 
 #pragma unroll
     for (int k = 0; k < 4; ++k) acc[t][k] = floatx16{0};
   {
-    // the path operand: thread (m = col, path pair kp) forms A'[2 kp + e, m]
-    // for e = 0, 1 of each pass of 4 NW paths
+    // the path operand: formed by the workgroup per stage (path_stage_store)
     const int m = col;
     const float2 g_row = m < M ? A.g[m] : make_float2(0.0f, 0.0f);
     const double mc_cyc = ((double)m - A.cm) * kInv2Pi;
     const int sx = 14 - cfr_link_scale_exp(A.a, off0, off1, g_row, lane);
     const float2 gm = make_float2(ldexpf(g_row.x, sx), ldexpf(g_row.y, sx));
-    const int kp0 = threadIdx.x >> 5;  // path pair of the thread's first pass
-    constexpr int PPASS = 2 * (NT / 32);  // paths per pass
     unsigned* opnd = reinterpret_cast<unsigned*>(smem);
     double* tau_s = reinterpret_cast<double*>(smem + F::ST_OPND_BYTES);
     // the wave's subcarrier phase slope per tile: t_q df for its lane's pair
     double tq[TPW];
 #pragma unroll
     for (int t = 0; t < TPW; ++t) tq[t] = ((double)(q_base + 32 * t + col) + A.t_off) * A.df;
+    PathFetch pf;
+    if (off0 < off1) path_fetch(A.a, A.psi, A.tau, off0, off1, NT, pf);
     for (int64_t s0 = off0; s0 < off1; s0 += F::ST_PATHS) {
       __syncthreads();  // the previous stage's operands are consumed
-#pragma unroll
-      for (int ps = 0; ps < F::ST_PATHS / PPASS; ++ps) {
-        const int k = 2 * (kp0 + (NT / 32) * ps);  // first of the two paths (even)
-        float re[2], im[2];
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-          const int64_t p = s0 + k + e;
-          float2 b = make_float2(0.0f, 0.0f);
-          if (p < off1) {
-            const float2 ph = expm2pi_f64_hw(fma(A.fref, A.tau[p], -(double)A.psi[p] * mc_cyc));
-            b = cmul(cmul(A.a[p], gm), ph);
-          }
-          re[e] = b.x;
-          im[e] = b.y;
-        }
-        // B-operand slot: chunk c = k / 16, lane m + 32 ((k % 16) / 8),
-        // element (k % 8) of the part's 8-vector; parts re_h, re_l, im_h, im_l
-        const unsigned wr = pack_f16(re[0], re[1]);
-        const unsigned wi = pack_f16(im[0], im[1]);
-        const unsigned lr = pack_f16(sub_f16<true>(re[0], wr), sub_f16<false>(re[1], wr));
-        const unsigned li = pack_f16(sub_f16<true>(im[0], wi), sub_f16<false>(im[1], wi));
-        const int c = k >> 4;
-        const int sl = m + 32 * ((k & 15) >> 3);
-        const int w32 = (k & 7) >> 1;  // 32-bit word within the 16-byte vector
-        opnd[((c * 4 + 0) * 64 + sl) * 4 + w32] = wr;
-        opnd[((c * 4 + 1) * 64 + sl) * 4 + w32] = lr;
-        opnd[((c * 4 + 2) * 64 + sl) * 4 + w32] = wi;
-        opnd[((c * 4 + 3) * 64 + sl) * 4 + w32] = li;
-      }
-      if (threadIdx.x < F::ST_PATHS) {
-        const int64_t p = s0 + threadIdx.x;
-        tau_s[threadIdx.x] = p < off1 ? A.tau[p] : 0.0;  // zero operand rows: any finite phase
-      }
+      path_stage_store(pf, s0, off1, NT, A.fref, mc_cyc, gm, col, opnd, tau_s);
       __syncthreads();
+      // the next stage's path data load while this stage's products run
+      if (s0 + F::ST_PATHS < off1) path_fetch(A.a, A.psi, A.tau, s0 + F::ST_PATHS, off1, NT, pf);
       const int nch = (int)min((int64_t)(F::ST_PATHS / 16), (off1 - s0 + 15) >> 4);
       for (int c = 0; c < nch; ++c) {
-        const u32x4* ob = reinterpret_cast<const u32x4*>(opnd) + (c * 4) * 64 + lane;
         Split2 AR, AI;
-        AR.h = __builtin_bit_cast(halfx8, ob[0]);
-        AR.l = __builtin_bit_cast(halfx8, ob[64]);
-        AI.h = __builtin_bit_cast(halfx8, ob[128]);
-        AI.l = __builtin_bit_cast(halfx8, ob[192]);
+        path_stage_read(opnd, c, lane, AR, AI);
         const double* tp = tau_s + 16 * c + 8 * half;
 #pragma unroll
         for (int t = 0; t < TPW; ++t) {
