@@ -395,7 +395,9 @@ __device__ __forceinline__ void adj_wave(const AdjArgs& A, int64_t w, int64_t l,
         for (int j = 0; j < 8; ++j)
           mx = fmaxf(mx, fmaxf(fmaxf(fabsf(sr[j]), fabsf(si[j])),
                                fmaxf(fabsf(ndr[j]), fabsf(di[j]))));
-        mx = wave_max_f32(mx);
+        // the wave-wide maximum only when some lane reaches the limit (a
+        // ballot; rare once the scale has settled)
+        if (__ballot(mx > 0.0f && mx >= lim)) mx = wave_max_f32(mx);
         if (mx > 0.0f && mx >= lim) {  // the same on every lane
           int e = 0;
           frexpf(mx, &e);  // mx < 2^e
