@@ -27,7 +27,8 @@
 //
 // The adjoint G[m, i] = sum_n dLdH[m, n] conj(E[i, n]) is the same kind of
 // product with the subcarriers as the contraction axis: lane l reads eight
-// consecutive subcarrier pairs of its dL/dH row (see adj_wave).
+// consecutive subcarrier pairs of its dL/dH row, the workgroup forming these
+// operands once in LDS for all its waves (see cfr_adjoint_kernel).
 #include <algorithm>
 #include <cmath>
 
@@ -42,8 +43,9 @@ constexpr int kCfrWaves = 8;      // waves per workgroup at most (forward): two 
 constexpr int kCfrPairTiles = 2;  // tiles of 32 subcarrier pairs per wave (forward)
 // the shared path operand's LDS stage at the largest workgroup (forward)
 constexpr int kCfrStageBytes = path_stage_bytes(kCfrWaves * 64);
-constexpr int kAdjWaves = 4;   // waves per workgroup (adjoint)
-constexpr int kAdjTP = 2;      // 32-path tiles per wave (adjoint)
+constexpr int kAdjPathsPerWave = 64;  // two 32-path tiles per wave (adjoint)
+constexpr int kAdjWaves = 4;   // waves per workgroup (per-wave adjoint)
+constexpr int kAdjTP = 2;      // 32-path tiles per wave (per-wave adjoint)
 
 struct CfrArgs {
   int n_links, M, N;
@@ -174,29 +176,23 @@ __global__ void __launch_bounds__(kCfrWaves * 64) cfr_kernel(CfrArgs A, float2* 
 }
 
 // ------------------------------------------------------------------ adjoint
-// One wave per (link, group of kAdjTP 32-path tiles), found by binary search
-// in a per-link exclusive scan of wave counts.  For each 32-row element
-// block the wave contracts over subcarriers: MFMA step s of a 64-subcarrier
-// chunk takes subcarriers n0 + s (k = 0) and n0 + 32 + s (k = 1), so lane l
-// reads a contiguous run of its own row (16-byte loads) and advances its
-// exponential by exp(-j 2 pi df tau) from an FP64 anchor per half-chunk.
 struct AdjArgs {
   int n_links, M, N, Q;
-  int64_t max_waves;
+  int64_t max_waves;        // work units of the launch (rows of g_part)
   const int64_t* link_off;
-  const int64_t* wave_off;  // [n_links + 1] exclusive scan of waves per link
+  const int64_t* wave_off;  // [n_links + 1] exclusive scan of work units per link
   const float2* a;
   const float* psi;
   const double* tau;
   const float2* g;
   const float2* dH;
   float2* dLda;    // may be null
-  double* g_part;  // [max_waves][M][2] per-wave dL/dg partials, or null
+  double* g_part;  // [max_waves][M][2] per-unit dL/dg partials, or null
   double fref, t_off, df, cm;  // grid midpoint, t of pair 0, spacing, (M-1)/2
 };
 
-// Exclusive scan of work units per link, ceil(P_l / unit) (unit = 32 kAdjTP
-// paths for the matrix-core adjoint's waves, kM1Block paths for the
+// Exclusive scan of work units per link, ceil(P_l / unit) (unit = 64 NWA
+// paths for the matrix-core adjoint's workgroups, kM1Block paths for the
 // single-element one); one block, thread t owns a contiguous run of links.
 __global__ void __launch_bounds__(1024) adj_wave_scan_kernel(const int64_t* link_off, int n_links,
                                                               int unit, int64_t* wave_off) {
@@ -239,6 +235,339 @@ __global__ void __launch_bounds__(1024) adj_wave_scan_kernel(const int64_t* link
     }
   }
   if (t == 1023) wave_off[n_links] = acc;
+}
+
+// One workgroup of NWA waves per (link, group of NWA x 64 paths), found by
+// binary search in a per-link exclusive scan of group counts; wave w takes
+// the group's 32-path tiles 2w and 2w + 1.  For each 32-row element block
+// the workgroup walks the subcarrier pairs in blocks of 8 NWA: it loads the
+// block's dL/dH (both subcarriers of each pair, 16-byte runs; the next
+// block's loads are in flight while the current block's products run),
+// forms S and D, scales them with the workgroup's running power-of-two scale,
+// splits them into FP16 parts and stores them in LDS in the MFMA's A-operand
+// layout (double-buffered); every wave reads them back and contracts them
+// with its own tiles' exponentials.  S and D are thus formed once per
+// workgroup instead of once per wave, and a link's dL/dH is read by its
+// ceil(P_l / (64 NWA)) groups instead of by each of its waves.
+//
+// Conjugate pairs of subcarriers (as in the forward product): with c_p =
+// exp(-j 2 pi f_ref tau_p) and u_p(t) = exp(-j 2 pi t df tau_p),
+// conj(E[p, n_hi]) = conj(c_p) conj(u_p(t_q)) and conj(E[p, n_lo]) =
+// conj(c_p) u_p(t_q), so
+//     G[m, p] = conj(c_p) sum_q (S[m, q] Re u_p(t_q) - j D[m, q] Im u_p(t_q))
+// with S = dH[., n_hi] + dH[., n_lo] and D = dH[., n_hi] - dH[., n_lo]: two
+// complex-by-real products per 16 pairs (32 subcarriers), accumulated over
+// the row in the matrix cores, and the path phase conj(c_p) applied once.
+template <int NWA>
+struct AdjWg {
+  static constexpr int NT = NWA * 64;
+  static constexpr int BLK = 8 * NWA;             // pairs per block: one (row, quad) item per thread
+  static constexpr int NCH = BLK / 16;            // 16-pair chunks per block
+  static constexpr int OPND_U32 = NCH * 8 * 64 * 4;  // chunks x 8 parts x 64 lanes x 16 B
+  static_assert(NCH >= 1 && 32 * (BLK / 4) == NT, "one staging item per thread");
+};
+
+// The four pairs q0 .. q0+3 of a dL/dH row: hi[j] = dH[n_hi(q0 + j)], lo[j] =
+// dH[n_lo(q0 + j)], zero past Q, for a padding row, and on the lo side of the
+// middle subcarrier of odd N (pair 0 pairs with itself and is counted on the
+// n_hi side); 16-byte loads where the rows allow them.
+__device__ __forceinline__ void adj_load4(const float2* row, int q0, int N, int Q, bool vec,
+                                          bool ok, float2 (&hi)[4], float2 (&lo)[4]) {
+  const int nh = N / 2;
+  if (ok && vec && q0 + 3 < Q && q0 > 0) {
+    const float4* ph = reinterpret_cast<const float4*>(row + nh + q0);
+    const float4* pl = reinterpret_cast<const float4*>(row + (N - 4 - nh - q0));
+    const float4 a = ph[0], b = ph[1], c = pl[0], d = pl[1];
+    hi[0] = make_float2(a.x, a.y);
+    hi[1] = make_float2(a.z, a.w);
+    hi[2] = make_float2(b.x, b.y);
+    hi[3] = make_float2(b.z, b.w);
+    lo[3] = make_float2(c.x, c.y);
+    lo[2] = make_float2(c.z, c.w);
+    lo[1] = make_float2(d.x, d.y);
+    lo[0] = make_float2(d.z, d.w);
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int q = q0 + j;
+      const bool use = ok && q < Q;
+      hi[j] = use ? row[nh + q] : make_float2(0.0f, 0.0f);
+      lo[j] = (use && !((N & 1) && q == 0)) ? row[N - 1 - nh - q] : make_float2(0.0f, 0.0f);
+    }
+  }
+}
+
+template <int NWA>
+__global__ void __launch_bounds__(NWA * 64) cfr_adjoint_kernel(AdjArgs A) {
+  using C = AdjWg<NWA>;
+  __shared__ __align__(16) unsigned opnd[2][C::OPND_U32];
+  __shared__ float smax[2][NWA];
+  __shared__ double gsh[NWA][32][2];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wv = tid >> 6;
+  const int half = lane >> 5;
+  const int col = lane & 31;
+  // XCD-aware order: workgroups go to the eight XCDs in turn, so the first
+  // 8 nb workgroups (nb = the real groups per XCD) give XCD b % 8 the
+  // (b % 8)-th eighth of the real groups, in order; the groups of one link
+  // then sit on one XCD and share its L2 for the link's dL/dH.  The surplus
+  // workgroups come after them (the grid is a multiple of eight, sized for
+  // the most groups possible).
+  const int64_t total = A.wave_off[A.n_links];
+  const int64_t nb = (total + 7) / 8;
+  const int64_t b = blockIdx.x, x = b & 7, bs = b >> 3;
+  const int64_t unit = bs < nb ? x * nb + bs : 8 * nb + (bs - nb) * 8 + x;
+  if (unit >= A.max_waves) return;
+  if (unit >= total) {
+    // surplus group: its dL/dg partial row is zero
+    if (A.g_part)
+      for (int i = tid; i < 2 * A.M; i += C::NT) A.g_part[unit * 2 * A.M + i] = 0.0;
+    return;
+  }
+  int lo_l = 0, hi_l = A.n_links - 1;
+  while (lo_l < hi_l) {
+    const int mid = (lo_l + hi_l + 1) >> 1;
+    if (A.wave_off[mid] <= unit)
+      lo_l = mid;
+    else
+      hi_l = mid - 1;
+  }
+  const int64_t l = lo_l;
+  const int grp = (int)(unit - A.wave_off[l]);
+  const int64_t off0 = A.link_off[l];
+  const int64_t off1 = A.link_off[l + 1];
+  const int N = A.N, Q = A.Q, M = A.M;
+  const int n_mblk = (M + 31) / 32;
+  const bool vec = (N & 3) == 0 && (reinterpret_cast<uintptr_t>(A.dH) & 15) == 0;
+  const float2* dHl = A.dH + l * (int64_t)M * N;
+  // this wave's tiles (0, 1 or 2 of them; the same on every lane)
+  const int64_t wp0 = off0 + (int64_t)grp * C::NT + 64 * wv;
+  const int ntw = (int)max((int64_t)0, min((int64_t)2, (off1 - wp0 + 31) >> 5));
+  auto path_of = [&](int u) { return wp0 + 32 * u + col; };
+  double tv[2];
+  float2 v1[2], v16[2], da[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int64_t p = path_of(u);
+    tv[u] = p < off1 ? A.tau[p] : 0.0;
+    v1[u] = expm2pi_f64_hw(A.df * tv[u]);
+    v16[u] = expm2pi_f64_hw(16.0 * A.df * tv[u]);
+    da[u] = make_float2(0.0f, 0.0f);
+  }
+  const int nblk = (Q + C::BLK - 1) / C::BLK;
+
+  for (int mblk = 0; mblk < n_mblk; ++mblk) {
+    // G~ = X - j Y accumulated directly:
+    //   Re G~ += S_re Re u + D_im Im u,  Im G~ += S_im Re u - D_re Im u
+    floatx16 gre[2], gim[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      gre[u] = floatx16{0};
+      gim[u] = floatx16{0};
+    }
+    // The A operand (S and D) carries the workgroup's scale 2^sx: every
+    // value seen so far is below lim = 2^(14 - sx), so scaled it stays below
+    // 2^14 (FP16 holds up to 65504) and values down to 2^-28 of the largest
+    // keep all their bits.  A block reaching lim lowers the scale and
+    // multiplies the accumulators by the same power of two (exact); lim = 0
+    // until the first nonzero block.
+    int sx = 0;
+    float lim = 0.0f;
+    // the thread's staging item: row r = tid / QB of the element block,
+    // pairs 4 (tid % QB) .. +3 of the pair block (QB = BLK / 4 quads per row;
+    // consecutive threads read consecutive runs of a row)
+    constexpr int QB = C::BLK / 4;
+    const int srow = tid / QB, squad = tid % QB;
+    float2 hv[4], lv[4];
+    auto load_block = [&](int blk) {
+      const int row = mblk * 32 + srow;
+      const bool ok = row < M;
+      adj_load4(dHl + (int64_t)(ok ? row : 0) * N, blk * C::BLK + 4 * squad, N, Q, vec, ok, hv,
+                lv);
+    };
+    // the thread's largest |S|, |D| of the loaded block, published per wave
+    // (the wave maximum only when some lane reaches the current limit)
+    auto publish_max = [&](int slot) {
+      float mx = 0.0f;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const float2 s = cadd(hv[j], lv[j]), d = csub(hv[j], lv[j]);
+        mx = fmaxf(mx, fmaxf(fmaxf(fabsf(s.x), fabsf(s.y)), fmaxf(fabsf(d.x), fabsf(d.y))));
+      }
+      if (__ballot(mx > 0.0f && mx >= lim)) mx = wave_max_f32(mx);
+      else mx = 0.0f;
+      if (lane == 0) smax[slot][wv] = mx;
+    };
+    // S, D of the loaded block times 2^sx, split into FP16 parts, to the
+    // A-operand slots of buffer `buf`: chunk c = quad / 4, lane
+    // r + 32 ((quad % 4) / 2), elements 4 (quad % 2) .. +3 of each part's
+    // 8-vector
+    auto store_block = [&](int buf, float sc) {
+      {
+        float sr[4], si[4], nd[4], di[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          sr[j] = (hv[j].x + lv[j].x) * sc;
+          si[j] = (hv[j].y + lv[j].y) * sc;
+          nd[j] = (lv[j].x - hv[j].x) * sc;
+          di[j] = (hv[j].y - lv[j].y) * sc;
+        }
+        const int c = squad >> 2, qr = squad & 3;
+        const int L = srow + 32 * (qr >> 1);
+        unsigned* base = opnd[buf] + ((c * 8) * 64 + L) * 4 + 2 * (qr & 1);
+        auto put = [&](int part, const float (&v)[4]) {
+          const unsigned h0 = pack_f16(v[0], v[1]), h1 = pack_f16(v[2], v[3]);
+          const unsigned l0 = pack_f16(sub_f16<true>(v[0], h0), sub_f16<false>(v[1], h0));
+          const unsigned l1 = pack_f16(sub_f16<true>(v[2], h1), sub_f16<false>(v[3], h1));
+          *reinterpret_cast<uint2*>(base + (2 * part) * 64 * 4) = make_uint2(h0, h1);
+          *reinterpret_cast<uint2*>(base + (2 * part + 1) * 64 * 4) = make_uint2(l0, l1);
+        };
+        put(0, sr);
+        put(1, si);
+        put(2, nd);
+        put(3, di);
+      }
+    };
+    load_block(0);
+    publish_max(0);
+    __syncthreads();
+    for (int blk = 0; blk < nblk; ++blk) {
+      // the block's scale (the same on every lane)
+      float mxb = smax[blk & 1][0];
+#pragma unroll
+      for (int w = 1; w < NWA; ++w) mxb = fmaxf(mxb, smax[blk & 1][w]);
+      if (mxb > 0.0f && mxb >= lim) {
+        int e = 0;
+        frexpf(mxb, &e);  // mxb < 2^e
+        e = min(max(e, -100), 100);
+        if (lim > 0.0f) {
+          const float f = ldexpf(1.0f, (14 - e) - sx);
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            gre[u] *= f;
+            gim[u] *= f;
+          }
+        }
+        sx = 14 - e;
+        lim = ldexpf(1.0f, e);
+      }
+      store_block(blk & 1, ldexpf(1.0f, sx));
+      if (blk + 1 < nblk) load_block(blk + 1);  // in flight during the products
+      __syncthreads();
+      if (ntw > 0) {
+        const int g0 = blk * C::BLK;
+        float2 uf[2];  // u_p(t) at the lane's first pair of the chunk
+        const double t_first = (double)(g0 + 8 * half) + A.t_off;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) uf[u] = expm2pi_f64_hw(t_first * A.df * tv[u]);
+#pragma unroll
+        for (int c = 0; c < C::NCH; ++c) {
+          if (g0 + 16 * c >= Q) break;
+          const u32x4* ob = reinterpret_cast<const u32x4*>(opnd[blk & 1]) + (c * 8) * 64 + lane;
+          Split2 SR, SI, NDR, DI;
+          SR.h = __builtin_bit_cast(halfx8, ob[0]);
+          SR.l = __builtin_bit_cast(halfx8, ob[64]);
+          SI.h = __builtin_bit_cast(halfx8, ob[128]);
+          SI.l = __builtin_bit_cast(halfx8, ob[192]);
+          NDR.h = __builtin_bit_cast(halfx8, ob[256]);
+          NDR.l = __builtin_bit_cast(halfx8, ob[320]);
+          DI.h = __builtin_bit_cast(halfx8, ob[384]);
+          DI.l = __builtin_bit_cast(halfx8, ob[448]);
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            if (u < ntw) {
+              if (c > 0) uf[u] = cmul(uf[u], v16[u]);
+              float ur[8], ui[8];
+              float2 e = uf[u];
+#pragma unroll
+              for (int j = 0; j < 8; ++j) {
+                if (j > 0) e = cmul(e, v1[u]);
+                ur[j] = e.x;
+                ui[j] = e.y;
+              }
+              const Split2 UR = split2(ur), UI = split2(ui);
+              gre[u] = mac3(SR, UR, gre[u]);
+              gim[u] = mac3(SI, UR, gim[u]);
+              gre[u] = mac3(DI, UI, gre[u]);
+              gim[u] = mac3(NDR, UI, gim[u]);
+            }
+          }
+        }
+      }
+      if (blk + 1 < nblk) publish_max((blk + 1) & 1);
+      __syncthreads();
+    }
+    // epilogue: rows m = mblk*32 + 8(r/4) + 4 half + r%4, column = path
+    const float unscale = ldexpf(1.0f, -sx);
+    float gacc_re[16], gacc_im[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) gacc_re[r] = gacc_im[r] = 0.0f;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      if (u < ntw) {
+        gre[u] *= unscale;
+        gim[u] *= unscale;
+        const int64_t p = path_of(u);
+        const bool ok = p < off1;
+        const float2 ai = ok ? A.a[p] : make_float2(0.0f, 0.0f);
+        const double psi_cyc = (double)(ok ? A.psi[p] : 0.0f) * kInv2Pi;
+        const float2 cc = cconj(expm2pi_f64_hw(A.fref * tv[u]));  // conj(c_p)
+        const float2 step = expm2pi_f64_hw(psi_cyc);
+#pragma unroll
+        for (int g4 = 0; g4 < 4; ++g4) {
+          const int mrow0 = mblk * 32 + 8 * g4 + 4 * half;
+          float2 ph = expm2pi_f64_hw(psi_cyc * ((double)mrow0 - A.cm));  // exp(-j psi (m - c))
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int r = g4 * 4 + q;
+            const int mrow = mrow0 + q;
+            if (q > 0) ph = cmul(ph, step);
+            const float2 G = cmul(cc, make_float2(gre[u][r], gim[u][r]));  // conj(c_p) G~
+            const float2 gm = mrow < M ? A.g[mrow] : make_float2(0.0f, 0.0f);
+            const float2 Gph = cmul(G, ph);
+            da[u] = cadd(da[u], cmulc(gm, Gph));
+            const float2 tg2 = cmulc(ai, Gph);
+            gacc_re[r] += tg2.x;  // tiles in order
+            gacc_im[r] += tg2.y;
+          }
+        }
+      }
+    }
+    if (A.g_part) {
+      // the wave's rows summed over its paths (each half's 32, fixed
+      // butterfly), then the waves in order
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float vr = half_sum_f32(gacc_re[r]), vi = half_sum_f32(gacc_im[r]);
+        if (col == 0) {
+          const int rl = 8 * (r >> 2) + 4 * half + (r & 3);
+          gsh[wv][rl][0] = (double)vr;
+          gsh[wv][rl][1] = (double)vi;
+        }
+      }
+      __syncthreads();
+      if (tid < 64) {
+        const int rl = tid & 31, k = tid >> 5;
+        double s = gsh[0][rl][k];
+#pragma unroll
+        for (int w = 1; w < NWA; ++w) s += gsh[w][rl][k];
+        const int mrow = mblk * 32 + rl;
+        if (mrow < M) A.g_part[(unit * M + mrow) * 2 + k] = s;
+      }
+      __syncthreads();
+    }
+  }
+  if (A.dLda) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      float2 d = da[u];
+      d.x += __shfl_xor(d.x, 32, 64);
+      d.y += __shfl_xor(d.y, 32, 64);
+      const int64_t p = path_of(u);
+      if (u < ntw && half == 0 && p < off1) A.dLda[p] = d;
+    }
+  }
 }
 
 // Eight consecutive values of a dL/dH row starting at subcarrier n (zero
@@ -284,9 +613,13 @@ __device__ __forceinline__ void load8_lo(const float2* row, int q1, int N, int Q
   }
 }
 
-// Contraction of one wave over NT (1 or 2) consecutive 32-path tiles of link
-// l, starting at tile grp * kAdjTP; the caller picks NT = 1 for a link's
-// last wave when it holds a single tile, so no MFMA runs on empty tiles.
+// The adjoint for links of a few hundred paths: one wave per (link, group of
+// kAdjTP 32-path tiles), found by binary search in a per-link exclusive scan
+// of wave counts, each wave forming the S/D operand of its link itself (no
+// workgroup-wide stage, so no tiles idle at the links' ends).  Contraction of
+// one wave over NT (1 or 2) consecutive 32-path tiles of link l, starting at
+// tile grp * kAdjTP; the caller picks NT = 1 for a link's last wave when it
+// holds a single tile, so no MFMA runs on empty tiles.
 //
 // Conjugate pairs of subcarriers (as in the forward product): with c_p =
 // exp(-j 2 pi f_ref tau_p) and u_p(t) = exp(-j 2 pi t df tau_p),
@@ -510,7 +843,7 @@ __device__ __forceinline__ void adj_wave(const AdjArgs& A, int64_t w, int64_t l,
   }
 }
 
-__global__ void __launch_bounds__(kAdjWaves * 64, 2) cfr_adjoint_kernel(AdjArgs A) {
+__global__ void __launch_bounds__(kAdjWaves * 64, 2) cfr_adjoint_wave_kernel(AdjArgs A) {
   const int lane = threadIdx.x & 63;
   // XCD-aware order: workgroups go to the eight XCDs in turn, so the first
   // 8 nb workgroups (nb = the workgroups of real waves per XCD) give XCD
@@ -628,7 +961,7 @@ __global__ void __launch_bounds__(kM1Block) cfr_adjoint_m1_kernel(AdjArgs A) {
   const float2 v1 = expm2pi_f64_hw(A.df * tau);
   const float2* row = A.dH + l * (int64_t)A.N;
   const int N = A.N, Q = A.Q, nh = N / 2;
-  float gre = 0.0f, gim = 0.0f;  // G~ = X - jY, accumulated as in adj_wave
+  float gre = 0.0f, gim = 0.0f;  // G~ = X - jY, accumulated as in cfr_adjoint_kernel
   float2 u = make_float2(1.0f, 0.0f);
   for (int q0 = 0; q0 < Q; q0 += kM1Block) {
     const int nq = min(kM1Block, Q - q0);
@@ -673,8 +1006,9 @@ __global__ void to_c64_kernel(const double* v, int M, float2* out) {
 }
 
 static int64_t adj_max_waves(int32_t n_links, int32_t n_paths) {
-  // sum over links of ceil(ceil(P_l / 32) / TP) <= n_paths / (32 TP) + n_links
-  return (int64_t)n_paths / (32 * kAdjTP) + n_links + 1;
+  // sum over links of ceil(P_l / 64) <= n_paths / 64 + n_links: bounds the
+  // work units (dL/dg partial rows) of any workgroup size
+  return (int64_t)n_paths / kAdjPathsPerWave + n_links + 1;
 }
 
 // Workspace: wave_off int64 [L+1] | per-wave dL/dg partials double
@@ -787,8 +1121,13 @@ extern "C" rtc_status rtc_cfr_adjoint(const rtc_radio* radio, const rtc_paths* p
   A.df = radio->df_hz;
   A.cm = 0.5 * (double)(radio->n_elem - 1);
   const bool m1 = radio->n_elem == 1;
+  // links of many paths (on average at least 512): workgroups of eight
+  // waves sharing the S/D operand; otherwise one wave per 64 paths
+  const bool wg = (int64_t)paths->n_paths >= 512 * (int64_t)std::max(1, paths->n_links);
+  constexpr int nwa = 8;
   hipLaunchKernelGGL(adj_wave_scan_kernel, dim3(1), dim3(1024), 0, s, paths->link_off,
-                     paths->n_links, m1 ? kM1Block : 32 * kAdjTP, wave_off);
+                     paths->n_links,
+                     m1 ? kM1Block : (wg ? kAdjPathsPerWave * nwa : kAdjPathsPerWave), wave_off);
   if ((st = check_launch(fn)) != RTC_OK) return st;
   // partial dL/dg rows the launch writes (every one, surplus ones as zeros)
   int64_t part_rows = A.max_waves;
@@ -800,11 +1139,20 @@ extern "C" rtc_status rtc_cfr_adjoint(const rtc_radio* radio, const rtc_paths* p
     RTC_REQUIRE(blocks <= A.max_waves && blocks < (1ll << 31), RTC_ERR_RANGE,
                 "%s: problem too large for one launch", fn);
     hipLaunchKernelGGL(cfr_adjoint_m1_kernel, dim3((unsigned)blocks), dim3(kM1Block), 0, s, A);
+  } else if (wg) {
+    // work units: sum over links of ceil(P_l / (64 nwa)), at most this many
+    A.max_waves = (int64_t)paths->n_paths / (kAdjPathsPerWave * nwa) + paths->n_links + 1;
+    part_rows = A.max_waves;
+    // a multiple of eight workgroups (the kernel's XCD-aware order)
+    const int64_t blocks = (A.max_waves + 7) / 8 * 8;
+    RTC_REQUIRE(blocks < (1ll << 31), RTC_ERR_RANGE, "%s: problem too large for one launch", fn);
+    hipLaunchKernelGGL(cfr_adjoint_kernel<nwa>, dim3((unsigned)blocks), dim3(nwa * 64), 0, s, A);
   } else {
     // a multiple of eight workgroups (the kernel's XCD-aware order)
     const int64_t blocks = ((A.max_waves + kAdjWaves - 1) / kAdjWaves + 7) / 8 * 8;
     RTC_REQUIRE(blocks < (1ll << 31), RTC_ERR_RANGE, "%s: problem too large for one launch", fn);
-    hipLaunchKernelGGL(cfr_adjoint_kernel, dim3((unsigned)blocks), dim3(kAdjWaves * 64), 0, s, A);
+    hipLaunchKernelGGL(cfr_adjoint_wave_kernel, dim3((unsigned)blocks), dim3(kAdjWaves * 64), 0,
+                       s, A);
   }
   if ((st = check_launch(fn)) != RTC_OK) return st;
   if (dLdg) {

@@ -412,6 +412,75 @@ def test_cfr_adjoint_value_range(rl, scale):
     assert eg <= 1e-5, eg
 
 
+def _long_link_store(rng, counts):
+    """A path store of the given paths per link for the CFR kernels alone
+    (delays only; the geometry is unused by the CFR and its adjoint)."""
+    from synth.store import PathStore
+    counts = np.asarray(counts, np.int64)
+    L, P = len(counts), int(counts.sum())
+    off = np.zeros(L + 1, np.int64)
+    off[1:] = np.cumsum(counts)
+    z3 = np.zeros((3, P), np.float32)
+    return PathStore(n_links=L, n_paths=P, max_depth=1, link_off=off,
+                     tx_pos=np.zeros((L, 3), np.float32), rx_pos=np.ones((L, 3), np.float32),
+                     depth=np.ones(P, np.uint8), kind=np.zeros(P, np.uint8), pts=z3, nrm=z3.copy(),
+                     mat=np.zeros(P, np.uint16), dA=np.zeros(P, np.float32),
+                     tau=rng.uniform(20e-9, 900e-9, P), face=np.zeros(P, np.int32))
+
+
+@pytest.mark.parametrize("scale", [1e-20, 1.0, 1e18])
+def test_cfr_adjoint_long_links(rl, scale):
+    """Links of hundreds to thousands of paths (the workgroup-staged
+    adjoint, whose groups of eight waves form the S/D operand once in LDS):
+    a link spanning several groups with a ragged last tile, a one-path and an
+    empty link, odd N (the middle subcarrier pairs with itself), 40 elements
+    (two element blocks), and dL/dH rising and falling by 1e6 along the
+    pairs, zero for a whole link and at overall scales 1e-20 to 1e18, against
+    the FP64 autograd of the direct sum."""
+    rng = np.random.default_rng(77)
+    st = _long_link_store(rng, [700, 1, 0, 1500, 513, 900, 1029])
+    radio = Radio(fc=3.5e9, bandwidth=40e6, n_sc=301, n_elem=40, ula_axis=(1.0, 0.0, 0.0))
+    L, M, N, P = st.n_links, radio.n_elem, radio.n_sc, st.n_paths
+    assert P >= 512 * L
+    a32 = torch.tensor(((rng.normal(size=P) + 1j * rng.normal(size=P))
+                        * 10.0 ** rng.uniform(-3, 0, P) * 1e-4).astype(np.complex64))
+    p32 = torch.tensor(rng.uniform(-3.1, 3.1, P).astype(np.float32))
+    g32 = torch.tensor((rng.uniform(0.5, 2.0, M) * np.exp(1j * rng.uniform(-3, 3, M))).astype(
+        np.complex64))
+    z = rng.normal(size=(L, M, N)) + 1j * rng.normal(size=(L, M, N))
+    dist = np.abs(np.arange(N) - (N - 1) / 2) / (N / 2)
+    prof = np.ones((L, N))
+    prof[0] = 10.0 ** (6 * dist - 6)   # rising along the pairs
+    prof[3] = 10.0 ** (-6 * dist)      # falling
+    prof[4] = 0.0                      # all zero
+    dH = torch.tensor((z * prof[:, None, :] * scale).astype(np.complex64))
+    assert torch.isfinite(torch.view_as_real(dH)).all()
+    a64 = a32.to(c128).requires_grad_(True)
+    g64 = g32.to(c128).requires_grad_(True)
+    H = och.cfr(st.link_off, st.tau, a64, p32.to(f64), g64, _freqs(radio))
+    da_ref, dg_ref = torch.autograd.grad(H, (a64, g64), grad_outputs=dH.to(c128))
+    say(f"cfr_adjoint long links scale {scale:g}: L={L} P={P} M={M} N={N}")
+    dp = rl.DevicePaths(st)
+    rc = _radio_c(rl, radio)
+    ws = rl.workspace(rl.RTC_OP_CFR_ADJOINT, rc, L, P)
+    dLda = torch.full((P,), float("nan"), dtype=torch.complex64, device="cuda")
+    dLdg = torch.empty(M, dtype=torch.complex64, device="cuda")
+    rl.cfr_adjoint(rc, dp, a32.cuda(), p32.cuda(), g32.cuda(), dH.cuda(), dLda, dLdg, ws)
+    torch.cuda.synchronize()
+    da = dLda.cpu().to(c128)
+    assert torch.isfinite(torch.view_as_real(da)).all()
+    lo, hi = int(st.link_off[4]), int(st.link_off[5])
+    assert torch.all(da[lo:hi] == 0), "an all-zero dL/dH link gives exact zeros"
+    keep = torch.ones(P, dtype=torch.bool)
+    keep[lo:hi] = False
+    per = _per_link_rel(da[keep], da_ref[keep],
+                        np.concatenate([st.link_off[:5], st.link_off[6:] - (hi - lo)]))
+    eg = (torch.linalg.norm(dLdg.cpu().to(c128) - dg_ref) / torch.linalg.norm(dg_ref)).item()
+    say(f"  dL/da max per-link error {per:.2e}, dL/dg error {eg:.2e}")
+    assert per <= 1e-5, per
+    assert eg <= 1e-5, eg
+
+
 @pytest.mark.parametrize("case", list(CASES))
 def test_trace_fields_adjoint_per_id(rl, case):
     st, raw, radio, g = CASES[case]
