@@ -507,7 +507,8 @@ def summarize_traffic(fetch_csv, write_csv):
     out = {"source_sha": hot_source_sha(), "copy_probe_bytes": COPY_PROBE_BYTES,
            "fetch_scale": sf, "write_scale": sw, "kernels": {}}
     names = {"rtc::cfr_fused_kernel<10>": "cfr_loss_adjoint",
-             "rtc::cfr_kernel": "cfr", "rtc::cfr_adjoint_kernel": "cfr_adjoint",
+             "rtc::cfr_kernel": "cfr", "rtc::cfr_adjoint_wave_kernel": "cfr_adjoint",
+             "rtc::cfr_adjoint_kernel<8>": "cfr_adjoint_wg",
              "rtc::cfr_loss_wave_kernel<10, false>": "cfr_loss",
              "rtc::paper_loss_wave_kernel<10, true>": "paper_loss",
              "rtc::gain_products_kernel": "gain_products"}
