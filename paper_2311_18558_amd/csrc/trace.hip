@@ -74,6 +74,7 @@ struct TraceArgs {
   double lam4pi;           // lambda_c / (4 pi)
   float cz_tx, sz_tx, cz_rx, sz_rx;
   float ux, uy, uz;  // ULA axis
+  int lane_acc;      // adjoint, per id: per-thread material sums in LDS (else a wave walk)
 };
 
 RTC_DEV int find_link(const int64_t* off, int n_links, int64_t p) {
@@ -635,8 +636,15 @@ __global__ void __launch_bounds__(kTraceBlock)
   double* acc = Ls.acc;
   stage_materials(A, tab);
   if constexpr (PAT) stage_patterns(A, Ls.vt, Ls.pt);
+  // per-thread material sums [3 n_mat][blockDim] (FP32, each thread's paths
+  // in order), after the per-wave rows
+  float* lacc = (PER_ID && A.lane_acc && GL.mat >= 0)
+                    ? reinterpret_cast<float*>(acc + GL.stride * (int)(blockDim.x >> 6))
+                    : nullptr;
   if (GL.stride > 0) {
     for (int i = threadIdx.x; i < GL.stride * (int)(blockDim.x >> 6); i += blockDim.x) acc[i] = 0.0;
+    if (lacc)
+      for (int i = threadIdx.x; i < 3 * A.n_mat * (int)blockDim.x; i += blockDim.x) lacc[i] = 0.0f;
     __syncthreads();
   }
   const int lane = threadIdx.x & 63;
@@ -841,12 +849,26 @@ __global__ void __launch_bounds__(kTraceBlock)
     } else {
       // a diffraction path carries its face-n gradient in slot 1
       if (DFR && dfr_path) Q = 2;
-      // Segmented reduction by material id, deterministic: each wave walks
-      // the distinct ids present in it in increasing order; for each id the
-      // lanes' contributions (fixed order over j) are summed by a butterfly
-      // in FP64 and added to the wave's own LDS table (waves are summed in
-      // order at the end).
-      {
+      // Per-id sums, deterministic.  With per-thread sums (lacc) each
+      // thread adds its interactions' gradients to its own column of the
+      // material table (the workgroup sums the columns in order at the end);
+      // otherwise each wave walks the distinct ids present in it in
+      // increasing order, and for each id the lanes' contributions (fixed
+      // order over j) are summed by a butterfly in FP64 and added to the
+      // wave's own LDS table (waves are summed in order at the end).
+      if (lacc) {
+        if (valid) {
+#pragma unroll
+          for (int j = 0; j < MAXD; ++j) {
+            if (j < Q) {
+              float* col = lacc + 3 * ids[j] * (int)blockDim.x + threadIdx.x;
+              col[0] += g_eps[j];
+              col[blockDim.x] += g_sig[j];
+              col[2 * blockDim.x] += g_S[j];
+            }
+          }
+        }
+      } else {
         double* wacc = acc + wave * GL.stride + GL.mat;
         {
           int done_mask = 0;  // bit j set once interaction j is accounted
@@ -936,6 +958,26 @@ __global__ void __launch_bounds__(kTraceBlock)
   }
   if (GL.stride > 0) {
     __syncthreads();
+    if (lacc) {
+      // the columns of each material entry: quarter qt of the threads'
+      // columns summed in order by one thread (FP64), the quarters in order
+      const int n_e = 3 * A.n_mat, nq = (int)blockDim.x / 64;
+      double* qsum = acc + GL.stride * n_waves + (3 * A.n_mat * blockDim.x + 1) / 2;
+      for (int t = threadIdx.x; t < n_e * nq; t += blockDim.x) {
+        const int e = t / nq, qt = t % nq;
+        const float* src = lacc + e * (int)blockDim.x + 64 * qt;
+        double v = 0.0;
+        for (int k = 0; k < 64; ++k) v += (double)src[k];
+        qsum[t] = v;
+      }
+      __syncthreads();
+      for (int e = threadIdx.x; e < n_e; e += blockDim.x) {
+        double v = 0.0;
+        for (int qt = 0; qt < nq; ++qt) v += qsum[e * nq + qt];
+        acc[GL.mat + e] += v;  // wave 0's row, untouched by the walk
+      }
+      __syncthreads();
+    }
     for (int i = threadIdx.x; i < GL.stride; i += blockDim.x) {
       double t = 0.0;
       for (int w = 0; w < n_waves; ++w) t += acc[w * GL.stride + i];
@@ -1034,6 +1076,7 @@ __global__ void trace_adjoint_transform_kernel(const double* tot, GradLayout GL,
 static TraceArgs make_args(const rtc_radio* r, const rtc_paths* P, const rtc_materials* M,
                            const rtc_patterns* pat) {
   TraceArgs A;
+  A.lane_acc = 0;
   A.n_links = P->n_links;
   A.n_paths = P->n_paths;
   A.n_mat = M->raw ? M->n_mat : 1;
@@ -1236,6 +1279,16 @@ extern "C" rtc_status rtc_trace_fields_adjoint_pat(
                 "%s: n_paths > 0 needs n_links >= 1", fn);
   }
   size_t shm = trace_lds_fixed(A) + (size_t)(kTraceBlock / 64) * GL.stride * sizeof(double);
+  // per-thread material sums (and their quarter sums) where they fit beside
+  // two workgroups per CU; beyond 16 materials the wave walk
+  {
+    const size_t lane_bytes = (size_t)3 * A.n_mat * kTraceBlock * sizeof(float);
+    const size_t q_bytes = ((size_t)3 * A.n_mat * (kTraceBlock / 64) + 1) * sizeof(double);
+    if (per_id && GL.mat >= 0 && lane_bytes <= 48 * 1024) {
+      A.lane_acc = 1;
+      shm += (lane_bytes + 7) / 8 * 8 + q_bytes;
+    }
+  }
   RTC_REQUIRE(shm <= 160 * 1024, RTC_ERR_RANGE,
               "%s: %zu bytes of LDS needed (too many materials for the gradients asked)", fn, shm);
   double* part = reinterpret_cast<double*>(ws);
