@@ -425,21 +425,28 @@ __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs 
     DI[c] = split2(di);
   }
 
-  // The epilogue of a tile is split over the waves by element rows: with up
-  // to four waves, wave w takes the row groups g4 in [G4W w, G4W (w + 1))
-  // (rows 8 g4 + 4 half + 0..3, registers 4 g4 .. 4 g4 + 3 of G); with eight,
-  // wave w takes rows 8 (w/2) + 4 (w%2) + 0..3, in the lanes of half w%2.
-  // Its dL/dg rows accumulate in the wave's registers (FP64, tiles in
-  // order); each half-wave's share of dL/da goes to LDS and the wave that
-  // finishes the tile adds the shares in order after the next barrier.
+  // The epilogue of a tile is split over the waves by element rows, RPL rows
+  // per lane: with up to four waves, wave w takes the row groups g4 in
+  // [G4W w, G4W (w + 1)) (rows 8 g4 + 4 half + 0..3, registers 4 g4 ..
+  // 4 g4 + 3 of G, in the lane's own half); with eight, wave w takes rows
+  // 8 (w/2) + 4 (w%2) + 0..3 (registers of the lanes of half w%2), two per
+  // lane: rows 2 half, 2 half + 1 of the four.  Its dL/dg rows accumulate in
+  // the wave's registers (FP64, tiles in order); each half-wave's share of
+  // dL/da goes to LDS and the wave that finishes the tile adds the shares in
+  // order after the next barrier.
   constexpr int G4W = NW <= 4 ? 4 / NW : 1;
-  const bool ep_act = NW <= 4 || half == (wv & 1);
-  auto g4_of = [&](int a) { return NW <= 4 ? G4W * wv + a : (wv >> 1); };
-  double dgw[G4W][4][2];
+  constexpr int RPL = NW <= 4 ? 4 * G4W : 2;  // rows per lane
+  auto ep_reg = [&](int i) {  // register of G (row within the 32-row block)
+    return NW <= 4 ? 4 * (G4W * wv + i / 4) + i % 4 : 4 * (wv >> 1) + 2 * half + i;
+  };
+  auto ep_row = [&](int i) {  // element row
+    return NW <= 4 ? 8 * (G4W * wv + i / 4) + 4 * half + i % 4
+                   : 8 * (wv >> 1) + 4 * (wv & 1) + 2 * half + i;
+  };
+  const int ep_src = NW <= 4 ? lane : 32 * (wv & 1) + col;  // the lane holding the rows
+  double dgw[RPL][2];
 #pragma unroll
-  for (int a = 0; a < G4W; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) dgw[a][b][0] = dgw[a][b][1] = 0.0;
+  for (int i = 0; i < RPL; ++i) dgw[i][0] = dgw[i][1] = 0.0;
   auto finish_da = [&](int T) {
     // dL/da of tile T: the shares of the waves' half-waves, in order
     const float2* db = dabuf[T & 1];
@@ -508,51 +515,48 @@ __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs 
     const float2 cc = cconj(expm2pi_f64_hw(A.fref * tau));  // conj(c_p)
     const float2 step = expm2pi_f64_hw(psi_cyc);
     float2 da = make_float2(0.0f, 0.0f);
+    float2 ph = make_float2(1.0f, 0.0f);
 #pragma unroll
-    for (int a = 0; a < G4W; ++a) {
-      const int g4 = g4_of(a);
-      const int mrow0 = 8 * g4 + 4 * half;
-      float2 ph = expm2pi_f64_hw(psi_cyc * ((double)mrow0 - A.cm));  // exp(-j psi (m - c))
+    for (int i = 0; i < RPL; ++i) {
+      const int r = ep_reg(i);
+      const int mrow = ep_row(i);
+      // exp(-j psi (m - c)) at the first row of each run of four, then by step
+      if (i % 4 == 0)
+        ph = expm2pi_f64_hw(psi_cyc * ((double)mrow - A.cm));
+      else
+        ph = cmul(ph, step);
+      float gr = 0.0f, gi = 0.0f;
 #pragma unroll
-      for (int qq = 0; qq < 4; ++qq) {
-        const int r = 4 * g4 + qq;
-        const int mrow = mrow0 + qq;
-        float gr = 0.0f, gi = 0.0f;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) {
-          gr += g0[w * F::GBUF_FLOATS + r * 64 + lane];
-          gi += g0[w * F::GBUF_FLOATS + (16 + r) * 64 + lane];
-        }
-        if (qq > 0) ph = cmul(ph, step);
-        const float2 G = cmul(cc, make_float2(gr * unsca, gi * unsca));
-        const float2 gmv = mrow < M ? A.g[mrow] : make_float2(0.0f, 0.0f);
-        const float2 Gph = cmul(G, ph);
-        da = cadd(da, cmulc(gmv, Gph));
-        // dL/dg: sum over the 32 paths of this half (fixed butterfly)
-        const float2 tg = cmulc(ai, Gph);
-        dgw[a][qq][0] += (double)half_sum_f32(tg.x);
-        dgw[a][qq][1] += (double)half_sum_f32(tg.y);
+      for (int w = 0; w < NW; ++w) {
+        gr += g0[w * F::GBUF_FLOATS + r * 64 + ep_src];
+        gi += g0[w * F::GBUF_FLOATS + (16 + r) * 64 + ep_src];
       }
+      const float2 G = cmul(cc, make_float2(gr * unsca, gi * unsca));
+      const float2 gmv = mrow < M ? A.g[mrow] : make_float2(0.0f, 0.0f);
+      const float2 Gph = cmul(G, ph);
+      da = cadd(da, cmulc(gmv, Gph));
+      // dL/dg: sum over the 32 paths of this half (fixed butterfly)
+      const float2 tg = cmulc(ai, Gph);
+      dgw[i][0] += (double)half_sum_f32(tg.x);
+      dgw[i][1] += (double)half_sum_f32(tg.y);
     }
     // the half-wave's share of dL/da (its rows of the path), added in order
     // by the wave that finishes the tile
-    dabuf[T & 1][wv * 64 + lane] = ep_act ? da : make_float2(0.0f, 0.0f);
+    dabuf[T & 1][wv * 64 + lane] = da;
   }
   __syncthreads();  // the last tile's shares are in LDS; every epilogue is done
   if (n_tiles > 0 && wv == (n_tiles - 1) % NW) finish_da(n_tiles - 1);
   if (A.g_part) {
-    // this wave's dL/dg rows of the link (disjoint across waves)
-    if (col == 0 && ep_act) {
+    // this wave's dL/dg rows of the link (disjoint across waves and halves)
+    if (col == 0) {
 #pragma unroll
-      for (int a = 0; a < G4W; ++a)
-#pragma unroll
-        for (int qq = 0; qq < 4; ++qq) {
-          const int mrow = 8 * g4_of(a) + 4 * half + qq;
-          if (mrow < M) {
-            A.g_part[(l * M + mrow) * 2 + 0] = dgw[a][qq][0];
-            A.g_part[(l * M + mrow) * 2 + 1] = dgw[a][qq][1];
-          }
+      for (int i = 0; i < RPL; ++i) {
+        const int mrow = ep_row(i);
+        if (mrow < M) {
+          A.g_part[(l * M + mrow) * 2 + 0] = dgw[i][0];
+          A.g_part[(l * M + mrow) * 2 + 1] = dgw[i][1];
         }
+      }
     }
   }
 }
