@@ -81,8 +81,11 @@ def kernel_work(name, L, M, N, P, D):
         # H and H* in (the target PDP formed from H*), dL/dH out
         return 0.0, 24.0 * taps
     if name == "cfr_loss_adjoint":
-        # forward and adjoint contractions; H* and the stored target PDP in
-        # (12 B per tap), the path data in and dL/da out
+        # forward and adjoint contractions; the targets' transforms X* in
+        # (8 B per tap), the path data in and dL/da out
+        return 16.0 * M * N * P, 8.0 * taps + 28.0 * P
+    if name == "cfr_loss_adjoint_cfr":
+        # the same with the targets as H* and the stored target PDP (12 B per tap)
         return 16.0 * M * N * P, 12.0 * taps + 28.0 * P
     if name in ("trace_fields", "trace_fields_adjoint"):
         # per interaction: point, normal (24 B) + material id (2 B); per path
@@ -107,7 +110,7 @@ def mfma_issued(name, link_off, M, N):
         return int((-(-cnt // 16)).sum()) * mblk * qchunks * 4 * 12
     if name == "cfr_adjoint":
         return int((-(-cnt // 32)).sum()) * mblk * (-(-Q // 16)) * 12
-    if name == "cfr_loss_adjoint":
+    if name in ("cfr_loss_adjoint", "cfr_loss_adjoint_cfr"):
         # the fused pass runs both products in the same tilings
         return mfma_issued("cfr", link_off, M, N) + mfma_issued("cfr_adjoint", link_off, M, N)
     return 0
@@ -164,11 +167,13 @@ def diffuse_bench(steps=3, warmup=1):
     return out
 
 
-def separate_calls_step(st, radio, w, raw0, H_tgt, steps, warmup=1):
+def separate_calls_step(st, radio, w, raw0, H_tgt, steps, warmup=1, label="separate-calls",
+                        **pipe_kw):
     """The same step with cfr, cfr_loss and cfr_adjoint as three library
-    calls (H and dL/dH through HBM) instead of the fused pass."""
+    calls (H and dL/dH through HBM) instead of the fused pass (or, with
+    pipe_kw, another variant of the step)."""
     from paper_2311_18558_amd.pipeline import Pipeline
-    pipe = Pipeline(st, radio, w.raw, w.g, fused=False)
+    pipe = Pipeline(st, radio, w.raw, w.g, **(pipe_kw or {"fused": False}))
     pipe.set_target(H_tgt)
     pipe.raw.copy_(torch.tensor(raw0, device=pipe.dev))
     for _ in range(warmup):
@@ -186,7 +191,7 @@ def separate_calls_step(st, radio, w, raw0, H_tgt, steps, warmup=1):
     per = {k: round(float(np.mean([a.elapsed_time(b) for a, b in v])), 4)
            for k, v in events.items()}
     res = {"steps": steps, "ms_per_step": round(ms, 4), "kernels_ms": per}
-    log(f"separate-calls step: {res}")
+    log(f"{label} step: {res}")
     del pipe
     torch.cuda.empty_cache()
     return res
@@ -506,7 +511,8 @@ def summarize_traffic(fetch_csv, write_csv):
     sf, sw = cf / COPY_PROBE_BYTES, cw / COPY_PROBE_BYTES
     out = {"source_sha": hot_source_sha(), "copy_probe_bytes": COPY_PROBE_BYTES,
            "fetch_scale": sf, "write_scale": sw, "kernels": {}}
-    names = {"rtc::cfr_fused_kernel<10>": "cfr_loss_adjoint",
+    names = {"rtc::cfr_fused_kernel<10, true>": "cfr_loss_adjoint",
+             "rtc::cfr_fused_kernel<10, false>": "cfr_loss_adjoint_cfr",
              "rtc::cfr_kernel": "cfr", "rtc::cfr_adjoint_wave_kernel": "cfr_adjoint",
              "rtc::cfr_adjoint_kernel<8>": "cfr_adjoint_wg",
              "rtc::cfr_loss_wave_kernel<10, false>": "cfr_loss",
@@ -730,6 +736,10 @@ def main():
     if pipe.fused:
         out["separate_calls_step"] = separate_calls_step(st, radio, w, raw0, H_tgt,
                                                          min(args.steps, 5))
+        # the fused pass with the targets as H* and the stored target PDP
+        out["fused_cfr_targets_step"] = separate_calls_step(
+            st, radio, w, raw0, H_tgt, min(args.steps, 5), label="fused (H*, p* targets)",
+            targets="cfr")
     out["paper_loss_step"] = paper_loss_step(st, radio, w, raw0, H_tgt, min(args.steps, 5))
     del pipe, H_tgt
     torch.cuda.empty_cache()

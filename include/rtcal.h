@@ -266,6 +266,19 @@ rtc_status rtc_cfr_target_stats(const rtc_radio* radio, int32_t n_links, const v
                                 double* stats, float* p_tgt, void* ws, size_t ws_bytes,
                                 void* stream);
 
+/* The targets in the delay domain, for rtc_cfr_loss_adjoint_cir: per row
+ * (n_rows = n_links * n_elem) the unnormalised transform
+ *   X_tgt[row, k] = X*_k = sum_n H*[n] exp(+j 2 pi n k / N),  k = 0..N-1
+ * (c64, natural order; the same transform whose |X*_k|^2 / N is the target
+ * PDP of rtc_cfr_target_stats, Sec. II-A), and the same stats (device
+ * double [2]: sum |H*|^2, sum (p*)^2).  Computed once per target set, like
+ * p_tgt.  X_tgt: device c64 [n_links, n_elem, n_sc], must not alias H_tgt.
+ * ws: rtc_workspace_size(RTC_OP_CFR_TARGET_STATS, ...) bytes.  n_sc a power
+ * of two, 2 <= n_sc <= 4096. */
+rtc_status rtc_cfr_target_cir(const rtc_radio* radio, int32_t n_links, const void* H_tgt,
+                              double* stats, void* X_tgt, void* ws, size_t ws_bytes,
+                              void* stream);
+
 /* Coherent + power-delay-profile loss over a batch (workload loss):
  *   L = w_coh * sum|H - H*|^2 / sum|H*|^2 + w_pdp * sum (p - p*)^2 / sum (p*)^2
  * H, H_tgt: c64 [n_links, n_elem, n_sc].  tgt_stats: device double [2] from
@@ -386,6 +399,22 @@ rtc_status rtc_cfr_loss_adjoint(const rtc_radio* radio, const rtc_paths* paths, 
                                 const double* tgt_stats, const float* p_tgt, float w_coh,
                                 float w_pdp, double* loss, void* dLda, void* dLdg, void* ws,
                                 size_t ws_bytes, void* stream);
+
+/* rtc_cfr_loss_adjoint with the targets given in the delay domain: X_tgt
+ * and tgt_stats from rtc_cfr_target_cir of the same H_tgt.  The loss and
+ * its gradient are the same functions of H: by Parseval
+ * sum_n |H - H*|^2 = sum_k |X - X*|^2 / N with X the row's transform, the
+ * PDP target is |X*|^2 / N, and dL/dH = IDFT(2 w_coh / (N Z0) (X - X*) +
+ * 4 w_pdp / (N Z1) (p - p*) X) with the inverse transform unnormalised.  A
+ * row then reads its 8 bytes of target per subcarrier once, after its first
+ * transform, instead of H* (8 bytes) and p* (4 bytes) around both.  Shapes,
+ * accuracy and workspace as rtc_cfr_loss_adjoint
+ * (RTC_OP_CFR_LOSS_ADJOINT). */
+rtc_status rtc_cfr_loss_adjoint_cir(const rtc_radio* radio, const rtc_paths* paths,
+                                    const void* a, const float* psi, const void* g,
+                                    const void* X_tgt, const double* tgt_stats, float w_coh,
+                                    float w_pdp, double* loss, void* dLda, void* dLdg, void* ws,
+                                    size_t ws_bytes, void* stream);
 
 /* Adjoint of rtc_trace_fields: from dLda (c64 [n_paths]) to
  *   per-id mode:          dLd_raw  float [n_mat*3], gradient w.r.t. the raw

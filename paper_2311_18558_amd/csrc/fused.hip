@@ -59,23 +59,27 @@ struct Fz {
   static constexpr int GROUP = 8;         // element rows per loss group
   static constexpr int RPW = GROUP / NW;  // rows per wave per group
   static_assert(NW >= 1 && NW <= 8 && GROUP % NW == 0, "1 to 8 waves");
+  // LDS in two arrays, so that the compiler can tell the direct-to-LDS
+  // target loads (second array) from the row slots' traffic (first array)
+  // and does not wait for those loads at every slot access.
   // loss: eight row slots of Q + Q/16 + 16 float4 (a slot is also its row's
-  // FFT buffer, N + N/16 float2 with the bank shift of row_slot0), then each
-  // wave's H - H* of its current row
+  // FFT buffer, N + N/16 float2 with the bank shift of row_slot0) in the
+  // first array; each wave's N targets (then H - H*) in the second
   static constexpr int LDQ = Q + Q / 16 + 16;
   static constexpr int ROW_BYTES = (GROUP * LDQ + 16) * 16;
   static constexpr int DIFF_BYTES = NW * N * 8;
-  static constexpr int LOSS_BYTES = ROW_BYTES + DIFF_BYTES;
-  // adjoint: each wave's partial G of a tile, two tiles in flight
+  // adjoint: each wave's partial G of a tile, two tiles in flight (tile T
+  // in array T % 2)
   static constexpr int GBUF_FLOATS = 64 * 32;
-  static constexpr int GBUF_BYTES = 2 * NW * GBUF_FLOATS * 4;
+  static constexpr int GBUF_HALF = NW * GBUF_FLOATS * 4;
   // forward: one stage of NW x 8 paths, the path operand in FP16 parts
-  // and the delays (path_stage_store)
+  // and the delays (path_stage_store), in the first array
   static constexpr int ST_PATHS = path_stage_paths(NW * 64);
   static constexpr int ST_OPND_BYTES = path_stage_opnd_bytes(NW * 64);
   static constexpr int ST_BYTES = path_stage_bytes(NW * 64);
-  static constexpr int M2 = LOSS_BYTES > GBUF_BYTES ? LOSS_BYTES : GBUF_BYTES;
-  static constexpr int SMEM = M2 > ST_BYTES ? M2 : ST_BYTES;
+  static constexpr int cmax(int a, int b) { return a > b ? a : b; }
+  static constexpr int SMEM_A = cmax(cmax(ROW_BYTES, GBUF_HALF), ST_BYTES);
+  static constexpr int SMEM_B = cmax(DIFF_BYTES, GBUF_HALF);
 };
 
 struct FusedArgs {
@@ -85,8 +89,9 @@ struct FusedArgs {
   const float* psi;
   const double* tau;
   const float2* g;
-  const float2* Ht;  // targets c64 [L, M, N]
-  const float* Pt;   // target PDP f32 [L, M, N] (natural tap order)
+  const float2* Ht;  // targets c64 [L, M, N], or null with Xt
+  const float* Pt;   // target PDP f32 [L, M, N] (natural tap order), or null with Xt
+  const float2* Xt;  // or the targets' transforms X* c64 [L, M, N] (natural tap order)
   const double* Z;   // {sum |H*|^2, sum (p*)^2} over the batch
   float w_coh, w_pdp;
   double fref, t_off, df, cm;  // grid midpoint, t of pair 0, spacing, (M-1)/2
@@ -159,9 +164,9 @@ __device__ __forceinline__ void load_row_pdp(const float* Pt, int64_t ridx, int 
 // pass (lane j < BA) is pair j + BA (r - 8) (upper half, r >= 8) or
 // BA - 1 - j + BA (7 - r) (lower half) -- the mirror n -> N - 1 - n is lane
 // BA - 1 - j, register 15 - r.
-template <int LOGN>
+template <int LOGN, bool CIR>
 __device__ __forceinline__ void fused_loss_row(float4* row, const float* Pt, int64_t ridx,
-                                               float us,
+                                               const float2* tgt, int64_t next_ridx, float us,
                                                float2* dbuf, const float2* tw, float gc,
                                                float gp, double (&sums)[2], int lane_in) {
   // the FFT twiddles depend on the lane and the pass only; an opaque lane
@@ -178,6 +183,75 @@ __device__ __forceinline__ void fused_loss_row(float4* row, const float* Pt, int
   const float invN = 1.0f / (float)N;
   const int j = lane;
   const bool act = BA == 64 || j < BA;
+  float2* fb = reinterpret_cast<float2*>(row);
+  if constexpr (CIR) {
+    // targets as X*: the coherent sum by Parseval, sum |H - H*|^2 =
+    // sum |X - X*|^2 / N, and dL/dH = IDFT(gc/N (X - X*) + gp d X) (the
+    // unnormalised inverse of the forward transform returns N H).  The
+    // row's X* loads into registers now and is first used after the forward
+    // transform; plain loads, unlike direct-to-LDS ones, pass the group
+    // barriers without a wait.
+    float2 xs[JZ][RZ];
+    {
+      const float2* xr = tgt + ridx * N;
+#pragma unroll
+      for (int i = 0; i < JZ; ++i) {
+        const int jj = lane + 64 * i;
+#pragma unroll
+        for (int r = 0; r < RZ; ++r)
+          xs[i][r] = (BZ % 64 == 0 || jj < BZ) ? xr[jj + r * BZ] : make_float2(0.0f, 0.0f);
+      }
+    }
+    float2 vh[1][16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      float2 h = make_float2(0.0f, 0.0f);
+      if (act) {
+        if (r >= 8) {
+          const float4 v = row[j + BA * (r - 8)];
+          h = make_float2((v.x - v.w) * us, (v.y + v.z) * us);  // X + jY
+        } else {
+          const float4 v = row[BA - 1 - j + BA * (7 - r)];
+          h = make_float2((v.x + v.w) * us, (v.y - v.z) * us);  // X - jY
+        }
+      }
+      vh[0][r] = h;
+    }
+    float2 xh[JZ][RZ];
+    WaveSync::sync();  // the row's reads are done before the transform writes
+    fft_full<LOGN, +1, +1, WaveSync, 64, true>(vh, xh, fb, fb, lane, tw);
+    const float gcn = gc * invN;
+    float ec = 0.0f, ep = 0.0f;
+#pragma unroll
+    for (int i = 0; i < JZ; ++i) {
+      const int jj = lane + 64 * i;
+      if (BZ % 64 == 0 || jj < BZ) {
+#pragma unroll
+        for (int r = 0; r < RZ; ++r) {
+          const float2 dx = csub(xh[i][r], xs[i][r]);
+          ec += cabs2(dx);
+          const float d = cabs2(xh[i][r]) * invN - cabs2(xs[i][r]) * invN;  // p - p*
+          ep += d * d;
+          xh[i][r] = cadd(cscale(dx, gcn), cscale(xh[i][r], gp * d));
+        }
+      }
+    }
+    sums[0] += (double)ec * (double)invN;
+    sums[1] += (double)ep;
+    float2 G[1][16];
+    fft_full<LOGN, -1, -1, WaveSync, 64, true>(xh, G, fb, fb, lane, tw);
+    if (act) {
+      float2* half_slots = reinterpret_cast<float2*>(row);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        if (r >= 8)
+          half_slots[2 * (j + BA * (r - 8))] = G[0][r];
+        else
+          half_slots[2 * (BA - 1 - j + BA * (7 - r)) + 1] = G[0][r];
+      }
+    }
+    return;
+  }
   float tp[JZ][RZ];
   load_row_pdp<LOGN>(Pt, ridx, lane, tp);
   float2 vh[1][16];
@@ -199,7 +273,6 @@ __device__ __forceinline__ void fused_loss_row(float4* row, const float* Pt, int
     ec += cabs2(df);
     if (act) dbuf[r * BA + j] = df;
   }
-  float2* fb = reinterpret_cast<float2*>(row);
   float2 xh[JZ][RZ];
   WaveSync::sync();  // the row's reads are done before the transform writes
   fft_full<LOGN, +1, +1, WaveSync, 64, true>(vh, xh, fb, fb, lane, tw);
@@ -236,19 +309,22 @@ __device__ __forceinline__ void fused_loss_row(float4* row, const float* Pt, int
         half_slots[2 * (BA - 1 - j + BA * (7 - r)) + 1] = dh;
     }
   }
+  // the buffer's last reads are done: the next row's targets go in
+  if (next_ridx >= 0) prefetch_row_targets<LOGN>(tgt, next_ridx, dbuf, lane);
 }
 
-template <int LOGN>
+template <int LOGN, bool CIR>
 __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs A) {
   using F = Fz<LOGN>;
   constexpr int N = F::N, NW = F::NW, TPW = F::TPW, NCH = F::NCH;
   constexpr int NT = NW * 64;
-  __shared__ __align__(16) char smem[F::SMEM];
+  __shared__ __align__(16) char smem[F::SMEM_A];
+  __shared__ __align__(16) char smem_b[F::SMEM_B];
   __shared__ float wmax[NW];
   __shared__ float2 dabuf[2][NW * 64];
   __shared__ float2 twtab[N];  // FFT twiddles exp(j 2 pi k / N)
   float4* rowbuf = reinterpret_cast<float4*>(smem);
-  float* gbuf = reinterpret_cast<float*>(smem);
+  auto gbuf = [&](int b) { return reinterpret_cast<float*>(b ? smem_b : smem); };
 
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
@@ -265,8 +341,9 @@ __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs 
   // into the wave's LDS buffer while the forward product runs (the buffer
   // lies outside the forward's stage area).
   auto row_of = [&](int k) { return 8 * (k / F::RPW) + wv + NW * (k % F::RPW); };
-  float2* dbuf = reinterpret_cast<float2*>(smem + F::ROW_BYTES) + wv * N;
-  if (row_of(0) < M) prefetch_row_targets<LOGN>(A.Ht, l * M + row_of(0), dbuf, lane);
+  float2* dbuf = reinterpret_cast<float2*>(smem_b) + wv * N;
+  const float2* tgt = CIR ? A.Xt : A.Ht;
+  if (!CIR && row_of(0) < M) prefetch_row_targets<LOGN>(tgt, l * M + row_of(0), dbuf, lane);
 
   // ------------------------------------------------------------ 1. forward
   // lane: element m = col (B operand A'), pair column col of each tile (A
@@ -347,11 +424,10 @@ __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs 
       const int k = grp * F::RPW + i;
       const int mrow = row_of(k);
       if (mrow < M) {
-        fused_loss_row<LOGN>(rowbuf + row_slot0(mrow & 7, F::LDQ), A.Pt, l * M + mrow,
-                             unscale, dbuf, twtab, gc, gp, sums, lane);
-        // the buffer's last reads are done: the next row's targets go in
         const int mnext = row_of(k + 1);
-        if (mnext < M) prefetch_row_targets<LOGN>(A.Ht, l * M + mnext, dbuf, lane);
+        fused_loss_row<LOGN, CIR>(rowbuf + row_slot0(mrow & 7, F::LDQ), A.Pt, l * M + mrow, tgt,
+                                  mnext < M ? l * M + mnext : -1, unscale, dbuf, twtab, gc, gp,
+                                  sums, lane);
       }
     }
     __syncthreads();
@@ -423,6 +499,9 @@ __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs 
     SI[c] = split2(si);
     NDR[c] = split2(nd);
     DI[c] = split2(di);
+    // packed here: the FP32 values die before the adjoint loop starts
+    asm volatile("" : "+v"(SR[c].h), "+v"(SR[c].l), "+v"(SI[c].h), "+v"(SI[c].l));
+    asm volatile("" : "+v"(NDR[c].h), "+v"(NDR[c].l), "+v"(DI[c].h), "+v"(DI[c].l));
   }
 
   // The epilogue of a tile is split over the waves by element rows, RPL rows
@@ -500,7 +579,7 @@ __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs 
     }
     // the waves' partial sums over their pairs meet in LDS (two buffers,
     // alternating by tile; register r at float r*64 + lane, conflict-free)
-    float* gb = gbuf + ((T & 1) * NW + wv) * F::GBUF_FLOATS;
+    float* gb = gbuf(T & 1) + wv * F::GBUF_FLOATS;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       gb[r * 64 + lane] = gre[r];
@@ -509,7 +588,7 @@ __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs 
     __syncthreads();
     if (T > 0 && wv == (T - 1) % NW) finish_da(T - 1);
     // this wave's rows of the tile: rows m = 8 g4 + 4 half + qq, column = path
-    const float* g0 = gbuf + (T & 1) * NW * F::GBUF_FLOATS;
+    const float* g0 = gbuf(T & 1);
     const float2 ai = ok ? A.a[p] : make_float2(0.0f, 0.0f);
     const double psi_cyc = (double)(ok ? A.psi[p] : 0.0f) * kInv2Pi;
     const float2 cc = cconj(expm2pi_f64_hw(A.fref * tau));  // conj(c_p)
@@ -599,13 +678,13 @@ size_t ws_cfr_loss_adjoint(const rtc_radio* r, int32_t n_links) {
 
 using namespace rtc;
 
-extern "C" rtc_status rtc_cfr_loss_adjoint(const rtc_radio* radio, const rtc_paths* paths,
-                                           const void* a, const float* psi, const void* g,
-                                           const void* H_tgt, const double* tgt_stats,
-                                           const float* p_tgt, float w_coh, float w_pdp,
-                                           double* loss, void* dLda, void* dLdg, void* ws,
-                                           size_t ws_bytes, void* stream) {
-  const char* fn = "rtc_cfr_loss_adjoint";
+// The fused pass with the targets as H* and p* (Xt null) or as X* (Ht and
+// Pt null); the arguments are checked by the entry points below.
+static rtc_status fused_run(const char* fn, const rtc_radio* radio, const rtc_paths* paths,
+                            const void* a, const float* psi, const void* g, const void* H_tgt,
+                            const float* p_tgt, const void* X_tgt, const double* tgt_stats,
+                            float w_coh, float w_pdp, double* loss, void* dLda, void* dLdg,
+                            void* ws, size_t ws_bytes, void* stream) {
   rtc_status st;
   if ((st = check_radio(radio, fn)) != RTC_OK) return st;
   if ((st = check_paths(paths, fn, false)) != RTC_OK) return st;
@@ -617,8 +696,8 @@ extern "C" rtc_status rtc_cfr_loss_adjoint(const rtc_radio* radio, const rtc_pat
   RTC_REQUIRE(g != nullptr, RTC_ERR_INVALID_ARG, "%s: g is NULL", fn);
   RTC_REQUIRE((a != nullptr && psi != nullptr) || paths->n_paths == 0, RTC_ERR_INVALID_ARG,
               "%s: a and psi are required", fn);
-  RTC_REQUIRE(H_tgt && tgt_stats && p_tgt && loss, RTC_ERR_INVALID_ARG,
-              "%s: H_tgt, tgt_stats, p_tgt and loss are required", fn);
+  RTC_REQUIRE(((H_tgt && p_tgt) || X_tgt) && tgt_stats && loss, RTC_ERR_INVALID_ARG,
+              "%s: the targets, tgt_stats and loss are required", fn);
   const size_t need = ws_cfr_loss_adjoint(radio, paths->n_links);
   RTC_REQUIRE(ws != nullptr && ws_bytes >= need, RTC_ERR_WORKSPACE,
               "%s: workspace of %zu bytes required", fn, need);
@@ -644,6 +723,7 @@ extern "C" rtc_status rtc_cfr_loss_adjoint(const rtc_radio* radio, const rtc_pat
   A.g = reinterpret_cast<const float2*>(g);
   A.Ht = reinterpret_cast<const float2*>(H_tgt);
   A.Pt = p_tgt;
+  A.Xt = reinterpret_cast<const float2*>(X_tgt);
   A.Z = tgt_stats;
   A.w_coh = w_coh;
   A.w_pdp = w_pdp;
@@ -655,17 +735,25 @@ extern "C" rtc_status rtc_cfr_loss_adjoint(const rtc_radio* radio, const rtc_pat
   A.row_out = rows;
   A.dLda = reinterpret_cast<float2*>(dLda);
   A.g_part = dLdg ? gpart : nullptr;
+  const bool cir = X_tgt != nullptr;
+#define RTC_FUSED(LG)                                                                         \
+  if (cir)                                                                                    \
+    hipLaunchKernelGGL((cfr_fused_kernel<LG, true>), dim3((unsigned)L), dim3(Fz<LG>::NW * 64), \
+                       0, s, A);                                                              \
+  else                                                                                        \
+    hipLaunchKernelGGL((cfr_fused_kernel<LG, false>), dim3((unsigned)L),                      \
+                       dim3(Fz<LG>::NW * 64), 0, s, A);
   switch (N) {
     case 256:
-      hipLaunchKernelGGL(cfr_fused_kernel<8>, dim3((unsigned)L), dim3(Fz<8>::NW * 64), 0, s, A);
+      RTC_FUSED(8)
       break;
     case 512:
-      hipLaunchKernelGGL(cfr_fused_kernel<9>, dim3((unsigned)L), dim3(Fz<9>::NW * 64), 0, s, A);
+      RTC_FUSED(9)
       break;
     default:
-      hipLaunchKernelGGL(cfr_fused_kernel<10>, dim3((unsigned)L), dim3(Fz<10>::NW * 64), 0, s,
-                         A);
+      RTC_FUSED(10)
   }
+#undef RTC_FUSED
   if ((st = check_launch(fn)) != RTC_OK) return st;
   if ((st = reduce_all(rows, R, 2, rtmp, sums, s, fn)) != RTC_OK) return st;
   hipLaunchKernelGGL(fused_finish_kernel, dim3(1), dim3(64), 0, s, sums, tgt_stats, w_coh, w_pdp,
@@ -678,4 +766,28 @@ extern "C" rtc_status rtc_cfr_loss_adjoint(const rtc_radio* radio, const rtc_pat
     return check_launch(fn);
   }
   return RTC_OK;
+}
+
+extern "C" rtc_status rtc_cfr_loss_adjoint(const rtc_radio* radio, const rtc_paths* paths,
+                                           const void* a, const float* psi, const void* g,
+                                           const void* H_tgt, const double* tgt_stats,
+                                           const float* p_tgt, float w_coh, float w_pdp,
+                                           double* loss, void* dLda, void* dLdg, void* ws,
+                                           size_t ws_bytes, void* stream) {
+  const char* fn = "rtc_cfr_loss_adjoint";
+  RTC_REQUIRE(H_tgt && p_tgt, RTC_ERR_INVALID_ARG, "%s: H_tgt and p_tgt are required", fn);
+  return fused_run(fn, radio, paths, a, psi, g, H_tgt, p_tgt, nullptr, tgt_stats, w_coh, w_pdp,
+                   loss, dLda, dLdg, ws, ws_bytes, stream);
+}
+
+extern "C" rtc_status rtc_cfr_loss_adjoint_cir(const rtc_radio* radio, const rtc_paths* paths,
+                                               const void* a, const float* psi, const void* g,
+                                               const void* X_tgt, const double* tgt_stats,
+                                               float w_coh, float w_pdp, double* loss,
+                                               void* dLda, void* dLdg, void* ws,
+                                               size_t ws_bytes, void* stream) {
+  const char* fn = "rtc_cfr_loss_adjoint_cir";
+  RTC_REQUIRE(X_tgt, RTC_ERR_INVALID_ARG, "%s: X_tgt is required", fn);
+  return fused_run(fn, radio, paths, a, psi, g, nullptr, nullptr, X_tgt, tgt_stats, w_coh, w_pdp,
+                   loss, dLda, dLdg, ws, ws_bytes, stream);
 }

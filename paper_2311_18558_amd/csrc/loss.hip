@@ -143,11 +143,12 @@ __global__ void __launch_bounds__(fft_threads(LOGN))
 }
 
 // Target statistics per row {sum |H*|^2, sum (p*)^2}; with Pt also the
-// target PDP p* (natural tap order) for later loss calls.
+// target PDP p* (natural tap order) for later loss calls, with Xt the
+// transform X* itself (natural tap order).
 template <int LOGN>
 __global__ void __launch_bounds__(fft_threads(LOGN))
     target_stats_wave_kernel(const float2* __restrict__ Ht, int64_t n_rows, double* row_out,
-                             float* Pt) {
+                             float* Pt, float2* Xt) {
   constexpr int N = 1 << LOGN;
   constexpr int NP = fft_npass(LOGN);
   constexpr int RA = fft_radix(LOGN, 0), RZ = fft_radix(LOGN, NP - 1);
@@ -185,6 +186,7 @@ __global__ void __launch_bounds__(fft_threads(LOGN))
           const float pt = cabs2(xt[i][r]) * invN;
           eq += pt * pt;
           if (Pt) Pt[row * N + j + r * BZ] = pt;
+          if (Xt) Xt[row * N + j + r * BZ] = xt[i][r];
         }
       }
     }
@@ -299,12 +301,12 @@ static unsigned wave_grid(int64_t R) {
 }
 
 static void launch_target_stats(int logN, const float2* Ht, int64_t R, double* rows, float* Pt,
-                                hipStream_t s) {
+                                float2* Xt, hipStream_t s) {
   switch (logN) {
 #define RTC_TS(L)                                                                            \
   case L:                                                                                    \
     hipLaunchKernelGGL(target_stats_wave_kernel<L>, dim3(wave_grid(R)),                      \
-                       dim3(fft_threads(L)), 0, s, Ht, R, rows, Pt);                         \
+                       dim3(fft_threads(L)), 0, s, Ht, R, rows, Pt, Xt);                     \
     return;
     RTC_TS(1) RTC_TS(2) RTC_TS(3) RTC_TS(4) RTC_TS(5) RTC_TS(6) RTC_TS(7) RTC_TS(8) RTC_TS(9)
     RTC_TS(10) RTC_TS(11) RTC_TS(12)
@@ -365,7 +367,31 @@ extern "C" rtc_status rtc_cfr_target_stats(const rtc_radio* radio, int32_t n_lin
   double* red = rows + R * 4;
   int N = radio->n_sc, logN = ilog2(N);
   (void)N;
-  launch_target_stats(logN, reinterpret_cast<const float2*>(H_tgt), R, rows, p_tgt, s);
+  launch_target_stats(logN, reinterpret_cast<const float2*>(H_tgt), R, rows, p_tgt, nullptr, s);
+  if ((st = check_launch(fn)) != RTC_OK) return st;
+  return reduce_all(rows, R, 2, red, stats, s, fn);
+}
+
+extern "C" rtc_status rtc_cfr_target_cir(const rtc_radio* radio, int32_t n_links,
+                                         const void* H_tgt, double* stats, void* X_tgt, void* ws,
+                                         size_t ws_bytes, void* stream) {
+  const char* fn = "rtc_cfr_target_cir";
+  rtc_status st;
+  if ((st = check_radio(radio, fn)) != RTC_OK) return st;
+  if ((st = check_fft_n(radio, fn)) != RTC_OK) return st;
+  RTC_REQUIRE(n_links >= 1, RTC_ERR_SHAPE, "%s: n_links must be >= 1", fn);
+  RTC_REQUIRE(H_tgt && stats && X_tgt, RTC_ERR_INVALID_ARG,
+              "%s: H_tgt, stats and X_tgt are required", fn);
+  RTC_REQUIRE(X_tgt != H_tgt, RTC_ERR_INVALID_ARG, "%s: X_tgt must not alias H_tgt", fn);
+  int64_t R = (int64_t)n_links * radio->n_elem;
+  size_t need = ws_target_stats(radio, n_links);
+  RTC_REQUIRE(ws != nullptr && ws_bytes >= need, RTC_ERR_WORKSPACE,
+              "%s: workspace of %zu bytes required", fn, need);
+  hipStream_t s = as_stream(stream);
+  double* rows = reinterpret_cast<double*>(ws);
+  double* red = rows + R * 4;
+  launch_target_stats(ilog2(radio->n_sc), reinterpret_cast<const float2*>(H_tgt), R, rows,
+                      nullptr, reinterpret_cast<float2*>(X_tgt), s);
   if ((st = check_launch(fn)) != RTC_OK) return st;
   return reduce_all(rows, R, 2, red, stats, s, fn);
 }
@@ -385,7 +411,8 @@ static rtc_status cfr_loss_run(const char* fn, const rtc_radio* radio, int32_t n
   int logN = ilog2(radio->n_sc);
   const double* Zuse = tgt_stats;
   if (dLdH && !tgt_stats) {
-    launch_target_stats(logN, reinterpret_cast<const float2*>(H_tgt), R, rows, nullptr, s);
+    launch_target_stats(logN, reinterpret_cast<const float2*>(H_tgt), R, rows, nullptr, nullptr,
+                        s);
     if ((st = check_launch(fn)) != RTC_OK) return st;
     if ((st = reduce_all(rows, R, 2, red, Z, s, fn)) != RTC_OK) return st;
     Zuse = Z;

@@ -960,14 +960,16 @@ __global__ void __launch_bounds__(kTraceBlock)
     __syncthreads();
     if (lacc) {
       // the columns of each material entry: quarter qt of the threads'
-      // columns summed in order by one thread (FP64), the quarters in order
+      // columns summed by one thread (FP64) in a fixed order that starts at
+      // its own column t % 64 (so the lanes of a wave read 64 different
+      // banks), the quarters in order
       const int n_e = 3 * A.n_mat, nq = (int)blockDim.x / 64;
       double* qsum = acc + GL.stride * n_waves + (3 * A.n_mat * blockDim.x + 1) / 2;
       for (int t = threadIdx.x; t < n_e * nq; t += blockDim.x) {
         const int e = t / nq, qt = t % nq;
         const float* src = lacc + e * (int)blockDim.x + 64 * qt;
         double v = 0.0;
-        for (int k = 0; k < 64; ++k) v += (double)src[k];
+        for (int k = 0; k < 64; ++k) v += (double)src[(k + t) & 63];
         qsum[t] = v;
       }
       __syncthreads();

@@ -81,6 +81,8 @@ _SIGS = {
                                c_vp, c_vp]),
     "rtc_cfr_target_stats": (ctypes.c_int, [ctypes.POINTER(Radio), c_i32, c_vp, c_vp, c_vp,
                                             c_vp, c_size, c_vp]),
+    "rtc_cfr_target_cir": (ctypes.c_int, [ctypes.POINTER(Radio), c_i32, c_vp, c_vp, c_vp, c_vp,
+                                          c_size, c_vp]),
     "rtc_cfr_loss": (ctypes.c_int, [ctypes.POINTER(Radio), c_i32, c_vp, c_vp, c_vp, c_vp, c_f32,
                                     c_f32, c_vp, c_vp, c_vp, c_size, c_vp]),
     "rtc_cfr_loss_noalloc": (ctypes.c_int, [ctypes.POINTER(Radio), c_i32, c_vp, c_vp, c_vp,
@@ -95,6 +97,9 @@ _SIGS = {
     "rtc_cfr_loss_adjoint": (ctypes.c_int, [ctypes.POINTER(Radio), ctypes.POINTER(Paths), c_vp,
                                             c_vp, c_vp, c_vp, c_vp, c_vp, c_f32, c_f32, c_vp,
                                             c_vp, c_vp, c_vp, c_size, c_vp]),
+    "rtc_cfr_loss_adjoint_cir": (ctypes.c_int, [ctypes.POINTER(Radio), ctypes.POINTER(Paths),
+                                                c_vp, c_vp, c_vp, c_vp, c_vp, c_f32, c_f32, c_vp,
+                                                c_vp, c_vp, c_vp, c_size, c_vp]),
     "rtc_trace_fields_adjoint": (ctypes.c_int, [ctypes.POINTER(Radio), ctypes.POINTER(Paths),
                                                 ctypes.POINTER(Materials), c_vp, c_vp, c_vp,
                                                 c_vp, c_size, c_vp]),
@@ -353,6 +358,14 @@ def cfr_target_stats(radio, n_links, H_tgt, stats, ws, stream=None, p_tgt=None):
            "rtc_cfr_target_stats")
 
 
+def cfr_target_cir(radio, n_links, H_tgt, stats, X_tgt, ws, stream=None):
+    """X_tgt: complex64 [n_links, n_elem, n_sc] receiving the targets'
+    transforms X*_k = sum_n H*[n] exp(+j 2 pi n k / N) (for cfr_loss_adjoint_cir)."""
+    _check(load().rtc_cfr_target_cir(ctypes.byref(radio), n_links, _ptr(H_tgt), _ptr(stats),
+                                     _ptr(X_tgt), _ptr(ws), ws.numel(), _stream(stream)),
+           "rtc_cfr_target_cir")
+
+
 def cfr_loss(radio, n_links, H, H_tgt, tgt_stats, w_coh, w_pdp, loss, dLdH, ws, stream=None,
              p_tgt=None):
     """p_tgt: optional target PDP from cfr_target_stats for the same H_tgt."""
@@ -418,6 +431,17 @@ def cfr_loss_adjoint(radio, paths, a, psi, g, H_tgt, tgt_stats, p_tgt, w_coh, w_
                                        _ptr(dLda), _ptr(dLdg), _ptr(ws),
                                        0 if ws is None else ws.numel(), _stream(stream)),
            "rtc_cfr_loss_adjoint")
+
+
+def cfr_loss_adjoint_cir(radio, paths, a, psi, g, X_tgt, tgt_stats, w_coh, w_pdp, loss, dLda,
+                         dLdg, ws, stream=None):
+    """cfr_loss_adjoint with the targets as their transforms X* and stats
+    from cfr_target_cir (the same loss and gradient)."""
+    _check(load().rtc_cfr_loss_adjoint_cir(ctypes.byref(radio), ctypes.byref(paths.c), _ptr(a),
+                                           _ptr(psi), _ptr(g), _ptr(X_tgt), _ptr(tgt_stats),
+                                           float(w_coh), float(w_pdp), _ptr(loss), _ptr(dLda),
+                                           _ptr(dLdg), _ptr(ws), 0 if ws is None else ws.numel(),
+                                           _stream(stream)), "rtc_cfr_loss_adjoint_cir")
 
 
 def trace_fields_adjoint(radio, paths, mats, dLda, dLd_raw, dLd_inter, ws, stream=None):

@@ -24,9 +24,14 @@ from . import lib
 
 class Pipeline:
     def __init__(self, store, radio, raw0, g0, device="cuda", stream=None, loss="workload",
-                 update_alpha=False, delta=0.99, fused=True):
+                 update_alpha=False, delta=0.99, fused=True, targets="cir"):
         if loss not in ("workload", "paper"):
             raise ValueError(loss)
+        if targets not in ("cir", "cfr"):
+            raise ValueError(targets)
+        # the fused pass takes the targets as their transforms X* ("cir") or
+        # as H* with the target PDP ("cfr"); the same loss either way
+        self.targets = targets
         self.loss_kind = loss
         self.update_alpha, self.delta = update_alpha, delta
         self.dev = torch.device(device)
@@ -69,6 +74,7 @@ class Pipeline:
         self.t = 0
         self.H_tgt = None
         self.tgt_stats = None
+        self.p_tgt = self.X_tgt = None
 
     # individual stages (each one library call)
     def trace(self):
@@ -92,11 +98,19 @@ class Pipeline:
             return
         # the separate loss reads H* for its coherent term anyway and forms p*
         # from it with one more transform per row (24 B per tap instead of 28
-        # with a stored p*, and measured faster); the fused pass takes p*
-        # stored
+        # with a stored p*, and measured faster); the fused pass takes X*
+        # (8 B per tap), or H* and a stored p* (12 B per tap)
         self.tgt_stats = torch.empty(2, dtype=torch.float64, device=self.dev)
-        self.p_tgt = (torch.empty((self.L, self.M, self.N), dtype=torch.float32, device=self.dev)
-                      if self.fused else None)
+        self.p_tgt = self.X_tgt = None
+        if self.fused and self.targets == "cir":
+            self.X_tgt = torch.empty((self.L, self.M, self.N), dtype=torch.complex64,
+                                     device=self.dev)
+            lib.cfr_target_cir(self.radio, self.L, H_tgt, self.tgt_stats, self.X_tgt,
+                               self.ws_loss, self.stream)
+            return
+        if self.fused:
+            self.p_tgt = torch.empty((self.L, self.M, self.N), dtype=torch.float32,
+                                     device=self.dev)
         lib.cfr_target_stats(self.radio, self.L, H_tgt, self.tgt_stats, self.ws_loss, self.stream,
                              p_tgt=self.p_tgt)
 
@@ -110,6 +124,11 @@ class Pipeline:
                      self.loss, self.H, self.ws_loss, self.stream, p_tgt=self.p_tgt)
 
     def cfr_loss_adjoint(self):
+        if self.X_tgt is not None:
+            lib.cfr_loss_adjoint_cir(self.radio, self.paths, self.a, self.psi, self.g, self.X_tgt,
+                                     self.tgt_stats, 1.0, 1.0, self.loss, self.dLda, self.dLdg,
+                                     self.ws_fused, self.stream)
+            return
         lib.cfr_loss_adjoint(self.radio, self.paths, self.a, self.psi, self.g, self.H_tgt,
                              self.tgt_stats, self.p_tgt, 1.0, 1.0, self.loss, self.dLda,
                              self.dLdg, self.ws_fused, self.stream)

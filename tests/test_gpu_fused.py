@@ -89,8 +89,10 @@ def _targets(st, raw, radio, g):
     return och.cfr(st.link_off, st.tau, a_t, p_t, torch.tensor(g_t), f).to(torch.complex64)
 
 
-def _run_both(rl, st, radio, a32, p32, g32, Ht, w=(1.0, 1.0)):
-    """Fused and separate entry points on the same device inputs."""
+def _run_both(rl, st, radio, a32, p32, g32, Ht, w=(1.0, 1.0), cir_out=None):
+    """Fused and separate entry points on the same device inputs; with
+    cir_out (a list) the fused pass with delay-domain targets too, its
+    (loss, dL/da, dL/dg) appended there."""
     L, M, N, P = st.n_links, radio.n_elem, radio.n_sc, st.n_paths
     dp = rl.DevicePaths(st)
     rc = rl.radio_from(radio)
@@ -105,6 +107,20 @@ def _run_both(rl, st, radio, a32, p32, g32, Ht, w=(1.0, 1.0)):
     dLdg = torch.full((M,), float("nan"), dtype=torch.complex64, device="cuda")
     ws = rl.workspace(rl.RTC_OP_CFR_LOSS_ADJOINT, rc, L, P)
     rl.cfr_loss_adjoint(rc, dp, a, psi, g, Htd, stats, p_tgt, w[0], w[1], loss, dLda, dLdg, ws)
+    if cir_out is not None:
+        # targets as X* (rtc_cfr_target_cir); H* and p* are not read
+        stats_c = torch.empty(2, dtype=torch.float64, device="cuda")
+        X_tgt = torch.empty((L, M, N), dtype=torch.complex64, device="cuda")
+        rl.cfr_target_cir(rc, L, Htd, stats_c, X_tgt,
+                          rl.workspace(rl.RTC_OP_CFR_TARGET_STATS, rc, L, P))
+        lc = torch.full((3,), float("nan"), dtype=torch.float64, device="cuda")
+        dac = torch.full((P,), float("nan"), dtype=torch.complex64, device="cuda")
+        dgc = torch.full((M,), float("nan"), dtype=torch.complex64, device="cuda")
+        rl.cfr_loss_adjoint_cir(rc, dp, a, psi, g, X_tgt, stats_c, w[0], w[1], lc, dac, dgc, ws)
+        torch.cuda.synchronize()
+        assert torch.equal(stats_c.cpu(), stats.cpu())
+        del X_tgt
+        cir_out.append((lc.cpu(), dac.cpu().to(c128), dgc.cpu().to(c128)))
     # the same through the three separate calls
     H = torch.empty((L, M, N), dtype=torch.complex64, device="cuda")
     rl.cfr(rc, dp, a, psi, g, H)
@@ -143,7 +159,9 @@ def test_fused_against_oracle(rl, case):
     g32 = torch.tensor(g)
     Ht = _targets(st, raw, radio, g)
     w = (0.8, 1.3)
-    (loss, da, dg), (loss2, da2, dg2) = _run_both(rl, st, radio, a32, p32, g32, Ht, w)
+    cir = []
+    (loss, da, dg), (loss2, da2, dg2) = _run_both(rl, st, radio, a32, p32, g32, Ht, w, cir)
+    (loss3, da3, dg3), = cir
     # oracle: the same inputs in FP64, reverse mode
     a64 = a32.to(c128).requires_grad_(True)
     g64 = g32.to(c128).requires_grad_(True)
@@ -151,13 +169,18 @@ def test_fused_against_oracle(rl, case):
     H = och.cfr(st.link_off, st.tau, a64, p32.to(f64), g64, f)
     tot, coh, inc = och.cfr_loss(H, Ht.to(c128), w_coh=w[0], w_pdp=w[1])
     da_ref, dg_ref = torch.autograd.grad(tot, (a64, g64))
-    for got, ref in zip(loss.tolist(), (tot.item(), coh.item(), inc.item())):
+    for got, got3, ref in zip(loss.tolist(), loss3.tolist(), (tot.item(), coh.item(), inc.item())):
         assert abs(got - ref) <= 1e-5 * abs(ref), (got, ref)
+        assert abs(got3 - ref) <= 1e-5 * abs(ref), (got3, ref)
     e_a, e_al, e_g = _rel(da, da_ref), _per_link(da, da_ref, st.link_off), _rel(dg, dg_ref)
     e_a2, e_g2 = _rel(da2, da_ref), _rel(dg2, dg_ref)
+    e_a3, e_al3, e_g3 = _rel(da3, da_ref), _per_link(da3, da_ref, st.link_off), _rel(dg3, dg_ref)
     say(f"fused {case}: dL/da {e_a:.2e} (per link {e_al:.2e}), dL/dg {e_g:.2e}; "
+        f"delay-domain targets {e_a3:.2e} ({e_al3:.2e}), {e_g3:.2e}; "
         f"separate calls {e_a2:.2e}, {e_g2:.2e}; fused vs separate {_rel(da, da2):.2e}")
     assert e_a <= 3e-5 and e_al <= 1e-4 and e_g <= 3e-5, (e_a, e_al, e_g)
+    assert e_a3 <= 3e-5 and e_al3 <= 1e-4 and e_g3 <= 3e-5, (e_a3, e_al3, e_g3)
+    assert torch.isfinite(da3).all()
     # links without paths get no gradient entries; every path gets one
     assert torch.isfinite(da).all()
     # and the separate calls agree with it
@@ -195,6 +218,8 @@ def test_fused_without_outputs_and_refusals(rl):
         with pytest.raises(RuntimeError, match="rtc_cfr_loss_adjoint.*separate|use rtc_cfr"):
             rl.cfr_loss_adjoint(rb, dp, a, psi, gd, Ht, stats, p_tgt, 1.0, 1.0, l1, None, None,
                                 ws)
+        with pytest.raises(RuntimeError, match="rtc_cfr_loss_adjoint_cir.*use rtc_cfr"):
+            rl.cfr_loss_adjoint_cir(rb, dp, a, psi, gd, Ht, stats, 1.0, 1.0, l1, None, None, ws)
 
 
 def test_fused_full_scale_sampled_links(rl):
@@ -215,8 +240,11 @@ def test_fused_full_scale_sampled_links(rl):
     power[np.diff(st.link_off) == 0] = 1e-12
     Ht = draw_target_cfr(rng, power, M, N)
     say(f"fused full scale: L={L} P={P}")
+    cir = []
     (loss, da, dg), (loss2, da2, dg2) = _run_both(
-        rl, st, radio, torch.tensor(a32), torch.tensor(p32), torch.tensor(w.g), torch.tensor(Ht))
+        rl, st, radio, torch.tensor(a32), torch.tensor(p32), torch.tensor(w.g), torch.tensor(Ht),
+        cir_out=cir)
+    (loss3, da3, dg3), = cir
     # batch normalisers by the oracle, in chunks of rows
     zc, zp = 0.0, 0.0
     Ht_rows = Ht.reshape(-1, N)
@@ -234,10 +262,44 @@ def test_fused_full_scale_sampled_links(rl):
     e_c, _, e_p, _ = och.cfr_loss_sums(H, torch.tensor(Ht[links]).to(c128))
     (da_ref,) = torch.autograd.grad(e_c / zc + e_p / zp, a64)
     worst = _per_link(da[sel], da_ref, off)
-    say(f"fused full scale: sampled links dL/da max per-link error {worst:.2e}; "
+    worst3 = _per_link(da3[sel], da_ref, off)
+    say(f"fused full scale: sampled links dL/da max per-link error {worst:.2e} "
+        f"(delay-domain targets {worst3:.2e}); "
         f"fused vs separate dL/da {_rel(da, da2):.2e}, dL/dg {_rel(dg, dg2):.2e}, "
-        f"loss {loss.tolist()} vs {loss2.tolist()}")
-    assert worst <= 1e-4
+        f"loss {loss.tolist()} vs {loss2.tolist()} vs {loss3.tolist()}")
+    assert worst <= 1e-4 and worst3 <= 1e-4
     assert _rel(da, da2) <= 3e-5 and _rel(dg, dg2) <= 3e-5
-    for x, y in zip(loss.tolist(), loss2.tolist()):
-        assert abs(x - y) <= 1e-5 * abs(y)
+    assert _rel(da3, da2) <= 3e-5 and _rel(dg3, dg2) <= 3e-5
+    for x, x3, y in zip(loss.tolist(), loss3.tolist(), loss2.tolist()):
+        assert abs(x - y) <= 1e-5 * abs(y) and abs(x3 - y) <= 1e-5 * abs(y)
+
+
+@pytest.mark.parametrize("n_sc", [2, 16, 256, 1024, 4096])
+def test_target_cir_transform(rl, n_sc):
+    """rtc_cfr_target_cir: X* per row against the unnormalised transform
+    with exp(+j 2 pi n k / N) (numpy's inverse FFT times N, FP64), and
+    |X*|^2 / N bit-equal to the target PDP of rtc_cfr_target_stats with the
+    same statistics (the same transform, the same FP32 arithmetic)."""
+    L, M = 5, 3
+    rng = np.random.default_rng(n_sc)
+    Ht = (rng.standard_normal((L, M, n_sc)) + 1j * rng.standard_normal((L, M, n_sc)))
+    Ht = Ht.astype(np.complex64)
+    rc = rl.make_radio(3.5e9, 50e6 / n_sc, n_sc, M)
+    Htd = torch.tensor(Ht).cuda()
+    ws = rl.workspace(rl.RTC_OP_CFR_TARGET_STATS, rc, L, 0)
+    s1 = torch.empty(2, dtype=torch.float64, device="cuda")
+    s2 = torch.empty(2, dtype=torch.float64, device="cuda")
+    X = torch.empty((L, M, n_sc), dtype=torch.complex64, device="cuda")
+    p = torch.empty((L, M, n_sc), dtype=torch.float32, device="cuda")
+    rl.cfr_target_cir(rc, L, Htd, s1, X, ws)
+    rl.cfr_target_stats(rc, L, Htd, s2, ws, p_tgt=p)
+    torch.cuda.synchronize()
+    Xc = X.cpu().numpy()
+    ref = n_sc * np.fft.ifft(Ht.astype(np.complex128), axis=-1)
+    err = np.linalg.norm(Xc - ref) / np.linalg.norm(ref)
+    say(f"target cir N={n_sc}: rel err {err:.2e}")
+    assert err <= 1e-6
+    Xt = X.cpu()
+    pc = (Xt.real * Xt.real + Xt.imag * Xt.imag) * (1.0 / n_sc)
+    assert torch.equal(s1.cpu(), s2.cpu())
+    np.testing.assert_allclose(pc.numpy(), p.cpu().numpy(), rtol=2e-7, atol=0)
