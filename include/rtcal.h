@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define RTC_ABI_VERSION 7
+#define RTC_ABI_VERSION 8
 
 typedef enum {
   RTC_OK = 0,
