@@ -4,7 +4,11 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdarg>
+#include <cstdint>
 #include <cstdio>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "rtcal.h"
 
@@ -28,6 +32,28 @@ inline rtc_status check_launch(const char* what) {
 rtc_status check_radio(const rtc_radio* r, const char* fn);
 rtc_status check_paths(const rtc_paths* p, const char* fn, bool need_geometry);
 rtc_status check_mats(const rtc_materials* m, const rtc_paths* p, const char* fn);
+
+// Workgroups of `threads` threads of `kernel` that the current device keeps
+// resident at once (its CUs times the occupancy), for persistent launches;
+// looked up once per device and block size (a host query, no stream work).
+inline int64_t resident_workgroups(const void* kernel, int threads) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, const void*, int>, int64_t> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 1024;
+  std::lock_guard<std::mutex> lock(mu);
+  const auto key = std::make_tuple(dev, kernel, threads);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int cus = 0, per_cu = 0;
+  int64_t n = 1024;  // a safe number if a query fails
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) == hipSuccess &&
+      cus > 0 && per_cu > 0)
+    n = (int64_t)cus * per_cu;
+  cache[key] = n;
+  return n;
+}
 
 inline bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
 

@@ -90,14 +90,19 @@ RTC_DEV void cfr_pair_tile(const Split2& AR, const Split2& AI, const Split2& UR,
 // layout in LDS); each wave reads it back with four 16-byte loads per 16
 // paths and forms its subcarrier operand u_i(t_q) directly from FP64-reduced
 // phases (no recurrence, no shuffles).
-__global__ void __launch_bounds__(kCfrWaves * 64) cfr_kernel(CfrArgs A, float2* __restrict__ H) {
+// Persistent: the launch holds as many workgroups as the device keeps
+// resident, and each takes work items b = blockIdx.x + k gridDim.x, so the
+// H stores of one item drain while the next item's products run (one
+// workgroup per CU at this register count).
+__global__ void __launch_bounds__(kCfrWaves * 64)
+    cfr_kernel(CfrArgs A, float2* __restrict__ H, int64_t n_work) {
   __shared__ __align__(16) char smem[kCfrStageBytes];
   const int nt = blockDim.x;
   const int lane = threadIdx.x & 63;
   const int half = lane >> 5;
   const int col = lane & 31;
   const int wv = threadIdx.x >> 6;
-  const int64_t b = blockIdx.x;
+  for (int64_t b = blockIdx.x; b < n_work; b += gridDim.x) {
   const int qg = (int)(b % A.n_qchunk);
   const int64_t rest = b / A.n_qchunk;
   const int mblk = (int)(rest % A.n_mblk);
@@ -173,6 +178,7 @@ __global__ void __launch_bounds__(kCfrWaves * 64) cfr_kernel(CfrArgs A, float2* 
       }
     }
   }
+  }  // work items
 }
 
 // ------------------------------------------------------------------ adjoint
@@ -1070,9 +1076,10 @@ extern "C" rtc_status rtc_cfr(const rtc_radio* radio, const rtc_paths* paths, co
     return check_launch(fn);
   }
   const int64_t blocks = (int64_t)A.n_links * A.n_mblk * A.n_qchunk;
-  RTC_REQUIRE(blocks < (1ll << 31), RTC_ERR_RANGE, "%s: problem too large for one launch", fn);
-  hipLaunchKernelGGL(cfr_kernel, dim3((unsigned)blocks), dim3(nw * 64), 0, as_stream(stream), A,
-                     reinterpret_cast<float2*>(H));
+  const int64_t grid = std::min<int64_t>(blocks, resident_workgroups(
+                                                     (const void*)cfr_kernel, nw * 64));
+  hipLaunchKernelGGL(cfr_kernel, dim3((unsigned)grid), dim3(nw * 64), 0, as_stream(stream), A,
+                     reinterpret_cast<float2*>(H), blocks);
   return check_launch(fn);
 }
 
