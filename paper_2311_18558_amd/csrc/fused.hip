@@ -537,19 +537,20 @@ __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs 
       A.dLda[p] = d;
     }
   };
-  const int n_tiles = (int)((off1 - off0 + 31) >> 5);
-  // the lane's path delay, a tile ahead (its phases start each tile)
-  double tau_nx = off0 + col < off1 ? A.tau[off0 + col] : 0.0;
-  for (int T = 0; T < n_tiles; ++T) {
-    const int64_t p = off0 + 32 * (int64_t)T + col;
-    const bool ok = p < off1;
-    const double tau = tau_nx;
-    tau_nx = p + 32 < off1 ? A.tau[p + 32] : 0.0;
+  // the gains of the lane's epilogue rows (zero for rows >= M), loaded once
+  float2 gep[RPL];
+#pragma unroll
+  for (int i = 0; i < RPL; ++i)
+    gep[i] = ep_row(i) < M ? A.g[ep_row(i)] : make_float2(0.0f, 0.0f);
+  // One tile's products: the wave's partial G~ of the tile's 32 paths (tau:
+  // the lane's path delay).  G~ = X - jY: Re G~ += S_re Re u + D_im Im u,
+  // Im G~ += S_im Re u - D_re Im u
+  auto tile_products = [&](double tau, floatx16& gre, floatx16& gim) {
     const float2 v1 = expm2pi_f64_hw(A.df * tau);
     const float2 v8 = expm2pi_f64_hw(8.0 * A.df * tau);
     const float2 v16 = expm2pi_f64_hw(16.0 * A.df * tau);
-    // G~ = X - jY: Re G~ += S_re Re u + D_im Im u, Im G~ += S_im Re u - D_re Im u
-    floatx16 gre = floatx16{0}, gim = floatx16{0};
+    gre = floatx16{0};
+    gim = floatx16{0};
     float2 e0 = make_float2(1.0f, 0.0f);
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
@@ -577,20 +578,23 @@ __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs 
       gre = mac3(DI[c], UI, gre);
       gim = mac3(NDR[c], UI, gim);
     }
-    // the waves' partial sums over their pairs meet in LDS (two buffers,
-    // alternating by tile; register r at float r*64 + lane, conflict-free)
+  };
+  // the waves' partial sums over their pairs meet in LDS (two buffers,
+  // alternating by tile; register r at float r*64 + lane, conflict-free)
+  auto tile_store = [&](int T, const floatx16& gre, const floatx16& gim) {
     float* gb = gbuf(T & 1) + wv * F::GBUF_FLOATS;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       gb[r * 64 + lane] = gre[r];
       gb[(16 + r) * 64 + lane] = gim[r];
     }
-    __syncthreads();
-    if (T > 0 && wv == (T - 1) % NW) finish_da(T - 1);
-    // this wave's rows of the tile: rows m = 8 g4 + 4 half + qq, column = path
+  };
+  // The epilogue of tile T, its G~ complete in gbuf(T & 1): this wave's rows
+  // of the tile, its half-wave's share of dL/da into dabuf[T & 1] (added in
+  // order by the wave that finishes the tile) and dL/dg into dgw.  ai,
+  // psi_cyc, tau: the lane's path of the tile (zero past the link).
+  auto tile_epilogue = [&](int T, float2 ai, double psi_cyc, double tau) {
     const float* g0 = gbuf(T & 1);
-    const float2 ai = ok ? A.a[p] : make_float2(0.0f, 0.0f);
-    const double psi_cyc = (double)(ok ? A.psi[p] : 0.0f) * kInv2Pi;
     const float2 cc = cconj(expm2pi_f64_hw(A.fref * tau));  // conj(c_p)
     const float2 step = expm2pi_f64_hw(psi_cyc);
     float2 da = make_float2(0.0f, 0.0f);
@@ -611,17 +615,57 @@ __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs 
         gi += g0[w * F::GBUF_FLOATS + (16 + r) * 64 + ep_src];
       }
       const float2 G = cmul(cc, make_float2(gr * unsca, gi * unsca));
-      const float2 gmv = mrow < M ? A.g[mrow] : make_float2(0.0f, 0.0f);
       const float2 Gph = cmul(G, ph);
-      da = cadd(da, cmulc(gmv, Gph));
+      da = cadd(da, cmulc(gep[i], Gph));
       // dL/dg: sum over the 32 paths of this half (fixed butterfly)
       const float2 tg = cmulc(ai, Gph);
       dgw[i][0] += (double)half_sum_f32(tg.x);
       dgw[i][1] += (double)half_sum_f32(tg.y);
     }
-    // the half-wave's share of dL/da (its rows of the path), added in order
-    // by the wave that finishes the tile
     dabuf[T & 1][wv * 64 + lane] = da;
+  };
+  // the lane's path data of tile T, loaded without a branch (index clamped
+  // to the link, values zeroed past it)
+  auto tile_path = [&](int T, float2& ai, double& psi_cyc, double& tau) {
+    const int64_t p = off0 + 32 * (int64_t)T + col;
+    const bool ok = p < off1;
+    const int64_t pc = ok ? p : off1 - 1;
+    const float2 a = A.a[pc];
+    const float ps = A.psi[pc];
+    const double tv = A.tau[pc];
+    ai = ok ? a : make_float2(0.0f, 0.0f);
+    psi_cyc = (double)(ok ? ps : 0.0f) * kInv2Pi;
+    tau = ok ? tv : 0.0;
+  };
+  // Software-pipelined by one tile: tile T's products are issued in the same
+  // straight-line code as tile T - 1's epilogue (VALU and LDS work), so the
+  // matrix cores and the vector units overlap; one barrier per tile.
+  const int n_tiles = (int)((off1 - off0 + 31) >> 5);
+  if (n_tiles > 0) {
+    float2 ai_c;
+    double psi_c, tau_c;
+    tile_path(0, ai_c, psi_c, tau_c);
+    {
+      floatx16 gre, gim;
+      tile_products(tau_c, gre, gim);
+      tile_store(0, gre, gim);
+    }
+    __syncthreads();
+    for (int T = 1; T < n_tiles; ++T) {
+      float2 ai_t;
+      double psi_t, tau_t;
+      tile_path(T, ai_t, psi_t, tau_t);
+      floatx16 gre, gim;
+      tile_products(tau_t, gre, gim);
+      tile_epilogue(T - 1, ai_c, psi_c, tau_c);
+      tile_store(T, gre, gim);
+      __syncthreads();
+      if (wv == (T - 1) % NW) finish_da(T - 1);
+      ai_c = ai_t;
+      psi_c = psi_t;
+      tau_c = tau_t;
+    }
+    tile_epilogue(n_tiles - 1, ai_c, psi_c, tau_c);
   }
   __syncthreads();  // the last tile's shares are in LDS; every epilogue is done
   if (n_tiles > 0 && wv == (n_tiles - 1) % NW) finish_da(n_tiles - 1);
