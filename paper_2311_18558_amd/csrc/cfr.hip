@@ -90,10 +90,10 @@ RTC_DEV void cfr_pair_tile(const Split2& AR, const Split2& AI, const Split2& UR,
 // layout in LDS); each wave reads it back with four 16-byte loads per 16
 // paths and forms its subcarrier operand u_i(t_q) directly from FP64-reduced
 // phases (no recurrence, no shuffles).
-// Persistent: the launch holds as many workgroups as the device keeps
-// resident, and each takes work items b = blockIdx.x + k gridDim.x, so the
-// H stores of one item drain while the next item's products run (one
-// workgroup per CU at this register count).
+// Work items b = blockIdx.x + k gridDim.x: with short links the launch holds
+// only the workgroups the device keeps resident (one per CU at this register
+// count), so the H stores of one item drain while the next item's products
+// run; otherwise one workgroup per item.
 __global__ void __launch_bounds__(kCfrWaves * 64)
     cfr_kernel(CfrArgs A, float2* __restrict__ H, int64_t n_work) {
   __shared__ __align__(16) char smem[kCfrStageBytes];
@@ -1076,8 +1076,14 @@ extern "C" rtc_status rtc_cfr(const rtc_radio* radio, const rtc_paths* paths, co
     return check_launch(fn);
   }
   const int64_t blocks = (int64_t)A.n_links * A.n_mblk * A.n_qchunk;
-  const int64_t grid = std::min<int64_t>(blocks, resident_workgroups(
-                                                     (const void*)cfr_kernel, nw * 64));
+  // persistent workgroups for short links (their stores are a large part of
+  // an item); long links of uneven length balance better one workgroup per
+  // item, dispatched by the hardware as CUs free up
+  const bool persistent = paths->n_paths < 512 * (int64_t)paths->n_links;
+  const int64_t grid =
+      persistent ? std::min<int64_t>(blocks, resident_workgroups((const void*)cfr_kernel, nw * 64))
+                 : blocks;
+  RTC_REQUIRE(grid < (1ll << 31), RTC_ERR_RANGE, "%s: problem too large for one launch", fn);
   hipLaunchKernelGGL(cfr_kernel, dim3((unsigned)grid), dim3(nw * 64), 0, as_stream(stream), A,
                      reinterpret_cast<float2*>(H), blocks);
   return check_launch(fn);
