@@ -241,3 +241,41 @@ def test_validate_argument_checks(lib):
     st = so.rtc_validate_paths(ctypes.byref(p), 3, q, q, 8, None)
     assert st == -4 and b"workspace" in so.rtc_last_error()
     assert lib.workspace_size(lib.RTC_OP_VALIDATE_PATHS, None, 0, 0, 0) > 0
+
+
+def test_delay_domain_target_argument_checks(lib):
+    """rtc_cfr_target_cir and rtc_cfr_loss_adjoint_cir reject missing or
+    aliased targets, non-power-of-two grids, unsupported shapes and short
+    workspaces on the host."""
+    so = lib.load()
+    r = _radio(lib)
+    vp = ctypes.c_void_p
+    st = so.rtc_cfr_target_cir(ctypes.byref(r), 4, vp(16), vp(32), None, vp(64), 1 << 20, None)
+    assert st == -1 and b"X_tgt" in so.rtc_last_error()
+    st = so.rtc_cfr_target_cir(ctypes.byref(r), 4, vp(16), vp(32), vp(16), vp(64), 1 << 20, None)
+    assert st == -1 and b"alias" in so.rtc_last_error()
+    odd = lib.make_radio(3.5e9, 1e5, 200, 4)
+    st = so.rtc_cfr_target_cir(ctypes.byref(odd), 4, vp(16), vp(32), vp(48), vp(64), 1 << 20,
+                               None)
+    assert st == -6 and b"power of two" in so.rtc_last_error()
+    st = so.rtc_cfr_target_cir(ctypes.byref(r), 4, vp(16), vp(32), vp(48), vp(64), 8, None)
+    assert st == -4 and b"workspace" in so.rtc_last_error()
+    # the fused pass with delay-domain targets
+    off = (ctypes.c_int64 * 2)(0, 0)
+    p = lib.Paths()
+    p.n_links, p.n_paths, p.max_depth = 1, 0, 0
+    p.link_off = ctypes.cast(off, ctypes.c_void_p)
+    st = so.rtc_cfr_loss_adjoint_cir(ctypes.byref(r), ctypes.byref(p), None, None, vp(16), None,
+                                     vp(32), 1.0, 1.0, vp(48), None, None, vp(64), 1 << 20, None)
+    assert st == -1 and b"X_tgt" in so.rtc_last_error()
+    st = so.rtc_cfr_loss_adjoint_cir(ctypes.byref(r), ctypes.byref(p), None, None, vp(16), vp(24),
+                                     None, 1.0, 1.0, vp(48), None, None, vp(64), 1 << 20, None)
+    assert st == -1 and b"tgt_stats" in so.rtc_last_error()
+    big = lib.make_radio(3.5e9, 1e5, 2048, 4)
+    st = so.rtc_cfr_loss_adjoint_cir(ctypes.byref(big), ctypes.byref(p), None, None, vp(16),
+                                     vp(24), vp(32), 1.0, 1.0, vp(48), None, None, vp(64),
+                                     1 << 20, None)
+    assert st == -6 and b"rtc_cfr_loss_adjoint_cir" in so.rtc_last_error()
+    st = so.rtc_cfr_loss_adjoint_cir(ctypes.byref(r), ctypes.byref(p), None, None, vp(16), vp(24),
+                                     vp(32), 1.0, 1.0, vp(48), None, None, vp(64), 8, None)
+    assert st == -4 and b"workspace" in so.rtc_last_error()
