@@ -49,10 +49,14 @@ class Calibrator:
     def __init__(self, dp, radio, H_all, mode, raw0=None, mlp_params0=None, g0=None,
                  aabb=None, lr=0.01, lr_mlp=1e-3, lr_gain=None, device="cuda", loss="workload",
                  update_alpha=False, delta=0.99, embed0=None, n_vmf=0, tx_raw0=None,
-                 pat_raw0=None):
+                 pat_raw0=None, fused=True):
         """embed0 = (v [L], W [n_mat, 4, L]) for mode 'embed'; n_vmf, tx_raw0
         [1 + 5 n_vmf] the initial raw Tx gain; pat_raw0 [n_mat, 6] the
-        initial raw scattering patterns (see rtc_patterns)."""
+        initial raw scattering patterns (see rtc_patterns).  fused: with the
+        workload loss at shapes the fused pass takes, each step runs CFR,
+        loss and CFR adjoint as one library call on the batch's targets in
+        the delay domain (rtc_cfr_target_cir, rtc_cfr_loss_adjoint_cir);
+        fused=False keeps the three separate calls."""
         if loss not in ("workload", "paper"):
             raise ValueError(loss)
         if mode not in ("per_id", "neural", "embed"):
@@ -61,6 +65,8 @@ class Calibrator:
             raise ValueError("scattering patterns are calibrated per material (per_id, embed)")
         self.dev = torch.device(device)
         self.loss_kind, self.update_alpha, self.delta = loss, update_alpha, delta
+        self.fused = bool(fused) and loss == "workload" and lib.fused_supported(
+            lib.radio_from(radio))
         self.alpha = torch.tensor([1.0, 0.0], dtype=torch.float64, device=self.dev)
         self.dp = dp
         self.radio = lib.radio_from(radio)
@@ -173,9 +179,26 @@ class Calibrator:
         b = lib.subset_links(self.dp, links)[0] if batch is None else batch
         L, P = b.n_links, b.n_paths
         M, N = self.radio.n_elem, self.radio.n_sc
+        loss = self._buf("loss", (3,), torch.float64)
+        dLda = self._buf("dLda", (P,), torch.complex64)
+        dLdg = self._buf("dLdg", (M,), torch.complex64)
+        if self.fused:
+            # the batch's targets as X* with their statistics (one transform
+            # per row, as the separate loss forms p* from H*), then CFR, loss
+            # and CFR adjoint in one pass: H and dL/dH stay on chip
+            Xt = self._buf("Xt", (L, M, N), torch.complex64)
+            tstats = self._buf("tstats", (2,), torch.float64)
+            lib.cfr_target_cir(self.radio, L, self.H_all[links], tstats, Xt,
+                               self._ws(lib.RTC_OP_CFR_TARGET_STATS, L, P))
+            mats, aux = self._materials(b)
+            a = self._buf("a", (P,), torch.complex64)
+            psi = self._buf("psi", (P,), torch.float32)
+            lib.trace_fields_pat(self.radio, b, mats, self.pats, a, psi)
+            lib.cfr_loss_adjoint_cir(self.radio, b, a, psi, self.g, Xt, tstats, 1.0, 1.0, loss,
+                                     dLda, dLdg, self._ws(lib.RTC_OP_CFR_LOSS_ADJOINT, L, P))
+            return self._backward_and_update(b, mats, aux, dLda, dLdg, loss, update)
         H = self._buf("H", (L, M, N), torch.complex64)
         mats, aux, a, psi = self.forward(b, H)
-        loss = self._buf("loss", (3,), torch.float64)
         if self.loss_kind == "paper":
             tgt = self.tgt_all[links].reshape(-1, 2)
             lib.paper_loss(self.radio, L, H, tgt, self.alpha, loss, H,
@@ -184,10 +207,15 @@ class Calibrator:
         else:
             lib.cfr_loss(self.radio, L, H, self.H_all[links], None, 1.0, 1.0, loss, H,
                          self._ws(lib.RTC_OP_CFR_LOSS, L, P))
-        dLda = self._buf("dLda", (P,), torch.complex64)
-        dLdg = self._buf("dLdg", (M,), torch.complex64)
         lib.cfr_adjoint(self.radio, b, a, psi, self.g, H, dLda, dLdg,
                         self._ws(lib.RTC_OP_CFR_ADJOINT, L, P))
+        return self._backward_and_update(b, mats, aux, dLda, dLdg, loss, update)
+
+    def _backward_and_update(self, b, mats, aux, dLda, dLdg, loss, update):
+        """From dL/da and dL/dg of the batch to the parameter gradients
+        (trace adjoint, MLP or embedding backward) and, with update, one
+        Adam step."""
+        L, P = b.n_links, b.n_paths
         op = (lib.RTC_OP_TRACE_FIELDS_ADJOINT_PAT if self.with_patterns
               else lib.RTC_OP_TRACE_FIELDS_ADJOINT)
         if self.mode != "neural":
