@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define RTC_ABI_VERSION 8
+#define RTC_ABI_VERSION 9
 
 typedef enum {
   RTC_OK = 0,
@@ -292,6 +292,19 @@ rtc_status rtc_cfr_loss(const rtc_radio* radio, int32_t n_links, const void* H,
                         const void* H_tgt, const double* tgt_stats, const float* p_tgt,
                         float w_coh, float w_pdp, double* loss, void* dLdH, void* ws,
                         size_t ws_bytes, void* stream);
+
+/* rtc_cfr_loss with the targets given as their transforms X* (X_tgt, c64
+ * [n_links, n_elem, n_sc], from rtc_cfr_target_cir): the same loss and
+ * dL/dH (by Parseval sum |H - H*|^2 = sum |X - X*|^2 / N, p* = |X*|^2 / N,
+ * dL/dH = IDFT(2 w_coh / (N Z0) (X - X*) + 4 w_pdp / (N Z1) (p - p*) X) with
+ * the unnormalised inverse), in two transforms per row instead of three.
+ * tgt_stats: from rtc_cfr_target_cir, required with dLdH (without it the
+ * loss is normalised by the batch's own target sums).  dLdH may alias H.
+ * ws: rtc_workspace_size(RTC_OP_CFR_LOSS, ...) bytes.  n_sc a power of two,
+ * 2 <= n_sc <= 4096. */
+rtc_status rtc_cfr_loss_cir(const rtc_radio* radio, int32_t n_links, const void* H,
+                            const void* X_tgt, const double* tgt_stats, float w_coh, float w_pdp,
+                            double* loss, void* dLdH, void* ws, size_t ws_bytes, void* stream);
 
 /* rtc_cfr_loss for callers that cannot allocate memory (code recorded into
  * a HIP graph, tight serving loops, harnesses that forbid hipMalloc): the

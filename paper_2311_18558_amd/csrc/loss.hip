@@ -34,7 +34,12 @@ constexpr int kRedChunk = 64;  // rows per reduction block (first two levels)
 // the target PDP comes precomputed (p_tgt from the target statistics)
 // instead of from a transform of H*.
 
-template <int LOGN, bool PT>
+// TGT: 0 = targets H* (p* by a transform of H*), 1 = H* and a stored p*,
+// 2 = the targets' transforms X* (rtc_cfr_target_cir): then the coherent
+// term is taken by Parseval, sum |H - H*|^2 = sum |X - X*|^2 / N, the PDP
+// target is |X*|^2 / N, and dL/dH = IDFT(gc/N (X - X*) + gp (p - p*) X)
+// (unnormalised inverse): two transforms per row and nothing of H* kept.
+template <int LOGN, int TGT>
 __global__ void __launch_bounds__(fft_threads(LOGN))
     cfr_loss_wave_kernel(const float2* H, const float2* __restrict__ Ht,
                          const float* __restrict__ Pt, int64_t n_rows, const double* Z,
@@ -59,8 +64,72 @@ __global__ void __launch_bounds__(fft_threads(LOGN))
     const float2* hs = H + row * N;
     const float2* ts = Ht + row * N;
     float ec = 0.0f, et = 0.0f;
+    if constexpr (TGT == 2) {
+      // X* in the last pass's layout (natural tap order j + r BZ)
+      float2 xs[JZ][RZ];
+#pragma unroll
+      for (int i = 0; i < JZ; ++i) {
+        const int j = lane + T * i;
+#pragma unroll
+        for (int r = 0; r < RZ; ++r)
+          xs[i][r] = (BZ % T == 0 || j < BZ) ? ts[j + r * BZ] : make_float2(0.0f, 0.0f);
+      }
+      float2 vh[JA][RA];
+#pragma unroll
+      for (int i = 0; i < JA; ++i) {
+        const int j = lane + T * i;
+#pragma unroll
+        for (int r = 0; r < RA; ++r)
+          vh[i][r] = (BA % T == 0 || j < BA) ? hs[j + r * BA] : make_float2(0.0f, 0.0f);
+      }
+      float2 xh[JZ][RZ];
+      fft_full<LOGN, +1, +1, BlockSync, T>(vh, xh, b0, b1, lane);
+      const float gcn = gc * invN;
+      float ep = 0.0f, eq = 0.0f;
+#pragma unroll
+      for (int i = 0; i < JZ; ++i) {
+        const int j = lane + T * i;
+        if (BZ % T == 0 || j < BZ) {
+#pragma unroll
+          for (int r = 0; r < RZ; ++r) {
+            const float2 dx = csub(xh[i][r], xs[i][r]);
+            ec += cabs2(dx);
+            const float pt = cabs2(xs[i][r]) * invN;
+            et += pt;
+            const float d = cabs2(xh[i][r]) * invN - pt;
+            ep += d * d;
+            eq += pt * pt;
+            xh[i][r] = cadd(cscale(dx, gcn), cscale(xh[i][r], gp * d));
+          }
+        }
+      }
+      double s1 = group_sum_f64<T>((double)ec * (double)invN, red);
+      double s2 = group_sum_f64<T>((double)et, red);
+      double s3 = group_sum_f64<T>((double)ep, red);
+      double s4 = group_sum_f64<T>((double)eq, red);
+      if (lane == 0) {
+        row_out[row * 4 + 0] = s1;
+        row_out[row * 4 + 1] = s2;
+        row_out[row * 4 + 2] = s3;
+        row_out[row * 4 + 3] = s4;
+      }
+      if (dLdH) {
+        float2 G[JA][RA];
+        fft_full<LOGN, -1, -1, BlockSync, T>(xh, G, b0, b1, lane);
+        float2* out = dLdH + row * N;
+#pragma unroll
+        for (int i = 0; i < JA; ++i) {
+          const int j = lane + T * i;
+          if (BA % T == 0 || j < BA) {
+#pragma unroll
+            for (int r = 0; r < RA; ++r) out[j + r * BA] = G[i][r];
+          }
+        }
+      }
+      continue;
+    }
     float pt[JZ][RZ];
-    if constexpr (PT) {
+    if constexpr (TGT == 1) {
       const float* ps = Pt + row * N;
 #pragma unroll
       for (int i = 0; i < JZ; ++i) {
@@ -316,18 +385,23 @@ static void launch_target_stats(int logN, const float2* Ht, int64_t R, double* r
   }
 }
 
-static void launch_loss(int logN, const float2* H, const float2* Ht, const float* Pt, int64_t R,
-                        const double* Z, float w_coh, float w_pdp, double* rows, float2* dLdH,
-                        hipStream_t s) {
+// tgt: the TGT mode of cfr_loss_wave_kernel (Ht is X* for mode 2)
+static void launch_loss(int logN, int tgt, const float2* H, const float2* Ht, const float* Pt,
+                        int64_t R, const double* Z, float w_coh, float w_pdp, double* rows,
+                        float2* dLdH, hipStream_t s) {
   switch (logN) {
 #define RTC_LW(L)                                                                             \
   case L:                                                                                     \
-    if (Pt)                                                                                   \
-      hipLaunchKernelGGL((cfr_loss_wave_kernel<L, true>), dim3(wave_grid(R)),                 \
+    if (tgt == 2)                                                                             \
+      hipLaunchKernelGGL((cfr_loss_wave_kernel<L, 2>), dim3(wave_grid(R)),                    \
+                         dim3(fft_threads(L)), 0, s, H, Ht, Pt, R, Z, w_coh, w_pdp, rows,     \
+                         dLdH);                                                               \
+    else if (tgt == 1)                                                                        \
+      hipLaunchKernelGGL((cfr_loss_wave_kernel<L, 1>), dim3(wave_grid(R)),                    \
                          dim3(fft_threads(L)), 0, s, H, Ht, Pt, R, Z, w_coh, w_pdp, rows,     \
                          dLdH);                                                               \
     else                                                                                      \
-      hipLaunchKernelGGL((cfr_loss_wave_kernel<L, false>), dim3(wave_grid(R)),                \
+      hipLaunchKernelGGL((cfr_loss_wave_kernel<L, 0>), dim3(wave_grid(R)),                    \
                          dim3(fft_threads(L)), 0, s, H, Ht, Pt, R, Z, w_coh, w_pdp, rows,     \
                          dLdH);                                                               \
     return;
@@ -417,8 +491,9 @@ static rtc_status cfr_loss_run(const char* fn, const rtc_radio* radio, int32_t n
     if ((st = reduce_all(rows, R, 2, red, Z, s, fn)) != RTC_OK) return st;
     Zuse = Z;
   }
-  launch_loss(logN, reinterpret_cast<const float2*>(H), reinterpret_cast<const float2*>(H_tgt),
-              p_tgt, R, Zuse, w_coh, w_pdp, rows, reinterpret_cast<float2*>(dLdH), s);
+  launch_loss(logN, p_tgt ? 1 : 0, reinterpret_cast<const float2*>(H),
+              reinterpret_cast<const float2*>(H_tgt), p_tgt, R, Zuse, w_coh, w_pdp, rows,
+              reinterpret_cast<float2*>(dLdH), s);
   if ((st = check_launch(fn)) != RTC_OK) return st;
   if ((st = reduce_all(rows, R, 4, red, sums, s, fn)) != RTC_OK) return st;
   hipLaunchKernelGGL(loss_finish_kernel, dim3(1), dim3(64), 0, s, sums, Zuse, w_coh, w_pdp, loss);
@@ -449,6 +524,37 @@ extern "C" rtc_status rtc_cfr_loss(const rtc_radio* radio, int32_t n_links, cons
               "%s: workspace of %zu bytes required", fn, need);
   return cfr_loss_run(fn, radio, n_links, H, H_tgt, tgt_stats, p_tgt, w_coh, w_pdp, loss, dLdH,
                       reinterpret_cast<double*>(ws), as_stream(stream));
+}
+
+extern "C" rtc_status rtc_cfr_loss_cir(const rtc_radio* radio, int32_t n_links, const void* H,
+                                       const void* X_tgt, const double* tgt_stats, float w_coh,
+                                       float w_pdp, double* loss, void* dLdH, void* ws,
+                                       size_t ws_bytes, void* stream) {
+  const char* fn = "rtc_cfr_loss_cir";
+  rtc_status st;
+  if ((st = check_radio(radio, fn)) != RTC_OK) return st;
+  if ((st = check_fft_n(radio, fn)) != RTC_OK) return st;
+  RTC_REQUIRE(n_links >= 1, RTC_ERR_SHAPE, "%s: n_links must be >= 1", fn);
+  RTC_REQUIRE(H && X_tgt && loss, RTC_ERR_INVALID_ARG, "%s: H, X_tgt and loss are required", fn);
+  RTC_REQUIRE(dLdH != X_tgt, RTC_ERR_INVALID_ARG, "%s: dLdH must not alias X_tgt", fn);
+  RTC_REQUIRE(tgt_stats || !dLdH, RTC_ERR_INVALID_ARG,
+              "%s: tgt_stats (rtc_cfr_target_cir) is required for dLdH", fn);
+  const size_t need = ws_cfr_loss(radio, n_links);
+  RTC_REQUIRE(ws != nullptr && ws_bytes >= need, RTC_ERR_WORKSPACE,
+              "%s: workspace of %zu bytes required", fn, need);
+  hipStream_t s = as_stream(stream);
+  const int64_t R = (int64_t)n_links * radio->n_elem;
+  double* rows = reinterpret_cast<double*>(ws);
+  double* red = rows + R * 4;
+  double* sums = red + (n_red1(R) + n_red1(n_red1(R)) + 1) * 4 + 2;
+  launch_loss(ilog2(radio->n_sc), 2, reinterpret_cast<const float2*>(H),
+              reinterpret_cast<const float2*>(X_tgt), nullptr, R, tgt_stats, w_coh, w_pdp, rows,
+              reinterpret_cast<float2*>(dLdH), s);
+  if ((st = check_launch(fn)) != RTC_OK) return st;
+  if ((st = reduce_all(rows, R, 4, red, sums, s, fn)) != RTC_OK) return st;
+  hipLaunchKernelGGL(loss_finish_kernel, dim3(1), dim3(64), 0, s, sums, tgt_stats, w_coh, w_pdp,
+                     loss);
+  return check_launch(fn);
 }
 
 // ------------------------------------------------ the allocation-free variant

@@ -85,6 +85,8 @@ _SIGS = {
                                           c_size, c_vp]),
     "rtc_cfr_loss": (ctypes.c_int, [ctypes.POINTER(Radio), c_i32, c_vp, c_vp, c_vp, c_vp, c_f32,
                                     c_f32, c_vp, c_vp, c_vp, c_size, c_vp]),
+    "rtc_cfr_loss_cir": (ctypes.c_int, [ctypes.POINTER(Radio), c_i32, c_vp, c_vp, c_vp, c_f32,
+                                        c_f32, c_vp, c_vp, c_vp, c_size, c_vp]),
     "rtc_cfr_loss_noalloc": (ctypes.c_int, [ctypes.POINTER(Radio), c_i32, c_vp, c_vp, c_vp,
                                             c_vp, c_f32, c_f32, c_vp, c_vp, c_vp]),
     "rtc_cfr_loss_noalloc_max_rows": (c_i64, []),
@@ -372,6 +374,16 @@ def cfr_loss(radio, n_links, H, H_tgt, tgt_stats, w_coh, w_pdp, loss, dLdH, ws, 
     _check(load().rtc_cfr_loss(ctypes.byref(radio), n_links, _ptr(H), _ptr(H_tgt), _ptr(tgt_stats),
                                _ptr(p_tgt), float(w_coh), float(w_pdp), _ptr(loss), _ptr(dLdH),
                                _ptr(ws), ws.numel(), _stream(stream)), "rtc_cfr_loss")
+
+
+def cfr_loss_cir(radio, n_links, H, X_tgt, tgt_stats, w_coh, w_pdp, loss, dLdH, ws,
+                 stream=None):
+    """cfr_loss with the targets as their transforms X* and stats from
+    cfr_target_cir (the same loss and gradient, two transforms per row)."""
+    _check(load().rtc_cfr_loss_cir(ctypes.byref(radio), n_links, _ptr(H), _ptr(X_tgt),
+                                   _ptr(tgt_stats), float(w_coh), float(w_pdp), _ptr(loss),
+                                   _ptr(dLdH), _ptr(ws), ws.numel(), _stream(stream)),
+           "rtc_cfr_loss_cir")
 
 
 def cfr_loss_noalloc(radio, n_links, H, H_tgt, tgt_stats, w_coh, w_pdp, loss, dLdH,

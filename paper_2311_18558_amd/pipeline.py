@@ -29,8 +29,10 @@ class Pipeline:
             raise ValueError(loss)
         if targets not in ("cir", "cfr"):
             raise ValueError(targets)
-        # the fused pass takes the targets as their transforms X* ("cir") or
-        # as H* with the target PDP ("cfr"); the same loss either way
+        # the targets as their transforms X* ("cir": the fused pass and the
+        # separate loss read X*) or as H* ("cfr": with the target PDP stored
+        # for the fused pass, formed per row by the separate loss); the same
+        # loss either way
         self.targets = targets
         self.loss_kind = loss
         self.update_alpha, self.delta = update_alpha, delta
@@ -96,13 +98,14 @@ class Pipeline:
             lib.cir_stats(self.radio, self.L, H_tgt, self.tgt_stats, self.stream)
             self.alpha.copy_(torch.tensor([1.0, 0.0], dtype=torch.float64))
             return
-        # the separate loss reads H* for its coherent term anyway and forms p*
-        # from it with one more transform per row (24 B per tap instead of 28
-        # with a stored p*, and measured faster); the fused pass takes X*
-        # (8 B per tap), or H* and a stored p* (12 B per tap)
+        # targets as X* (targets="cir"): the fused pass reads 8 B per tap of
+        # them, the separate loss runs two transforms per row; as H*
+        # (targets="cfr"): the fused pass takes H* and a stored p* (12 B per
+        # tap), the separate loss forms p* from H* by one more transform per
+        # row (24 B per tap instead of 28 with a stored p*, and faster)
         self.tgt_stats = torch.empty(2, dtype=torch.float64, device=self.dev)
         self.p_tgt = self.X_tgt = None
-        if self.fused and self.targets == "cir":
+        if self.targets == "cir":
             self.X_tgt = torch.empty((self.L, self.M, self.N), dtype=torch.complex64,
                                      device=self.dev)
             lib.cfr_target_cir(self.radio, self.L, H_tgt, self.tgt_stats, self.X_tgt,
@@ -119,6 +122,10 @@ class Pipeline:
             lib.paper_loss(self.radio, self.L, self.H, self.tgt_stats, self.alpha, self.loss,
                            self.H, self.ws_loss, update_alpha=self.update_alpha,
                            delta=self.delta, stream=self.stream)
+            return
+        if self.X_tgt is not None:
+            lib.cfr_loss_cir(self.radio, self.L, self.H, self.X_tgt, self.tgt_stats, 1.0, 1.0,
+                             self.loss, self.H, self.ws_loss, self.stream)
             return
         lib.cfr_loss(self.radio, self.L, self.H, self.H_tgt, self.tgt_stats, 1.0, 1.0,
                      self.loss, self.H, self.ws_loss, self.stream, p_tgt=self.p_tgt)

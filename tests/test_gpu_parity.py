@@ -242,7 +242,8 @@ def _pow2_cases():
 
 def _loss_check(rl, radio, L, Ht, H, mode):
     """mode: 'none' (the loss call derives everything from H*), 'stats'
-    (target energies given), 'stats_pdp' (energies and target PDP given)."""
+    (target energies given), 'stats_pdp' (energies and target PDP given),
+    'cir' (the targets as their transforms X*, rtc_cfr_loss_cir)."""
     M, N = radio.n_elem, radio.n_sc
     rc = _radio_c(rl, radio)
     Hd = torch.tensor(H, device="cuda")
@@ -256,7 +257,14 @@ def _loss_check(rl, radio, L, Ht, H, mode):
         rl.cfr_target_stats(rc, L, Htd, stats, ws, p_tgt=p_tgt)
     loss = torch.empty(3, dtype=torch.float64, device="cuda")
     dLdH = torch.empty_like(Hd)
-    rl.cfr_loss(rc, L, Hd, Htd, stats, 0.7, 1.3, loss, dLdH, ws, p_tgt=p_tgt)
+    if mode == "cir":
+        stats = torch.empty(2, dtype=torch.float64, device="cuda")
+        X = torch.full_like(Htd, float("nan"))
+        rl.cfr_target_cir(rc, L, Htd, stats, X, ws)
+        del Htd  # the loss reads X* only
+        rl.cfr_loss_cir(rc, L, Hd, X, stats, 0.7, 1.3, loss, dLdH, ws)
+    else:
+        rl.cfr_loss(rc, L, Hd, Htd, stats, 0.7, 1.3, loss, dLdH, ws, p_tgt=p_tgt)
     torch.cuda.synchronize()
     Hr = torch.tensor(H, dtype=c128, requires_grad=True)
     Ht64 = torch.tensor(Ht, dtype=c128)
@@ -280,7 +288,7 @@ def _loss_check(rl, radio, L, Ht, H, mode):
 
 
 @pytest.mark.parametrize("case", _pow2_cases())
-@pytest.mark.parametrize("mode", ["none", "stats", "stats_pdp"])
+@pytest.mark.parametrize("mode", ["none", "stats", "stats_pdp", "cir"])
 def test_cfr_loss_parity(rl, case, mode):
     st, raw, radio, g = CASES[case]
     rng = np.random.default_rng(5)
@@ -293,7 +301,7 @@ def test_cfr_loss_parity(rl, case, mode):
 
 
 @pytest.mark.parametrize("N", [2048, 4096])
-@pytest.mark.parametrize("mode", ["none", "stats_pdp"])
+@pytest.mark.parametrize("mode", ["none", "stats_pdp", "cir"])
 def test_cfr_loss_long_rows(rl, N, mode):
     """Rows longer than one wave's transform (the workgroup-per-row path)."""
     rng = np.random.default_rng(N)
