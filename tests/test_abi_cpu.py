@@ -279,3 +279,27 @@ def test_delay_domain_target_argument_checks(lib):
     st = so.rtc_cfr_loss_adjoint_cir(ctypes.byref(r), ctypes.byref(p), None, None, vp(16), vp(24),
                                      vp(32), 1.0, 1.0, vp(48), None, None, vp(64), 8, None)
     assert st == -4 and b"workspace" in so.rtc_last_error()
+
+
+def test_loss_with_delay_domain_targets_argument_checks(lib):
+    """rtc_cfr_loss_cir needs X_tgt, the statistics when it forms dL/dH, a
+    power-of-two grid and its workspace, all checked on the host."""
+    so = lib.load()
+    r = _radio(lib)
+    vp = ctypes.c_void_p
+    st = so.rtc_cfr_loss_cir(ctypes.byref(r), 4, vp(16), None, vp(32), 1.0, 1.0, vp(48), None,
+                             vp(64), 1 << 20, None)
+    assert st == -1 and b"X_tgt" in so.rtc_last_error()
+    st = so.rtc_cfr_loss_cir(ctypes.byref(r), 4, vp(16), vp(24), None, 1.0, 1.0, vp(48), vp(16),
+                             vp(64), 1 << 20, None)
+    assert st == -1 and b"tgt_stats" in so.rtc_last_error()
+    st = so.rtc_cfr_loss_cir(ctypes.byref(r), 4, vp(16), vp(24), vp(32), 1.0, 1.0, vp(48), vp(24),
+                             vp(64), 1 << 20, None)
+    assert st == -1 and b"alias" in so.rtc_last_error()
+    odd = lib.make_radio(3.5e9, 1e5, 200, 4)
+    st = so.rtc_cfr_loss_cir(ctypes.byref(odd), 4, vp(16), vp(24), vp(32), 1.0, 1.0, vp(48),
+                             None, vp(64), 1 << 20, None)
+    assert st == -6 and b"power of two" in so.rtc_last_error()
+    st = so.rtc_cfr_loss_cir(ctypes.byref(r), 4, vp(16), vp(24), vp(32), 1.0, 1.0, vp(48), None,
+                             vp(64), 8, None)
+    assert st == -4 and b"workspace" in so.rtc_last_error()
