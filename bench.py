@@ -515,7 +515,7 @@ def summarize_traffic(fetch_csv, write_csv):
              "rtc::cfr_fused_kernel<10, false>": "cfr_loss_adjoint_cfr",
              "rtc::cfr_kernel": "cfr", "rtc::cfr_adjoint_wave_kernel": "cfr_adjoint",
              "rtc::cfr_adjoint_kernel<8>": "cfr_adjoint_wg",
-             "rtc::cfr_loss_wave_kernel<10, false>": "cfr_loss",
+             "rtc::cfr_loss_wave_kernel<10, 2>": "cfr_loss",
              "rtc::paper_loss_wave_kernel<10, true>": "paper_loss",
              "rtc::gain_products_kernel": "gain_products"}
     lines = ["| kernel | dispatches | FETCH_SIZE (GB) | WRITE_SIZE (GB) | HBM read (GB) "
