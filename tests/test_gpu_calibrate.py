@@ -99,3 +99,44 @@ def test_paper_loss_calibration_with_unknown_scale(gpu_lib, small):
     assert m1["loss"] < 0.3 * m0["loss"]
     assert m1["ale"] < 0.3 * m0["ale"]
     assert abs(a1 * c - 1.0) < 0.1
+
+
+@pytest.mark.parametrize("mode", ["per_id", "neural"])
+def test_fused_step_matches_separate_calls(gpu_lib, small, mode):
+    """One Algorithm-1 step with the workload loss through the fused pass
+    (batch targets as X*, rtc_cfr_loss_adjoint_cir) and through the three
+    separate calls, from the same parameters on the same batch: the same
+    loss terms and the same gradients (materials or MLP, element gains)."""
+    from paper_2311_18558_amd import lib
+    from paper_2311_18558_amd.calibrate import Calibrator, mlp_out_bias, raw_prior, targets
+    from synth.params import mlp_init
+    w = small
+    say(f"fused vs separate calibration step ({mode})")
+    dp = lib.DevicePaths(w.store)
+    H = targets(dp, w.radio, raw=w.raw, g=w.g)
+    rng = np.random.default_rng(4)
+    g0 = (rng.uniform(0.9, 1.1, w.radio.n_elem)
+          * np.exp(1j * rng.uniform(-0.3, 0.3, w.radio.n_elem))).astype(np.complex64)
+    if mode == "per_id":
+        kw = dict(raw0=raw_prior(w.meta["n_mat"]))
+    else:
+        kw = dict(mlp_params0=mlp_init(np.random.default_rng(5), mlp_out_bias()), aabb=w.aabb)
+    cals = [Calibrator(dp, w.radio, H, mode, g0=g0, fused=f, **kw) for f in (True, False)]
+    assert cals[0].fused and not cals[1].fused
+    train = torch.tensor(w.meta["train"], device="cuda")
+    links = train[torch.tensor(rng.choice(len(train), 128, replace=False), device="cuda")]
+    out = []
+    for cal in cals:
+        loss = cal.step(links, update=False).clone()
+        torch.cuda.synchronize()
+        out.append((loss.cpu(), cal.dparams.detach().cpu().double().clone(),
+                    cal.dLdg.detach().cpu().to(torch.complex128).clone()))
+    (lf, gf, df), (ls, gs, ds) = out
+    rel = lambda a, b: (torch.linalg.norm(a - b) / torch.linalg.norm(b)).item()
+    say(f"loss {lf.tolist()} vs {ls.tolist()}; d params {rel(gf, gs):.2e}; d g {rel(df, ds):.2e}")
+    for x, y in zip(lf.tolist(), ls.tolist()):
+        assert abs(x - y) <= 1e-5 * abs(y)
+    # the MLP's backward rounds its deltas to BF16, so a few roundings may
+    # differ between the two (equal up to FP32 rounding) dL/da inputs
+    tol = 1e-4 if mode == "per_id" else 1e-3
+    assert rel(gf, gs) <= tol and rel(df, ds) <= 1e-4
