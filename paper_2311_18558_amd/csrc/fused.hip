@@ -80,6 +80,9 @@ struct Fz {
   static constexpr int cmax(int a, int b) { return a > b ? a : b; }
   static constexpr int SMEM_A = cmax(cmax(ROW_BYTES, GBUF_HALF), ST_BYTES);
   static constexpr int SMEM_B = cmax(DIFF_BYTES, GBUF_HALF);
+  // with X* targets at 1,024 subcarriers the loss takes 16 rows per group,
+  // eight slots in each array (the second holds no targets then)
+  static constexpr int SMEM_B16 = cmax(SMEM_B, ROW_BYTES);
 };
 
 struct FusedArgs {
@@ -319,7 +322,12 @@ __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs 
   constexpr int N = F::N, NW = F::NW, TPW = F::TPW, NCH = F::NCH;
   constexpr int NT = NW * 64;
   __shared__ __align__(16) char smem[F::SMEM_A];
-  __shared__ __align__(16) char smem_b[F::SMEM_B];
+  // rows per loss group: 16 (eight slots in each LDS array) with X* targets
+  // at 1,024 subcarriers (half the groups, so half the group barriers, and
+  // twice the lanes in each slot write and read-back), else 8
+  constexpr int GRP = (CIR && LOGN == 10) ? 16 : F::GROUP;
+  constexpr int RPW = GRP / NW;  // rows per wave per group
+  __shared__ __align__(16) char smem_b[GRP == 16 ? F::SMEM_B16 : F::SMEM_B];
   __shared__ float wmax[NW];
   __shared__ float2 dabuf[2][NW * 64];
   __shared__ float2 twtab[N];  // FFT twiddles exp(j 2 pi k / N)
@@ -336,11 +344,17 @@ __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs 
   const int64_t off1 = A.link_off[l + 1];
   const int q_base = wv * 32 * TPW;
   fft_tw_fill<N>(twtab, threadIdx.x, NT);  // read after the barriers below
-  // loss rows of this wave: k -> element row 8 (k / RPW) + wv + NW (k % RPW);
+  // loss rows of this wave: k -> element row GRP (k / RPW) + wv + NW (k % RPW);
   // the rows that exist (< M) are a prefix.  The first one's targets load
   // into the wave's LDS buffer while the forward product runs (the buffer
   // lies outside the forward's stage area).
-  auto row_of = [&](int k) { return 8 * (k / F::RPW) + wv + NW * (k % F::RPW); };
+  auto row_of = [&](int k) { return GRP * (k / RPW) + wv + NW * (k % RPW); };
+  // slot of row rl of a group: the first eight in the first array, the rest
+  // in the second
+  auto slot = [&](int rl) {
+    return rl < 8 ? rowbuf + row_slot0(rl, F::LDQ)
+                  : reinterpret_cast<float4*>(smem_b) + row_slot0(rl - 8, F::LDQ);
+  };
   float2* dbuf = reinterpret_cast<float2*>(smem_b) + wv * N;
   const float2* tgt = CIR ? A.Xt : A.Ht;
   if (!CIR && row_of(0) < M) prefetch_row_targets<LOGN>(tgt, l * M + row_of(0), dbuf, lane);
@@ -404,12 +418,12 @@ __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs 
   // --------------------------------------------------------------- 2. loss
   const float gc = (float)(2.0 * (double)A.w_coh / A.Z[0]);
   const float gp = (float)(4.0 * (double)A.w_pdp / (A.Z[1] * (double)N));
-  const int n_groups = (M + 7) >> 3;
+  const int n_groups = (M + GRP - 1) / GRP;
   double sums[2] = {0.0, 0.0};
   for (int grp = 0; grp < n_groups; ++grp) {
     __syncthreads();  // the forward's stage buffer, or the previous group's read-back, is done
-    if ((col >> 3) == grp) {
-      float4* row = rowbuf + row_slot0(col & 7, F::LDQ);
+    if (col / GRP == grp) {
+      float4* row = slot(col % GRP);
 #pragma unroll
       for (int t = 0; t < TPW; ++t)
 #pragma unroll
@@ -420,22 +434,22 @@ __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs 
     }
     __syncthreads();
 #pragma unroll 1
-    for (int i = 0; i < F::RPW; ++i) {
-      const int k = grp * F::RPW + i;
+    for (int i = 0; i < RPW; ++i) {
+      const int k = grp * RPW + i;
       const int mrow = row_of(k);
       if (mrow < M) {
         const int mnext = row_of(k + 1);
-        fused_loss_row<LOGN, CIR>(rowbuf + row_slot0(mrow & 7, F::LDQ), A.Pt, l * M + mrow, tgt,
+        fused_loss_row<LOGN, CIR>(slot(mrow % GRP), A.Pt, l * M + mrow, tgt,
                                   mnext < M ? l * M + mnext : -1, unscale, dbuf, twtab, gc, gp,
                                   sums, lane);
       }
     }
     __syncthreads();
-    if ((col >> 3) == grp) {
+    if (col / GRP == grp) {
       // slot q: {dL/dH[N/2 + q], dL/dH[N/2 - 1 - q]} -> S = hi + lo,
       // D = hi - lo; rows m >= M hold X = Y = 0 (zero gains), read back as
       // zero operands
-      const float4* row = rowbuf + row_slot0(col & 7, F::LDQ);
+      const float4* row = slot(col % GRP);
 #pragma unroll
       for (int t = 0; t < TPW; ++t)
 #pragma unroll
