@@ -80,8 +80,8 @@ struct Fz {
   static constexpr int cmax(int a, int b) { return a > b ? a : b; }
   static constexpr int SMEM_A = cmax(cmax(ROW_BYTES, GBUF_HALF), ST_BYTES);
   static constexpr int SMEM_B = cmax(DIFF_BYTES, GBUF_HALF);
-  // with X* targets at 1,024 subcarriers the loss takes 16 rows per group,
-  // eight slots in each array (the second holds no targets then)
+  // with X* targets the loss takes 16 rows per group, eight slots in each
+  // array (the second holds no targets then)
   static constexpr int SMEM_B16 = cmax(SMEM_B, ROW_BYTES);
 };
 
@@ -323,9 +323,10 @@ __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs 
   constexpr int NT = NW * 64;
   __shared__ __align__(16) char smem[F::SMEM_A];
   // rows per loss group: 16 (eight slots in each LDS array) with X* targets
-  // at 1,024 subcarriers (half the groups, so half the group barriers, and
-  // twice the lanes in each slot write and read-back), else 8
-  constexpr int GRP = (CIR && LOGN == 10) ? 16 : F::GROUP;
+  // (half the groups, so half the group barriers, and twice the lanes in
+  // each slot write and read-back), else 8 (the second array holds the
+  // rows' targets)
+  constexpr int GRP = CIR ? 16 : F::GROUP;
   constexpr int RPW = GRP / NW;  // rows per wave per group
   __shared__ __align__(16) char smem_b[GRP == 16 ? F::SMEM_B16 : F::SMEM_B];
   __shared__ float wmax[NW];
