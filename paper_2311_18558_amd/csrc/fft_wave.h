@@ -186,30 +186,122 @@ RTC_DEV void fft_twiddle(float2* v, int j, int Ns) {
   }
 }
 
-// The same twiddles read from a table tw[k] = exp(+j 2 pi k / N), k < N
-// (LDS, filled by fft_tw_fill): w^r = tw[r (j mod Ns) N / (Ns R)] (index
-// below N), conjugated for SIGN < 0.  One read and one address add per
-// element instead of a product of the recurrence, and no error growth.
+// The same twiddles read from LDS rows (filled once by fft_tw_fill): for a
+// pass (R, Ns), row r - 1 holds w^r of every j mod Ns = 0 .. Ns - 1 side by
+// side, conjugated on reading for SIGN < 0.  A lane reads its values at one
+// base plus a constant offset per r, and the lanes of one read hit
+// consecutive values.  (In a plain table exp(j 2 pi k / N) the lanes'
+// indices for one r lie r N / (Ns R) apart, a power-of-two stride that puts
+// them on one or a few LDS banks.)  No error growth: every value is
+// evaluated, none is a product of others.
+//
+// Segments: one per (R, Ns) of the passes with Ns > 1 of the forward and
+// then the reverse radix order, each pair once.
+template <int LOGN>
+struct TwSegs {
+  static constexpr int NP = fft_npass(LOGN);
+  // pass p of order o (0 forward, 1 reverse): radix and Ns
+  static constexpr int rad(int o, int p) { return fft_radix(LOGN, o == 0 ? p : NP - 1 - p); }
+  static constexpr int ns(int o, int p) {
+    int v = 1;
+    for (int q = 0; q < p; ++q) v *= rad(o, q);
+    return v;
+  }
+  // offset of the segment of (R, Ns), or the total length for R = 0
+  static constexpr int off(int R, int Ns) {
+    int o_acc = 0;
+    for (int o = 0; o < 2; ++o)
+      for (int p = 1; p < NP; ++p) {
+        const int r = rad(o, p), n = ns(o, p);
+        bool seen = false;
+        for (int o2 = 0; o2 <= o; ++o2)
+          for (int p2 = 1; p2 < (o2 < o ? NP : p); ++p2)
+            if (rad(o2, p2) == r && ns(o2, p2) == n) seen = true;
+        if (seen) continue;
+        if (r == R && n == Ns) return o_acc;
+        o_acc += (r - 1) * n;
+      }
+    return o_acc;
+  }
+};
+template <int LOGN>
+constexpr int fft_tw_len() {
+  return TwSegs<LOGN>::off(0, 0);
+}
+
 template <int N, int R, int SIGN>
 RTC_DEV void fft_twiddle_tab(float2* v, int j, int Ns, const float2* tw) {
   if (Ns == 1) return;
-  const int step = (j % Ns) * (N / (Ns * R));
-  int k = 0;
+  constexpr int LOGN = __builtin_ctz(N);
+  const float2* row = tw + TwSegs<LOGN>::off(R, Ns) + (j % Ns);
 #pragma unroll
   for (int r = 1; r < R; ++r) {
-    k += step;
-    const float2 w = tw[k];
+    const float2 w = row[(r - 1) * Ns];
     v[r] = SIGN > 0 ? cmul(v[r], w) : cmulc(w, v[r]);
   }
 }
 
-template <int N>
-RTC_DEV void fft_tw_fill(float2* tw, int tid, int nthreads) {
-  for (int k = tid; k < N; k += nthreads) {
-    float s, c;
-    sincos2pi((float)k / (float)N, &s, &c);  // k / N exact
-    tw[k] = make_float2(c, s);
+// The row values, computed at compile time: exp(j 2 pi k / N) in double
+// (exact reduction of k / N to the first eighth of a turn by symmetry, then
+// Taylor series whose remainder is far below FP32 rounding), rounded once to
+// FP32.  Entry m of row r - 1 of segment (R, Ns) has k = r m N / (Ns R).
+struct TwVal {
+  float x, y;
+};
+template <int LOGN>
+struct alignas(16) TwTable {
+  TwVal v[fft_tw_len<LOGN>()];
+};
+
+// sin x (sine) or cos x by their Taylor series, |x| <= pi / 4
+constexpr double cx_taylor(double x, bool sine) {
+  double t = sine ? x : 1.0, s = t;
+  for (int m = 2; m < 40; m += 2) {
+    t *= -x * x / (double)(sine ? m * (m + 1) : m * (m - 1));
+    s += t;
   }
+  return s;
+}
+// cos and sin of 2 pi k / n (n a multiple of 8)
+constexpr TwVal cx_expj2pi(int k, int n) {
+  constexpr double kTwoPi = 6.283185307179586476925286766559;
+  k %= n;
+  const int q = 4 * k / n;           // quarter turns
+  const int r = k - q * (n / 4);     // 0 <= r < n / 4
+  const bool comp = 8 * r > n;       // beyond an eighth: use the complement
+  const double x = kTwoPi * (double)(comp ? n / 4 - r : r) / (double)n;
+  const double sx = cx_taylor(x, true), cxv = cx_taylor(x, false);
+  double c = comp ? sx : cxv, s = comp ? cxv : sx;
+  for (int i = 0; i < q; ++i) {  // rotate by a quarter turn
+    const double t = c;
+    c = -s;
+    s = t;
+  }
+  return TwVal{(float)c, (float)s};
+}
+
+template <int LOGN>
+constexpr TwTable<LOGN> make_tw_table() {
+  using S = TwSegs<LOGN>;
+  constexpr int N = 1 << LOGN;
+  TwTable<LOGN> t{};
+  for (int o = 0; o < 2; ++o)
+    for (int p = 1; p < S::NP; ++p) {
+      const int R = S::rad(o, p), n = S::ns(o, p), b = S::off(R, n);
+      for (int r = 1; r < R; ++r)
+        for (int m = 0; m < n; ++m) t.v[b + (r - 1) * n + m] = cx_expj2pi(r * m * (N / (n * R)), N);
+    }
+  return t;
+}
+
+// Copies the rows from global memory (tab: make_tw_table<LOGN>()) into LDS.
+template <int LOGN>
+RTC_DEV void fft_tw_fill(float2* tw, const TwTable<LOGN>* tab, int tid, int nthreads) {
+  constexpr int L4 = fft_tw_len<LOGN>() / 2;
+  static_assert(fft_tw_len<LOGN>() % 2 == 0, "whole 16-byte pairs");
+  const float4* src = reinterpret_cast<const float4*>(tab->v);
+  float4* dst = reinterpret_cast<float4*>(tw);
+  for (int i = tid; i < L4; i += nthreads) dst[i] = src[i];
 }
 
 template <int N, int R, int SIGN, bool TAB>

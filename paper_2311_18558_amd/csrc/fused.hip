@@ -72,18 +72,32 @@ struct Fz {
   // in array T % 2)
   static constexpr int GBUF_FLOATS = 64 * 32;
   static constexpr int GBUF_HALF = NW * GBUF_FLOATS * 4;
+  // and after them the waves' shares of the tile's dL/da
+  static constexpr int DA_BYTES = NW * 64 * 8;
   // forward: one stage of NW x 8 paths, the path operand in FP16 parts
   // and the delays (path_stage_store), in the first array
   static constexpr int ST_PATHS = path_stage_paths(NW * 64);
   static constexpr int ST_OPND_BYTES = path_stage_opnd_bytes(NW * 64);
   static constexpr int ST_BYTES = path_stage_bytes(NW * 64);
   static constexpr int cmax(int a, int b) { return a > b ? a : b; }
-  static constexpr int SMEM_A = cmax(cmax(ROW_BYTES, GBUF_HALF), ST_BYTES);
-  static constexpr int SMEM_B = cmax(DIFF_BYTES, GBUF_HALF);
+  static constexpr int SMEM_A = cmax(cmax(ROW_BYTES, GBUF_HALF + DA_BYTES), ST_BYTES);
+  static constexpr int SMEM_B = cmax(DIFF_BYTES, GBUF_HALF + DA_BYTES);
   // with X* targets the loss takes 16 rows per group, eight slots in each
   // array (the second holds no targets then)
   static constexpr int SMEM_B16 = cmax(SMEM_B, ROW_BYTES);
 };
+
+// the twiddle rows of the loss transforms (fft_twiddle_tab), per length
+__constant__ TwTable<8> kTwRows8 = make_tw_table<8>();
+__constant__ TwTable<9> kTwRows9 = make_tw_table<9>();
+__constant__ TwTable<10> kTwRows10 = make_tw_table<10>();
+template <int LOGN>
+RTC_DEV const TwTable<LOGN>* tw_rows() {
+  static_assert(LOGN >= 8 && LOGN <= 10, "fused pass lengths");
+  if constexpr (LOGN == 8) return &kTwRows8;
+  else if constexpr (LOGN == 9) return &kTwRows9;
+  else return &kTwRows10;
+}
 
 struct FusedArgs {
   int n_links, M;
@@ -330,10 +344,14 @@ __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs 
   constexpr int RPW = GRP / NW;  // rows per wave per group
   __shared__ __align__(16) char smem_b[GRP == 16 ? F::SMEM_B16 : F::SMEM_B];
   __shared__ float wmax[NW];
-  __shared__ float2 dabuf[2][NW * 64];
-  __shared__ float2 twtab[N];  // FFT twiddles exp(j 2 pi k / N)
+  __shared__ float2 twtab[fft_tw_len<LOGN>()];  // FFT twiddle rows (fft_tw_fill)
   float4* rowbuf = reinterpret_cast<float4*>(smem);
   auto gbuf = [&](int b) { return reinterpret_cast<float*>(b ? smem_b : smem); };
+  // the waves' shares of a tile's dL/da (adjoint), after the partial G of
+  // the same array
+  auto dabuf = [&](int b) {
+    return reinterpret_cast<float2*>((b ? smem_b : smem) + F::GBUF_HALF);
+  };
 
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
@@ -344,7 +362,7 @@ __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs 
   const int64_t off0 = A.link_off[l];
   const int64_t off1 = A.link_off[l + 1];
   const int q_base = wv * 32 * TPW;
-  fft_tw_fill<N>(twtab, threadIdx.x, NT);  // read after the barriers below
+  fft_tw_fill<LOGN>(twtab, tw_rows<LOGN>(), threadIdx.x, NT);  // read after the barriers below
   // loss rows of this wave: k -> element row GRP (k / RPW) + wv + NW (k % RPW);
   // the rows that exist (< M) are a prefix.  The first one's targets load
   // into the wave's LDS buffer while the forward product runs (the buffer
@@ -543,7 +561,7 @@ __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs 
   for (int i = 0; i < RPL; ++i) dgw[i][0] = dgw[i][1] = 0.0;
   auto finish_da = [&](int T) {
     // dL/da of tile T: the shares of the waves' half-waves, in order
-    const float2* db = dabuf[T & 1];
+    const float2* db = dabuf(T & 1);
     const int64_t p = off0 + 32 * (int64_t)T + col;
     if (half == 0 && p < off1 && A.dLda) {
       float2 d = cadd(db[col], db[32 + col]);
@@ -605,7 +623,7 @@ __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs 
     }
   };
   // The epilogue of tile T, its G~ complete in gbuf(T & 1): this wave's rows
-  // of the tile, its half-wave's share of dL/da into dabuf[T & 1] (added in
+  // of the tile, its half-wave's share of dL/da into dabuf(T & 1) (added in
   // order by the wave that finishes the tile) and dL/dg into dgw.  ai,
   // psi_cyc, tau: the lane's path of the tile (zero past the link).
   auto tile_epilogue = [&](int T, float2 ai, double psi_cyc, double tau) {
@@ -637,7 +655,7 @@ __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs 
       dgw[i][0] += (double)half_sum_f32(tg.x);
       dgw[i][1] += (double)half_sum_f32(tg.y);
     }
-    dabuf[T & 1][wv * 64 + lane] = da;
+    dabuf(T & 1)[wv * 64 + lane] = da;
   };
   // the lane's path data of tile T, loaded without a branch (index clamped
   // to the link, values zeroed past it)
