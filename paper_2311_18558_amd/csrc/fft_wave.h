@@ -18,6 +18,8 @@
 //    transform left in each lane, and vice versa.
 #pragma once
 
+#include <type_traits>
+
 #include "dev_common.h"
 
 namespace rtc {
@@ -293,6 +295,52 @@ constexpr TwTable<LOGN> make_tw_table() {
     }
   return t;
 }
+
+// The rows of the lengths whose one-wave transforms read them from LDS
+// (256 to 1,024 points), one copy per code object.
+static __constant__ TwTable<8> kTwRows8 = make_tw_table<8>();
+static __constant__ TwTable<9> kTwRows9 = make_tw_table<9>();
+static __constant__ TwTable<10> kTwRows10 = make_tw_table<10>();
+template <int LOGN>
+RTC_DEV const TwTable<LOGN>* tw_rows() {
+  static_assert(LOGN >= 8 && LOGN <= 10, "lengths with twiddle rows");
+  if constexpr (LOGN == 8)
+    return &kTwRows8;
+  else if constexpr (LOGN == 9)
+    return &kTwRows9;
+  else
+    return &kTwRows10;
+}
+
+// Row-parallel transforms (the loss kernels): up to 1,024 points a wave
+// takes a row, four waves per workgroup, each transforming in place in its
+// own LDS buffer and all reading the workgroup's twiddle rows (256 points
+// and up); longer rows take a workgroup of N/16 threads and two buffers.
+constexpr int fft_row_waves(int logn) { return logn <= 10 ? 4 : 1; }
+constexpr bool fft_row_tab(int logn) { return logn >= 8 && logn <= 10; }
+constexpr int fft_row_tab_logn(int logn) { return fft_row_tab(logn) ? logn : 8; }
+
+// Declarations of a row-parallel transform kernel over rows of N = 2^LOGN
+// points with T = fft_threads(LOGN) threads per row: W rows in flight, the
+// exchange order SY, the row buffers b0, b1 of this thread's row (one buffer
+// in place for one-wave rows), the twiddle rows twr (filled here, TAB), the
+// reduction scratch red, the thread's row slot wv and index lane0 in its row.
+#define RTC_FFT_ROWS_SETUP()                                                               \
+  constexpr int W = fft_row_waves(LOGN);                                                   \
+  constexpr bool TAB = fft_row_tab(LOGN);                                                  \
+  using SY = typename std::conditional<W == 1, BlockSync, WaveSync>::type;                 \
+  __shared__ float2 rowbufs[W == 1 ? 2 : W][fft_lds_len(N)];                               \
+  __shared__ float2 twr[TAB ? fft_tw_len<fft_row_tab_logn(LOGN)>() : 2];                   \
+  __shared__ double red[T / 64];                                                           \
+  const int wv = W == 1 ? 0 : (int)(threadIdx.x >> 6);                                     \
+  const int lane0 = W == 1 ? (int)threadIdx.x : (int)(threadIdx.x & 63);                   \
+  float2* b0 = rowbufs[wv];                                                                \
+  float2* b1 = rowbufs[W == 1 ? 1 : wv];                                                   \
+  if constexpr (TAB) {                                                                     \
+    fft_tw_fill<fft_row_tab_logn(LOGN)>(twr, tw_rows<fft_row_tab_logn(LOGN)>(),            \
+                                        (int)threadIdx.x, (int)blockDim.x);                \
+    __syncthreads();                                                                       \
+  }
 
 // Copies the rows from global memory (tab: make_tw_table<LOGN>()) into LDS.
 template <int LOGN>

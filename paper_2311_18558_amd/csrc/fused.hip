@@ -87,18 +87,6 @@ struct Fz {
   static constexpr int SMEM_B16 = cmax(SMEM_B, ROW_BYTES);
 };
 
-// the twiddle rows of the loss transforms (fft_twiddle_tab), per length
-__constant__ TwTable<8> kTwRows8 = make_tw_table<8>();
-__constant__ TwTable<9> kTwRows9 = make_tw_table<9>();
-__constant__ TwTable<10> kTwRows10 = make_tw_table<10>();
-template <int LOGN>
-RTC_DEV const TwTable<LOGN>* tw_rows() {
-  static_assert(LOGN >= 8 && LOGN <= 10, "fused pass lengths");
-  if constexpr (LOGN == 8) return &kTwRows8;
-  else if constexpr (LOGN == 9) return &kTwRows9;
-  else return &kTwRows10;
-}
-
 struct FusedArgs {
   int n_links, M;
   const int64_t* link_off;

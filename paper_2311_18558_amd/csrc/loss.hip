@@ -30,7 +30,10 @@ constexpr int kRedChunk = 64;  // rows per reduction block (first two levels)
 // threads (one radix-16 butterfly each per pass) beyond.  The H and H* rows
 // are read straight into the first FFT pass, the last inverse pass leaves
 // the taps in dL/dH in the row's natural order, next to H - H* kept from the
-// load.  The Stockham passes ping-pong between two LDS row buffers.  With PT
+// load.  Up to 1,024 points four waves share a workgroup, each taking its own
+// rows and transforming them in place in its own LDS buffer, with the
+// twiddles from the workgroup's LDS rows (fft_row_waves, fft_twiddle_tab);
+// longer rows ping-pong between two buffers of the workgroup.  With PT
 // the target PDP comes precomputed (p_tgt from the target statistics)
 // instead of from a transform of H*.
 
@@ -40,7 +43,7 @@ constexpr int kRedChunk = 64;  // rows per reduction block (first two levels)
 // target is |X*|^2 / N, and dL/dH = IDFT(gc/N (X - X*) + gp (p - p*) X)
 // (unnormalised inverse): two transforms per row and nothing of H* kept.
 template <int LOGN, int TGT>
-__global__ void __launch_bounds__(fft_threads(LOGN))
+__global__ void __launch_bounds__(fft_threads(LOGN) * fft_row_waves(LOGN))
     cfr_loss_wave_kernel(const float2* H, const float2* __restrict__ Ht,
                          const float* __restrict__ Pt, int64_t n_rows, const double* Z,
                          float w_coh, float w_pdp, double* row_out, float2* dLdH) {
@@ -50,16 +53,15 @@ __global__ void __launch_bounds__(fft_threads(LOGN))
   constexpr int T = fft_threads(LOGN);
   constexpr int JA = fft_bpl(N, RA, T), JZ = fft_bpl(N, RZ, T);
   constexpr int BA = N / RA, BZ = N / RZ;
-  __shared__ float2 b0[fft_lds_len(N)], b1[fft_lds_len(N)];
-  __shared__ double red[T / 64];
+  RTC_FFT_ROWS_SETUP();
   const float invN = 1.0f / (float)N;
   float gc = 0.0f, gp = 0.0f;
   if (dLdH) {
     gc = (float)(2.0 * (double)w_coh / Z[0]);
     gp = (float)(4.0 * (double)w_pdp / (Z[1] * (double)N));
   }
-  for (int64_t row = blockIdx.x; row < n_rows; row += gridDim.x) {
-    int lane = threadIdx.x;
+  for (int64_t row = (int64_t)blockIdx.x * W + wv; row < n_rows; row += (int64_t)gridDim.x * W) {
+    int lane = lane0;
     asm volatile("" : "+v"(lane));  // twiddles per row, not held across rows
     const float2* hs = H + row * N;
     const float2* ts = Ht + row * N;
@@ -83,7 +85,7 @@ __global__ void __launch_bounds__(fft_threads(LOGN))
           vh[i][r] = (BA % T == 0 || j < BA) ? hs[j + r * BA] : make_float2(0.0f, 0.0f);
       }
       float2 xh[JZ][RZ];
-      fft_full<LOGN, +1, +1, BlockSync, T>(vh, xh, b0, b1, lane);
+      fft_full<LOGN, +1, +1, SY, T, TAB>(vh, xh, b0, b1, lane, twr);
       const float gcn = gc * invN;
       float ep = 0.0f, eq = 0.0f;
 #pragma unroll
@@ -115,7 +117,7 @@ __global__ void __launch_bounds__(fft_threads(LOGN))
       }
       if (dLdH) {
         float2 G[JA][RA];
-        fft_full<LOGN, -1, -1, BlockSync, T>(xh, G, b0, b1, lane);
+        fft_full<LOGN, -1, -1, SY, T, TAB>(xh, G, b0, b1, lane, twr);
         float2* out = dLdH + row * N;
 #pragma unroll
         for (int i = 0; i < JA; ++i) {
@@ -147,7 +149,7 @@ __global__ void __launch_bounds__(fft_threads(LOGN))
         for (int r = 0; r < RA; ++r)
           vt[i][r] = (BA % T == 0 || j < BA) ? ts[j + r * BA] : make_float2(0.0f, 0.0f);
       }
-      fft_full<LOGN, +1, +1, BlockSync, T>(vt, xt, b0, b1, lane);
+      fft_full<LOGN, +1, +1, SY, T, TAB>(vt, xt, b0, b1, lane, twr);
 #pragma unroll
       for (int i = 0; i < JZ; ++i) {
 #pragma unroll
@@ -169,7 +171,7 @@ __global__ void __launch_bounds__(fft_threads(LOGN))
       }
     }
     float2 xh[JZ][RZ];
-    fft_full<LOGN, +1, +1, BlockSync, T>(vh, xh, b0, b1, lane);
+    fft_full<LOGN, +1, +1, SY, T, TAB>(vh, xh, b0, b1, lane, twr);
     float ep = 0.0f, eq = 0.0f;
 #pragma unroll
     for (int i = 0; i < JZ; ++i) {
@@ -197,7 +199,7 @@ __global__ void __launch_bounds__(fft_threads(LOGN))
     }
     if (dLdH) {
       float2 G[JA][RA];
-      fft_full<LOGN, -1, -1, BlockSync, T>(xh, G, b0, b1, lane);
+      fft_full<LOGN, -1, -1, SY, T, TAB>(xh, G, b0, b1, lane, twr);
       float2* out = dLdH + row * N;
 #pragma unroll
       for (int i = 0; i < JA; ++i) {
@@ -215,7 +217,7 @@ __global__ void __launch_bounds__(fft_threads(LOGN))
 // target PDP p* (natural tap order) for later loss calls, with Xt the
 // transform X* itself (natural tap order).
 template <int LOGN>
-__global__ void __launch_bounds__(fft_threads(LOGN))
+__global__ void __launch_bounds__(fft_threads(LOGN) * fft_row_waves(LOGN))
     target_stats_wave_kernel(const float2* __restrict__ Ht, int64_t n_rows, double* row_out,
                              float* Pt, float2* Xt) {
   constexpr int N = 1 << LOGN;
@@ -224,11 +226,10 @@ __global__ void __launch_bounds__(fft_threads(LOGN))
   constexpr int T = fft_threads(LOGN);
   constexpr int JA = fft_bpl(N, RA, T), JZ = fft_bpl(N, RZ, T);
   constexpr int BA = N / RA, BZ = N / RZ;
-  __shared__ float2 b0[fft_lds_len(N)], b1[fft_lds_len(N)];
-  __shared__ double red[T / 64];
-  const int lane = threadIdx.x;
+  RTC_FFT_ROWS_SETUP();
+  const int lane = lane0;
   const float invN = 1.0f / (float)N;
-  for (int64_t row = blockIdx.x; row < n_rows; row += gridDim.x) {
+  for (int64_t row = (int64_t)blockIdx.x * W + wv; row < n_rows; row += (int64_t)gridDim.x * W) {
     const float2* ts = Ht + row * N;
     float2 vt[JA][RA];
     float et = 0.0f;
@@ -244,7 +245,7 @@ __global__ void __launch_bounds__(fft_threads(LOGN))
       }
     }
     float2 xt[JZ][RZ];
-    fft_full<LOGN, +1, +1, BlockSync, T>(vt, xt, b0, b1, lane);
+    fft_full<LOGN, +1, +1, SY, T, TAB>(vt, xt, b0, b1, lane, twr);
     float eq = 0.0f;
 #pragma unroll
     for (int i = 0; i < JZ; ++i) {
@@ -364,18 +365,22 @@ size_t ws_cfr_loss(const rtc_radio* r, int32_t n_links) {
 
 size_t ws_target_stats(const rtc_radio* r, int32_t n_links) { return ws_cfr_loss(r, n_links); }
 
-static unsigned wave_grid(int64_t R) {
-  int64_t g = R < 40960 ? R : 40960;
+// workgroups for R rows of 2^logn points (fft_row_waves rows in flight each)
+static unsigned wave_grid(int64_t R, int logn) {
+  const int w = fft_row_waves(logn);
+  int64_t g = (R + w - 1) / w;
+  g = g < 40960 / w ? g : 40960 / w;
   return (unsigned)(g > 0 ? g : 1);
 }
+static unsigned row_block(int logn) { return (unsigned)(fft_threads(logn) * fft_row_waves(logn)); }
 
 static void launch_target_stats(int logN, const float2* Ht, int64_t R, double* rows, float* Pt,
                                 float2* Xt, hipStream_t s) {
   switch (logN) {
 #define RTC_TS(L)                                                                            \
   case L:                                                                                    \
-    hipLaunchKernelGGL(target_stats_wave_kernel<L>, dim3(wave_grid(R)),                      \
-                       dim3(fft_threads(L)), 0, s, Ht, R, rows, Pt, Xt);                     \
+    hipLaunchKernelGGL(target_stats_wave_kernel<L>, dim3(wave_grid(R, L)),                      \
+                       dim3(row_block(L)), 0, s, Ht, R, rows, Pt, Xt);                     \
     return;
     RTC_TS(1) RTC_TS(2) RTC_TS(3) RTC_TS(4) RTC_TS(5) RTC_TS(6) RTC_TS(7) RTC_TS(8) RTC_TS(9)
     RTC_TS(10) RTC_TS(11) RTC_TS(12)
@@ -393,16 +398,16 @@ static void launch_loss(int logN, int tgt, const float2* H, const float2* Ht, co
 #define RTC_LW(L)                                                                             \
   case L:                                                                                     \
     if (tgt == 2)                                                                             \
-      hipLaunchKernelGGL((cfr_loss_wave_kernel<L, 2>), dim3(wave_grid(R)),                    \
-                         dim3(fft_threads(L)), 0, s, H, Ht, Pt, R, Z, w_coh, w_pdp, rows,     \
+      hipLaunchKernelGGL((cfr_loss_wave_kernel<L, 2>), dim3(wave_grid(R, L)),                    \
+                         dim3(row_block(L)), 0, s, H, Ht, Pt, R, Z, w_coh, w_pdp, rows,     \
                          dLdH);                                                               \
     else if (tgt == 1)                                                                        \
-      hipLaunchKernelGGL((cfr_loss_wave_kernel<L, 1>), dim3(wave_grid(R)),                    \
-                         dim3(fft_threads(L)), 0, s, H, Ht, Pt, R, Z, w_coh, w_pdp, rows,     \
+      hipLaunchKernelGGL((cfr_loss_wave_kernel<L, 1>), dim3(wave_grid(R, L)),                    \
+                         dim3(row_block(L)), 0, s, H, Ht, Pt, R, Z, w_coh, w_pdp, rows,     \
                          dLdH);                                                               \
     else                                                                                      \
-      hipLaunchKernelGGL((cfr_loss_wave_kernel<L, 0>), dim3(wave_grid(R)),                    \
-                         dim3(fft_threads(L)), 0, s, H, Ht, Pt, R, Z, w_coh, w_pdp, rows,     \
+      hipLaunchKernelGGL((cfr_loss_wave_kernel<L, 0>), dim3(wave_grid(R, L)),                    \
+                         dim3(row_block(L)), 0, s, H, Ht, Pt, R, Z, w_coh, w_pdp, rows,     \
                          dLdH);                                                               \
     return;
     RTC_LW(1) RTC_LW(2) RTC_LW(3) RTC_LW(4) RTC_LW(5) RTC_LW(6) RTC_LW(7) RTC_LW(8) RTC_LW(9)

@@ -78,11 +78,12 @@ RTC_DEV RowGrad row_loss(const PaperLossArgs& A, int64_t row, double alpha, doub
 }
 
 // ------------------------------------------------------- register-FFT rows
-// T = fft_threads(LOGN) threads own a row (one wave up to N = 1024, N/16
-// beyond); the row is read straight into the first FFT pass and the
-// gradient's transform leaves dL/dH in natural order.
+// T = fft_threads(LOGN) threads own a row (one wave up to N = 1024, four
+// rows per workgroup then; N/16 threads beyond, fft_row_waves); the row is
+// read straight into the first FFT pass and the gradient's transform leaves
+// dL/dH in natural order.
 template <int LOGN, bool LOSS>
-__global__ void __launch_bounds__(fft_threads(LOGN))
+__global__ void __launch_bounds__(fft_threads(LOGN) * fft_row_waves(LOGN))
     paper_loss_wave_kernel(const float2* H, int64_t n_rows, PaperLossArgs A) {
   constexpr int N = 1 << LOGN;
   constexpr int NP = fft_npass(LOGN);
@@ -90,12 +91,11 @@ __global__ void __launch_bounds__(fft_threads(LOGN))
   constexpr int T = fft_threads(LOGN);
   constexpr int JA = fft_bpl(N, RA, T), JZ = fft_bpl(N, RZ, T);
   constexpr int BA = N / RA, BZ = N / RZ;
-  __shared__ float2 b0[fft_lds_len(N)], b1[fft_lds_len(N)];
-  __shared__ double red[T / 64];
+  RTC_FFT_ROWS_SETUP();
   const float invN = 1.0f / (float)N;
   const double alpha = LOSS ? A.alpha[0] : 1.0;
-  for (int64_t row = blockIdx.x; row < n_rows; row += gridDim.x) {
-    int lane = threadIdx.x;
+  for (int64_t row = (int64_t)blockIdx.x * W + wv; row < n_rows; row += (int64_t)gridDim.x * W) {
+    int lane = lane0;
     asm volatile("" : "+v"(lane));  // twiddles per row, not held across rows
     const float2* hs = H + row * N;
     float2 vh[JA][RA];
@@ -107,7 +107,7 @@ __global__ void __launch_bounds__(fft_threads(LOGN))
         vh[i][r] = (BA % T == 0 || j < BA) ? hs[j + r * BA] : make_float2(0.0f, 0.0f);
     }
     float2 xh[JZ][RZ];
-    fft_full<LOGN, +1, +1, BlockSync, T>(vh, xh, b0, b1, lane);
+    fft_full<LOGN, +1, +1, SY, T, TAB>(vh, xh, b0, b1, lane, twr);
     float s0 = 0.0f, s1 = 0.0f;
 #pragma unroll
     for (int i = 0; i < JZ; ++i) {
@@ -158,7 +158,7 @@ __global__ void __launch_bounds__(fft_threads(LOGN))
           }
         }
         float2 G[JA][RA];
-        fft_full<LOGN, -1, -1, BlockSync, T>(xh, G, b0, b1, lane);
+        fft_full<LOGN, -1, -1, SY, T, TAB>(xh, G, b0, b1, lane, twr);
         float2* out = A.dLdH + row * N;
 #pragma unroll
         for (int i = 0; i < JA; ++i) {
@@ -241,8 +241,11 @@ static int ilog2_pl(int n) {
   return k;
 }
 
-static unsigned pl_wave_grid(int64_t R) {
-  int64_t g = R < 40960 ? R : 40960;
+// workgroups for R rows of 2^logn points (fft_row_waves rows in flight each)
+static unsigned pl_wave_grid(int64_t R, int logn) {
+  const int w = fft_row_waves(logn);
+  int64_t g = (R + w - 1) / w;
+  g = g < 40960 / w ? g : 40960 / w;
   return (unsigned)(g > 0 ? g : 1);
 }
 
@@ -252,8 +255,8 @@ static void launch_paper_rows(int logN, const float2* H, int64_t R, const PaperL
   switch (logN) {
 #define RTC_PL(L)                                                                            \
   case L:                                                                                    \
-    hipLaunchKernelGGL((paper_loss_wave_kernel<L, LOSS>), dim3(pl_wave_grid(R)),             \
-                       dim3(fft_threads(L)), 0, s, H, R, A);                                 \
+    hipLaunchKernelGGL((paper_loss_wave_kernel<L, LOSS>), dim3(pl_wave_grid(R, L)),          \
+                       dim3(fft_threads(L) * fft_row_waves(L)), 0, s, H, R, A);             \
     return;
     RTC_PL(1) RTC_PL(2) RTC_PL(3) RTC_PL(4) RTC_PL(5) RTC_PL(6) RTC_PL(7) RTC_PL(8) RTC_PL(9)
     RTC_PL(10) RTC_PL(11) RTC_PL(12)
