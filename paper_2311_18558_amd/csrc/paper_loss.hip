@@ -175,16 +175,21 @@ __global__ void __launch_bounds__(fft_threads(LOGN) * fft_row_waves(LOGN))
 
 // ------------------------------------------------------------ scale alpha
 // One wave per row: rows_out[r] = {P_r E_r, P_r^2} with E_r = sum_n |H_n|^2
-// and P_r the measured gain.
+// and P_r the measured gain.  16-byte loads (two taps; N is even), unrolled
+// so that a wave has its row's loads in flight together.
 __global__ void __launch_bounds__(256)
     gain_products_kernel(const float2* __restrict__ H, int64_t n_rows, int N,
                          const double* __restrict__ tgt, double* rows_out) {
   const int lane = threadIdx.x & 63;
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= n_rows) return;
-  const float2* hs = H + row * N;
+  const float4* hs = reinterpret_cast<const float4*>(H + row * N);
   float e = 0.0f;
-  for (int n = lane; n < N; n += 64) e += cabs2(hs[n]);
+#pragma unroll 8
+  for (int n = lane; n < N / 2; n += 64) {
+    const float4 v = hs[n];
+    e += v.x * v.x + v.y * v.y + v.z * v.z + v.w * v.w;
+  }
   const double E = wave_sum_f64((double)e);
   if (lane == 0) {
     const double P = tgt[row * 2];
