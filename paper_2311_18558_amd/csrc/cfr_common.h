@@ -29,6 +29,23 @@ RTC_DEV float half_sum_f32(float v) {
   return v;
 }
 
+// The same butterfly in FP64 (each half of the double swizzled alike).
+template <int O>
+RTC_DEV double swz_xor_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_ds_swizzle((int)(unsigned)(b & 0xffffffffll), (O << 10) | 0x1f);
+  const int hi = __builtin_amdgcn_ds_swizzle((int)(b >> 32), (O << 10) | 0x1f);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+RTC_DEV double half_sum_f64(double v) {
+  v += swz_xor_f64<16>(v);
+  v += swz_xor_f64<8>(v);
+  v += swz_xor_f64<4>(v);
+  v += swz_xor_f64<2>(v);
+  v += swz_xor_f64<1>(v);
+  return v;
+}
+
 RTC_DEV float wave_max_f32(float v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));

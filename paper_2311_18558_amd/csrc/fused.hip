@@ -531,7 +531,8 @@ __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs 
   // 4 g4 + 3 of G, in the lane's own half); with eight, wave w takes rows
   // 8 (w/2) + 4 (w%2) + 0..3 (registers of the lanes of half w%2), two per
   // lane: rows 2 half, 2 half + 1 of the four.  Its dL/dg rows accumulate in
-  // the wave's registers (FP64, tiles in order); each half-wave's share of
+  // the lanes' registers (FP64, each lane its paths, tiles in order; the
+  // half-wave's lanes are added at the end of the link); each half-wave's share of
   // dL/da goes to LDS and the wave that finishes the tile adds the shares in
   // order after the next barrier.
   constexpr int G4W = NW <= 4 ? 4 / NW : 1;
@@ -638,10 +639,11 @@ __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs 
       const float2 G = cmul(cc, make_float2(gr * unsca, gi * unsca));
       const float2 Gph = cmul(G, ph);
       da = cadd(da, cmulc(gep[i], Gph));
-      // dL/dg: sum over the 32 paths of this half (fixed butterfly)
+      // dL/dg: the lane's path, summed over the tiles in the lane (FP64),
+      // over the half's 32 lanes once at the end of the link
       const float2 tg = cmulc(ai, Gph);
-      dgw[i][0] += (double)half_sum_f32(tg.x);
-      dgw[i][1] += (double)half_sum_f32(tg.y);
+      dgw[i][0] += (double)tg.x;
+      dgw[i][1] += (double)tg.y;
     }
     dabuf(T & 1)[wv * 64 + lane] = da;
   };
@@ -691,7 +693,13 @@ __global__ void __launch_bounds__(Fz<LOGN>::NW * 64) cfr_fused_kernel(FusedArgs 
   __syncthreads();  // the last tile's shares are in LDS; every epilogue is done
   if (n_tiles > 0 && wv == (n_tiles - 1) % NW) finish_da(n_tiles - 1);
   if (A.g_part) {
-    // this wave's dL/dg rows of the link (disjoint across waves and halves)
+    // this wave's dL/dg rows of the link (disjoint across waves and halves):
+    // the lanes' sums over their paths, added over the half (fixed butterfly)
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+      dgw[i][0] = half_sum_f64(dgw[i][0]);
+      dgw[i][1] = half_sum_f64(dgw[i][1]);
+    }
     if (col == 0) {
 #pragma unroll
       for (int i = 0; i < RPL; ++i) {
