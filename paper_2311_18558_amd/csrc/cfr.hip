@@ -783,6 +783,11 @@ __device__ __forceinline__ void adj_wave(const AdjArgs& A, int64_t w, int64_t l,
     }
     // epilogue: rows m = mblk*32 + 8(r/4) + 4 half + r%4, column = path
     const float unscale = ldexpf(1.0f, -sx);
+    // dL/dg: each lane sums its paths over the tiles, the half-wave's lanes
+    // are added once after them (fixed butterfly)
+    float gacc_re[16], gacc_im[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) gacc_re[r] = gacc_im[r] = 0.0f;
 #pragma unroll
     for (int u = 0; u < NT; ++u) {
       gre[u] *= unscale;
@@ -792,7 +797,6 @@ __device__ __forceinline__ void adj_wave(const AdjArgs& A, int64_t w, int64_t l,
       const float2 ai = ok ? A.a[p] : make_float2(0.0f, 0.0f);
       const double psi_cyc = (double)(ok ? A.psi[p] : 0.0f) * kInv2Pi;
       const float2 cc = cconj(expm2pi_f64_hw(A.fref * tv[u]));  // conj(c_p)
-      float gacc_re[16], gacc_im[16];
 #pragma unroll
       for (int grp4 = 0; grp4 < 4; ++grp4) {
         const int mrow0 = mblk * 32 + 8 * grp4 + 4 * half;
@@ -808,31 +812,20 @@ __device__ __forceinline__ void adj_wave(const AdjArgs& A, int64_t w, int64_t l,
           float2 Gph = cmul(G, ph);
           da[u] = cadd(da[u], cmulc(gm, Gph));
           float2 tg2 = cmulc(ai, Gph);
-          gacc_re[r] = tg2.x;
-          gacc_im[r] = tg2.y;
+          gacc_re[r] += tg2.x;  // tiles in order
+          gacc_im[r] += tg2.y;
         }
       }
-      if (A.g_part) {
-        // sum over the 32 paths of this half (fixed butterfly), add tiles in order
+    }
+    if (A.g_part) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          float vr = gacc_re[r], vi = gacc_im[r];
-#pragma unroll
-          for (int o = 16; o >= 1; o >>= 1) {
-            vr += __shfl_xor(vr, o, 64);
-            vi += __shfl_xor(vi, o, 64);
-          }
-          const int mrow = mblk * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
-          if (col == 0 && mrow < A.M) {
-            double* dst = A.g_part + (w * A.M + mrow) * 2;
-            if (u == 0) {
-              dst[0] = (double)vr;
-              dst[1] = (double)vi;
-            } else {
-              dst[0] += (double)vr;
-              dst[1] += (double)vi;
-            }
-          }
+      for (int r = 0; r < 16; ++r) {
+        const float vr = half_sum_f32(gacc_re[r]), vi = half_sum_f32(gacc_im[r]);
+        const int mrow = mblk * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+        if (col == 0 && mrow < A.M) {
+          double* dst = A.g_part + (w * A.M + mrow) * 2;
+          dst[0] = (double)vr;
+          dst[1] = (double)vi;
         }
       }
     }
