@@ -274,16 +274,29 @@ struct MlpBwdArgs {
 };
 
 // Transposed store of a wave's K-blocks (register layout, feature order
-// given by `feat`) into LDS rows = features, columns = the wave's 32 points.
+// kperm or natural) into LDS rows = features, columns = the wave's 32
+// points.  A word of the register layout holds features j, j + 1 (j even)
+// of the lane's point; the lanes of points col, col ^ 1 swap that word (DPP
+// within a quad), and the even lane stores feature j of both points, the odd
+// lane feature j + 1, each as one 4-byte store (two 2-byte stores a lane
+// otherwise, which bound the kernel).  Every lane of the wave must take part.
 template <int NKB, bool KPERM>
 RTC_DEV void put_rows(uint16_t* rows, const bf16x8* v, int col, int h) {
+  const int odd = col & 1;
+  const unsigned sel = odd ? 0x03020706u : 0x05040100u;  // {oth.hi, own.hi} : {own.lo, oth.lo}
+  // feature j = 2 q + odd of K-block c is row fc(c, q) + the lane's part
+  // (kperm: 4 h + odd; natural: 8 h + odd); the even column starts the word
+  uint16_t* base = rows + (KPERM ? 4 * h : 8 * h) * kBwdLd + odd * kBwdLd + (col - odd);
 #pragma unroll
   for (int c = 0; c < NKB; ++c) {
     const u32x4 w = __builtin_bit_cast(u32x4, v[c]);
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int f = KPERM ? kperm(c, h, j) : 16 * c + 8 * h + j;
-      rows[f * kBwdLd + col] = (uint16_t)(w[j >> 1] >> (16 * (j & 1)));
+    for (int q = 0; q < 4; ++q) {
+      const unsigned own = w[q];
+      const unsigned oth = (unsigned)__builtin_amdgcn_mov_dpp((int)own, 0xB1, 0xF, 0xF, false);  // lane ^ 1
+      const int fc = KPERM ? 32 * (c >> 1) + 16 * (c & 1) + 8 * (q >> 1) + 2 * (q & 1)
+                           : 16 * c + 2 * q;
+      *reinterpret_cast<uint32_t*>(base + fc * kBwdLd) = __builtin_amdgcn_perm(oth, own, sel);
     }
   }
 }
